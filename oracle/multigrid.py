@@ -1,0 +1,112 @@
+"""Geometric multigrid V-cycle with the FS-AS smoother (paper Section 3).
+
+GMRES is preconditioned by GMG; on every level l >= 1 a damped Richardson
+iteration preconditioned by the field-split smoother is used, on level 0 a
+direct solver (Section 3.2, after eq. matrix_J2).  Level operators are
+re-discretized on each level.  The coarse solve is a dense LU with partial
+pivoting.
+
+The transposed cycle applies M^T exactly: it is the V-cycle of A^T with the
+smoother B^T, restriction by (D_f P)^T, prolongation by (D_c R)^T and the
+numbers of pre- and post-sweeps exchanged.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as la
+import scipy.sparse as sp
+
+from . import fem, transfer
+from .mesh import Level, hierarchy_levels
+from .schwarz import FieldSplitSchwarz, build_blocks
+
+
+class Hierarchy:
+    def __init__(self, cfg: dict, w_finest: np.ndarray | None = None,
+                 taus: list | None = None, build_smoothers: bool = True):
+        self.cfg = cfg
+        self.L = int(cfg["n_levels"])
+        self.levels = hierarchy_levels(cfg)
+        self.w_finest = w_finest
+        self.A_full, self.A, self.parts = [], [], []
+        for l, lv in enumerate(self.levels):
+            w = None if w_finest is None else lv.inject_from_finest(w_finest, self.L)
+            tau = None if taus is None else taus[l]
+            asm = fem.assemble_level(lv, cfg, w, tau)
+            self.parts.append(asm)
+            self.A_full.append(asm["A"])
+            self.A.append(fem.dirichlet_reduce(lv, asm["A"]))
+        self.P = [None] + [transfer.prolongation(self.levels[l], self.levels[l - 1])
+                           for l in range(1, self.L)]
+        self.R = [None] + [transfer.restriction(self.levels[l], self.levels[l - 1])
+                           for l in range(1, self.L)]
+        self.coarse_lu = la.lu_factor(self.A[0].toarray())
+        self.smoothers = [None] * self.L
+        if build_smoothers:
+            self.build_smoothers()
+
+    @property
+    def finest(self) -> Level:
+        return self.levels[-1]
+
+    def build_smoothers(self, core=None, halo=None):
+        cfg = self.cfg
+        core = tuple(cfg["core"]) if core is None else tuple(core)
+        halo = int(cfg["halo"]) if halo is None else int(halo)
+        for l in range(1, self.L):
+            blocks, _ = build_blocks(self.levels[l], core, halo)
+            self.smoothers[l] = FieldSplitSchwarz(self.A[l], blocks)
+
+    def rhs(self, fnodal: np.ndarray) -> np.ndarray:
+        """Finest-level right-hand side for a nodal body force (Dirichlet-lifted)."""
+        lv = self.finest
+        w = None if self.w_finest is None else self.w_finest
+        tau = self.parts[-1]["tau"]
+        b_raw = fem.load_vector(lv, self.cfg, fnodal, w, tau)
+        return fem.dirichlet_rhs(lv, self.A_full[-1], b_raw)
+
+    # ------------------------------------------------------------------
+    def _sweeps(self, l, b, x, n, transpose):
+        A = self.A[l]
+        S = self.smoothers[l]
+        om = self.cfg["omega"]
+        for s in range(n):
+            if x is None:                      # first sweep from x = 0: r = b
+                x = om * (S.apply_transpose(b) if transpose else S.apply(b))
+            else:
+                r = b - (A.T @ x if transpose else A @ x)
+                x = x + om * (S.apply_transpose(r) if transpose else S.apply(r))
+        return x
+
+    def vcycle(self, b: np.ndarray, l: int | None = None, transpose: bool = False):
+        """z = M^{-1} b (or M^{-T} b) on level l (default finest)."""
+        if l is None:
+            l = self.L - 1
+        if l == 0:
+            return la.lu_solve(self.coarse_lu, b, trans=1 if transpose else 0)
+        cfg = self.cfg
+        n1, n2 = cfg["nu_pre"], cfg["nu_post"]
+        if transpose:
+            n1, n2 = n2, n1
+        x = self._sweeps(l, b, None, n1, transpose)
+        A = self.A[l]
+        if x is None:
+            x = np.zeros_like(b)
+        r = b - (A.T @ x if transpose else A @ x)
+        if transpose:
+            bc = self.P[l].T @ r
+        else:
+            bc = self.R[l] @ r
+        xc = self.vcycle(bc, l - 1, transpose)
+        x = x + (self.R[l].T @ xc if transpose else self.P[l] @ xc)
+        x = self._sweeps(l, b, x, n2, transpose)
+        return x
+
+    def dense_preconditioner(self, transpose=False) -> np.ndarray:
+        N = self.A[-1].shape[0]
+        M = np.zeros((N, N))
+        for i in range(N):
+            e = np.zeros(N)
+            e[i] = 1.0
+            M[:, i] = self.vcycle(e, transpose=transpose)
+        return M

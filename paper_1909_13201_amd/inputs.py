@@ -1,0 +1,237 @@
+"""Seeded synthetic workloads for the FS-AS-GMG-GMRES solver.
+
+This module only describes problems and draws random numbers: mesh shape,
+material constants, boundary-condition tags, the seeded nodal body force and
+the seeded advecting velocity of the Oseen linearization.  It holds none of
+the solver's arithmetic (no assembly, no transfer, no smoother), so both the
+CPU oracle and the GPU library can be fed from it without sharing code.
+
+Configurations (stand-ins for the paper's aneurysm / valve meshes, which are
+not public; Section 4 of the paper):
+
+* ``c1``  2D unit square, coarse 4x4, 2 levels (finest 8x8).  Bottom coarse row
+  is a linear-elastic solid (E=1e3, nu=0.3), Stokes fluid above (mu=1e-2),
+  parabolic inflow, clamped bottom.  2x2-element subdomains with a one-element
+  halo (the literal Vanka rule), 2 pre/post sweeps, FP64.
+* ``c2``  2D straight channel, coarse 8x8 graded (walls of height 0.1 at top
+  and bottom are solid, E=1e4, nu=0.45), 5 levels (finest 128x128), fluid
+  mu=3.5e-3, Oseen about a seeded smooth field of amplitude 1, SUPG on,
+  4x4-element subdomains.
+* ``c3``  2D aneurysm-like channel with a circular bulge (radius 0.3) on the
+  top wall, coarse 16x8, 6 levels (finest 512x256), 2-element-thick walls.
+* ``c5``  c2 at 4 levels (finest 64x64), one backward-Euler step dt = 1/32,
+  with 32 seeded (load, E, mu) samples.
+
+``dt`` absent (or inf) means the steady problem.
+
+Conventions shared by every consumer (a data format, not arithmetic):
+
+* Element ``(ex, ey)`` is stored x-fastest; ``region`` is 1 for solid, 0 for
+  fluid, given on the coarse mesh and inherited by refinement.
+* Faces are numbered 0:x-min 1:x-max 2:y-min 3:y-max (4:z-min 5:z-max).
+* ``bc_d[face][region]``: 0 natural, 1 homogeneous Dirichlet on displacement.
+* ``bc_u[face][region]``: 0 natural, 1 no-slip (u=0), 2 parabolic inflow.
+* The finest-level Q2 node grid has ``2*nc[a]*2**(L-1)+1`` nodes per axis,
+  numbered x-fastest; nodal arrays are ``(N2, dim)`` row-major.
+"""
+from __future__ import annotations
+
+import copy
+import numpy as np
+
+FACE_XMIN, FACE_XMAX, FACE_YMIN, FACE_YMAX, FACE_ZMIN, FACE_ZMAX = range(6)
+MAP_IDENTITY, MAP_BULGE = 0, 1
+
+
+def _uniform(n, lo=0.0, hi=1.0):
+    return list(np.linspace(lo, hi, n + 1))
+
+
+def _bc_tables():
+    return [[0, 0] for _ in range(6)], [[0, 0] for _ in range(6)]
+
+
+def _channel_bcs():
+    """Straight channel: solid walls clamped at both ends, fluid inflow on x-min,
+    natural outflow on x-max, mesh displacement fixed on fluid outer faces."""
+    bc_d, bc_u = _bc_tables()
+    for f in (FACE_XMIN, FACE_XMAX):
+        bc_d[f][1] = 1          # solid clamped at inlet and outlet ends
+        bc_d[f][0] = 1          # fluid mesh displacement fixed
+    bc_u[FACE_XMIN][0] = 2      # parabolic inflow
+    return bc_d, bc_u
+
+
+def config(name: str) -> dict:
+    """Return a fresh description of configuration ``name``."""
+    if name == "c1":
+        bc_d, bc_u = _bc_tables()
+        bc_d[FACE_YMIN][1] = 1                      # bottom clamped
+        bc_d[FACE_XMIN][0] = bc_d[FACE_XMAX][0] = bc_d[FACE_YMAX][0] = 1
+        bc_u[FACE_XMIN][0] = 2                      # inflow
+        bc_u[FACE_YMAX][0] = 1                      # top wall
+        region = np.zeros((4, 4), np.int8)
+        region[0, :] = 1
+        cfg = dict(dim=2, n_levels=2, nc=(4, 4), breaks=(_uniform(4), _uniform(4)),
+                   region=region.ravel(), mapping=MAP_IDENTITY, map_params=[],
+                   bc_d=bc_d, bc_u=bc_u, inflow_peak=1.0,
+                   E=1e3, nu=0.3, mu=1e-2, rho=1.0, supg=False, w_amp=0.0,
+                   ale_k=0, k_mass=0,
+                   core=(2, 2), halo=1, nu_pre=2, nu_post=2, omega=1.0,
+                   restart=30, rtol=1e-10, seed=0)
+    elif name in ("c2", "c5"):
+        bc_d, bc_u = _channel_bcs()
+        yb = [0.0] + list(np.linspace(0.1, 0.9, 7)) + [1.0]
+        region = np.zeros((8, 8), np.int8)
+        region[0, :] = 1
+        region[7, :] = 1
+        cfg = dict(dim=2, n_levels=5, nc=(8, 8), breaks=(_uniform(8), yb),
+                   region=region.ravel(), mapping=MAP_IDENTITY, map_params=[],
+                   bc_d=bc_d, bc_u=bc_u, inflow_peak=1.0,
+                   E=1e4, nu=0.45, mu=3.5e-3, rho=1.0, supg=True, w_amp=1.0,
+                   ale_k=0, k_mass=0,
+                   core=(4, 4), halo=1, nu_pre=2, nu_post=2, omega=1.0,
+                   restart=30, rtol=1e-10, seed=0)
+        if name == "c5":
+            cfg["n_levels"] = 4
+            cfg["batch"] = 32
+            # one backward-Euler step of the time-periodic problem (32 steps per
+            # period, Section 4): makes u^s = dd/dt so the outlet flux depends on
+            # the wall stiffness (the steady problem is one-way coupled)
+            cfg["dt"] = 1.0 / 32.0
+    elif name == "c3":
+        bc_d, bc_u = _channel_bcs()
+        yb = [0.0, 0.05, 0.1, 0.3, 0.5, 0.7, 0.9, 0.95, 1.0]
+        region = np.zeros((8, 16), np.int8)
+        region[0:2, :] = 1
+        region[6:8, :] = 1
+        cfg = dict(dim=2, n_levels=6, nc=(16, 8), breaks=(_uniform(16, 0.0, 2.0), yb),
+                   region=region.ravel(), mapping=MAP_BULGE,
+                   # bulge centre x, radius, blend start y, blend end y
+                   map_params=[1.0, 0.3, 0.5, 0.9],
+                   bc_d=bc_d, bc_u=bc_u, inflow_peak=1.0,
+                   E=1e4, nu=0.45, mu=3.5e-3, rho=1.0, supg=True, w_amp=1.0,
+                   ale_k=0, k_mass=0,
+                   core=(4, 4), halo=1, nu_pre=2, nu_post=2, omega=1.0,
+                   restart=30, rtol=1e-10, seed=0)
+    else:
+        raise KeyError(name)
+    cfg["name"] = name
+    return cfg
+
+
+def with_levels(cfg: dict, n_levels: int) -> dict:
+    """Copy of ``cfg`` with a different number of levels (same coarse mesh)."""
+    out = copy.deepcopy(cfg)
+    out["n_levels"] = int(n_levels)
+    return out
+
+
+# ----------------------------------------------------------------------------
+# finest-grid index helpers (pure bookkeeping)
+# ----------------------------------------------------------------------------
+
+def finest_elems(cfg: dict) -> tuple:
+    s = 2 ** (cfg["n_levels"] - 1)
+    return tuple(int(n) * s for n in cfg["nc"])
+
+
+def finest_nodes_shape(cfg: dict) -> tuple:
+    return tuple(2 * n + 1 for n in finest_elems(cfg))
+
+
+def n_finest_nodes(cfg: dict) -> int:
+    return int(np.prod(finest_nodes_shape(cfg)))
+
+
+def _refined_breaks(b, times):
+    b = np.asarray(b, float)
+    for _ in range(times):
+        mid = 0.5 * (b[:-1] + b[1:])
+        out = np.empty(2 * len(b) - 1)
+        out[0::2] = b
+        out[1::2] = mid
+        b = out
+    return b
+
+
+def finest_node_reference_coords(cfg: dict) -> list:
+    """Per-axis reference coordinates of the finest Q2 node lines."""
+    return [_refined_breaks(cfg["breaks"][a], cfg["n_levels"])
+            for a in range(cfg["dim"])]
+
+
+# ----------------------------------------------------------------------------
+# seeded random inputs
+# ----------------------------------------------------------------------------
+
+def body_force(cfg: dict, seed: int | None = None) -> np.ndarray:
+    """Nodal body force f ~ U[-1,1]^dim at every finest Q2 node, shape (N2, dim)."""
+    rng = np.random.default_rng(cfg["seed"] if seed is None else seed)
+    return rng.uniform(-1.0, 1.0, size=(n_finest_nodes(cfg), cfg["dim"]))
+
+
+def _fluid_box(cfg: dict):
+    """Reference-coordinate bounding box of the fluid region (2D only)."""
+    nc = cfg["nc"]
+    reg = np.asarray(cfg["region"]).reshape(nc[1], nc[0])
+    rows = np.where((reg == 0).any(axis=1))[0]
+    cols = np.where((reg == 0).any(axis=0))[0]
+    xb, yb = cfg["breaks"][0], cfg["breaks"][1]
+    return (xb[cols.min()], xb[cols.max() + 1]), (yb[rows.min()], yb[rows.max() + 1])
+
+
+def advecting_field(cfg: dict, seed: int | None = None) -> np.ndarray | None:
+    """Seeded smooth advecting velocity w at every finest Q2 node, shape (N2, dim).
+
+    w = (d psi/dt, -d psi/ds) with psi = (t(1-t))^2 sum_{k,l<=3} a_kl sin(k pi s)
+    sin(l pi t), a_kl ~ N(0,1), where (s, t) are the reference coordinates
+    normalised to the fluid box.  w vanishes outside the open fluid box (so on
+    the fluid-solid interface) and is scaled to max |w|_2 = w_amp.  Returns
+    None when w_amp == 0.
+    """
+    if not cfg.get("w_amp", 0.0):
+        return None
+    if cfg["dim"] != 2:
+        raise NotImplementedError("advecting field is defined for 2D configurations")
+    rng = np.random.default_rng(1000 + (cfg["seed"] if seed is None else seed))
+    a = rng.standard_normal((3, 3))
+    (x0, x1), (y0, y1) = _fluid_box(cfg)
+    xr, yr = finest_node_reference_coords(cfg)
+    X, Y = np.meshgrid(xr, yr, indexing="xy")          # (ny, nx): x fastest
+    s = (X - x0) / (x1 - x0)
+    t = (Y - y0) / (y1 - y0)
+    inside = (s > 0) & (s < 1) & (t > 0) & (t < 1)
+    B = (t * (1 - t)) ** 2
+    dB = 2 * t * (1 - t) * (1 - 2 * t)
+    S = np.zeros_like(s)
+    dS_ds = np.zeros_like(s)
+    dS_dt = np.zeros_like(s)
+    for k in range(1, 4):
+        for l in range(1, 4):
+            sk, ck = np.sin(k * np.pi * s), np.cos(k * np.pi * s)
+            sl, cl = np.sin(l * np.pi * t), np.cos(l * np.pi * t)
+            S += a[k - 1, l - 1] * sk * sl
+            dS_ds += a[k - 1, l - 1] * k * np.pi * ck * sl
+            dS_dt += a[k - 1, l - 1] * l * np.pi * sk * cl
+    wx = dB * S + B * dS_dt
+    wy = -B * dS_ds
+    wx = np.where(inside, wx, 0.0)
+    wy = np.where(inside, wy, 0.0)
+    w = np.stack([wx.ravel(), wy.ravel()], axis=1)
+    mx = np.sqrt((w ** 2).sum(axis=1)).max()
+    return w * (cfg["w_amp"] / mx)
+
+
+def sample_parameters(cfg: dict, batch: int, seed: int | None = None):
+    """Log-uniform (E, mu) pairs in [1e3,1e5] x [1e-3,1e-1], shape (batch, 2)."""
+    rng = np.random.default_rng(2000 + (cfg["seed"] if seed is None else seed))
+    logE = rng.uniform(3.0, 5.0, size=batch)
+    logmu = rng.uniform(-3.0, -1.0, size=batch)
+    return np.stack([10.0 ** logE, 10.0 ** logmu], axis=1)
+
+
+def sample_loads(cfg: dict, batch: int, seed: int | None = None) -> np.ndarray:
+    """Batch of nodal body forces, shape (batch, N2, dim)."""
+    base = cfg["seed"] if seed is None else seed
+    return np.stack([body_force(cfg, seed=base + 100 + i) for i in range(batch)])
