@@ -1,0 +1,228 @@
+"""Benchmark of the FS-AS-GMG-FGMRES solve on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2]
+
+A step is one full solve of A x = b to a true relative residual of 1e-10
+(FGMRES(30) right-preconditioned by one V-cycle per iteration: finest-level
+operator products, CGS2 dot products, Givens updates, and in the V-cycle the
+residual products, the FS-AS smoother sweeps, restriction, the coarse FP64
+solve and prolongation on every level), with the hierarchy and the block
+factors built before the timed region and b resident on the GPU.  `value` is
+solves/s of the mixed-precision path (FP32 smoother and level operators, FP64
+Krylov, outer products and coarse solve); the FP64 path, V-cycles/s, the
+setup times, one adjoint solve, the roofline of the dominant kernel (the
+finest-level smoother sweep, timed with HIP events on the library's stream
+over the timed solves) and the CPU oracle's time are reported beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "solves/s to 1e-10 rel. residual, mixed vs FP64 FS-AS-GMG-GMRES; V-cycles/s"
+HBM_PEAK_GBS = 8000.0
+WORKLOADS = {
+    "c2": "2D straight channel, coarse 8x8 graded -> finest 128x128 Q2/Q1 (5 levels, "
+          "281,095 unknowns), solid walls E=1e4 nu=0.45, fluid mu=3.5e-3, Oseen about a "
+          "seeded field of amplitude 1 with SUPG, FS-AS on 4x4-element cores with the "
+          "one-element Vanka halo, 2+2 sweeps",
+    "c1": "2D unit square, coarse 4x4 -> 8x8 (2 levels), solid bottom row, Stokes fluid",
+    "c3": "2D aneurysm-like channel with circular bulge, coarse 16x8 -> 512x256 (6 levels)",
+}
+
+
+def smoother_bytes(H, level, prec):
+    """Algorithmic bytes of one FS-AS sweep on `level`: owned rows of every
+    block inverse (n_j x m_j values), the gather / scatter index lists, and
+    the residual read plus the correction read and write (one pass each)."""
+    from paper_1909_13201_amd import fsgmg
+    ptr, dofs, owner = fsgmg.export_blocks(H.h, level)
+    n = np.diff(ptr)
+    own = owner[owner >= 0]
+    m = np.bincount(own, minlength=len(n))
+    sW = {"fp64": 8, "fp32": 4, "bf16": 2}[prec]
+    sV = 8 if prec == "fp64" else 4
+    N = H.info[level]["N"]
+    return int((n * m).sum() * sW + 4 * (n.sum() + m.sum()) + 3 * N * sV), int(len(n))
+
+
+def timed_solves(H, b, x, steps, warmup, rtol):
+    import torch
+    infos = []
+    for _ in range(warmup):
+        H.gmres_solve(b, x, restart=30, rtol=rtol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        infos.append(H.gmres_solve(b, x, restart=30, rtol=rtol))
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    return t, infos
+
+
+def cpu_baseline(cfg, w, f):
+    """The oracle as it stands: one full FGMRES solve of the same workload on
+    the host (hierarchy and LU factors built first, untimed)."""
+    try:
+        from threadpoolctl import threadpool_limits
+        limiter = threadpool_limits(1)
+    except Exception:   # pragma: no cover
+        limiter = None
+    from oracle.krylov import fgmres
+    from oracle.multigrid import Hierarchy as OracleHierarchy
+    t0 = time.perf_counter()
+    O = OracleHierarchy(cfg, w)
+    t_setup = time.perf_counter() - t0
+    b = O.rhs(f)
+    A = O.A[-1]
+    t0 = time.perf_counter()
+    x, info = fgmres(lambda v: A @ v, O.vcycle, b, restart=30, rtol=cfg["rtol"])
+    t = time.perf_counter() - t0
+    if limiter is not None:
+        limiter.unregister() if hasattr(limiter, "unregister") else None
+    return dict(value=1.0 / t, unit="solves/s", cores=1, kind="oracle",
+                sample="one full FGMRES(30) solve of the same %s workload to 1e-10 "
+                       "(%d iterations, %.1f s; hierarchy and block LUs built "
+                       "beforehand in %.1f s, untimed), NumPy/SciPy FP64, one thread"
+                       % (cfg["name"], info["iters"], t, t_setup))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="c2")
+    ap.add_argument("--levels", type=int, default=0, help="override the number of levels")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--bf16", action="store_true", help="also time BF16-stored block inverses")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the solver has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1909_13201_amd import fsgmg, inputs
+
+    cfg = inputs.config(args.config)
+    if args.levels:
+        cfg = inputs.with_levels(cfg, args.levels)
+    w = inputs.advecting_field(cfg)
+    f = inputs.body_force(cfg)
+    rtol = cfg["rtol"]
+    dev = torch.device("cuda:0")
+
+    t0 = time.perf_counter()
+    H = fsgmg.Hierarchy(cfg, w, device=0)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    b = torch.zeros(H.N, dtype=torch.float64, device=dev)
+    H.assemble_load(torch.tensor(f.ravel(), dtype=torch.float64, device=dev), b)
+    x64 = torch.zeros_like(b)
+    x32 = torch.zeros_like(b)
+
+    res = {}
+    # ---- plain FP64 path ----
+    t0 = time.perf_counter()
+    H.build_fs_as_blocks(prec="fp64")
+    torch.cuda.synchronize()
+    t_blocks64 = time.perf_counter() - t0
+    t64, inf64 = timed_solves(H, b, x64, args.steps, args.warmup, rtol)
+    # ---- mixed FP32 path (the reported value) ----
+    t0 = time.perf_counter()
+    H.build_fs_as_blocks(prec="fp32")
+    torch.cuda.synchronize()
+    t_blocks32 = time.perf_counter() - t0
+    for _ in range(args.warmup):
+        H.gmres_solve(b, x32, restart=30, rtol=rtol)
+    torch.cuda.synchronize()
+    H.kernel_timing(True)
+    t0 = time.perf_counter()
+    inf32 = []
+    for _ in range(args.steps):
+        inf32.append(H.gmres_solve(b, x32, restart=30, rtol=rtol))
+    torch.cuda.synchronize()
+    t32 = time.perf_counter() - t0
+    ktime = H.kernel_timing(False)
+    # V-cycles/s (mixed)
+    r = b / b.norm()
+    z = torch.zeros_like(b)
+    for _ in range(3):
+        H.vcycle_apply(r, z)
+    torch.cuda.synchronize()
+    nv = max(20, 5 * args.steps)
+    t0 = time.perf_counter()
+    for _ in range(nv):
+        H.vcycle_apply(r, z)
+    torch.cuda.synchronize()
+    tv = time.perf_counter() - t0
+    # adjoint solve (mixed)
+    c = torch.zeros_like(b)
+    c[H.info[-1]["off_u"]:H.info[-1]["off_u"] + 2 * H.info[-1]["N2"]:2] = 1.0
+    lam = torch.zeros_like(b)
+    t0 = time.perf_counter()
+    ainfo = H.adjoint_solve(c, lam, rtol=rtol)
+    torch.cuda.synchronize()
+    t_adj = time.perf_counter() - t0
+    bf = None
+    if args.bf16:
+        H.build_fs_as_blocks(prec="bf16")
+        xb = torch.zeros_like(b)
+        tb, infb = timed_solves(H, b, xb, args.steps, 1, rtol)
+        bf = dict(solves_per_s=args.steps / tb, iters=infb[-1]["iters"],
+                  rel_res_true=infb[-1]["rel_res_true"])
+        H.build_fs_as_blocks(prec="fp32")
+
+    x64h = x64.double()
+    rel_diff = float((x32 - x64h).norm() / x64h.norm())
+    sm_bytes, nblk = smoother_bytes(H, H.L - 1, "fp32")
+    n_sm, ms_sm = ktime["smoother"]
+    avg_ms = ms_sm / max(n_sm, 1)
+    achieved = sm_bytes / (avg_ms * 1e-3) / 1e9
+    roof = dict(bound="hbm", kernel="k_smooth_fwd<float,float> (finest level)",
+                achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                bytes_per_launch=sm_bytes, blocks_per_launch=nblk,
+                avg_launch_us=round(avg_ms * 1e3, 2), launches=n_sm)
+    other = {}
+    for k in ("vspmv", "outer_spmv", "transfer"):
+        n, ms = ktime[k]
+        other[k] = dict(launches=n, avg_us=round(ms * 1e3 / max(n, 1), 2))
+
+    sps32 = args.steps / t32
+    sps64 = args.steps / t64
+    out = dict(metric=METRIC, value=round(sps32, 4), unit="solves/s", n_gpus=1,
+               steps=args.steps, warmup=args.warmup,
+               ms_per_step=round(1e3 * t32 / args.steps, 3), higher_is_better=True,
+               scaling="weak", vs_baseline=None, dtype="f32 smoother + f64 Krylov",
+               data="synthetic",
+               config=dict(workload=WORKLOADS.get(cfg["name"], cfg["name"]),
+                           name=cfg["name"], levels=int(cfg["n_levels"]), unknowns=H.N,
+                           core=list(cfg["core"]), halo=cfg["halo"], restart=30, rtol=rtol),
+               fp64_solves_per_s=round(sps64, 4), mixed_over_fp64=round(sps32 / sps64, 3),
+               vcycles_per_s=round(nv / tv, 2), iters_mixed=inf32[-1]["iters"],
+               iters_fp64=inf64[-1]["iters"], rel_res_true_mixed=inf32[-1]["rel_res_true"],
+               rel_res_true_fp64=inf64[-1]["rel_res_true"], rel_diff_mixed_vs_fp64=rel_diff,
+               setup_hierarchy_s=round(t_setup, 3), build_blocks_fp64_s=round(t_blocks64, 3),
+               build_blocks_fp32_s=round(t_blocks32, 3),
+               adjoint=dict(seconds=round(t_adj, 4), iters=ainfo["iters"],
+                            rel_res_true=ainfo["rel_res_true"]),
+               kernels=other, roofline=roof)
+    if bf is not None:
+        out["bf16_factors"] = bf
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, w, f)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,205 @@
+/*
+ * fsgmg — field-split additive-Schwarz geometric multigrid + FGMRES for the
+ * linearized monolithic fluid-structure-interaction system on MI355X (gfx950).
+ *
+ * Method: Calandrini, Aulisa, Ke, "A field-split preconditioning technique for
+ * fluid-structure interaction problems with applications in biomedicine":
+ *   - the system is ordered as J2 (Section 3.2, eq. matrix_J2): unknowns
+ *     d^s d^f p^s | u^s u^f p^f, equations S A V | K F W;
+ *   - outer GMRES preconditioned by one geometric-multigrid V-cycle
+ *     (Section 3.2): damped Richardson on levels l >= 1, direct solve on l = 0;
+ *   - the Richardson smoother is the additive field-split preconditioner P_2
+ *     (eq. FS) whose field blocks are solved by additive Schwarz AS_1 / AS_2
+ *     (Vanka saddle-point blocks, overlapping ALE blocks, Jacobi on the
+ *     lumped kinematic mass), last-writer additive update (Section 3.2);
+ *   - prolongation = natural injection, restriction = the equation-routed
+ *     R_2 of Section 3.3 (not P^T).
+ *
+ * Vector layout of a level (all vectors crossing this ABI are the finest
+ * level, FP64, device memory unless stated otherwise):
+ *   [ d (dim*N2, node-major) | p^s (Nps) | u (dim*N2) | p^f (Npf) ]
+ * N2 = Q2 nodes, numbered x-fastest; p^s / p^f = Q1 vertices of solid / fluid
+ * elements in vertex order.  Offsets are returned by level_info().
+ *
+ * Ownership: the handle owns every matrix, transfer, block inverse and
+ * Krylov work vector (device memory from hipMalloc on the handle's device).
+ * Vector arguments are caller-owned and must not alias each other.
+ * Streams: all device work is enqueued on the stream given to
+ * setup_hierarchy (NULL = default stream).  vcycle_apply, apply_operator and
+ * assemble_load are asynchronous; gmres_solve and adjoint_solve return after
+ * the convergence decision.  Handles are not thread-safe.
+ * Errors: every call returns an fsgmg_status; no exception crosses the ABI;
+ * last_error() gives a message for the last failing call on a handle.
+ */
+#ifndef FSGMG_H
+#define FSGMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fsgmg_hierarchy* fsgmg_h;
+
+typedef enum {
+  FSGMG_OK = 0,
+  FSGMG_NOT_CONVERGED = 1, /* x holds the last iterate, info is filled */
+  FSGMG_EINVAL = -1,       /* bad argument (sizes, NULL, NaN/Inf in b)  */
+  FSGMG_EHIP = -2,         /* a HIP runtime call failed                */
+  FSGMG_ESINGULAR = -3,    /* a zero pivot in a block or coarse matrix */
+  FSGMG_ENOMEM = -4,       /* device or host allocation failed         */
+  FSGMG_ESTATE = -5        /* call not valid in this state (e.g. no blocks
+                              built yet, or a device call on a host-only
+                              handle)                                  */
+} fsgmg_status;
+
+typedef enum { FSGMG_FP64 = 0, FSGMG_FP32 = 1, FSGMG_BF16 = 2 } fsgmg_prec;
+
+/* Nested structured mesh (Section 3.3: every level is the midpoint
+ * refinement of a conforming coarse mesh, regions are the same on every
+ * level).  Faces: 0 x-min, 1 x-max, 2 y-min, 3 y-max, 4 z-min, 5 z-max.
+ * bc_d[face][region]: 0 natural, 1 d = 0.  bc_u[face][region]: 0 natural,
+ * 1 u = 0, 2 parabolic inflow of peak inflow_peak over the fluid extent of
+ * the face.  A tag applies to every node of the face that belongs to an
+ * element of that region.  region: 0 fluid, 1 solid. */
+typedef struct {
+  int dim;                     /* 2 (3 reserved)                          */
+  int n_levels;                /* >= 1; level 0 = coarse mesh             */
+  int nc[3];                   /* coarse elements per axis                */
+  const double* breaks[3];     /* host, nc[a]+1 reference breakpoints     */
+  const int8_t* region;        /* host, prod(nc) tags, x fastest          */
+  int mapping;                 /* 0 identity, 1 circular bulge (2D)       */
+  double map_params[8];        /* bulge: centre x, radius, blend y0, y1   */
+  int8_t bc_d[6][2];
+  int8_t bc_u[6][2];
+  double inflow_peak;
+} fsgmg_mesh_desc;
+
+/* Linearized physics (Section 2.2 at the stress-free state, frozen advecting
+ * velocity w): solid G = E/(2(1+nu)), 1/lambda_L = (1+nu)(1-2nu)/(E nu);
+ * Newtonian fluid mu; density rho; dt > 0 finite adds one backward-Euler
+ * step (K_ds = -K_us/dt and rho M/dt inertia), dt <= 0 or inf is steady.
+ * supg != 0 enables SUPG (eqs. tausupg, lambda_k).  ale_k: 0 k = 1/V of the
+ * coarse element containing the point, 1 k = 1.  k_mass: 0 lumped, 1
+ * consistent kinematic mass.  w: host array (finest N2 x dim) or NULL. */
+typedef struct {
+  double E, nu, mu, rho, dt;
+  int supg, ale_k, k_mass;
+  const double* w;
+} fsgmg_physics;
+
+/* Smoother: cores of core[0] x core[1] elements per region, Vanka halo of
+ * `halo` element layers (1 = the paper's selection rule), nu_pre / nu_post
+ * Richardson sweeps with damping omega, block inverses and level operators
+ * of the V-cycle in `prec` (the coarse solve is always FP64; FSGMG_BF16
+ * stores block inverses in bfloat16 and keeps FP32 level operators).
+ * use_graph != 0 captures the V-cycle in a HIP graph. */
+typedef struct {
+  int core[3];
+  int halo;
+  int nu_pre, nu_post;
+  double omega;
+  fsgmg_prec prec;
+  int use_graph;
+} fsgmg_smoother_opts;
+
+/* FGMRES(restart), right preconditioned, x0 = 0, CGS2; converged when the
+ * true residual ||b - A x||_2 <= rtol ||b||_2. */
+typedef struct {
+  int restart;       /* 1..64 */
+  int max_restarts;
+  double rtol;
+} fsgmg_krylov_opts;
+
+typedef struct {
+  int iters;          /* Arnoldi steps (= preconditioner applications) */
+  int restarts;
+  int converged;
+  double rel_res_true;
+  double* history;    /* host, optional: Givens estimates / ||b||         */
+  int history_cap;
+  int history_len;
+  double t_solve_ms;  /* wall time of the call                           */
+} fsgmg_solve_info;
+
+/* Build the mesh hierarchy, assemble every level operator (re-discretized,
+ * Dirichlet rows/columns eliminated symmetrically), the transfers and the
+ * coarse FP64 inverse.  device >= 0: upload to that HIP device and use
+ * `stream`; device == -1: host-only handle (export_* queries only). */
+fsgmg_status setup_hierarchy(const fsgmg_mesh_desc* mesh, const fsgmg_physics* phys,
+                             int device, void* stream, fsgmg_h* out);
+
+/* Build the FS-AS block index sets (Section 3.2 selection rule, last-writer
+ * owner map), gather every block's principal submatrix, invert it in FP64 on
+ * the device (partial pivoting) and keep the owned rows in opts->prec.
+ * ESINGULAR (block id in last_error) on a zero pivot.  On a host-only handle
+ * only the index sets are built. */
+fsgmg_status build_fs_as_blocks(fsgmg_h h, const fsgmg_smoother_opts* opts);
+
+/* z = M^{-1} r (transpose = 0) or z = M^{-T} r (transpose = 1), one V-cycle. */
+fsgmg_status vcycle_apply(fsgmg_h h, const double* r, double* z, int transpose);
+
+/* Solve A x = b on the finest level (x is overwritten; x0 = 0). */
+fsgmg_status gmres_solve(fsgmg_h h, const double* b, double* x,
+                         const fsgmg_krylov_opts* opts, fsgmg_solve_info* info);
+
+/* Solve A^T lam = c with the transposed V-cycle as right preconditioner. */
+fsgmg_status adjoint_solve(fsgmg_h h, const double* c, double* lam,
+                           const fsgmg_krylov_opts* opts, fsgmg_solve_info* info);
+
+/* b = F (L f) + lift: momentum load rho (f_h, phi) (+ SUPG) of a nodal body
+ * force f (device, finest N2 x dim), Dirichlet rows set to their values and
+ * the Dirichlet lift applied (F zeroes Dirichlet rows). */
+fsgmg_status assemble_load(fsgmg_h h, const double* f_nodal, double* b);
+
+/* y = A_l x or A_l^T x on level `level` (FP64 operator, device vectors of
+ * that level's size). */
+fsgmg_status apply_operator(fsgmg_h h, int level, const double* x, double* y, int transpose);
+
+/* out[0] = -(F lam)^T dA/dE x, out[1] = -(F lam)^T dA/dmu x on the finest
+ * level (unreduced derivative, tau frozen); lam, x device; out host. */
+fsgmg_status param_grad(fsgmg_h h, const double* lam, const double* x, double out[2]);
+
+/* Recombine every level operator and the Dirichlet lift for new (E, mu)
+ * from the stored affine pieces (SUPG tau frozen at setup).  Invalidates the
+ * blocks: call build_fs_as_blocks again. */
+fsgmg_status update_params(fsgmg_h h, double E, double mu);
+
+/* out[0..8] = N, N2, Nps, Npf, off_ps, off_u, off_pf, nnz(A_l), dim. */
+fsgmg_status level_info(fsgmg_h h, int level, int64_t out[9]);
+
+/* Host copies of setup data (inspection and tests).  which: 0 reduced level
+ * operator A_l, 1 prolongation P_l (level l from l-1, Dirichlet-masked),
+ * 2 restriction R_l (level l-1 from l, equation-routed, Dirichlet-masked),
+ * 3 load operator L of the finest level (N x dim*N2).  Call with NULL
+ * arrays to get sizes in dims[0..2] = rows, cols, nnz. */
+fsgmg_status export_csr(fsgmg_h h, int level, int which, int64_t dims[3],
+                        int64_t* rowptr, int32_t* col, double* val);
+
+/* Host copy of a level vector: which 0 = Dirichlet lift (finest), 1 =
+ * Dirichlet mask (1.0 / 0.0). */
+fsgmg_status export_vector(fsgmg_h h, int level, int which, double* out);
+
+/* Block index sets of level l: sizes[0] = number of blocks, sizes[1] = total
+ * entries; ptr (nblk+1), dofs (total, sorted per block), owner (N, -1 if
+ * none). */
+fsgmg_status export_blocks(fsgmg_h h, int level, int64_t sizes[2], int64_t* ptr,
+                           int32_t* dofs, int32_t* owner);
+
+/* Measurement: enable != 0 starts recording HIP events on the handle's
+ * stream around selected launches (cleared on start); enable == 0 stops,
+ * synchronizes and returns per kind the number of launches and their summed
+ * duration: 0 smoother sweep on the finest level, 1 residual SpMV of the
+ * V-cycle on the finest level, 2 outer FP64 SpMV of FGMRES, 3 restriction +
+ * prolongation between the two finest levels.  counts / total_ms may be NULL. */
+fsgmg_status kernel_timing(fsgmg_h h, int enable, int64_t counts[4], double total_ms[4]);
+
+const char* last_error(fsgmg_h h);
+void hierarchy_destroy(fsgmg_h h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FSGMG_H */

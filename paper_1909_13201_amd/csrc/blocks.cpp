@@ -1,0 +1,126 @@
+// Field-split additive Schwarz block index sets (paper Section 3.2).
+//
+// The level is split into the fields [d, p^s] and [u, p^f] (eq. FS).  Each
+// region is tiled by non-overlapping element-aligned cores of core[] elements.
+// Vanka rule: a block takes the pressures whose support meets the core (the
+// Q1 vertices of the core's elements) and the displacements / velocities
+// whose support meets the support of those pressures: the Q2 nodes of the
+// core's elements grown by `halo` element layers of the same region.
+//   field d, solid core: d of those nodes + p^s      ([S_ds S_ps; V_ds 0])
+//   field d, fluid core: d of fluid nodes only        ([A_df], overlapping DD)
+//   field u, fluid core: u of fluid nodes + p^f       ([F_uf F_pf; W_uf 0])
+//   u^s: Jacobi on the lumped mass (no block).
+// Dirichlet unknowns belong to no block.  Order: field d then field u, tiles
+// x-fastest, solid before fluid within a tile.  owner(i) = last block that
+// contains i (the additive update takes entry i from the last block).
+#include <algorithm>
+#include <stdexcept>
+
+#include "host.hpp"
+
+namespace fsgmg {
+
+void build_blocks(const Level& lv, const int* core, int halo, BlockSet& bs) {
+  const int D = lv.D;
+  int nt[kMaxDim] = {1, 1, 1};
+  int64_t ntiles = 1;
+  for (int a = 0; a < D; ++a) {
+    if (core[a] < 1) throw std::invalid_argument("core size must be >= 1");
+    nt[a] = (lv.ne[a] + core[a] - 1) / core[a];
+    ntiles *= nt[a];
+  }
+  bs.ptr.assign(1, 0);
+  bs.dofs.clear();
+  std::vector<int32_t> stamp_el(lv.nE, -1), stamp_node(lv.N2, -1), stamp_vert(lv.NV, -1);
+  int32_t stamp = 0;
+  std::vector<int64_t> core_el, blk_el, dofs;
+  for (int field = 0; field < 2; ++field) {
+    for (int64_t t = 0; t < ntiles; ++t) {
+      int tx[kMaxDim] = {0, 0, 0};
+      int64_t tt = t;
+      for (int a = 0; a < D; ++a) {
+        tx[a] = (int)(tt % nt[a]);
+        tt /= nt[a];
+      }
+      const int regions[2] = {1, 0};
+      for (int ri = (field == 0 ? 0 : 1); ri < 2; ++ri) {
+        const int region = regions[ri];
+        core_el.clear();
+        int lo[kMaxDim] = {0, 0, 0}, hi[kMaxDim] = {1, 1, 1};
+        for (int a = 0; a < D; ++a) {
+          lo[a] = tx[a] * core[a];
+          hi[a] = std::min(lo[a] + core[a], lv.ne[a]);
+        }
+        for (int z = lo[2]; z < (D > 2 ? hi[2] : 1); ++z)
+          for (int y = lo[1]; y < hi[1]; ++y)
+            for (int x = lo[0]; x < hi[0]; ++x) {
+              const int64_t e = x + (int64_t)lv.ne[0] * (y + (int64_t)lv.ne[1] * z);
+              if (lv.region[e] == region) core_el.push_back(e);
+            }
+        if (core_el.empty()) continue;
+        ++stamp;
+        blk_el.clear();
+        for (int64_t e : core_el) {
+          int ex[kMaxDim] = {0, 0, 0};
+          int64_t r = e;
+          for (int a = 0; a < D; ++a) {
+            ex[a] = (int)(r % lv.ne[a]);
+            r /= lv.ne[a];
+          }
+          const int hz = D > 2 ? halo : 0;
+          for (int dz = -hz; dz <= hz; ++dz)
+            for (int dy = -halo; dy <= halo; ++dy)
+              for (int dx = -halo; dx <= halo; ++dx) {
+                const int q[3] = {ex[0] + dx, ex[1] + dy, D > 2 ? ex[2] + dz : 0};
+                bool ok = true;
+                for (int a = 0; a < D; ++a) ok &= q[a] >= 0 && q[a] < lv.ne[a];
+                if (!ok) continue;
+                const int64_t n = q[0] + (int64_t)lv.ne[0] * (q[1] + (int64_t)lv.ne[1] * q[2]);
+                if (lv.region[n] != region || stamp_el[n] == stamp) continue;
+                stamp_el[n] = stamp;
+                blk_el.push_back(n);
+              }
+        }
+        dofs.clear();
+        for (int64_t e : blk_el)
+          for (int k = 0; k < lv.nb; ++k) {
+            const int64_t n = lv.elem_nodes[e * lv.nb + k];
+            if (stamp_node[n] == stamp) continue;
+            stamp_node[n] = stamp;
+            const bool ss = lv.solid_side[n];
+            if (field == 0 && region == 1) {
+              for (int c = 0; c < D; ++c) dofs.push_back((int64_t)D * n + c);
+            } else if (field == 0) {
+              if (!ss)
+                for (int c = 0; c < D; ++c) dofs.push_back((int64_t)D * n + c);
+            } else {
+              if (!ss)
+                for (int c = 0; c < D; ++c) dofs.push_back(lv.off_u + (int64_t)D * n + c);
+            }
+          }
+        if (!(field == 0 && region == 0))
+          for (int64_t e : core_el)
+            for (int k = 0; k < lv.npv; ++k) {
+              const int64_t v = lv.elem_verts[e * lv.npv + k];
+              if (stamp_vert[v] == stamp) continue;
+              stamp_vert[v] = stamp;
+              dofs.push_back(region == 1 ? lv.ps_of_vert[v] : lv.pf_of_vert[v]);
+            }
+        std::sort(dofs.begin(), dofs.end());
+        size_t before = bs.dofs.size();
+        for (int64_t d : dofs)
+          if (!lv.dir[d]) bs.dofs.push_back((int32_t)d);
+        if (bs.dofs.size() == before) continue;
+        bs.ptr.push_back((int64_t)bs.dofs.size());
+      }
+    }
+  }
+  bs.owner.assign(lv.N, -1);
+  for (int64_t j = 0; j < bs.nblk(); ++j)
+    for (int64_t k = bs.ptr[j]; k < bs.ptr[j + 1]; ++k) bs.owner[bs.dofs[k]] = (int32_t)j;
+  bs.jac.clear();
+  for (int64_t i = 0; i < lv.N; ++i)
+    if (bs.owner[i] < 0) bs.jac.push_back((int32_t)i);
+}
+
+}  // namespace fsgmg

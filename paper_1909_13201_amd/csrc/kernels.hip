@@ -1,0 +1,1017 @@
+// HIP kernels of the fsgmg library for gfx950 (CDNA4, wave64).
+//
+//  * node-block SpMV / residual of a level operator (HBM-bound)
+//  * inter-grid transfers: natural-injection prolongation and the
+//    equation-routed restriction of paper Section 3.3, and their transposes
+//  * field-split additive Schwarz sweep: one workgroup per block gathers the
+//    block residual into LDS and multiplies it by the block inverse's owned
+//    rows (column-major, 16-byte vector loads); the last-writer update of
+//    Section 3.2 becomes a conflict-free scatter because every unknown has
+//    exactly one owner
+//  * block setup: gather of principal submatrices, in-place Gauss-Jordan
+//    inversion with partial pivoting (FP64), owned-row extraction
+//  * FGMRES building blocks: multi-vector dot products with fixed-order
+//    partial sums (deterministic), fused MAXPY + dot, norms
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include <cstdint>
+
+#include "kernels.hpp"
+
+namespace fsgmg {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kPartials = 512;    // workgroups of the Krylov reductions
+constexpr int kMaxK = 32;         // vectors per multi-dot (restart <= 31)
+
+inline unsigned grid_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+template <typename T>
+struct Acc {
+  using type = T;
+};
+
+// ------------------------------------------------------------------------
+// SpMV: LG lanes per node row block / pressure row
+// ------------------------------------------------------------------------
+template <typename T, int D, int LG>
+__global__ __launch_bounds__(kThreads) void k_spmv(BOpView<T> A, const T* __restrict__ x,
+                                                   const T* __restrict__ b, T* __restrict__ y,
+                                                   int residual) {
+  const int lane = threadIdx.x & (LG - 1);
+  const int64_t item = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LG;
+  if (item < A.nrb) {
+    T acc[D];
+#pragma unroll
+    for (int r = 0; r < D; ++r) acc[r] = T(0);
+    const int k1 = A.nn_ptr[item + 1];
+    for (int k = A.nn_ptr[item] + lane; k < k1; k += LG) {
+      const int c = A.nn_col[k];
+      const T* v = A.nn_val + (int64_t)k * (D * D);
+      T xv[D];
+#pragma unroll
+      for (int q = 0; q < D; ++q) xv[q] = x[c + q];
+#pragma unroll
+      for (int r = 0; r < D; ++r)
+#pragma unroll
+        for (int q = 0; q < D; ++q) acc[r] += v[r * D + q] * xv[q];
+    }
+    const int p1 = A.np_ptr[item + 1];
+    for (int k = A.np_ptr[item] + lane; k < p1; k += LG) {
+      const T xv = x[A.np_col[k]];
+      const T* v = A.np_val + (int64_t)k * D;
+#pragma unroll
+      for (int r = 0; r < D; ++r) acc[r] += v[r] * xv;
+    }
+#pragma unroll
+    for (int off = LG / 2; off > 0; off >>= 1)
+#pragma unroll
+      for (int r = 0; r < D; ++r) acc[r] += __shfl_xor(acc[r], off, LG);
+    if (lane == 0) {
+      const int o = A.nrow_off[item];
+#pragma unroll
+      for (int r = 0; r < D; ++r) y[o + r] = residual ? b[o + r] - acc[r] : acc[r];
+    }
+  } else {
+    const int64_t p = item - A.nrb;
+    if (p >= A.npr) return;
+    T acc = T(0);
+    const int k1 = A.pn_ptr[p + 1];
+    for (int k = A.pn_ptr[p] + lane; k < k1; k += LG) {
+      const int c = A.pn_col[k];
+      const T* v = A.pn_val + (int64_t)k * D;
+#pragma unroll
+      for (int q = 0; q < D; ++q) acc += v[q] * x[c + q];
+    }
+    const int p1 = A.pp_ptr[p + 1];
+    for (int k = A.pp_ptr[p] + lane; k < p1; k += LG) acc += A.pp_val[k] * x[A.pp_col[k]];
+#pragma unroll
+    for (int off = LG / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, LG);
+    if (lane == 0) {
+      const int o = A.prow_off[p];
+      y[o] = residual ? b[o] - acc : acc;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_csr_spmv(int64_t nrows, const int64_t* __restrict__ rp,
+                                                       const int32_t* __restrict__ col,
+                                                       const double* __restrict__ val,
+                                                       const double* __restrict__ x,
+                                                       double* __restrict__ y, double beta) {
+  constexpr int LG = 8;
+  const int lane = threadIdx.x & (LG - 1);
+  const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LG;
+  if (row >= nrows) return;
+  double acc = 0.0;
+  for (int64_t k = rp[row] + lane; k < rp[row + 1]; k += LG) acc += val[k] * x[col[k]];
+#pragma unroll
+  for (int off = LG / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, LG);
+  if (lane == 0) y[row] = (beta == 0.0 ? 0.0 : beta * y[row]) + acc;
+}
+
+// ------------------------------------------------------------------------
+// transfers
+// ------------------------------------------------------------------------
+constexpr uint8_t kSolid = 1, kDirD = 2, kDirU = 4;
+
+template <typename T, int D>
+__global__ __launch_bounds__(kThreads) void k_transfer(TransferView<T> t, int mode,
+                                                       const T* __restrict__ in,
+                                                       T* __restrict__ out) {
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (mode == 0 || mode == 2) {
+    // coarse outputs
+    if (id < t.N2c) {
+      const int64_t I = id;
+      const uint8_t fc = t.flags_c[I];
+      const bool ssI = fc & kSolid;
+      T bd[D], bu[D];
+#pragma unroll
+      for (int c = 0; c < D; ++c) bd[c] = bu[c] = T(0);
+      for (int k = t.rn_ptr[I]; k < t.rn_ptr[I + 1]; ++k) {
+        const int64_t i = t.rn_col[k];
+        const T w = t.rn_val[k];
+        const uint8_t ff = t.flags_f[i];
+        if (mode == 0) {
+          const bool ssi = ff & kSolid;
+          if (ssI == ssi) {
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+              bd[c] += w * in[D * i + c];
+              bu[c] += w * in[t.offu_f + D * i + c];
+            }
+          } else if (ssI) {
+#pragma unroll
+            for (int c = 0; c < D; ++c) bd[c] += w * in[t.offu_f + D * i + c];
+          }
+        } else {
+#pragma unroll
+          for (int c = 0; c < D; ++c) {
+            if (!(ff & kDirD)) bd[c] += w * in[D * i + c];
+            if (!(ff & kDirU)) bu[c] += w * in[t.offu_f + D * i + c];
+          }
+        }
+      }
+      const bool zd = (mode == 0) && (fc & kDirD), zu = (mode == 0) && (fc & kDirU);
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        out[D * I + c] = zd ? T(0) : bd[c];
+        out[t.offu_c + D * I + c] = zu ? T(0) : bu[c];
+      }
+      return;
+    }
+    int64_t p = id - t.N2c;
+    if (p < t.Npsc) {
+      T s = T(0);
+      for (int k = t.rps_ptr[p]; k < t.rps_ptr[p + 1]; ++k) s += t.rps_val[k] * in[t.offps_f + t.rps_col[k]];
+      out[t.offps_c + p] = s;
+      return;
+    }
+    p -= t.Npsc;
+    if (p < t.Npfc) {
+      T s = T(0);
+      for (int k = t.rpf_ptr[p]; k < t.rpf_ptr[p + 1]; ++k) s += t.rpf_val[k] * in[t.offpf_f + t.rpf_col[k]];
+      out[t.offpf_c + p] = s;
+    }
+    return;
+  }
+  // fine outputs (mode 1: x_f += D_f P x_c, mode 3: x_f += (D_c R)^T x_c)
+  if (id < t.N2f) {
+    const int64_t i = id;
+    const uint8_t ff = t.flags_f[i];
+    const bool ssi = ff & kSolid;
+    T ad[D], au[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) ad[c] = au[c] = T(0);
+    for (int k = t.pn_ptr[i]; k < t.pn_ptr[i + 1]; ++k) {
+      const int64_t I = t.pn_col[k];
+      const T w = t.pn_val[k];
+      if (mode == 1) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+          ad[c] += w * in[D * I + c];
+          au[c] += w * in[t.offu_c + D * I + c];
+        }
+      } else {
+        const uint8_t fc = t.flags_c[I];
+        const bool ssI = fc & kSolid;
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+          const T xd = (fc & kDirD) ? T(0) : in[D * I + c];
+          const T xu = (fc & kDirU) ? T(0) : in[t.offu_c + D * I + c];
+          if (ssI == ssi) {
+            ad[c] += w * xd;
+            au[c] += w * xu;
+          } else if (ssI) {
+            au[c] += w * xd;
+          }
+        }
+      }
+    }
+    const bool md = (mode == 1) && (ff & kDirD), mu = (mode == 1) && (ff & kDirU);
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      if (!md) out[D * i + c] += ad[c];
+      if (!mu) out[t.offu_f + D * i + c] += au[c];
+    }
+    return;
+  }
+  int64_t p = id - t.N2f;
+  if (p < t.Npsf) {
+    T s = T(0);
+    for (int k = t.pps_ptr[p]; k < t.pps_ptr[p + 1]; ++k) s += t.pps_val[k] * in[t.offps_c + t.pps_col[k]];
+    out[t.offps_f + p] += s;
+    return;
+  }
+  p -= t.Npsf;
+  if (p < t.Npff) {
+    T s = T(0);
+    for (int k = t.ppf_ptr[p]; k < t.ppf_ptr[p + 1]; ++k) s += t.ppf_val[k] * in[t.offpf_c + t.ppf_col[k]];
+    out[t.offpf_f + p] += s;
+  }
+}
+
+// ------------------------------------------------------------------------
+// smoother
+// ------------------------------------------------------------------------
+template <typename TW>
+struct WTraits;
+template <>
+struct WTraits<double> {
+  static constexpr int RV = 2;
+  using vec = double2;
+  __device__ static void load(const double* p, double* o) {
+    const double2 v = *reinterpret_cast<const double2*>(p);
+    o[0] = v.x;
+    o[1] = v.y;
+  }
+  __device__ static void load(const double* p, float* o) {
+    const double2 v = *reinterpret_cast<const double2*>(p);
+    o[0] = (float)v.x;
+    o[1] = (float)v.y;
+  }
+};
+template <>
+struct WTraits<float> {
+  static constexpr int RV = 4;
+  template <typename TA>
+  __device__ static void load(const float* p, TA* o) {
+    const float4 v = *reinterpret_cast<const float4*>(p);
+    o[0] = v.x;
+    o[1] = v.y;
+    o[2] = v.z;
+    o[3] = v.w;
+  }
+};
+template <>
+struct WTraits<__hip_bfloat16> {
+  static constexpr int RV = 8;
+  template <typename TA>
+  __device__ static void load(const __hip_bfloat16* p, TA* o) {
+    const uint4 v = *reinterpret_cast<const uint4*>(p);
+    const uint32_t u[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      o[2 * q] = __uint_as_float(u[q] << 16);
+      o[2 * q + 1] = __uint_as_float(u[q] & 0xffff0000u);
+    }
+  }
+};
+
+// Forward sweep: x[own] = (first ? 0 : x[own]) + omega * (W_j r[I_j])[own].
+template <typename TV, typename TW>
+__global__ __launch_bounds__(kThreads) void k_smooth_fwd(BlocksView B, const TW* __restrict__ W,
+                                                         const TV* __restrict__ r,
+                                                         TV* __restrict__ x, TV omega, int first) {
+  using TA = TV;
+  constexpr int RV = WTraits<TW>::RV;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  TA* smem = reinterpret_cast<TA*>(smem_raw);
+  const int64_t j = blockIdx.x;
+  const int tid = threadIdx.x;
+  if (j >= B.nblk) {
+    const int64_t q = (j - B.nblk) * blockDim.x + tid;
+    if (q < B.njac) {
+      const int32_t gi = B.jac[q];
+      const TV jv = reinterpret_cast<const TV*>(B.jac_inv)[q];
+      x[gi] = (first ? TV(0) : x[gi]) + omega * r[gi] * jv;
+    }
+    return;
+  }
+  const int64_t d0 = B.dof_ptr[j];
+  const int n = (int)(B.dof_ptr[j + 1] - d0);
+  const int o0 = B.own_ptr[j];
+  const int m = B.own_ptr[j + 1] - o0;
+  const int mp = B.mpad[j];
+  TA* rl = smem;
+  TA* red = smem + ((n + 3) & ~3);
+  for (int k = tid; k < n; k += blockDim.x) rl[k] = (TA)r[B.dofs[d0 + k]];
+  __syncthreads();
+  const int G = mp / RV;
+  const int S = G >= (int)blockDim.x ? 1 : (int)blockDim.x / G;
+  const TW* Wj = W + B.w_off[j];
+  for (int gg = tid; gg < G * S; gg += blockDim.x) {
+    const int g = gg % G, s = gg / G;
+    TA acc[RV];
+#pragma unroll
+    for (int i = 0; i < RV; ++i) acc[i] = TA(0);
+    const TW* p = Wj + (int64_t)g * RV;
+    for (int k = s; k < n; k += S) {
+      TA w[RV];
+      WTraits<TW>::load(p + (int64_t)k * mp, w);
+      const TA rk = rl[k];
+#pragma unroll
+      for (int i = 0; i < RV; ++i) acc[i] += w[i] * rk;
+    }
+#pragma unroll
+    for (int i = 0; i < RV; ++i) red[s * mp + g * RV + i] = acc[i];
+  }
+  __syncthreads();
+  for (int i = tid; i < m; i += blockDim.x) {
+    TA v = TA(0);
+    for (int s = 0; s < S; ++s) v += red[s * mp + i];
+    const int32_t gi = B.own_dof[o0 + i];
+    x[gi] = (first ? TV(0) : x[gi]) + omega * (TV)v;
+  }
+}
+
+// Transposed sweep, part 1: t_j = W_j^T r[own_j] into the per-block buffer.
+template <typename TV, typename TW>
+__global__ __launch_bounds__(kThreads) void k_smooth_t1(BlocksView B, const TW* __restrict__ W,
+                                                        const TV* __restrict__ r,
+                                                        TV* __restrict__ tbuf) {
+  using TA = TV;
+  constexpr int RV = WTraits<TW>::RV;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  TA* so = reinterpret_cast<TA*>(smem_raw);
+  const int64_t j = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int64_t d0 = B.dof_ptr[j];
+  const int n = (int)(B.dof_ptr[j + 1] - d0);
+  const int o0 = B.own_ptr[j];
+  const int m = B.own_ptr[j + 1] - o0;
+  const int mp = B.mpad[j];
+  for (int i = tid; i < mp; i += blockDim.x) so[i] = i < m ? (TA)r[B.own_dof[o0 + i]] : TA(0);
+  __syncthreads();
+  const TW* Wj = W + B.w_off[j];
+  for (int k = tid; k < n; k += blockDim.x) {
+    TA acc = TA(0);
+    const TW* col = Wj + (int64_t)k * mp;
+    for (int i = 0; i < mp; i += RV) {
+      TA w[RV];
+      WTraits<TW>::load(col + i, w);
+#pragma unroll
+      for (int q = 0; q < RV; ++q) acc += w[q] * so[i + q];
+    }
+    tbuf[d0 + k] = (TV)acc;
+  }
+}
+
+// Transposed sweep, part 2: fixed-order sum of the block outputs per unknown.
+template <typename TV>
+__global__ __launch_bounds__(kThreads) void k_smooth_t2(BlocksView B, const TV* __restrict__ tbuf,
+                                                        const TV* __restrict__ r,
+                                                        TV* __restrict__ x, int64_t N, TV omega,
+                                                        int first) {
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id < N) {
+    const int b = B.tpos_ptr[id], e = B.tpos_ptr[id + 1];
+    if (b == e) return;
+    TV s = TV(0);
+    for (int k = b; k < e; ++k) s += tbuf[B.tpos[k]];
+    x[id] = (first ? TV(0) : x[id]) + omega * s;
+    return;
+  }
+  const int64_t q = id - N;
+  if (q < B.njac) {
+    const int32_t gi = B.jac[q];
+    const TV jv = reinterpret_cast<const TV*>(B.jac_inv)[q];
+    x[gi] = (first ? TV(0) : x[gi]) + omega * r[gi] * jv;
+  }
+}
+
+// ------------------------------------------------------------------------
+// block setup
+// ------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_gather_blocks(int64_t j0, BlocksView B,
+                                                            const int64_t* __restrict__ rp,
+                                                            const int32_t* __restrict__ col,
+                                                            const double* __restrict__ val,
+                                                            const int64_t* __restrict__ doff,
+                                                            double* __restrict__ dense) {
+  const int64_t j = j0 + blockIdx.x;
+  const int64_t d0 = B.dof_ptr[j];
+  const int n = (int)(B.dof_ptr[j + 1] - d0);
+  double* a = dense + doff[blockIdx.x];
+  for (int64_t e = threadIdx.x; e < (int64_t)n * n; e += blockDim.x) a[e] = 0.0;
+  __syncthreads();
+  const int32_t* I = B.dofs + d0;
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    const int32_t g = I[k];
+    for (int64_t e = rp[g]; e < rp[g + 1]; ++e) {
+      const int32_t c = col[e];
+      int lo = 0, hi = n - 1;
+      while (lo <= hi) {
+        const int mid = (lo + hi) >> 1;
+        const int32_t v = I[mid];
+        if (v == c) {
+          a[(int64_t)k * n + mid] = val[e];
+          break;
+        }
+        if (v < c)
+          lo = mid + 1;
+        else
+          hi = mid - 1;
+      }
+    }
+  }
+}
+
+// In-place Gauss-Jordan inversion with row interchanges (partial pivoting),
+// followed by the inverse column interchanges.  One workgroup per matrix.
+constexpr int kInvThreads = 512;
+
+__global__ __launch_bounds__(kInvThreads) void k_invert(int64_t j0, const int64_t* __restrict__ dof_ptr,
+                                                        const int64_t* __restrict__ doff,
+                                                        double* __restrict__ dense,
+                                                        int32_t* __restrict__ status) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int64_t j = j0 + blockIdx.x;
+  const int n = (int)(dof_ptr[j + 1] - dof_ptr[j]);
+  double* a = dense + doff[blockIdx.x];
+  double* colk = reinterpret_cast<double*>(smem_raw);
+  double* rowk = colk + n;
+  double* redv = rowk + n;
+  int* redi = reinterpret_cast<int*>(redv + kInvThreads);
+  int* piv = redi + kInvThreads;
+  __shared__ int s_fail;
+  const int tid = threadIdx.x, T = blockDim.x;
+  if (tid == 0) s_fail = 0;
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    // pivot search over rows k..n-1 (ties: smallest row)
+    double best = -1.0;
+    int bi = n;
+    for (int i = k + tid; i < n; i += T) {
+      const double v = fabs(a[(int64_t)i * n + k]);
+      if (v > best) {
+        best = v;
+        bi = i;
+      }
+    }
+    redv[tid] = best;
+    redi[tid] = bi;
+    __syncthreads();
+    for (int s = T / 2; s > 0; s >>= 1) {
+      if (tid < s) {
+        const double v2 = redv[tid + s];
+        const int i2 = redi[tid + s];
+        if (v2 > redv[tid] || (v2 == redv[tid] && i2 < redi[tid])) {
+          redv[tid] = v2;
+          redi[tid] = i2;
+        }
+      }
+      __syncthreads();
+    }
+    const int p = redi[0];
+    if (!(redv[0] > 0.0)) {
+      if (tid == 0) {
+        s_fail = 1;
+        status[j] = 1;
+      }
+      __syncthreads();
+      return;
+    }
+    if (tid == 0) piv[k] = p;
+    if (p != k)
+      for (int c = tid; c < n; c += T) {
+        const double t0 = a[(int64_t)k * n + c];
+        a[(int64_t)k * n + c] = a[(int64_t)p * n + c];
+        a[(int64_t)p * n + c] = t0;
+      }
+    __syncthreads();
+    const double d = 1.0 / a[(int64_t)k * n + k];
+    for (int i = tid; i < n; i += T) {
+      colk[i] = a[(int64_t)i * n + k];
+      rowk[i] = (i == k) ? d : a[(int64_t)k * n + i] * d;
+    }
+    __syncthreads();
+    for (int64_t e = tid; e < (int64_t)n * n; e += T) {
+      const int i = (int)(e / n), c = (int)(e - (int64_t)i * n);
+      if (i == k) {
+        a[e] = rowk[c];
+      } else {
+        const double base = (c == k) ? 0.0 : a[e];
+        a[e] = base - colk[i] * rowk[c];
+      }
+    }
+    __syncthreads();
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    const int p = piv[k];
+    if (p != k)
+      for (int i = tid; i < n; i += T) {
+        const double t0 = a[(int64_t)i * n + k];
+        a[(int64_t)i * n + k] = a[(int64_t)i * n + p];
+        a[(int64_t)i * n + p] = t0;
+      }
+    __syncthreads();
+  }
+  if (tid == 0) status[j] = 0;
+}
+
+template <typename TW>
+__device__ inline TW to_w(double v);
+template <>
+__device__ inline double to_w<double>(double v) { return v; }
+template <>
+__device__ inline float to_w<float>(double v) { return (float)v; }
+template <>
+__device__ inline __hip_bfloat16 to_w<__hip_bfloat16>(double v) { return __float2bfloat16((float)v); }
+
+template <typename TW>
+__global__ __launch_bounds__(kThreads) void k_extract(int64_t j0, BlocksView B,
+                                                      const int64_t* __restrict__ doff,
+                                                      const double* __restrict__ dense,
+                                                      TW* __restrict__ W) {
+  const int64_t j = j0 + blockIdx.x;
+  const int n = (int)(B.dof_ptr[j + 1] - B.dof_ptr[j]);
+  const int o0 = B.own_ptr[j];
+  const int m = B.own_ptr[j + 1] - o0;
+  const int mp = B.mpad[j];
+  const double* a = dense + doff[blockIdx.x];
+  TW* Wj = W + B.w_off[j];
+  for (int64_t e = threadIdx.x; e < (int64_t)n * mp; e += blockDim.x) {
+    const int k = (int)(e / mp), i = (int)(e - (int64_t)k * mp);
+    const double v = i < m ? a[(int64_t)B.own_loc[o0 + i] * n + k] : 0.0;
+    Wj[e] = to_w<TW>(v);
+  }
+}
+
+// ------------------------------------------------------------------------
+// coarse dense solve (explicit FP64 inverse)
+// ------------------------------------------------------------------------
+template <typename TV>
+__global__ __launch_bounds__(kThreads) void k_gemv_rows(int64_t n, const double* __restrict__ A,
+                                                        const TV* __restrict__ x,
+                                                        TV* __restrict__ y) {
+  // one wavefront per row
+  const int lane = threadIdx.x & 63;
+  const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (row >= n) return;
+  double acc = 0.0;
+  const double* a = A + row * n;
+  for (int64_t k = lane; k < n; k += 64) acc += a[k] * (double)x[k];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (lane == 0) y[row] = (TV)acc;
+}
+
+template <typename TV>
+__global__ __launch_bounds__(kThreads) void k_gemv_cols(int64_t n, const double* __restrict__ A,
+                                                        const TV* __restrict__ x,
+                                                        TV* __restrict__ y) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  double acc = 0.0;
+  for (int64_t k = 0; k < n; ++k) acc += A[k * n + c] * (double)x[k];
+  y[c] = (TV)acc;
+}
+
+// ------------------------------------------------------------------------
+// Krylov reductions (FP64, deterministic fixed-order partial sums)
+// ------------------------------------------------------------------------
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// reduce acc[0..k) over the workgroup, write part[blockIdx.x * kMaxK + i]
+__device__ inline void block_store_partials(const double* acc, int k, double* part) {
+  __shared__ double sh[kThreads / 64][kMaxK];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < kMaxK; ++i) {
+    if (i < k) {
+      const double s = wave_sum(acc[i]);
+      if (lane == 0) sh[wv][i] = s;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < k) {
+    double s = 0.0;
+    for (int w = 0; w < kThreads / 64; ++w) s += sh[w][threadIdx.x];
+    part[(int64_t)blockIdx.x * kMaxK + threadIdx.x] = s;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_mdot(const double* __restrict__ V, int64_t ld, int k,
+                                                   const double* __restrict__ w, int64_t N,
+                                                   double* __restrict__ part) {
+  double acc[kMaxK];
+#pragma unroll
+  for (int i = 0; i < kMaxK; ++i) acc[i] = 0.0;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < N;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    const double wr = w[r];
+#pragma unroll
+    for (int i = 0; i < kMaxK; ++i)
+      if (i < k) acc[i] += V[i * ld + r] * wr;
+  }
+  block_store_partials(acc, k, part);
+}
+
+__global__ __launch_bounds__(kThreads) void k_maxpy_mdot(const double* __restrict__ V, int64_t ld,
+                                                         int k, const double* __restrict__ h,
+                                                         double* __restrict__ w, int64_t N,
+                                                         double* __restrict__ part) {
+  __shared__ double hs[kMaxK];
+  if (threadIdx.x < kMaxK) hs[threadIdx.x] = threadIdx.x < k ? h[threadIdx.x] : 0.0;
+  __syncthreads();
+  double acc[kMaxK];
+#pragma unroll
+  for (int i = 0; i < kMaxK; ++i) acc[i] = 0.0;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < N;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    double v[kMaxK];
+    double wr = w[r];
+#pragma unroll
+    for (int i = 0; i < kMaxK; ++i)
+      if (i < k) {
+        v[i] = V[i * ld + r];
+        wr -= hs[i] * v[i];
+      }
+    w[r] = wr;
+#pragma unroll
+    for (int i = 0; i < kMaxK; ++i)
+      if (i < k) acc[i] += v[i] * wr;
+  }
+  block_store_partials(acc, k, part);
+}
+
+__global__ __launch_bounds__(kThreads) void k_maxpy_norm(const double* __restrict__ V, int64_t ld,
+                                                         int k, const double* __restrict__ h,
+                                                         double* __restrict__ w, int64_t N,
+                                                         double* __restrict__ part) {
+  __shared__ double hs[kMaxK];
+  if (threadIdx.x < kMaxK) hs[threadIdx.x] = threadIdx.x < k ? h[threadIdx.x] : 0.0;
+  __syncthreads();
+  double acc[kMaxK];
+#pragma unroll
+  for (int i = 0; i < kMaxK; ++i) acc[i] = 0.0;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < N;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    double wr = w[r];
+    for (int i = 0; i < k; ++i) wr -= hs[i] * V[i * ld + r];
+    w[r] = wr;
+    acc[0] += wr * wr;
+  }
+  block_store_partials(acc, 1, part);
+}
+
+__global__ __launch_bounds__(kThreads) void k_norm2(const double* __restrict__ w, int64_t N,
+                                                    double* __restrict__ part) {
+  double acc[kMaxK];
+  acc[0] = 0.0;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < N;
+       r += (int64_t)gridDim.x * blockDim.x)
+    acc[0] += w[r] * w[r];
+  block_store_partials(acc, 1, part);
+}
+
+// out[i] = sum_g part[g][i] (fixed tree order) (+ add_to[i]); sqrt of the
+// last entry when sqrt_last (norms)
+__global__ __launch_bounds__(kThreads) void k_reduce_partials(const double* __restrict__ part,
+                                                              int k, double* __restrict__ out,
+                                                              const double* __restrict__ add_to,
+                                                              int sqrt_last) {
+  __shared__ double sh[kThreads];
+  for (int i = 0; i < k; ++i) {
+    double s = 0.0;
+    for (int g = threadIdx.x; g < kPartials; g += blockDim.x) s += part[(int64_t)g * kMaxK + i];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+      if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      double v = sh[0];
+      if (sqrt_last && i == k - 1) v = sqrt(v);
+      if (add_to) v += add_to[i];
+      out[i] = v;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_scale_copy(const double* __restrict__ w,
+                                                         const double* __restrict__ beta,
+                                                         double* __restrict__ v, int64_t N) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < N) v[r] = w[r] / beta[0];
+}
+
+__global__ __launch_bounds__(kThreads) void k_gemv_update(const double* __restrict__ Z, int64_t ld,
+                                                          int k, const double* __restrict__ y,
+                                                          double* __restrict__ x, int64_t N) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= N) return;
+  double s = x[r];
+  for (int i = 0; i < k; ++i) s += y[i] * Z[i * ld + r];
+  x[r] = s;
+}
+
+template <typename TA, typename TB>
+__global__ __launch_bounds__(kThreads) void k_cast(const TA* __restrict__ a, TB* __restrict__ b,
+                                                   int64_t n) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) b[r] = (TB)a[r];
+}
+
+__global__ __launch_bounds__(kThreads) void k_axpby(double a, const double* __restrict__ x, double b,
+                                                    double* __restrict__ y, int64_t n) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) y[r] = a * x[r] + (b == 0.0 ? 0.0 : b * y[r]);
+}
+
+__global__ __launch_bounds__(kThreads) void k_load_rhs(int64_t n, const int64_t* __restrict__ rp,
+                                                       const int32_t* __restrict__ col,
+                                                       const double* __restrict__ val,
+                                                       const double* __restrict__ f,
+                                                       const double* __restrict__ lift,
+                                                       double* __restrict__ b) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  double s = lift[r];
+  for (int64_t k = rp[r]; k < rp[r + 1]; ++k) s += val[k] * f[col[k]];
+  b[r] = s;
+}
+
+__global__ __launch_bounds__(kThreads) void k_masked_dot(const double* __restrict__ a,
+                                                         const uint8_t* __restrict__ mask,
+                                                         const double* __restrict__ b, int64_t n,
+                                                         double* __restrict__ part) {
+  double acc[kMaxK];
+  acc[0] = 0.0;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n;
+       r += (int64_t)gridDim.x * blockDim.x)
+    if (!mask[r]) acc[0] += a[r] * b[r];
+  block_store_partials(acc, 1, part);
+}
+
+__global__ __launch_bounds__(kThreads) void k_recombine(int64_t n, const double* __restrict__ p0,
+                                                        const double* __restrict__ p1,
+                                                        const double* __restrict__ p2,
+                                                        const double* __restrict__ p3, double c1,
+                                                        double c2, double c3,
+                                                        double* __restrict__ o64,
+                                                        float* __restrict__ o32) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const double v = p0[r] + c1 * p1[r] + c2 * p2[r] + c3 * p3[r];
+  if (o64) o64[r] = v;
+  if (o32) o32[r] = (float)v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_fill(T* __restrict__ p, T v, int64_t n) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) p[r] = v;
+}
+
+__global__ __launch_bounds__(kThreads) void k_scatter(int64_t n, const double* __restrict__ v,
+                                                      const int64_t* __restrict__ map,
+                                                      double* __restrict__ o64,
+                                                      float* __restrict__ o32) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int64_t d = map[k];
+  if (o64) o64[d] = v[k];
+  if (o32) o32[d] = (float)v[k];
+}
+
+}  // namespace
+
+// ========================================================================
+// launchers
+// ========================================================================
+template <typename T>
+void launch_spmv(const BOpView<T>& A, int D, const T* x, const T* b, T* y, bool residual,
+                 hipStream_t s) {
+  constexpr int LG = 8;
+  const int64_t items = A.nrb + A.npr;
+  const unsigned g = grid_for(items * LG, kThreads);
+  if (g == 0) return;
+  if (D == 2)
+    hipLaunchKernelGGL((k_spmv<T, 2, LG>), dim3(g), dim3(kThreads), 0, s, A, x, b, y, (int)residual);
+  else
+    hipLaunchKernelGGL((k_spmv<T, 3, LG>), dim3(g), dim3(kThreads), 0, s, A, x, b, y, (int)residual);
+}
+template void launch_spmv<double>(const BOpView<double>&, int, const double*, const double*,
+                                  double*, bool, hipStream_t);
+template void launch_spmv<float>(const BOpView<float>&, int, const float*, const float*, float*,
+                                 bool, hipStream_t);
+
+void launch_csr_spmv(int64_t nrows, const int64_t* rowptr, const int32_t* col, const double* val,
+                     const double* x, double* y, double beta, hipStream_t s) {
+  const unsigned g = grid_for(nrows * 8, kThreads);
+  if (g) hipLaunchKernelGGL(k_csr_spmv, dim3(g), dim3(kThreads), 0, s, nrows, rowptr, col, val, x, y, beta);
+}
+
+template <typename T>
+void launch_transfer(const TransferView<T>& t, int D, int mode, const T* in, T* out,
+                     hipStream_t s) {
+  const int64_t n = (mode == 0 || mode == 2) ? t.N2c + t.Npsc + t.Npfc : t.N2f + t.Npsf + t.Npff;
+  const unsigned g = grid_for(n, kThreads);
+  if (!g) return;
+  if (D == 2)
+    hipLaunchKernelGGL((k_transfer<T, 2>), dim3(g), dim3(kThreads), 0, s, t, mode, in, out);
+  else
+    hipLaunchKernelGGL((k_transfer<T, 3>), dim3(g), dim3(kThreads), 0, s, t, mode, in, out);
+}
+template void launch_transfer<double>(const TransferView<double>&, int, int, const double*,
+                                      double*, hipStream_t);
+template void launch_transfer<float>(const TransferView<float>&, int, int, const float*, float*,
+                                     hipStream_t);
+
+template <typename TV, typename TW>
+static void smooth_impl(const BlocksView& B, const TW* W, const TV* r, TV* x, TV* tbuf,
+                        double omega, bool first, bool transpose, int64_t N, hipStream_t s) {
+  if (!transpose) {
+    const int64_t nj = (B.njac + kThreads - 1) / kThreads;
+    const unsigned g = (unsigned)(B.nblk + nj);
+    if (!g) return;
+    const int RV = WTraits<TW>::RV;
+    const size_t sm = sizeof(TV) * (size_t)(((B.max_n + 3) & ~3) + kThreads * RV + B.max_mpad);
+    hipLaunchKernelGGL((k_smooth_fwd<TV, TW>), dim3(g), dim3(kThreads), sm, s, B, W, r, x,
+                       (TV)omega, (int)first);
+    return;
+  }
+  if (B.nblk) {
+    const size_t sm = sizeof(TV) * (size_t)B.max_mpad;
+    hipLaunchKernelGGL((k_smooth_t1<TV, TW>), dim3((unsigned)B.nblk), dim3(kThreads), sm, s, B, W,
+                       r, tbuf);
+  }
+  const unsigned g = grid_for(N + B.njac, kThreads);
+  if (g)
+    hipLaunchKernelGGL((k_smooth_t2<TV>), dim3(g), dim3(kThreads), 0, s, B, tbuf, r, x, N,
+                       (TV)omega, (int)first);
+}
+
+template <typename TV>
+void launch_smooth(const BlocksView& B, WPrec wp, const void* W, const TV* r, TV* x, TV* tbuf,
+                   double omega, bool first, bool transpose, int64_t N, hipStream_t s) {
+  switch (wp) {
+    case WPrec::F64:
+      smooth_impl<TV, double>(B, (const double*)W, r, x, tbuf, omega, first, transpose, N, s);
+      break;
+    case WPrec::F32:
+      smooth_impl<TV, float>(B, (const float*)W, r, x, tbuf, omega, first, transpose, N, s);
+      break;
+    case WPrec::BF16:
+      smooth_impl<TV, __hip_bfloat16>(B, (const __hip_bfloat16*)W, r, x, tbuf, omega, first,
+                                      transpose, N, s);
+      break;
+  }
+}
+template void launch_smooth<double>(const BlocksView&, WPrec, const void*, const double*, double*,
+                                    double*, double, bool, bool, int64_t, hipStream_t);
+template void launch_smooth<float>(const BlocksView&, WPrec, const void*, const float*, float*,
+                                   float*, double, bool, bool, int64_t, hipStream_t);
+
+void launch_gather_blocks(int64_t j0, int64_t nb, const BlocksView& B, const int64_t* rowptr,
+                          const int32_t* col, const double* val, const int64_t* dense_off,
+                          double* dense, hipStream_t s) {
+  if (nb > 0)
+    hipLaunchKernelGGL(k_gather_blocks, dim3((unsigned)nb), dim3(kThreads), 0, s, j0, B, rowptr,
+                       col, val, dense_off, dense);
+}
+
+void launch_invert_blocks(int64_t j0, int64_t nb, const int64_t* dof_ptr, const int64_t* dense_off,
+                          double* dense, int32_t* status, int max_n, hipStream_t s) {
+  // LDS: colk, rowk (n doubles each), reduction scratch (T doubles + T ints), piv (n ints)
+  const size_t sm = (size_t)max_n * 20 + (size_t)kInvThreads * 12 + 64;
+  if (nb > 0)
+    hipLaunchKernelGGL(k_invert, dim3((unsigned)nb), dim3(kInvThreads), sm, s, j0, dof_ptr,
+                       dense_off, dense, status);
+}
+
+void launch_extract_owned(int64_t j0, int64_t nb, const BlocksView& B, const int64_t* dense_off,
+                          const double* dense, WPrec wp, void* W, hipStream_t s) {
+  if (nb <= 0) return;
+  switch (wp) {
+    case WPrec::F64:
+      hipLaunchKernelGGL((k_extract<double>), dim3((unsigned)nb), dim3(kThreads), 0, s, j0, B,
+                         dense_off, dense, (double*)W);
+      break;
+    case WPrec::F32:
+      hipLaunchKernelGGL((k_extract<float>), dim3((unsigned)nb), dim3(kThreads), 0, s, j0, B,
+                         dense_off, dense, (float*)W);
+      break;
+    case WPrec::BF16:
+      hipLaunchKernelGGL((k_extract<__hip_bfloat16>), dim3((unsigned)nb), dim3(kThreads), 0, s,
+                         j0, B, dense_off, dense, (__hip_bfloat16*)W);
+      break;
+  }
+}
+
+template <typename TV>
+void launch_dense_gemv(int64_t n, const double* Ainv, bool transpose, const TV* x, TV* y,
+                       hipStream_t s) {
+  if (!transpose)
+    hipLaunchKernelGGL((k_gemv_rows<TV>), dim3(grid_for(n * 64, kThreads)), dim3(kThreads), 0, s,
+                       n, Ainv, x, y);
+  else
+    hipLaunchKernelGGL((k_gemv_cols<TV>), dim3(grid_for(n, kThreads)), dim3(kThreads), 0, s, n,
+                       Ainv, x, y);
+}
+template void launch_dense_gemv<double>(int64_t, const double*, bool, const double*, double*,
+                                        hipStream_t);
+template void launch_dense_gemv<float>(int64_t, const double*, bool, const float*, float*,
+                                       hipStream_t);
+
+int krylov_partials() { return kPartials * kMaxK; }
+
+void launch_mdot(const double* V, int64_t ld, int k, const double* w, int64_t N, double* part,
+                 hipStream_t s) {
+  hipLaunchKernelGGL(k_mdot, dim3(kPartials), dim3(kThreads), 0, s, V, ld, k, w, N, part);
+}
+void launch_maxpy_mdot(const double* V, int64_t ld, int k, const double* h, double* w, int64_t N,
+                       double* part, hipStream_t s) {
+  hipLaunchKernelGGL(k_maxpy_mdot, dim3(kPartials), dim3(kThreads), 0, s, V, ld, k, h, w, N, part);
+}
+void launch_maxpy_norm(const double* V, int64_t ld, int k, const double* h, double* w, int64_t N,
+                       double* part, hipStream_t s) {
+  hipLaunchKernelGGL(k_maxpy_norm, dim3(kPartials), dim3(kThreads), 0, s, V, ld, k, h, w, N, part);
+}
+void launch_reduce_partials(const double* part, int k, double* out, double* add_to,
+                            bool sqrt_last, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(kThreads), 0, s, part, k, out, add_to,
+                     (int)sqrt_last);
+}
+void launch_norm2_partial(const double* w, int64_t N, double* part, hipStream_t s) {
+  hipLaunchKernelGGL(k_norm2, dim3(kPartials), dim3(kThreads), 0, s, w, N, part);
+}
+void launch_scale_copy(const double* w, const double* beta, double* v, int64_t N, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_copy, dim3(grid_for(N, kThreads)), dim3(kThreads), 0, s, w, beta, v, N);
+}
+void launch_gemv_update(const double* Z, int64_t ld, int k, const double* y, double* x,
+                        int64_t N, hipStream_t s) {
+  hipLaunchKernelGGL(k_gemv_update, dim3(grid_for(N, kThreads)), dim3(kThreads), 0, s, Z, ld, k,
+                     y, x, N);
+}
+
+template <typename TA, typename TB>
+void launch_cast(const TA* a, TB* b, int64_t n, hipStream_t s) {
+  if (n > 0)
+    hipLaunchKernelGGL((k_cast<TA, TB>), dim3(grid_for(n, kThreads)), dim3(kThreads), 0, s, a, b, n);
+}
+template void launch_cast<double, float>(const double*, float*, int64_t, hipStream_t);
+template void launch_cast<float, double>(const float*, double*, int64_t, hipStream_t);
+template void launch_cast<double, double>(const double*, double*, int64_t, hipStream_t);
+
+void launch_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t s) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_axpby, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, s, a, x, b, y, n);
+}
+
+void launch_load_rhs(int64_t n, const int64_t* rowptr, const int32_t* col, const double* val,
+                     const double* f, const double* lift, double* b, hipStream_t s) {
+  hipLaunchKernelGGL(k_load_rhs, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, s, n, rowptr, col,
+                     val, f, lift, b);
+}
+
+void launch_masked_dot_partial(const double* a, const uint8_t* mask, const double* b, int64_t n,
+                               double* part, hipStream_t s) {
+  hipLaunchKernelGGL(k_masked_dot, dim3(kPartials), dim3(kThreads), 0, s, a, mask, b, n, part);
+}
+
+template <typename T>
+void launch_fill(T* p, T v, int64_t n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL((k_fill<T>), dim3(grid_for(n, kThreads)), dim3(kThreads), 0, s, p, v, n);
+}
+template void launch_fill<double>(double*, double, int64_t, hipStream_t);
+template void launch_fill<float>(float*, float, int64_t, hipStream_t);
+
+void launch_scatter(int64_t n, const double* v, const int64_t* map, double* out64, float* out32,
+                    hipStream_t s) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_scatter, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, s, n, v, map,
+                       out64, out32);
+}
+
+void launch_recombine(int64_t n, const double* p0, const double* p1, const double* p2,
+                      const double* p3, double c1, double c2, double c3, double* out64,
+                      float* out32, hipStream_t s) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_recombine, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, s, n, p0, p1,
+                       p2, p3, c1, c2, c3, out64, out32);
+}
+
+}  // namespace fsgmg

@@ -1,0 +1,153 @@
+// Device data views and kernel launchers of the fsgmg library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace fsgmg {
+
+// Level operator in node-block form.  Node row blocks rb in [0, 2*N2): the
+// D scalar rows of one Q2 node's d-equations (rb < N2) or u-equations.
+//   NN: D x D blocks against a node's d or u unknowns (column = scalar offset
+//       of the block's first column), values row-major per block;
+//   NP: D x 1 columns against one pressure unknown.
+// Pressure rows p in [0, Nps + Npf):
+//   PN: 1 x D rows against a node block; PP: scalar entries.
+template <typename T>
+struct BOpView {
+  int64_t nrb, npr;
+  const int32_t* nrow_off;
+  const int32_t* nn_ptr;
+  const int32_t* nn_col;
+  const T* nn_val;
+  const int32_t* np_ptr;
+  const int32_t* np_col;
+  const T* np_val;
+  const int32_t* prow_off;
+  const int32_t* pn_ptr;
+  const int32_t* pn_col;
+  const T* pn_val;
+  const int32_t* pp_ptr;
+  const int32_t* pp_col;
+  const T* pp_val;
+};
+
+// Transfer between level l-1 (coarse) and l (fine), node-level form.
+template <typename T>
+struct TransferView {
+  int64_t N2f, N2c, Npsf, Npff, Npsc, Npfc;
+  int64_t offu_f, offps_f, offpf_f, offu_c, offps_c, offpf_c;
+  const int32_t* pn_ptr;   // fine node -> coarse nodes
+  const int32_t* pn_col;
+  const T* pn_val;
+  const int32_t* rn_ptr;   // coarse node -> fine nodes (transpose of pn)
+  const int32_t* rn_col;
+  const T* rn_val;
+  const int32_t* pps_ptr;  // fine p^s -> coarse p^s (local indices)
+  const int32_t* pps_col;
+  const T* pps_val;
+  const int32_t* ppf_ptr;
+  const int32_t* ppf_col;
+  const T* ppf_val;
+  const int32_t* rps_ptr;  // coarse p^s -> fine p^s
+  const int32_t* rps_col;
+  const T* rps_val;
+  const int32_t* rpf_ptr;
+  const int32_t* rpf_col;
+  const T* rpf_val;
+  const uint8_t* flags_f;  // per node: 1 solid-side, 2 d Dirichlet, 4 u Dirichlet
+  const uint8_t* flags_c;
+};
+
+// Schwarz blocks of one level.  W holds, per block, the rows of the block
+// inverse that belong to unknowns the block owns, column-major with the
+// owned-row count padded to mpad (a multiple of the vector width).
+struct BlocksView {
+  int64_t nblk, njac;
+  const int64_t* dof_ptr;   // nblk + 1
+  const int32_t* dofs;
+  const int32_t* own_ptr;   // nblk + 1
+  const int32_t* own_dof;   // global DOF of each owned row
+  const int32_t* own_loc;   // local index (in the block) of each owned row
+  const int64_t* w_off;     // element offset of each block in W
+  const int32_t* mpad;      // padded owned-row count per block
+  const int32_t* jac;       // DOFs in no block
+  const void* jac_inv;      // 1 / A_ii in the vector precision
+  int max_n, max_mpad;
+  // transposed apply: DOF -> positions in the per-block output buffer
+  const int32_t* tpos_ptr;  // N + 1
+  const int32_t* tpos;
+};
+
+enum class WPrec { F64 = 0, F32 = 1, BF16 = 2 };
+
+// ---- level operator ----
+template <typename T>
+void launch_spmv(const BOpView<T>& A, int D, const T* x, const T* b, T* y, bool residual,
+                 hipStream_t s);
+
+// scalar CSR (FP64): y = A x (+ beta y)
+void launch_csr_spmv(int64_t nrows, const int64_t* rowptr, const int32_t* col, const double* val,
+                     const double* x, double* y, double beta, hipStream_t s);
+
+// ---- transfers (mode 0: b_c = D_c R r_f, 1: x_f += D_f P x_c,
+//      2: b_c = (D_f P)^T r_f, 3: x_f += (D_c R)^T x_c) ----
+template <typename T>
+void launch_transfer(const TransferView<T>& t, int D, int mode, const T* in, T* out,
+                     hipStream_t s);
+
+// ---- smoother: x = (first ? 0 : x) + omega * B r  (transpose: B^T) ----
+template <typename TV>
+void launch_smooth(const BlocksView& B, WPrec wp, const void* W, const TV* r, TV* x, TV* tbuf,
+                   double omega, bool first, bool transpose, int64_t N, hipStream_t s);
+
+// ---- block setup ----
+void launch_gather_blocks(int64_t j0, int64_t nb, const BlocksView& B, const int64_t* rowptr,
+                          const int32_t* col, const double* val, const int64_t* dense_off,
+                          double* dense, hipStream_t s);
+// In-place Gauss-Jordan inversion with partial pivoting of nb dense blocks
+// (sizes from dof_ptr); status[j] = 1 on a zero pivot.
+void launch_invert_blocks(int64_t j0, int64_t nb, const int64_t* dof_ptr, const int64_t* dense_off,
+                          double* dense, int32_t* status, int max_n, hipStream_t s);
+void launch_extract_owned(int64_t j0, int64_t nb, const BlocksView& B, const int64_t* dense_off,
+                          const double* dense, WPrec wp, void* W, hipStream_t s);
+
+// ---- coarse solve: y = Ainv * x (transpose: Ainv^T x), FP64 matrix ----
+template <typename TV>
+void launch_dense_gemv(int64_t n, const double* Ainv, bool transpose, const TV* x, TV* y,
+                       hipStream_t s);
+
+// ---- Krylov (FP64) ----
+int krylov_partials();
+void launch_mdot(const double* V, int64_t ld, int k, const double* w, int64_t N, double* part,
+                 hipStream_t s);
+void launch_maxpy_mdot(const double* V, int64_t ld, int k, const double* h, double* w, int64_t N,
+                       double* part, hipStream_t s);
+void launch_maxpy_norm(const double* V, int64_t ld, int k, const double* h, double* w,
+                       int64_t N, double* part, hipStream_t s);
+void launch_reduce_partials(const double* part, int k, double* out, double* add_to,
+                            bool sqrt_last, hipStream_t s);
+void launch_norm2_partial(const double* w, int64_t N, double* part, hipStream_t s);
+void launch_scale_copy(const double* w, const double* beta, double* v, int64_t N, hipStream_t s);
+void launch_gemv_update(const double* Z, int64_t ld, int k, const double* y, double* x,
+                        int64_t N, hipStream_t s);
+
+// ---- elementwise ----
+template <typename TA, typename TB>
+void launch_cast(const TA* a, TB* b, int64_t n, hipStream_t s);
+void launch_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t s);
+void launch_load_rhs(int64_t n, const int64_t* rowptr, const int32_t* col, const double* val,
+                     const double* f, const double* lift, double* b, hipStream_t s);
+void launch_masked_dot_partial(const double* a, const uint8_t* mask, const double* b, int64_t n,
+                               double* part, hipStream_t s);
+template <typename T>
+void launch_fill(T* p, T v, int64_t n, hipStream_t s);
+// out[map[k]] = v[k] (either output may be null)
+void launch_scatter(int64_t n, const double* v, const int64_t* map, double* out64, float* out32,
+                    hipStream_t s);
+void launch_recombine(int64_t n, const double* p0, const double* p1, const double* p2,
+                      const double* p3, double c1, double c2, double c3, double* out64,
+                      float* out32, hipStream_t s);
+
+}  // namespace fsgmg

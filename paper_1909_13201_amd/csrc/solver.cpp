@@ -1,0 +1,1210 @@
+// fsgmg C ABI: hierarchy setup, field-split additive Schwarz blocks, the
+// multigrid V-cycle (and its transpose), right-preconditioned FGMRES with
+// classical Gram-Schmidt twice, the adjoint solve and parameter gradients.
+//
+// Method (paper Sections 3.2-3.3): GMRES preconditioned by one GMG V-cycle;
+// damped Richardson with the additive field-split smoother on levels >= 1,
+// direct solve on level 0; natural-injection prolongation and the
+// equation-routed restriction.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "fsgmg.h"
+#include "host.hpp"
+#include "kernels.hpp"
+
+using namespace fsgmg;
+
+namespace {
+
+struct Fail {
+  fsgmg_status st;
+  std::string msg;
+};
+
+#define HIPCHECK(expr)                                                                 \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) throw Fail{FSGMG_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// node-block operator: structure, and a map from scalar CSR entries to the
+// concatenated value array [NN | NP | PN | PP]
+// ---------------------------------------------------------------------------
+struct BOpHost {
+  int64_t nrb = 0, npr = 0;
+  std::vector<int32_t> nrow_off, nn_ptr, nn_col, np_ptr, np_col, prow_off, pn_ptr, pn_col, pp_ptr,
+      pp_col;
+  int64_t n_nn = 0, n_np = 0, n_pn = 0, n_pp = 0;
+  std::vector<int64_t> map;
+  int64_t nvals() const { return n_nn + n_np + n_pn + n_pp; }
+};
+
+BOpHost build_bop(const Level& lv, const CsrHost& A) {
+  const int D = lv.D;
+  BOpHost b;
+  b.nrb = 2 * lv.N2;
+  b.npr = lv.Nps + lv.Npf;
+  b.map.assign(A.nnz(), -1);
+  auto node_col = [&](int64_t c) { return c < lv.off_ps || (c >= lv.off_u && c < lv.off_pf); };
+  auto block_off = [&](int64_t c) -> int64_t {
+    return c < lv.off_ps ? D * (c / D) : lv.off_u + D * ((c - lv.off_u) / D);
+  };
+  std::vector<std::pair<int64_t, int64_t>> sec[4];  // (k, relative value index)
+  struct E {
+    int64_t key;
+    int r, q;
+    int64_t k;
+  };
+  std::vector<E> ne, pe;
+  b.nn_ptr.push_back(0);
+  b.np_ptr.push_back(0);
+  for (int64_t rb = 0; rb < b.nrb; ++rb) {
+    const int64_t r0 = rb < lv.N2 ? D * rb : lv.off_u + D * (rb - lv.N2);
+    b.nrow_off.push_back((int32_t)r0);
+    ne.clear();
+    pe.clear();
+    for (int r = 0; r < D; ++r) {
+      const int64_t row = r0 + r;
+      for (int64_t k = A.rowptr[row]; k < A.rowptr[row + 1]; ++k) {
+        const int64_t c = A.col[k];
+        if (node_col(c)) {
+          const int64_t bo = block_off(c);
+          ne.push_back({bo, r, (int)(c - bo), k});
+        } else {
+          pe.push_back({c, r, 0, k});
+        }
+      }
+    }
+    std::sort(ne.begin(), ne.end(), [](const E& x, const E& y) { return x.key < y.key; });
+    std::sort(pe.begin(), pe.end(), [](const E& x, const E& y) { return x.key < y.key; });
+    for (size_t i = 0; i < ne.size(); ++i) {
+      if (i == 0 || ne[i].key != ne[i - 1].key) b.nn_col.push_back((int32_t)ne[i].key);
+      const int64_t bi = (int64_t)b.nn_col.size() - 1;
+      sec[0].emplace_back(ne[i].k, bi * D * D + ne[i].r * D + ne[i].q);
+    }
+    for (size_t i = 0; i < pe.size(); ++i) {
+      if (i == 0 || pe[i].key != pe[i - 1].key) b.np_col.push_back((int32_t)pe[i].key);
+      const int64_t pi = (int64_t)b.np_col.size() - 1;
+      sec[1].emplace_back(pe[i].k, pi * D + pe[i].r);
+    }
+    b.nn_ptr.push_back((int32_t)b.nn_col.size());
+    b.np_ptr.push_back((int32_t)b.np_col.size());
+  }
+  b.pn_ptr.push_back(0);
+  b.pp_ptr.push_back(0);
+  for (int64_t p = 0; p < b.npr; ++p) {
+    const int64_t row = p < lv.Nps ? lv.off_ps + p : lv.off_pf + (p - lv.Nps);
+    b.prow_off.push_back((int32_t)row);
+    ne.clear();
+    pe.clear();
+    for (int64_t k = A.rowptr[row]; k < A.rowptr[row + 1]; ++k) {
+      const int64_t c = A.col[k];
+      if (node_col(c)) {
+        const int64_t bo = block_off(c);
+        ne.push_back({bo, 0, (int)(c - bo), k});
+      } else {
+        pe.push_back({c, 0, 0, k});
+      }
+    }
+    std::sort(ne.begin(), ne.end(), [](const E& x, const E& y) { return x.key < y.key; });
+    std::sort(pe.begin(), pe.end(), [](const E& x, const E& y) { return x.key < y.key; });
+    for (size_t i = 0; i < ne.size(); ++i) {
+      if (i == 0 || ne[i].key != ne[i - 1].key) b.pn_col.push_back((int32_t)ne[i].key);
+      sec[2].emplace_back(ne[i].k, ((int64_t)b.pn_col.size() - 1) * D + ne[i].q);
+    }
+    for (size_t i = 0; i < pe.size(); ++i) {
+      b.pp_col.push_back((int32_t)pe[i].key);
+      sec[3].emplace_back(pe[i].k, (int64_t)b.pp_col.size() - 1);
+    }
+    b.pn_ptr.push_back((int32_t)b.pn_col.size());
+    b.pp_ptr.push_back((int32_t)b.pp_col.size());
+  }
+  b.n_nn = (int64_t)b.nn_col.size() * D * D;
+  b.n_np = (int64_t)b.np_col.size() * D;
+  b.n_pn = (int64_t)b.pn_col.size() * D;
+  b.n_pp = (int64_t)b.pp_col.size();
+  const int64_t base[4] = {0, b.n_nn, b.n_nn + b.n_np, b.n_nn + b.n_np + b.n_pn};
+  for (int s = 0; s < 4; ++s)
+    for (auto& e : sec[s]) b.map[e.first] = base[s] + e.second;
+  return b;
+}
+
+// ---------------------------------------------------------------------------
+struct DevBOp {
+  BOpView<double> v64{};
+  BOpView<float> v32{};
+  double* vals64 = nullptr;
+  float* vals32 = nullptr;
+  int64_t* map = nullptr;      // scalar entry of A -> value index
+  int64_t nvals = 0;
+  bool ready = false;
+};
+
+struct DLevel {
+  int64_t N = 0, nnz = 0;
+  DevBOp A, AT;
+  int64_t* rp = nullptr;
+  int32_t* col = nullptr;
+  double* val = nullptr;
+  double* piece[4] = {nullptr, nullptr, nullptr, nullptr};
+  uint8_t* flags = nullptr;
+  TransferView<double> t64{};
+  TransferView<float> t32{};
+  BlocksView bv{};
+  void* W = nullptr;
+  int64_t W_elems = 0;
+  double *b64 = nullptr, *x64 = nullptr, *r64 = nullptr, *tb64 = nullptr;
+  float *b32 = nullptr, *x32 = nullptr, *r32 = nullptr, *tb32 = nullptr;
+};
+
+}  // namespace
+
+struct fsgmg_hierarchy {
+  // description
+  fsgmg_mesh_desc mesh{};
+  std::vector<double> breaks[3];
+  std::vector<int8_t> region;
+  Physics phys{};
+  std::vector<double> w_finest;
+  int L = 0, D = 2;
+  int device = -1;
+  hipStream_t stream = nullptr;
+  std::string err;
+  // host setup data
+  std::vector<Level> levels;
+  std::vector<LevelOperator> ops;
+  std::vector<Transfer> tr;      // tr[l] for l >= 1
+  std::vector<BlockSet> blocks;  // blocks[l] for l >= 1
+  bool have_blocks = false;      // index sets built
+  bool factors_valid = false;    // block inverses match the current operator
+  fsgmg_smoother_opts sopt{};
+  // device data
+  std::vector<void*> allocs;
+  std::vector<DLevel> dl;
+  double* coarse_inv = nullptr;
+  int64_t n0 = 0;
+  // finest-level extras
+  int64_t* load_rp = nullptr;
+  int32_t* load_col = nullptr;
+  double* load_val = nullptr;
+  double* lift = nullptr;
+  double* lift_piece[4] = {nullptr, nullptr, nullptr, nullptr};
+  int64_t* full_rp = nullptr;
+  int32_t* full_col = nullptr;
+  double* full_piece[4] = {nullptr, nullptr, nullptr, nullptr};
+  uint8_t* dir_mask = nullptr;
+  // Krylov workspace
+  int ws_restart = 0;
+  int64_t ld = 0;
+  double *V = nullptr, *Z = nullptr, *w = nullptr, *part = nullptr, *small = nullptr;
+  double* tmp = nullptr;
+  double* pinned = nullptr;
+  // kernel timing: HIP events around selected launches on the handle stream
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_rec[4];
+
+  bool host_only() const { return device < 0; }
+  hipEvent_t next_event() {
+    if (ev_used == ev_pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) throw Fail{FSGMG_EHIP, "hipEventCreate failed"};
+      ev_pool.push_back(e);
+    }
+    return ev_pool[ev_used++];
+  }
+
+  void* dalloc(size_t bytes) {
+    void* p = nullptr;
+    if (bytes == 0) bytes = 16;
+    if (hipMalloc(&p, bytes) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      throw Fail{FSGMG_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+    }
+    allocs.push_back(p);
+    return p;
+  }
+  template <typename T>
+  T* upload(const std::vector<T>& v) {
+    T* p = (T*)dalloc(v.size() * sizeof(T));
+    if (!v.empty()) HIPCHECK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return p;
+  }
+  template <typename T>
+  T* zeros(int64_t n) {
+    T* p = (T*)dalloc((size_t)n * sizeof(T));
+    HIPCHECK(hipMemset(p, 0, (size_t)n * sizeof(T)));
+    return p;
+  }
+  ~fsgmg_hierarchy() {
+    if (device >= 0) {
+      (void)hipSetDevice(device);
+      for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+      for (void* p : allocs) (void)hipFree(p);
+      if (pinned) (void)hipHostFree(pinned);
+    }
+  }
+};
+
+namespace {
+
+template <typename F>
+fsgmg_status guarded(fsgmg_h h, F&& f) {
+  try {
+    if (h && h->device >= 0) HIPCHECK(hipSetDevice(h->device));
+    return f();
+  } catch (const Fail& e) {
+    if (h) h->err = e.msg;
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    if (h) h->err = "host allocation failed";
+    return FSGMG_ENOMEM;
+  } catch (const std::exception& e) {
+    if (h) h->err = e.what();
+    return FSGMG_EINVAL;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// uploads
+// ---------------------------------------------------------------------------
+void upload_bop(fsgmg_hierarchy& h, const Level& lv, const CsrHost& A, DevBOp& d) {
+  BOpHost b = build_bop(lv, A);
+  std::vector<double> v(b.nvals(), 0.0);
+  for (int64_t k = 0; k < A.nnz(); ++k) v[b.map[k]] = A.val[k];
+  std::vector<float> v32(v.begin(), v.end());
+  d.vals64 = h.upload(v);
+  d.vals32 = h.upload(v32);
+  d.map = h.upload(b.map);
+  d.nvals = b.nvals();
+  BOpView<double>& x = d.v64;
+  x.nrb = b.nrb;
+  x.npr = b.npr;
+  x.nrow_off = h.upload(b.nrow_off);
+  x.nn_ptr = h.upload(b.nn_ptr);
+  x.nn_col = h.upload(b.nn_col);
+  x.np_ptr = h.upload(b.np_ptr);
+  x.np_col = h.upload(b.np_col);
+  x.prow_off = h.upload(b.prow_off);
+  x.pn_ptr = h.upload(b.pn_ptr);
+  x.pn_col = h.upload(b.pn_col);
+  x.pp_ptr = h.upload(b.pp_ptr);
+  x.pp_col = h.upload(b.pp_col);
+  x.nn_val = d.vals64;
+  x.np_val = d.vals64 + b.n_nn;
+  x.pn_val = d.vals64 + b.n_nn + b.n_np;
+  x.pp_val = d.vals64 + b.n_nn + b.n_np + b.n_pn;
+  BOpView<float>& y = d.v32;
+  y.nrb = x.nrb;
+  y.npr = x.npr;
+  y.nrow_off = x.nrow_off;
+  y.nn_ptr = x.nn_ptr;
+  y.nn_col = x.nn_col;
+  y.np_ptr = x.np_ptr;
+  y.np_col = x.np_col;
+  y.prow_off = x.prow_off;
+  y.pn_ptr = x.pn_ptr;
+  y.pn_col = x.pn_col;
+  y.pp_ptr = x.pp_ptr;
+  y.pp_col = x.pp_col;
+  y.nn_val = d.vals32;
+  y.np_val = d.vals32 + b.n_nn;
+  y.pn_val = d.vals32 + b.n_nn + b.n_np;
+  y.pp_val = d.vals32 + b.n_nn + b.n_np + b.n_pn;
+  d.ready = true;
+}
+
+std::vector<uint8_t> node_flags(const Level& lv) {
+  std::vector<uint8_t> f(lv.N2, 0);
+  for (int64_t n = 0; n < lv.N2; ++n) {
+    uint8_t v = lv.solid_side[n] ? 1 : 0;
+    if (lv.dir[(int64_t)lv.D * n]) v |= 2;
+    if (lv.dir[lv.off_u + (int64_t)lv.D * n]) v |= 4;
+    f[n] = v;
+  }
+  return f;
+}
+
+std::vector<int32_t> ptr32(const std::vector<int64_t>& p) {
+  std::vector<int32_t> o(p.size());
+  for (size_t i = 0; i < p.size(); ++i) o[i] = (int32_t)p[i];
+  return o;
+}
+
+template <typename T>
+std::vector<T> conv(const std::vector<double>& v) {
+  return std::vector<T>(v.begin(), v.end());
+}
+
+void upload_transfer(fsgmg_hierarchy& h, int l) {
+  const Level& f = h.levels[l];
+  const Level& c = h.levels[l - 1];
+  const Transfer& t = h.tr[l];
+  DLevel& d = h.dl[l];
+  TransferView<double>& v = d.t64;
+  v.N2f = f.N2;
+  v.N2c = c.N2;
+  v.Npsf = f.Nps;
+  v.Npff = f.Npf;
+  v.Npsc = c.Nps;
+  v.Npfc = c.Npf;
+  v.offu_f = f.off_u;
+  v.offps_f = f.off_ps;
+  v.offpf_f = f.off_pf;
+  v.offu_c = c.off_u;
+  v.offps_c = c.off_ps;
+  v.offpf_c = c.off_pf;
+  v.pn_ptr = h.upload(ptr32(t.Pn.rowptr));
+  v.pn_col = h.upload(t.Pn.col);
+  v.rn_ptr = h.upload(ptr32(t.Rn.rowptr));
+  v.rn_col = h.upload(t.Rn.col);
+  v.pps_ptr = h.upload(ptr32(t.Pps.rowptr));
+  v.pps_col = h.upload(t.Pps.col);
+  v.ppf_ptr = h.upload(ptr32(t.Ppf.rowptr));
+  v.ppf_col = h.upload(t.Ppf.col);
+  v.rps_ptr = h.upload(ptr32(t.Rps.rowptr));
+  v.rps_col = h.upload(t.Rps.col);
+  v.rpf_ptr = h.upload(ptr32(t.Rpf.rowptr));
+  v.rpf_col = h.upload(t.Rpf.col);
+  v.flags_f = h.dl[l].flags;
+  v.flags_c = h.dl[l - 1].flags;
+  TransferView<float>& u = d.t32;
+  std::memcpy((void*)&u, (const void*)&v, sizeof(u));   // same layout: ints/pointers
+  v.pn_val = h.upload(t.Pn.val);
+  v.rn_val = h.upload(t.Rn.val);
+  v.pps_val = h.upload(t.Pps.val);
+  v.ppf_val = h.upload(t.Ppf.val);
+  v.rps_val = h.upload(t.Rps.val);
+  v.rpf_val = h.upload(t.Rpf.val);
+  u.pn_val = h.upload(conv<float>(t.Pn.val));
+  u.rn_val = h.upload(conv<float>(t.Rn.val));
+  u.pps_val = h.upload(conv<float>(t.Pps.val));
+  u.ppf_val = h.upload(conv<float>(t.Ppf.val));
+  u.rps_val = h.upload(conv<float>(t.Rps.val));
+  u.rpf_val = h.upload(conv<float>(t.Rpf.val));
+}
+
+// dense FP64 copy of a (small) CSR matrix, inverted on the device
+void build_coarse_inverse(fsgmg_hierarchy& h) {
+  const CsrHost& A = h.ops[0].A;
+  const int64_t n = A.nrows;
+  if (n > 2800) throw Fail{FSGMG_EINVAL, "coarse level too large for the dense inverse (n > 2800)"};
+  std::vector<double> dense((size_t)(n * n), 0.0);
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k) dense[i * n + A.col[k]] = A.val[k];
+  if (!h.coarse_inv) h.coarse_inv = (double*)h.dalloc((size_t)(n * n) * sizeof(double));
+  HIPCHECK(hipMemcpy(h.coarse_inv, dense.data(), dense.size() * sizeof(double), hipMemcpyHostToDevice));
+  std::vector<int64_t> dp = {0, n}, off = {0};
+  int64_t* d_dp = (int64_t*)h.dalloc(2 * sizeof(int64_t));
+  int64_t* d_off = (int64_t*)h.dalloc(sizeof(int64_t));
+  int32_t* d_st = (int32_t*)h.dalloc(sizeof(int32_t));
+  HIPCHECK(hipMemcpy(d_dp, dp.data(), 2 * sizeof(int64_t), hipMemcpyHostToDevice));
+  HIPCHECK(hipMemcpy(d_off, off.data(), sizeof(int64_t), hipMemcpyHostToDevice));
+  launch_invert_blocks(0, 1, d_dp, d_off, h.coarse_inv, d_st, (int)n, h.stream);
+  HIPCHECK(hipGetLastError());
+  int32_t st = 0;
+  HIPCHECK(hipMemcpyAsync(&st, d_st, sizeof(int32_t), hipMemcpyDeviceToHost, h.stream));
+  HIPCHECK(hipStreamSynchronize(h.stream));
+  if (st) throw Fail{FSGMG_ESINGULAR, "coarse-level matrix is singular"};
+  h.n0 = n;
+}
+
+void upload_all(fsgmg_hierarchy& h) {
+  h.dl.resize(h.L);
+  for (int l = 0; l < h.L; ++l) {
+    const Level& lv = h.levels[l];
+    const LevelOperator& op = h.ops[l];
+    DLevel& d = h.dl[l];
+    d.N = lv.N;
+    d.nnz = op.A.nnz();
+    d.flags = h.upload(node_flags(lv));
+    upload_bop(h, lv, op.A, d.A);
+    d.rp = h.upload(op.A.rowptr);
+    d.col = h.upload(op.A.col);
+    d.val = h.upload(op.A.val);
+    for (int p = 0; p < 4; ++p) d.piece[p] = h.upload(op.piece[p]);
+    d.b64 = h.zeros<double>(lv.N);
+    d.x64 = h.zeros<double>(lv.N);
+    d.r64 = h.zeros<double>(lv.N);
+    d.b32 = h.zeros<float>(lv.N);
+    d.x32 = h.zeros<float>(lv.N);
+    d.r32 = h.zeros<float>(lv.N);
+  }
+  for (int l = 1; l < h.L; ++l) upload_transfer(h, l);
+  const Level& F = h.levels[h.L - 1];
+  const LevelOperator& op = h.ops[h.L - 1];
+  h.load_rp = h.upload(op.load.rowptr);
+  h.load_col = h.upload(op.load.col);
+  h.load_val = h.upload(op.load.val);
+  for (int p = 0; p < 4; ++p) h.lift_piece[p] = h.upload(op.lift_piece[p]);
+  std::vector<double> lift(F.N);
+  for (int64_t i = 0; i < F.N; ++i)
+    lift[i] = op.lift_piece[0][i] + op.G * op.lift_piece[1][i] + op.invlam * op.lift_piece[2][i] +
+              op.mu * op.lift_piece[3][i];
+  h.lift = h.upload(lift);
+  h.full_rp = h.upload(op.full.rowptr);
+  h.full_col = h.upload(op.full.col);
+  for (int p = 0; p < 4; ++p) h.full_piece[p] = h.upload(op.full_piece[p]);
+  h.dir_mask = h.upload(F.dir);
+  h.tmp = h.zeros<double>(F.N);
+  build_coarse_inverse(h);
+}
+
+void ensure_transposed(fsgmg_hierarchy& h) {
+  for (int l = 0; l < h.L; ++l) {
+    DLevel& d = h.dl[l];
+    if (d.AT.ready) continue;
+    const CsrHost& A = h.ops[l].A;
+    CsrHost T = csr_transpose(A);
+    upload_bop(h, h.levels[l], T, d.AT);
+    // value map from A's entries into AT: position of (i,j) in T
+    std::vector<int64_t> pos(A.nnz());
+    std::vector<int64_t> cur(T.rowptr.begin(), T.rowptr.end() - 1);
+    for (int64_t i = 0; i < A.nrows; ++i)
+      for (int64_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k) pos[k] = cur[A.col[k]]++;
+    BOpHost bt = build_bop(h.levels[l], T);
+    std::vector<int64_t> m(A.nnz());
+    for (int64_t k = 0; k < A.nnz(); ++k) m[k] = bt.map[pos[k]];
+    HIPCHECK(hipMemcpy(d.AT.map, m.data(), m.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FS-AS block factors
+// ---------------------------------------------------------------------------
+int rows_per_vector(fsgmg_prec p) { return p == FSGMG_FP64 ? 2 : (p == FSGMG_FP32 ? 4 : 8); }
+size_t w_bytes(fsgmg_prec p) { return p == FSGMG_FP64 ? 8 : (p == FSGMG_FP32 ? 4 : 2); }
+WPrec wprec(fsgmg_prec p) {
+  return p == FSGMG_FP64 ? WPrec::F64 : (p == FSGMG_FP32 ? WPrec::F32 : WPrec::BF16);
+}
+
+void upload_blocks(fsgmg_hierarchy& h, int l) {
+  const Level& lv = h.levels[l];
+  const BlockSet& bs = h.blocks[l];
+  DLevel& d = h.dl[l];
+  const int RV = rows_per_vector(h.sopt.prec);
+  const int64_t nb = bs.nblk();
+  std::vector<int32_t> own_ptr(1, 0), own_dof, own_loc, mpad(nb);
+  std::vector<int64_t> w_off(nb + 1, 0);
+  int max_n = 0, max_mpad = 0;
+  for (int64_t j = 0; j < nb; ++j) {
+    const int64_t b0 = bs.ptr[j], n = bs.ptr[j + 1] - b0;
+    int m = 0;
+    for (int64_t k = 0; k < n; ++k)
+      if (bs.owner[bs.dofs[b0 + k]] == (int32_t)j) {
+        own_dof.push_back(bs.dofs[b0 + k]);
+        own_loc.push_back((int32_t)k);
+        ++m;
+      }
+    own_ptr.push_back((int32_t)own_dof.size());
+    const int mp = std::max(RV, (m + RV - 1) / RV * RV);
+    mpad[j] = mp;
+    w_off[j + 1] = w_off[j] + n * mp;
+    max_n = std::max(max_n, (int)n);
+    max_mpad = std::max(max_mpad, mp);
+  }
+  // transposed apply: DOF -> positions (block order)
+  std::vector<int32_t> tcnt(lv.N + 1, 0), tpos(bs.dofs.size());
+  for (int32_t g : bs.dofs) tcnt[g + 1]++;
+  for (int64_t i = 0; i < lv.N; ++i) tcnt[i + 1] += tcnt[i];
+  {
+    std::vector<int32_t> cur(tcnt.begin(), tcnt.end() - 1);
+    for (int64_t p = 0; p < (int64_t)bs.dofs.size(); ++p) tpos[cur[bs.dofs[p]]++] = (int32_t)p;
+  }
+  // Jacobi inverse diagonal
+  const CsrHost& A = h.ops[l].A;
+  std::vector<double> jinv(bs.jac.size());
+  for (size_t q = 0; q < bs.jac.size(); ++q) {
+    const int32_t i = bs.jac[q];
+    double dg = 0.0;
+    for (int64_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k)
+      if (A.col[k] == i) dg = A.val[k];
+    if (dg == 0.0) throw Fail{FSGMG_ESINGULAR, "zero diagonal on a Jacobi row " + std::to_string(i)};
+    jinv[q] = 1.0 / dg;
+  }
+  BlocksView& v = d.bv;
+  v.nblk = nb;
+  v.njac = (int64_t)bs.jac.size();
+  v.dof_ptr = h.upload(bs.ptr);
+  v.dofs = h.upload(bs.dofs);
+  v.own_ptr = h.upload(own_ptr);
+  v.own_dof = h.upload(own_dof);
+  v.own_loc = h.upload(own_loc);
+  v.w_off = h.upload(w_off);
+  v.mpad = h.upload(mpad);
+  v.jac = h.upload(bs.jac);
+  v.jac_inv = h.sopt.prec == FSGMG_FP64 ? (const void*)h.upload(jinv)
+                                        : (const void*)h.upload(conv<float>(jinv));
+  v.max_n = max_n;
+  v.max_mpad = max_mpad;
+  v.tpos_ptr = h.upload(tcnt);
+  v.tpos = h.upload(tpos);
+  d.W_elems = w_off[nb];
+  d.W = h.dalloc((size_t)d.W_elems * w_bytes(h.sopt.prec) + 64);
+  const int64_t ntot = (int64_t)bs.dofs.size();
+  if (h.sopt.prec == FSGMG_FP64)
+    d.tb64 = h.zeros<double>(std::max<int64_t>(ntot, 1));
+  else
+    d.tb32 = h.zeros<float>(std::max<int64_t>(ntot, 1));
+}
+
+void factor_blocks(fsgmg_hierarchy& h, int l) {
+  const BlockSet& bs = h.blocks[l];
+  DLevel& d = h.dl[l];
+  const int64_t nb = bs.nblk();
+  if (nb == 0) return;
+  const size_t budget = (size_t)1 << 30;   // dense FP64 scratch per chunk
+  size_t maxchunk = 0;
+  std::vector<int64_t> starts(1, 0);
+  {
+    size_t acc = 0;
+    for (int64_t j = 0; j < nb; ++j) {
+      const size_t n = (size_t)(bs.ptr[j + 1] - bs.ptr[j]);
+      if (acc > 0 && acc + n * n * 8 > budget) {
+        starts.push_back(j);
+        maxchunk = std::max(maxchunk, acc);
+        acc = 0;
+      }
+      acc += n * n * 8;
+    }
+    maxchunk = std::max(maxchunk, acc);
+    starts.push_back(nb);
+  }
+  double* dense = (double*)h.dalloc(maxchunk);
+  int64_t* doff = (int64_t*)h.dalloc((size_t)(nb + 1) * sizeof(int64_t));
+  int32_t* status = h.zeros<int32_t>(nb);
+  std::vector<int64_t> hoff;
+  for (size_t c = 0; c + 1 < starts.size(); ++c) {
+    const int64_t j0 = starts[c], j1 = starts[c + 1];
+    hoff.assign(1, 0);
+    for (int64_t j = j0; j < j1; ++j) {
+      const int64_t n = bs.ptr[j + 1] - bs.ptr[j];
+      hoff.push_back(hoff.back() + n * n);
+    }
+    HIPCHECK(hipMemcpyAsync(doff, hoff.data(), hoff.size() * sizeof(int64_t), hipMemcpyHostToDevice,
+                            h.stream));
+    launch_gather_blocks(j0, j1 - j0, d.bv, d.rp, d.col, d.val, doff, dense, h.stream);
+    launch_invert_blocks(j0, j1 - j0, d.bv.dof_ptr, doff, dense, status, d.bv.max_n, h.stream);
+    launch_extract_owned(j0, j1 - j0, d.bv, doff, dense, wprec(h.sopt.prec), d.W, h.stream);
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipStreamSynchronize(h.stream));
+  }
+  std::vector<int32_t> st(nb);
+  HIPCHECK(hipMemcpy(st.data(), status, nb * sizeof(int32_t), hipMemcpyDeviceToHost));
+  // scratch is released at once (bump allocations are freed in order)
+  for (void* p : {(void*)dense, (void*)doff, (void*)status}) {
+    auto it = std::find(h.allocs.begin(), h.allocs.end(), p);
+    if (it != h.allocs.end()) {
+      (void)hipFree(p);
+      h.allocs.erase(it);
+    }
+  }
+  for (int64_t j = 0; j < nb; ++j)
+    if (st[j]) throw Fail{FSGMG_ESINGULAR, "singular Schwarz block " + std::to_string(j) + " on level " + std::to_string(l)};
+}
+
+// ---------------------------------------------------------------------------
+// optional event timing of selected launches (kinds: 0 finest smoother sweep,
+// 1 finest residual SpMV of the V-cycle, 2 outer FP64 SpMV, 3 finest-level
+// restriction + prolongation)
+// ---------------------------------------------------------------------------
+struct TimedLaunch {
+  fsgmg_hierarchy& h;
+  int kind;
+  hipEvent_t b = nullptr;
+  TimedLaunch(fsgmg_hierarchy& hh, int k, bool on) : h(hh), kind(k) {
+    if (on && h.timing) {
+      b = h.next_event();
+      HIPCHECK(hipEventRecord(b, h.stream));
+    }
+  }
+  ~TimedLaunch() noexcept(false) {
+    if (b) {
+      hipEvent_t e = h.next_event();
+      HIPCHECK(hipEventRecord(e, h.stream));
+      h.ev_rec[kind].emplace_back(b, e);
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
+// V-cycle
+// ---------------------------------------------------------------------------
+template <typename TV>
+struct Vec;
+template <>
+struct Vec<double> {
+  static double* b(DLevel& d) { return d.b64; }
+  static double* x(DLevel& d) { return d.x64; }
+  static double* r(DLevel& d) { return d.r64; }
+  static double* t(DLevel& d) { return d.tb64; }
+  static const BOpView<double>& op(DLevel& d, bool tr) { return tr ? d.AT.v64 : d.A.v64; }
+  static const TransferView<double>& tv(DLevel& d) { return d.t64; }
+};
+template <>
+struct Vec<float> {
+  static float* b(DLevel& d) { return d.b32; }
+  static float* x(DLevel& d) { return d.x32; }
+  static float* r(DLevel& d) { return d.r32; }
+  static float* t(DLevel& d) { return d.tb32; }
+  static const BOpView<float>& op(DLevel& d, bool tr) { return tr ? d.AT.v32 : d.A.v32; }
+  static const TransferView<float>& tv(DLevel& d) { return d.t32; }
+};
+
+template <typename TV>
+void smooth_level(fsgmg_hierarchy& h, int l, int nsweeps, bool transpose, bool from_zero) {
+  DLevel& d = h.dl[l];
+  const int D = h.D;
+  const WPrec wp = wprec(h.sopt.prec);
+  TV* b = Vec<TV>::b(d);
+  TV* x = Vec<TV>::x(d);
+  TV* r = Vec<TV>::r(d);
+  const bool fin = l == h.L - 1;
+  for (int s = 0; s < nsweeps; ++s) {
+    if (s == 0 && from_zero) {
+      TimedLaunch t(h, 0, fin);
+      launch_smooth<TV>(d.bv, wp, d.W, b, x, Vec<TV>::t(d), h.sopt.omega, true, transpose, d.N,
+                        h.stream);
+    } else {
+      {
+        TimedLaunch t(h, 1, fin);
+        launch_spmv<TV>(Vec<TV>::op(d, transpose), D, x, b, r, true, h.stream);
+      }
+      TimedLaunch t(h, 0, fin);
+      launch_smooth<TV>(d.bv, wp, d.W, r, x, Vec<TV>::t(d), h.sopt.omega, false, transpose, d.N,
+                        h.stream);
+    }
+  }
+}
+
+template <typename TV>
+void vcycle_impl(fsgmg_hierarchy& h, const double* rin, double* zout, bool transpose) {
+  const int L = h.L, D = h.D;
+  const int npre = transpose ? h.sopt.nu_post : h.sopt.nu_pre;
+  const int npost = transpose ? h.sopt.nu_pre : h.sopt.nu_post;
+  DLevel& F = h.dl[L - 1];
+  launch_cast<double, TV>(rin, Vec<TV>::b(F), F.N, h.stream);
+  for (int l = L - 1; l >= 1; --l) {
+    DLevel& d = h.dl[l];
+    if (npre == 0) launch_fill<TV>(Vec<TV>::x(d), TV(0), d.N, h.stream);
+    smooth_level<TV>(h, l, npre, transpose, true);
+    {
+      TimedLaunch t(h, 1, l == L - 1);
+      launch_spmv<TV>(Vec<TV>::op(d, transpose), D, Vec<TV>::x(d), Vec<TV>::b(d), Vec<TV>::r(d),
+                      true, h.stream);
+    }
+    TimedLaunch t(h, 3, l == L - 1);
+    launch_transfer<TV>(Vec<TV>::tv(d), D, transpose ? 2 : 0, Vec<TV>::r(d), Vec<TV>::b(h.dl[l - 1]),
+                        h.stream);
+  }
+  DLevel& C = h.dl[0];
+  launch_dense_gemv<TV>(h.n0, h.coarse_inv, transpose, Vec<TV>::b(C), Vec<TV>::x(C), h.stream);
+  for (int l = 1; l < L; ++l) {
+    DLevel& d = h.dl[l];
+    {
+      TimedLaunch t(h, 3, l == L - 1);
+      launch_transfer<TV>(Vec<TV>::tv(d), D, transpose ? 3 : 1, Vec<TV>::x(h.dl[l - 1]),
+                          Vec<TV>::x(d), h.stream);
+    }
+    smooth_level<TV>(h, l, npost, transpose, false);
+  }
+  launch_cast<TV, double>(Vec<TV>::x(F), zout, F.N, h.stream);
+}
+
+void vcycle(fsgmg_hierarchy& h, const double* r, double* z, bool transpose) {
+  if (h.L == 1) {
+    launch_dense_gemv<double>(h.n0, h.coarse_inv, transpose, r, z, h.stream);
+    return;
+  }
+  if (h.sopt.prec == FSGMG_FP64)
+    vcycle_impl<double>(h, r, z, transpose);
+  else
+    vcycle_impl<float>(h, r, z, transpose);
+}
+
+// ---------------------------------------------------------------------------
+// FGMRES
+// ---------------------------------------------------------------------------
+void ensure_workspace(fsgmg_hierarchy& h, int m) {
+  if (h.ws_restart >= m) return;
+  const int64_t N = h.dl[h.L - 1].N;
+  h.ld = (N + 63) / 64 * 64;
+  h.V = h.zeros<double>((int64_t)(m + 1) * h.ld);
+  h.Z = h.zeros<double>((int64_t)m * h.ld);
+  h.w = h.zeros<double>(h.ld);
+  if (!h.part) h.part = h.zeros<double>(krylov_partials());
+  if (!h.small) h.small = h.zeros<double>(256);
+  if (!h.pinned) HIPCHECK(hipHostMalloc((void**)&h.pinned, 256 * sizeof(double), hipHostMallocDefault));
+  h.ws_restart = m;
+}
+
+double device_norm(fsgmg_hierarchy& h, const double* v, int64_t N) {
+  launch_norm2_partial(v, N, h.part, h.stream);
+  launch_reduce_partials(h.part, 1, h.small + 128, nullptr, true, h.stream);
+  HIPCHECK(hipMemcpyAsync(h.pinned, h.small + 128, sizeof(double), hipMemcpyDeviceToHost, h.stream));
+  HIPCHECK(hipStreamSynchronize(h.stream));
+  return h.pinned[0];
+}
+
+fsgmg_status fgmres(fsgmg_hierarchy& h, const double* b, double* x, const fsgmg_krylov_opts& o,
+                    fsgmg_solve_info* info, bool transpose) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (o.restart < 1 || o.restart > 31 || o.rtol <= 0 || o.max_restarts < 0)
+    throw Fail{FSGMG_EINVAL, "krylov options out of range (restart 1..31, rtol > 0)"};
+  if (!h.factors_valid) throw Fail{FSGMG_ESTATE, "build_fs_as_blocks has not been called"};
+  if (transpose) ensure_transposed(h);
+  const int m = o.restart;
+  ensure_workspace(h, m);
+  DLevel& F = h.dl[h.L - 1];
+  const int64_t N = F.N, ld = h.ld;
+  const BOpView<double>& A = transpose ? F.AT.v64 : F.A.v64;
+  double* const h1 = h.small;       // 32
+  double* const h2 = h.small + 32;  // 32
+  double* const nr = h.small + 64;  // 1
+  double* const yv = h.small + 96;  // 32
+  std::vector<double> hist;
+  const double bnorm = device_norm(h, b, N);
+  if (!std::isfinite(bnorm)) throw Fail{FSGMG_EINVAL, "right-hand side contains NaN or Inf"};
+  launch_fill<double>(x, 0.0, N, h.stream);
+  int iters = 0, restarts = 0;
+  bool converged = false;
+  double true_rel = NAN;
+  if (bnorm == 0.0) {
+    converged = true;
+    true_rel = 0.0;
+  }
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  for (int cycle = 0; !converged && cycle <= o.max_restarts; ++cycle) {
+    launch_spmv<double>(A, h.D, x, b, h.w, true, h.stream);
+    const double beta = device_norm(h, h.w, N);
+    if (cycle == 0) hist.push_back(beta / bnorm);
+    if (beta <= o.rtol * bnorm) {
+      converged = true;
+      true_rel = beta / bnorm;
+      break;
+    }
+    launch_scale_copy(h.w, h.small + 128, h.V, N, h.stream);
+    std::fill(H.begin(), H.end(), 0.0);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int k = 0;
+    for (int j = 0; j < m; ++j) {
+      double* vj = h.V + (int64_t)j * ld;
+      double* zj = h.Z + (int64_t)j * ld;
+      vcycle(h, vj, zj, transpose);
+      {
+        TimedLaunch t(h, 2, true);
+        launch_spmv<double>(A, h.D, zj, nullptr, h.w, false, h.stream);
+      }
+      launch_mdot(h.V, ld, j + 1, h.w, N, h.part, h.stream);
+      launch_reduce_partials(h.part, j + 1, h1, nullptr, false, h.stream);
+      launch_maxpy_mdot(h.V, ld, j + 1, h1, h.w, N, h.part, h.stream);
+      launch_reduce_partials(h.part, j + 1, h2, nullptr, false, h.stream);
+      launch_maxpy_norm(h.V, ld, j + 1, h2, h.w, N, h.part, h.stream);
+      launch_reduce_partials(h.part, 1, nr, nullptr, true, h.stream);
+      HIPCHECK(hipMemcpyAsync(h.pinned, h.small, 65 * sizeof(double), hipMemcpyDeviceToHost, h.stream));
+      HIPCHECK(hipStreamSynchronize(h.stream));
+      const double hn = h.pinned[64];
+      for (int i = 0; i <= j; ++i) H[i * m + j] = h.pinned[i] + h.pinned[32 + i];
+      H[(j + 1) * m + j] = hn;
+      for (int i = 0; i < j; ++i) {
+        const double t = cs[i] * H[i * m + j] + sn[i] * H[(i + 1) * m + j];
+        H[(i + 1) * m + j] = -sn[i] * H[i * m + j] + cs[i] * H[(i + 1) * m + j];
+        H[i * m + j] = t;
+      }
+      const double den = std::hypot(H[j * m + j], H[(j + 1) * m + j]);
+      cs[j] = H[j * m + j] / den;
+      sn[j] = H[(j + 1) * m + j] / den;
+      H[j * m + j] = den;
+      H[(j + 1) * m + j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++iters;
+      k = j + 1;
+      const double est = std::fabs(g[j + 1]);
+      hist.push_back(est / bnorm);
+      if (!std::isfinite(est)) throw Fail{FSGMG_EINVAL, "non-finite residual estimate"};
+      if (est <= o.rtol * bnorm || hn == 0.0) break;
+      launch_scale_copy(h.w, nr, h.V + (int64_t)(j + 1) * ld, N, h.stream);
+    }
+    for (int i = k - 1; i >= 0; --i) {
+      double s = g[i];
+      for (int q = i + 1; q < k; ++q) s -= H[i * m + q] * y[q];
+      y[i] = s / H[i * m + i];
+    }
+    HIPCHECK(hipMemcpyAsync(yv, y.data(), k * sizeof(double), hipMemcpyHostToDevice, h.stream));
+    launch_gemv_update(h.Z, ld, k, yv, x, N, h.stream);
+    launch_spmv<double>(A, h.D, x, b, h.w, true, h.stream);
+    true_rel = device_norm(h, h.w, N) / bnorm;
+    if (true_rel <= o.rtol) {
+      converged = true;
+      break;
+    }
+    ++restarts;
+  }
+  HIPCHECK(hipGetLastError());
+  if (info) {
+    info->iters = iters;
+    info->restarts = restarts;
+    info->converged = converged ? 1 : 0;
+    info->rel_res_true = true_rel;
+    info->history_len = (int)hist.size();
+    if (info->history && info->history_cap > 0)
+      for (int i = 0; i < std::min(info->history_cap, (int)hist.size()); ++i) info->history[i] = hist[i];
+    info->t_solve_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return converged ? FSGMG_OK : FSGMG_NOT_CONVERGED;
+}
+
+void check_device(fsgmg_hierarchy& h) {
+  if (h.host_only()) throw Fail{FSGMG_ESTATE, "device call on a host-only handle"};
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+fsgmg_status setup_hierarchy(const fsgmg_mesh_desc* mesh, const fsgmg_physics* phys, int device,
+                             void* stream, fsgmg_h* out) {
+  if (!mesh || !phys || !out) return FSGMG_EINVAL;
+  *out = nullptr;
+  auto h = std::make_unique<fsgmg_hierarchy>();
+  h->device = device;
+  h->stream = (hipStream_t)stream;
+  fsgmg_status st = guarded(h.get(), [&]() -> fsgmg_status {
+    if (mesh->dim != 2) throw Fail{FSGMG_EINVAL, "only dim = 2 is supported"};
+    if (mesh->n_levels < 1 || mesh->n_levels > 12) throw Fail{FSGMG_EINVAL, "n_levels out of range"};
+    int64_t nce = 1;
+    for (int a = 0; a < mesh->dim; ++a) {
+      if (mesh->nc[a] < 1 || !mesh->breaks[a]) throw Fail{FSGMG_EINVAL, "bad coarse mesh"};
+      nce *= mesh->nc[a];
+    }
+    if (!mesh->region) throw Fail{FSGMG_EINVAL, "region tags missing"};
+    if (!(phys->E > 0) || !(phys->nu > 0 && phys->nu <= 0.5) || !(phys->mu > 0) || !(phys->rho > 0))
+      throw Fail{FSGMG_EINVAL, "physical parameters out of range"};
+    h->mesh = *mesh;
+    for (int a = 0; a < mesh->dim; ++a) {
+      h->breaks[a].assign(mesh->breaks[a], mesh->breaks[a] + mesh->nc[a] + 1);
+      h->mesh.breaks[a] = h->breaks[a].data();
+    }
+    h->region.assign(mesh->region, mesh->region + nce);
+    h->mesh.region = h->region.data();
+    h->L = mesh->n_levels;
+    h->D = mesh->dim;
+    h->levels.resize(h->L);
+    for (int l = 0; l < h->L; ++l) build_level(h->mesh, l, h->levels[l]);
+    const Level& Fl = h->levels[h->L - 1];
+    if (phys->w) h->w_finest.assign(phys->w, phys->w + Fl.N2 * h->D);
+    h->phys = Physics{phys->E, phys->nu, phys->mu, phys->rho,
+                      (phys->dt > 0 && std::isfinite(phys->dt)) ? 1.0 / phys->dt : 0.0,
+                      phys->supg, phys->ale_k, phys->k_mass,
+                      h->w_finest.empty() ? nullptr : h->w_finest.data(), h->L};
+    std::vector<double> cvol = element_volumes(h->levels[0]);
+    h->ops.resize(h->L);
+    for (int l = 0; l < h->L; ++l) {
+      const Level& lv = h->levels[l];
+      std::vector<double> wl;
+      if (!h->w_finest.empty()) {
+        const int step = 1 << (h->L - 1 - l);
+        wl.resize(lv.N2 * h->D);
+        for (int64_t n = 0; n < lv.N2; ++n) {
+          int ix[kMaxDim] = {0, 0, 0};
+          lv.node_ijk(n, ix);
+          int fx[kMaxDim] = {0, 0, 0};
+          for (int a = 0; a < h->D; ++a) fx[a] = ix[a] * step;
+          const int64_t fn = Fl.node_index(fx);
+          for (int c = 0; c < h->D; ++c) wl[n * h->D + c] = h->w_finest[fn * h->D + c];
+        }
+      }
+      assemble_level(lv, h->phys, cvol, wl.empty() ? nullptr : &wl, l == h->L - 1, h->ops[l]);
+    }
+    h->tr.resize(h->L);
+    for (int l = 1; l < h->L; ++l) build_transfer(h->levels[l], h->levels[l - 1], h->tr[l]);
+    h->blocks.resize(h->L);
+    if (device >= 0) {
+      int ndev = 0;
+      HIPCHECK(hipGetDeviceCount(&ndev));
+      if (device >= ndev) throw Fail{FSGMG_EINVAL, "device index out of range"};
+      HIPCHECK(hipSetDevice(device));
+      upload_all(*h);
+      HIPCHECK(hipStreamSynchronize(h->stream));
+    }
+    return FSGMG_OK;
+  });
+  // on failure the handle is still returned so that last_error() can be read;
+  // the caller destroys it
+  *out = h.release();
+  return st;
+}
+
+fsgmg_status build_fs_as_blocks(fsgmg_h h, const fsgmg_smoother_opts* opts) {
+  if (!h || !opts) return FSGMG_EINVAL;
+  return guarded(h, [&]() -> fsgmg_status {
+    if (opts->halo < 0 || opts->nu_pre < 0 || opts->nu_post < 0 || !(opts->omega > 0))
+      throw Fail{FSGMG_EINVAL, "smoother options out of range"};
+    for (int a = 0; a < h->D; ++a)
+      if (opts->core[a] < 1) throw Fail{FSGMG_EINVAL, "core sizes must be >= 1"};
+    if (opts->prec < FSGMG_FP64 || opts->prec > FSGMG_BF16) throw Fail{FSGMG_EINVAL, "bad precision"};
+    const bool same_sets = h->have_blocks && h->sopt.halo == opts->halo &&
+                           h->sopt.core[0] == opts->core[0] && h->sopt.core[1] == opts->core[1] &&
+                           h->sopt.prec == opts->prec;
+    h->sopt = *opts;
+    h->factors_valid = false;
+    if (!same_sets) {
+      for (int l = 1; l < h->L; ++l) build_blocks(h->levels[l], opts->core, opts->halo, h->blocks[l]);
+      h->have_blocks = true;
+      if (!h->host_only())
+        for (int l = 1; l < h->L; ++l) upload_blocks(*h, l);
+    }
+    if (h->host_only()) return FSGMG_OK;
+    for (int l = 1; l < h->L; ++l) factor_blocks(*h, l);
+    h->factors_valid = true;
+    return FSGMG_OK;
+  });
+}
+
+fsgmg_status vcycle_apply(fsgmg_h h, const double* r, double* z, int transpose) {
+  if (!h || !r || !z || r == z) return FSGMG_EINVAL;
+  return guarded(h, [&]() -> fsgmg_status {
+    check_device(*h);
+    if (!h->factors_valid) throw Fail{FSGMG_ESTATE, "build_fs_as_blocks has not been called"};
+    if (transpose) ensure_transposed(*h);
+    vcycle(*h, r, z, transpose != 0);
+    HIPCHECK(hipGetLastError());
+    return FSGMG_OK;
+  });
+}
+
+fsgmg_status gmres_solve(fsgmg_h h, const double* b, double* x, const fsgmg_krylov_opts* opts,
+                         fsgmg_solve_info* info) {
+  if (!h || !b || !x || !opts || b == x) return FSGMG_EINVAL;
+  return guarded(h, [&]() -> fsgmg_status {
+    check_device(*h);
+    return fgmres(*h, b, x, *opts, info, false);
+  });
+}
+
+fsgmg_status adjoint_solve(fsgmg_h h, const double* c, double* lam, const fsgmg_krylov_opts* opts,
+                           fsgmg_solve_info* info) {
+  if (!h || !c || !lam || !opts || c == lam) return FSGMG_EINVAL;
+  return guarded(h, [&]() -> fsgmg_status {
+    check_device(*h);
+    return fgmres(*h, c, lam, *opts, info, true);
+  });
+}
+
+fsgmg_status assemble_load(fsgmg_h h, const double* f, double* b) {
+  if (!h || !f || !b) return FSGMG_EINVAL;
+  return guarded(h, [&]() -> fsgmg_status {
+    check_device(*h);
+    launch_load_rhs(h->dl[h->L - 1].N, h->load_rp, h->load_col, h->load_val, f, h->lift, b, h->stream);
+    HIPCHECK(hipGetLastError());
+    return FSGMG_OK;
+  });
+}
+
+fsgmg_status apply_operator(fsgmg_h h, int level, const double* x, double* y, int transpose) {
+  if (!h || !x || !y || x == y) return FSGMG_EINVAL;
+  return guarded(h, [&]() -> fsgmg_status {
+    check_device(*h);
+    if (level < 0 || level >= h->L) throw Fail{FSGMG_EINVAL, "level out of range"};
+    if (transpose) ensure_transposed(*h);
+    DLevel& d = h->dl[level];
+    launch_spmv<double>(transpose ? d.AT.v64 : d.A.v64, h->D, x, nullptr, y, false, h->stream);
+    HIPCHECK(hipGetLastError());
+    return FSGMG_OK;
+  });
+}
+
+fsgmg_status param_grad(fsgmg_h h, const double* lam, const double* x, double out[2]) {
+  if (!h || !lam || !x || !out) return FSGMG_EINVAL;
+  return guarded(h, [&]() -> fsgmg_status {
+    check_device(*h);
+    const Level& F = h->levels[h->L - 1];
+    const LevelOperator& op = h->ops[h->L - 1];
+    double s[3];
+    const int pieces[3] = {1, 2, 3};
+    for (int q = 0; q < 3; ++q) {
+      launch_csr_spmv(F.N, h->full_rp, h->full_col, h->full_piece[pieces[q]], x, h->tmp, 0.0, h->stream);
+      launch_masked_dot_partial(lam, h->dir_mask, h->tmp, F.N, h->part ? h->part : (h->part = h->zeros<double>(krylov_partials())), h->stream);
+      if (!h->small) h->small = h->zeros<double>(256);
+      if (!h->pinned) HIPCHECK(hipHostMalloc((void**)&h->pinned, 256 * sizeof(double), hipHostMallocDefault));
+      launch_reduce_partials(h->part, 1, h->small + 200, nullptr, false, h->stream);
+      HIPCHECK(hipMemcpyAsync(h->pinned, h->small + 200, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+      HIPCHECK(hipStreamSynchronize(h->stream));
+      s[q] = h->pinned[0];
+    }
+    const double nu = h->phys.nu, E = h->phys.E;
+    const double dG = 1.0 / (2.0 * (1.0 + nu));
+    const double dI = nu >= 0.5 ? 0.0 : -(1.0 + nu) * (1.0 - 2.0 * nu) / (nu * E * E);
+    (void)op;
+    out[0] = -(dG * s[0] + dI * s[1]);
+    out[1] = -s[2];
+    return FSGMG_OK;
+  });
+}
+
+fsgmg_status update_params(fsgmg_h h, double E, double mu) {
+  if (!h) return FSGMG_EINVAL;
+  return guarded(h, [&]() -> fsgmg_status {
+    if (!(E > 0) || !(mu > 0)) throw Fail{FSGMG_EINVAL, "parameters must be positive"};
+    h->phys.E = E;
+    h->phys.mu = mu;
+    double G, invlam;
+    lame(E, h->phys.nu, G, invlam);
+    for (int l = 0; l < h->L; ++l) {
+      LevelOperator& op = h->ops[l];
+      op.G = G;
+      op.invlam = invlam;
+      op.mu = mu;
+      for (size_t k = 0; k < op.A.val.size(); ++k)
+        op.A.val[k] = op.piece[0][k] + G * op.piece[1][k] + invlam * op.piece[2][k] + mu * op.piece[3][k];
+    }
+    h->factors_valid = false;
+    if (h->host_only()) return FSGMG_OK;
+    for (int l = 0; l < h->L; ++l) {
+      DLevel& d = h->dl[l];
+      launch_recombine(d.nnz, d.piece[0], d.piece[1], d.piece[2], d.piece[3], G, invlam, mu, d.val,
+                       nullptr, h->stream);
+      launch_scatter(d.nnz, d.val, d.A.map, d.A.vals64, d.A.vals32, h->stream);
+      if (d.AT.ready) launch_scatter(d.nnz, d.val, d.AT.map, d.AT.vals64, d.AT.vals32, h->stream);
+    }
+    const int64_t NF = h->dl[h->L - 1].N;
+    launch_recombine(NF, h->lift_piece[0], h->lift_piece[1], h->lift_piece[2], h->lift_piece[3], G,
+                     invlam, mu, h->lift, nullptr, h->stream);
+    HIPCHECK(hipGetLastError());
+    build_coarse_inverse(*h);
+    return FSGMG_OK;
+  });
+}
+
+fsgmg_status level_info(fsgmg_h h, int level, int64_t out[9]) {
+  if (!h || !out) return FSGMG_EINVAL;
+  if (level < 0 || level >= h->L) return FSGMG_EINVAL;
+  const Level& lv = h->levels[level];
+  out[0] = lv.N;
+  out[1] = lv.N2;
+  out[2] = lv.Nps;
+  out[3] = lv.Npf;
+  out[4] = lv.off_ps;
+  out[5] = lv.off_u;
+  out[6] = lv.off_pf;
+  out[7] = h->ops[level].A.nnz();
+  out[8] = lv.D;
+  return FSGMG_OK;
+}
+
+fsgmg_status export_csr(fsgmg_h h, int level, int which, int64_t dims[3], int64_t* rowptr,
+                        int32_t* col, double* val) {
+  if (!h || !dims) return FSGMG_EINVAL;
+  return guarded(h, [&]() -> fsgmg_status {
+    if (level < 0 || level >= h->L) throw Fail{FSGMG_EINVAL, "level out of range"};
+    CsrHost tmp;
+    const CsrHost* M = nullptr;
+    if (which == 0) {
+      M = &h->ops[level].A;
+    } else if (which == 1 || which == 2) {
+      if (level < 1) throw Fail{FSGMG_EINVAL, "transfers exist for level >= 1"};
+      tmp = which == 1 ? prolongation_full(h->levels[level], h->levels[level - 1], h->tr[level])
+                       : restriction_full(h->levels[level], h->levels[level - 1], h->tr[level]);
+      M = &tmp;
+    } else if (which == 3) {
+      if (level != h->L - 1) throw Fail{FSGMG_EINVAL, "load operator exists on the finest level"};
+      M = &h->ops[level].load;
+    } else {
+      throw Fail{FSGMG_EINVAL, "unknown matrix"};
+    }
+    dims[0] = M->nrows;
+    dims[1] = M->ncols;
+    dims[2] = M->nnz();
+    if (rowptr) std::memcpy(rowptr, M->rowptr.data(), M->rowptr.size() * sizeof(int64_t));
+    if (col) std::memcpy(col, M->col.data(), M->col.size() * sizeof(int32_t));
+    if (val) std::memcpy(val, M->val.data(), M->val.size() * sizeof(double));
+    return FSGMG_OK;
+  });
+}
+
+fsgmg_status export_vector(fsgmg_h h, int level, int which, double* out) {
+  if (!h || !out) return FSGMG_EINVAL;
+  return guarded(h, [&]() -> fsgmg_status {
+    if (level < 0 || level >= h->L) throw Fail{FSGMG_EINVAL, "level out of range"};
+    const Level& lv = h->levels[level];
+    if (which == 0) {
+      if (level != h->L - 1) throw Fail{FSGMG_EINVAL, "lift exists on the finest level"};
+      const LevelOperator& op = h->ops[level];
+      for (int64_t i = 0; i < lv.N; ++i)
+        out[i] = op.lift_piece[0][i] + op.G * op.lift_piece[1][i] + op.invlam * op.lift_piece[2][i] +
+                 op.mu * op.lift_piece[3][i];
+    } else if (which == 1) {
+      for (int64_t i = 0; i < lv.N; ++i) out[i] = lv.dir[i] ? 1.0 : 0.0;
+    } else {
+      throw Fail{FSGMG_EINVAL, "unknown vector"};
+    }
+    return FSGMG_OK;
+  });
+}
+
+fsgmg_status export_blocks(fsgmg_h h, int level, int64_t sizes[2], int64_t* ptr, int32_t* dofs,
+                           int32_t* owner) {
+  if (!h || !sizes) return FSGMG_EINVAL;
+  return guarded(h, [&]() -> fsgmg_status {
+    if (!h->have_blocks) throw Fail{FSGMG_ESTATE, "blocks not built"};
+    if (level < 1 || level >= h->L) throw Fail{FSGMG_EINVAL, "blocks exist on levels >= 1"};
+    const BlockSet& bs = h->blocks[level];
+    sizes[0] = bs.nblk();
+    sizes[1] = (int64_t)bs.dofs.size();
+    if (ptr) std::memcpy(ptr, bs.ptr.data(), bs.ptr.size() * sizeof(int64_t));
+    if (dofs) std::memcpy(dofs, bs.dofs.data(), bs.dofs.size() * sizeof(int32_t));
+    if (owner) std::memcpy(owner, bs.owner.data(), bs.owner.size() * sizeof(int32_t));
+    return FSGMG_OK;
+  });
+}
+
+fsgmg_status kernel_timing(fsgmg_h h, int enable, int64_t counts[4], double total_ms[4]) {
+  if (!h) return FSGMG_EINVAL;
+  return guarded(h, [&]() -> fsgmg_status {
+    check_device(*h);
+    if (enable) {
+      for (auto& v : h->ev_rec) v.clear();
+      h->ev_used = 0;
+      h->timing = true;
+      return FSGMG_OK;
+    }
+    h->timing = false;
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    for (int k = 0; k < 4; ++k) {
+      double tot = 0.0;
+      for (auto& p : h->ev_rec[k]) {
+        float ms = 0.f;
+        HIPCHECK(hipEventElapsedTime(&ms, p.first, p.second));
+        tot += ms;
+      }
+      if (counts) counts[k] = (int64_t)h->ev_rec[k].size();
+      if (total_ms) total_ms[k] = tot;
+      h->ev_rec[k].clear();
+    }
+    h->ev_used = 0;
+    return FSGMG_OK;
+  });
+}
+
+const char* last_error(fsgmg_h h) { return h ? h->err.c_str() : "null handle"; }
+
+void hierarchy_destroy(fsgmg_h h) { delete h; }
+
+}  // extern "C"

@@ -1,0 +1,369 @@
+"""Thin ctypes binding of libfsgmg.so (argument marshalling only).
+
+Module-level functions carry the C-ABI names (setup_hierarchy,
+build_fs_as_blocks, vcycle_apply, gmres_solve, adjoint_solve, assemble_load,
+apply_operator, param_grad, update_params, ...); ``Hierarchy`` wraps a handle.
+Device vectors are torch CUDA (HIP) tensors of dtype float64; every compute
+step runs inside the library.  The library is loaded from this directory and
+the import fails loudly when it has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfsgmg.so")
+
+FSGMG_OK, FSGMG_NOT_CONVERGED = 0, 1
+STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "EHIP", -3: "ESINGULAR",
+          -4: "ENOMEM", -5: "ESTATE"}
+PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
+
+EXPORTED = ["setup_hierarchy", "build_fs_as_blocks", "vcycle_apply", "gmres_solve",
+            "adjoint_solve", "assemble_load", "apply_operator", "param_grad",
+            "update_params", "level_info", "export_csr", "export_vector", "export_blocks",
+            "kernel_timing", "last_error", "hierarchy_destroy"]
+
+
+class MeshDesc(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n_levels", C.c_int), ("nc", C.c_int * 3),
+                ("breaks", C.POINTER(C.c_double) * 3), ("region", C.POINTER(C.c_int8)),
+                ("mapping", C.c_int), ("map_params", C.c_double * 8),
+                ("bc_d", (C.c_int8 * 2) * 6), ("bc_u", (C.c_int8 * 2) * 6),
+                ("inflow_peak", C.c_double)]
+
+
+class Physics(C.Structure):
+    _fields_ = [("E", C.c_double), ("nu", C.c_double), ("mu", C.c_double),
+                ("rho", C.c_double), ("dt", C.c_double), ("supg", C.c_int),
+                ("ale_k", C.c_int), ("k_mass", C.c_int), ("w", C.POINTER(C.c_double))]
+
+
+class SmootherOpts(C.Structure):
+    _fields_ = [("core", C.c_int * 3), ("halo", C.c_int), ("nu_pre", C.c_int),
+                ("nu_post", C.c_int), ("omega", C.c_double), ("prec", C.c_int),
+                ("use_graph", C.c_int)]
+
+
+class KrylovOpts(C.Structure):
+    _fields_ = [("restart", C.c_int), ("max_restarts", C.c_int), ("rtol", C.c_double)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iters", C.c_int), ("restarts", C.c_int), ("converged", C.c_int),
+                ("rel_res_true", C.c_double), ("history", C.POINTER(C.c_double)),
+                ("history_cap", C.c_int), ("history_len", C.c_int),
+                ("t_solve_ms", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libfsgmg.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libfsgmg.so is not built: run "
+                               "`python -m paper_1909_13201_amd.build` first")
+        L = C.CDLL(LIB_PATH)
+        H = C.c_void_p
+        P = C.c_void_p
+        sig = {
+            "setup_hierarchy": ([C.POINTER(MeshDesc), C.POINTER(Physics), C.c_int, P,
+                                 C.POINTER(H)], C.c_int),
+            "build_fs_as_blocks": ([H, C.POINTER(SmootherOpts)], C.c_int),
+            "vcycle_apply": ([H, P, P, C.c_int], C.c_int),
+            "gmres_solve": ([H, P, P, C.POINTER(KrylovOpts), C.POINTER(SolveInfo)], C.c_int),
+            "adjoint_solve": ([H, P, P, C.POINTER(KrylovOpts), C.POINTER(SolveInfo)], C.c_int),
+            "assemble_load": ([H, P, P], C.c_int),
+            "apply_operator": ([H, C.c_int, P, P, C.c_int], C.c_int),
+            "param_grad": ([H, P, P, C.POINTER(C.c_double)], C.c_int),
+            "update_params": ([H, C.c_double, C.c_double], C.c_int),
+            "level_info": ([H, C.c_int, C.POINTER(C.c_int64)], C.c_int),
+            "export_csr": ([H, C.c_int, C.c_int, C.POINTER(C.c_int64), P, P, P], C.c_int),
+            "export_vector": ([H, C.c_int, C.c_int, P], C.c_int),
+            "export_blocks": ([H, C.c_int, C.POINTER(C.c_int64), P, P, P], C.c_int),
+            "kernel_timing": ([H, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double)],
+                              C.c_int),
+            "last_error": ([H], C.c_char_p),
+            "hierarchy_destroy": ([H], None),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+class FsgmgError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+def _ptr(t):
+    """Device pointer of a contiguous torch tensor (or None)."""
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _mesh_desc(cfg, keep):
+    m = MeshDesc()
+    m.dim = int(cfg["dim"])
+    m.n_levels = int(cfg["n_levels"])
+    for a in range(3):
+        m.nc[a] = int(cfg["nc"][a]) if a < m.dim else 1
+    for a in range(m.dim):
+        arr = np.ascontiguousarray(np.asarray(cfg["breaks"][a], dtype=np.float64))
+        keep.append(arr)
+        m.breaks[a] = arr.ctypes.data_as(C.POINTER(C.c_double))
+    reg = np.ascontiguousarray(np.asarray(cfg["region"], dtype=np.int8))
+    keep.append(reg)
+    m.region = reg.ctypes.data_as(C.POINTER(C.c_int8))
+    m.mapping = int(cfg["mapping"])
+    for i, v in enumerate(cfg.get("map_params", [])):
+        m.map_params[i] = float(v)
+    for f in range(6):
+        for r in range(2):
+            m.bc_d[f][r] = int(cfg["bc_d"][f][r])
+            m.bc_u[f][r] = int(cfg["bc_u"][f][r])
+    m.inflow_peak = float(cfg["inflow_peak"])
+    return m
+
+
+def _physics(cfg, w, keep):
+    p = Physics()
+    p.E, p.nu, p.mu, p.rho = float(cfg["E"]), float(cfg["nu"]), float(cfg["mu"]), float(cfg["rho"])
+    p.dt = float(cfg.get("dt", float("inf")))
+    p.supg = int(bool(cfg.get("supg", False)))
+    p.ale_k = int(cfg.get("ale_k", 0))
+    p.k_mass = int(cfg.get("k_mass", 0))
+    if w is not None:
+        arr = np.ascontiguousarray(np.asarray(w, dtype=np.float64))
+        keep.append(arr)
+        p.w = arr.ctypes.data_as(C.POINTER(C.c_double))
+    return p
+
+
+def _check(h, st, allow_not_converged=False):
+    if st == FSGMG_OK or (allow_not_converged and st == FSGMG_NOT_CONVERGED):
+        return st
+    msg = lib().last_error(h).decode() if h else ""
+    raise FsgmgError(st, msg)
+
+
+# ----------------------------------------------------------------------------
+# C-ABI named wrappers
+# ----------------------------------------------------------------------------
+
+def setup_hierarchy(cfg, w=None, device=0, stream=None):
+    keep = []
+    m = _mesh_desc(cfg, keep)
+    p = _physics(cfg, w, keep)
+    h = C.c_void_p()
+    s = C.c_void_p(stream) if stream is not None else None
+    st = lib().setup_hierarchy(C.byref(m), C.byref(p), int(device), s, C.byref(h))
+    if st != FSGMG_OK:
+        msg = lib().last_error(h).decode() if h else ""
+        if h:
+            lib().hierarchy_destroy(h)
+        raise FsgmgError(st, msg)
+    return h
+
+
+def build_fs_as_blocks(h, core=(4, 4), halo=1, nu_pre=2, nu_post=2, omega=1.0, prec="fp64",
+                       use_graph=False):
+    o = SmootherOpts()
+    for a in range(3):
+        o.core[a] = int(core[a]) if a < len(core) else 1
+    o.halo, o.nu_pre, o.nu_post = int(halo), int(nu_pre), int(nu_post)
+    o.omega = float(omega)
+    o.prec = PREC[prec] if isinstance(prec, str) else int(prec)
+    o.use_graph = int(bool(use_graph))
+    _check(h, lib().build_fs_as_blocks(h, C.byref(o)))
+
+
+def vcycle_apply(h, r, z, transpose=False):
+    _check(h, lib().vcycle_apply(h, _ptr(r), _ptr(z), int(bool(transpose))))
+
+
+def _solve(fn, h, b, x, restart, max_restarts, rtol, history_cap):
+    o = KrylovOpts(int(restart), int(max_restarts), float(rtol))
+    info = SolveInfo()
+    hist = np.zeros(max(1, history_cap))
+    info.history = hist.ctypes.data_as(C.POINTER(C.c_double))
+    info.history_cap = int(history_cap)
+    st = fn(h, _ptr(b), _ptr(x), C.byref(o), C.byref(info))
+    _check(h, st, allow_not_converged=True)
+    n = min(info.history_len, history_cap)
+    return dict(converged=bool(info.converged), iters=info.iters, restarts=info.restarts,
+                rel_res_true=info.rel_res_true, history=hist[:n].copy(),
+                t_solve_ms=info.t_solve_ms, status=STATUS[st])
+
+
+def gmres_solve(h, b, x, restart=30, max_restarts=20, rtol=1e-10, history_cap=1024):
+    return _solve(lib().gmres_solve, h, b, x, restart, max_restarts, rtol, history_cap)
+
+
+def adjoint_solve(h, c, lam, restart=30, max_restarts=20, rtol=1e-10, history_cap=1024):
+    return _solve(lib().adjoint_solve, h, c, lam, restart, max_restarts, rtol, history_cap)
+
+
+def assemble_load(h, f, b):
+    _check(h, lib().assemble_load(h, _ptr(f), _ptr(b)))
+
+
+def apply_operator(h, level, x, y, transpose=False):
+    _check(h, lib().apply_operator(h, int(level), _ptr(x), _ptr(y), int(bool(transpose))))
+
+
+def param_grad(h, lam, x):
+    out = (C.c_double * 2)()
+    _check(h, lib().param_grad(h, _ptr(lam), _ptr(x), out))
+    return float(out[0]), float(out[1])
+
+
+def update_params(h, E, mu):
+    _check(h, lib().update_params(h, float(E), float(mu)))
+
+
+def level_info(h, level):
+    out = (C.c_int64 * 9)()
+    _check(h, lib().level_info(h, int(level), out))
+    keys = ["N", "N2", "Nps", "Npf", "off_ps", "off_u", "off_pf", "nnz", "dim"]
+    return {k: int(v) for k, v in zip(keys, out)}
+
+
+def export_csr(h, level, which):
+    """Host copy of a setup matrix as (rowptr, col, val, shape)."""
+    dims = (C.c_int64 * 3)()
+    _check(h, lib().export_csr(h, int(level), int(which), dims, None, None, None))
+    nr, nc, nnz = int(dims[0]), int(dims[1]), int(dims[2])
+    rp = np.zeros(nr + 1, np.int64)
+    col = np.zeros(max(nnz, 1), np.int32)
+    val = np.zeros(max(nnz, 1), np.float64)
+    _check(h, lib().export_csr(h, int(level), int(which), dims, rp.ctypes.data_as(C.c_void_p),
+                               col.ctypes.data_as(C.c_void_p), val.ctypes.data_as(C.c_void_p)))
+    return rp, col[:nnz], val[:nnz], (nr, nc)
+
+
+def export_vector(h, level, which):
+    n = level_info(h, level)["N"]
+    out = np.zeros(n)
+    _check(h, lib().export_vector(h, int(level), int(which), out.ctypes.data_as(C.c_void_p)))
+    return out
+
+
+def export_blocks(h, level):
+    sizes = (C.c_int64 * 2)()
+    _check(h, lib().export_blocks(h, int(level), sizes, None, None, None))
+    nb, tot = int(sizes[0]), int(sizes[1])
+    N = level_info(h, level)["N"]
+    ptr = np.zeros(nb + 1, np.int64)
+    dofs = np.zeros(max(tot, 1), np.int32)
+    owner = np.zeros(N, np.int32)
+    _check(h, lib().export_blocks(h, int(level), sizes, ptr.ctypes.data_as(C.c_void_p),
+                                  dofs.ctypes.data_as(C.c_void_p),
+                                  owner.ctypes.data_as(C.c_void_p)))
+    return ptr, dofs[:tot], owner
+
+
+def kernel_timing(h, enable):
+    """Start (enable=True) or stop event timing; on stop returns
+    {kind: (launches, total_ms)} for kinds smoother / vspmv / outer_spmv / transfer."""
+    counts = (C.c_int64 * 4)()
+    tot = (C.c_double * 4)()
+    _check(h, lib().kernel_timing(h, int(bool(enable)), counts, tot))
+    if enable:
+        return None
+    names = ["smoother", "vspmv", "outer_spmv", "transfer"]
+    return {n: (int(counts[i]), float(tot[i])) for i, n in enumerate(names)}
+
+
+def hierarchy_destroy(h):
+    if h:
+        lib().hierarchy_destroy(h)
+
+
+# ----------------------------------------------------------------------------
+class Hierarchy:
+    """Owning wrapper of a handle.  device=-1 builds a host-only handle (setup
+    data can be inspected, no device call is valid)."""
+
+    def __init__(self, cfg, w=None, device=0, stream=None):
+        self.cfg = dict(cfg)
+        self.device = device
+        if device >= 0 and stream is None:
+            import torch
+            stream = torch.cuda.current_stream(device).cuda_stream
+        self.h = setup_hierarchy(cfg, w, device, stream)
+        self.L = int(cfg["n_levels"])
+        self.info = [level_info(self.h, l) for l in range(self.L)]
+        self.N = self.info[-1]["N"]
+
+    def close(self):
+        if self.h:
+            hierarchy_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def build_fs_as_blocks(self, **kw):
+        opts = dict(core=self.cfg.get("core", (4, 4)), halo=self.cfg.get("halo", 1),
+                    nu_pre=self.cfg.get("nu_pre", 2), nu_post=self.cfg.get("nu_post", 2),
+                    omega=self.cfg.get("omega", 1.0))
+        opts.update(kw)
+        build_fs_as_blocks(self.h, **opts)
+
+    def csr(self, level, which=0):
+        import scipy.sparse as sp
+        rp, col, val, shape = export_csr(self.h, level, which)
+        return sp.csr_matrix((val, col, rp), shape=shape)
+
+    def _vec(self, t, n=None):
+        import torch
+        n = self.N if n is None else n
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
+            raise TypeError("expected a float64 device tensor")
+        if t.numel() != n or not t.is_contiguous():
+            raise ValueError("expected a contiguous tensor of %d entries, got %d" % (n, t.numel()))
+        return t
+
+    def vcycle_apply(self, r, z, transpose=False):
+        vcycle_apply(self.h, self._vec(r), self._vec(z), transpose)
+
+    def gmres_solve(self, b, x, **kw):
+        return gmres_solve(self.h, self._vec(b), self._vec(x), **kw)
+
+    def adjoint_solve(self, c, lam, **kw):
+        return adjoint_solve(self.h, self._vec(c), self._vec(lam), **kw)
+
+    def assemble_load(self, f, b):
+        n2d = self.info[-1]["N2"] * self.info[-1]["dim"]
+        assemble_load(self.h, self._vec(f, n2d), self._vec(b))
+
+    def apply_operator(self, level, x, y, transpose=False):
+        n = self.info[level]["N"]
+        apply_operator(self.h, level, self._vec(x, n), self._vec(y, n), transpose)
+
+    def param_grad(self, lam, x):
+        return param_grad(self.h, self._vec(lam), self._vec(x))
+
+    def update_params(self, E, mu):
+        update_params(self.h, E, mu)
+        self.cfg.update(E=float(E), mu=float(mu))
+
+    def kernel_timing(self, enable):
+        return kernel_timing(self.h, enable)

@@ -1,0 +1,239 @@
+"""GPU parity tests: the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerances (derived in the design doc):
+* operator apply, transfers, load: elementwise |y - y_ref| <= 64 eps (|A| |x|)_i
+  (summation-order rounding only);
+* FP64 V-cycle: the block inverses come from Gauss-Jordan (GPU) versus LU
+  (oracle), so outputs differ by rounding amplified by block conditioning:
+  relative 2-norm error <= 1e-9;
+* FP32 / BF16 smoother V-cycles: relative error to the FP64 oracle cycle
+  <= 2e-4 / 2e-2 (unit roundoff 6e-8 / 4e-3 times the same amplification);
+* solves: true relative residual <= 1e-10 (checked here with the oracle's
+  matrix on the CPU) and solution within 1e-8 of the oracle's direct solve.
+"""
+import sys
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle import adjoint as oadj
+from oracle import fem
+from oracle.multigrid import Hierarchy as OracleHierarchy
+from paper_1909_13201_amd import fsgmg, inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+EPS = np.finfo(np.float64).eps
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(x):
+    return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+CASES = {"c1": ("c1", 2), "c2L3": ("c2", 3), "c5L2": ("c5", 2)}
+
+
+class Pair:
+    def __init__(self, key, prec="fp64"):
+        name, L = CASES[key]
+        self.key = key
+        self.cfg = inputs.with_levels(inputs.config(name), L)
+        self.w = inputs.advecting_field(self.cfg)
+        say("[setup]", key, "L", L)
+        self.H = fsgmg.Hierarchy(self.cfg, self.w, device=0)
+        self.O = OracleHierarchy(self.cfg, self.w)
+        self.prec = None
+        self.build(prec)
+
+    def build(self, prec):
+        if prec != self.prec:
+            say("[blocks]", self.key, prec)
+            self.H.build_fs_as_blocks(prec=prec)
+            self.prec = prec
+
+
+_pairs = {}
+
+
+def pair(key, prec="fp64"):
+    if key not in _pairs:
+        _pairs[key] = Pair(key, prec)
+    p = _pairs[key]
+    p.build(prec)
+    return p
+
+
+@pytest.mark.parametrize("key", ["c1", "c2L3"])
+def test_operator_apply_parity(key):
+    p = pair(key)
+    rng = np.random.default_rng(1)
+    for l in range(p.H.L):
+        A = p.O.A[l]
+        x = rng.standard_normal(A.shape[0])
+        for tr in (False, True):
+            say("[apply]", key, "level", l, "transpose", tr)
+            y = torch.zeros(A.shape[0], dtype=torch.float64, device="cuda")
+            p.H.apply_operator(l, dev(x), y, transpose=tr)
+            M = A.T if tr else A
+            ref = M @ x
+            bound = 64 * EPS * (abs(M) @ abs(x)) + 1e-300
+            assert np.all(abs(host(y) - ref) <= bound)
+
+
+@pytest.mark.parametrize("key", ["c1", "c2L3", "c5L2"])
+def test_load_parity(key):
+    p = pair(key)
+    f = inputs.body_force(p.cfg)
+    say("[load]", key)
+    b = torch.zeros(p.H.N, dtype=torch.float64, device="cuda")
+    p.H.assemble_load(dev(f.ravel()), b)
+    ref = p.O.rhs(f)
+    assert np.allclose(host(b), ref, rtol=0, atol=1e-13 * abs(ref).max())
+
+
+@pytest.mark.parametrize("key", ["c1", "c2L3"])
+@pytest.mark.parametrize("transpose", [False, True])
+def test_vcycle_fp64_parity(key, transpose):
+    p = pair(key, "fp64")
+    rng = np.random.default_rng(2)
+    r = rng.standard_normal(p.H.N)
+    say("[vcycle fp64]", key, "transpose", transpose)
+    z = torch.zeros(p.H.N, dtype=torch.float64, device="cuda")
+    p.H.vcycle_apply(dev(r), z, transpose=transpose)
+    ref = p.O.vcycle(r, transpose=transpose)
+    err = np.linalg.norm(host(z) - ref) / np.linalg.norm(ref)
+    say("   rel err %.3e" % err)
+    assert err <= 1e-9
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 2e-4), ("bf16", 2e-2)])
+def test_vcycle_mixed_precision(prec, tol):
+    p = pair("c2L3", prec)
+    rng = np.random.default_rng(3)
+    r = rng.standard_normal(p.H.N)
+    say("[vcycle]", prec)
+    z = torch.zeros(p.H.N, dtype=torch.float64, device="cuda")
+    p.H.vcycle_apply(dev(r), z)
+    ref = p.O.vcycle(r)
+    err = np.linalg.norm(host(z) - ref) / np.linalg.norm(ref)
+    say("   rel err %.3e" % err)
+    assert err <= tol
+    p.build("fp64")
+
+
+def test_vcycle_deterministic():
+    p = pair("c2L3", "fp32")
+    r = dev(np.random.default_rng(4).standard_normal(p.H.N))
+    say("[determinism]")
+    z1 = torch.zeros_like(r)
+    z2 = torch.zeros_like(r)
+    p.H.vcycle_apply(r, z1)
+    p.H.vcycle_apply(r, z2)
+    assert torch.equal(z1, z2)
+    p.build("fp64")
+
+
+@pytest.mark.parametrize("key", ["c1", "c2L3"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_gmres_solve(key, prec):
+    p = pair(key, prec)
+    f = inputs.body_force(p.cfg)
+    b = p.O.rhs(f)
+    A = p.O.A[-1]
+    say("[gmres]", key, prec)
+    x = torch.zeros(p.H.N, dtype=torch.float64, device="cuda")
+    info = p.H.gmres_solve(dev(b), x, restart=30, rtol=1e-10)
+    xs = host(x)
+    true = np.linalg.norm(b - A @ xs) / np.linalg.norm(b)
+    xd = spla.splu(A.tocsc()).solve(b)
+    err = np.linalg.norm(xs - xd) / np.linalg.norm(xd)
+    say("   iters", info["iters"], "true %.2e" % true, "lib %.2e" % info["rel_res_true"],
+        "err %.2e" % err)
+    assert info["converged"]
+    assert true <= 1e-10
+    assert abs(info["rel_res_true"] - true) <= 1e-3 * true + 1e-14
+    assert err <= 1e-8
+    hist = info["history"]
+    assert np.all(np.diff(hist) <= 1e-12)
+    if prec == "fp64":
+        from oracle.krylov import fgmres
+        _, oinfo = fgmres(lambda v: A @ v, p.O.vcycle, b, restart=30, rtol=1e-10)
+        assert abs(oinfo["iters"] - info["iters"]) <= 1
+    p.build("fp64")
+
+
+def test_adjoint_and_gradients():
+    p = pair("c5L2", "fp64")
+    lv = p.O.finest
+    A = p.O.A[-1]
+    f = inputs.body_force(p.cfg)
+    b = p.O.rhs(f)
+    c = oadj.outlet_flux_vector(lv)
+    say("[adjoint]")
+    x = torch.zeros(p.H.N, dtype=torch.float64, device="cuda")
+    info = p.H.gmres_solve(dev(b), x, rtol=1e-12, max_restarts=40)
+    lam = torch.zeros_like(x)
+    ainfo = p.H.adjoint_solve(dev(c), lam, rtol=1e-11, max_restarts=40)
+    assert info["converged"] and ainfo["converged"]
+    lam_d = spla.splu(A.T.tocsc()).solve(c)
+    err = np.linalg.norm(host(lam) - lam_d) / np.linalg.norm(lam_d)
+    say("   lambda err %.2e" % err)
+    assert err <= 1e-8
+    gE, gmu = p.H.param_grad(lam, x)
+    x_d = spla.splu(A.tocsc()).solve(b)
+    oE, omu = oadj.gradients(p.O, x_d, lam_d)
+    say("   grads", gE, gmu, "oracle", oE, omu)
+    assert gE == pytest.approx(oE, rel=1e-6)
+    assert gmu == pytest.approx(omu, rel=1e-6)
+
+
+def test_update_params_matches_reassembly():
+    p = _pairs.pop("c5L2", None) or Pair("c5L2")
+    E2, mu2 = 3.0e3, 2.0e-2
+    say("[update_params]")
+    p.H.update_params(E2, mu2)
+    taus = [q["tau"] for q in p.O.parts]
+    cfg2 = dict(p.cfg, E=E2, mu=mu2)
+    O2 = OracleHierarchy(cfg2, p.w, taus=taus, build_smoothers=False)
+    rng = np.random.default_rng(6)
+    for l in range(p.H.L):
+        x = rng.standard_normal(O2.A[l].shape[0])
+        y = torch.zeros(len(x), dtype=torch.float64, device="cuda")
+        p.H.apply_operator(l, dev(x), y)
+        ref = O2.A[l] @ x
+        assert np.all(abs(host(y) - ref) <= 64 * EPS * (abs(O2.A[l]) @ abs(x)) + 1e-300)
+    p.H.build_fs_as_blocks(prec="fp64")
+    b = O2.rhs(inputs.body_force(cfg2))
+    bl = torch.zeros(p.H.N, dtype=torch.float64, device="cuda")
+    p.H.assemble_load(dev(inputs.body_force(cfg2).ravel()), bl)
+    assert np.allclose(host(bl), b, rtol=0, atol=1e-13 * abs(b).max())
+    x = torch.zeros_like(bl)
+    info = p.H.gmres_solve(bl, x, rtol=1e-10)
+    assert info["converged"]
+    assert np.linalg.norm(b - O2.A[-1] @ host(x)) <= 1e-10 * np.linalg.norm(b)
+    p.H.close()
+
+
+def test_status_codes():
+    p = pair("c1", "fp64")
+    say("[status]")
+    b = torch.full((p.H.N,), float("nan"), dtype=torch.float64, device="cuda")
+    x = torch.zeros_like(b)
+    with pytest.raises(fsgmg.FsgmgError) as e:
+        p.H.gmres_solve(b, x)
+    assert e.value.status == -1
+    b = dev(p.O.rhs(inputs.body_force(p.cfg)))
+    info = p.H.gmres_solve(b, x, restart=2, max_restarts=0, rtol=1e-10)
+    assert info["status"] == "NOT_CONVERGED" and not info["converged"] and info["iters"] == 2
