@@ -54,6 +54,25 @@ def smoother_bytes(H, level, prec):
     return int((n * m).sum() * sW + 4 * (n.sum() + m.sum()) + 3 * N * sV), int(len(n))
 
 
+def measured_traffic():
+    """HBM bytes per launch of the finest-level smoother from the committed
+    rocprofv3 counter summary, or None when kernels.hip has changed since the
+    counters were taken."""
+    import hashlib
+    prof = os.path.join(ROOT, "profiles", "k_smooth_fwd_c2_traffic.md")
+    src = os.path.join(ROOT, "paper_1909_13201_amd", "csrc", "kernels.hip")
+    try:
+        txt = open(prof).read()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    vals = dict(l.split(":", 1) for l in txt.splitlines()
+                if l.startswith(("kernels_hip_sha256:", "traffic_bytes_per_launch:")))
+    if vals.get("kernels_hip_sha256", "").strip() != sha:
+        return None
+    return int(vals["traffic_bytes_per_launch"])
+
+
 def timed_solves(H, b, x, steps, warmup, rtol):
     import torch
     infos = []
@@ -104,6 +123,8 @@ def main():
     ap.add_argument("--levels", type=int, default=0, help="override the number of levels")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--bf16", action="store_true", help="also time BF16-stored block inverses")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run three plain 256 MiB device copies first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the solver has no multi-GPU path "
@@ -121,6 +142,13 @@ def main():
     rtol = cfg["rtol"]
     dev = torch.device("cuda:0")
 
+    if args.copy_probe:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     t0 = time.perf_counter()
     H = fsgmg.Hierarchy(cfg, w, device=0)
     torch.cuda.synchronize()
@@ -190,7 +218,8 @@ def main():
     achieved = sm_bytes / (avg_ms * 1e-3) / 1e9
     roof = dict(bound="hbm", kernel="k_smooth_fwd<float,float> (finest level)",
                 achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                frac=round(achieved / HBM_PEAK_GBS, 4),
+                traffic=measured_traffic() if cfg["name"] == "c2" and not args.levels else None,
                 bytes_per_launch=sm_bytes, blocks_per_launch=nblk,
                 avg_launch_us=round(avg_ms * 1e3, 2), launches=n_sm)
     other = {}

@@ -118,11 +118,13 @@ __global__ __launch_bounds__(kThreads) void k_csr_spmv(int64_t nrows, const int6
 // ------------------------------------------------------------------------
 constexpr uint8_t kSolid = 1, kDirD = 2, kDirU = 4;
 
-template <typename T, int D>
+// LG lanes per output row (coarse node / fine node / pressure), shuffle reduction
+template <typename T, int D, int LG>
 __global__ __launch_bounds__(kThreads) void k_transfer(TransferView<T> t, int mode,
                                                        const T* __restrict__ in,
                                                        T* __restrict__ out) {
-  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & (LG - 1);
+  const int64_t id = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LG;
   if (mode == 0 || mode == 2) {
     // coarse outputs
     if (id < t.N2c) {
@@ -132,7 +134,7 @@ __global__ __launch_bounds__(kThreads) void k_transfer(TransferView<T> t, int mo
       T bd[D], bu[D];
 #pragma unroll
       for (int c = 0; c < D; ++c) bd[c] = bu[c] = T(0);
-      for (int k = t.rn_ptr[I]; k < t.rn_ptr[I + 1]; ++k) {
+      for (int k = t.rn_ptr[I] + lane; k < t.rn_ptr[I + 1]; k += LG) {
         const int64_t i = t.rn_col[k];
         const T w = t.rn_val[k];
         const uint8_t ff = t.flags_f[i];
@@ -156,27 +158,40 @@ __global__ __launch_bounds__(kThreads) void k_transfer(TransferView<T> t, int mo
           }
         }
       }
-      const bool zd = (mode == 0) && (fc & kDirD), zu = (mode == 0) && (fc & kDirU);
 #pragma unroll
-      for (int c = 0; c < D; ++c) {
-        out[D * I + c] = zd ? T(0) : bd[c];
-        out[t.offu_c + D * I + c] = zu ? T(0) : bu[c];
+      for (int off = LG / 2; off > 0; off >>= 1)
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+          bd[c] += __shfl_xor(bd[c], off, LG);
+          bu[c] += __shfl_xor(bu[c], off, LG);
+        }
+      if (lane == 0) {
+        const bool zd = (mode == 0) && (fc & kDirD), zu = (mode == 0) && (fc & kDirU);
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+          out[D * I + c] = zd ? T(0) : bd[c];
+          out[t.offu_c + D * I + c] = zu ? T(0) : bu[c];
+        }
       }
       return;
     }
     int64_t p = id - t.N2c;
+    const int32_t* rp;
+    const int32_t* rc;
+    const T* rv;
+    int64_t off_in, off_out;
     if (p < t.Npsc) {
-      T s = T(0);
-      for (int k = t.rps_ptr[p]; k < t.rps_ptr[p + 1]; ++k) s += t.rps_val[k] * in[t.offps_f + t.rps_col[k]];
-      out[t.offps_c + p] = s;
-      return;
+      rp = t.rps_ptr; rc = t.rps_col; rv = t.rps_val; off_in = t.offps_f; off_out = t.offps_c;
+    } else {
+      p -= t.Npsc;
+      if (p >= t.Npfc) return;
+      rp = t.rpf_ptr; rc = t.rpf_col; rv = t.rpf_val; off_in = t.offpf_f; off_out = t.offpf_c;
     }
-    p -= t.Npsc;
-    if (p < t.Npfc) {
-      T s = T(0);
-      for (int k = t.rpf_ptr[p]; k < t.rpf_ptr[p + 1]; ++k) s += t.rpf_val[k] * in[t.offpf_f + t.rpf_col[k]];
-      out[t.offpf_c + p] = s;
-    }
+    T s = T(0);
+    for (int k = rp[p] + lane; k < rp[p + 1]; k += LG) s += rv[k] * in[off_in + rc[k]];
+#pragma unroll
+    for (int off = LG / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, LG);
+    if (lane == 0) out[off_out + p] = s;
     return;
   }
   // fine outputs (mode 1: x_f += D_f P x_c, mode 3: x_f += (D_c R)^T x_c)
@@ -187,7 +202,7 @@ __global__ __launch_bounds__(kThreads) void k_transfer(TransferView<T> t, int mo
     T ad[D], au[D];
 #pragma unroll
     for (int c = 0; c < D; ++c) ad[c] = au[c] = T(0);
-    for (int k = t.pn_ptr[i]; k < t.pn_ptr[i + 1]; ++k) {
+    for (int k = t.pn_ptr[i] + lane; k < t.pn_ptr[i + 1]; k += LG) {
       const int64_t I = t.pn_col[k];
       const T w = t.pn_val[k];
       if (mode == 1) {
@@ -212,27 +227,40 @@ __global__ __launch_bounds__(kThreads) void k_transfer(TransferView<T> t, int mo
         }
       }
     }
-    const bool md = (mode == 1) && (ff & kDirD), mu = (mode == 1) && (ff & kDirU);
 #pragma unroll
-    for (int c = 0; c < D; ++c) {
-      if (!md) out[D * i + c] += ad[c];
-      if (!mu) out[t.offu_f + D * i + c] += au[c];
+    for (int off = LG / 2; off > 0; off >>= 1)
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        ad[c] += __shfl_xor(ad[c], off, LG);
+        au[c] += __shfl_xor(au[c], off, LG);
+      }
+    if (lane == 0) {
+      const bool md = (mode == 1) && (ff & kDirD), mu = (mode == 1) && (ff & kDirU);
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        if (!md) out[D * i + c] += ad[c];
+        if (!mu) out[t.offu_f + D * i + c] += au[c];
+      }
     }
     return;
   }
   int64_t p = id - t.N2f;
+  const int32_t* rp;
+  const int32_t* rc;
+  const T* rv;
+  int64_t off_in, off_out;
   if (p < t.Npsf) {
-    T s = T(0);
-    for (int k = t.pps_ptr[p]; k < t.pps_ptr[p + 1]; ++k) s += t.pps_val[k] * in[t.offps_c + t.pps_col[k]];
-    out[t.offps_f + p] += s;
-    return;
+    rp = t.pps_ptr; rc = t.pps_col; rv = t.pps_val; off_in = t.offps_c; off_out = t.offps_f;
+  } else {
+    p -= t.Npsf;
+    if (p >= t.Npff) return;
+    rp = t.ppf_ptr; rc = t.ppf_col; rv = t.ppf_val; off_in = t.offpf_c; off_out = t.offpf_f;
   }
-  p -= t.Npsf;
-  if (p < t.Npff) {
-    T s = T(0);
-    for (int k = t.ppf_ptr[p]; k < t.ppf_ptr[p + 1]; ++k) s += t.ppf_val[k] * in[t.offpf_c + t.ppf_col[k]];
-    out[t.offpf_f + p] += s;
-  }
+  T s = T(0);
+  for (int k = rp[p] + lane; k < rp[p + 1]; k += LG) s += rv[k] * in[off_in + rc[k]];
+#pragma unroll
+  for (int off = LG / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, LG);
+  if (lane == 0) out[off_out + p] += s;
 }
 
 // ------------------------------------------------------------------------
@@ -283,8 +311,10 @@ struct WTraits<__hip_bfloat16> {
 };
 
 // Forward sweep: x[own] = (first ? 0 : x[own]) + omega * (W_j r[I_j])[own].
+constexpr int kSmoothMaxThreads = 1024;
+
 template <typename TV, typename TW>
-__global__ __launch_bounds__(kThreads) void k_smooth_fwd(BlocksView B, const TW* __restrict__ W,
+__global__ __launch_bounds__(kSmoothMaxThreads) void k_smooth_fwd(BlocksView B, const TW* __restrict__ W,
                                                          const TV* __restrict__ r,
                                                          TV* __restrict__ x, TV omega, int first) {
   using TA = TV;
@@ -320,7 +350,24 @@ __global__ __launch_bounds__(kThreads) void k_smooth_fwd(BlocksView B, const TW*
 #pragma unroll
     for (int i = 0; i < RV; ++i) acc[i] = TA(0);
     const TW* p = Wj + (int64_t)g * RV;
-    for (int k = s; k < n; k += S) {
+    int k = s;
+    // four columns per step: four independent 16-byte loads in flight per lane
+    for (; k + 3 * S < n; k += 4 * S) {
+      TA w0[RV], w1[RV], w2[RV], w3[RV];
+      WTraits<TW>::load(p + (int64_t)k * mp, w0);
+      WTraits<TW>::load(p + (int64_t)(k + S) * mp, w1);
+      WTraits<TW>::load(p + (int64_t)(k + 2 * S) * mp, w2);
+      WTraits<TW>::load(p + (int64_t)(k + 3 * S) * mp, w3);
+      const TA r0 = rl[k], r1 = rl[k + S], r2 = rl[k + 2 * S], r3 = rl[k + 3 * S];
+#pragma unroll
+      for (int i = 0; i < RV; ++i) {
+        acc[i] += w0[i] * r0;
+        acc[i] += w1[i] * r1;
+        acc[i] += w2[i] * r2;
+        acc[i] += w3[i] * r3;
+      }
+    }
+    for (; k < n; k += S) {
       TA w[RV];
       WTraits<TW>::load(p + (int64_t)k * mp, w);
       const TA rk = rl[k];
@@ -690,23 +737,18 @@ __global__ __launch_bounds__(kThreads) void k_reduce_partials(const double* __re
                                                               int k, double* __restrict__ out,
                                                               const double* __restrict__ add_to,
                                                               int sqrt_last) {
-  __shared__ double sh[kThreads];
-  for (int i = 0; i < k; ++i) {
+  // one wavefront per vector; lanes take partials g = lane, lane + 64, ... in
+  // a fixed order, then a fixed butterfly: the result is run-to-run identical
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int i = wv; i < k; i += kThreads / 64) {
     double s = 0.0;
-    for (int g = threadIdx.x; g < kPartials; g += blockDim.x) s += part[(int64_t)g * kMaxK + i];
-    sh[threadIdx.x] = s;
-    __syncthreads();
-    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
-      if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
-      __syncthreads();
+    for (int g = lane; g < kPartials; g += 64) s += part[(int64_t)g * kMaxK + i];
+    s = wave_sum(s);
+    if (lane == 0) {
+      if (sqrt_last && i == k - 1) s = sqrt(s);
+      if (add_to) s += add_to[i];
+      out[i] = s;
     }
-    if (threadIdx.x == 0) {
-      double v = sh[0];
-      if (sqrt_last && i == k - 1) v = sqrt(v);
-      if (add_to) v += add_to[i];
-      out[i] = v;
-    }
-    __syncthreads();
   }
 }
 
@@ -779,6 +821,102 @@ __global__ __launch_bounds__(kThreads) void k_recombine(int64_t n, const double*
   if (o32) o32[r] = (float)v;
 }
 
+// Multi-workgroup Gauss-Jordan step for one large matrix (the coarse level).
+// Step k, part 1 (one workgroup): pivot search in column k over rows >= k,
+// row interchange, scaled pivot row and a copy of column k.
+constexpr int kGJThreads = 1024;
+__global__ __launch_bounds__(kGJThreads) void k_gj_pivot(double* __restrict__ a, int64_t n, int64_t k,
+                                                          double* __restrict__ colk,
+                                                          double* __restrict__ rowk,
+                                                          int32_t* __restrict__ piv,
+                                                          int32_t* __restrict__ status) {
+  __shared__ double rv[kGJThreads];
+  __shared__ int64_t ri[kGJThreads];
+  const int tid = threadIdx.x;
+  if (status[0]) return;
+  double best = -1.0;
+  int64_t bi = n;
+  for (int64_t i = k + tid; i < n; i += blockDim.x) {
+    const double v = fabs(a[i * n + k]);
+    if (v > best) {
+      best = v;
+      bi = i;
+    }
+  }
+  rv[tid] = best;
+  ri[tid] = bi;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (tid < s) {
+      const double v2 = rv[tid + s];
+      const int64_t i2 = ri[tid + s];
+      if (v2 > rv[tid] || (v2 == rv[tid] && i2 < ri[tid])) {
+        rv[tid] = v2;
+        ri[tid] = i2;
+      }
+    }
+    __syncthreads();
+  }
+  const int64_t p = ri[0];
+  if (!(rv[0] > 0.0)) {
+    if (tid == 0) status[0] = 1;
+    return;
+  }
+  if (tid == 0) piv[k] = (int32_t)p;
+  if (p != k)
+    for (int64_t c = tid; c < n; c += blockDim.x) {
+      const double t0 = a[k * n + c];
+      a[k * n + c] = a[p * n + c];
+      a[p * n + c] = t0;
+    }
+  __syncthreads();
+  const double d = 1.0 / a[k * n + k];
+  for (int64_t i = tid; i < n; i += blockDim.x) {
+    colk[i] = a[i * n + k];
+    rowk[i] = (i == k) ? d : a[k * n + i] * d;
+  }
+}
+
+// Step k, part 2 (whole grid): rank-1 elimination of every row but k.
+__global__ __launch_bounds__(kThreads) void k_gj_update(double* __restrict__ a, int64_t n, int64_t k,
+                                                        const double* __restrict__ colk,
+                                                        const double* __restrict__ rowk,
+                                                        const int32_t* __restrict__ status) {
+  if (status[0]) return;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * n) return;
+  const int64_t i = e / n, c = e - i * n;
+  if (i == k)
+    a[e] = rowk[c];
+  else
+    a[e] = ((c == k) ? 0.0 : a[e]) - colk[i] * rowk[c];
+}
+
+// Undo the row interchanges as column interchanges (reverse order).
+__global__ __launch_bounds__(kGJThreads) void k_gj_colswap(double* __restrict__ a, int64_t n,
+                                                            const int32_t* __restrict__ piv,
+                                                            const int32_t* __restrict__ status) {
+  if (status[0]) return;
+  for (int64_t k = n - 1; k >= 0; --k) {
+    const int64_t p = piv[k];
+    if (p != k)
+      for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const double t0 = a[i * n + k];
+        a[i * n + k] = a[i * n + p];
+        a[i * n + p] = t0;
+      }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_transpose(const double* __restrict__ a,
+                                                        double* __restrict__ at, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * n) return;
+  const int64_t i = e / n, c = e - i * n;
+  at[c * n + i] = a[e];
+}
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_fill(T* __restrict__ p, T v, int64_t n) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -827,13 +965,14 @@ void launch_csr_spmv(int64_t nrows, const int64_t* rowptr, const int32_t* col, c
 template <typename T>
 void launch_transfer(const TransferView<T>& t, int D, int mode, const T* in, T* out,
                      hipStream_t s) {
+  constexpr int LG = 8;
   const int64_t n = (mode == 0 || mode == 2) ? t.N2c + t.Npsc + t.Npfc : t.N2f + t.Npsf + t.Npff;
-  const unsigned g = grid_for(n, kThreads);
+  const unsigned g = grid_for(n * LG, kThreads);
   if (!g) return;
   if (D == 2)
-    hipLaunchKernelGGL((k_transfer<T, 2>), dim3(g), dim3(kThreads), 0, s, t, mode, in, out);
+    hipLaunchKernelGGL((k_transfer<T, 2, LG>), dim3(g), dim3(kThreads), 0, s, t, mode, in, out);
   else
-    hipLaunchKernelGGL((k_transfer<T, 3>), dim3(g), dim3(kThreads), 0, s, t, mode, in, out);
+    hipLaunchKernelGGL((k_transfer<T, 3, LG>), dim3(g), dim3(kThreads), 0, s, t, mode, in, out);
 }
 template void launch_transfer<double>(const TransferView<double>&, int, int, const double*,
                                       double*, hipStream_t);
@@ -844,13 +983,15 @@ template <typename TV, typename TW>
 static void smooth_impl(const BlocksView& B, const TW* W, const TV* r, TV* x, TV* tbuf,
                         double omega, bool first, bool transpose, int64_t N, hipStream_t s) {
   if (!transpose) {
-    const int64_t nj = (B.njac + kThreads - 1) / kThreads;
+    // few blocks (coarse levels): wider workgroups shorten each lane's column loop
+    const int T = B.nblk < 1024 ? kSmoothMaxThreads : kThreads;
+    const int64_t nj = (B.njac + T - 1) / T;
     const unsigned g = (unsigned)(B.nblk + nj);
     if (!g) return;
     const int RV = WTraits<TW>::RV;
-    const size_t sm = sizeof(TV) * (size_t)(((B.max_n + 3) & ~3) + kThreads * RV + B.max_mpad);
-    hipLaunchKernelGGL((k_smooth_fwd<TV, TW>), dim3(g), dim3(kThreads), sm, s, B, W, r, x,
-                       (TV)omega, (int)first);
+    const size_t sm = sizeof(TV) * (size_t)(((B.max_n + 3) & ~3) + T * RV + B.max_mpad);
+    hipLaunchKernelGGL((k_smooth_fwd<TV, TW>), dim3(g), dim3(T), sm, s, B, W, r, x, (TV)omega,
+                       (int)first);
     return;
   }
   if (B.nblk) {
@@ -990,6 +1131,17 @@ void launch_load_rhs(int64_t n, const int64_t* rowptr, const int32_t* col, const
 void launch_masked_dot_partial(const double* a, const uint8_t* mask, const double* b, int64_t n,
                                double* part, hipStream_t s) {
   hipLaunchKernelGGL(k_masked_dot, dim3(kPartials), dim3(kThreads), 0, s, a, mask, b, n, part);
+}
+
+void launch_invert_dense(int64_t n, double* a, double* at, double* colk, double* rowk,
+                         int32_t* piv, int32_t* status, hipStream_t s) {
+  const unsigned gu = grid_for(n * n, kThreads);
+  for (int64_t k = 0; k < n; ++k) {
+    hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(kGJThreads), 0, s, a, n, k, colk, rowk, piv, status);
+    hipLaunchKernelGGL(k_gj_update, dim3(gu), dim3(kThreads), 0, s, a, n, k, colk, rowk, status);
+  }
+  hipLaunchKernelGGL(k_gj_colswap, dim3(1), dim3(kGJThreads), 0, s, a, n, piv, status);
+  hipLaunchKernelGGL(k_transpose, dim3(gu), dim3(kThreads), 0, s, a, at, n);
 }
 
 template <typename T>

@@ -113,6 +113,13 @@ void launch_invert_blocks(int64_t j0, int64_t nb, const int64_t* dof_ptr, const 
 void launch_extract_owned(int64_t j0, int64_t nb, const BlocksView& B, const int64_t* dense_off,
                           const double* dense, WPrec wp, void* W, hipStream_t s);
 
+// In-place inversion of one dense n x n FP64 matrix by Gauss-Jordan with
+// partial pivoting spread over the whole GPU (one pivot kernel and one
+// rank-1 update kernel per column); at receives the transpose of the
+// inverse; status[0] = 1 on a zero pivot (must be zero on entry).
+void launch_invert_dense(int64_t n, double* a, double* at, double* colk, double* rowk,
+                         int32_t* piv, int32_t* status, hipStream_t s);
+
 // ---- coarse solve: y = Ainv * x (transpose: Ainv^T x), FP64 matrix ----
 template <typename TV>
 void launch_dense_gemv(int64_t n, const double* Ainv, bool transpose, const TV* x, TV* y,

@@ -192,6 +192,9 @@ struct fsgmg_hierarchy {
   std::vector<void*> allocs;
   std::vector<DLevel> dl;
   double* coarse_inv = nullptr;
+  double* coarse_invT = nullptr;
+  double* coarse_work = nullptr;
+  int32_t* coarse_piv = nullptr;
   int64_t n0 = 0;
   // finest-level extras
   int64_t* load_rp = nullptr;
@@ -395,26 +398,28 @@ void upload_transfer(fsgmg_hierarchy& h, int l) {
   u.rpf_val = h.upload(conv<float>(t.Rpf.val));
 }
 
-// dense FP64 copy of a (small) CSR matrix, inverted on the device
+// dense FP64 copy of the coarse-level matrix, inverted on the device; the
+// transpose of the inverse is kept for the transposed V-cycle
 void build_coarse_inverse(fsgmg_hierarchy& h) {
   const CsrHost& A = h.ops[0].A;
   const int64_t n = A.nrows;
-  if (n > 2800) throw Fail{FSGMG_EINVAL, "coarse level too large for the dense inverse (n > 2800)"};
+  if (n > 20000) throw Fail{FSGMG_EINVAL, "coarse level too large for the dense inverse (n > 20000)"};
   std::vector<double> dense((size_t)(n * n), 0.0);
   for (int64_t i = 0; i < n; ++i)
     for (int64_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k) dense[i * n + A.col[k]] = A.val[k];
-  if (!h.coarse_inv) h.coarse_inv = (double*)h.dalloc((size_t)(n * n) * sizeof(double));
+  if (!h.coarse_inv) {
+    h.coarse_inv = (double*)h.dalloc((size_t)(n * n) * sizeof(double));
+    h.coarse_invT = (double*)h.dalloc((size_t)(n * n) * sizeof(double));
+    h.coarse_work = (double*)h.dalloc((size_t)(2 * n) * sizeof(double));
+    h.coarse_piv = (int32_t*)h.dalloc((size_t)(n + 1) * sizeof(int32_t));
+  }
   HIPCHECK(hipMemcpy(h.coarse_inv, dense.data(), dense.size() * sizeof(double), hipMemcpyHostToDevice));
-  std::vector<int64_t> dp = {0, n}, off = {0};
-  int64_t* d_dp = (int64_t*)h.dalloc(2 * sizeof(int64_t));
-  int64_t* d_off = (int64_t*)h.dalloc(sizeof(int64_t));
-  int32_t* d_st = (int32_t*)h.dalloc(sizeof(int32_t));
-  HIPCHECK(hipMemcpy(d_dp, dp.data(), 2 * sizeof(int64_t), hipMemcpyHostToDevice));
-  HIPCHECK(hipMemcpy(d_off, off.data(), sizeof(int64_t), hipMemcpyHostToDevice));
-  launch_invert_blocks(0, 1, d_dp, d_off, h.coarse_inv, d_st, (int)n, h.stream);
+  HIPCHECK(hipMemset(h.coarse_piv + n, 0, sizeof(int32_t)));
+  launch_invert_dense(n, h.coarse_inv, h.coarse_invT, h.coarse_work, h.coarse_work + n, h.coarse_piv,
+                      h.coarse_piv + n, h.stream);
   HIPCHECK(hipGetLastError());
   int32_t st = 0;
-  HIPCHECK(hipMemcpyAsync(&st, d_st, sizeof(int32_t), hipMemcpyDeviceToHost, h.stream));
+  HIPCHECK(hipMemcpyAsync(&st, h.coarse_piv + n, sizeof(int32_t), hipMemcpyDeviceToHost, h.stream));
   HIPCHECK(hipStreamSynchronize(h.stream));
   if (st) throw Fail{FSGMG_ESINGULAR, "coarse-level matrix is singular"};
   h.n0 = n;
@@ -709,7 +714,8 @@ void vcycle_impl(fsgmg_hierarchy& h, const double* rin, double* zout, bool trans
                         h.stream);
   }
   DLevel& C = h.dl[0];
-  launch_dense_gemv<TV>(h.n0, h.coarse_inv, transpose, Vec<TV>::b(C), Vec<TV>::x(C), h.stream);
+  launch_dense_gemv<TV>(h.n0, transpose ? h.coarse_invT : h.coarse_inv, false, Vec<TV>::b(C),
+                        Vec<TV>::x(C), h.stream);
   for (int l = 1; l < L; ++l) {
     DLevel& d = h.dl[l];
     {
@@ -724,7 +730,7 @@ void vcycle_impl(fsgmg_hierarchy& h, const double* rin, double* zout, bool trans
 
 void vcycle(fsgmg_hierarchy& h, const double* r, double* z, bool transpose) {
   if (h.L == 1) {
-    launch_dense_gemv<double>(h.n0, h.coarse_inv, transpose, r, z, h.stream);
+    launch_dense_gemv<double>(h.n0, transpose ? h.coarse_invT : h.coarse_inv, false, r, z, h.stream);
     return;
   }
   if (h.sopt.prec == FSGMG_FP64)

@@ -77,7 +77,7 @@ def config(name: str) -> dict:
                    bc_d=bc_d, bc_u=bc_u, inflow_peak=1.0,
                    E=1e3, nu=0.3, mu=1e-2, rho=1.0, supg=False, w_amp=0.0,
                    ale_k=0, k_mass=0,
-                   core=(2, 2), halo=1, nu_pre=2, nu_post=2, omega=1.0,
+                   core=(2, 2), halo=1, nu_pre=2, nu_post=2, omega=0.8,
                    restart=30, rtol=1e-10, seed=0)
     elif name in ("c2", "c5"):
         bc_d, bc_u = _channel_bcs()
@@ -90,7 +90,7 @@ def config(name: str) -> dict:
                    bc_d=bc_d, bc_u=bc_u, inflow_peak=1.0,
                    E=1e4, nu=0.45, mu=3.5e-3, rho=1.0, supg=True, w_amp=1.0,
                    ale_k=0, k_mass=0,
-                   core=(4, 4), halo=1, nu_pre=2, nu_post=2, omega=1.0,
+                   core=(4, 4), halo=1, nu_pre=2, nu_post=2, omega=0.8,
                    restart=30, rtol=1e-10, seed=0)
         if name == "c5":
             cfg["n_levels"] = 4
@@ -112,7 +112,7 @@ def config(name: str) -> dict:
                    bc_d=bc_d, bc_u=bc_u, inflow_peak=1.0,
                    E=1e4, nu=0.45, mu=3.5e-3, rho=1.0, supg=True, w_amp=1.0,
                    ale_k=0, k_mass=0,
-                   core=(4, 4), halo=1, nu_pre=2, nu_post=2, omega=1.0,
+                   core=(4, 4), halo=1, nu_pre=2, nu_post=2, omega=0.8,
                    restart=30, rtol=1e-10, seed=0)
     else:
         raise KeyError(name)

@@ -237,3 +237,45 @@ def test_status_codes():
     b = dev(p.O.rhs(inputs.body_force(p.cfg)))
     info = p.H.gmres_solve(b, x, restart=2, max_restarts=0, rtol=1e-10)
     assert info["status"] == "NOT_CONVERGED" and not info["converged"] and info["iters"] == 2
+
+
+def test_full_size_c2_bench_configuration():
+    """c2 at full size (5 levels, 281,095 unknowns), the configuration the
+    benchmark times: FP32 V-cycle against the oracle's FP64 cycle and FP32 /
+    BF16 solves whose true residual is recomputed with the oracle's matrix."""
+    cfg = inputs.config("c2")
+    w = inputs.advecting_field(cfg)
+    f = inputs.body_force(cfg)
+    say("[full c2] oracle setup")
+    O = OracleHierarchy(cfg, w)
+    say("[full c2] library setup")
+    H = fsgmg.Hierarchy(cfg, w, device=0)
+    H.build_fs_as_blocks(prec="fp64")
+    rng = np.random.default_rng(9)
+    r = rng.standard_normal(H.N)
+    z = torch.zeros(H.N, dtype=torch.float64, device="cuda")
+    say("[full c2] vcycle fp64")
+    H.vcycle_apply(dev(r), z)
+    ref = O.vcycle(r)
+    err = np.linalg.norm(host(z) - ref) / np.linalg.norm(ref)
+    say("   fp64 cycle rel err %.3e" % err)
+    assert err <= 1e-9
+    b = O.rhs(f)
+    bd = torch.zeros(H.N, dtype=torch.float64, device="cuda")
+    H.assemble_load(dev(f.ravel()), bd)
+    assert np.allclose(host(bd), b, rtol=0, atol=1e-13 * abs(b).max())
+    A = O.A[-1]
+    for prec, tol in (("fp32", 2e-4), ("bf16", 2e-2)):
+        say("[full c2]", prec)
+        H.build_fs_as_blocks(prec=prec)
+        H.vcycle_apply(dev(r), z)
+        e = np.linalg.norm(host(z) - ref) / np.linalg.norm(ref)
+        say("   cycle rel err %.3e" % e)
+        assert e <= tol
+        x = torch.zeros_like(bd)
+        info = H.gmres_solve(bd, x, rtol=1e-10)
+        xs = host(x)
+        true = np.linalg.norm(b - A @ xs) / np.linalg.norm(b)
+        say("   iters", info["iters"], "true %.2e" % true)
+        assert info["converged"] and true <= 1e-10
+    H.close()
