@@ -95,7 +95,10 @@ typedef struct {
  * Richardson sweeps with damping omega, block inverses and level operators
  * of the V-cycle in `prec` (the coarse solve is always FP64; FSGMG_BF16
  * stores block inverses in bfloat16 and keeps FP32 level operators).
- * use_graph != 0 captures the V-cycle in a HIP graph. */
+ * use_graph != 0 captures each FGMRES Arnoldi step (V-cycle, operator
+ * product, Gram-Schmidt, Hessenberg read-back) and the V-cycle of
+ * vcycle_apply as HIP graphs on first use; the graphs are rebuilt after the
+ * next build_fs_as_blocks.  Graphs are bypassed while kernel_timing records. */
 typedef struct {
   int core[3];
   int halo;
@@ -195,6 +198,15 @@ fsgmg_status export_blocks(fsgmg_h h, int level, int64_t sizes[2], int64_t* ptr,
  * V-cycle on the finest level, 2 outer FP64 SpMV of FGMRES, 3 restriction +
  * prolongation between the two finest levels.  counts / total_ms may be NULL. */
 fsgmg_status kernel_timing(fsgmg_h h, int enable, int64_t counts[4], double total_ms[4]);
+
+/* Launch shapes chosen by the autotuner that build_fs_as_blocks runs on the
+ * device (HIP-event timing of the candidates on the level's own data; kept
+ * by later builds with the same block structure and precision):
+ * out[0] = lanes per row of the level's V-cycle SpMV (4, 8, 16), out[1] =
+ * smoother workgroup width (256, 512, 1024; negative = the same width with
+ * non-temporal loads of the block inverses; 0 on level 0), out[2] = lanes of
+ * the outer FP64 product.  ESTATE before the first device block build. */
+fsgmg_status tuning_info(fsgmg_h h, int level, int32_t out[3]);
 
 const char* last_error(fsgmg_h h);
 void hierarchy_destroy(fsgmg_h h);

@@ -37,6 +37,43 @@ struct Acc {
 // ------------------------------------------------------------------------
 // SpMV: LG lanes per node row block / pressure row
 // ------------------------------------------------------------------------
+// load a D x D block (row-major) or a D-vector with 16-byte loads when D = 2
+template <typename T, int D>
+__device__ inline void load_block(const T* v, T* out) {
+  if constexpr (D == 2 && sizeof(T) == 4) {
+    const float4 q = *reinterpret_cast<const float4*>(v);
+    out[0] = q.x;
+    out[1] = q.y;
+    out[2] = q.z;
+    out[3] = q.w;
+  } else if constexpr (D == 2) {
+    const double2 a = reinterpret_cast<const double2*>(v)[0];
+    const double2 b = reinterpret_cast<const double2*>(v)[1];
+    out[0] = a.x;
+    out[1] = a.y;
+    out[2] = b.x;
+    out[3] = b.y;
+  } else {
+#pragma unroll
+    for (int q = 0; q < D * D; ++q) out[q] = v[q];
+  }
+}
+template <typename T, int D>
+__device__ inline void load_col(const T* v, T* out) {
+  if constexpr (D == 2 && sizeof(T) == 4) {
+    const float2 q = *reinterpret_cast<const float2*>(v);
+    out[0] = q.x;
+    out[1] = q.y;
+  } else if constexpr (D == 2) {
+    const double2 q = *reinterpret_cast<const double2*>(v);
+    out[0] = q.x;
+    out[1] = q.y;
+  } else {
+#pragma unroll
+    for (int q = 0; q < D; ++q) out[q] = v[q];
+  }
+}
+
 template <typename T, int D, int LG>
 __global__ __launch_bounds__(kThreads) void k_spmv(BOpView<T> A, const T* __restrict__ x,
                                                    const T* __restrict__ b, T* __restrict__ y,
@@ -50,8 +87,8 @@ __global__ __launch_bounds__(kThreads) void k_spmv(BOpView<T> A, const T* __rest
     const int k1 = A.nn_ptr[item + 1];
     for (int k = A.nn_ptr[item] + lane; k < k1; k += LG) {
       const int c = A.nn_col[k];
-      const T* v = A.nn_val + (int64_t)k * (D * D);
-      T xv[D];
+      T v[D * D], xv[D];
+      load_block<T, D>(A.nn_val + (int64_t)k * (D * D), v);
 #pragma unroll
       for (int q = 0; q < D; ++q) xv[q] = x[c + q];
 #pragma unroll
@@ -62,7 +99,8 @@ __global__ __launch_bounds__(kThreads) void k_spmv(BOpView<T> A, const T* __rest
     const int p1 = A.np_ptr[item + 1];
     for (int k = A.np_ptr[item] + lane; k < p1; k += LG) {
       const T xv = x[A.np_col[k]];
-      const T* v = A.np_val + (int64_t)k * D;
+      T v[D];
+      load_col<T, D>(A.np_val + (int64_t)k * D, v);
 #pragma unroll
       for (int r = 0; r < D; ++r) acc[r] += v[r] * xv;
     }
@@ -82,7 +120,8 @@ __global__ __launch_bounds__(kThreads) void k_spmv(BOpView<T> A, const T* __rest
     const int k1 = A.pn_ptr[p + 1];
     for (int k = A.pn_ptr[p] + lane; k < k1; k += LG) {
       const int c = A.pn_col[k];
-      const T* v = A.pn_val + (int64_t)k * D;
+      T v[D];
+      load_col<T, D>(A.pn_val + (int64_t)k * D, v);
 #pragma unroll
       for (int q = 0; q < D; ++q) acc += v[q] * x[c + q];
     }
@@ -266,29 +305,38 @@ __global__ __launch_bounds__(kThreads) void k_transfer(TransferView<T> t, int mo
 // ------------------------------------------------------------------------
 // smoother
 // ------------------------------------------------------------------------
+// 16-byte loads of block-inverse values; NT = non-temporal (streamed once,
+// kept out of the caches so that coarse-level data stays resident)
+typedef float wf4 __attribute__((ext_vector_type(4)));
+typedef double wd2 __attribute__((ext_vector_type(2)));
+typedef unsigned wu4 __attribute__((ext_vector_type(4)));
+
+template <bool NT, typename V>
+__device__ inline V load16(const V* p) {
+  if constexpr (NT)
+    return __builtin_nontemporal_load(p);
+  else
+    return *p;
+}
+
 template <typename TW>
 struct WTraits;
 template <>
 struct WTraits<double> {
   static constexpr int RV = 2;
-  using vec = double2;
-  __device__ static void load(const double* p, double* o) {
-    const double2 v = *reinterpret_cast<const double2*>(p);
-    o[0] = v.x;
-    o[1] = v.y;
-  }
-  __device__ static void load(const double* p, float* o) {
-    const double2 v = *reinterpret_cast<const double2*>(p);
-    o[0] = (float)v.x;
-    o[1] = (float)v.y;
+  template <bool NT, typename TA>
+  __device__ static void load(const double* p, TA* o) {
+    const wd2 v = load16<NT>(reinterpret_cast<const wd2*>(p));
+    o[0] = (TA)v.x;
+    o[1] = (TA)v.y;
   }
 };
 template <>
 struct WTraits<float> {
   static constexpr int RV = 4;
-  template <typename TA>
+  template <bool NT, typename TA>
   __device__ static void load(const float* p, TA* o) {
-    const float4 v = *reinterpret_cast<const float4*>(p);
+    const wf4 v = load16<NT>(reinterpret_cast<const wf4*>(p));
     o[0] = v.x;
     o[1] = v.y;
     o[2] = v.z;
@@ -298,9 +346,9 @@ struct WTraits<float> {
 template <>
 struct WTraits<__hip_bfloat16> {
   static constexpr int RV = 8;
-  template <typename TA>
+  template <bool NT, typename TA>
   __device__ static void load(const __hip_bfloat16* p, TA* o) {
-    const uint4 v = *reinterpret_cast<const uint4*>(p);
+    const wu4 v = load16<NT>(reinterpret_cast<const wu4*>(p));
     const uint32_t u[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -313,7 +361,7 @@ struct WTraits<__hip_bfloat16> {
 // Forward sweep: x[own] = (first ? 0 : x[own]) + omega * (W_j r[I_j])[own].
 constexpr int kSmoothMaxThreads = 1024;
 
-template <typename TV, typename TW>
+template <typename TV, typename TW, bool NT>
 __global__ __launch_bounds__(kSmoothMaxThreads) void k_smooth_fwd(BlocksView B, const TW* __restrict__ W,
                                                          const TV* __restrict__ r,
                                                          TV* __restrict__ x, TV omega, int first) {
@@ -354,10 +402,10 @@ __global__ __launch_bounds__(kSmoothMaxThreads) void k_smooth_fwd(BlocksView B, 
     // four columns per step: four independent 16-byte loads in flight per lane
     for (; k + 3 * S < n; k += 4 * S) {
       TA w0[RV], w1[RV], w2[RV], w3[RV];
-      WTraits<TW>::load(p + (int64_t)k * mp, w0);
-      WTraits<TW>::load(p + (int64_t)(k + S) * mp, w1);
-      WTraits<TW>::load(p + (int64_t)(k + 2 * S) * mp, w2);
-      WTraits<TW>::load(p + (int64_t)(k + 3 * S) * mp, w3);
+      WTraits<TW>::template load<NT>(p + (int64_t)k * mp, w0);
+      WTraits<TW>::template load<NT>(p + (int64_t)(k + S) * mp, w1);
+      WTraits<TW>::template load<NT>(p + (int64_t)(k + 2 * S) * mp, w2);
+      WTraits<TW>::template load<NT>(p + (int64_t)(k + 3 * S) * mp, w3);
       const TA r0 = rl[k], r1 = rl[k + S], r2 = rl[k + 2 * S], r3 = rl[k + 3 * S];
 #pragma unroll
       for (int i = 0; i < RV; ++i) {
@@ -369,7 +417,7 @@ __global__ __launch_bounds__(kSmoothMaxThreads) void k_smooth_fwd(BlocksView B, 
     }
     for (; k < n; k += S) {
       TA w[RV];
-      WTraits<TW>::load(p + (int64_t)k * mp, w);
+      WTraits<TW>::template load<NT>(p + (int64_t)k * mp, w);
       const TA rk = rl[k];
 #pragma unroll
       for (int i = 0; i < RV; ++i) acc[i] += w[i] * rk;
@@ -410,7 +458,7 @@ __global__ __launch_bounds__(kThreads) void k_smooth_t1(BlocksView B, const TW* 
     const TW* col = Wj + (int64_t)k * mp;
     for (int i = 0; i < mp; i += RV) {
       TA w[RV];
-      WTraits<TW>::load(col + i, w);
+      WTraits<TW>::template load<false>(col + i, w);
 #pragma unroll
       for (int q = 0; q < RV; ++q) acc += w[q] * so[i + q];
     }
@@ -657,6 +705,23 @@ __device__ inline void block_store_partials(const double* acc, int k, double* pa
   }
 }
 
+// out[i] = sum over workgroups g of part[g][i] in a fixed order (one
+// wavefront per vector, lanes take g = lane, lane + 64, ..., then a fixed
+// butterfly), sqrt of the last entry when sqrt_last.  A separate kernel: a
+// "last workgroup reduces" variant needs agent-scope release fences, which
+// write back the whole L2 of each XCD and cost ~30 us per reduction here.
+__global__ __launch_bounds__(kThreads) void k_reduce_partials(const double* __restrict__ part,
+                                                              int k, double* __restrict__ out,
+                                                              int sqrt_last) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int i = wv; i < k; i += kThreads / 64) {
+    double s = 0.0;
+    for (int g = lane; g < kPartials; g += 64) s += part[(int64_t)g * kMaxK + i];
+    s = wave_sum(s);
+    if (lane == 0) out[i] = (sqrt_last && i == k - 1) ? sqrt(s) : s;
+  }
+}
+
 __global__ __launch_bounds__(kThreads) void k_mdot(const double* __restrict__ V, int64_t ld, int k,
                                                    const double* __restrict__ w, int64_t N,
                                                    double* __restrict__ part) {
@@ -729,27 +794,6 @@ __global__ __launch_bounds__(kThreads) void k_norm2(const double* __restrict__ w
        r += (int64_t)gridDim.x * blockDim.x)
     acc[0] += w[r] * w[r];
   block_store_partials(acc, 1, part);
-}
-
-// out[i] = sum_g part[g][i] (fixed tree order) (+ add_to[i]); sqrt of the
-// last entry when sqrt_last (norms)
-__global__ __launch_bounds__(kThreads) void k_reduce_partials(const double* __restrict__ part,
-                                                              int k, double* __restrict__ out,
-                                                              const double* __restrict__ add_to,
-                                                              int sqrt_last) {
-  // one wavefront per vector; lanes take partials g = lane, lane + 64, ... in
-  // a fixed order, then a fixed butterfly: the result is run-to-run identical
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int i = wv; i < k; i += kThreads / 64) {
-    double s = 0.0;
-    for (int g = lane; g < kPartials; g += 64) s += part[(int64_t)g * kMaxK + i];
-    s = wave_sum(s);
-    if (lane == 0) {
-      if (sqrt_last && i == k - 1) s = sqrt(s);
-      if (add_to) s += add_to[i];
-      out[i] = s;
-    }
-  }
 }
 
 __global__ __launch_bounds__(kThreads) void k_scale_copy(const double* __restrict__ w,
@@ -939,22 +983,33 @@ __global__ __launch_bounds__(kThreads) void k_scatter(int64_t n, const double* _
 // ========================================================================
 // launchers
 // ========================================================================
+template <typename T, int D>
+static void spmv_lanes(const BOpView<T>& A, int lanes, const T* x, const T* b, T* y,
+                       bool residual, hipStream_t s) {
+  const int lg = (lanes == 4 || lanes == 16) ? lanes : 8;
+  const int64_t items = A.nrb + A.npr;
+  const unsigned g = grid_for(items * lg, kThreads);
+  if (g == 0) return;
+  if (lg == 4)
+    hipLaunchKernelGGL((k_spmv<T, D, 4>), dim3(g), dim3(kThreads), 0, s, A, x, b, y, (int)residual);
+  else if (lg == 16)
+    hipLaunchKernelGGL((k_spmv<T, D, 16>), dim3(g), dim3(kThreads), 0, s, A, x, b, y, (int)residual);
+  else
+    hipLaunchKernelGGL((k_spmv<T, D, 8>), dim3(g), dim3(kThreads), 0, s, A, x, b, y, (int)residual);
+}
+
 template <typename T>
 void launch_spmv(const BOpView<T>& A, int D, const T* x, const T* b, T* y, bool residual,
-                 hipStream_t s) {
-  constexpr int LG = 8;
-  const int64_t items = A.nrb + A.npr;
-  const unsigned g = grid_for(items * LG, kThreads);
-  if (g == 0) return;
+                 hipStream_t s, int lanes) {
   if (D == 2)
-    hipLaunchKernelGGL((k_spmv<T, 2, LG>), dim3(g), dim3(kThreads), 0, s, A, x, b, y, (int)residual);
+    spmv_lanes<T, 2>(A, lanes, x, b, y, residual, s);
   else
-    hipLaunchKernelGGL((k_spmv<T, 3, LG>), dim3(g), dim3(kThreads), 0, s, A, x, b, y, (int)residual);
+    spmv_lanes<T, 3>(A, lanes, x, b, y, residual, s);
 }
 template void launch_spmv<double>(const BOpView<double>&, int, const double*, const double*,
-                                  double*, bool, hipStream_t);
+                                  double*, bool, hipStream_t, int);
 template void launch_spmv<float>(const BOpView<float>&, int, const float*, const float*, float*,
-                                 bool, hipStream_t);
+                                 bool, hipStream_t, int);
 
 void launch_csr_spmv(int64_t nrows, const int64_t* rowptr, const int32_t* col, const double* val,
                      const double* x, double* y, double beta, hipStream_t s) {
@@ -981,17 +1036,25 @@ template void launch_transfer<float>(const TransferView<float>&, int, int, const
 
 template <typename TV, typename TW>
 static void smooth_impl(const BlocksView& B, const TW* W, const TV* r, TV* x, TV* tbuf,
-                        double omega, bool first, bool transpose, int64_t N, hipStream_t s) {
+                        double omega, bool first, bool transpose, int64_t N, hipStream_t s,
+                        int threads) {
   if (!transpose) {
     // few blocks (coarse levels): wider workgroups shorten each lane's column loop
-    const int T = B.nblk < 1024 ? kSmoothMaxThreads : kThreads;
+    // threads < 0: non-temporal loads of the block inverses with |threads| lanes
+    const bool nt = threads < 0;
+    const int tabs = threads < 0 ? -threads : threads;
+    const int T = tabs > 0 ? tabs : (B.nblk < 1024 ? kSmoothMaxThreads : kThreads);
     const int64_t nj = (B.njac + T - 1) / T;
     const unsigned g = (unsigned)(B.nblk + nj);
     if (!g) return;
     const int RV = WTraits<TW>::RV;
     const size_t sm = sizeof(TV) * (size_t)(((B.max_n + 3) & ~3) + T * RV + B.max_mpad);
-    hipLaunchKernelGGL((k_smooth_fwd<TV, TW>), dim3(g), dim3(T), sm, s, B, W, r, x, (TV)omega,
-                       (int)first);
+    if (nt)
+      hipLaunchKernelGGL((k_smooth_fwd<TV, TW, true>), dim3(g), dim3(T), sm, s, B, W, r, x,
+                         (TV)omega, (int)first);
+    else
+      hipLaunchKernelGGL((k_smooth_fwd<TV, TW, false>), dim3(g), dim3(T), sm, s, B, W, r, x,
+                         (TV)omega, (int)first);
     return;
   }
   if (B.nblk) {
@@ -1007,24 +1070,27 @@ static void smooth_impl(const BlocksView& B, const TW* W, const TV* r, TV* x, TV
 
 template <typename TV>
 void launch_smooth(const BlocksView& B, WPrec wp, const void* W, const TV* r, TV* x, TV* tbuf,
-                   double omega, bool first, bool transpose, int64_t N, hipStream_t s) {
+                   double omega, bool first, bool transpose, int64_t N, hipStream_t s,
+                   int threads) {
   switch (wp) {
     case WPrec::F64:
-      smooth_impl<TV, double>(B, (const double*)W, r, x, tbuf, omega, first, transpose, N, s);
+      smooth_impl<TV, double>(B, (const double*)W, r, x, tbuf, omega, first, transpose, N, s,
+                              threads);
       break;
     case WPrec::F32:
-      smooth_impl<TV, float>(B, (const float*)W, r, x, tbuf, omega, first, transpose, N, s);
+      smooth_impl<TV, float>(B, (const float*)W, r, x, tbuf, omega, first, transpose, N, s,
+                             threads);
       break;
     case WPrec::BF16:
       smooth_impl<TV, __hip_bfloat16>(B, (const __hip_bfloat16*)W, r, x, tbuf, omega, first,
-                                      transpose, N, s);
+                                      transpose, N, s, threads);
       break;
   }
 }
 template void launch_smooth<double>(const BlocksView&, WPrec, const void*, const double*, double*,
-                                    double*, double, bool, bool, int64_t, hipStream_t);
+                                    double*, double, bool, bool, int64_t, hipStream_t, int);
 template void launch_smooth<float>(const BlocksView&, WPrec, const void*, const float*, float*,
-                                   float*, double, bool, bool, int64_t, hipStream_t);
+                                   float*, double, bool, bool, int64_t, hipStream_t, int);
 
 void launch_gather_blocks(int64_t j0, int64_t nb, const BlocksView& B, const int64_t* rowptr,
                           const int32_t* col, const double* val, const int64_t* dense_off,
@@ -1079,25 +1145,27 @@ template void launch_dense_gemv<float>(int64_t, const double*, bool, const float
 
 int krylov_partials() { return kPartials * kMaxK; }
 
+static void reduce(const double* part, int k, double* out, bool sqrt_last, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(kThreads), 0, s, part, k, out, (int)sqrt_last);
+}
 void launch_mdot(const double* V, int64_t ld, int k, const double* w, int64_t N, double* part,
-                 hipStream_t s) {
+                 double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_mdot, dim3(kPartials), dim3(kThreads), 0, s, V, ld, k, w, N, part);
+  reduce(part, k, out, false, s);
 }
 void launch_maxpy_mdot(const double* V, int64_t ld, int k, const double* h, double* w, int64_t N,
-                       double* part, hipStream_t s) {
+                       double* part, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_maxpy_mdot, dim3(kPartials), dim3(kThreads), 0, s, V, ld, k, h, w, N, part);
+  reduce(part, k, out, false, s);
 }
 void launch_maxpy_norm(const double* V, int64_t ld, int k, const double* h, double* w, int64_t N,
-                       double* part, hipStream_t s) {
+                       double* part, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_maxpy_norm, dim3(kPartials), dim3(kThreads), 0, s, V, ld, k, h, w, N, part);
+  reduce(part, 1, out, true, s);
 }
-void launch_reduce_partials(const double* part, int k, double* out, double* add_to,
-                            bool sqrt_last, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(kThreads), 0, s, part, k, out, add_to,
-                     (int)sqrt_last);
-}
-void launch_norm2_partial(const double* w, int64_t N, double* part, hipStream_t s) {
+void launch_norm2(const double* w, int64_t N, double* part, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_norm2, dim3(kPartials), dim3(kThreads), 0, s, w, N, part);
+  reduce(part, 1, out, true, s);
 }
 void launch_scale_copy(const double* w, const double* beta, double* v, int64_t N, hipStream_t s) {
   hipLaunchKernelGGL(k_scale_copy, dim3(grid_for(N, kThreads)), dim3(kThreads), 0, s, w, beta, v, N);
@@ -1128,9 +1196,10 @@ void launch_load_rhs(int64_t n, const int64_t* rowptr, const int32_t* col, const
                      val, f, lift, b);
 }
 
-void launch_masked_dot_partial(const double* a, const uint8_t* mask, const double* b, int64_t n,
-                               double* part, hipStream_t s) {
+void launch_masked_dot(const double* a, const uint8_t* mask, const double* b, int64_t n,
+                       double* part, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_masked_dot, dim3(kPartials), dim3(kThreads), 0, s, a, mask, b, n, part);
+  reduce(part, 1, out, false, s);
 }
 
 void launch_invert_dense(int64_t n, double* a, double* at, double* colk, double* rowk,

@@ -83,9 +83,10 @@ struct BlocksView {
 enum class WPrec { F64 = 0, F32 = 1, BF16 = 2 };
 
 // ---- level operator ----
+// lanes: 4, 8 or 16 lanes per node row block / pressure row
 template <typename T>
 void launch_spmv(const BOpView<T>& A, int D, const T* x, const T* b, T* y, bool residual,
-                 hipStream_t s);
+                 hipStream_t s, int lanes = 8);
 
 // scalar CSR (FP64): y = A x (+ beta y)
 void launch_csr_spmv(int64_t nrows, const int64_t* rowptr, const int32_t* col, const double* val,
@@ -98,9 +99,12 @@ void launch_transfer(const TransferView<T>& t, int D, int mode, const T* in, T* 
                      hipStream_t s);
 
 // ---- smoother: x = (first ? 0 : x) + omega * B r  (transpose: B^T) ----
+// threads: workgroup width of the forward sweep (256 / 512 / 1024, 0 = by
+// block count); a negative value selects non-temporal loads of the inverses
 template <typename TV>
 void launch_smooth(const BlocksView& B, WPrec wp, const void* W, const TV* r, TV* x, TV* tbuf,
-                   double omega, bool first, bool transpose, int64_t N, hipStream_t s);
+                   double omega, bool first, bool transpose, int64_t N, hipStream_t s,
+                   int threads = 0);
 
 // ---- block setup ----
 void launch_gather_blocks(int64_t j0, int64_t nb, const BlocksView& B, const int64_t* rowptr,
@@ -125,17 +129,18 @@ template <typename TV>
 void launch_dense_gemv(int64_t n, const double* Ainv, bool transpose, const TV* x, TV* y,
                        hipStream_t s);
 
-// ---- Krylov (FP64) ----
+// ---- Krylov (FP64): partial sums per workgroup, then a fixed-order
+// reduction kernel that writes out[0..k) (deterministic) ----
 int krylov_partials();
 void launch_mdot(const double* V, int64_t ld, int k, const double* w, int64_t N, double* part,
-                 hipStream_t s);
+                 double* out, hipStream_t s);
 void launch_maxpy_mdot(const double* V, int64_t ld, int k, const double* h, double* w, int64_t N,
-                       double* part, hipStream_t s);
+                       double* part, double* out, hipStream_t s);
+// w -= V h; out[0] = ||w||
 void launch_maxpy_norm(const double* V, int64_t ld, int k, const double* h, double* w,
-                       int64_t N, double* part, hipStream_t s);
-void launch_reduce_partials(const double* part, int k, double* out, double* add_to,
-                            bool sqrt_last, hipStream_t s);
-void launch_norm2_partial(const double* w, int64_t N, double* part, hipStream_t s);
+                       int64_t N, double* part, double* out, hipStream_t s);
+// out[0] = ||w||
+void launch_norm2(const double* w, int64_t N, double* part, double* out, hipStream_t s);
 void launch_scale_copy(const double* w, const double* beta, double* v, int64_t N, hipStream_t s);
 void launch_gemv_update(const double* Z, int64_t ld, int k, const double* y, double* x,
                         int64_t N, hipStream_t s);
@@ -146,8 +151,9 @@ void launch_cast(const TA* a, TB* b, int64_t n, hipStream_t s);
 void launch_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t s);
 void launch_load_rhs(int64_t n, const int64_t* rowptr, const int32_t* col, const double* val,
                      const double* f, const double* lift, double* b, hipStream_t s);
-void launch_masked_dot_partial(const double* a, const uint8_t* mask, const double* b, int64_t n,
-                               double* part, hipStream_t s);
+// out[0] = sum over unmasked i of a_i b_i
+void launch_masked_dot(const double* a, const uint8_t* mask, const double* b, int64_t n,
+                       double* part, double* out, hipStream_t s);
 template <typename T>
 void launch_fill(T* p, T v, int64_t n, hipStream_t s);
 // out[map[k]] = v[k] (either output may be null)

@@ -210,6 +210,32 @@ struct fsgmg_hierarchy {
   int ws_restart = 0;
   int64_t ld = 0;
   double *V = nullptr, *Z = nullptr, *w = nullptr, *part = nullptr, *small = nullptr;
+  // autotuned launch shapes per level: SpMV lanes per row (V-cycle precision),
+  // smoother workgroup width; lanes of the outer FP64 products
+  struct Tune {
+    int spmv_lanes = 8;
+    int smooth_threads = 0;
+  };
+  std::vector<Tune> tune;
+  int outer_lanes = 8;
+  bool tuned = false;
+  // HIP graphs: one per Arnoldi step j (V-cycle included) and transposition,
+  // one per V-cycle core; captured on a private stream, launched on `stream`
+  std::vector<hipGraphExec_t> step_graph[2];
+  hipGraphExec_t vcore_graph[2] = {nullptr, nullptr};
+  hipStream_t cap_stream = nullptr;
+  bool capturing = false;
+  void invalidate_graphs() {
+    for (auto& v : step_graph) {
+      for (hipGraphExec_t g : v)
+        if (g) (void)hipGraphExecDestroy(g);
+      v.clear();
+    }
+    for (auto& g : vcore_graph) {
+      if (g) (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+  }
   double* tmp = nullptr;
   double* pinned = nullptr;
   // kernel timing: HIP events around selected launches on the handle stream
@@ -254,6 +280,8 @@ struct fsgmg_hierarchy {
     if (device >= 0) {
       (void)hipSetDevice(device);
       for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+      invalidate_graphs();
+      if (cap_stream) (void)hipStreamDestroy(cap_stream);
       for (void* p : allocs) (void)hipFree(p);
       if (pinned) (void)hipHostFree(pinned);
     }
@@ -427,6 +455,7 @@ void build_coarse_inverse(fsgmg_hierarchy& h) {
 
 void upload_all(fsgmg_hierarchy& h) {
   h.dl.resize(h.L);
+  h.tune.assign(h.L, {});
   for (int l = 0; l < h.L; ++l) {
     const Level& lv = h.levels[l];
     const LevelOperator& op = h.ops[l];
@@ -680,26 +709,25 @@ void smooth_level(fsgmg_hierarchy& h, int l, int nsweeps, bool transpose, bool f
     if (s == 0 && from_zero) {
       TimedLaunch t(h, 0, fin);
       launch_smooth<TV>(d.bv, wp, d.W, b, x, Vec<TV>::t(d), h.sopt.omega, true, transpose, d.N,
-                        h.stream);
+                        h.stream, h.tune[l].smooth_threads);
     } else {
       {
         TimedLaunch t(h, 1, fin);
-        launch_spmv<TV>(Vec<TV>::op(d, transpose), D, x, b, r, true, h.stream);
+        launch_spmv<TV>(Vec<TV>::op(d, transpose), D, x, b, r, true, h.stream, h.tune[l].spmv_lanes);
       }
       TimedLaunch t(h, 0, fin);
       launch_smooth<TV>(d.bv, wp, d.W, r, x, Vec<TV>::t(d), h.sopt.omega, false, transpose, d.N,
-                        h.stream);
+                        h.stream, h.tune[l].smooth_threads);
     }
   }
 }
 
+// V-cycle from the finest right-hand side buffer b to the finest x buffer
 template <typename TV>
-void vcycle_impl(fsgmg_hierarchy& h, const double* rin, double* zout, bool transpose) {
+void vcycle_core(fsgmg_hierarchy& h, bool transpose) {
   const int L = h.L, D = h.D;
   const int npre = transpose ? h.sopt.nu_post : h.sopt.nu_pre;
   const int npost = transpose ? h.sopt.nu_pre : h.sopt.nu_post;
-  DLevel& F = h.dl[L - 1];
-  launch_cast<double, TV>(rin, Vec<TV>::b(F), F.N, h.stream);
   for (int l = L - 1; l >= 1; --l) {
     DLevel& d = h.dl[l];
     if (npre == 0) launch_fill<TV>(Vec<TV>::x(d), TV(0), d.N, h.stream);
@@ -707,7 +735,7 @@ void vcycle_impl(fsgmg_hierarchy& h, const double* rin, double* zout, bool trans
     {
       TimedLaunch t(h, 1, l == L - 1);
       launch_spmv<TV>(Vec<TV>::op(d, transpose), D, Vec<TV>::x(d), Vec<TV>::b(d), Vec<TV>::r(d),
-                      true, h.stream);
+                      true, h.stream, h.tune[l].spmv_lanes);
     }
     TimedLaunch t(h, 3, l == L - 1);
     launch_transfer<TV>(Vec<TV>::tv(d), D, transpose ? 2 : 0, Vec<TV>::r(d), Vec<TV>::b(h.dl[l - 1]),
@@ -724,6 +752,49 @@ void vcycle_impl(fsgmg_hierarchy& h, const double* rin, double* zout, bool trans
                           Vec<TV>::x(d), h.stream);
     }
     smooth_level<TV>(h, l, npost, transpose, false);
+  }
+}
+
+bool graphs_on(const fsgmg_hierarchy& h) { return h.sopt.use_graph && !h.timing && !h.capturing; }
+
+// Capture whatever `enqueue` puts on the handle stream into an executable graph.
+template <typename F>
+hipGraphExec_t capture(fsgmg_hierarchy& h, F&& enqueue) {
+  if (!h.cap_stream) HIPCHECK(hipStreamCreateWithFlags(&h.cap_stream, hipStreamNonBlocking));
+  hipStream_t saved = h.stream;
+  h.stream = h.cap_stream;
+  h.capturing = true;
+  HIPCHECK(hipStreamBeginCapture(h.cap_stream, hipStreamCaptureModeThreadLocal));
+  hipGraph_t g = nullptr;
+  try {
+    enqueue();
+  } catch (...) {
+    (void)hipStreamEndCapture(h.cap_stream, &g);
+    if (g) (void)hipGraphDestroy(g);
+    h.stream = saved;
+    h.capturing = false;
+    throw;
+  }
+  h.stream = saved;
+  h.capturing = false;
+  HIPCHECK(hipStreamEndCapture(h.cap_stream, &g));
+  hipGraphExec_t ex = nullptr;
+  const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) throw Fail{FSGMG_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e)};
+  return ex;
+}
+
+template <typename TV>
+void vcycle_impl(fsgmg_hierarchy& h, const double* rin, double* zout, bool transpose) {
+  DLevel& F = h.dl[h.L - 1];
+  launch_cast<double, TV>(rin, Vec<TV>::b(F), F.N, h.stream);
+  if (graphs_on(h)) {
+    hipGraphExec_t& g = h.vcore_graph[transpose ? 1 : 0];
+    if (!g) g = capture(h, [&] { vcycle_core<TV>(h, transpose); });
+    HIPCHECK(hipGraphLaunch(g, h.stream));
+  } else {
+    vcycle_core<TV>(h, transpose);
   }
   launch_cast<TV, double>(Vec<TV>::x(F), zout, F.N, h.stream);
 }
@@ -742,25 +813,65 @@ void vcycle(fsgmg_hierarchy& h, const double* r, double* z, bool transpose) {
 // ---------------------------------------------------------------------------
 // FGMRES
 // ---------------------------------------------------------------------------
+void ensure_reduction_buffers(fsgmg_hierarchy& h) {
+  if (!h.part) h.part = h.zeros<double>(krylov_partials());
+  if (!h.small) h.small = h.zeros<double>(256);
+  if (!h.pinned) HIPCHECK(hipHostMalloc((void**)&h.pinned, 256 * sizeof(double), hipHostMallocDefault));
+}
+
 void ensure_workspace(fsgmg_hierarchy& h, int m) {
   if (h.ws_restart >= m) return;
   const int64_t N = h.dl[h.L - 1].N;
+  h.invalidate_graphs();
   h.ld = (N + 63) / 64 * 64;
   h.V = h.zeros<double>((int64_t)(m + 1) * h.ld);
   h.Z = h.zeros<double>((int64_t)m * h.ld);
   h.w = h.zeros<double>(h.ld);
-  if (!h.part) h.part = h.zeros<double>(krylov_partials());
-  if (!h.small) h.small = h.zeros<double>(256);
-  if (!h.pinned) HIPCHECK(hipHostMalloc((void**)&h.pinned, 256 * sizeof(double), hipHostMallocDefault));
+  ensure_reduction_buffers(h);
   h.ws_restart = m;
 }
 
 double device_norm(fsgmg_hierarchy& h, const double* v, int64_t N) {
-  launch_norm2_partial(v, N, h.part, h.stream);
-  launch_reduce_partials(h.part, 1, h.small + 128, nullptr, true, h.stream);
+  ensure_reduction_buffers(h);
+  launch_norm2(v, N, h.part, h.small + 128, h.stream);
   HIPCHECK(hipMemcpyAsync(h.pinned, h.small + 128, sizeof(double), hipMemcpyDeviceToHost, h.stream));
   HIPCHECK(hipStreamSynchronize(h.stream));
   return h.pinned[0];
+}
+
+// Enqueue Arnoldi step j: v_j = w / ||w|| (j > 0), z_j = M^{-1} v_j,
+// w = A z_j, two classical Gram-Schmidt passes and ||w||; the Hessenberg
+// column pieces [h1 | h2 | ||w||] are copied to pinned host memory.
+void arnoldi_step(fsgmg_hierarchy& h, int j, bool transpose) {
+  DLevel& F = h.dl[h.L - 1];
+  const int64_t N = F.N, ld = h.ld;
+  const BOpView<double>& A = transpose ? F.AT.v64 : F.A.v64;
+  double* const h1 = h.small;
+  double* const h2 = h.small + 32;
+  double* const nr = h.small + 64;
+  double* vj = h.V + (int64_t)j * ld;
+  double* zj = h.Z + (int64_t)j * ld;
+  if (j > 0) launch_scale_copy(h.w, nr, vj, N, h.stream);
+  vcycle(h, vj, zj, transpose);
+  {
+    TimedLaunch t(h, 2, true);
+    launch_spmv<double>(A, h.D, zj, nullptr, h.w, false, h.stream, h.outer_lanes);
+  }
+  launch_mdot(h.V, ld, j + 1, h.w, N, h.part, h1, h.stream);
+  launch_maxpy_mdot(h.V, ld, j + 1, h1, h.w, N, h.part, h2, h.stream);
+  launch_maxpy_norm(h.V, ld, j + 1, h2, h.w, N, h.part, nr, h.stream);
+  HIPCHECK(hipMemcpyAsync(h.pinned, h.small, 65 * sizeof(double), hipMemcpyDeviceToHost, h.stream));
+}
+
+void run_arnoldi_step(fsgmg_hierarchy& h, int j, bool transpose) {
+  if (!graphs_on(h)) {
+    arnoldi_step(h, j, transpose);
+    return;
+  }
+  auto& v = h.step_graph[transpose ? 1 : 0];
+  if ((int)v.size() <= j) v.resize(j + 1, nullptr);
+  if (!v[j]) v[j] = capture(h, [&] { arnoldi_step(h, j, transpose); });
+  HIPCHECK(hipGraphLaunch(v[j], h.stream));
 }
 
 fsgmg_status fgmres(fsgmg_hierarchy& h, const double* b, double* x, const fsgmg_krylov_opts& o,
@@ -775,10 +886,7 @@ fsgmg_status fgmres(fsgmg_hierarchy& h, const double* b, double* x, const fsgmg_
   DLevel& F = h.dl[h.L - 1];
   const int64_t N = F.N, ld = h.ld;
   const BOpView<double>& A = transpose ? F.AT.v64 : F.A.v64;
-  double* const h1 = h.small;       // 32
-  double* const h2 = h.small + 32;  // 32
-  double* const nr = h.small + 64;  // 1
-  double* const yv = h.small + 96;  // 32
+  double* const yv = h.small + 96;  // 32 (h1, h2, ||w|| live in small[0..64])
   std::vector<double> hist;
   const double bnorm = device_norm(h, b, N);
   if (!std::isfinite(bnorm)) throw Fail{FSGMG_EINVAL, "right-hand side contains NaN or Inf"};
@@ -792,7 +900,7 @@ fsgmg_status fgmres(fsgmg_hierarchy& h, const double* b, double* x, const fsgmg_
   }
   std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
   for (int cycle = 0; !converged && cycle <= o.max_restarts; ++cycle) {
-    launch_spmv<double>(A, h.D, x, b, h.w, true, h.stream);
+    launch_spmv<double>(A, h.D, x, b, h.w, true, h.stream, h.outer_lanes);
     const double beta = device_norm(h, h.w, N);
     if (cycle == 0) hist.push_back(beta / bnorm);
     if (beta <= o.rtol * bnorm) {
@@ -806,20 +914,7 @@ fsgmg_status fgmres(fsgmg_hierarchy& h, const double* b, double* x, const fsgmg_
     g[0] = beta;
     int k = 0;
     for (int j = 0; j < m; ++j) {
-      double* vj = h.V + (int64_t)j * ld;
-      double* zj = h.Z + (int64_t)j * ld;
-      vcycle(h, vj, zj, transpose);
-      {
-        TimedLaunch t(h, 2, true);
-        launch_spmv<double>(A, h.D, zj, nullptr, h.w, false, h.stream);
-      }
-      launch_mdot(h.V, ld, j + 1, h.w, N, h.part, h.stream);
-      launch_reduce_partials(h.part, j + 1, h1, nullptr, false, h.stream);
-      launch_maxpy_mdot(h.V, ld, j + 1, h1, h.w, N, h.part, h.stream);
-      launch_reduce_partials(h.part, j + 1, h2, nullptr, false, h.stream);
-      launch_maxpy_norm(h.V, ld, j + 1, h2, h.w, N, h.part, h.stream);
-      launch_reduce_partials(h.part, 1, nr, nullptr, true, h.stream);
-      HIPCHECK(hipMemcpyAsync(h.pinned, h.small, 65 * sizeof(double), hipMemcpyDeviceToHost, h.stream));
+      run_arnoldi_step(h, j, transpose);
       HIPCHECK(hipStreamSynchronize(h.stream));
       const double hn = h.pinned[64];
       for (int i = 0; i <= j; ++i) H[i * m + j] = h.pinned[i] + h.pinned[32 + i];
@@ -842,7 +937,6 @@ fsgmg_status fgmres(fsgmg_hierarchy& h, const double* b, double* x, const fsgmg_
       hist.push_back(est / bnorm);
       if (!std::isfinite(est)) throw Fail{FSGMG_EINVAL, "non-finite residual estimate"};
       if (est <= o.rtol * bnorm || hn == 0.0) break;
-      launch_scale_copy(h.w, nr, h.V + (int64_t)(j + 1) * ld, N, h.stream);
     }
     for (int i = k - 1; i >= 0; --i) {
       double s = g[i];
@@ -851,7 +945,7 @@ fsgmg_status fgmres(fsgmg_hierarchy& h, const double* b, double* x, const fsgmg_
     }
     HIPCHECK(hipMemcpyAsync(yv, y.data(), k * sizeof(double), hipMemcpyHostToDevice, h.stream));
     launch_gemv_update(h.Z, ld, k, yv, x, N, h.stream);
-    launch_spmv<double>(A, h.D, x, b, h.w, true, h.stream);
+    launch_spmv<double>(A, h.D, x, b, h.w, true, h.stream, h.outer_lanes);
     true_rel = device_norm(h, h.w, N) / bnorm;
     if (true_rel <= o.rtol) {
       converged = true;
@@ -872,6 +966,79 @@ fsgmg_status fgmres(fsgmg_hierarchy& h, const double* b, double* x, const fsgmg_
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   }
   return converged ? FSGMG_OK : FSGMG_NOT_CONVERGED;
+}
+
+// Launch-shape autotuner: for every level time the V-cycle SpMV with 4, 8
+// and 16 lanes per row and the smoother sweep with 256, 512 and 1024-thread
+// workgroups (HIP events on the handle's stream, best of the averages of
+// three launches after one warm-up), and the outer FP64 product's lanes.
+template <typename F>
+float time_launch(fsgmg_hierarchy& h, F&& f) {
+  hipEvent_t a = h.next_event(), b = h.next_event();
+  f();
+  HIPCHECK(hipEventRecord(a, h.stream));
+  for (int i = 0; i < 3; ++i) f();
+  HIPCHECK(hipEventRecord(b, h.stream));
+  HIPCHECK(hipEventSynchronize(b));
+  float ms = 0.f;
+  HIPCHECK(hipEventElapsedTime(&ms, a, b));
+  h.ev_used -= 2;
+  return ms / 3.f;
+}
+
+template <typename TV>
+void autotune_impl(fsgmg_hierarchy& h) {
+  const bool was_timing = h.timing;
+  h.timing = false;
+  h.tune.assign(h.L, {});
+  const WPrec wp = wprec(h.sopt.prec);
+  const int lanes[3] = {4, 8, 16}, threads[6] = {256, 512, 1024, -256, -512, -1024};
+  for (int l = 0; l < h.L; ++l) {
+    DLevel& d = h.dl[l];
+    float best = 1e30f;
+    for (int lg : lanes) {
+      const float t = time_launch(h, [&] {
+        launch_spmv<TV>(Vec<TV>::op(d, false), h.D, Vec<TV>::x(d), Vec<TV>::b(d), Vec<TV>::r(d),
+                        true, h.stream, lg);
+      });
+      if (t < best) {
+        best = t;
+        h.tune[l].spmv_lanes = lg;
+      }
+    }
+    if (l == 0) continue;
+    best = 1e30f;
+    for (int th : threads) {
+      const float t = time_launch(h, [&] {
+        launch_smooth<TV>(d.bv, wp, d.W, Vec<TV>::b(d), Vec<TV>::x(d), Vec<TV>::t(d), 1.0, true,
+                          false, d.N, h.stream, th);
+      });
+      if (t < best) {
+        best = t;
+        h.tune[l].smooth_threads = th;
+      }
+    }
+  }
+  DLevel& F = h.dl[h.L - 1];
+  float best = 1e30f;
+  for (int lg : lanes) {
+    const float t = time_launch(h, [&] {
+      launch_spmv<double>(F.A.v64, h.D, F.x64, F.b64, F.r64, true, h.stream, lg);
+    });
+    if (t < best) {
+      best = t;
+      h.outer_lanes = lg;
+    }
+  }
+  HIPCHECK(hipGetLastError());
+  h.timing = was_timing;
+}
+
+void autotune(fsgmg_hierarchy& h) {
+  if (h.sopt.prec == FSGMG_FP64)
+    autotune_impl<double>(h);
+  else
+    autotune_impl<float>(h);
 }
 
 void check_device(fsgmg_hierarchy& h) {
@@ -971,6 +1138,7 @@ fsgmg_status build_fs_as_blocks(fsgmg_h h, const fsgmg_smoother_opts* opts) {
                            h->sopt.prec == opts->prec;
     h->sopt = *opts;
     h->factors_valid = false;
+    h->invalidate_graphs();
     if (!same_sets) {
       for (int l = 1; l < h->L; ++l) build_blocks(h->levels[l], opts->core, opts->halo, h->blocks[l]);
       h->have_blocks = true;
@@ -979,6 +1147,10 @@ fsgmg_status build_fs_as_blocks(fsgmg_h h, const fsgmg_smoother_opts* opts) {
     }
     if (h->host_only()) return FSGMG_OK;
     for (int l = 1; l < h->L; ++l) factor_blocks(*h, l);
+    // launch shapes depend on the block structure only: keep them while the
+    // index sets and precision are unchanged, so rebuilds stay reproducible
+    if (!same_sets || !h->tuned) autotune(*h);
+    h->tuned = true;
     h->factors_valid = true;
     return FSGMG_OK;
   });
@@ -1047,10 +1219,8 @@ fsgmg_status param_grad(fsgmg_h h, const double* lam, const double* x, double ou
     const int pieces[3] = {1, 2, 3};
     for (int q = 0; q < 3; ++q) {
       launch_csr_spmv(F.N, h->full_rp, h->full_col, h->full_piece[pieces[q]], x, h->tmp, 0.0, h->stream);
-      launch_masked_dot_partial(lam, h->dir_mask, h->tmp, F.N, h->part ? h->part : (h->part = h->zeros<double>(krylov_partials())), h->stream);
-      if (!h->small) h->small = h->zeros<double>(256);
-      if (!h->pinned) HIPCHECK(hipHostMalloc((void**)&h->pinned, 256 * sizeof(double), hipHostMallocDefault));
-      launch_reduce_partials(h->part, 1, h->small + 200, nullptr, false, h->stream);
+      ensure_reduction_buffers(*h);
+      launch_masked_dot(lam, h->dir_mask, h->tmp, F.N, h->part, h->small + 200, h->stream);
       HIPCHECK(hipMemcpyAsync(h->pinned, h->small + 200, sizeof(double), hipMemcpyDeviceToHost, h->stream));
       HIPCHECK(hipStreamSynchronize(h->stream));
       s[q] = h->pinned[0];
@@ -1207,6 +1377,16 @@ fsgmg_status kernel_timing(fsgmg_h h, int enable, int64_t counts[4], double tota
     h->ev_used = 0;
     return FSGMG_OK;
   });
+}
+
+fsgmg_status tuning_info(fsgmg_h h, int level, int32_t out[3]) {
+  // out[1] < 0 means non-temporal loads of the block inverses
+  if (!h || !out) return FSGMG_EINVAL;
+  if (level < 0 || level >= h->L || (int)h->tune.size() != h->L) return FSGMG_ESTATE;
+  out[0] = h->tune[level].spmv_lanes;
+  out[1] = h->tune[level].smooth_threads;
+  out[2] = h->outer_lanes;
+  return FSGMG_OK;
 }
 
 const char* last_error(fsgmg_h h) { return h ? h->err.c_str() : "null handle"; }

@@ -25,7 +25,7 @@ PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
 EXPORTED = ["setup_hierarchy", "build_fs_as_blocks", "vcycle_apply", "gmres_solve",
             "adjoint_solve", "assemble_load", "apply_operator", "param_grad",
             "update_params", "level_info", "export_csr", "export_vector", "export_blocks",
-            "kernel_timing", "last_error", "hierarchy_destroy"]
+            "kernel_timing", "tuning_info", "last_error", "hierarchy_destroy"]
 
 
 class MeshDesc(C.Structure):
@@ -89,6 +89,7 @@ def lib():
             "export_blocks": ([H, C.c_int, C.POINTER(C.c_int64), P, P, P], C.c_int),
             "kernel_timing": ([H, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double)],
                               C.c_int),
+            "tuning_info": ([H, C.c_int, C.POINTER(C.c_int32)], C.c_int),
             "last_error": ([H], C.c_char_p),
             "hierarchy_destroy": ([H], None),
         }
@@ -179,8 +180,8 @@ def setup_hierarchy(cfg, w=None, device=0, stream=None):
     return h
 
 
-def build_fs_as_blocks(h, core=(4, 4), halo=1, nu_pre=2, nu_post=2, omega=1.0, prec="fp64",
-                       use_graph=False):
+def build_fs_as_blocks(h, core=(4, 4), halo=1, nu_pre=2, nu_post=2, omega=0.8, prec="fp64",
+                       use_graph=True):
     o = SmootherOpts()
     for a in range(3):
         o.core[a] = int(core[a]) if a < len(core) else 1
@@ -288,6 +289,12 @@ def kernel_timing(h, enable):
     return {n: (int(counts[i]), float(tot[i])) for i, n in enumerate(names)}
 
 
+def tuning_info(h, level):
+    out = (C.c_int32 * 3)()
+    _check(h, lib().tuning_info(h, int(level), out))
+    return dict(spmv_lanes=int(out[0]), smooth_threads=int(out[1]), outer_lanes=int(out[2]))
+
+
 def hierarchy_destroy(h):
     if h:
         lib().hierarchy_destroy(h)
@@ -323,7 +330,7 @@ class Hierarchy:
     def build_fs_as_blocks(self, **kw):
         opts = dict(core=self.cfg.get("core", (4, 4)), halo=self.cfg.get("halo", 1),
                     nu_pre=self.cfg.get("nu_pre", 2), nu_post=self.cfg.get("nu_post", 2),
-                    omega=self.cfg.get("omega", 1.0))
+                    omega=self.cfg.get("omega", 0.8))
         opts.update(kw)
         build_fs_as_blocks(self.h, **opts)
 
@@ -367,3 +374,6 @@ class Hierarchy:
 
     def kernel_timing(self, enable):
         return kernel_timing(self.h, enable)
+
+    def tuning_info(self):
+        return [tuning_info(self.h, l) for l in range(self.L)]

@@ -279,3 +279,34 @@ def test_full_size_c2_bench_configuration():
         say("   iters", info["iters"], "true %.2e" % true)
         assert info["converged"] and true <= 1e-10
     H.close()
+
+
+def test_graph_replays_match_eager():
+    """Arnoldi-step and V-cycle graphs replayed several times, with eager
+    library work and host synchronizations in between, give bitwise the
+    eager results (all reductions are fixed-order)."""
+    p = pair("c2L3", "fp32")
+    f = inputs.body_force(p.cfg)
+    b = dev(p.O.rhs(f))
+    r = dev(np.random.default_rng(12).standard_normal(p.H.N))
+    say("[graphs] eager")
+    p.H.build_fs_as_blocks(prec="fp32", use_graph=False)
+    xe = torch.zeros_like(b)
+    ie = p.H.gmres_solve(b, xe)
+    ze = torch.zeros_like(b)
+    p.H.vcycle_apply(r, ze)
+    say("[graphs] captured")
+    p.H.build_fs_as_blocks(prec="fp32", use_graph=True)
+    for rep in range(3):
+        xg = torch.zeros_like(b)
+        ig = p.H.gmres_solve(b, xg)
+        assert ig["iters"] == ie["iters"]
+        assert torch.equal(xg, xe), rep
+        zg = torch.zeros_like(b)
+        p.H.vcycle_apply(r, zg)
+        assert torch.equal(zg, ze), rep
+        y = torch.zeros_like(b)
+        p.H.apply_operator(p.H.L - 1, xg, y)      # eager work between replays
+        torch.cuda.synchronize()
+    p.prec = None
+    p.build("fp64")
