@@ -157,6 +157,11 @@ fsgmg_status adjoint_solve(fsgmg_h h, const double* c, double* lam,
  * the Dirichlet lift applied (F zeroes Dirichlet rows). */
 fsgmg_status assemble_load(fsgmg_h h, const double* f_nodal, double* b);
 
+/* gf = (F L)^T lam: the adjoint of assemble_load's linear part, i.e. the
+ * gradient of lam^T b with respect to the nodal body force (device, finest
+ * N2 x dim output, lam of the finest level size). */
+fsgmg_status load_adjoint(fsgmg_h h, const double* lam, double* gf);
+
 /* y = A_l x or A_l^T x on level `level` (FP64 operator, device vectors of
  * that level's size). */
 fsgmg_status apply_operator(fsgmg_h h, int level, const double* x, double* y, int transpose);

@@ -200,6 +200,9 @@ struct fsgmg_hierarchy {
   int64_t* load_rp = nullptr;
   int32_t* load_col = nullptr;
   double* load_val = nullptr;
+  int64_t* loadT_rp = nullptr;   // transpose of the load operator (adjoint of the load)
+  int32_t* loadT_col = nullptr;
+  double* loadT_val = nullptr;
   double* lift = nullptr;
   double* lift_piece[4] = {nullptr, nullptr, nullptr, nullptr};
   int64_t* full_rp = nullptr;
@@ -481,6 +484,12 @@ void upload_all(fsgmg_hierarchy& h) {
   h.load_rp = h.upload(op.load.rowptr);
   h.load_col = h.upload(op.load.col);
   h.load_val = h.upload(op.load.val);
+  {
+    CsrHost LT = csr_transpose(op.load);
+    h.loadT_rp = h.upload(LT.rowptr);
+    h.loadT_col = h.upload(LT.col);
+    h.loadT_val = h.upload(LT.val);
+  }
   for (int p = 0; p < 4; ++p) h.lift_piece[p] = h.upload(op.lift_piece[p]);
   std::vector<double> lift(F.N);
   for (int64_t i = 0; i < F.N; ++i)
@@ -1191,6 +1200,18 @@ fsgmg_status assemble_load(fsgmg_h h, const double* f, double* b) {
   return guarded(h, [&]() -> fsgmg_status {
     check_device(*h);
     launch_load_rhs(h->dl[h->L - 1].N, h->load_rp, h->load_col, h->load_val, f, h->lift, b, h->stream);
+    HIPCHECK(hipGetLastError());
+    return FSGMG_OK;
+  });
+}
+
+fsgmg_status load_adjoint(fsgmg_h h, const double* lam, double* gf) {
+  if (!h || !lam || !gf || (const void*)lam == (void*)gf) return FSGMG_EINVAL;
+  return guarded(h, [&]() -> fsgmg_status {
+    check_device(*h);
+    const Level& F = h->levels[h->L - 1];
+    launch_csr_spmv((int64_t)F.D * F.N2, h->loadT_rp, h->loadT_col, h->loadT_val, lam, gf, 0.0,
+                    h->stream);
     HIPCHECK(hipGetLastError());
     return FSGMG_OK;
   });

@@ -23,7 +23,7 @@ STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "EHIP", -3: "ESINGULAR"
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
 
 EXPORTED = ["setup_hierarchy", "build_fs_as_blocks", "vcycle_apply", "gmres_solve",
-            "adjoint_solve", "assemble_load", "apply_operator", "param_grad",
+            "adjoint_solve", "assemble_load", "load_adjoint", "apply_operator", "param_grad",
             "update_params", "level_info", "export_csr", "export_vector", "export_blocks",
             "kernel_timing", "tuning_info", "last_error", "hierarchy_destroy"]
 
@@ -80,6 +80,7 @@ def lib():
             "gmres_solve": ([H, P, P, C.POINTER(KrylovOpts), C.POINTER(SolveInfo)], C.c_int),
             "adjoint_solve": ([H, P, P, C.POINTER(KrylovOpts), C.POINTER(SolveInfo)], C.c_int),
             "assemble_load": ([H, P, P], C.c_int),
+            "load_adjoint": ([H, P, P], C.c_int),
             "apply_operator": ([H, C.c_int, P, P, C.c_int], C.c_int),
             "param_grad": ([H, P, P, C.POINTER(C.c_double)], C.c_int),
             "update_params": ([H, C.c_double, C.c_double], C.c_int),
@@ -222,6 +223,10 @@ def assemble_load(h, f, b):
     _check(h, lib().assemble_load(h, _ptr(f), _ptr(b)))
 
 
+def load_adjoint(h, lam, gf):
+    _check(h, lib().load_adjoint(h, _ptr(lam), _ptr(gf)))
+
+
 def apply_operator(h, level, x, y, transpose=False):
     _check(h, lib().apply_operator(h, int(level), _ptr(x), _ptr(y), int(bool(transpose))))
 
@@ -360,6 +365,10 @@ class Hierarchy:
     def assemble_load(self, f, b):
         n2d = self.info[-1]["N2"] * self.info[-1]["dim"]
         assemble_load(self.h, self._vec(f, n2d), self._vec(b))
+
+    def load_adjoint(self, lam, gf):
+        n2d = self.info[-1]["N2"] * self.info[-1]["dim"]
+        load_adjoint(self.h, self._vec(lam), self._vec(gf, n2d))
 
     def apply_operator(self, level, x, y, transpose=False):
         n = self.info[level]["N"]

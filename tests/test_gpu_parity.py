@@ -310,3 +310,50 @@ def test_graph_replays_match_eager():
         torch.cuda.synchronize()
     p.prec = None
     p.build("fp64")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_autograd_batch_gradients(prec):
+    """Differentiation workload (c5 shape at 2 levels): x = FSISolve(f, E, mu),
+    J = outlet flux; torch autograd (adjoint solve, load adjoint, parameter
+    gradient in the library) against the oracle's adjoint gradients for three
+    seeded (f, E, mu) samples.  tau is frozen at the hierarchy's setup
+    parameters on both sides."""
+    from paper_1909_13201_amd.autograd import FSISolve
+    cfg = inputs.with_levels(inputs.config("c5"), 2)
+    w = inputs.advecting_field(cfg)
+    say("[autograd]", prec)
+    H = fsgmg.Hierarchy(cfg, w, device=0)
+    O0 = OracleHierarchy(cfg, w, build_smoothers=False)
+    taus = [q["tau"] for q in O0.parts]
+    lv = O0.finest
+    c = oadj.outlet_flux_vector(lv)
+    ct = dev(c)
+    params = inputs.sample_parameters(cfg, 3)
+    loads = inputs.sample_loads(cfg, 3)
+    rng = np.random.default_rng(21)
+    for i in range(3):
+        E, mu = params[i]
+        f = torch.tensor(loads[i].ravel(), dtype=torch.float64, device="cuda", requires_grad=True)
+        Et = torch.tensor(E, dtype=torch.float64, requires_grad=True)
+        mt = torch.tensor(mu, dtype=torch.float64, requires_grad=True)
+        x = FSISolve.apply(f, Et, mt, H, dict(prec=prec, rtol=1e-11, max_restarts=40))
+        J = (ct * x).sum()
+        J.backward()
+        cfg_i = dict(cfg, E=float(E), mu=float(mu))
+        Oi = OracleHierarchy(cfg_i, w, taus=taus, build_smoothers=False)
+        A = Oi.A[-1]
+        b = Oi.rhs(loads[i])
+        xd = spla.splu(A.tocsc()).solve(b)
+        lam = spla.splu(A.T.tocsc()).solve(c)
+        oE, omu = oadj.gradients(Oi, xd, lam)
+        df = rng.standard_normal(loads[i].shape)
+        dJ = lam @ (Oi.rhs(loads[i] + df) - b)
+        gdf = float((f.grad.detach().cpu().numpy() * df.ravel()).sum())
+        say("   sample", i, "E %.3g mu %.3g" % (E, mu), "dJ/dE %.6e vs %.6e" % (Et.grad.item(), oE),
+            "dJ/dmu %.6e vs %.6e" % (mt.grad.item(), omu), "df %.6e vs %.6e" % (gdf, dJ))
+        assert float(J.detach()) == pytest.approx(c @ xd, rel=1e-8)
+        assert Et.grad.item() == pytest.approx(oE, rel=1e-6)
+        assert mt.grad.item() == pytest.approx(omu, rel=1e-6)
+        assert gdf == pytest.approx(dJ, rel=1e-6)
+    H.close()
