@@ -8,8 +8,9 @@
 //    rows (column-major, 16-byte vector loads); the last-writer update of
 //    Section 3.2 becomes a conflict-free scatter because every unknown has
 //    exactly one owner
-//  * block setup: gather of principal submatrices, in-place Gauss-Jordan
-//    inversion with partial pivoting (FP64), owned-row extraction
+//  * block setup: gather of principal submatrices, blocked in-place
+//    Gauss-Jordan inversion with partial pivoting (FP64, trailing updates on
+//    the FP64 matrix cores), owned-row extraction
 //  * FGMRES building blocks: multi-vector dot products with fixed-order
 //    partial sums (deterministic), fused MAXPY + dot, norms
 #include <hip/hip_runtime.h>
@@ -492,6 +493,12 @@ __global__ __launch_bounds__(kThreads) void k_smooth_t2(BlocksView B, const TV* 
 // ------------------------------------------------------------------------
 // block setup
 // ------------------------------------------------------------------------
+// Dense principal submatrix A[I_j, I_j] of block j, row-major with the row
+// stride np = n rounded up to 16; the padding is the identity, so the padded
+// matrix is blockdiag(A[I_j, I_j], I) and its inverse carries A[I_j, I_j]^-1
+// in the leading n x n corner.
+__device__ inline int pad16(int n) { return (n + 15) & ~15; }
+
 __global__ __launch_bounds__(kThreads) void k_gather_blocks(int64_t j0, BlocksView B,
                                                             const int64_t* __restrict__ rp,
                                                             const int32_t* __restrict__ col,
@@ -501,8 +508,12 @@ __global__ __launch_bounds__(kThreads) void k_gather_blocks(int64_t j0, BlocksVi
   const int64_t j = j0 + blockIdx.x;
   const int64_t d0 = B.dof_ptr[j];
   const int n = (int)(B.dof_ptr[j + 1] - d0);
+  const int np = pad16(n);
   double* a = dense + doff[blockIdx.x];
-  for (int64_t e = threadIdx.x; e < (int64_t)n * n; e += blockDim.x) a[e] = 0.0;
+  for (int64_t e = threadIdx.x; e < (int64_t)np * np; e += blockDim.x) {
+    const int r = (int)(e / np);
+    a[e] = (r >= n && e == (int64_t)r * np + r) ? 1.0 : 0.0;
+  }
   __syncthreads();
   const int32_t* I = B.dofs + d0;
   for (int k = threadIdx.x; k < n; k += blockDim.x) {
@@ -514,7 +525,7 @@ __global__ __launch_bounds__(kThreads) void k_gather_blocks(int64_t j0, BlocksVi
         const int mid = (lo + hi) >> 1;
         const int32_t v = I[mid];
         if (v == c) {
-          a[(int64_t)k * n + mid] = val[e];
+          a[(int64_t)k * np + mid] = val[e];
           break;
         }
         if (v < c)
@@ -526,96 +537,170 @@ __global__ __launch_bounds__(kThreads) void k_gather_blocks(int64_t j0, BlocksVi
   }
 }
 
-// In-place Gauss-Jordan inversion with row interchanges (partial pivoting),
-// followed by the inverse column interchanges.  One workgroup per matrix.
-constexpr int kInvThreads = 512;
+// Blocked in-place Gauss-Jordan inversion with partial pivoting, one
+// workgroup (four wavefronts) per padded np x np FP64 block.
+//
+// Columns are processed in panels of NB.  For a panel the workgroup loads
+// the np x NB column strip into LDS and runs the scalar Gauss-Jordan steps
+// on it (pivot = largest magnitude in the column at or below the diagonal,
+// smallest row on ties; the row interchange is applied to the whole row in
+// global memory).  Afterwards the strip holds T = [-A_iK A_KK^-1 ; A_KK^-1]
+// (K = the panel's pivot rows), and every other column j of the matrix is
+// updated in one rank-NB step
+//     A[:, j] += (T - E_K) A[K, j]
+// which is a dense contraction: 16 x 16 FP64 output tiles, one wavefront per
+// column tile, v_mfma_f64_16x16x4f64 over the NB panel columns.  The
+// interchanges are undone by a column permutation sigma (inverse[:, q] =
+// result[:, sigma[q]]) that the owned-row extraction applies, instead of
+// column swaps over the whole matrix.
+using f64x4 = __attribute__((__vector_size__(4 * sizeof(double)))) double;
+constexpr int kPanel = 16;
 
-__global__ __launch_bounds__(kInvThreads) void k_invert(int64_t j0, const int64_t* __restrict__ dof_ptr,
-                                                        const int64_t* __restrict__ doff,
-                                                        double* __restrict__ dense,
-                                                        int32_t* __restrict__ status) {
+template <int NB>
+__global__ __launch_bounds__(kThreads) void k_invert_blocked(
+    int64_t j0, const int64_t* __restrict__ dof_ptr, const int64_t* __restrict__ doff,
+    const int64_t* __restrict__ soff, double* __restrict__ dense, int32_t* __restrict__ sigma_all,
+    int32_t* __restrict__ status) {
+  static_assert(NB % 16 == 0, "panel width must be a multiple of the tile");
+  constexpr int LDT = NB + 1;   // LDS row stride (doubles) of the strip
+  constexpr int NW = kThreads / 64;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int64_t j = j0 + blockIdx.x;
   const int n = (int)(dof_ptr[j + 1] - dof_ptr[j]);
+  const int np = pad16(n);
   double* a = dense + doff[blockIdx.x];
-  double* colk = reinterpret_cast<double*>(smem_raw);
-  double* rowk = colk + n;
-  double* redv = rowk + n;
-  int* redi = reinterpret_cast<int*>(redv + kInvThreads);
-  int* piv = redi + kInvThreads;
-  __shared__ int s_fail;
-  const int tid = threadIdx.x, T = blockDim.x;
-  if (tid == 0) s_fail = 0;
-  __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    // pivot search over rows k..n-1 (ties: smallest row)
-    double best = -1.0;
-    int bi = n;
-    for (int i = k + tid; i < n; i += T) {
-      const double v = fabs(a[(int64_t)i * n + k]);
-      if (v > best) {
-        best = v;
-        bi = i;
-      }
+  double* T = reinterpret_cast<double*>(smem_raw);   // np x LDT
+  double* rowc = T + (size_t)np * LDT;                // NB
+  double* wval = rowc + NB;                           // NW
+  int* widx = reinterpret_cast<int*>(wval + NW);      // NW
+  int* piv = widx + NW;                               // np
+  int* sig = piv + np;                                // np
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int lr = lane & 15, lg = lane >> 4;
+  const int ntile = np / 16;
+
+  for (int k0 = 0; k0 < np; k0 += NB) {
+    const int nbk = min(NB, np - k0);   // NB or 16 on the last panel
+    for (int e = tid; e < np * nbk; e += kThreads) {
+      const int r = e / nbk, q = e - r * nbk;
+      T[r * LDT + q] = a[(int64_t)r * np + k0 + q];
     }
-    redv[tid] = best;
-    redi[tid] = bi;
     __syncthreads();
-    for (int s = T / 2; s > 0; s >>= 1) {
-      if (tid < s) {
-        const double v2 = redv[tid + s];
-        const int i2 = redi[tid + s];
-        if (v2 > redv[tid] || (v2 == redv[tid] && i2 < redi[tid])) {
-          redv[tid] = v2;
-          redi[tid] = i2;
+    for (int kk = 0; kk < nbk; ++kk) {
+      const int c = k0 + kk;
+      double best = -1.0;
+      int bi = np;
+      for (int r = c + tid; r < np; r += kThreads) {
+        const double v = fabs(T[r * LDT + kk]);
+        if (v > best) {
+          best = v;
+          bi = r;
+        }
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const double v2 = __shfl_xor(best, off, 64);
+        const int i2 = __shfl_xor(bi, off, 64);
+        if (v2 > best || (v2 == best && i2 < bi)) {
+          best = v2;
+          bi = i2;
+        }
+      }
+      if (lane == 0) {
+        wval[wv] = best;
+        widx[wv] = bi;
+      }
+      __syncthreads();
+      best = wval[0];
+      bi = widx[0];
+#pragma unroll
+      for (int w = 1; w < NW; ++w)
+        if (wval[w] > best || (wval[w] == best && widx[w] < bi)) {
+          best = wval[w];
+          bi = widx[w];
+        }
+      if (!(best > 0.0)) {   // the same decision in every thread
+        if (tid == 0) status[j] = 1;
+        return;
+      }
+      const int p = bi;
+      if (tid == 0) piv[c] = p;
+      if (p != c) {
+        for (int q = tid; q < nbk; q += kThreads) {
+          const double t0 = T[c * LDT + q];
+          T[c * LDT + q] = T[p * LDT + q];
+          T[p * LDT + q] = t0;
+        }
+        for (int q = tid; q < np - nbk; q += kThreads) {
+          const int cc = q < k0 ? q : q + nbk;
+          const double t0 = a[(int64_t)c * np + cc];
+          a[(int64_t)c * np + cc] = a[(int64_t)p * np + cc];
+          a[(int64_t)p * np + cc] = t0;
+        }
+      }
+      __syncthreads();
+      const double d = 1.0 / T[c * LDT + kk];
+      if (tid < nbk) rowc[tid] = (tid == kk) ? d : T[c * LDT + tid] * d;
+      __syncthreads();
+      for (int r = tid; r < np; r += kThreads) {
+        double* Tr = T + r * LDT;
+        if (r == c) {
+          for (int q = 0; q < nbk; ++q) Tr[q] = rowc[q];
+        } else {
+          const double t = Tr[kk];
+          for (int q = 0; q < nbk; ++q) Tr[q] = (q == kk ? 0.0 : Tr[q]) - t * rowc[q];
         }
       }
       __syncthreads();
     }
-    const int p = redi[0];
-    if (!(redv[0] > 0.0)) {
-      if (tid == 0) {
-        s_fail = 1;
-        status[j] = 1;
-      }
-      __syncthreads();
-      return;
-    }
-    if (tid == 0) piv[k] = p;
-    if (p != k)
-      for (int c = tid; c < n; c += T) {
-        const double t0 = a[(int64_t)k * n + c];
-        a[(int64_t)k * n + c] = a[(int64_t)p * n + c];
-        a[(int64_t)p * n + c] = t0;
-      }
-    __syncthreads();
-    const double d = 1.0 / a[(int64_t)k * n + k];
-    for (int i = tid; i < n; i += T) {
-      colk[i] = a[(int64_t)i * n + k];
-      rowk[i] = (i == k) ? d : a[(int64_t)k * n + i] * d;
+    // the strip's final values, then T - E_K in LDS for the update
+    for (int e = tid; e < np * nbk; e += kThreads) {
+      const int r = e / nbk, q = e - r * nbk;
+      const double v = T[r * LDT + q];
+      a[(int64_t)r * np + k0 + q] = v;
+      if (r == k0 + q) T[r * LDT + q] = v - 1.0;
     }
     __syncthreads();
-    for (int64_t e = tid; e < (int64_t)n * n; e += T) {
-      const int i = (int)(e / n), c = (int)(e - (int64_t)i * n);
-      if (i == k) {
-        a[e] = rowk[c];
-      } else {
-        const double base = (c == k) ? 0.0 : a[e];
-        a[e] = base - colk[i] * rowk[c];
+    // rank-nbk update of every column tile outside the panel
+    const int t0 = k0 / 16, t1 = t0 + nbk / 16;
+    for (int J = wv; J < ntile; J += NW) {
+      if (J >= t0 && J < t1) continue;
+      const int c0 = J * 16 + lr;
+      double bq[NB / 4];
+#pragma unroll
+      for (int q = 0; q < NB / 4; ++q)
+        bq[q] = (4 * q < nbk) ? a[(int64_t)(k0 + 4 * q + lg) * np + c0] : 0.0;
+      // accumulator layout of v_mfma_f64_16x16x4f64: lane (lr, lg) holds
+      // rows lg, lg + 4, lg + 8, lg + 12 of column lr
+      for (int it = 0; it < ntile; ++it) {
+        const int r0 = it * 16 + lg;
+        f64x4 acc;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[r] = a[(int64_t)(r0 + 4 * r) * np + c0];
+        const double* Tt = T + (it * 16 + lr) * LDT + lg;
+#pragma unroll
+        for (int q = 0; q < NB / 4; ++q)
+          if (4 * q < nbk) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Tt[4 * q], bq[q], acc, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) a[(int64_t)(r0 + 4 * r) * np + c0] = acc[r];
       }
     }
     __syncthreads();
   }
-  for (int k = n - 1; k >= 0; --k) {
-    const int p = piv[k];
-    if (p != k)
-      for (int i = tid; i < n; i += T) {
-        const double t0 = a[(int64_t)i * n + k];
-        a[(int64_t)i * n + k] = a[(int64_t)i * n + p];
-        a[(int64_t)i * n + p] = t0;
-      }
-    __syncthreads();
+  // column permutation that undoes the row interchanges (applied in
+  // reverse order of the pivot steps)
+  if (tid == 0) {
+    for (int c = 0; c < np; ++c) sig[c] = c;
+    for (int c = np - 1; c >= 0; --c) {
+      const int p = piv[c];
+      const int t = sig[c];
+      sig[c] = sig[p];
+      sig[p] = t;
+    }
   }
+  __syncthreads();
+  int32_t* sg = sigma_all + soff[blockIdx.x];
+  for (int c = tid; c < np; c += kThreads) sg[c] = sig[c];
   if (tid == 0) status[j] = 0;
 }
 
@@ -631,18 +716,23 @@ __device__ inline __hip_bfloat16 to_w<__hip_bfloat16>(double v) { return __float
 template <typename TW>
 __global__ __launch_bounds__(kThreads) void k_extract(int64_t j0, BlocksView B,
                                                       const int64_t* __restrict__ doff,
+                                                      const int64_t* __restrict__ soff,
                                                       const double* __restrict__ dense,
+                                                      const int32_t* __restrict__ sigma_all,
                                                       TW* __restrict__ W) {
   const int64_t j = j0 + blockIdx.x;
   const int n = (int)(B.dof_ptr[j + 1] - B.dof_ptr[j]);
+  const int np = pad16(n);
   const int o0 = B.own_ptr[j];
   const int m = B.own_ptr[j + 1] - o0;
   const int mp = B.mpad[j];
   const double* a = dense + doff[blockIdx.x];
+  const int32_t* sg = sigma_all + soff[blockIdx.x];
   TW* Wj = W + B.w_off[j];
+  // W (column-major, mp rows): W[k][i] = inverse[own_loc[i]][k]
   for (int64_t e = threadIdx.x; e < (int64_t)n * mp; e += blockDim.x) {
     const int k = (int)(e / mp), i = (int)(e - (int64_t)k * mp);
-    const double v = i < m ? a[(int64_t)B.own_loc[o0 + i] * n + k] : 0.0;
+    const double v = i < m ? a[(int64_t)B.own_loc[o0 + i] * np + sg[k]] : 0.0;
     Wj[e] = to_w<TW>(v);
   }
 }
@@ -1100,30 +1190,36 @@ void launch_gather_blocks(int64_t j0, int64_t nb, const BlocksView& B, const int
                        col, val, dense_off, dense);
 }
 
+size_t invert_blocks_lds(int np_max) {
+  return (size_t)np_max * (kPanel + 1) * 8 + (size_t)kPanel * 8 + (kThreads / 64) * 12 +
+         (size_t)np_max * 8;
+}
+
 void launch_invert_blocks(int64_t j0, int64_t nb, const int64_t* dof_ptr, const int64_t* dense_off,
-                          double* dense, int32_t* status, int max_n, hipStream_t s) {
-  // LDS: colk, rowk (n doubles each), reduction scratch (T doubles + T ints), piv (n ints)
-  const size_t sm = (size_t)max_n * 20 + (size_t)kInvThreads * 12 + 64;
-  if (nb > 0)
-    hipLaunchKernelGGL(k_invert, dim3((unsigned)nb), dim3(kInvThreads), sm, s, j0, dof_ptr,
-                       dense_off, dense, status);
+                          const int64_t* sigma_off, double* dense, int32_t* sigma,
+                          int32_t* status, int max_n, hipStream_t s) {
+  if (nb <= 0) return;
+  const size_t sm = invert_blocks_lds((max_n + 15) & ~15);
+  hipLaunchKernelGGL((k_invert_blocked<kPanel>), dim3((unsigned)nb), dim3(kThreads), sm, s, j0,
+                     dof_ptr, dense_off, sigma_off, dense, sigma, status);
 }
 
 void launch_extract_owned(int64_t j0, int64_t nb, const BlocksView& B, const int64_t* dense_off,
-                          const double* dense, WPrec wp, void* W, hipStream_t s) {
+                          const int64_t* sigma_off, const double* dense, const int32_t* sigma,
+                          WPrec wp, void* W, hipStream_t s) {
   if (nb <= 0) return;
   switch (wp) {
     case WPrec::F64:
       hipLaunchKernelGGL((k_extract<double>), dim3((unsigned)nb), dim3(kThreads), 0, s, j0, B,
-                         dense_off, dense, (double*)W);
+                         dense_off, sigma_off, dense, sigma, (double*)W);
       break;
     case WPrec::F32:
       hipLaunchKernelGGL((k_extract<float>), dim3((unsigned)nb), dim3(kThreads), 0, s, j0, B,
-                         dense_off, dense, (float*)W);
+                         dense_off, sigma_off, dense, sigma, (float*)W);
       break;
     case WPrec::BF16:
       hipLaunchKernelGGL((k_extract<__hip_bfloat16>), dim3((unsigned)nb), dim3(kThreads), 0, s,
-                         j0, B, dense_off, dense, (__hip_bfloat16*)W);
+                         j0, B, dense_off, sigma_off, dense, sigma, (__hip_bfloat16*)W);
       break;
   }
 }

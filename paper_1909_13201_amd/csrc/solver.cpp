@@ -607,46 +607,64 @@ void factor_blocks(fsgmg_hierarchy& h, int l) {
   DLevel& d = h.dl[l];
   const int64_t nb = bs.nblk();
   if (nb == 0) return;
+  auto padded = [](int64_t n) { return (n + 15) & ~(int64_t)15; };
+  const int npm = (int)padded(d.bv.max_n);
+  int max_lds = 0;
+  HIPCHECK(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h.device));
+  // panel width 16: the np x 17 FP64 strip of a 363-unknown block takes 50 KB
+  // of LDS, three workgroups per CU (measured faster than 32-wide panels,
+  // which halve the passes over the matrix but leave one workgroup per CU)
+  if (invert_blocks_lds(npm) > (size_t)max_lds)
+    throw Fail{FSGMG_EINVAL, "Schwarz block of " + std::to_string(d.bv.max_n) +
+                                 " unknowns exceeds the LDS of one workgroup"};
   const size_t budget = (size_t)1 << 30;   // dense FP64 scratch per chunk
-  size_t maxchunk = 0;
+  size_t maxchunk = 0, maxsig = 0;
   std::vector<int64_t> starts(1, 0);
   {
-    size_t acc = 0;
+    size_t acc = 0, sacc = 0;
     for (int64_t j = 0; j < nb; ++j) {
-      const size_t n = (size_t)(bs.ptr[j + 1] - bs.ptr[j]);
-      if (acc > 0 && acc + n * n * 8 > budget) {
+      const size_t np = (size_t)padded(bs.ptr[j + 1] - bs.ptr[j]);
+      if (acc > 0 && acc + np * np * 8 > budget) {
         starts.push_back(j);
         maxchunk = std::max(maxchunk, acc);
-        acc = 0;
+        maxsig = std::max(maxsig, sacc);
+        acc = sacc = 0;
       }
-      acc += n * n * 8;
+      acc += np * np * 8;
+      sacc += np * 4;
     }
     maxchunk = std::max(maxchunk, acc);
+    maxsig = std::max(maxsig, sacc);
     starts.push_back(nb);
   }
   double* dense = (double*)h.dalloc(maxchunk);
-  int64_t* doff = (int64_t*)h.dalloc((size_t)(nb + 1) * sizeof(int64_t));
+  int32_t* sigma = (int32_t*)h.dalloc(maxsig);
+  int64_t* offs = (int64_t*)h.dalloc((size_t)2 * (nb + 1) * sizeof(int64_t));
   int32_t* status = h.zeros<int32_t>(nb);
   std::vector<int64_t> hoff;
   for (size_t c = 0; c + 1 < starts.size(); ++c) {
-    const int64_t j0 = starts[c], j1 = starts[c + 1];
-    hoff.assign(1, 0);
+    const int64_t j0 = starts[c], j1 = starts[c + 1], cnt = j1 - j0;
+    hoff.assign((size_t)2 * (cnt + 1), 0);
     for (int64_t j = j0; j < j1; ++j) {
-      const int64_t n = bs.ptr[j + 1] - bs.ptr[j];
-      hoff.push_back(hoff.back() + n * n);
+      const int64_t np = padded(bs.ptr[j + 1] - bs.ptr[j]);
+      hoff[j - j0 + 1] = hoff[j - j0] + np * np;
+      hoff[cnt + 1 + j - j0 + 1] = hoff[cnt + 1 + j - j0] + np;
     }
-    HIPCHECK(hipMemcpyAsync(doff, hoff.data(), hoff.size() * sizeof(int64_t), hipMemcpyHostToDevice,
+    HIPCHECK(hipMemcpyAsync(offs, hoff.data(), hoff.size() * sizeof(int64_t), hipMemcpyHostToDevice,
                             h.stream));
-    launch_gather_blocks(j0, j1 - j0, d.bv, d.rp, d.col, d.val, doff, dense, h.stream);
-    launch_invert_blocks(j0, j1 - j0, d.bv.dof_ptr, doff, dense, status, d.bv.max_n, h.stream);
-    launch_extract_owned(j0, j1 - j0, d.bv, doff, dense, wprec(h.sopt.prec), d.W, h.stream);
+    const int64_t* doff = offs;
+    const int64_t* soff = offs + cnt + 1;
+    launch_gather_blocks(j0, cnt, d.bv, d.rp, d.col, d.val, doff, dense, h.stream);
+    launch_invert_blocks(j0, cnt, d.bv.dof_ptr, doff, soff, dense, sigma, status, d.bv.max_n,
+                         h.stream);
+    launch_extract_owned(j0, cnt, d.bv, doff, soff, dense, sigma, wprec(h.sopt.prec), d.W, h.stream);
     HIPCHECK(hipGetLastError());
     HIPCHECK(hipStreamSynchronize(h.stream));
   }
   std::vector<int32_t> st(nb);
   HIPCHECK(hipMemcpy(st.data(), status, nb * sizeof(int32_t), hipMemcpyDeviceToHost));
   // scratch is released at once (bump allocations are freed in order)
-  for (void* p : {(void*)dense, (void*)doff, (void*)status}) {
+  for (void* p : {(void*)dense, (void*)sigma, (void*)offs, (void*)status}) {
     auto it = std::find(h.allocs.begin(), h.allocs.end(), p);
     if (it != h.allocs.end()) {
       (void)hipFree(p);
