@@ -36,7 +36,7 @@ WORKLOADS = {
           "seeded field of amplitude 1 with SUPG, FS-AS on 4x4-element cores with the "
           "one-element Vanka halo, 2+2 sweeps",
     "c1": "2D unit square, coarse 4x4 -> 8x8 (2 levels), solid bottom row, Stokes fluid",
-    "c3": "2D aneurysm-like channel with circular bulge, coarse 16x8 -> 512x256 (6 levels)",
+    "c3": "2D aneurysm-like channel with a smooth bulge of height 0.3 on the top wall, coarse 16x8 -> 512x256 (6 levels, 2,236,167 unknowns), 2-element walls, 4x4 interior and 4x12 interface cores",
 }
 
 

@@ -70,7 +70,8 @@ typedef struct {
   int nc[3];                   /* coarse elements per axis                */
   const double* breaks[3];     /* host, nc[a]+1 reference breakpoints     */
   const int8_t* region;        /* host, prod(nc) tags, x fastest          */
-  int mapping;                 /* 0 identity, 1 circular bulge (2D)       */
+  int mapping;                 /* 0 identity, 1 circular bulge, 2 smooth  *
+                                * cos^2 bulge tangent to the wall (2D)    */
   double map_params[8];        /* bulge: centre x, radius, blend y0, y1   */
   int8_t bc_d[6][2];
   int8_t bc_u[6][2];
@@ -98,7 +99,12 @@ typedef struct {
  * use_graph != 0 captures each FGMRES Arnoldi step (V-cycle, operator
  * product, Gram-Schmidt, Hessenberg read-back) and the V-cycle of
  * vcycle_apply as HIP graphs on first use; the graphs are rebuilt after the
- * next build_fs_as_blocks.  Graphs are bypassed while kernel_timing records. */
+ * next build_fs_as_blocks.  Graphs are bypassed while kernel_timing records.
+ * iface_mult (0 or 1 = off): for each region, a tile row of cores touching
+ * another region across a face normal to axis 1 absorbs the next
+ * iface_mult - 1 tile rows away from that interface, giving enlarged
+ * interface blocks (layered walls only: the regions must be constant along
+ * the other axes, else FSGMG_EINVAL). */
 typedef struct {
   int core[3];
   int halo;
@@ -106,6 +112,7 @@ typedef struct {
   double omega;
   fsgmg_prec prec;
   int use_graph;
+  int iface_mult;
 } fsgmg_smoother_opts;
 
 /* FGMRES(restart), right preconditioned, x0 = 0, CGS2; converged when the

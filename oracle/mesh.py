@@ -57,6 +57,18 @@ def physical_map(cfg: dict, xref: np.ndarray) -> np.ndarray:
         s = np.clip((xref[:, 1] - ya) / (yb - ya), 0.0, 1.0)
         x[:, 1] = xref[:, 1] + bump * s
         return x
+    if cfg["mapping"] == 2:
+        # smooth bulge of height and half-width R centred at xc: the profile
+        # R cos^2(pi (x - xc) / (2R)) is tangent to the straight wall at
+        # |x - xc| = R, so the shear of the mapped elements is bounded under
+        # refinement (the circular profile meets the wall vertically and
+        # shears the elements there without bound); same blending as above
+        xc, R, ya, yb = cfg["map_params"]
+        dx = xref[:, 0] - xc
+        bump = np.where(np.abs(dx) < R, R * np.cos(np.pi * dx / (2.0 * R)) ** 2, 0.0)
+        s = np.clip((xref[:, 1] - ya) / (yb - ya), 0.0, 1.0)
+        x[:, 1] = xref[:, 1] + bump * s
+        return x
     raise ValueError("unknown mapping %r" % cfg["mapping"])
 
 

@@ -49,12 +49,13 @@ class Hierarchy:
     def finest(self) -> Level:
         return self.levels[-1]
 
-    def build_smoothers(self, core=None, halo=None):
+    def build_smoothers(self, core=None, halo=None, iface_mult=None):
         cfg = self.cfg
         core = tuple(cfg["core"]) if core is None else tuple(core)
         halo = int(cfg["halo"]) if halo is None else int(halo)
+        mult = int(cfg.get("iface_mult", 1)) if iface_mult is None else int(iface_mult)
         for l in range(1, self.L):
-            blocks, _ = build_blocks(self.levels[l], core, halo)
+            blocks, _ = build_blocks(self.levels[l], core, halo, mult)
             self.smoothers[l] = FieldSplitSchwarz(self.A[l], blocks)
 
     def rhs(self, fnodal: np.ndarray) -> np.ndarray:

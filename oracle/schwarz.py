@@ -32,6 +32,16 @@ contains it, i.e. owner(i) = max{j : i in I_j}.  Unknowns in no block (u^s and
 Dirichlet rows, whose rows are identity) get one Jacobi step r_i / A_ii.
 Blocks are ordered field d before field u, tiles lexicographically (x
 fastest), solid before fluid inside a tile.
+
+Enlarged interface cores (``iface_mult`` = m > 1; a reading of the
+configuration that asks for interface blocks about three times the interior
+ones, not a rule of the paper): for each region, a tile row whose region
+elements touch another region across a face normal to axis 1 takes over the
+next m - 1 tile rows on the side away from that interface (rows that touch an
+interface themselves are never taken over; a row touching interfaces on both
+sides is not enlarged).  The enlarged core is emitted in the place of the
+interface tile and the tiles it took over are not emitted.  Requires regions
+that are constant along the other axes (layered walls).
 """
 from __future__ import annotations
 
@@ -43,7 +53,47 @@ from scipy import ndimage
 from .mesh import Level
 
 
-def build_blocks(lv: Level, core, halo: int):
+def interface_row_groups(lv: Level, core, region: int, iface_mult: int):
+    """For each tile row (axis 1) the (first, last) tile rows of its core, or
+    None when another row's enlarged core took it over."""
+    nt1 = -(-lv.ne[1] // core[1])
+    groups = [(t, t) for t in range(nt1)]
+    if iface_mult <= 1:
+        return groups
+    reg = lv.region.reshape(lv.ne[::-1])             # [z][y][x]
+    rows = np.moveaxis(reg, -2, 0).reshape(lv.ne[1], -1)
+    if not np.all(rows == rows[:, :1]):
+        raise ValueError("enlarged interface cores need regions constant along x (and z)")
+    rr = rows[:, 0]
+    ny = lv.ne[1]
+
+    def flags(t):
+        ys = range(t * core[1], min((t + 1) * core[1], ny))
+        has = any(rr[y] == region for y in ys)
+        below = any(rr[y] == region and y > 0 and rr[y - 1] != region for y in ys)
+        above = any(rr[y] == region and y + 1 < ny and rr[y + 1] != region for y in ys)
+        return has, below, above
+
+    fl = [flags(t) for t in range(nt1)]
+    taken = [False] * nt1
+    for t in range(nt1):
+        has, below, above = fl[t]
+        if not has or below == above or taken[t]:
+            continue
+        step = 1 if below else -1
+        lo = hi = t
+        for k in range(1, iface_mult):
+            u = t + step * k
+            if not (0 <= u < nt1) or taken[u] or not fl[u][0] or fl[u][1] or fl[u][2]:
+                break
+            taken[u] = True
+            groups[u] = None
+            lo, hi = min(lo, u), max(hi, u)
+        groups[t] = (lo, hi)
+    return groups
+
+
+def build_blocks(lv: Level, core, halo: int, iface_mult: int = 1):
     """Return (blocks, kinds): blocks is a list of sorted global index arrays;
     kinds[j] = (field, region) with field 0 = [d,p^s], 1 = [u,p^f]."""
     D = lv.D
@@ -52,13 +102,19 @@ def build_blocks(lv: Level, core, halo: int):
     nt = [-(-ne[a] // core[a]) for a in range(D)]
     tiles = Level._x_fastest(tuple(nt))
     struct = np.ones((3,) * D, bool)
+    groups = {r: interface_row_groups(lv, core, r, iface_mult) for r in (0, 1)}
     blocks, kinds = [], []
     for field in (0, 1):
         for t in tiles:
             for region in ((1, 0) if field == 0 else (0,)):
+                g = groups[region][t[1]]
+                if g is None:
+                    continue
+                lo = [t[a] * core[a] for a in range(D)]
+                hi = [min((t[a] + 1) * core[a], ne[a]) for a in range(D)]
+                lo[1], hi[1] = g[0] * core[1], min((g[1] + 1) * core[1], ne[1])
                 box = np.zeros(ne[::-1], bool)
-                sl = tuple(slice(t[a] * core[a], min((t[a] + 1) * core[a], ne[a]))
-                           for a in reversed(range(D)))
+                sl = tuple(slice(lo[a], hi[a]) for a in reversed(range(D)))
                 box[sl] = True
                 core_mask = box & (reg == region)
                 if not core_mask.any():

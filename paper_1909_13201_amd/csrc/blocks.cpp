@@ -13,6 +13,13 @@
 // Dirichlet unknowns belong to no block.  Order: field d then field u, tiles
 // x-fastest, solid before fluid within a tile.  owner(i) = last block that
 // contains i (the additive update takes entry i from the last block).
+//
+// Enlarged interface cores (iface_mult = m > 1, layered walls): per region, a
+// tile row whose region elements touch another region across a face normal
+// to axis 1 takes over the next m - 1 tile rows on the side away from the
+// interface (never a row that touches an interface itself; a row touching
+// interfaces on both sides keeps its size).  The enlarged core is emitted in
+// the place of the interface tile; the rows taken over emit nothing.
 #include <algorithm>
 #include <stdexcept>
 
@@ -20,7 +27,59 @@
 
 namespace fsgmg {
 
-void build_blocks(const Level& lv, const int* core, int halo, BlockSet& bs) {
+namespace {
+
+// first / last tile row (axis 1) of the core of each tile row, {-1, -1} for
+// rows taken over by an enlarged interface core
+std::vector<std::pair<int, int>> row_groups(const Level& lv, const int* core, int region,
+                                            int mult) {
+  const int ny = lv.ne[1];
+  const int nt1 = (ny + core[1] - 1) / core[1];
+  std::vector<std::pair<int, int>> g(nt1);
+  for (int t = 0; t < nt1; ++t) g[t] = {t, t};
+  if (mult <= 1) return g;
+  // region of each element row (must not vary along x, or z in 3D)
+  std::vector<int8_t> rr(ny, -1);
+  for (int64_t e = 0; e < lv.nE; ++e) {
+    const int y = (int)((e / lv.ne[0]) % ny);
+    if (rr[y] < 0)
+      rr[y] = lv.region[e];
+    else if (rr[y] != lv.region[e])
+      throw std::invalid_argument("enlarged interface cores need regions constant along x (and z)");
+  }
+  struct Flags { bool has, below, above; };
+  std::vector<Flags> fl(nt1);
+  for (int t = 0; t < nt1; ++t) {
+    Flags f{false, false, false};
+    for (int y = t * core[1]; y < std::min((t + 1) * core[1], ny); ++y) {
+      if (rr[y] != region) continue;
+      f.has = true;
+      if (y > 0 && rr[y - 1] != region) f.below = true;
+      if (y + 1 < ny && rr[y + 1] != region) f.above = true;
+    }
+    fl[t] = f;
+  }
+  std::vector<char> taken(nt1, 0);
+  for (int t = 0; t < nt1; ++t) {
+    if (!fl[t].has || fl[t].below == fl[t].above || taken[t]) continue;
+    const int step = fl[t].below ? 1 : -1;
+    int lo = t, hi = t;
+    for (int k = 1; k < mult; ++k) {
+      const int u = t + step * k;
+      if (u < 0 || u >= nt1 || taken[u] || !fl[u].has || fl[u].below || fl[u].above) break;
+      taken[u] = 1;
+      g[u] = {-1, -1};
+      lo = std::min(lo, u);
+      hi = std::max(hi, u);
+    }
+    g[t] = {lo, hi};
+  }
+  return g;
+}
+
+}  // namespace
+
+void build_blocks(const Level& lv, const int* core, int halo, int iface_mult, BlockSet& bs) {
   const int D = lv.D;
   int nt[kMaxDim] = {1, 1, 1};
   int64_t ntiles = 1;
@@ -29,6 +88,8 @@ void build_blocks(const Level& lv, const int* core, int halo, BlockSet& bs) {
     nt[a] = (lv.ne[a] + core[a] - 1) / core[a];
     ntiles *= nt[a];
   }
+  const std::vector<std::pair<int, int>> groups[2] = {row_groups(lv, core, 0, iface_mult),
+                                                      row_groups(lv, core, 1, iface_mult)};
   bs.ptr.assign(1, 0);
   bs.dofs.clear();
   std::vector<int32_t> stamp_el(lv.nE, -1), stamp_node(lv.N2, -1), stamp_vert(lv.NV, -1);
@@ -45,12 +106,16 @@ void build_blocks(const Level& lv, const int* core, int halo, BlockSet& bs) {
       const int regions[2] = {1, 0};
       for (int ri = (field == 0 ? 0 : 1); ri < 2; ++ri) {
         const int region = regions[ri];
+        const std::pair<int, int> g = groups[region][tx[1]];
+        if (g.first < 0) continue;
         core_el.clear();
         int lo[kMaxDim] = {0, 0, 0}, hi[kMaxDim] = {1, 1, 1};
         for (int a = 0; a < D; ++a) {
           lo[a] = tx[a] * core[a];
           hi[a] = std::min(lo[a] + core[a], lv.ne[a]);
         }
+        lo[1] = g.first * core[1];
+        hi[1] = std::min((g.second + 1) * core[1], lv.ne[1]);
         for (int z = lo[2]; z < (D > 2 ? hi[2] : 1); ++z)
           for (int y = lo[1]; y < hi[1]; ++y)
             for (int x = lo[0]; x < hi[0]; ++x) {

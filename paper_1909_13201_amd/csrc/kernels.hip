@@ -86,7 +86,25 @@ __global__ __launch_bounds__(kThreads) void k_spmv(BOpView<T> A, const T* __rest
 #pragma unroll
     for (int r = 0; r < D; ++r) acc[r] = T(0);
     const int k1 = A.nn_ptr[item + 1];
-    for (int k = A.nn_ptr[item] + lane; k < k1; k += LG) {
+    int k = A.nn_ptr[item] + lane;
+    // two blocks per lane per trip: both column indices, then both x
+    // gathers, are in flight together
+    for (; k + LG < k1; k += 2 * LG) {
+      const int c0 = A.nn_col[k], c1 = A.nn_col[k + LG];
+      T v0[D * D], v1[D * D], x0[D], x1[D];
+      load_block<T, D>(A.nn_val + (int64_t)k * (D * D), v0);
+      load_block<T, D>(A.nn_val + (int64_t)(k + LG) * (D * D), v1);
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        x0[q] = x[c0 + q];
+        x1[q] = x[c1 + q];
+      }
+#pragma unroll
+      for (int r = 0; r < D; ++r)
+#pragma unroll
+        for (int q = 0; q < D; ++q) acc[r] += v0[r * D + q] * x0[q] + v1[r * D + q] * x1[q];
+    }
+    if (k < k1) {
       const int c = A.nn_col[k];
       T v[D * D], xv[D];
       load_block<T, D>(A.nn_val + (int64_t)k * (D * D), v);
@@ -370,10 +388,9 @@ __global__ __launch_bounds__(kSmoothMaxThreads) void k_smooth_fwd(BlocksView B, 
   constexpr int RV = WTraits<TW>::RV;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   TA* smem = reinterpret_cast<TA*>(smem_raw);
-  const int64_t j = blockIdx.x;
   const int tid = threadIdx.x;
-  if (j >= B.nblk) {
-    const int64_t q = (j - B.nblk) * blockDim.x + tid;
+  if (blockIdx.x >= B.nblk) {
+    const int64_t q = (blockIdx.x - B.nblk) * blockDim.x + tid;
     if (q < B.njac) {
       const int32_t gi = B.jac[q];
       const TV jv = reinterpret_cast<const TV*>(B.jac_inv)[q];
@@ -381,6 +398,7 @@ __global__ __launch_bounds__(kSmoothMaxThreads) void k_smooth_fwd(BlocksView B, 
     }
     return;
   }
+  const int64_t j = B.order[blockIdx.x];
   const int64_t d0 = B.dof_ptr[j];
   const int n = (int)(B.dof_ptr[j + 1] - d0);
   const int o0 = B.own_ptr[j];
@@ -444,7 +462,7 @@ __global__ __launch_bounds__(kThreads) void k_smooth_t1(BlocksView B, const TW* 
   constexpr int RV = WTraits<TW>::RV;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   TA* so = reinterpret_cast<TA*>(smem_raw);
-  const int64_t j = blockIdx.x;
+  const int64_t j = B.order[blockIdx.x];
   const int tid = threadIdx.x;
   const int64_t d0 = B.dof_ptr[j];
   const int n = (int)(B.dof_ptr[j + 1] - d0);
@@ -499,13 +517,14 @@ __global__ __launch_bounds__(kThreads) void k_smooth_t2(BlocksView B, const TV* 
 // in the leading n x n corner.
 __device__ inline int pad16(int n) { return (n + 15) & ~15; }
 
-__global__ __launch_bounds__(kThreads) void k_gather_blocks(int64_t j0, BlocksView B,
+__global__ __launch_bounds__(kThreads) void k_gather_blocks(const int32_t* __restrict__ jlist,
+                                                            BlocksView B,
                                                             const int64_t* __restrict__ rp,
                                                             const int32_t* __restrict__ col,
                                                             const double* __restrict__ val,
                                                             const int64_t* __restrict__ doff,
                                                             double* __restrict__ dense) {
-  const int64_t j = j0 + blockIdx.x;
+  const int64_t j = jlist[blockIdx.x];
   const int64_t d0 = B.dof_ptr[j];
   const int n = (int)(B.dof_ptr[j + 1] - d0);
   const int np = pad16(n);
@@ -558,14 +577,14 @@ constexpr int kPanel = 16;
 
 template <int NB>
 __global__ __launch_bounds__(kThreads) void k_invert_blocked(
-    int64_t j0, const int64_t* __restrict__ dof_ptr, const int64_t* __restrict__ doff,
-    const int64_t* __restrict__ soff, double* __restrict__ dense, int32_t* __restrict__ sigma_all,
-    int32_t* __restrict__ status) {
+    const int32_t* __restrict__ jlist, const int64_t* __restrict__ dof_ptr,
+    const int64_t* __restrict__ doff, const int64_t* __restrict__ soff, double* __restrict__ dense,
+    int32_t* __restrict__ sigma_all, int32_t* __restrict__ status) {
   static_assert(NB % 16 == 0, "panel width must be a multiple of the tile");
   constexpr int LDT = NB + 1;   // LDS row stride (doubles) of the strip
   constexpr int NW = kThreads / 64;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int64_t j = j0 + blockIdx.x;
+  const int64_t j = jlist[blockIdx.x];
   const int n = (int)(dof_ptr[j + 1] - dof_ptr[j]);
   const int np = pad16(n);
   double* a = dense + doff[blockIdx.x];
@@ -714,13 +733,14 @@ template <>
 __device__ inline __hip_bfloat16 to_w<__hip_bfloat16>(double v) { return __float2bfloat16((float)v); }
 
 template <typename TW>
-__global__ __launch_bounds__(kThreads) void k_extract(int64_t j0, BlocksView B,
+__global__ __launch_bounds__(kThreads) void k_extract(const int32_t* __restrict__ jlist,
+                                                      BlocksView B,
                                                       const int64_t* __restrict__ doff,
                                                       const int64_t* __restrict__ soff,
                                                       const double* __restrict__ dense,
                                                       const int32_t* __restrict__ sigma_all,
                                                       TW* __restrict__ W) {
-  const int64_t j = j0 + blockIdx.x;
+  const int64_t j = jlist[blockIdx.x];
   const int n = (int)(B.dof_ptr[j + 1] - B.dof_ptr[j]);
   const int np = pad16(n);
   const int o0 = B.own_ptr[j];
@@ -1182,11 +1202,11 @@ template void launch_smooth<double>(const BlocksView&, WPrec, const void*, const
 template void launch_smooth<float>(const BlocksView&, WPrec, const void*, const float*, float*,
                                    float*, double, bool, bool, int64_t, hipStream_t, int);
 
-void launch_gather_blocks(int64_t j0, int64_t nb, const BlocksView& B, const int64_t* rowptr,
-                          const int32_t* col, const double* val, const int64_t* dense_off,
-                          double* dense, hipStream_t s) {
+void launch_gather_blocks(const int32_t* jlist, int64_t nb, const BlocksView& B,
+                          const int64_t* rowptr, const int32_t* col, const double* val,
+                          const int64_t* dense_off, double* dense, hipStream_t s) {
   if (nb > 0)
-    hipLaunchKernelGGL(k_gather_blocks, dim3((unsigned)nb), dim3(kThreads), 0, s, j0, B, rowptr,
+    hipLaunchKernelGGL(k_gather_blocks, dim3((unsigned)nb), dim3(kThreads), 0, s, jlist, B, rowptr,
                        col, val, dense_off, dense);
 }
 
@@ -1195,31 +1215,31 @@ size_t invert_blocks_lds(int np_max) {
          (size_t)np_max * 8;
 }
 
-void launch_invert_blocks(int64_t j0, int64_t nb, const int64_t* dof_ptr, const int64_t* dense_off,
-                          const int64_t* sigma_off, double* dense, int32_t* sigma,
-                          int32_t* status, int max_n, hipStream_t s) {
+void launch_invert_blocks(const int32_t* jlist, int64_t nb, const int64_t* dof_ptr,
+                          const int64_t* dense_off, const int64_t* sigma_off, double* dense,
+                          int32_t* sigma, int32_t* status, int max_n, hipStream_t s) {
   if (nb <= 0) return;
   const size_t sm = invert_blocks_lds((max_n + 15) & ~15);
-  hipLaunchKernelGGL((k_invert_blocked<kPanel>), dim3((unsigned)nb), dim3(kThreads), sm, s, j0,
+  hipLaunchKernelGGL((k_invert_blocked<kPanel>), dim3((unsigned)nb), dim3(kThreads), sm, s, jlist,
                      dof_ptr, dense_off, sigma_off, dense, sigma, status);
 }
 
-void launch_extract_owned(int64_t j0, int64_t nb, const BlocksView& B, const int64_t* dense_off,
-                          const int64_t* sigma_off, const double* dense, const int32_t* sigma,
-                          WPrec wp, void* W, hipStream_t s) {
+void launch_extract_owned(const int32_t* jlist, int64_t nb, const BlocksView& B,
+                          const int64_t* dense_off, const int64_t* sigma_off, const double* dense,
+                          const int32_t* sigma, WPrec wp, void* W, hipStream_t s) {
   if (nb <= 0) return;
   switch (wp) {
     case WPrec::F64:
-      hipLaunchKernelGGL((k_extract<double>), dim3((unsigned)nb), dim3(kThreads), 0, s, j0, B,
+      hipLaunchKernelGGL((k_extract<double>), dim3((unsigned)nb), dim3(kThreads), 0, s, jlist, B,
                          dense_off, sigma_off, dense, sigma, (double*)W);
       break;
     case WPrec::F32:
-      hipLaunchKernelGGL((k_extract<float>), dim3((unsigned)nb), dim3(kThreads), 0, s, j0, B,
+      hipLaunchKernelGGL((k_extract<float>), dim3((unsigned)nb), dim3(kThreads), 0, s, jlist, B,
                          dense_off, sigma_off, dense, sigma, (float*)W);
       break;
     case WPrec::BF16:
       hipLaunchKernelGGL((k_extract<__hip_bfloat16>), dim3((unsigned)nb), dim3(kThreads), 0, s,
-                         j0, B, dense_off, sigma_off, dense, sigma, (__hip_bfloat16*)W);
+                         jlist, B, dense_off, sigma_off, dense, sigma, (__hip_bfloat16*)W);
       break;
   }
 }

@@ -78,6 +78,10 @@ struct BlocksView {
   // transposed apply: DOF -> positions in the per-block output buffer
   const int32_t* tpos_ptr;  // N + 1
   const int32_t* tpos;
+  // launch order of the sweeps: workgroup b works on block order[b]; the
+  // blocks are sorted by decreasing inverse size so that the largest start
+  // first (longest-processing-time-first over the CUs)
+  const int32_t* order;
 };
 
 enum class WPrec { F64 = 0, F32 = 1, BF16 = 2 };
@@ -107,24 +111,26 @@ void launch_smooth(const BlocksView& B, WPrec wp, const void* W, const TV* r, TV
                    int threads = 0);
 
 // ---- block setup ----
-// Dense copies of the blocks' principal submatrices, row stride
-// np = n rounded up to 16, identity in the padding; dense_off[b] = element
-// offset of block j0 + b.
-void launch_gather_blocks(int64_t j0, int64_t nb, const BlocksView& B, const int64_t* rowptr,
-                          const int32_t* col, const double* val, const int64_t* dense_off,
-                          double* dense, hipStream_t s);
-// Blocked in-place Gauss-Jordan inversion with partial pivoting of nb padded
+// Block setup over a list of block ids (jlist[b], b < nb; launch b of the
+// list works on block jlist[b]).  Dense copies of the blocks' principal
+// submatrices, row stride np = n rounded up to 16, identity in the padding;
+// dense_off[b] = element offset of list entry b.
+void launch_gather_blocks(const int32_t* jlist, int64_t nb, const BlocksView& B,
+                          const int64_t* rowptr, const int32_t* col, const double* val,
+                          const int64_t* dense_off, double* dense, hipStream_t s);
+// Blocked in-place Gauss-Jordan inversion with partial pivoting of the padded
 // dense blocks (16-column panels, FP64 MFMA trailing updates);
 // sigma[sigma_off[b] + q] receives the column permutation that completes the
-// inverse; status[j] = 1 on a zero pivot.  invert_blocks_lds: the LDS bytes
-// one workgroup needs for blocks of padded size np_max.
+// inverse; status[j] = 1 on a zero pivot.  max_n bounds the listed blocks'
+// sizes (it sizes the LDS); invert_blocks_lds: the LDS bytes one workgroup
+// needs for blocks of padded size np_max.
 size_t invert_blocks_lds(int np_max);
-void launch_invert_blocks(int64_t j0, int64_t nb, const int64_t* dof_ptr, const int64_t* dense_off,
-                          const int64_t* sigma_off, double* dense, int32_t* sigma,
-                          int32_t* status, int max_n, hipStream_t s);
-void launch_extract_owned(int64_t j0, int64_t nb, const BlocksView& B, const int64_t* dense_off,
-                          const int64_t* sigma_off, const double* dense, const int32_t* sigma,
-                          WPrec wp, void* W, hipStream_t s);
+void launch_invert_blocks(const int32_t* jlist, int64_t nb, const int64_t* dof_ptr,
+                          const int64_t* dense_off, const int64_t* sigma_off, double* dense,
+                          int32_t* sigma, int32_t* status, int max_n, hipStream_t s);
+void launch_extract_owned(const int32_t* jlist, int64_t nb, const BlocksView& B,
+                          const int64_t* dense_off, const int64_t* sigma_off, const double* dense,
+                          const int32_t* sigma, WPrec wp, void* W, hipStream_t s);
 
 // In-place inversion of one dense n x n FP64 matrix by Gauss-Jordan with
 // partial pivoting spread over the whole GPU (one pivot kernel and one

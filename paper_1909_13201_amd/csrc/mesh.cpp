@@ -67,6 +67,19 @@ static void map_point(const fsgmg_mesh_desc& m, const double* xr, double* x) {
     x[1] = xr[1] + bump * s;
     return;
   }
+  if (m.mapping == 2) {
+    // smooth bulge R cos^2(pi dx / (2R)), tangent to the straight wall at
+    // |dx| = R (bounded element shear under refinement)
+    const double xc = m.map_params[0], R = m.map_params[1];
+    const double ya = m.map_params[2], yb = m.map_params[3];
+    const double dx = xr[0] - xc;
+    const double c = std::cos(M_PI * dx / (2.0 * R));
+    const double bump = std::fabs(dx) < R ? R * c * c : 0.0;
+    double s = (xr[1] - ya) / (yb - ya);
+    s = std::min(1.0, std::max(0.0, s));
+    x[1] = xr[1] + bump * s;
+    return;
+  }
   throw std::invalid_argument("unknown mapping");
 }
 

@@ -593,6 +593,14 @@ void upload_blocks(fsgmg_hierarchy& h, int l) {
   v.max_mpad = max_mpad;
   v.tpos_ptr = h.upload(tcnt);
   v.tpos = h.upload(tpos);
+  {
+    std::vector<int32_t> order(nb);
+    for (int64_t j = 0; j < nb; ++j) order[j] = (int32_t)j;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+      return w_off[a + 1] - w_off[a] > w_off[b + 1] - w_off[b];
+    });
+    v.order = h.upload(order);
+  }
   d.W_elems = w_off[nb];
   d.W = h.dalloc((size_t)d.W_elems * w_bytes(h.sopt.prec) + 64);
   const int64_t ntot = (int64_t)bs.dofs.size();
@@ -608,63 +616,82 @@ void factor_blocks(fsgmg_hierarchy& h, int l) {
   const int64_t nb = bs.nblk();
   if (nb == 0) return;
   auto padded = [](int64_t n) { return (n + 15) & ~(int64_t)15; };
-  const int npm = (int)padded(d.bv.max_n);
   int max_lds = 0;
   HIPCHECK(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h.device));
-  // panel width 16: the np x 17 FP64 strip of a 363-unknown block takes 50 KB
-  // of LDS, three workgroups per CU (measured faster than 32-wide panels,
-  // which halve the passes over the matrix but leave one workgroup per CU)
-  if (invert_blocks_lds(npm) > (size_t)max_lds)
+  if (invert_blocks_lds((int)padded(d.bv.max_n)) > (size_t)max_lds)
     throw Fail{FSGMG_EINVAL, "Schwarz block of " + std::to_string(d.bv.max_n) +
                                  " unknowns exceeds the LDS of one workgroup"};
-  const size_t budget = (size_t)1 << 30;   // dense FP64 scratch per chunk
+  // Size buckets: the LDS of a launch is set by its largest block, so blocks
+  // that fit three workgroups per CU (np <= 384: 55 KB) are factored apart
+  // from larger ones (enlarged interface blocks).  Inside a bucket, chunks
+  // of at most 1 GiB of dense FP64 scratch, larger blocks first.
+  constexpr int64_t kSmallNp = 384;
+  std::vector<int32_t> order(nb);
+  for (int64_t j = 0; j < nb; ++j) order[j] = (int32_t)j;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    return bs.ptr[a + 1] - bs.ptr[a] > bs.ptr[b + 1] - bs.ptr[b];
+  });
+  struct Chunk { int64_t b0, b1; int max_n; };
+  std::vector<Chunk> chunks;
+  const size_t budget = (size_t)1 << 30;
   size_t maxchunk = 0, maxsig = 0;
-  std::vector<int64_t> starts(1, 0);
   {
     size_t acc = 0, sacc = 0;
-    for (int64_t j = 0; j < nb; ++j) {
-      const size_t np = (size_t)padded(bs.ptr[j + 1] - bs.ptr[j]);
-      if (acc > 0 && acc + np * np * 8 > budget) {
-        starts.push_back(j);
+    int64_t b0 = 0;
+    bool big = true;
+    for (int64_t b = 0; b < nb; ++b) {
+      const int64_t n = bs.ptr[order[b] + 1] - bs.ptr[order[b]];
+      const int64_t np = padded(n);
+      const bool isbig = np > kSmallNp;
+      if (b > b0 && (acc + (size_t)(np * np * 8) > budget || isbig != big)) {
+        chunks.push_back({b0, b, (int)(bs.ptr[order[b0] + 1] - bs.ptr[order[b0]])});
         maxchunk = std::max(maxchunk, acc);
         maxsig = std::max(maxsig, sacc);
         acc = sacc = 0;
+        b0 = b;
       }
-      acc += np * np * 8;
-      sacc += np * 4;
+      big = isbig;
+      acc += (size_t)(np * np * 8);
+      sacc += (size_t)np * 4;
     }
+    chunks.push_back({b0, nb, (int)(bs.ptr[order[b0] + 1] - bs.ptr[order[b0]])});
     maxchunk = std::max(maxchunk, acc);
     maxsig = std::max(maxsig, sacc);
-    starts.push_back(nb);
   }
   double* dense = (double*)h.dalloc(maxchunk);
   int32_t* sigma = (int32_t*)h.dalloc(maxsig);
+  int32_t* jlist = (int32_t*)h.dalloc((size_t)nb * sizeof(int32_t));
   int64_t* offs = (int64_t*)h.dalloc((size_t)2 * (nb + 1) * sizeof(int64_t));
   int32_t* status = h.zeros<int32_t>(nb);
+  HIPCHECK(hipMemcpyAsync(jlist, order.data(), (size_t)nb * sizeof(int32_t), hipMemcpyHostToDevice,
+                          h.stream));
   std::vector<int64_t> hoff;
-  for (size_t c = 0; c + 1 < starts.size(); ++c) {
-    const int64_t j0 = starts[c], j1 = starts[c + 1], cnt = j1 - j0;
+  for (const Chunk& c : chunks) {
+    const int64_t cnt = c.b1 - c.b0;
     hoff.assign((size_t)2 * (cnt + 1), 0);
-    for (int64_t j = j0; j < j1; ++j) {
+    for (int64_t b = 0; b < cnt; ++b) {
+      const int32_t j = order[c.b0 + b];
       const int64_t np = padded(bs.ptr[j + 1] - bs.ptr[j]);
-      hoff[j - j0 + 1] = hoff[j - j0] + np * np;
-      hoff[cnt + 1 + j - j0 + 1] = hoff[cnt + 1 + j - j0] + np;
+      hoff[b + 1] = hoff[b] + np * np;
+      hoff[cnt + 1 + b + 1] = hoff[cnt + 1 + b] + np;
     }
     HIPCHECK(hipMemcpyAsync(offs, hoff.data(), hoff.size() * sizeof(int64_t), hipMemcpyHostToDevice,
                             h.stream));
+    const int32_t* jl = jlist + c.b0;
     const int64_t* doff = offs;
     const int64_t* soff = offs + cnt + 1;
-    launch_gather_blocks(j0, cnt, d.bv, d.rp, d.col, d.val, doff, dense, h.stream);
-    launch_invert_blocks(j0, cnt, d.bv.dof_ptr, doff, soff, dense, sigma, status, d.bv.max_n,
+    launch_gather_blocks(jl, cnt, d.bv, d.rp, d.col, d.val, doff, dense, h.stream);
+    launch_invert_blocks(jl, cnt, d.bv.dof_ptr, doff, soff, dense, sigma, status, c.max_n,
                          h.stream);
-    launch_extract_owned(j0, cnt, d.bv, doff, soff, dense, sigma, wprec(h.sopt.prec), d.W, h.stream);
+    launch_extract_owned(jl, cnt, d.bv, doff, soff, dense, sigma, wprec(h.sopt.prec), d.W, h.stream);
     HIPCHECK(hipGetLastError());
+    // the offsets are rewritten for the next chunk
     HIPCHECK(hipStreamSynchronize(h.stream));
   }
   std::vector<int32_t> st(nb);
   HIPCHECK(hipMemcpy(st.data(), status, nb * sizeof(int32_t), hipMemcpyDeviceToHost));
   // scratch is released at once (bump allocations are freed in order)
-  for (void* p : {(void*)dense, (void*)sigma, (void*)offs, (void*)status}) {
+  for (void* p : {(void*)dense, (void*)sigma, (void*)jlist, (void*)offs, (void*)status}) {
     auto it = std::find(h.allocs.begin(), h.allocs.end(), p);
     if (it != h.allocs.end()) {
       (void)hipFree(p);
@@ -1160,14 +1187,23 @@ fsgmg_status build_fs_as_blocks(fsgmg_h h, const fsgmg_smoother_opts* opts) {
     for (int a = 0; a < h->D; ++a)
       if (opts->core[a] < 1) throw Fail{FSGMG_EINVAL, "core sizes must be >= 1"};
     if (opts->prec < FSGMG_FP64 || opts->prec > FSGMG_BF16) throw Fail{FSGMG_EINVAL, "bad precision"};
+    if (opts->iface_mult < 0) throw Fail{FSGMG_EINVAL, "iface_mult must be >= 0"};
+    const int mult = std::max(1, opts->iface_mult);
     const bool same_sets = h->have_blocks && h->sopt.halo == opts->halo &&
                            h->sopt.core[0] == opts->core[0] && h->sopt.core[1] == opts->core[1] &&
-                           h->sopt.prec == opts->prec;
+                           h->sopt.core[2] == opts->core[2] &&
+                           std::max(1, h->sopt.iface_mult) == mult && h->sopt.prec == opts->prec;
     h->sopt = *opts;
     h->factors_valid = false;
     h->invalidate_graphs();
     if (!same_sets) {
-      for (int l = 1; l < h->L; ++l) build_blocks(h->levels[l], opts->core, opts->halo, h->blocks[l]);
+      try {
+        for (int l = 1; l < h->L; ++l)
+          build_blocks(h->levels[l], opts->core, opts->halo, mult, h->blocks[l]);
+      } catch (const std::invalid_argument& e) {
+        h->have_blocks = false;
+        throw Fail{FSGMG_EINVAL, e.what()};
+      }
       h->have_blocks = true;
       if (!h->host_only())
         for (int l = 1; l < h->L; ++l) upload_blocks(*h, l);

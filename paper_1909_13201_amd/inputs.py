@@ -17,8 +17,9 @@ not public; Section 4 of the paper):
   and bottom are solid, E=1e4, nu=0.45), 5 levels (finest 128x128), fluid
   mu=3.5e-3, Oseen about a seeded smooth field of amplitude 1, SUPG on,
   4x4-element subdomains.
-* ``c3``  2D aneurysm-like channel with a circular bulge (radius 0.3) on the
-  top wall, coarse 16x8, 6 levels (finest 512x256), 2-element-thick walls.
+* ``c3``  2D aneurysm-like channel with a bulge of height and half-width 0.3
+  on the top wall (smooth cos^2 profile tangent to the wall), coarse 16x8,
+  6 levels (finest 512x256), 2-element-thick walls, interface cores 4 x 12.
 * ``c5``  c2 at 4 levels (finest 64x64), one backward-Euler step dt = 1/32,
   with 32 seeded (load, E, mu) samples.
 
@@ -40,7 +41,7 @@ import copy
 import numpy as np
 
 FACE_XMIN, FACE_XMAX, FACE_YMIN, FACE_YMAX, FACE_ZMIN, FACE_ZMAX = range(6)
-MAP_IDENTITY, MAP_BULGE = 0, 1
+MAP_IDENTITY, MAP_BULGE, MAP_SMOOTH_BULGE = 0, 1, 2
 
 
 def _uniform(n, lo=0.0, hi=1.0):
@@ -106,13 +107,20 @@ def config(name: str) -> dict:
         region[0:2, :] = 1
         region[6:8, :] = 1
         cfg = dict(dim=2, n_levels=6, nc=(16, 8), breaks=(_uniform(16, 0.0, 2.0), yb),
-                   region=region.ravel(), mapping=MAP_BULGE,
+                   # bulge of height / half-width 0.3 with a profile tangent to
+                   # the straight wall (the circular one, MAP_BULGE, meets the
+                   # wall vertically and its elements shear without bound
+                   # under refinement)
+                   region=region.ravel(), mapping=MAP_SMOOTH_BULGE,
                    # bulge centre x, radius, blend start y, blend end y
                    map_params=[1.0, 0.3, 0.5, 0.9],
                    bc_d=bc_d, bc_u=bc_u, inflow_peak=1.0,
                    E=1e4, nu=0.45, mu=3.5e-3, rho=1.0, supg=True, w_amp=1.0,
                    ale_k=0, k_mass=0,
                    core=(4, 4), halo=1, nu_pre=2, nu_post=2, omega=0.8,
+                   # interface cores 4 x 12 elements: uneven blocks, the
+                   # enlarged ones about 2x the unknowns of the interior ones
+                   iface_mult=3,
                    restart=30, rtol=1e-10, seed=0)
     else:
         raise KeyError(name)

@@ -103,6 +103,36 @@ def test_blocks_match_oracle(pair):
         assert np.array_equal(owner, owners(O.levels[l].N, blocks))
 
 
+@pytest.mark.parametrize("name,L", [("c3", 4), ("c2", 4)])
+def test_enlarged_interface_blocks_match_oracle(name, L):
+    cfg = inputs.with_levels(inputs.config(name), L)
+    H = fsgmg.Hierarchy(cfg, None, device=-1)
+    O = OracleHierarchy(cfg, None, build_smoothers=False)
+    fsgmg.build_fs_as_blocks(H.h, core=cfg["core"], halo=cfg["halo"], iface_mult=3)
+    for l in range(1, H.L):
+        ptr, dofs, owner = fsgmg.export_blocks(H.h, l)
+        blocks, _ = build_blocks(O.levels[l], cfg["core"], cfg["halo"], 3)
+        assert len(ptr) - 1 == len(blocks)
+        for j, I in enumerate(blocks):
+            assert np.array_equal(dofs[ptr[j]:ptr[j + 1]], I)
+        assert np.array_equal(owner, owners(O.levels[l].N, blocks))
+    H.close()
+
+
+def test_enlarged_interface_needs_layered_regions():
+    import tests.cfgs as cfgs
+    cfg = cfgs.small(nc=(4, 4), solid_rows=(), levels=2)
+    reg = np.zeros((4, 4), np.int8)
+    reg[0, :2] = 1                       # solid patch not constant along x
+    cfg["region"] = reg.ravel()
+    H = fsgmg.Hierarchy(cfg, None, device=-1)
+    with pytest.raises(fsgmg.FsgmgError) as e:
+        fsgmg.build_fs_as_blocks(H.h, core=(2, 2), halo=1, iface_mult=3)
+    assert e.value.status == -1
+    fsgmg.build_fs_as_blocks(H.h, core=(2, 2), halo=1, iface_mult=1)   # still usable
+    H.close()
+
+
 def test_error_paths():
     cfg = inputs.with_levels(inputs.config("c1"), 2)
     bad = dict(cfg, E=-1.0)

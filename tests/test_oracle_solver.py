@@ -61,6 +61,31 @@ def test_blocks_structure(c1):
     assert np.all(cover | lv.dir_mask | np.isin(np.arange(lv.N), us))
 
 
+def test_enlarged_interface_cores_counted_by_hand():
+    """c3 at 4 levels: 128 x 64 elements, solid rows [0,16) and [48,64), 4x4
+    tiles (32 columns x 16 rows).  With iface_mult = 3 the tile rows touching
+    the interface (3 and 12 solid, 4 and 11 fluid) take over two rows each
+    away from the interface, leaving per tile column 2 + 2 solid, 4 fluid-d
+    and 4 fluid-u cores; the enlarged fluid cores are 4 x 12 elements, so
+    their u-blocks carry 5 x 13 pressures instead of 5 x 5."""
+    cfg = inputs.with_levels(inputs.config("c3"), 4)
+    H = Hierarchy(cfg, None, build_smoothers=False)
+    lv = H.finest
+    assert tuple(lv.ne) == (128, 64)
+    plain, _ = build_blocks(lv, cfg["core"], cfg["halo"], 1)
+    blocks, kinds = build_blocks(lv, cfg["core"], cfg["halo"], 3)
+    assert len(plain) == 32 * (8 + 8 + 8)
+    assert len(blocks) == 32 * (4 + 4 + 4)
+    assert sum(k == (0, 1) for k in kinds) == 32 * 4
+    npf = sorted(int(np.sum(I >= lv.off_pf)) for I, k in zip(blocks, kinds) if k[0] == 1)
+    assert npf == [25] * 64 + [65] * 64
+    # interior u-block: 6x6 elements with the halo -> 13x13 nodes x 2 + 25;
+    # enlarged: 6x13 elements, the interface node row excluded -> 13x26 x 2 + 65
+    small = [len(I) for I, k in zip(blocks, kinds) if k[0] == 1 and np.sum(I >= lv.off_pf) == 25]
+    big = [len(I) for I, k in zip(blocks, kinds) if k[0] == 1 and np.sum(I >= lv.off_pf) == 65]
+    assert max(small) == 13 * 13 * 2 + 25 and max(big) == 13 * 26 * 2 + 65
+
+
 def test_smoother_matches_dense_inverse(c1):
     cfg, H = c1
     S = H.smoothers[-1]
