@@ -55,6 +55,52 @@ def smoother_bytes(H, level, prec):
     return int((n * m).sum() * sW + 4 * (n.sum() + m.sum()) + 3 * N * sV), int(len(n))
 
 
+def _units(info):
+    """Node-block unit of every unknown: a Q2 node's dim components of d (or
+    u) form one unit, each pressure is its own unit."""
+    N, N2, Nps, D = info["N"], info["N2"], info["Nps"], info["dim"]
+    i = np.arange(N)
+    unit = np.empty(N, np.int64)
+    d = i < info["off_ps"]
+    ps = (i >= info["off_ps"]) & (i < info["off_u"])
+    u = (i >= info["off_u"]) & (i < info["off_pf"])
+    pf = i >= info["off_pf"]
+    unit[d] = i[d] // D
+    unit[ps] = N2 + i[ps] - info["off_ps"]
+    unit[u] = N2 + Nps + (i[u] - info["off_u"]) // D
+    unit[pf] = 2 * N2 + Nps + i[pf] - info["off_pf"]
+    return unit, int(unit.max()) + 1
+
+
+def _unit_pairs(M, urow, ucol, ncol):
+    r = np.repeat(np.arange(M.shape[0]), np.diff(M.indptr))
+    return int(np.unique(urow[r] * ncol + ucol[M.indices]).size)
+
+
+def operator_bytes(H, level, sv, nvec):
+    """Algorithmic bytes of one level-operator product: every stored value,
+    one 4-byte column index per nonzero node block (dim x dim, dim x 1, 1 x dim
+    or scalar), one row pointer per unit row, and nvec vector passes (x, b, y)."""
+    A = H.csr(level, 0)
+    unit, nu = _units(H.info[level])
+    return int(A.nnz * sv + 4 * _unit_pairs(A, unit, unit, nu) + 4 * nu
+               + nvec * H.info[level]["N"] * sv)
+
+
+def transfer_bytes(H, level, sv):
+    """Mean algorithmic bytes of the restriction to level-1 and the
+    prolongation from it: the node-weight entries (shared by the dim
+    components; 4-byte index + value), the pressure entries, the input read
+    and the output write (read + write for the prolongation's update)."""
+    uf, nf = _units(H.info[level])
+    uc, nc = _units(H.info[level - 1])
+    Nf, Nc = H.info[level]["N"], H.info[level - 1]["N"]
+    R, P = H.csr(level, 2), H.csr(level, 1)
+    br = _unit_pairs(R, uc, uf, nf) * (4 + sv) + Nf * sv + Nc * sv
+    bp = _unit_pairs(P, uf, uc, nc) * (4 + sv) + Nc * sv + 2 * Nf * sv
+    return int((br + bp) / 2)
+
+
 def measured_traffic():
     """HBM bytes per launch of the finest-level smoother from the committed
     rocprofv3 counter summary, or None when kernels.hip has changed since the
@@ -195,6 +241,8 @@ def main():
     c = torch.zeros_like(b)
     c[H.info[-1]["off_u"]:H.info[-1]["off_u"] + 2 * H.info[-1]["N2"]:2] = 1.0
     lam = torch.zeros_like(b)
+    H.adjoint_solve(c, lam, rtol=rtol)      # first call builds the transposed operators
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     ainfo = H.adjoint_solve(c, lam, rtol=rtol)
     torch.cuda.synchronize()
@@ -220,10 +268,20 @@ def main():
                 traffic=measured_traffic() if cfg["name"] == "c2" and not args.levels else None,
                 bytes_per_launch=sm_bytes, blocks_per_launch=nblk,
                 avg_launch_us=round(avg_ms * 1e3, 2), launches=n_sm)
+    # the other HBM-bound kernels of the path, same live HIP-event timing
+    fin = H.L - 1
+    model = dict(vspmv=("k_spmv<float> residual, finest", operator_bytes(H, fin, 4, 3)),
+                 outer_spmv=("k_spmv<double> outer product, finest", operator_bytes(H, fin, 8, 2)),
+                 transfer=("k_transfer<float> restriction / prolongation, finest",
+                           transfer_bytes(H, fin, 4)))
     other = {}
     for k in ("vspmv", "outer_spmv", "transfer"):
         n, ms = ktime[k]
-        other[k] = dict(launches=n, avg_us=round(ms * 1e3 / max(n, 1), 2))
+        us = ms * 1e3 / max(n, 1)
+        name, nbytes = model[k]
+        gbs = nbytes / (us * 1e-6) / 1e9 if n else 0.0
+        other[k] = dict(kernel=name, launches=n, avg_us=round(us, 2), bytes_per_launch=nbytes,
+                        achieved_gbs=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4))
 
     sps32 = args.steps / t32
     sps64 = args.steps / t64
