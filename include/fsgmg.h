@@ -214,11 +214,13 @@ fsgmg_status kernel_timing(fsgmg_h h, int enable, int64_t counts[4], double tota
 /* Launch shapes chosen by the autotuner that build_fs_as_blocks runs on the
  * device (HIP-event timing of the candidates on the level's own data; kept
  * by later builds with the same block structure and precision):
- * out[0] = lanes per row of the level's V-cycle SpMV (4, 8, 16), out[1] =
- * smoother workgroup width (256, 512, 1024; negative = the same width with
- * non-temporal loads of the block inverses; 0 on level 0), out[2] = lanes of
- * the outer FP64 product.  ESTATE before the first device block build. */
-fsgmg_status tuning_info(fsgmg_h h, int level, int32_t out[3]);
+ * out[0] = lanes per row of the level's V-cycle SpMV (1, 2, 4, 8, 16),
+ * out[1] = smoother workgroup width (256, 512, 1024; negative = the same
+ * width with non-temporal loads of the block inverses; 0 on level 0),
+ * out[2] = lanes per row of the outer FP64 product, out[3] / out[4] = lanes
+ * per output of the restriction from / prolongation to this level (0 on
+ * level 0).  ESTATE before the first device block build. */
+fsgmg_status tuning_info(fsgmg_h h, int level, int32_t out[5]);
 
 const char* last_error(fsgmg_h h);
 void hierarchy_destroy(fsgmg_h h);

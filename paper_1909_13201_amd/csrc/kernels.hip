@@ -75,83 +75,94 @@ __device__ inline void load_col(const T* v, T* out) {
   }
 }
 
-template <typename T, int D, int LG>
+// One wavefront per (slice, part): L lanes per row, 64 / L rows of the slice;
+// lane (row r, sublane j) takes the row's entries j, j + L, ...  The slice
+// metadata is wavefront-uniform (scalar loads).
+template <typename T, int D, int L>
 __global__ __launch_bounds__(kThreads) void k_spmv(BOpView<T> A, const T* __restrict__ x,
                                                    const T* __restrict__ b, T* __restrict__ y,
                                                    int residual) {
-  const int lane = threadIdx.x & (LG - 1);
-  const int64_t item = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LG;
-  if (item < A.nrb) {
+  constexpr int R = 64 / L;
+  const int lane = threadIdx.x & 63;
+  const int64_t wave =
+      (int64_t)blockIdx.x * (kThreads / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int sub = lane % L;
+  if (wave < A.nsn * L) {
+    const int64_t sl = wave / L;
+    const int r = (int)(wave % L) * R + lane / L;
+    const int row = A.n_rows[sl * 64 + r];
+    const int wa = A.n_wa[sl], wb = A.n_wb[sl];
+    const int32_t* ca = A.n_ca + A.n_oa[sl] + r;
+    const T* va = A.n_va + (A.n_oa[sl] + r) * (D * D);
     T acc[D];
 #pragma unroll
-    for (int r = 0; r < D; ++r) acc[r] = T(0);
-    const int k1 = A.nn_ptr[item + 1];
-    int k = A.nn_ptr[item] + lane;
-    // two blocks per lane per trip: both column indices, then both x
-    // gathers, are in flight together
-    for (; k + LG < k1; k += 2 * LG) {
-      const int c0 = A.nn_col[k], c1 = A.nn_col[k + LG];
-      T v0[D * D], v1[D * D], x0[D], x1[D];
-      load_block<T, D>(A.nn_val + (int64_t)k * (D * D), v0);
-      load_block<T, D>(A.nn_val + (int64_t)(k + LG) * (D * D), v1);
-#pragma unroll
-      for (int q = 0; q < D; ++q) {
-        x0[q] = x[c0 + q];
-        x1[q] = x[c1 + q];
-      }
-#pragma unroll
-      for (int r = 0; r < D; ++r)
-#pragma unroll
-        for (int q = 0; q < D; ++q) acc[r] += v0[r * D + q] * x0[q] + v1[r * D + q] * x1[q];
-    }
-    if (k < k1) {
-      const int c = A.nn_col[k];
+    for (int q = 0; q < D; ++q) acc[q] = T(0);
+#pragma unroll 4
+    for (int k = sub; k < wa; k += L) {
+      const int c = ca[(int64_t)k * 64];
       T v[D * D], xv[D];
-      load_block<T, D>(A.nn_val + (int64_t)k * (D * D), v);
+      load_block<T, D>(va + (int64_t)k * 64 * (D * D), v);
+      // x offsets of u-field columns are odd when Nps is: scalar gathers
 #pragma unroll
       for (int q = 0; q < D; ++q) xv[q] = x[c + q];
 #pragma unroll
-      for (int r = 0; r < D; ++r)
+      for (int i = 0; i < D; ++i)
 #pragma unroll
-        for (int q = 0; q < D; ++q) acc[r] += v[r * D + q] * xv[q];
+        for (int q = 0; q < D; ++q) acc[i] += v[i * D + q] * xv[q];
     }
-    const int p1 = A.np_ptr[item + 1];
-    for (int k = A.np_ptr[item] + lane; k < p1; k += LG) {
-      const T xv = x[A.np_col[k]];
+    const int32_t* cb = A.n_cb + A.n_ob[sl] + r;
+    const T* vb = A.n_vb + (A.n_ob[sl] + r) * D;
+#pragma unroll 2
+    for (int k = sub; k < wb; k += L) {
+      const T xp = x[cb[(int64_t)k * 64]];
       T v[D];
-      load_col<T, D>(A.np_val + (int64_t)k * D, v);
+      load_col<T, D>(vb + (int64_t)k * 64 * D, v);
 #pragma unroll
-      for (int r = 0; r < D; ++r) acc[r] += v[r] * xv;
+      for (int i = 0; i < D; ++i) acc[i] += v[i] * xp;
     }
+    if constexpr (L > 1) {
 #pragma unroll
-    for (int off = LG / 2; off > 0; off >>= 1)
+      for (int off = L / 2; off > 0; off >>= 1)
 #pragma unroll
-      for (int r = 0; r < D; ++r) acc[r] += __shfl_xor(acc[r], off, LG);
-    if (lane == 0) {
-      const int o = A.nrow_off[item];
-#pragma unroll
-      for (int r = 0; r < D; ++r) y[o + r] = residual ? b[o + r] - acc[r] : acc[r];
+        for (int i = 0; i < D; ++i) acc[i] += __shfl_xor(acc[i], off, L);
     }
-  } else {
-    const int64_t p = item - A.nrb;
-    if (p >= A.npr) return;
-    T acc = T(0);
-    const int k1 = A.pn_ptr[p + 1];
-    for (int k = A.pn_ptr[p] + lane; k < k1; k += LG) {
-      const int c = A.pn_col[k];
-      T v[D];
-      load_col<T, D>(A.pn_val + (int64_t)k * D, v);
+    if (sub == 0 && row >= 0) {
+      const int o = A.nrow_off[row];
 #pragma unroll
-      for (int q = 0; q < D; ++q) acc += v[q] * x[c + q];
+      for (int i = 0; i < D; ++i) y[o + i] = residual ? b[o + i] - acc[i] : acc[i];
     }
-    const int p1 = A.pp_ptr[p + 1];
-    for (int k = A.pp_ptr[p] + lane; k < p1; k += LG) acc += A.pp_val[k] * x[A.pp_col[k]];
+    return;
+  }
+  const int64_t pw = wave - A.nsn * L;
+  if (pw >= A.nsp * L) return;
+  const int64_t sl = pw / L;
+  const int r = (int)(pw % L) * R + lane / L;
+  const int row = A.p_rows[sl * 64 + r];
+  const int wa = A.p_wa[sl], wb = A.p_wb[sl];
+  const int32_t* ca = A.p_ca + A.p_oa[sl] + r;
+  const T* va = A.p_va + (A.p_oa[sl] + r) * D;
+  T acc = T(0);
+#pragma unroll 4
+  for (int k = sub; k < wa; k += L) {
+    const int c = ca[(int64_t)k * 64];
+    T v[D], xv[D];
+    load_col<T, D>(va + (int64_t)k * 64 * D, v);
 #pragma unroll
-    for (int off = LG / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, LG);
-    if (lane == 0) {
-      const int o = A.prow_off[p];
-      y[o] = residual ? b[o] - acc : acc;
-    }
+    for (int q = 0; q < D; ++q) xv[q] = x[c + q];
+#pragma unroll
+    for (int q = 0; q < D; ++q) acc += v[q] * xv[q];
+  }
+  const int32_t* cb = A.p_cb + A.p_ob[sl] + r;
+  const T* vb = A.p_vb + A.p_ob[sl] + r;
+#pragma unroll 2
+  for (int k = sub; k < wb; k += L) acc += vb[(int64_t)k * 64] * x[cb[(int64_t)k * 64]];
+  if constexpr (L > 1) {
+#pragma unroll
+    for (int off = L / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, L);
+  }
+  if (sub == 0 && row >= 0) {
+    const int o = A.prow_off[row];
+    y[o] = residual ? b[o] - acc : acc;
   }
 }
 
@@ -1096,16 +1107,26 @@ __global__ __launch_bounds__(kThreads) void k_scatter(int64_t n, const double* _
 template <typename T, int D>
 static void spmv_lanes(const BOpView<T>& A, int lanes, const T* x, const T* b, T* y,
                        bool residual, hipStream_t s) {
-  const int lg = (lanes == 4 || lanes == 16) ? lanes : 8;
-  const int64_t items = A.nrb + A.npr;
-  const unsigned g = grid_for(items * lg, kThreads);
+  const int L = (lanes == 2 || lanes == 4 || lanes == 8 || lanes == 16) ? lanes : 1;
+  const int64_t waves = (A.nsn + A.nsp) * L;
+  const unsigned g = grid_for(waves * 64, kThreads);
   if (g == 0) return;
-  if (lg == 4)
-    hipLaunchKernelGGL((k_spmv<T, D, 4>), dim3(g), dim3(kThreads), 0, s, A, x, b, y, (int)residual);
-  else if (lg == 16)
-    hipLaunchKernelGGL((k_spmv<T, D, 16>), dim3(g), dim3(kThreads), 0, s, A, x, b, y, (int)residual);
-  else
-    hipLaunchKernelGGL((k_spmv<T, D, 8>), dim3(g), dim3(kThreads), 0, s, A, x, b, y, (int)residual);
+  switch (L) {
+    case 1:
+      hipLaunchKernelGGL((k_spmv<T, D, 1>), dim3(g), dim3(kThreads), 0, s, A, x, b, y, (int)residual);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_spmv<T, D, 2>), dim3(g), dim3(kThreads), 0, s, A, x, b, y, (int)residual);
+      break;
+    case 4:
+      hipLaunchKernelGGL((k_spmv<T, D, 4>), dim3(g), dim3(kThreads), 0, s, A, x, b, y, (int)residual);
+      break;
+    case 8:
+      hipLaunchKernelGGL((k_spmv<T, D, 8>), dim3(g), dim3(kThreads), 0, s, A, x, b, y, (int)residual);
+      break;
+    default:
+      hipLaunchKernelGGL((k_spmv<T, D, 16>), dim3(g), dim3(kThreads), 0, s, A, x, b, y, (int)residual);
+  }
 }
 
 template <typename T>
@@ -1127,22 +1148,43 @@ void launch_csr_spmv(int64_t nrows, const int64_t* rowptr, const int32_t* col, c
   if (g) hipLaunchKernelGGL(k_csr_spmv, dim3(g), dim3(kThreads), 0, s, nrows, rowptr, col, val, x, y, beta);
 }
 
-template <typename T>
-void launch_transfer(const TransferView<T>& t, int D, int mode, const T* in, T* out,
-                     hipStream_t s) {
-  constexpr int LG = 8;
+template <typename T, int D>
+static void transfer_lanes(const TransferView<T>& t, int mode, const T* in, T* out, int lanes,
+                           hipStream_t s) {
+  const int LG = (lanes == 1 || lanes == 2 || lanes == 4 || lanes == 16) ? lanes : 8;
   const int64_t n = (mode == 0 || mode == 2) ? t.N2c + t.Npsc + t.Npfc : t.N2f + t.Npsf + t.Npff;
   const unsigned g = grid_for(n * LG, kThreads);
   if (!g) return;
+  switch (LG) {
+    case 1:
+      hipLaunchKernelGGL((k_transfer<T, D, 1>), dim3(g), dim3(kThreads), 0, s, t, mode, in, out);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_transfer<T, D, 2>), dim3(g), dim3(kThreads), 0, s, t, mode, in, out);
+      break;
+    case 4:
+      hipLaunchKernelGGL((k_transfer<T, D, 4>), dim3(g), dim3(kThreads), 0, s, t, mode, in, out);
+      break;
+    case 16:
+      hipLaunchKernelGGL((k_transfer<T, D, 16>), dim3(g), dim3(kThreads), 0, s, t, mode, in, out);
+      break;
+    default:
+      hipLaunchKernelGGL((k_transfer<T, D, 8>), dim3(g), dim3(kThreads), 0, s, t, mode, in, out);
+  }
+}
+
+template <typename T>
+void launch_transfer(const TransferView<T>& t, int D, int mode, const T* in, T* out,
+                     hipStream_t s, int lanes) {
   if (D == 2)
-    hipLaunchKernelGGL((k_transfer<T, 2, LG>), dim3(g), dim3(kThreads), 0, s, t, mode, in, out);
+    transfer_lanes<T, 2>(t, mode, in, out, lanes, s);
   else
-    hipLaunchKernelGGL((k_transfer<T, 3, LG>), dim3(g), dim3(kThreads), 0, s, t, mode, in, out);
+    transfer_lanes<T, 3>(t, mode, in, out, lanes, s);
 }
 template void launch_transfer<double>(const TransferView<double>&, int, int, const double*,
-                                      double*, hipStream_t);
+                                      double*, hipStream_t, int);
 template void launch_transfer<float>(const TransferView<float>&, int, int, const float*, float*,
-                                     hipStream_t);
+                                     hipStream_t, int);
 
 template <typename TV, typename TW>
 static void smooth_impl(const BlocksView& B, const TW* W, const TV* r, TV* x, TV* tbuf,

@@ -14,23 +14,41 @@ namespace fsgmg {
 //   NP: D x 1 columns against one pressure unknown.
 // Pressure rows p in [0, Nps + Npf):
 //   PN: 1 x D rows against a node block; PP: scalar entries.
+// Level operator in sliced-ELL node-block form.  Rows are "units": node rows
+// (dim outputs: the d or u components of one Q2 node) and pressure rows (one
+// output).  Each class is cut into slices of 64 rows (rows sorted by length
+// inside windows of 1,024 so a slice holds rows of similar length); slice s
+// stores the k-th entry of its row r at entry index off[s] + 64 k + r, so a
+// wavefront reads consecutive entries.  Entry kinds: node rows x node columns
+// (dim x dim block, row-major), node rows x pressure columns (dim values),
+// pressure rows x node columns (dim values), pressure rows x pressure columns
+// (one value).  Padding entries have column 0 and value 0.
 template <typename T>
 struct BOpView {
-  int64_t nrb, npr;
-  const int32_t* nrow_off;
-  const int32_t* nn_ptr;
-  const int32_t* nn_col;
-  const T* nn_val;
-  const int32_t* np_ptr;
-  const int32_t* np_col;
-  const T* np_val;
-  const int32_t* prow_off;
-  const int32_t* pn_ptr;
-  const int32_t* pn_col;
-  const T* pn_val;
-  const int32_t* pp_ptr;
-  const int32_t* pp_col;
-  const T* pp_val;
+  int64_t nrb, npr;          // node rows (2 N2), pressure rows (Nps + Npf)
+  int64_t nsn, nsp;          // slices of the node / pressure class
+  const int32_t* nrow_off;   // node row -> first output unknown
+  const int32_t* prow_off;   // pressure row -> output unknown
+  // node class: per slice rows[64] (-1 = padding), widths and entry offsets
+  const int32_t* n_rows;
+  const int32_t* n_wa;
+  const int32_t* n_wb;
+  const int64_t* n_oa;
+  const int64_t* n_ob;
+  const int32_t* n_ca;       // per entry: offset of the column node's first unknown
+  const int32_t* n_cb;       // per entry: pressure column
+  const T* n_va;             // dim*dim per entry
+  const T* n_vb;             // dim per entry
+  // pressure class
+  const int32_t* p_rows;
+  const int32_t* p_wa;
+  const int32_t* p_wb;
+  const int64_t* p_oa;
+  const int64_t* p_ob;
+  const int32_t* p_ca;
+  const int32_t* p_cb;
+  const T* p_va;             // dim per entry
+  const T* p_vb;             // one per entry
 };
 
 // Transfer between level l-1 (coarse) and l (fine), node-level form.
@@ -87,10 +105,11 @@ struct BlocksView {
 enum class WPrec { F64 = 0, F32 = 1, BF16 = 2 };
 
 // ---- level operator ----
-// lanes: 4, 8 or 16 lanes per node row block / pressure row
+// lanes: 1, 2, 4, 8 or 16 lanes per row (the entries of a row are dealt
+// round-robin)
 template <typename T>
 void launch_spmv(const BOpView<T>& A, int D, const T* x, const T* b, T* y, bool residual,
-                 hipStream_t s, int lanes = 8);
+                 hipStream_t s, int lanes = 1);
 
 // scalar CSR (FP64): y = A x (+ beta y)
 void launch_csr_spmv(int64_t nrows, const int64_t* rowptr, const int32_t* col, const double* val,
@@ -100,7 +119,7 @@ void launch_csr_spmv(int64_t nrows, const int64_t* rowptr, const int32_t* col, c
 //      2: b_c = (D_f P)^T r_f, 3: x_f += (D_c R)^T x_c) ----
 template <typename T>
 void launch_transfer(const TransferView<T>& t, int D, int mode, const T* in, T* out,
-                     hipStream_t s);
+                     hipStream_t s, int lanes = 8);
 
 // ---- smoother: x = (first ? 0 : x) + omega * B r  (transpose: B^T) ----
 // threads: workgroup width of the forward sweep (256 / 512 / 1024, 0 = by

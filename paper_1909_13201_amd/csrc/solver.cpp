@@ -37,17 +37,89 @@ struct Fail {
   } while (0)
 
 // ---------------------------------------------------------------------------
-// node-block operator: structure, and a map from scalar CSR entries to the
-// concatenated value array [NN | NP | PN | PP]
+// node-block operator in sliced-ELL form (see BOpView), and a map from the
+// scalar CSR entries to the concatenated value array [n_va | n_vb | p_va | p_vb]
 // ---------------------------------------------------------------------------
+struct SellClass {
+  int64_t nslices = 0, ea = 0, eb = 0;   // slices, entries of kind a / b (padding included)
+  std::vector<int32_t> rows, wa, wb, ca, cb;
+  std::vector<int64_t> oa, ob;
+};
+
 struct BOpHost {
   int64_t nrb = 0, npr = 0;
-  std::vector<int32_t> nrow_off, nn_ptr, nn_col, np_ptr, np_col, prow_off, pn_ptr, pn_col, pp_ptr,
-      pp_col;
-  int64_t n_nn = 0, n_np = 0, n_pn = 0, n_pp = 0;
+  std::vector<int32_t> nrow_off, prow_off;
+  SellClass node, pres;
+  int64_t n_na = 0, n_nb = 0, n_pa = 0, n_pb = 0;   // value counts per region
   std::vector<int64_t> map;
-  int64_t nvals() const { return n_nn + n_np + n_pn + n_pp; }
+  int64_t nvals() const { return n_na + n_nb + n_pa + n_pb; }
 };
+
+namespace {
+
+// Rows' entry lists (CSR of entries, column per entry) -> slices of 64 rows,
+// rows sorted by (a-length, b-length) descending inside windows of 1,024.
+// pos_a[i] / pos_b[i]: the sliced entry index of CSR entry i.
+void make_slices(int64_t nrows, const std::vector<int64_t>& pa, const std::vector<int32_t>& ca,
+                 const std::vector<int64_t>& pb, const std::vector<int32_t>& cb, SellClass& S,
+                 std::vector<int64_t>& pos_a, std::vector<int64_t>& pos_b) {
+  constexpr int64_t C = 64, kWindow = 1024;
+  std::vector<int32_t> order(nrows);
+  for (int64_t r = 0; r < nrows; ++r) order[r] = (int32_t)r;
+  for (int64_t w0 = 0; w0 < nrows; w0 += kWindow) {
+    const int64_t w1 = std::min(nrows, w0 + kWindow);
+    std::stable_sort(order.begin() + w0, order.begin() + w1, [&](int32_t x, int32_t y) {
+      const int64_t ax = pa[x + 1] - pa[x], ay = pa[y + 1] - pa[y];
+      if (ax != ay) return ax > ay;
+      return pb[x + 1] - pb[x] > pb[y + 1] - pb[y];
+    });
+  }
+  S.nslices = (nrows + C - 1) / C;
+  S.rows.assign(S.nslices * C, -1);
+  S.wa.assign(S.nslices, 0);
+  S.wb.assign(S.nslices, 0);
+  S.oa.assign(S.nslices, 0);
+  S.ob.assign(S.nslices, 0);
+  pos_a.assign(ca.size(), -1);
+  pos_b.assign(cb.size(), -1);
+  int64_t ea = 0, eb = 0;
+  for (int64_t sl = 0; sl < S.nslices; ++sl) {
+    int64_t wa = 0, wb = 0;
+    for (int64_t r = 0; r < C && sl * C + r < nrows; ++r) {
+      const int32_t row = order[sl * C + r];
+      S.rows[sl * C + r] = row;
+      wa = std::max(wa, pa[row + 1] - pa[row]);
+      wb = std::max(wb, pb[row + 1] - pb[row]);
+    }
+    S.wa[sl] = (int32_t)wa;
+    S.wb[sl] = (int32_t)wb;
+    S.oa[sl] = ea;
+    S.ob[sl] = eb;
+    ea += wa * C;
+    eb += wb * C;
+  }
+  S.ea = ea;
+  S.eb = eb;
+  S.ca.assign(ea, 0);
+  S.cb.assign(eb, 0);
+  for (int64_t sl = 0; sl < S.nslices; ++sl)
+    for (int64_t r = 0; r < C; ++r) {
+      const int32_t row = S.rows[sl * C + r];
+      if (row < 0) continue;
+      for (int64_t k = 0; k < pa[row + 1] - pa[row]; ++k) {
+        const int64_t e = S.oa[sl] + k * C + r;
+        S.ca[e] = ca[pa[row] + k];
+        pos_a[pa[row] + k] = e;
+      }
+      for (int64_t k = 0; k < pb[row + 1] - pb[row]; ++k) {
+        const int64_t e = S.ob[sl] + k * C + r;
+        S.cb[e] = cb[pb[row] + k];
+        pos_b[pb[row] + k] = e;
+      }
+    }
+}
+
+}  // namespace
 
 BOpHost build_bop(const Level& lv, const CsrHost& A) {
   const int D = lv.D;
@@ -59,22 +131,28 @@ BOpHost build_bop(const Level& lv, const CsrHost& A) {
   auto block_off = [&](int64_t c) -> int64_t {
     return c < lv.off_ps ? D * (c / D) : lv.off_u + D * ((c - lv.off_u) / D);
   };
-  std::vector<std::pair<int64_t, int64_t>> sec[4];  // (k, relative value index)
   struct E {
     int64_t key;
     int r, q;
     int64_t k;
   };
+  // per class: CSR of entries (kind a: node columns, kind b: pressure columns)
+  // and, per scalar entry, (CSR entry, position inside the entry's values)
+  std::vector<int64_t> pa[2], pb[2];
+  std::vector<int32_t> ca[2], cb[2];
+  std::vector<std::pair<int64_t, int>> sa[2], sb[2];   // indexed by scalar entry k
+  for (int c = 0; c < 2; ++c) {
+    pa[c].assign(1, 0);
+    pb[c].assign(1, 0);
+  }
+  std::vector<int64_t> ka, kb;   // scalar entry of each recorded (CSR entry, offset)
   std::vector<E> ne, pe;
-  b.nn_ptr.push_back(0);
-  b.np_ptr.push_back(0);
-  for (int64_t rb = 0; rb < b.nrb; ++rb) {
-    const int64_t r0 = rb < lv.N2 ? D * rb : lv.off_u + D * (rb - lv.N2);
-    b.nrow_off.push_back((int32_t)r0);
+  std::vector<int64_t> ent_a[2], ent_b[2];   // scalar k list per class (parallel to sa/sb)
+  auto add_row = [&](int cls, const std::vector<int64_t>& rows_scalar, int nout) {
     ne.clear();
     pe.clear();
-    for (int r = 0; r < D; ++r) {
-      const int64_t row = r0 + r;
+    for (int r = 0; r < nout; ++r) {
+      const int64_t row = rows_scalar[r];
       for (int64_t k = A.rowptr[row]; k < A.rowptr[row + 1]; ++k) {
         const int64_t c = A.col[k];
         if (node_col(c)) {
@@ -87,59 +165,55 @@ BOpHost build_bop(const Level& lv, const CsrHost& A) {
     }
     std::sort(ne.begin(), ne.end(), [](const E& x, const E& y) { return x.key < y.key; });
     std::sort(pe.begin(), pe.end(), [](const E& x, const E& y) { return x.key < y.key; });
+    const int wva = cls == 0 ? D * D : D;   // values per entry of kind a
     for (size_t i = 0; i < ne.size(); ++i) {
-      if (i == 0 || ne[i].key != ne[i - 1].key) b.nn_col.push_back((int32_t)ne[i].key);
-      const int64_t bi = (int64_t)b.nn_col.size() - 1;
-      sec[0].emplace_back(ne[i].k, bi * D * D + ne[i].r * D + ne[i].q);
+      if (i == 0 || ne[i].key != ne[i - 1].key) ca[cls].push_back((int32_t)ne[i].key);
+      const int off = cls == 0 ? ne[i].r * D + ne[i].q : ne[i].q;
+      (void)wva;
+      sa[cls].emplace_back((int64_t)ca[cls].size() - 1, off);
+      ent_a[cls].push_back(ne[i].k);
     }
     for (size_t i = 0; i < pe.size(); ++i) {
-      if (i == 0 || pe[i].key != pe[i - 1].key) b.np_col.push_back((int32_t)pe[i].key);
-      const int64_t pi = (int64_t)b.np_col.size() - 1;
-      sec[1].emplace_back(pe[i].k, pi * D + pe[i].r);
+      if (i == 0 || pe[i].key != pe[i - 1].key) cb[cls].push_back((int32_t)pe[i].key);
+      sb[cls].emplace_back((int64_t)cb[cls].size() - 1, pe[i].r);
+      ent_b[cls].push_back(pe[i].k);
     }
-    b.nn_ptr.push_back((int32_t)b.nn_col.size());
-    b.np_ptr.push_back((int32_t)b.np_col.size());
+    pa[cls].push_back((int64_t)ca[cls].size());
+    pb[cls].push_back((int64_t)cb[cls].size());
+  };
+  std::vector<int64_t> rs(D);
+  for (int64_t rb = 0; rb < b.nrb; ++rb) {
+    const int64_t r0 = rb < lv.N2 ? D * rb : lv.off_u + D * (rb - lv.N2);
+    b.nrow_off.push_back((int32_t)r0);
+    for (int r = 0; r < D; ++r) rs[r] = r0 + r;
+    add_row(0, rs, D);
   }
-  b.pn_ptr.push_back(0);
-  b.pp_ptr.push_back(0);
   for (int64_t p = 0; p < b.npr; ++p) {
     const int64_t row = p < lv.Nps ? lv.off_ps + p : lv.off_pf + (p - lv.Nps);
     b.prow_off.push_back((int32_t)row);
-    ne.clear();
-    pe.clear();
-    for (int64_t k = A.rowptr[row]; k < A.rowptr[row + 1]; ++k) {
-      const int64_t c = A.col[k];
-      if (node_col(c)) {
-        const int64_t bo = block_off(c);
-        ne.push_back({bo, 0, (int)(c - bo), k});
-      } else {
-        pe.push_back({c, 0, 0, k});
-      }
-    }
-    std::sort(ne.begin(), ne.end(), [](const E& x, const E& y) { return x.key < y.key; });
-    std::sort(pe.begin(), pe.end(), [](const E& x, const E& y) { return x.key < y.key; });
-    for (size_t i = 0; i < ne.size(); ++i) {
-      if (i == 0 || ne[i].key != ne[i - 1].key) b.pn_col.push_back((int32_t)ne[i].key);
-      sec[2].emplace_back(ne[i].k, ((int64_t)b.pn_col.size() - 1) * D + ne[i].q);
-    }
-    for (size_t i = 0; i < pe.size(); ++i) {
-      b.pp_col.push_back((int32_t)pe[i].key);
-      sec[3].emplace_back(pe[i].k, (int64_t)b.pp_col.size() - 1);
-    }
-    b.pn_ptr.push_back((int32_t)b.pn_col.size());
-    b.pp_ptr.push_back((int32_t)b.pp_col.size());
+    rs[0] = row;
+    add_row(1, rs, 1);
   }
-  b.n_nn = (int64_t)b.nn_col.size() * D * D;
-  b.n_np = (int64_t)b.np_col.size() * D;
-  b.n_pn = (int64_t)b.pn_col.size() * D;
-  b.n_pp = (int64_t)b.pp_col.size();
-  const int64_t base[4] = {0, b.n_nn, b.n_nn + b.n_np, b.n_nn + b.n_np + b.n_pn};
-  for (int s = 0; s < 4; ++s)
-    for (auto& e : sec[s]) b.map[e.first] = base[s] + e.second;
+  std::vector<int64_t> pos_a[2], pos_b[2];
+  make_slices(b.nrb, pa[0], ca[0], pb[0], cb[0], b.node, pos_a[0], pos_b[0]);
+  make_slices(b.npr, pa[1], ca[1], pb[1], cb[1], b.pres, pos_a[1], pos_b[1]);
+  b.n_na = b.node.ea * D * D;
+  b.n_nb = b.node.eb * D;
+  b.n_pa = b.pres.ea * D;
+  b.n_pb = b.pres.eb;
+  const int64_t base_a[2] = {0, b.n_na + b.n_nb};
+  const int64_t base_b[2] = {b.n_na, b.n_na + b.n_nb + b.n_pa};
+  const int64_t per_a[2] = {(int64_t)D * D, (int64_t)D};
+  const int64_t per_b[2] = {(int64_t)D, 1};
+  for (int c = 0; c < 2; ++c) {
+    for (size_t i = 0; i < sa[c].size(); ++i)
+      b.map[ent_a[c][i]] = base_a[c] + pos_a[c][sa[c][i].first] * per_a[c] + sa[c][i].second;
+    for (size_t i = 0; i < sb[c].size(); ++i)
+      b.map[ent_b[c][i]] = base_b[c] + pos_b[c][sb[c][i].first] * per_b[c] + sb[c][i].second;
+  }
   return b;
 }
 
-// ---------------------------------------------------------------------------
 struct DevBOp {
   BOpView<double> v64{};
   BOpView<float> v32{};
@@ -216,11 +290,13 @@ struct fsgmg_hierarchy {
   // autotuned launch shapes per level: SpMV lanes per row (V-cycle precision),
   // smoother workgroup width; lanes of the outer FP64 products
   struct Tune {
-    int spmv_lanes = 8;
+    int spmv_lanes = 1;
     int smooth_threads = 0;
+    int restrict_lanes = 8;   // transfers into this level's coarse neighbour
+    int prolong_lanes = 2;    // transfers from it
   };
   std::vector<Tune> tune;
-  int outer_lanes = 8;
+  int outer_lanes = 1;
   bool tuned = false;
   // HIP graphs: one per Arnoldi step j (V-cycle included) and transposition,
   // one per V-cycle core; captured on a private stream, launched on `stream`
@@ -325,37 +401,53 @@ void upload_bop(fsgmg_hierarchy& h, const Level& lv, const CsrHost& A, DevBOp& d
   BOpView<double>& x = d.v64;
   x.nrb = b.nrb;
   x.npr = b.npr;
+  x.nsn = b.node.nslices;
+  x.nsp = b.pres.nslices;
   x.nrow_off = h.upload(b.nrow_off);
-  x.nn_ptr = h.upload(b.nn_ptr);
-  x.nn_col = h.upload(b.nn_col);
-  x.np_ptr = h.upload(b.np_ptr);
-  x.np_col = h.upload(b.np_col);
   x.prow_off = h.upload(b.prow_off);
-  x.pn_ptr = h.upload(b.pn_ptr);
-  x.pn_col = h.upload(b.pn_col);
-  x.pp_ptr = h.upload(b.pp_ptr);
-  x.pp_col = h.upload(b.pp_col);
-  x.nn_val = d.vals64;
-  x.np_val = d.vals64 + b.n_nn;
-  x.pn_val = d.vals64 + b.n_nn + b.n_np;
-  x.pp_val = d.vals64 + b.n_nn + b.n_np + b.n_pn;
-  BOpView<float>& y = d.v32;
+  x.n_rows = h.upload(b.node.rows);
+  x.n_wa = h.upload(b.node.wa);
+  x.n_wb = h.upload(b.node.wb);
+  x.n_oa = h.upload(b.node.oa);
+  x.n_ob = h.upload(b.node.ob);
+  x.n_ca = h.upload(b.node.ca);
+  x.n_cb = h.upload(b.node.cb);
+  x.p_rows = h.upload(b.pres.rows);
+  x.p_wa = h.upload(b.pres.wa);
+  x.p_wb = h.upload(b.pres.wb);
+  x.p_oa = h.upload(b.pres.oa);
+  x.p_ob = h.upload(b.pres.ob);
+  x.p_ca = h.upload(b.pres.ca);
+  x.p_cb = h.upload(b.pres.cb);
+  auto set_vals = [&](auto& view, auto* base) {
+    view.n_va = base;
+    view.n_vb = base + b.n_na;
+    view.p_va = base + b.n_na + b.n_nb;
+    view.p_vb = base + b.n_na + b.n_nb + b.n_pa;
+  };
+  set_vals(x, d.vals64);
+  BOpView<float>& y = d.v32;   // same index arrays, FP32 values
   y.nrb = x.nrb;
   y.npr = x.npr;
+  y.nsn = x.nsn;
+  y.nsp = x.nsp;
   y.nrow_off = x.nrow_off;
-  y.nn_ptr = x.nn_ptr;
-  y.nn_col = x.nn_col;
-  y.np_ptr = x.np_ptr;
-  y.np_col = x.np_col;
   y.prow_off = x.prow_off;
-  y.pn_ptr = x.pn_ptr;
-  y.pn_col = x.pn_col;
-  y.pp_ptr = x.pp_ptr;
-  y.pp_col = x.pp_col;
-  y.nn_val = d.vals32;
-  y.np_val = d.vals32 + b.n_nn;
-  y.pn_val = d.vals32 + b.n_nn + b.n_np;
-  y.pp_val = d.vals32 + b.n_nn + b.n_np + b.n_pn;
+  y.n_rows = x.n_rows;
+  y.n_wa = x.n_wa;
+  y.n_wb = x.n_wb;
+  y.n_oa = x.n_oa;
+  y.n_ob = x.n_ob;
+  y.n_ca = x.n_ca;
+  y.n_cb = x.n_cb;
+  y.p_rows = x.p_rows;
+  y.p_wa = x.p_wa;
+  y.p_wb = x.p_wb;
+  y.p_oa = x.p_oa;
+  y.p_ob = x.p_ob;
+  y.p_ca = x.p_ca;
+  y.p_cb = x.p_cb;
+  set_vals(y, d.vals32);
   d.ready = true;
 }
 
@@ -793,7 +885,7 @@ void vcycle_core(fsgmg_hierarchy& h, bool transpose) {
     }
     TimedLaunch t(h, 3, l == L - 1);
     launch_transfer<TV>(Vec<TV>::tv(d), D, transpose ? 2 : 0, Vec<TV>::r(d), Vec<TV>::b(h.dl[l - 1]),
-                        h.stream);
+                        h.stream, h.tune[l].restrict_lanes);
   }
   DLevel& C = h.dl[0];
   launch_dense_gemv<TV>(h.n0, transpose ? h.coarse_invT : h.coarse_inv, false, Vec<TV>::b(C),
@@ -803,7 +895,7 @@ void vcycle_core(fsgmg_hierarchy& h, bool transpose) {
     {
       TimedLaunch t(h, 3, l == L - 1);
       launch_transfer<TV>(Vec<TV>::tv(d), D, transpose ? 3 : 1, Vec<TV>::x(h.dl[l - 1]),
-                          Vec<TV>::x(d), h.stream);
+                          Vec<TV>::x(d), h.stream, h.tune[l].prolong_lanes);
     }
     smooth_level<TV>(h, l, npost, transpose, false);
   }
@@ -1046,7 +1138,7 @@ void autotune_impl(fsgmg_hierarchy& h) {
   h.timing = false;
   h.tune.assign(h.L, {});
   const WPrec wp = wprec(h.sopt.prec);
-  const int lanes[3] = {4, 8, 16}, threads[6] = {256, 512, 1024, -256, -512, -1024};
+  const int lanes[5] = {1, 2, 4, 8, 16}, threads[6] = {256, 512, 1024, -256, -512, -1024};
   for (int l = 0; l < h.L; ++l) {
     DLevel& d = h.dl[l];
     float best = 1e30f;
@@ -1061,6 +1153,30 @@ void autotune_impl(fsgmg_hierarchy& h) {
       }
     }
     if (l == 0) continue;
+    // transfers: restriction into level l-1 (coarse outputs, ~9-25 weights
+    // each) and prolongation from it (fine outputs, 1-4 weights each)
+    best = 1e30f;
+    for (int lg : lanes) {
+      const float t = time_launch(h, [&] {
+        launch_transfer<TV>(Vec<TV>::tv(d), h.D, 0, Vec<TV>::r(d), Vec<TV>::b(h.dl[l - 1]),
+                            h.stream, lg);
+      });
+      if (t < best) {
+        best = t;
+        h.tune[l].restrict_lanes = lg;
+      }
+    }
+    best = 1e30f;
+    for (int lg : lanes) {
+      const float t = time_launch(h, [&] {
+        launch_transfer<TV>(Vec<TV>::tv(d), h.D, 1, Vec<TV>::x(h.dl[l - 1]), Vec<TV>::r(d),
+                            h.stream, lg);
+      });
+      if (t < best) {
+        best = t;
+        h.tune[l].prolong_lanes = lg;
+      }
+    }
     best = 1e30f;
     for (int th : threads) {
       const float t = time_launch(h, [&] {
@@ -1454,13 +1570,15 @@ fsgmg_status kernel_timing(fsgmg_h h, int enable, int64_t counts[4], double tota
   });
 }
 
-fsgmg_status tuning_info(fsgmg_h h, int level, int32_t out[3]) {
+fsgmg_status tuning_info(fsgmg_h h, int level, int32_t out[5]) {
   // out[1] < 0 means non-temporal loads of the block inverses
   if (!h || !out) return FSGMG_EINVAL;
   if (level < 0 || level >= h->L || (int)h->tune.size() != h->L) return FSGMG_ESTATE;
   out[0] = h->tune[level].spmv_lanes;
   out[1] = h->tune[level].smooth_threads;
   out[2] = h->outer_lanes;
+  out[3] = level > 0 ? h->tune[level].restrict_lanes : 0;
+  out[4] = level > 0 ? h->tune[level].prolong_lanes : 0;
   return FSGMG_OK;
 }
 

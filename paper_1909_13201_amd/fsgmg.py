@@ -296,9 +296,10 @@ def kernel_timing(h, enable):
 
 
 def tuning_info(h, level):
-    out = (C.c_int32 * 3)()
+    out = (C.c_int32 * 5)()
     _check(h, lib().tuning_info(h, int(level), out))
-    return dict(spmv_lanes=int(out[0]), smooth_threads=int(out[1]), outer_lanes=int(out[2]))
+    return dict(spmv_lanes=int(out[0]), smooth_threads=int(out[1]), outer_lanes=int(out[2]),
+                restrict_lanes=int(out[3]), prolong_lanes=int(out[4]))
 
 
 def hierarchy_destroy(h):
