@@ -1230,7 +1230,7 @@ fsgmg_status setup_hierarchy(const fsgmg_mesh_desc* mesh, const fsgmg_physics* p
   h->device = device;
   h->stream = (hipStream_t)stream;
   fsgmg_status st = guarded(h.get(), [&]() -> fsgmg_status {
-    if (mesh->dim != 2) throw Fail{FSGMG_EINVAL, "only dim = 2 is supported"};
+    if (mesh->dim != 2 && mesh->dim != 3) throw Fail{FSGMG_EINVAL, "dim must be 2 or 3"};
     if (mesh->n_levels < 1 || mesh->n_levels > 12) throw Fail{FSGMG_EINVAL, "n_levels out of range"};
     int64_t nce = 1;
     for (int a = 0; a < mesh->dim; ++a) {

@@ -133,6 +133,33 @@ def test_enlarged_interface_needs_layered_regions():
     H.close()
 
 
+def test_3d_channel_matches_oracle():
+    """Hexahedral Q2/Q1 (dim = 3): the library's host assembly, transfers,
+    load and Schwarz index sets reproduce the oracle's."""
+    import tests.cfgs as cfgs
+    cfg = cfgs.channel3d()
+    H = fsgmg.Hierarchy(cfg, None, device=-1)
+    O = OracleHierarchy(cfg, None, build_smoothers=False)
+    for l in range(H.L):
+        assert H.info[l]["N"] == O.levels[l].N and H.info[l]["dim"] == 3
+        assert _rel(H.csr(l, 0), O.A[l]) < 1e-13
+        if l:
+            assert _rel(H.csr(l, 1), O.P[l]) < 1e-15
+            assert _rel(H.csr(l, 2), O.R[l]) < 1e-15
+    f = inputs.body_force(cfg)
+    b = H.csr(H.L - 1, 3) @ f.ravel() + fsgmg.export_vector(H.h, H.L - 1, 0)
+    bo = O.rhs(f)
+    assert np.allclose(b, bo, rtol=0, atol=1e-13 * abs(bo).max())
+    fsgmg.build_fs_as_blocks(H.h, core=cfg["core"], halo=cfg["halo"])
+    ptr, dofs, owner = fsgmg.export_blocks(H.h, 1)
+    blocks, _ = build_blocks(O.levels[1], cfg["core"], cfg["halo"])
+    assert len(ptr) - 1 == len(blocks)
+    for j, I in enumerate(blocks):
+        assert np.array_equal(dofs[ptr[j]:ptr[j + 1]], I)
+    assert np.array_equal(owner, owners(O.levels[1].N, blocks))
+    H.close()
+
+
 def test_error_paths():
     cfg = inputs.with_levels(inputs.config("c1"), 2)
     bad = dict(cfg, E=-1.0)
