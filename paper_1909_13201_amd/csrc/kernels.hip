@@ -584,14 +584,15 @@ __global__ __launch_bounds__(kThreads) void k_gather_blocks(const int32_t* __res
 // result[:, sigma[q]]) that the owned-row extraction applies, instead of
 // column swaps over the whole matrix.
 using f64x4 = __attribute__((__vector_size__(4 * sizeof(double)))) double;
-constexpr int kPanel = 16;
+constexpr int kPanel = 16;      // LDS strip width
+constexpr int kOuterPanel = 64; // columns per pass over the block
 
-template <int NB>
+template <int NB, int NO>
 __global__ __launch_bounds__(kThreads) void k_invert_blocked(
     const int32_t* __restrict__ jlist, const int64_t* __restrict__ dof_ptr,
     const int64_t* __restrict__ doff, const int64_t* __restrict__ soff, double* __restrict__ dense,
     int32_t* __restrict__ sigma_all, int32_t* __restrict__ status) {
-  static_assert(NB % 16 == 0, "panel width must be a multiple of the tile");
+  static_assert(NB == 16 && NO % NB == 0, "strip of one tile, outer panel of whole strips");
   constexpr int LDT = NB + 1;   // LDS row stride (doubles) of the strip
   constexpr int NW = kThreads / 64;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -605,12 +606,18 @@ __global__ __launch_bounds__(kThreads) void k_invert_blocked(
   int* widx = reinterpret_cast<int*>(wval + NW);      // NW
   int* piv = widx + NW;                               // np
   int* sig = piv + np;                                // np
+  int* swl = sig + np;                                // 2 NB: rows receiving
+  int* swv = swl + 2 * NB;                            // 2 NB: their source rows
+  int* swn = swv + 2 * NB;                            // 1
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int lr = lane & 15, lg = lane >> 4;
   const int ntile = np / 16;
 
-  for (int k0 = 0; k0 < np; k0 += NB) {
-    const int nbk = min(NB, np - k0);   // NB or 16 on the last panel
+  for (int K0 = 0; K0 < np; K0 += NO) {
+  const int nko = min(NO, np - K0);   // a multiple of 16
+  const int u0 = K0 / 16, u1 = u0 + nko / 16;   // tiles of the outer panel
+  for (int k0 = K0; k0 < K0 + nko; k0 += NB) {
+    const int nbk = NB;
     for (int e = tid; e < np * nbk; e += kThreads) {
       const int r = e / nbk, q = e - r * nbk;
       T[r * LDT + q] = a[(int64_t)r * np + k0 + q];
@@ -655,34 +662,81 @@ __global__ __launch_bounds__(kThreads) void k_invert_blocked(
       }
       const int p = bi;
       if (tid == 0) piv[c] = p;
-      if (p != c) {
-        for (int q = tid; q < nbk; q += kThreads) {
-          const double t0 = T[c * LDT + q];
-          T[c * LDT + q] = T[p * LDT + q];
-          T[p * LDT + q] = t0;
-        }
-        for (int q = tid; q < np - nbk; q += kThreads) {
-          const int cc = q < k0 ? q : q + nbk;
-          const double t0 = a[(int64_t)c * np + cc];
-          a[(int64_t)c * np + cc] = a[(int64_t)p * np + cc];
-          a[(int64_t)p * np + cc] = t0;
-        }
+      // every thread takes the pivot row and row c into registers, then the
+      // interchange and the elimination are one pass: position c receives
+      // the scaled pivot row, position p the eliminated old row c, every
+      // other row is eliminated in place (rows are owned by single threads)
+      double prow[NB], crow[NB];
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        prow[q] = T[p * LDT + q];
+        crow[q] = T[c * LDT + q];
       }
       __syncthreads();
-      const double d = 1.0 / T[c * LDT + kk];
-      if (tid < nbk) rowc[tid] = (tid == kk) ? d : T[c * LDT + tid] * d;
-      __syncthreads();
+      const double d = 1.0 / prow[kk];
+      double rc[NB];
+#pragma unroll
+      for (int q = 0; q < NB; ++q) rc[q] = (q == kk) ? d : prow[q] * d;
       for (int r = tid; r < np; r += kThreads) {
         double* Tr = T + r * LDT;
         if (r == c) {
-          for (int q = 0; q < nbk; ++q) Tr[q] = rowc[q];
+#pragma unroll
+          for (int q = 0; q < NB; ++q) Tr[q] = rc[q];
+        } else if (r == p) {
+          const double t = crow[kk];
+#pragma unroll
+          for (int q = 0; q < NB; ++q) Tr[q] = (q == kk ? 0.0 : crow[q]) - t * rc[q];
         } else {
           const double t = Tr[kk];
-          for (int q = 0; q < nbk; ++q) Tr[q] = (q == kk ? 0.0 : Tr[q]) - t * rowc[q];
+#pragma unroll
+          for (int q = 0; q < NB; ++q) Tr[q] = (q == kk ? 0.0 : Tr[q]) - t * rc[q];
         }
       }
       __syncthreads();
     }
+    // The strip's interchanges, applied to the rest of the block at once:
+    // their composition moves at most 2 NB rows; new row L[x] = old row V[x].
+    if (tid == 0) {
+      int ns = 0;
+      for (int kk = 0; kk < nbk; ++kk) {
+        const int c = k0 + kk, p = piv[c];
+        if (p == c) continue;
+        int ic = -1, ip = -1;
+        for (int x = 0; x < ns; ++x) {
+          if (swl[x] == c) ic = x;
+          if (swl[x] == p) ip = x;
+        }
+        if (ic < 0) {
+          swl[ns] = c;
+          swv[ns] = c;
+          ic = ns++;
+        }
+        if (ip < 0) {
+          swl[ns] = p;
+          swv[ns] = p;
+          ip = ns++;
+        }
+        const int t = swv[ic];
+        swv[ic] = swv[ip];
+        swv[ip] = t;
+      }
+      swn[0] = ns;
+    }
+    __syncthreads();
+    {
+      const int ns = swn[0];
+      for (int col = tid; col < np - nbk; col += kThreads) {
+        const int cc = col < k0 ? col : col + nbk;
+        double v[2 * NB];
+#pragma unroll
+        for (int x = 0; x < 2 * NB; ++x)
+          if (x < ns) v[x] = a[(int64_t)swv[x] * np + cc];
+#pragma unroll
+        for (int x = 0; x < 2 * NB; ++x)
+          if (x < ns) a[(int64_t)swl[x] * np + cc] = v[x];
+      }
+    }
+    __syncthreads();
     // the strip's final values, then T - E_K in LDS for the update
     for (int e = tid; e < np * nbk; e += kThreads) {
       const int r = e / nbk, q = e - r * nbk;
@@ -691,15 +745,15 @@ __global__ __launch_bounds__(kThreads) void k_invert_blocked(
       if (r == k0 + q) T[r * LDT + q] = v - 1.0;
     }
     __syncthreads();
-    // rank-nbk update of every column tile outside the panel
-    const int t0 = k0 / 16, t1 = t0 + nbk / 16;
-    for (int J = wv; J < ntile; J += NW) {
-      if (J >= t0 && J < t1) continue;
+    // rank-16 update of the outer panel's other column tiles (one wavefront
+    // per tile); the columns beyond the outer panel wait for its end
+    const int ts = k0 / 16;
+    for (int J = u0 + wv; J < u1; J += NW) {
+      if (J == ts) continue;
       const int c0 = J * 16 + lr;
       double bq[NB / 4];
 #pragma unroll
-      for (int q = 0; q < NB / 4; ++q)
-        bq[q] = (4 * q < nbk) ? a[(int64_t)(k0 + 4 * q + lg) * np + c0] : 0.0;
+      for (int q = 0; q < NB / 4; ++q) bq[q] = a[(int64_t)(k0 + 4 * q + lg) * np + c0];
       // accumulator layout of v_mfma_f64_16x16x4f64: lane (lr, lg) holds
       // rows lg, lg + 4, lg + 8, lg + 12 of column lr
       for (int it = 0; it < ntile; ++it) {
@@ -710,12 +764,45 @@ __global__ __launch_bounds__(kThreads) void k_invert_blocked(
         const double* Tt = T + (it * 16 + lr) * LDT + lg;
 #pragma unroll
         for (int q = 0; q < NB / 4; ++q)
-          if (4 * q < nbk) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Tt[4 * q], bq[q], acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Tt[4 * q], bq[q], acc, 0, 0, 0);
 #pragma unroll
         for (int r = 0; r < 4; ++r) a[(int64_t)(r0 + 4 * r) * np + c0] = acc[r];
       }
     }
     __syncthreads();
+  }
+  // The outer panel now holds T = [-A_iK A_KK^-1 ; A_KK^-1] for its nko pivot
+  // rows K (all its row interchanges were applied to whole rows as they
+  // happened; an interchange never involves an earlier pivot row, so they
+  // commute with the earlier eliminations).  Every column tile outside it
+  // takes A[:, j] += (T - E_K) A[K, j] in one rank-nko pass: the block is
+  // streamed once per NO columns instead of once per strip.
+  for (int J = wv; J < ntile; J += NW) {
+    if (J >= u0 && J < u1) continue;
+    const int c0 = J * 16 + lr;
+    double bq[NO / 4];
+#pragma unroll
+    for (int q = 0; q < NO / 4; ++q)
+      bq[q] = (4 * q < nko) ? a[(int64_t)(K0 + 4 * q + lg) * np + c0] : 0.0;
+    for (int it = 0; it < ntile; ++it) {
+      const int r0 = it * 16 + lg;
+      const int ra = it * 16 + lr;   // A-operand row of this lane
+      f64x4 acc;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[r] = a[(int64_t)(r0 + 4 * r) * np + c0];
+      const double* Ta = a + (int64_t)ra * np + K0 + lg;
+#pragma unroll
+      for (int q = 0; q < NO / 4; ++q) {
+        if (4 * q < nko) {
+          const double t = Ta[4 * q] - (ra == K0 + 4 * q + lg ? 1.0 : 0.0);
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(t, bq[q], acc, 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) a[(int64_t)(r0 + 4 * r) * np + c0] = acc[r];
+    }
+  }
+  __syncthreads();
   }
   // column permutation that undoes the row interchanges (applied in
   // reverse order of the pivot steps)
@@ -1254,7 +1341,7 @@ void launch_gather_blocks(const int32_t* jlist, int64_t nb, const BlocksView& B,
 
 size_t invert_blocks_lds(int np_max) {
   return (size_t)np_max * (kPanel + 1) * 8 + (size_t)kPanel * 8 + (kThreads / 64) * 12 +
-         (size_t)np_max * 8;
+         (size_t)np_max * 8 + (size_t)(4 * kPanel + 1) * 4;
 }
 
 void launch_invert_blocks(const int32_t* jlist, int64_t nb, const int64_t* dof_ptr,
@@ -1262,7 +1349,7 @@ void launch_invert_blocks(const int32_t* jlist, int64_t nb, const int64_t* dof_p
                           int32_t* sigma, int32_t* status, int max_n, hipStream_t s) {
   if (nb <= 0) return;
   const size_t sm = invert_blocks_lds((max_n + 15) & ~15);
-  hipLaunchKernelGGL((k_invert_blocked<kPanel>), dim3((unsigned)nb), dim3(kThreads), sm, s, jlist,
+  hipLaunchKernelGGL((k_invert_blocked<kPanel, kOuterPanel>), dim3((unsigned)nb), dim3(kThreads), sm, s, jlist,
                      dof_ptr, dense_off, sigma_off, dense, sigma, status);
 }
 

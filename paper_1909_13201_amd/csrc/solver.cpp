@@ -224,9 +224,31 @@ struct DevBOp {
   bool ready = false;
 };
 
+// Device factorization plan of one level's Schwarz blocks: the blocks in
+// decreasing size, cut into chunks of at most 1 GiB of dense FP64 scratch
+// (small and large blocks never share a chunk: the LDS of a launch is set by
+// its largest block), with the per-chunk offsets uploaded once; the scratch
+// stays allocated and each level is factored on its own stream.
+struct FactorPlan {
+  struct Chunk {
+    int64_t b0, b1, off;   // list range, position of its offsets in `offs`
+    int max_n;
+  };
+  bool ready = false;
+  std::vector<Chunk> chunks;
+  int32_t* jlist = nullptr;
+  int64_t* offs = nullptr;
+  double* dense = nullptr;
+  int32_t* sigma = nullptr;
+  int32_t* status = nullptr;
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+};
+
 struct DLevel {
   int64_t N = 0, nnz = 0;
   DevBOp A, AT;
+  FactorPlan fp;
   int64_t* rp = nullptr;
   int32_t* col = nullptr;
   double* val = nullptr;
@@ -355,9 +377,25 @@ struct fsgmg_hierarchy {
     HIPCHECK(hipMemset(p, 0, (size_t)n * sizeof(T)));
     return p;
   }
+  hipEvent_t factor_start = nullptr;
+  // release device memory obtained by dalloc before the handle ends
+  void dfree(void* p) {
+    if (!p) return;
+    auto it = std::find(allocs.begin(), allocs.end(), p);
+    if (it != allocs.end()) {
+      (void)hipFree(p);
+      allocs.erase(it);
+    }
+  }
+
   ~fsgmg_hierarchy() {
     if (device >= 0) {
       (void)hipSetDevice(device);
+      for (DLevel& d : dl) {
+        if (d.fp.stream) (void)hipStreamDestroy(d.fp.stream);
+        if (d.fp.done) (void)hipEventDestroy(d.fp.done);
+      }
+      if (factor_start) (void)hipEventDestroy(factor_start);
       for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
       invalidate_graphs();
       if (cap_stream) (void)hipStreamDestroy(cap_stream);
@@ -702,96 +740,124 @@ void upload_blocks(fsgmg_hierarchy& h, int l) {
     d.tb32 = h.zeros<float>(std::max<int64_t>(ntot, 1));
 }
 
-void factor_blocks(fsgmg_hierarchy& h, int l) {
+void plan_factor(fsgmg_hierarchy& h, int l) {
   const BlockSet& bs = h.blocks[l];
   DLevel& d = h.dl[l];
+  FactorPlan& fp = d.fp;
+  for (void* q : {(void*)fp.jlist, (void*)fp.offs, (void*)fp.dense, (void*)fp.sigma,
+                  (void*)fp.status})
+    h.dfree(q);
+  fp.ready = false;
+  fp.chunks.clear();
+  fp.jlist = nullptr;
+  fp.offs = nullptr;
+  fp.dense = nullptr;
+  fp.sigma = nullptr;
+  fp.status = nullptr;
   const int64_t nb = bs.nblk();
-  if (nb == 0) return;
+  if (nb == 0) {
+    fp.ready = true;
+    return;
+  }
   auto padded = [](int64_t n) { return (n + 15) & ~(int64_t)15; };
   int max_lds = 0;
   HIPCHECK(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h.device));
   if (invert_blocks_lds((int)padded(d.bv.max_n)) > (size_t)max_lds)
     throw Fail{FSGMG_EINVAL, "Schwarz block of " + std::to_string(d.bv.max_n) +
                                  " unknowns exceeds the LDS of one workgroup"};
-  // Size buckets: the LDS of a launch is set by its largest block, so blocks
-  // that fit three workgroups per CU (np <= 384: 55 KB) are factored apart
-  // from larger ones (enlarged interface blocks).  Inside a bucket, chunks
-  // of at most 1 GiB of dense FP64 scratch, larger blocks first.
+  // np <= 384: 55 KB of LDS, three workgroups per CU
   constexpr int64_t kSmallNp = 384;
   std::vector<int32_t> order(nb);
   for (int64_t j = 0; j < nb; ++j) order[j] = (int32_t)j;
   std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
     return bs.ptr[a + 1] - bs.ptr[a] > bs.ptr[b + 1] - bs.ptr[b];
   });
-  struct Chunk { int64_t b0, b1; int max_n; };
-  std::vector<Chunk> chunks;
   const size_t budget = (size_t)1 << 30;
   size_t maxchunk = 0, maxsig = 0;
+  std::vector<int64_t> hoff;
   {
     size_t acc = 0, sacc = 0;
     int64_t b0 = 0;
     bool big = true;
-    for (int64_t b = 0; b < nb; ++b) {
-      const int64_t n = bs.ptr[order[b] + 1] - bs.ptr[order[b]];
-      const int64_t np = padded(n);
-      const bool isbig = np > kSmallNp;
-      if (b > b0 && (acc + (size_t)(np * np * 8) > budget || isbig != big)) {
-        chunks.push_back({b0, b, (int)(bs.ptr[order[b0] + 1] - bs.ptr[order[b0]])});
-        maxchunk = std::max(maxchunk, acc);
-        maxsig = std::max(maxsig, sacc);
-        acc = sacc = 0;
-        b0 = b;
+    auto close = [&](int64_t b1) {
+      const int64_t cnt = b1 - b0;
+      FactorPlan::Chunk c{b0, b1, (int64_t)hoff.size(),
+                          (int)(bs.ptr[order[b0] + 1] - bs.ptr[order[b0]])};
+      const size_t base = hoff.size();
+      hoff.resize(base + 2 * (cnt + 1), 0);
+      for (int64_t b = 0; b < cnt; ++b) {
+        const int32_t j = order[b0 + b];
+        const int64_t np = padded(bs.ptr[j + 1] - bs.ptr[j]);
+        hoff[base + b + 1] = hoff[base + b] + np * np;
+        hoff[base + cnt + 1 + b + 1] = hoff[base + cnt + 1 + b] + np;
       }
+      fp.chunks.push_back(c);
+      maxchunk = std::max(maxchunk, acc);
+      maxsig = std::max(maxsig, sacc);
+      acc = sacc = 0;
+      b0 = b1;
+    };
+    for (int64_t b = 0; b < nb; ++b) {
+      const int64_t np = padded(bs.ptr[order[b] + 1] - bs.ptr[order[b]]);
+      const bool isbig = np > kSmallNp;
+      if (b > b0 && (acc + (size_t)(np * np * 8) > budget || isbig != big)) close(b);
       big = isbig;
       acc += (size_t)(np * np * 8);
       sacc += (size_t)np * 4;
     }
-    chunks.push_back({b0, nb, (int)(bs.ptr[order[b0] + 1] - bs.ptr[order[b0]])});
-    maxchunk = std::max(maxchunk, acc);
-    maxsig = std::max(maxsig, sacc);
+    close(nb);
   }
-  double* dense = (double*)h.dalloc(maxchunk);
-  int32_t* sigma = (int32_t*)h.dalloc(maxsig);
-  int32_t* jlist = (int32_t*)h.dalloc((size_t)nb * sizeof(int32_t));
-  int64_t* offs = (int64_t*)h.dalloc((size_t)2 * (nb + 1) * sizeof(int64_t));
-  int32_t* status = h.zeros<int32_t>(nb);
-  HIPCHECK(hipMemcpyAsync(jlist, order.data(), (size_t)nb * sizeof(int32_t), hipMemcpyHostToDevice,
-                          h.stream));
-  std::vector<int64_t> hoff;
-  for (const Chunk& c : chunks) {
-    const int64_t cnt = c.b1 - c.b0;
-    hoff.assign((size_t)2 * (cnt + 1), 0);
-    for (int64_t b = 0; b < cnt; ++b) {
-      const int32_t j = order[c.b0 + b];
-      const int64_t np = padded(bs.ptr[j + 1] - bs.ptr[j]);
-      hoff[b + 1] = hoff[b] + np * np;
-      hoff[cnt + 1 + b + 1] = hoff[cnt + 1 + b] + np;
+  fp.jlist = h.upload(order);
+  fp.offs = h.upload(hoff);
+  fp.dense = (double*)h.dalloc(maxchunk);
+  fp.sigma = (int32_t*)h.dalloc(maxsig);
+  fp.status = (int32_t*)h.dalloc((size_t)nb * sizeof(int32_t));
+  if (!fp.stream) HIPCHECK(hipStreamCreateWithFlags(&fp.stream, hipStreamNonBlocking));
+  if (!fp.done) HIPCHECK(hipEventCreateWithFlags(&fp.done, hipEventDisableTiming));
+  fp.ready = true;
+}
+
+// Gather, invert and extract the blocks of every level l >= 1: each level on
+// its own stream (the small coarse levels, one block per CU, overlap the fine
+// one), joined back into the handle's stream.
+void factor_blocks(fsgmg_hierarchy& h) {
+  if (!h.factor_start) HIPCHECK(hipEventCreateWithFlags(&h.factor_start, hipEventDisableTiming));
+  HIPCHECK(hipEventRecord(h.factor_start, h.stream));
+  for (int l = 1; l < h.L; ++l) {
+    DLevel& d = h.dl[l];
+    FactorPlan& fp = d.fp;
+    if (!fp.ready) plan_factor(h, l);
+    const int64_t nb = h.blocks[l].nblk();
+    if (nb == 0) continue;
+    HIPCHECK(hipStreamWaitEvent(fp.stream, h.factor_start, 0));
+    HIPCHECK(hipMemsetAsync(fp.status, 0, (size_t)nb * sizeof(int32_t), fp.stream));
+    for (const FactorPlan::Chunk& c : fp.chunks) {
+      const int64_t cnt = c.b1 - c.b0;
+      const int32_t* jl = fp.jlist + c.b0;
+      const int64_t* doff = fp.offs + c.off;
+      const int64_t* soff = doff + cnt + 1;
+      launch_gather_blocks(jl, cnt, d.bv, d.rp, d.col, d.val, doff, fp.dense, fp.stream);
+      launch_invert_blocks(jl, cnt, d.bv.dof_ptr, doff, soff, fp.dense, fp.sigma, fp.status,
+                           c.max_n, fp.stream);
+      launch_extract_owned(jl, cnt, d.bv, doff, soff, fp.dense, fp.sigma, wprec(h.sopt.prec),
+                           d.W, fp.stream);
+      HIPCHECK(hipGetLastError());
     }
-    HIPCHECK(hipMemcpyAsync(offs, hoff.data(), hoff.size() * sizeof(int64_t), hipMemcpyHostToDevice,
-                            h.stream));
-    const int32_t* jl = jlist + c.b0;
-    const int64_t* doff = offs;
-    const int64_t* soff = offs + cnt + 1;
-    launch_gather_blocks(jl, cnt, d.bv, d.rp, d.col, d.val, doff, dense, h.stream);
-    launch_invert_blocks(jl, cnt, d.bv.dof_ptr, doff, soff, dense, sigma, status, c.max_n,
-                         h.stream);
-    launch_extract_owned(jl, cnt, d.bv, doff, soff, dense, sigma, wprec(h.sopt.prec), d.W, h.stream);
-    HIPCHECK(hipGetLastError());
-    // the offsets are rewritten for the next chunk
-    HIPCHECK(hipStreamSynchronize(h.stream));
+    HIPCHECK(hipEventRecord(fp.done, fp.stream));
   }
-  std::vector<int32_t> st(nb);
-  HIPCHECK(hipMemcpy(st.data(), status, nb * sizeof(int32_t), hipMemcpyDeviceToHost));
-  // scratch is released at once (bump allocations are freed in order)
-  for (void* p : {(void*)dense, (void*)sigma, (void*)jlist, (void*)offs, (void*)status}) {
-    auto it = std::find(h.allocs.begin(), h.allocs.end(), p);
-    if (it != h.allocs.end()) {
-      (void)hipFree(p);
-      h.allocs.erase(it);
-    }
+  for (int l = 1; l < h.L; ++l)
+    if (h.blocks[l].nblk() > 0) HIPCHECK(hipStreamWaitEvent(h.stream, h.dl[l].fp.done, 0));
+  HIPCHECK(hipStreamSynchronize(h.stream));
+  for (int l = 1; l < h.L; ++l) {
+    const int64_t nb = h.blocks[l].nblk();
+    if (nb == 0) continue;
+    std::vector<int32_t> st(nb);
+    HIPCHECK(hipMemcpy(st.data(), h.dl[l].fp.status, nb * sizeof(int32_t), hipMemcpyDeviceToHost));
+    for (int64_t j = 0; j < nb; ++j)
+      if (st[j])
+        throw Fail{FSGMG_ESINGULAR, "singular Schwarz block " + std::to_string(j) + " on level " +
+                                        std::to_string(l)};
   }
-  for (int64_t j = 0; j < nb; ++j)
-    if (st[j]) throw Fail{FSGMG_ESINGULAR, "singular Schwarz block " + std::to_string(j) + " on level " + std::to_string(l)};
 }
 
 // ---------------------------------------------------------------------------
@@ -1322,10 +1388,13 @@ fsgmg_status build_fs_as_blocks(fsgmg_h h, const fsgmg_smoother_opts* opts) {
       }
       h->have_blocks = true;
       if (!h->host_only())
-        for (int l = 1; l < h->L; ++l) upload_blocks(*h, l);
+        for (int l = 1; l < h->L; ++l) {
+          upload_blocks(*h, l);
+          h->dl[l].fp.ready = false;   // new index sets: new factorization plan
+        }
     }
     if (h->host_only()) return FSGMG_OK;
-    for (int l = 1; l < h->L; ++l) factor_blocks(*h, l);
+    factor_blocks(*h);
     // launch shapes depend on the block structure only: keep them while the
     // index sets and precision are unchanged, so rebuilds stay reproducible
     if (!same_sets || !h->tuned) autotune(*h);
