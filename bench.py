@@ -31,6 +31,9 @@ sys.path.insert(0, ROOT)
 METRIC = "solves/s to 1e-10 rel. residual, mixed vs FP64 FS-AS-GMG-GMRES; V-cycles/s"
 HBM_PEAK_GBS = 8000.0
 WORKLOADS = {
+    "c5": "differentiation: 2D channel of c2 at 4 levels (64x64 finest), one backward-Euler "
+          "step dt=1/32, batch of 32 seeded loads and (E, mu) log-uniform in "
+          "[1e3,1e5] x [1e-3,1e-1]",
     "c2": "2D straight channel, coarse 8x8 graded -> finest 128x128 Q2/Q1 (5 levels, "
           "281,095 unknowns), solid walls E=1e4 nu=0.45, fluid mu=3.5e-3, Oseen about a "
           "seeded field of amplitude 1 with SUPG, FS-AS on 4x4-element cores with the "
@@ -161,6 +164,67 @@ def cpu_baseline(cfg, w, f):
                        % (cfg["name"], info["iters"], t, t_setup))
 
 
+def grad_bench(cfg, args):
+    """Differentiation workload: the batch of seeded (f, E, mu) samples through
+    FSISolve (forward: update_params + build_fs_as_blocks + assemble_load +
+    gmres_solve; backward: adjoint_solve + load_adjoint + param_grad), once
+    with FP64 block inverses and once with FP32 ones.  Accuracy against the
+    oracle's gradients is checked by the GPU tests; here: throughput and the
+    FP32 / FP64 agreement of every gradient.  J = sum of the outlet
+    x-velocities (a linear functional of the solution)."""
+    import torch
+    from paper_1909_13201_amd import fsgmg, inputs
+    from paper_1909_13201_amd.autograd import FSISolve
+    batch = int(cfg.get("batch", 32))
+    w = inputs.advecting_field(cfg)
+    H = fsgmg.Hierarchy(cfg, w, device=0)
+    dev = torch.device("cuda:0")
+    params = inputs.sample_parameters(cfg, batch)
+    loads = inputs.sample_loads(cfg, batch)
+    # J = sum of the x-velocities on the outlet face (x = max, node lines x-fastest)
+    nx = inputs.finest_nodes_shape(cfg)[0]
+    fin = H.info[-1]
+    outlet = np.arange(nx - 1, fin["N2"], nx)
+    cnp = np.zeros(H.N)
+    cnp[fin["off_u"] + fin["dim"] * outlet] = 1.0
+    c = torch.tensor(cnp, device=dev)
+    rng = np.random.default_rng(7)
+    probe = torch.tensor(rng.standard_normal(loads[0].size), device=dev)
+
+    def one(i, prec):
+        f = torch.tensor(loads[i].ravel(), dtype=torch.float64, device=dev, requires_grad=True)
+        E = torch.tensor(float(params[i][0]), dtype=torch.float64, requires_grad=True)
+        mu = torch.tensor(float(params[i][1]), dtype=torch.float64, requires_grad=True)
+        x = FSISolve.apply(f, E, mu, H, dict(prec=prec, rtol=cfg["rtol"]))
+        J = (c * x).sum()
+        J.backward()
+        return (float(J.detach()), float(E.grad), float(mu.grad), float((f.grad * probe).sum()))
+
+    res, out = {}, {}
+    for prec in ("fp64", "fp32"):
+        H._blocks_ok = False
+        one(0, prec)                                   # warm-up: plan, graphs, tuning
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res[prec] = [one(i, prec) for i in range(batch)]
+        torch.cuda.synchronize()
+        out[prec] = batch / (time.perf_counter() - t0)
+    a, b = np.array(res["fp64"]), np.array(res["fp32"])
+    rel = np.abs(a - b) / np.maximum(np.abs(a), 1e-300)
+    line = dict(metric="differentiated solves/s (forward + adjoint + gradients, blocks refactored per sample)",
+                value=round(out["fp32"], 3), unit="samples/s", n_gpus=1, steps=batch, warmup=1,
+                ms_per_step=round(1e3 / out["fp32"], 3), higher_is_better=True, scaling="weak",
+                vs_baseline=None, dtype="f32 smoother + f64 Krylov", data="synthetic",
+                config=dict(workload=WORKLOADS.get(cfg["name"], cfg["name"]), name=cfg["name"],
+                            levels=int(cfg["n_levels"]), unknowns=H.N, batch=batch),
+                fp64_samples_per_s=round(out["fp64"], 3),
+                max_rel_diff_fp32_vs_fp64=dict(J=float(rel[:, 0].max()), dJ_dE=float(rel[:, 1].max()),
+                                               dJ_dmu=float(rel[:, 2].max()),
+                                               dJ_df_probe=float(rel[:, 3].max())))
+    H.close()
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -184,6 +248,9 @@ def main():
     cfg = inputs.config(args.config)
     if args.levels:
         cfg = inputs.with_levels(cfg, args.levels)
+    if cfg.get("batch"):
+        grad_bench(cfg, args)
+        return
     w = inputs.advecting_field(cfg)
     f = inputs.body_force(cfg)
     rtol = cfg["rtol"]

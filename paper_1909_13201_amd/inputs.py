@@ -100,6 +100,10 @@ def config(name: str) -> dict:
             # period, Section 4): makes u^s = dd/dt so the outlet flux depends on
             # the wall stiffness (the steady problem is one-way coupled)
             cfg["dt"] = 1.0 / 32.0
+            # samples pair E = 1e5 with mu = 1e-3: ||A|| ||x|| / ||b|| reaches ~1e6,
+            # so an FP64 iterate cannot push the relative residual much below
+            # 1e-10 (rounding of x alone); 1e-9 is attainable for every sample
+            cfg["rtol"] = 1e-9
     elif name == "c3":
         bc_d, bc_u = _channel_bcs()
         yb = [0.0, 0.05, 0.1, 0.3, 0.5, 0.7, 0.9, 0.95, 1.0]
