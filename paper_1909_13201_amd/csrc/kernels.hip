@@ -1073,100 +1073,212 @@ __global__ __launch_bounds__(kThreads) void k_recombine(int64_t n, const double*
   if (o32) o32[r] = (float)v;
 }
 
-// Multi-workgroup Gauss-Jordan step for one large matrix (the coarse level).
-// Step k, part 1 (one workgroup): pivot search in column k over rows >= k,
-// row interchange, scaled pivot row and a copy of column k.
-constexpr int kGJThreads = 1024;
-__global__ __launch_bounds__(kGJThreads) void k_gj_pivot(double* __restrict__ a, int64_t n, int64_t k,
-                                                          double* __restrict__ colk,
-                                                          double* __restrict__ rowk,
-                                                          int32_t* __restrict__ piv,
-                                                          int32_t* __restrict__ status) {
-  __shared__ double rv[kGJThreads];
-  __shared__ int64_t ri[kGJThreads];
-  const int tid = threadIdx.x;
-  if (status[0]) return;
-  double best = -1.0;
-  int64_t bi = n;
-  for (int64_t i = k + tid; i < n; i += blockDim.x) {
-    const double v = fabs(a[i * n + k]);
-    if (v > best) {
-      best = v;
-      bi = i;
-    }
-  }
-  rv[tid] = best;
-  ri[tid] = bi;
+// Dense inverse of the coarse-level matrix: blocked Gauss-Jordan with partial
+// pivoting spread over the GPU.  The matrix is padded to np (multiple of 16)
+// with an identity tail.  Per panel of NB columns:
+//  * k_cgj_panel (one workgroup): the panel's NB scalar Gauss-Jordan steps in
+//    LDS (pivot = largest magnitude at or below the diagonal, smallest row on
+//    ties), the composition of its row interchanges applied to every other
+//    column, and the pivot rows of every other column saved in ybuf;
+//  * k_cgj_update (whole grid, one wavefront per 16-column x 64-row piece):
+//    A[:, j] += (T - E_K) ybuf[:, j] on v_mfma_f64_16x16x4f64, T the panel.
+// The interchanges are finally undone as a column permutation.
+constexpr int kCgjThreads = 1024;
+
+__global__ __launch_bounds__(kThreads) void k_dense_from_csr(int64_t n, int64_t np,
+                                                             const int64_t* __restrict__ rp,
+                                                             const int32_t* __restrict__ col,
+                                                             const double* __restrict__ val,
+                                                             double* __restrict__ a) {
+  const int64_t r = blockIdx.x;   // one workgroup per padded row
+  double* ar = a + r * np;
+  for (int64_t c = threadIdx.x; c < np; c += blockDim.x) ar[c] = (r >= n && c == r) ? 1.0 : 0.0;
   __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (tid < s) {
-      const double v2 = rv[tid + s];
-      const int64_t i2 = ri[tid + s];
-      if (v2 > rv[tid] || (v2 == rv[tid] && i2 < ri[tid])) {
-        rv[tid] = v2;
-        ri[tid] = i2;
+  if (r < n)
+    for (int64_t k = rp[r] + threadIdx.x; k < rp[r + 1]; k += blockDim.x) ar[col[k]] = val[k];
+}
+
+template <int NB>
+__global__ __launch_bounds__(kCgjThreads) void k_cgj_panel(double* __restrict__ a, int64_t np,
+                                                            int64_t k0, int32_t* __restrict__ piv,
+                                                            double* __restrict__ ybuf,
+                                                            int32_t* __restrict__ status) {
+  constexpr int LDT = NB + 1;
+  constexpr int NW = kCgjThreads / 64;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* T = reinterpret_cast<double*>(smem_raw);   // np x LDT
+  __shared__ double wval[NW];
+  __shared__ int widx[NW];
+  __shared__ int swl[2 * NB], swv[2 * NB], swn;
+  __shared__ int lpiv[NB];
+  if (status[0]) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int n = (int)np;
+  for (int e = tid; e < n * NB; e += kCgjThreads) {
+    const int r = e / NB, q = e - r * NB;
+    T[r * LDT + q] = a[(int64_t)r * np + k0 + q];
+  }
+  __syncthreads();
+  for (int kk = 0; kk < NB; ++kk) {
+    const int c = (int)k0 + kk;
+    double best = -1.0;
+    int bi = n;
+    for (int r = c + tid; r < n; r += kCgjThreads) {
+      const double v = fabs(T[r * LDT + kk]);
+      if (v > best) {
+        best = v;
+        bi = r;
+      }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double v2 = __shfl_xor(best, off, 64);
+      const int i2 = __shfl_xor(bi, off, 64);
+      if (v2 > best || (v2 == best && i2 < bi)) {
+        best = v2;
+        bi = i2;
+      }
+    }
+    if (lane == 0) {
+      wval[wv] = best;
+      widx[wv] = bi;
+    }
+    __syncthreads();
+    best = wval[0];
+    bi = widx[0];
+    for (int w = 1; w < NW; ++w)
+      if (wval[w] > best || (wval[w] == best && widx[w] < bi)) {
+        best = wval[w];
+        bi = widx[w];
+      }
+    if (!(best > 0.0)) {   // the same decision in every thread
+      if (tid == 0) status[0] = 1;
+      return;
+    }
+    const int p = bi;
+    if (tid == 0) lpiv[kk] = p;
+    double prow[NB], crow[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      prow[q] = T[p * LDT + q];
+      crow[q] = T[c * LDT + q];
+    }
+    __syncthreads();
+    const double d = 1.0 / prow[kk];
+    double rc[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) rc[q] = (q == kk) ? d : prow[q] * d;
+    for (int r = tid; r < n; r += kCgjThreads) {
+      double* Tr = T + r * LDT;
+      if (r == c) {
+#pragma unroll
+        for (int q = 0; q < NB; ++q) Tr[q] = rc[q];
+      } else if (r == p) {
+        const double t = crow[kk];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) Tr[q] = (q == kk ? 0.0 : crow[q]) - t * rc[q];
+      } else {
+        const double t = Tr[kk];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) Tr[q] = (q == kk ? 0.0 : Tr[q]) - t * rc[q];
       }
     }
     __syncthreads();
   }
-  const int64_t p = ri[0];
-  if (!(rv[0] > 0.0)) {
-    if (tid == 0) status[0] = 1;
-    return;
+  for (int e = tid; e < n * NB; e += kCgjThreads) {
+    const int r = e / NB, q = e - r * NB;
+    a[(int64_t)r * np + k0 + q] = T[r * LDT + q];
   }
-  if (tid == 0) piv[k] = (int32_t)p;
-  if (p != k)
-    for (int64_t c = tid; c < n; c += blockDim.x) {
-      const double t0 = a[k * n + c];
-      a[k * n + c] = a[p * n + c];
-      a[p * n + c] = t0;
-    }
-  __syncthreads();
-  const double d = 1.0 / a[k * n + k];
-  for (int64_t i = tid; i < n; i += blockDim.x) {
-    colk[i] = a[i * n + k];
-    rowk[i] = (i == k) ? d : a[k * n + i] * d;
-  }
-}
-
-// Step k, part 2 (whole grid): rank-1 elimination of every row but k.
-__global__ __launch_bounds__(kThreads) void k_gj_update(double* __restrict__ a, int64_t n, int64_t k,
-                                                        const double* __restrict__ colk,
-                                                        const double* __restrict__ rowk,
-                                                        const int32_t* __restrict__ status) {
-  if (status[0]) return;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n * n) return;
-  const int64_t i = e / n, c = e - i * n;
-  if (i == k)
-    a[e] = rowk[c];
-  else
-    a[e] = ((c == k) ? 0.0 : a[e]) - colk[i] * rowk[c];
-}
-
-// Undo the row interchanges as column interchanges (reverse order).
-__global__ __launch_bounds__(kGJThreads) void k_gj_colswap(double* __restrict__ a, int64_t n,
-                                                            const int32_t* __restrict__ piv,
-                                                            const int32_t* __restrict__ status) {
-  if (status[0]) return;
-  for (int64_t k = n - 1; k >= 0; --k) {
-    const int64_t p = piv[k];
-    if (p != k)
-      for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-        const double t0 = a[i * n + k];
-        a[i * n + k] = a[i * n + p];
-        a[i * n + p] = t0;
+  if (tid == 0) {
+    int ns = 0;
+    for (int kk = 0; kk < NB; ++kk) {
+      const int c = (int)k0 + kk, p = lpiv[kk];
+      piv[c] = p;
+      if (p == c) continue;
+      int ic = -1, ip = -1;
+      for (int x = 0; x < ns; ++x) {
+        if (swl[x] == c) ic = x;
+        if (swl[x] == p) ip = x;
       }
-    __syncthreads();
+      if (ic < 0) {
+        swl[ns] = c;
+        swv[ns] = c;
+        ic = ns++;
+      }
+      if (ip < 0) {
+        swl[ns] = p;
+        swv[ns] = p;
+        ip = ns++;
+      }
+      const int t = swv[ic];
+      swv[ic] = swv[ip];
+      swv[ip] = t;
+    }
+    swn = ns;
+  }
+  __syncthreads();
+  // other columns: apply the interchanges (new row swl[x] = old row swv[x])
+  // and keep their pivot rows for the update
+  const int ns = swn;
+  for (int col = tid; col < n; col += kCgjThreads) {
+    if (col >= k0 && col < k0 + NB) continue;
+    double v[2 * NB];
+#pragma unroll
+    for (int x = 0; x < 2 * NB; ++x)
+      if (x < ns) v[x] = a[(int64_t)swv[x] * np + col];
+#pragma unroll
+    for (int x = 0; x < 2 * NB; ++x)
+      if (x < ns) a[(int64_t)swl[x] * np + col] = v[x];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) ybuf[(int64_t)q * np + col] = a[(k0 + q) * np + col];
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_transpose(const double* __restrict__ a,
-                                                        double* __restrict__ at, int64_t n) {
+template <int NB>
+__global__ __launch_bounds__(kThreads) void k_cgj_update(double* __restrict__ a, int64_t np,
+                                                         int64_t k0, const double* __restrict__ ybuf,
+                                                         const int32_t* __restrict__ status) {
+  constexpr int kRowTiles = 4;   // 64 rows per wavefront
+  if (status[0]) return;
+  const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+  const int64_t item = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  const int64_t ntile = np / 16;
+  const int64_t nchunk = (ntile + kRowTiles - 1) / kRowTiles;
+  if (item >= ntile * nchunk) return;
+  const int64_t J = item / nchunk, ch = item % nchunk;
+  const int64_t c0 = J * 16 + lr;
+  const bool in_panel = c0 >= k0 && c0 < k0 + NB;   // the panel's columns are final
+  double bq[NB / 4];
+#pragma unroll
+  for (int q = 0; q < NB / 4; ++q) bq[q] = ybuf[(int64_t)(4 * q + lg) * np + c0];
+  for (int64_t it = ch * kRowTiles; it < min(ntile, (ch + 1) * kRowTiles); ++it) {
+    const int64_t r0 = it * 16 + lg, ra = it * 16 + lr;
+    f64x4 acc;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r] = a[(r0 + 4 * r) * np + c0];
+#pragma unroll
+    for (int q = 0; q < NB / 4; ++q) {
+      const int64_t kc = k0 + 4 * q + lg;
+      const double t = a[ra * np + kc] - (ra == kc ? 1.0 : 0.0);
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(t, bq[q], acc, 0, 0, 0);
+    }
+    if (!in_panel)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) a[(r0 + 4 * r) * np + c0] = acc[r];
+  }
+}
+
+// inverse[i][q] = a[i][sigma[q]] and its transpose, i, q < n
+__global__ __launch_bounds__(kThreads) void k_cgj_finish(const double* __restrict__ a, int64_t np,
+                                                         int64_t n, const int32_t* __restrict__ sigma,
+                                                         double* __restrict__ inv,
+                                                         double* __restrict__ invT) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n * n) return;
-  const int64_t i = e / n, c = e - i * n;
-  at[c * n + i] = a[e];
+  const int64_t i = e / n, q = e - i * n;
+  const double v = a[i * np + sigma[q]];
+  inv[e] = v;
+  invT[q * n + i] = v;
 }
 
 template <typename T>
@@ -1447,15 +1559,36 @@ void launch_masked_dot(const double* a, const uint8_t* mask, const double* b, in
   reduce(part, 1, out, false, s);
 }
 
-void launch_invert_dense(int64_t n, double* a, double* at, double* colk, double* rowk,
-                         int32_t* piv, int32_t* status, hipStream_t s) {
-  const unsigned gu = grid_for(n * n, kThreads);
-  for (int64_t k = 0; k < n; ++k) {
-    hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(kGJThreads), 0, s, a, n, k, colk, rowk, piv, status);
-    hipLaunchKernelGGL(k_gj_update, dim3(gu), dim3(kThreads), 0, s, a, n, k, colk, rowk, status);
+int coarse_panel_width(int64_t np, int max_lds) {
+  return (size_t)np * 9 * 8 <= (size_t)max_lds ? 8 : 4;
+}
+
+void launch_coarse_factor(int64_t n, int64_t np, const int64_t* rp, const int32_t* col,
+                          const double* val, double* a, double* ybuf, int32_t* piv,
+                          int32_t* status, int nb, hipStream_t s) {
+  hipLaunchKernelGGL(k_dense_from_csr, dim3((unsigned)np), dim3(kThreads), 0, s, n, np, rp, col, val,
+                     a);
+  const int64_t ntile = np / 16;
+  const int64_t items = ntile * ((ntile + 3) / 4);
+  const unsigned gu = grid_for(items * 64, kThreads);
+  const size_t sm = (size_t)np * (nb + 1) * sizeof(double);
+  for (int64_t k0 = 0; k0 < np; k0 += nb) {
+    if (nb == 8) {
+      hipLaunchKernelGGL((k_cgj_panel<8>), dim3(1), dim3(kCgjThreads), sm, s, a, np, k0, piv, ybuf,
+                         status);
+      hipLaunchKernelGGL((k_cgj_update<8>), dim3(gu), dim3(kThreads), 0, s, a, np, k0, ybuf, status);
+    } else {
+      hipLaunchKernelGGL((k_cgj_panel<4>), dim3(1), dim3(kCgjThreads), sm, s, a, np, k0, piv, ybuf,
+                         status);
+      hipLaunchKernelGGL((k_cgj_update<4>), dim3(gu), dim3(kThreads), 0, s, a, np, k0, ybuf, status);
+    }
   }
-  hipLaunchKernelGGL(k_gj_colswap, dim3(1), dim3(kGJThreads), 0, s, a, n, piv, status);
-  hipLaunchKernelGGL(k_transpose, dim3(gu), dim3(kThreads), 0, s, a, at, n);
+}
+
+void launch_coarse_finish(const double* a, int64_t np, int64_t n, const int32_t* sigma, double* inv,
+                          double* invT, hipStream_t s) {
+  const unsigned g = grid_for(n * n, kThreads);
+  if (g) hipLaunchKernelGGL(k_cgj_finish, dim3(g), dim3(kThreads), 0, s, a, np, n, sigma, inv, invT);
 }
 
 template <typename T>

@@ -151,12 +151,21 @@ void launch_extract_owned(const int32_t* jlist, int64_t nb, const BlocksView& B,
                           const int64_t* dense_off, const int64_t* sigma_off, const double* dense,
                           const int32_t* sigma, WPrec wp, void* W, hipStream_t s);
 
-// In-place inversion of one dense n x n FP64 matrix by Gauss-Jordan with
-// partial pivoting spread over the whole GPU (one pivot kernel and one
-// rank-1 update kernel per column); at receives the transpose of the
-// inverse; status[0] = 1 on a zero pivot (must be zero on entry).
-void launch_invert_dense(int64_t n, double* a, double* at, double* colk, double* rowk,
-                         int32_t* piv, int32_t* status, hipStream_t s);
+// Dense inverse of the coarse-level matrix (CSR, n rows) by blocked
+// Gauss-Jordan with partial pivoting spread over the GPU.  launch_coarse_factor
+// gathers the CSR into the work matrix a (np x np, np = n rounded up to 16,
+// identity tail) and factors it in panels of nb (8 or 4, coarse_panel_width)
+// columns; piv (np) receives the pivot row of every column, status[0] = 1 on
+// a zero pivot (must be 0 on entry); ybuf: nb x np scratch.  After the host
+// has turned piv into the column permutation sigma (inverse[:, q] =
+// a[:, sigma[q]]), launch_coarse_finish writes the n x n inverse and its
+// transpose.
+int coarse_panel_width(int64_t np, int max_lds);
+void launch_coarse_factor(int64_t n, int64_t np, const int64_t* rp, const int32_t* col,
+                          const double* val, double* a, double* ybuf, int32_t* piv,
+                          int32_t* status, int nb, hipStream_t s);
+void launch_coarse_finish(const double* a, int64_t np, int64_t n, const int32_t* sigma, double* inv,
+                          double* invT, hipStream_t s);
 
 // ---- coarse solve: y = Ainv * x (transpose: Ainv^T x), FP64 matrix ----
 template <typename TV>

@@ -378,6 +378,17 @@ struct fsgmg_hierarchy {
     return p;
   }
   hipEvent_t factor_start = nullptr;
+  // host copies of the level operators' values lag behind update_params on
+  // a device handle until a host consumer needs them
+  bool host_vals_stale = false;
+  void ensure_host_values() {
+    if (!host_vals_stale) return;
+    for (LevelOperator& op : ops)
+      for (size_t k = 0; k < op.A.val.size(); ++k)
+        op.A.val[k] = op.piece[0][k] + op.G * op.piece[1][k] + op.invlam * op.piece[2][k] +
+                      op.mu * op.piece[3][k];
+    host_vals_stale = false;
+  }
   // release device memory obtained by dalloc before the handle ends
   void dfree(void* p) {
     if (!p) return;
@@ -562,27 +573,41 @@ void upload_transfer(fsgmg_hierarchy& h, int l) {
 // dense FP64 copy of the coarse-level matrix, inverted on the device; the
 // transpose of the inverse is kept for the transposed V-cycle
 void build_coarse_inverse(fsgmg_hierarchy& h) {
-  const CsrHost& A = h.ops[0].A;
-  const int64_t n = A.nrows;
+  const int64_t n = h.ops[0].A.nrows;
   if (n > 20000) throw Fail{FSGMG_EINVAL, "coarse level too large for the dense inverse (n > 20000)"};
-  std::vector<double> dense((size_t)(n * n), 0.0);
-  for (int64_t i = 0; i < n; ++i)
-    for (int64_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k) dense[i * n + A.col[k]] = A.val[k];
+  const int64_t np = (n + 15) & ~(int64_t)15;
+  int max_lds = 0;
+  HIPCHECK(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h.device));
+  const int nb = coarse_panel_width(np, max_lds);
+  if ((size_t)np * (nb + 1) * 8 > (size_t)max_lds)
+    throw Fail{FSGMG_EINVAL, "coarse level too large for the panel factorization"};
   if (!h.coarse_inv) {
     h.coarse_inv = (double*)h.dalloc((size_t)(n * n) * sizeof(double));
     h.coarse_invT = (double*)h.dalloc((size_t)(n * n) * sizeof(double));
-    h.coarse_work = (double*)h.dalloc((size_t)(2 * n) * sizeof(double));
-    h.coarse_piv = (int32_t*)h.dalloc((size_t)(n + 1) * sizeof(int32_t));
+    h.coarse_work = (double*)h.dalloc((size_t)(np * np + 8 * np) * sizeof(double));
+    h.coarse_piv = (int32_t*)h.dalloc((size_t)(2 * np + 1) * sizeof(int32_t));
   }
-  HIPCHECK(hipMemcpy(h.coarse_inv, dense.data(), dense.size() * sizeof(double), hipMemcpyHostToDevice));
-  HIPCHECK(hipMemset(h.coarse_piv + n, 0, sizeof(int32_t)));
-  launch_invert_dense(n, h.coarse_inv, h.coarse_invT, h.coarse_work, h.coarse_work + n, h.coarse_piv,
-                      h.coarse_piv + n, h.stream);
+  int32_t* status = h.coarse_piv + 2 * np;
+  HIPCHECK(hipMemsetAsync(status, 0, sizeof(int32_t), h.stream));
+  const DLevel& C = h.dl[0];   // device CSR of level 0 (current parameter values)
+  launch_coarse_factor(n, np, C.rp, C.col, C.val, h.coarse_work, h.coarse_work + np * np,
+                       h.coarse_piv, status, nb, h.stream);
   HIPCHECK(hipGetLastError());
-  int32_t st = 0;
-  HIPCHECK(hipMemcpyAsync(&st, h.coarse_piv + n, sizeof(int32_t), hipMemcpyDeviceToHost, h.stream));
+  std::vector<int32_t> piv(np + 1);
+  HIPCHECK(hipMemcpyAsync(piv.data(), h.coarse_piv, np * sizeof(int32_t), hipMemcpyDeviceToHost,
+                          h.stream));
+  HIPCHECK(hipMemcpyAsync(piv.data() + np, status, sizeof(int32_t), hipMemcpyDeviceToHost, h.stream));
   HIPCHECK(hipStreamSynchronize(h.stream));
-  if (st) throw Fail{FSGMG_ESINGULAR, "coarse-level matrix is singular"};
+  if (piv[np]) throw Fail{FSGMG_ESINGULAR, "coarse-level matrix is singular"};
+  // the row interchanges, undone in reverse order, as a column permutation
+  std::vector<int32_t> sig(np);
+  for (int64_t c = 0; c < np; ++c) sig[c] = (int32_t)c;
+  for (int64_t c = np - 1; c >= 0; --c) std::swap(sig[c], sig[piv[c]]);
+  int32_t* dsig = h.coarse_piv + np;
+  HIPCHECK(hipMemcpyAsync(dsig, sig.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, h.stream));
+  launch_coarse_finish(h.coarse_work, np, n, dsig, h.coarse_inv, h.coarse_invT, h.stream);
+  HIPCHECK(hipGetLastError());
+  HIPCHECK(hipStreamSynchronize(h.stream));
   h.n0 = n;
 }
 
@@ -638,6 +663,7 @@ void ensure_transposed(fsgmg_hierarchy& h) {
   for (int l = 0; l < h.L; ++l) {
     DLevel& d = h.dl[l];
     if (d.AT.ready) continue;
+    h.ensure_host_values();
     const CsrHost& A = h.ops[l].A;
     CsrHost T = csr_transpose(A);
     upload_bop(h, h.levels[l], T, d.AT);
@@ -663,6 +689,7 @@ WPrec wprec(fsgmg_prec p) {
 }
 
 void upload_blocks(fsgmg_hierarchy& h, int l) {
+  h.ensure_host_values();
   const Level& lv = h.levels[l];
   const BlockSet& bs = h.blocks[l];
   DLevel& d = h.dl[l];
@@ -1508,11 +1535,13 @@ fsgmg_status update_params(fsgmg_h h, double E, double mu) {
       op.G = G;
       op.invlam = invlam;
       op.mu = mu;
-      for (size_t k = 0; k < op.A.val.size(); ++k)
-        op.A.val[k] = op.piece[0][k] + G * op.piece[1][k] + invlam * op.piece[2][k] + mu * op.piece[3][k];
     }
+    h->host_vals_stale = true;
     h->factors_valid = false;
-    if (h->host_only()) return FSGMG_OK;
+    if (h->host_only()) {
+      h->ensure_host_values();
+      return FSGMG_OK;
+    }
     for (int l = 0; l < h->L; ++l) {
       DLevel& d = h->dl[l];
       launch_recombine(d.nnz, d.piece[0], d.piece[1], d.piece[2], d.piece[3], G, invlam, mu, d.val,
@@ -1553,6 +1582,7 @@ fsgmg_status export_csr(fsgmg_h h, int level, int which, int64_t dims[3], int64_
     CsrHost tmp;
     const CsrHost* M = nullptr;
     if (which == 0) {
+      h->ensure_host_values();
       M = &h->ops[level].A;
     } else if (which == 1 || which == 2) {
       if (level < 1) throw Fail{FSGMG_EINVAL, "transfers exist for level >= 1"};
