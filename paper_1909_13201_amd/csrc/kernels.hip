@@ -585,16 +585,17 @@ __global__ __launch_bounds__(kThreads) void k_gather_blocks(const int32_t* __res
 // column swaps over the whole matrix.
 using f64x4 = __attribute__((__vector_size__(4 * sizeof(double)))) double;
 constexpr int kPanel = 16;      // LDS strip width
+constexpr int kInvThreads = 256;   // workgroup of the block inversion (measured best of 256 / 512 / 1024)
 constexpr int kOuterPanel = 64; // columns per pass over the block
 
 template <int NB, int NO>
-__global__ __launch_bounds__(kThreads) void k_invert_blocked(
+__global__ __launch_bounds__(kInvThreads) void k_invert_blocked(
     const int32_t* __restrict__ jlist, const int64_t* __restrict__ dof_ptr,
     const int64_t* __restrict__ doff, const int64_t* __restrict__ soff, double* __restrict__ dense,
     int32_t* __restrict__ sigma_all, int32_t* __restrict__ status) {
   static_assert(NB == 16 && NO % NB == 0, "strip of one tile, outer panel of whole strips");
   constexpr int LDT = NB + 1;   // LDS row stride (doubles) of the strip
-  constexpr int NW = kThreads / 64;
+  constexpr int NW = kInvThreads / 64;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int64_t j = jlist[blockIdx.x];
   const int n = (int)(dof_ptr[j + 1] - dof_ptr[j]);
@@ -618,7 +619,7 @@ __global__ __launch_bounds__(kThreads) void k_invert_blocked(
   const int u0 = K0 / 16, u1 = u0 + nko / 16;   // tiles of the outer panel
   for (int k0 = K0; k0 < K0 + nko; k0 += NB) {
     const int nbk = NB;
-    for (int e = tid; e < np * nbk; e += kThreads) {
+    for (int e = tid; e < np * nbk; e += kInvThreads) {
       const int r = e / nbk, q = e - r * nbk;
       T[r * LDT + q] = a[(int64_t)r * np + k0 + q];
     }
@@ -627,7 +628,7 @@ __global__ __launch_bounds__(kThreads) void k_invert_blocked(
       const int c = k0 + kk;
       double best = -1.0;
       int bi = np;
-      for (int r = c + tid; r < np; r += kThreads) {
+      for (int r = c + tid; r < np; r += kInvThreads) {
         const double v = fabs(T[r * LDT + kk]);
         if (v > best) {
           best = v;
@@ -677,7 +678,7 @@ __global__ __launch_bounds__(kThreads) void k_invert_blocked(
       double rc[NB];
 #pragma unroll
       for (int q = 0; q < NB; ++q) rc[q] = (q == kk) ? d : prow[q] * d;
-      for (int r = tid; r < np; r += kThreads) {
+      for (int r = tid; r < np; r += kInvThreads) {
         double* Tr = T + r * LDT;
         if (r == c) {
 #pragma unroll
@@ -725,7 +726,7 @@ __global__ __launch_bounds__(kThreads) void k_invert_blocked(
     __syncthreads();
     {
       const int ns = swn[0];
-      for (int col = tid; col < np - nbk; col += kThreads) {
+      for (int col = tid; col < np - nbk; col += kInvThreads) {
         const int cc = col < k0 ? col : col + nbk;
         double v[2 * NB];
 #pragma unroll
@@ -738,7 +739,7 @@ __global__ __launch_bounds__(kThreads) void k_invert_blocked(
     }
     __syncthreads();
     // the strip's final values, then T - E_K in LDS for the update
-    for (int e = tid; e < np * nbk; e += kThreads) {
+    for (int e = tid; e < np * nbk; e += kInvThreads) {
       const int r = e / nbk, q = e - r * nbk;
       const double v = T[r * LDT + q];
       a[(int64_t)r * np + k0 + q] = v;
@@ -817,7 +818,7 @@ __global__ __launch_bounds__(kThreads) void k_invert_blocked(
   }
   __syncthreads();
   int32_t* sg = sigma_all + soff[blockIdx.x];
-  for (int c = tid; c < np; c += kThreads) sg[c] = sig[c];
+  for (int c = tid; c < np; c += kInvThreads) sg[c] = sig[c];
   if (tid == 0) status[j] = 0;
 }
 
@@ -1452,7 +1453,7 @@ void launch_gather_blocks(const int32_t* jlist, int64_t nb, const BlocksView& B,
 }
 
 size_t invert_blocks_lds(int np_max) {
-  return (size_t)np_max * (kPanel + 1) * 8 + (size_t)kPanel * 8 + (kThreads / 64) * 12 +
+  return (size_t)np_max * (kPanel + 1) * 8 + (size_t)kPanel * 8 + (kInvThreads / 64) * 12 +
          (size_t)np_max * 8 + (size_t)(4 * kPanel + 1) * 4;
 }
 
@@ -1461,7 +1462,7 @@ void launch_invert_blocks(const int32_t* jlist, int64_t nb, const int64_t* dof_p
                           int32_t* sigma, int32_t* status, int max_n, hipStream_t s) {
   if (nb <= 0) return;
   const size_t sm = invert_blocks_lds((max_n + 15) & ~15);
-  hipLaunchKernelGGL((k_invert_blocked<kPanel, kOuterPanel>), dim3((unsigned)nb), dim3(kThreads), sm, s, jlist,
+  hipLaunchKernelGGL((k_invert_blocked<kPanel, kOuterPanel>), dim3((unsigned)nb), dim3(kInvThreads), sm, s, jlist,
                      dof_ptr, dense_off, sigma_off, dense, sigma, status);
 }
 
