@@ -1,6 +1,6 @@
 """GPU parity tests: the HIP path (through the C ABI) against the CPU oracle.
 
-Tolerances (derived in the design doc):
+Tolerances (each derived from the arithmetic):
 * operator apply, transfers, load: elementwise |y - y_ref| <= 64 eps (|A| |x|)_i
   (summation-order rounding only);
 * FP64 V-cycle: the block inverses come from Gauss-Jordan (GPU) versus LU
