@@ -371,6 +371,27 @@ def main():
                kernels=other, tuning=H.tuning_info(), roofline=roof)
     if bf is not None:
         out["bf16_factors"] = bf
+    # the paper's comparator: monolithic Vanka blocks over d, u, p (no field
+    # split), everything else identical
+    comp = {}
+    try:
+        for prec in ("fp64", "fp32"):
+            t0 = time.perf_counter()
+            H.build_fs_as_blocks(prec=prec, monolithic=True)
+            torch.cuda.synchronize()
+            tb = time.perf_counter() - t0
+            xa = torch.zeros_like(b)
+            ta, infa = timed_solves(H, b, xa, args.steps, args.warmup, rtol)
+            comp[prec] = dict(solves_per_s=round(args.steps / ta, 4), iters=infa[-1]["iters"],
+                              rel_res_true=infa[-1]["rel_res_true"], build_blocks_s=round(tb, 3))
+        ptr, _, _ = fsgmg.export_blocks(H.h, H.L - 1)
+        comp["max_block"] = int(np.diff(ptr).max())
+        comp["fs_over_as_fp32"] = round((args.steps / t32) / comp["fp32"]["solves_per_s"], 3)
+        comp["fs_over_as_fp64"] = round((args.steps / t64) / comp["fp64"]["solves_per_s"], 3)
+    except fsgmg.FsgmgError as e:     # e.g. monolithic blocks beyond one workgroup's LDS
+        comp = dict(not_run=str(e))
+
+    out["comparator_as"] = comp
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, w, f)
     print(json.dumps(out), flush=True)

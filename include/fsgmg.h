@@ -104,7 +104,11 @@ typedef struct {
  * another region across a face normal to axis 1 absorbs the next
  * iface_mult - 1 tile rows away from that interface, giving enlarged
  * interface blocks (layered walls only: the regions must be constant along
- * the other axes, else FSGMG_EINVAL). */
+ * the other axes, else FSGMG_EINVAL).
+ * monolithic != 0 builds the comparator of the paper instead of the field
+ * split (the AS formula of Section 3.2, P^s_1j / P^f_1j): one Vanka block per
+ * core and region over its displacements, velocities and pressures together,
+ * u^s included; the rest of the V-cycle is unchanged. */
 typedef struct {
   int core[3];
   int halo;
@@ -113,6 +117,7 @@ typedef struct {
   fsgmg_prec prec;
   int use_graph;
   int iface_mult;
+  int monolithic;
 } fsgmg_smoother_opts;
 
 /* FGMRES(restart), right preconditioned, x0 = 0, CGS2; converged when the

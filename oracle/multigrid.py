@@ -49,13 +49,14 @@ class Hierarchy:
     def finest(self) -> Level:
         return self.levels[-1]
 
-    def build_smoothers(self, core=None, halo=None, iface_mult=None):
+    def build_smoothers(self, core=None, halo=None, iface_mult=None, monolithic=None):
         cfg = self.cfg
         core = tuple(cfg["core"]) if core is None else tuple(core)
         halo = int(cfg["halo"]) if halo is None else int(halo)
         mult = int(cfg.get("iface_mult", 1)) if iface_mult is None else int(iface_mult)
+        mono = bool(cfg.get("monolithic", False)) if monolithic is None else bool(monolithic)
         for l in range(1, self.L):
-            blocks, _ = build_blocks(self.levels[l], core, halo, mult)
+            blocks, _ = build_blocks(self.levels[l], core, halo, mult, mono)
             self.smoothers[l] = FieldSplitSchwarz(self.A[l], blocks)
 
     def rhs(self, fnodal: np.ndarray) -> np.ndarray:

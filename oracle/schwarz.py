@@ -93,9 +93,16 @@ def interface_row_groups(lv: Level, core, region: int, iface_mult: int):
     return groups
 
 
-def build_blocks(lv: Level, core, halo: int, iface_mult: int = 1):
+def build_blocks(lv: Level, core, halo: int, iface_mult: int = 1, monolithic: bool = False):
     """Return (blocks, kinds): blocks is a list of sorted global index arrays;
-    kinds[j] = (field, region) with field 0 = [d,p^s], 1 = [u,p^f]."""
+    kinds[j] = (field, region) with field 0 = [d,p^s], 1 = [u,p^f], and
+    field 2 = [d, u, p] for the monolithic blocks.
+
+    monolithic: the additive Schwarz comparator of Section 3.2 (the AS
+    formula, P^s_1j / P^f_1j): no field split, one Vanka block per core and
+    region holding the displacements, velocities and pressures of that region
+    (the same selection rule), so the solid blocks carry u^s and the
+    kinematic rows K and only Dirichlet unknowns stay outside every block."""
     D = lv.D
     ne = lv.ne
     reg = lv.region.reshape(ne[::-1])                # [z][y][x]
@@ -104,9 +111,10 @@ def build_blocks(lv: Level, core, halo: int, iface_mult: int = 1):
     struct = np.ones((3,) * D, bool)
     groups = {r: interface_row_groups(lv, core, r, iface_mult) for r in (0, 1)}
     blocks, kinds = [], []
-    for field in (0, 1):
+    passes = ((2, (1, 0)),) if monolithic else ((0, (1, 0)), (1, (0,)))
+    for field, regions in passes:
         for t in tiles:
-            for region in ((1, 0) if field == 0 else (0,)):
+            for region in regions:
                 g = groups[region][t[1]]
                 if g is None:
                     continue
@@ -127,7 +135,12 @@ def build_blocks(lv: Level, core, halo: int, iface_mult: int = 1):
                 blk_el = np.where(blk_mask.ravel())[0]
                 nodes = np.unique(lv.elem_nodes[blk_el])
                 verts = np.unique(lv.elem_verts[core_el])
-                if field == 0 and region == 1:
+                if field == 2:
+                    rn = nodes if region == 1 else nodes[~lv.solid_side[nodes]]
+                    dofs = np.concatenate([(D * rn[:, None] + np.arange(D)).ravel(),
+                                           (lv.off_u + D * rn[:, None] + np.arange(D)).ravel(),
+                                           (lv.ps_of_vert if region == 1 else lv.pf_of_vert)[verts]])
+                elif field == 0 and region == 1:
                     dofs = np.concatenate([(D * nodes[:, None] + np.arange(D)).ravel(),
                                            lv.ps_of_vert[verts]])
                 elif field == 0:

@@ -20,6 +20,12 @@
 // interface (never a row that touches an interface itself; a row touching
 // interfaces on both sides keeps its size).  The enlarged core is emitted in
 // the place of the interface tile; the rows taken over emit nothing.
+//
+// Monolithic comparator (the AS formula of Section 3.2, P^s_1j and P^f_1j):
+// no field split; one block per core and region with the displacements,
+// velocities and pressures of that region (same selection rule), so u^s and
+// the kinematic rows K sit in the solid blocks and only Dirichlet unknowns
+// stay outside every block.
 #include <algorithm>
 #include <stdexcept>
 
@@ -79,7 +85,8 @@ std::vector<std::pair<int, int>> row_groups(const Level& lv, const int* core, in
 
 }  // namespace
 
-void build_blocks(const Level& lv, const int* core, int halo, int iface_mult, BlockSet& bs) {
+void build_blocks(const Level& lv, const int* core, int halo, int iface_mult, bool monolithic,
+                  BlockSet& bs) {
   const int D = lv.D;
   int nt[kMaxDim] = {1, 1, 1};
   int64_t ntiles = 1;
@@ -95,7 +102,11 @@ void build_blocks(const Level& lv, const int* core, int halo, int iface_mult, Bl
   std::vector<int32_t> stamp_el(lv.nE, -1), stamp_node(lv.N2, -1), stamp_vert(lv.NV, -1);
   int32_t stamp = 0;
   std::vector<int64_t> core_el, blk_el, dofs;
-  for (int field = 0; field < 2; ++field) {
+  // passes: field 0 = [d, p^s] (solid, then fluid cores), field 1 = [u, p^f]
+  // (fluid cores); monolithic: field 2 = [d, u, p] (solid, then fluid)
+  const int fields[2] = {monolithic ? 2 : 0, 1};
+  for (int fi = 0; fi < (monolithic ? 1 : 2); ++fi) {
+    const int field = fields[fi];
     for (int64_t t = 0; t < ntiles; ++t) {
       int tx[kMaxDim] = {0, 0, 0};
       int64_t tt = t;
@@ -104,7 +115,7 @@ void build_blocks(const Level& lv, const int* core, int halo, int iface_mult, Bl
         tt /= nt[a];
       }
       const int regions[2] = {1, 0};
-      for (int ri = (field == 0 ? 0 : 1); ri < 2; ++ri) {
+      for (int ri = (field == 1 ? 1 : 0); ri < 2; ++ri) {
         const int region = regions[ri];
         const std::pair<int, int> g = groups[region][tx[1]];
         if (g.first < 0) continue;
@@ -153,7 +164,13 @@ void build_blocks(const Level& lv, const int* core, int halo, int iface_mult, Bl
             if (stamp_node[n] == stamp) continue;
             stamp_node[n] = stamp;
             const bool ss = lv.solid_side[n];
-            if (field == 0 && region == 1) {
+            if (field == 2) {
+              if (region == 1 || !ss)
+                for (int c = 0; c < D; ++c) {
+                  dofs.push_back((int64_t)D * n + c);
+                  dofs.push_back(lv.off_u + (int64_t)D * n + c);
+                }
+            } else if (field == 0 && region == 1) {
               for (int c = 0; c < D; ++c) dofs.push_back((int64_t)D * n + c);
             } else if (field == 0) {
               if (!ss)

@@ -108,6 +108,7 @@ struct BlockSet {
   int64_t nblk() const { return ptr.empty() ? 0 : (int64_t)ptr.size() - 1; }
 };
 
-void build_blocks(const Level& lv, const int* core, int halo, int iface_mult, BlockSet& bs);
+void build_blocks(const Level& lv, const int* core, int halo, int iface_mult, bool monolithic,
+                  BlockSet& bs);
 
 }  // namespace fsgmg

@@ -1401,14 +1401,17 @@ fsgmg_status build_fs_as_blocks(fsgmg_h h, const fsgmg_smoother_opts* opts) {
     const bool same_sets = h->have_blocks && h->sopt.halo == opts->halo &&
                            h->sopt.core[0] == opts->core[0] && h->sopt.core[1] == opts->core[1] &&
                            h->sopt.core[2] == opts->core[2] &&
-                           std::max(1, h->sopt.iface_mult) == mult && h->sopt.prec == opts->prec;
+                           std::max(1, h->sopt.iface_mult) == mult &&
+                           (h->sopt.monolithic != 0) == (opts->monolithic != 0) &&
+                           h->sopt.prec == opts->prec;
     h->sopt = *opts;
     h->factors_valid = false;
     h->invalidate_graphs();
     if (!same_sets) {
       try {
         for (int l = 1; l < h->L; ++l)
-          build_blocks(h->levels[l], opts->core, opts->halo, mult, h->blocks[l]);
+          build_blocks(h->levels[l], opts->core, opts->halo, mult, opts->monolithic != 0,
+                       h->blocks[l]);
       } catch (const std::invalid_argument& e) {
         h->have_blocks = false;
         throw Fail{FSGMG_EINVAL, e.what()};

@@ -45,7 +45,7 @@ class Physics(C.Structure):
 class SmootherOpts(C.Structure):
     _fields_ = [("core", C.c_int * 3), ("halo", C.c_int), ("nu_pre", C.c_int),
                 ("nu_post", C.c_int), ("omega", C.c_double), ("prec", C.c_int),
-                ("use_graph", C.c_int), ("iface_mult", C.c_int)]
+                ("use_graph", C.c_int), ("iface_mult", C.c_int), ("monolithic", C.c_int)]
 
 
 class KrylovOpts(C.Structure):
@@ -182,7 +182,7 @@ def setup_hierarchy(cfg, w=None, device=0, stream=None):
 
 
 def build_fs_as_blocks(h, core=(4, 4), halo=1, nu_pre=2, nu_post=2, omega=0.8, prec="fp64",
-                       use_graph=True, iface_mult=1):
+                       use_graph=True, iface_mult=1, monolithic=False):
     o = SmootherOpts()
     for a in range(3):
         o.core[a] = int(core[a]) if a < len(core) else 1
@@ -191,6 +191,7 @@ def build_fs_as_blocks(h, core=(4, 4), halo=1, nu_pre=2, nu_post=2, omega=0.8, p
     o.prec = PREC[prec] if isinstance(prec, str) else int(prec)
     o.use_graph = int(bool(use_graph))
     o.iface_mult = int(iface_mult)
+    o.monolithic = int(bool(monolithic))
     _check(h, lib().build_fs_as_blocks(h, C.byref(o)))
 
 
@@ -337,7 +338,8 @@ class Hierarchy:
     def build_fs_as_blocks(self, **kw):
         opts = dict(core=self.cfg.get("core", (4, 4)), halo=self.cfg.get("halo", 1),
                     nu_pre=self.cfg.get("nu_pre", 2), nu_post=self.cfg.get("nu_post", 2),
-                    omega=self.cfg.get("omega", 0.8), iface_mult=self.cfg.get("iface_mult", 1))
+                    omega=self.cfg.get("omega", 0.8), iface_mult=self.cfg.get("iface_mult", 1),
+                    monolithic=self.cfg.get("monolithic", False))
         opts.update(kw)
         build_fs_as_blocks(self.h, **opts)
 

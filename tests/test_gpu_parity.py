@@ -118,6 +118,36 @@ def test_vcycle_fp64_parity(key, transpose):
     assert err <= 1e-9
 
 
+@pytest.mark.parametrize("key", ["c1", "c2L3"])
+def test_monolithic_comparator_parity(key):
+    """The comparator (monolithic Vanka blocks over d, u, p): FP64 V-cycle and
+    its transpose against the oracle's with the same blocks, and an FP32
+    solve to a true 1e-10."""
+    cfg = inputs.config("c1") if key == "c1" else inputs.with_levels(inputs.config("c2"), 3)
+    w = inputs.advecting_field(cfg)
+    O = OracleHierarchy(cfg, w, build_smoothers=False)
+    O.build_smoothers(monolithic=True)
+    H = fsgmg.Hierarchy(cfg, w, device=0)
+    H.build_fs_as_blocks(prec="fp64", monolithic=True)
+    rng = np.random.default_rng(5)
+    r = rng.standard_normal(H.N)
+    z = torch.zeros(H.N, dtype=torch.float64, device="cuda")
+    for tr in (False, True):
+        H.vcycle_apply(dev(r), z, transpose=tr)
+        ref = O.vcycle(r, transpose=tr)
+        err = np.linalg.norm(host(z) - ref) / np.linalg.norm(ref)
+        say("[monolithic]", key, "transpose", tr, "rel err %.3e" % err)
+        assert err <= 1e-9
+    H.build_fs_as_blocks(prec="fp32", monolithic=True)
+    b = O.rhs(inputs.body_force(cfg))
+    x = torch.zeros(H.N, dtype=torch.float64, device="cuda")
+    info = H.gmres_solve(dev(b), x, rtol=1e-10)
+    true = np.linalg.norm(b - O.A[-1] @ host(x)) / np.linalg.norm(b)
+    say("   fp32 solve iters %d true %.2e" % (info["iters"], true))
+    assert info["converged"] and true <= 1e-10
+    H.close()
+
+
 @pytest.mark.parametrize("prec,tol", [("fp32", 2e-4), ("bf16", 2e-2)])
 def test_vcycle_mixed_precision(prec, tol):
     p = pair("c2L3", prec)

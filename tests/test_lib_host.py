@@ -119,6 +119,23 @@ def test_enlarged_interface_blocks_match_oracle(name, L):
     H.close()
 
 
+@pytest.mark.parametrize("name,L,mult", [("c1", 2, 1), ("c2", 3, 1), ("c3", 3, 3)])
+def test_monolithic_blocks_match_oracle(name, L, mult):
+    cfg = inputs.with_levels(inputs.config(name), L)
+    H = fsgmg.Hierarchy(cfg, None, device=-1)
+    O = OracleHierarchy(cfg, None, build_smoothers=False)
+    fsgmg.build_fs_as_blocks(H.h, core=cfg["core"], halo=cfg["halo"], iface_mult=mult,
+                             monolithic=True)
+    for l in range(1, H.L):
+        ptr, dofs, owner = fsgmg.export_blocks(H.h, l)
+        blocks, _ = build_blocks(O.levels[l], cfg["core"], cfg["halo"], mult, True)
+        assert len(ptr) - 1 == len(blocks)
+        for j, I in enumerate(blocks):
+            assert np.array_equal(dofs[ptr[j]:ptr[j + 1]], I)
+        assert np.array_equal(owner, owners(O.levels[l].N, blocks))
+    H.close()
+
+
 def test_enlarged_interface_needs_layered_regions():
     import tests.cfgs as cfgs
     cfg = cfgs.small(nc=(4, 4), solid_rows=(), levels=2)

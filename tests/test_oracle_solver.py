@@ -86,6 +86,39 @@ def test_enlarged_interface_cores_counted_by_hand():
     assert max(small) == 13 * 13 * 2 + 25 and max(big) == 13 * 26 * 2 + 65
 
 
+def test_monolithic_blocks_structure():
+    """The comparator's blocks (the AS formula of Section 3.2): per core and
+    region one block over d, u and p of that region, so u^s and the kinematic
+    rows sit in the solid blocks and only Dirichlet unknowns are left to the
+    Jacobi step; the principal submatrices have the zero pattern of P^s_1j
+    (p^s rows see no u, kinematic rows no p) and P^f_1j (ALE rows see only d).
+    The field-split index sets of the same cores are subsets of them."""
+    cfg = inputs.with_levels(inputs.config("c2"), 3)
+    H = Hierarchy(cfg, inputs.advecting_field(cfg), build_smoothers=False)
+    lv, A = H.finest, H.A[-1].tocsr()
+    mono, kinds = build_blocks(lv, cfg["core"], cfg["halo"], 1, True)
+    fs, _ = build_blocks(lv, cfg["core"], cfg["halo"], 1, False)
+    assert all(k[0] == 2 for k in kinds)
+    cover = np.zeros(lv.N, bool)
+    for I in mono:
+        cover[I] = True
+    assert np.array_equal(~cover, lv.dir_mask)
+    N2D = 2 * lv.N2
+    for I, (_, region) in zip(mono, kinds):
+        isd = I < N2D
+        isu = (I >= lv.off_u) & (I < lv.off_pf)
+        isp = ~(isd | isu)
+        Aj = A[I][:, I].toarray()
+        if region == 1:
+            assert np.all(Aj[np.ix_(isp, isu)] == 0) and np.all(Aj[np.ix_(isu, isp)] == 0)
+        else:
+            assert np.all(Aj[np.ix_(isd, isu | isp)] == 0)
+    # every field-split block lies inside the monolithic block of its core
+    mono_sets = [set(I.tolist()) for I in mono]
+    for I in fs:
+        assert any(set(I.tolist()) <= M for M in mono_sets)
+
+
 def test_smoother_matches_dense_inverse(c1):
     cfg, H = c1
     S = H.smoothers[-1]
