@@ -234,6 +234,7 @@ def main():
     ap.add_argument("--levels", type=int, default=0, help="override the number of levels")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--bf16", action="store_true", help="also time BF16-stored block inverses")
+    ap.add_argument("--cycle", default="V", choices=["V", "W", "F"], help="multigrid cycle")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run three plain 256 MiB device copies first (counter calibration)")
     args = ap.parse_args()
@@ -248,6 +249,7 @@ def main():
     cfg = inputs.config(args.config)
     if args.levels:
         cfg = inputs.with_levels(cfg, args.levels)
+    cfg["cycle"] = args.cycle
     if cfg.get("batch"):
         grad_bench(cfg, args)
         return
@@ -359,7 +361,8 @@ def main():
                data="synthetic",
                config=dict(workload=WORKLOADS.get(cfg["name"], cfg["name"]),
                            name=cfg["name"], levels=int(cfg["n_levels"]), unknowns=H.N,
-                           core=list(cfg["core"]), halo=cfg["halo"], restart=30, rtol=rtol),
+                           core=list(cfg["core"]), halo=cfg["halo"], cycle=cfg["cycle"],
+                           restart=30, rtol=rtol),
                fp64_solves_per_s=round(sps64, 4), mixed_over_fp64=round(sps32 / sps64, 3),
                vcycles_per_s=round(nv / tv, 2), iters_mixed=inf32[-1]["iters"],
                iters_fp64=inf64[-1]["iters"], rel_res_true_mixed=inf32[-1]["rel_res_true"],

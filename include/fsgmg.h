@@ -57,6 +57,10 @@ typedef enum {
 
 typedef enum { FSGMG_FP64 = 0, FSGMG_FP32 = 1, FSGMG_BF16 = 2 } fsgmg_prec;
 
+/* Multigrid cycle (Section 3.2 admits any): V, W (two coarse cycles per
+ * level), F (an F-cycle then a V-cycle on the coarser level). */
+typedef enum { FSGMG_CYCLE_V = 0, FSGMG_CYCLE_W = 1, FSGMG_CYCLE_F = 2 } fsgmg_cycle;
+
 /* Nested structured mesh (Section 3.3: every level is the midpoint
  * refinement of a conforming coarse mesh, regions are the same on every
  * level).  Faces: 0 x-min, 1 x-max, 2 y-min, 3 y-max, 4 z-min, 5 z-max.
@@ -108,7 +112,9 @@ typedef struct {
  * monolithic != 0 builds the comparator of the paper instead of the field
  * split (the AS formula of Section 3.2, P^s_1j / P^f_1j): one Vanka block per
  * core and region over its displacements, velocities and pressures together,
- * u^s included; the rest of the V-cycle is unchanged. */
+ * u^s included; the rest of the V-cycle is unchanged.
+ * cycle: fsgmg_cycle used by vcycle_apply, gmres_solve and adjoint_solve
+ * (the transposed cycle is the exact transpose of the chosen one). */
 typedef struct {
   int core[3];
   int halo;
@@ -118,6 +124,7 @@ typedef struct {
   int use_graph;
   int iface_mult;
   int monolithic;
+  int cycle;
 } fsgmg_smoother_opts;
 
 /* FGMRES(restart), right preconditioned, x0 = 0, CGS2; converged when the

@@ -80,17 +80,32 @@ class Hierarchy:
                 x = x + om * (S.apply_transpose(r) if transpose else S.apply(r))
         return x
 
-    def vcycle(self, b: np.ndarray, l: int | None = None, transpose: bool = False):
-        """z = M^{-1} b (or M^{-T} b) on level l (default finest)."""
+    def vcycle(self, b: np.ndarray, l: int | None = None, transpose: bool = False,
+               x0: np.ndarray | None = None, kind: str | None = None):
+        """z = M^{-1} b (or M^{-T} b) on level l (default finest) for the
+        configured cycle (cfg["cycle"]: "V" default, "W" or "F"; Section 3.2
+        allows any).  With an initial guess x0 the cycle returns
+        x0 + M^{-1} (b - A x0) (pre-smoothing starts from x0).
+
+        The coarse correction solves the restricted residual equation by
+          V: one cycle on level l-1 from zero,
+          W: two W-cycles, the second from the first one's result,
+          F: an F-cycle then a V-cycle from its result.
+        Transposed: pre and post smoothing swapped, every operator
+        transposed; the coarse cycles of F run in the reverse order (V, then
+        F), which is what transposing x1 = M_F b, x2 = x1 + M_V (b - A x1)
+        gives."""
         if l is None:
             l = self.L - 1
+        if kind is None:
+            kind = self.cfg.get("cycle", "V")
         if l == 0:
             return la.lu_solve(self.coarse_lu, b, trans=1 if transpose else 0)
         cfg = self.cfg
         n1, n2 = cfg["nu_pre"], cfg["nu_post"]
         if transpose:
             n1, n2 = n2, n1
-        x = self._sweeps(l, b, None, n1, transpose)
+        x = self._sweeps(l, b, x0, n1, transpose)
         A = self.A[l]
         if x is None:
             x = np.zeros_like(b)
@@ -99,7 +114,12 @@ class Hierarchy:
             bc = self.P[l].T @ r
         else:
             bc = self.R[l] @ r
-        xc = self.vcycle(bc, l - 1, transpose)
+        coarse = {"V": ["V"], "W": ["W", "W"], "F": ["F", "V"]}[kind]
+        if transpose:
+            coarse = coarse[::-1]
+        xc = None
+        for k in coarse:
+            xc = self.vcycle(bc, l - 1, transpose, xc, k)
         x = x + (self.R[l].T @ xc if transpose else self.P[l] @ xc)
         x = self._sweeps(l, b, x, n2, transpose)
         return x

@@ -962,36 +962,58 @@ void smooth_level(fsgmg_hierarchy& h, int l, int nsweeps, bool transpose, bool f
 }
 
 // V-cycle from the finest right-hand side buffer b to the finest x buffer
+// One multigrid cycle on level l for the right-hand side in b_l, result in
+// x_l (zero_init: from x_l = 0, else from the iterate already in x_l).  The
+// coarse correction runs one cycle on level l-1 (V), two W-cycles (W), or an
+// F-cycle then a V-cycle (F; transposed: V then F, the transpose of that
+// composition); every coarse cycle after the first starts from the previous
+// result.  Level 0 is the direct solve.
 template <typename TV>
-void vcycle_core(fsgmg_hierarchy& h, bool transpose) {
+void cycle_level(fsgmg_hierarchy& h, int l, int kind, bool transpose, bool zero_init) {
   const int L = h.L, D = h.D;
+  if (l == 0) {
+    DLevel& C = h.dl[0];
+    launch_dense_gemv<TV>(h.n0, transpose ? h.coarse_invT : h.coarse_inv, false, Vec<TV>::b(C),
+                          Vec<TV>::x(C), h.stream);
+    return;
+  }
   const int npre = transpose ? h.sopt.nu_post : h.sopt.nu_pre;
   const int npost = transpose ? h.sopt.nu_pre : h.sopt.nu_post;
-  for (int l = L - 1; l >= 1; --l) {
-    DLevel& d = h.dl[l];
-    if (npre == 0) launch_fill<TV>(Vec<TV>::x(d), TV(0), d.N, h.stream);
-    smooth_level<TV>(h, l, npre, transpose, true);
-    {
-      TimedLaunch t(h, 1, l == L - 1);
-      launch_spmv<TV>(Vec<TV>::op(d, transpose), D, Vec<TV>::x(d), Vec<TV>::b(d), Vec<TV>::r(d),
-                      true, h.stream, h.tune[l].spmv_lanes);
-    }
+  DLevel& d = h.dl[l];
+  if (npre == 0 && zero_init) launch_fill<TV>(Vec<TV>::x(d), TV(0), d.N, h.stream);
+  smooth_level<TV>(h, l, npre, transpose, zero_init);
+  {
+    TimedLaunch t(h, 1, l == L - 1);
+    launch_spmv<TV>(Vec<TV>::op(d, transpose), D, Vec<TV>::x(d), Vec<TV>::b(d), Vec<TV>::r(d),
+                    true, h.stream, h.tune[l].spmv_lanes);
+  }
+  {
     TimedLaunch t(h, 3, l == L - 1);
     launch_transfer<TV>(Vec<TV>::tv(d), D, transpose ? 2 : 0, Vec<TV>::r(d), Vec<TV>::b(h.dl[l - 1]),
                         h.stream, h.tune[l].restrict_lanes);
   }
-  DLevel& C = h.dl[0];
-  launch_dense_gemv<TV>(h.n0, transpose ? h.coarse_invT : h.coarse_inv, false, Vec<TV>::b(C),
-                        Vec<TV>::x(C), h.stream);
-  for (int l = 1; l < L; ++l) {
-    DLevel& d = h.dl[l];
-    {
-      TimedLaunch t(h, 3, l == L - 1);
-      launch_transfer<TV>(Vec<TV>::tv(d), D, transpose ? 3 : 1, Vec<TV>::x(h.dl[l - 1]),
-                          Vec<TV>::x(d), h.stream, h.tune[l].prolong_lanes);
-    }
-    smooth_level<TV>(h, l, npost, transpose, false);
+  int seq[2] = {FSGMG_CYCLE_V, FSGMG_CYCLE_V};
+  int nseq = 1;
+  if (kind == FSGMG_CYCLE_W) {
+    seq[0] = seq[1] = FSGMG_CYCLE_W;
+    nseq = 2;
+  } else if (kind == FSGMG_CYCLE_F) {
+    seq[0] = transpose ? FSGMG_CYCLE_V : FSGMG_CYCLE_F;
+    seq[1] = transpose ? FSGMG_CYCLE_F : FSGMG_CYCLE_V;
+    nseq = 2;
   }
+  for (int i = 0; i < nseq; ++i) cycle_level<TV>(h, l - 1, seq[i], transpose, i == 0);
+  {
+    TimedLaunch t(h, 3, l == L - 1);
+    launch_transfer<TV>(Vec<TV>::tv(d), D, transpose ? 3 : 1, Vec<TV>::x(h.dl[l - 1]),
+                        Vec<TV>::x(d), h.stream, h.tune[l].prolong_lanes);
+  }
+  smooth_level<TV>(h, l, npost, transpose, false);
+}
+
+template <typename TV>
+void vcycle_core(fsgmg_hierarchy& h, bool transpose) {
+  cycle_level<TV>(h, h.L - 1, h.sopt.cycle, transpose, true);
 }
 
 bool graphs_on(const fsgmg_hierarchy& h) { return h.sopt.use_graph && !h.timing && !h.capturing; }
@@ -1396,6 +1418,8 @@ fsgmg_status build_fs_as_blocks(fsgmg_h h, const fsgmg_smoother_opts* opts) {
     for (int a = 0; a < h->D; ++a)
       if (opts->core[a] < 1) throw Fail{FSGMG_EINVAL, "core sizes must be >= 1"};
     if (opts->prec < FSGMG_FP64 || opts->prec > FSGMG_BF16) throw Fail{FSGMG_EINVAL, "bad precision"};
+    if (opts->cycle < FSGMG_CYCLE_V || opts->cycle > FSGMG_CYCLE_F)
+      throw Fail{FSGMG_EINVAL, "cycle must be FSGMG_CYCLE_V, _W or _F"};
     if (opts->iface_mult < 0) throw Fail{FSGMG_EINVAL, "iface_mult must be >= 0"};
     const int mult = std::max(1, opts->iface_mult);
     const bool same_sets = h->have_blocks && h->sopt.halo == opts->halo &&

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libfsgmg.so")
 FSGMG_OK, FSGMG_NOT_CONVERGED = 0, 1
 STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "EHIP", -3: "ESINGULAR",
           -4: "ENOMEM", -5: "ESTATE"}
+CYCLE = {"V": 0, "W": 1, "F": 2}
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
 
 EXPORTED = ["setup_hierarchy", "build_fs_as_blocks", "vcycle_apply", "gmres_solve",
@@ -45,7 +46,8 @@ class Physics(C.Structure):
 class SmootherOpts(C.Structure):
     _fields_ = [("core", C.c_int * 3), ("halo", C.c_int), ("nu_pre", C.c_int),
                 ("nu_post", C.c_int), ("omega", C.c_double), ("prec", C.c_int),
-                ("use_graph", C.c_int), ("iface_mult", C.c_int), ("monolithic", C.c_int)]
+                ("use_graph", C.c_int), ("iface_mult", C.c_int), ("monolithic", C.c_int),
+                ("cycle", C.c_int)]
 
 
 class KrylovOpts(C.Structure):
@@ -182,7 +184,7 @@ def setup_hierarchy(cfg, w=None, device=0, stream=None):
 
 
 def build_fs_as_blocks(h, core=(4, 4), halo=1, nu_pre=2, nu_post=2, omega=0.8, prec="fp64",
-                       use_graph=True, iface_mult=1, monolithic=False):
+                       use_graph=True, iface_mult=1, monolithic=False, cycle="V"):
     o = SmootherOpts()
     for a in range(3):
         o.core[a] = int(core[a]) if a < len(core) else 1
@@ -192,6 +194,7 @@ def build_fs_as_blocks(h, core=(4, 4), halo=1, nu_pre=2, nu_post=2, omega=0.8, p
     o.use_graph = int(bool(use_graph))
     o.iface_mult = int(iface_mult)
     o.monolithic = int(bool(monolithic))
+    o.cycle = CYCLE[cycle] if isinstance(cycle, str) else int(cycle)
     _check(h, lib().build_fs_as_blocks(h, C.byref(o)))
 
 
@@ -339,7 +342,8 @@ class Hierarchy:
         opts = dict(core=self.cfg.get("core", (4, 4)), halo=self.cfg.get("halo", 1),
                     nu_pre=self.cfg.get("nu_pre", 2), nu_post=self.cfg.get("nu_post", 2),
                     omega=self.cfg.get("omega", 0.8), iface_mult=self.cfg.get("iface_mult", 1),
-                    monolithic=self.cfg.get("monolithic", False))
+                    monolithic=self.cfg.get("monolithic", False),
+                    cycle=self.cfg.get("cycle", "V"))
         opts.update(kw)
         build_fs_as_blocks(self.h, **opts)
 

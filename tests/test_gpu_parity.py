@@ -148,6 +148,35 @@ def test_monolithic_comparator_parity(key):
     H.close()
 
 
+@pytest.mark.parametrize("kind", ["W", "F"])
+def test_w_and_f_cycles_parity(kind):
+    """W- and F-cycles (c2 at 3 levels): FP64 cycle and its transpose against
+    the oracle's (whose compositions are pinned in closed form), and an FP32
+    FGMRES solve to a true 1e-10."""
+    cfg = dict(inputs.with_levels(inputs.config("c2"), 3), cycle=kind)
+    w = inputs.advecting_field(cfg)
+    O = OracleHierarchy(cfg, w)
+    H = fsgmg.Hierarchy(cfg, w, device=0)
+    H.build_fs_as_blocks(prec="fp64")
+    rng = np.random.default_rng(8)
+    r = rng.standard_normal(H.N)
+    z = torch.zeros(H.N, dtype=torch.float64, device="cuda")
+    for tr in (False, True):
+        H.vcycle_apply(dev(r), z, transpose=tr)
+        ref = O.vcycle(r, transpose=tr)
+        err = np.linalg.norm(host(z) - ref) / np.linalg.norm(ref)
+        say("[%s-cycle] transpose %s rel err %.3e" % (kind, tr, err))
+        assert err <= 1e-9
+    H.build_fs_as_blocks(prec="fp32")
+    b = O.rhs(inputs.body_force(cfg))
+    x = torch.zeros(H.N, dtype=torch.float64, device="cuda")
+    info = H.gmres_solve(dev(b), x, rtol=1e-10)
+    true = np.linalg.norm(b - O.A[-1] @ host(x)) / np.linalg.norm(b)
+    say("   fp32 solve iters %d true %.2e" % (info["iters"], true))
+    assert info["converged"] and true <= 1e-10
+    H.close()
+
+
 @pytest.mark.parametrize("prec,tol", [("fp32", 2e-4), ("bf16", 2e-2)])
 def test_vcycle_mixed_precision(prec, tol):
     p = pair("c2L3", prec)

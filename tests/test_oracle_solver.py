@@ -156,6 +156,49 @@ def test_two_level_exact_composition(c1):
     assert np.allclose(MT, M.T, rtol=0, atol=1e-12 * abs(M).max())
 
 
+@pytest.mark.parametrize("kind", ["V", "W", "F"])
+def test_three_level_cycle_compositions(kind):
+    """Three levels (coarse 2x2 with a solid bottom row -> 8x8): the cycle
+    equals (I - E_2) A_2^-1 with the closed-form error propagation
+        E_l = S_l^nu2 (I - P_l (I - E_c) A_{l-1}^-1 R_l A_l) S_l^nu1,
+        E_c = E_{l-1} (V),  E_{l-1}^2 (W),  E^V_{l-1} E^F_{l-1} (F),  E_0 = 0,
+    S_l = I - omega B_l A_l with B_l the dense smoother (numpy.linalg.inv
+    blocks); and the transposed cycle is its transpose."""
+    import tests.cfgs as cfgs
+    cfg = cfgs.small(nc=(2, 2), solid_rows=(0,), levels=3, yb=[0.0, 0.25, 1.0],
+                     core=(2, 2), halo=1, omega=0.8, cycle=kind,
+                     bc_d=inputs.config("c1")["bc_d"], bc_u=inputs.config("c1")["bc_u"])
+    H = Hierarchy(cfg)
+    A = [a.toarray() for a in H.A]
+    om = cfg["omega"]
+
+    def S(l):
+        B = H.smoothers[l].dense(H.A[l])
+        return np.eye(A[l].shape[0]) - om * B @ A[l]
+
+    def E(l, k):
+        if l == 0:
+            return np.zeros_like(A[0])
+        P, R = H.P[l].toarray(), H.R[l].toarray()
+        Ec = {"V": lambda: E(l - 1, "V"), "W": lambda: np.linalg.matrix_power(E(l - 1, "W"), 2),
+              "F": lambda: E(l - 1, "V") @ E(l - 1, "F")}[k]()
+        n = A[l].shape[0]
+        cgc = np.eye(n) - P @ (np.eye(Ec.shape[0]) - Ec) @ np.linalg.inv(A[l - 1]) @ R @ A[l]
+        Sl = S(l)
+        return (np.linalg.matrix_power(Sl, cfg["nu_post"]) @ cgc
+                @ np.linalg.matrix_power(Sl, cfg["nu_pre"]))
+
+    N = A[2].shape[0]
+    M_expected = (np.eye(N) - E(2, kind)) @ np.linalg.inv(A[2])
+    M = H.dense_preconditioner()
+    assert np.allclose(M, M_expected, rtol=0, atol=1e-9 * abs(M_expected).max())
+    MT = H.dense_preconditioner(transpose=True)
+    assert np.allclose(MT, M.T, rtol=0, atol=1e-11 * abs(M).max())
+    if kind != "V":    # the cycles differ once there are three levels
+        Hv = Hierarchy(dict(cfg, cycle="V"))
+        assert not np.allclose(M, Hv.dense_preconditioner(), rtol=0, atol=1e-6 * abs(M).max())
+
+
 def test_one_level_gmres_one_iteration():
     cfg = inputs.with_levels(inputs.config("c1"), 1)
     H = Hierarchy(cfg)
