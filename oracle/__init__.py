@@ -16,8 +16,9 @@ Modules
 mesh       nested structured hierarchy, node types, J2 DOF layout, Dirichlet
 fem        Q2/Q1 assembly of the linearized monolithic system (Section 2.2)
 transfer   prolongation and equation-routed restriction (Section 3.3)
-schwarz    Vanka / overlapping blocks and the additive update (Section 3.2)
-multigrid  the V-cycle and its transpose (Section 3)
+schwarz    Vanka / overlapping blocks, the additive update and the colour-ordered
+           multiplicative sweep (Section 3.2)
+multigrid  the V-, W- and F-cycles and their transposes (Section 3)
 krylov     restarted FGMRES with classical Gram-Schmidt twice
 adjoint    adjoint solve and parameter gradients
 """

@@ -18,7 +18,8 @@ import scipy.sparse as sp
 
 from . import fem, transfer
 from .mesh import Level, hierarchy_levels
-from .schwarz import FieldSplitSchwarz, build_blocks
+from .schwarz import (FieldSplitSchwarz, MultiplicativeSchwarz, block_colouring,
+                      build_blocks, colour_major, coupling_pattern)
 
 
 class Hierarchy:
@@ -49,15 +50,35 @@ class Hierarchy:
     def finest(self) -> Level:
         return self.levels[-1]
 
-    def build_smoothers(self, core=None, halo=None, iface_mult=None, monolithic=None):
+    def build_smoothers(self, core=None, halo=None, iface_mult=None, monolithic=None,
+                        schwarz=None):
+        """schwarz: "additive" (default) or "multiplicative"; the
+        multiplicative sweep takes the blocks colour by colour (greedy
+        colouring in block order), the block order inside a colour kept."""
         cfg = self.cfg
         core = tuple(cfg["core"]) if core is None else tuple(core)
         halo = int(cfg["halo"]) if halo is None else int(halo)
         mult = int(cfg.get("iface_mult", 1)) if iface_mult is None else int(iface_mult)
         mono = bool(cfg.get("monolithic", False)) if monolithic is None else bool(monolithic)
+        kind = cfg.get("schwarz", "additive") if schwarz is None else schwarz
+        if kind not in ("additive", "multiplicative"):
+            raise ValueError(f"unknown Schwarz kind {kind!r}")
+        self.colours = [None] * self.L
         for l in range(1, self.L):
             blocks, _ = build_blocks(self.levels[l], core, halo, mult, mono)
-            self.smoothers[l] = FieldSplitSchwarz(self.A[l], blocks)
+            if kind == "additive":
+                self.smoothers[l] = FieldSplitSchwarz(self.A[l], blocks)
+            else:
+                blocks, self.colours[l] = colour_major(
+                    blocks, block_colouring(self.coupling_pattern(l), blocks))
+                self.smoothers[l] = MultiplicativeSchwarz(self.A[l], blocks)
+
+    def coupling_pattern(self, l: int) -> sp.csr_matrix:
+        """Parameter-independent coupling pattern of the level-l operator (the
+        union over its Dirichlet-reduced affine pieces)."""
+        lv = self.levels[l]
+        return coupling_pattern([fem.dirichlet_reduce(lv, self.parts[l][k])
+                                 for k in ("base", "AG", "AC", "Amu")])
 
     def rhs(self, fnodal: np.ndarray) -> np.ndarray:
         """Finest-level right-hand side for a nodal body force (Dirichlet-lifted)."""

@@ -33,6 +33,12 @@ Dirichlet rows, whose rows are identity) get one Jacobi step r_i / A_ii.
 Blocks are ordered field d before field u, tiles lexicographically (x
 fastest), solid before fluid inside a tile.
 
+Multiplicative sweep (the formula after the additive one): block j uses the
+residual of the latest iterate and writes all of its entries.  The blocks
+run colour by colour (a greedy first-fit colouring of the block conflict
+graph in block order, the order inside a colour kept); blocks of one colour
+are uncoupled, so their order inside the colour does not change the sweep.
+
 Enlarged interface cores (``iface_mult`` = m > 1; a reading of the
 configuration that asks for interface blocks about three times the interior
 ones, not a rule of the paper): for each region, a tile row whose region
@@ -206,3 +212,116 @@ class FieldSplitSchwarz:
             B[np.ix_(I[own], I)] = Ainv[own]
         B[self.jac, self.jac] = self.jac_inv
         return B
+
+
+# ----------------------------------------------------------------------
+# Multiplicative Schwarz (the formula after the additive one in Section 3.2)
+# ----------------------------------------------------------------------
+COUPLING_REL = 1e-14
+
+
+def coupling_pattern(pieces) -> sp.csr_matrix:
+    """Boolean pattern of the entries that couple two unknowns.
+
+    The level operator is an affine combination of parameter-independent
+    pieces.  An entry counts when some piece holds it above COUPLING_REL
+    times that piece's largest magnitude in the row, so the pattern does not
+    change with the parameters, and entries that vanish mathematically but
+    carry assembly rounding (about 1e-17 of the row) do not count."""
+    out = None
+    for P in pieces:
+        P = sp.csr_matrix(abs(P.tocsr()))
+        rmax = np.zeros(P.shape[0])
+        nz = np.diff(P.indptr) > 0
+        rmax[nz] = np.maximum.reduceat(P.data, P.indptr[:-1][nz]) if P.nnz else 0.0
+        keep = P.data > COUPLING_REL * np.repeat(rmax, np.diff(P.indptr))
+        Q = sp.csr_matrix((keep.astype(np.float64), P.indices, P.indptr), shape=P.shape)
+        Q.eliminate_zeros()
+        out = Q if out is None else out + Q
+    out.data[:] = 1.0
+    return out
+
+
+def block_colouring(pattern: sp.csr_matrix, blocks) -> np.ndarray:
+    """Greedy first-fit colouring of the blocks in their given order.
+
+    Blocks j and k conflict when they share an unknown or the pattern couples
+    them in either direction (pattern[a, b] for some a in I_j, b in I_k, or
+    the reverse).  Blocks of one colour then neither read what another
+    writes nor write what it reads, so inside a colour the multiplicative
+    update equals the additive one.  Returns colour[j] >= 0."""
+    n = len(blocks)
+    if n == 0:
+        return np.zeros(0, np.int64)
+    N = pattern.shape[0]
+    rows = np.concatenate([np.full(len(I), j) for j, I in enumerate(blocks)])
+    cols = np.concatenate(blocks)
+    M = sp.csr_matrix((np.ones(len(rows)), (rows, cols)), shape=(n, N))
+    P = sp.csr_matrix(pattern, dtype=np.float64)
+    P.data[:] = 1.0
+    reach = M @ (P + P.T + sp.identity(N, format="csr"))   # unknowns I_j touches
+    conflict = (reach @ M.T).tocsr()
+    colour = -np.ones(n, np.int64)
+    for j in range(n):
+        nb = conflict.indices[conflict.indptr[j]:conflict.indptr[j + 1]]
+        used = set(colour[nb[(nb != j) & (colour[nb] >= 0)]].tolist())
+        c = 0
+        while c in used:
+            c += 1
+        colour[j] = c
+    return colour
+
+
+def colour_major(blocks, colour):
+    """Blocks sorted by colour, the given order kept inside a colour."""
+    order = sorted(range(len(blocks)), key=lambda j: (colour[j], j))
+    return [blocks[j] for j in order], [int(colour[j]) for j in order]
+
+
+class MultiplicativeSchwarz:
+    """One multiplicative sweep (Section 3.2): for j = 1..n in order,
+        y_{I_j} <- y_{I_j} + A_j^{-1} (f - A y)_{I_j},
+    every entry of block j written (no owner rule).  The unknowns in no block
+    (u^s and Dirichlet rows) follow as one-unknown blocks with A_ii, in
+    increasing index order.  apply(r) returns B r, the correction that the
+    sweep adds when started from x with r = f - A x (the sweep is affine in
+    x, so B is the preconditioner of the damped Richardson step
+    x <- x + omega B (f - A x)).
+
+    apply_transpose(r) returns B^T r.  With every block a principal
+    submatrix, I - B^T A^T equals the product of (I - E_j A_j^{-T} R_j A^T)
+    over j = 1..n with block n applied first: the sweep on A^T with the
+    transposed block solves in the reverse order."""
+
+    def __init__(self, A: sp.csr_matrix, blocks):
+        A = A.tocsr()
+        self.N = A.shape[0]
+        self.A, self.AT = A, A.T.tocsr()
+        self.blocks = list(blocks)
+        self.lu = [la.lu_factor(A[I][:, I].toarray()) for I in self.blocks]
+        self.rows = [A[I] for I in self.blocks]
+        self.rows_t = [self.AT[I] for I in self.blocks]
+        covered = np.zeros(self.N, bool)
+        for I in self.blocks:
+            covered[I] = True
+        self.jac = np.where(~covered)[0]
+        self.jac_diag = A.diagonal()[self.jac]
+        self.jac_rows = A[self.jac]
+        self.jac_rows_t = self.AT[self.jac]
+
+    def apply(self, r: np.ndarray) -> np.ndarray:
+        e = np.zeros(self.N)
+        for lu, I, Ar in zip(self.lu, self.blocks, self.rows):
+            e[I] += la.lu_solve(lu, r[I] - Ar @ e)
+        for q, i in enumerate(self.jac):
+            e[i] += (r[i] - self.jac_rows[q] @ e)[0] / self.jac_diag[q]
+        return e
+
+    def apply_transpose(self, r: np.ndarray) -> np.ndarray:
+        e = np.zeros(self.N)
+        for q in range(len(self.jac) - 1, -1, -1):
+            i = self.jac[q]
+            e[i] += (r[i] - self.jac_rows_t[q] @ e)[0] / self.jac_diag[q]
+        for lu, I, At in zip(self.lu[::-1], self.blocks[::-1], self.rows_t[::-1]):
+            e[I] += la.lu_solve(lu, r[I] - At @ e, trans=1)
+        return e
