@@ -61,6 +61,12 @@ typedef enum { FSGMG_FP64 = 0, FSGMG_FP32 = 1, FSGMG_BF16 = 2 } fsgmg_prec;
  * level), F (an F-cycle then a V-cycle on the coarser level). */
 typedef enum { FSGMG_CYCLE_V = 0, FSGMG_CYCLE_W = 1, FSGMG_CYCLE_F = 2 } fsgmg_cycle;
 
+/* Schwarz update of the smoother (Section 3.2): additive (every block takes
+ * the residual of the iterate the sweep starts from, entry i from the last
+ * block containing it) or multiplicative (block after block, each taking
+ * the residual of the latest iterate and writing all of its entries). */
+typedef enum { FSGMG_SCHWARZ_ADDITIVE = 0, FSGMG_SCHWARZ_MULTIPLICATIVE = 1 } fsgmg_schwarz;
+
 /* Nested structured mesh (Section 3.3: every level is the midpoint
  * refinement of a conforming coarse mesh, regions are the same on every
  * level).  Faces: 0 x-min, 1 x-max, 2 y-min, 3 y-max, 4 z-min, 5 z-max.
@@ -114,7 +120,18 @@ typedef struct {
  * core and region over its displacements, velocities and pressures together,
  * u^s included; the rest of the V-cycle is unchanged.
  * cycle: fsgmg_cycle used by vcycle_apply, gmres_solve and adjoint_solve
- * (the transposed cycle is the exact transpose of the chosen one). */
+ * (the transposed cycle is the exact transpose of the chosen one).
+ * schwarz: fsgmg_schwarz.  The multiplicative sweep colours the blocks of
+ * each level (greedy first fit in block order; blocks conflict when they
+ * share an unknown or the operator couples them either way, an entry
+ * counting when an affine piece of the operator holds it above 1e-14 of
+ * that piece's largest magnitude in the row), runs the colours in order,
+ * each colour's blocks at once on the residual of the latest iterate, then
+ * the unknowns in no block (which must be mutually uncoupled, else
+ * FSGMG_EINVAL); the damping omega scales the whole sweep's correction.  The
+ * blocks are then stored colour by colour (export_blocks shows that order),
+ * with full inverses (every row of a block is written).  The transposed
+ * sweep runs the reverse order with transposed block solves. */
 typedef struct {
   int core[3];
   int halo;
@@ -125,6 +142,7 @@ typedef struct {
   int iface_mult;
   int monolithic;
   int cycle;
+  int schwarz;
 } fsgmg_smoother_opts;
 
 /* FGMRES(restart), right preconditioned, x0 = 0, CGS2; converged when the
@@ -214,6 +232,12 @@ fsgmg_status export_vector(fsgmg_h h, int level, int which, double* out);
  * none). */
 fsgmg_status export_blocks(fsgmg_h h, int level, int64_t sizes[2], int64_t* ptr,
                            int32_t* dofs, int32_t* owner);
+
+/* Colours of the multiplicative sweep on level l >= 1: *ncolours (0 for the
+ * additive smoother) and, if colour_ptr is not NULL, colour_ptr[0..ncolours]
+ * = index of the first block of each colour in export_blocks order (the
+ * last entry is the number of blocks).  ESTATE before build_fs_as_blocks. */
+fsgmg_status block_colours(fsgmg_h h, int level, int64_t* ncolours, int64_t* colour_ptr);
 
 /* Measurement: enable != 0 starts recording HIP events on the handle's
  * stream around selected launches (cleared on start); enable == 0 stops,

@@ -27,6 +27,7 @@
 // the kinematic rows K sit in the solid blocks and only Dirichlet unknowns
 // stay outside every block.
 #include <algorithm>
+#include <cmath>
 #include <stdexcept>
 
 #include "host.hpp"
@@ -99,6 +100,7 @@ void build_blocks(const Level& lv, const int* core, int halo, int iface_mult, bo
                                                       row_groups(lv, core, 1, iface_mult)};
   bs.ptr.assign(1, 0);
   bs.dofs.clear();
+  bs.colour_ptr.clear();
   std::vector<int32_t> stamp_el(lv.nE, -1), stamp_node(lv.N2, -1), stamp_vert(lv.NV, -1);
   int32_t stamp = 0;
   std::vector<int64_t> core_el, blk_el, dofs;
@@ -203,6 +205,98 @@ void build_blocks(const Level& lv, const int* core, int halo, int iface_mult, bo
   bs.jac.clear();
   for (int64_t i = 0; i < lv.N; ++i)
     if (bs.owner[i] < 0) bs.jac.push_back((int32_t)i);
+}
+
+}  // namespace fsgmg
+
+namespace fsgmg {
+
+void colour_blocks(const CsrHost& A, const std::vector<double>* pieces, int npieces,
+                   BlockSet& bs) {
+  const int64_t N = A.nrows, nb = bs.nblk();
+  // entries that couple (per-piece row-relative threshold)
+  std::vector<uint8_t> cpl(A.nnz(), 0);
+  for (int64_t i = 0; i < N; ++i)
+    for (int q = 0; q < npieces; ++q) {
+      const std::vector<double>& P = pieces[q];
+      double mx = 0.0;
+      for (int64_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k) mx = std::max(mx, std::fabs(P[k]));
+      if (mx == 0.0) continue;
+      for (int64_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k)
+        if (std::fabs(P[k]) > kCouplingRel * mx) cpl[k] = 1;
+    }
+  // blocks containing each unknown
+  std::vector<int64_t> mptr(N + 1, 0);
+  for (int32_t g : bs.dofs) mptr[g + 1]++;
+  for (int64_t i = 0; i < N; ++i) mptr[i + 1] += mptr[i];
+  std::vector<int32_t> mblk(bs.dofs.size());
+  {
+    std::vector<int64_t> cur(mptr.begin(), mptr.end() - 1);
+    for (int64_t j = 0; j < nb; ++j)
+      for (int64_t p = bs.ptr[j]; p < bs.ptr[j + 1]; ++p) mblk[cur[bs.dofs[p]]++] = (int32_t)j;
+  }
+  // blocks that block j reaches through its rows (shared unknowns included);
+  // the conflict graph is this relation made symmetric
+  std::vector<std::vector<int32_t>> adj(nb);
+  std::vector<int64_t> seen(nb, -1);
+  for (int64_t j = 0; j < nb; ++j) {
+    auto touch = [&](int64_t g) {
+      for (int64_t t = mptr[g]; t < mptr[g + 1]; ++t) {
+        const int32_t k = mblk[t];
+        if (k == j || seen[k] == j) continue;
+        seen[k] = j;
+        adj[j].push_back(k);
+        adj[k].push_back((int32_t)j);
+      }
+    };
+    for (int64_t p = bs.ptr[j]; p < bs.ptr[j + 1]; ++p) {
+      const int32_t a = bs.dofs[p];
+      touch(a);
+      for (int64_t k = A.rowptr[a]; k < A.rowptr[a + 1]; ++k)
+        if (cpl[k]) touch(A.col[k]);
+    }
+  }
+  // first fit in block order
+  std::vector<int32_t> colour(nb, -1), mark;
+  int32_t ncol = 0;
+  for (int64_t j = 0; j < nb; ++j) {
+    mark.assign(ncol + 1, 0);
+    for (int32_t k : adj[j])
+      if (colour[k] >= 0) mark[colour[k]] = 1;
+    int32_t c = 0;
+    while (mark[c]) ++c;
+    colour[j] = c;
+    ncol = std::max(ncol, c + 1);
+  }
+  // regroup colour by colour
+  std::vector<int64_t> ord(nb);
+  for (int64_t j = 0; j < nb; ++j) ord[j] = j;
+  std::stable_sort(ord.begin(), ord.end(),
+                   [&](int64_t a, int64_t b) { return colour[a] < colour[b]; });
+  std::vector<int64_t> ptr(1, 0);
+  std::vector<int32_t> dofs;
+  dofs.reserve(bs.dofs.size());
+  bs.colour_ptr.assign(ncol + 1, 0);
+  for (int64_t q = 0; q < nb; ++q) {
+    const int64_t j = ord[q];
+    dofs.insert(dofs.end(), bs.dofs.begin() + bs.ptr[j], bs.dofs.begin() + bs.ptr[j + 1]);
+    ptr.push_back((int64_t)dofs.size());
+    bs.colour_ptr[colour[j] + 1] = q + 1;
+  }
+  for (int32_t c = 0; c < ncol; ++c)
+    bs.colour_ptr[c + 1] = std::max(bs.colour_ptr[c + 1], bs.colour_ptr[c]);
+  bs.ptr.swap(ptr);
+  bs.dofs.swap(dofs);
+  for (int64_t j = 0; j < nb; ++j)
+    for (int64_t p = bs.ptr[j]; p < bs.ptr[j + 1]; ++p) bs.owner[bs.dofs[p]] = (int32_t)j;
+  // the Jacobi unknowns must be mutually uncoupled
+  std::vector<uint8_t> isjac(N, 0);
+  for (int32_t i : bs.jac) isjac[i] = 1;
+  for (int32_t i : bs.jac)
+    for (int64_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k)
+      if (cpl[k] && A.col[k] != i && isjac[A.col[k]])
+        throw std::invalid_argument(
+            "multiplicative Schwarz: two unknowns outside every block are coupled");
 }
 
 }  // namespace fsgmg

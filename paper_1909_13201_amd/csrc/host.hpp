@@ -105,10 +105,24 @@ struct BlockSet {
   std::vector<int32_t> dofs;    // sorted per block
   std::vector<int32_t> owner;   // N, last block containing the DOF, -1 if none
   std::vector<int32_t> jac;     // DOFs in no block (Jacobi)
+  std::vector<int64_t> colour_ptr;  // multiplicative sweep: first block of each colour
   int64_t nblk() const { return ptr.empty() ? 0 : (int64_t)ptr.size() - 1; }
 };
 
 void build_blocks(const Level& lv, const int* core, int halo, int iface_mult, bool monolithic,
                   BlockSet& bs);
+
+// Order of the multiplicative sweep (Section 3.2): greedy first-fit colouring
+// of the blocks in their current order, then the blocks regrouped colour by
+// colour with the order inside a colour kept (owner recomputed, colour_ptr
+// filled).  Blocks conflict when they share an unknown or the operator
+// couples them in either direction; an entry couples when one of the affine
+// pieces holds it above kCouplingRel times that piece's largest magnitude in
+// the row (parameter-independent, blind to assembly rounding of entries that
+// vanish).  Throws std::invalid_argument when two unknowns outside every
+// block are coupled (their Jacobi step would then not be the sequential one).
+constexpr double kCouplingRel = 1e-14;
+void colour_blocks(const CsrHost& A, const std::vector<double>* pieces, int npieces,
+                   BlockSet& bs);
 
 }  // namespace fsgmg

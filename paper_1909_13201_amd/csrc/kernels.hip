@@ -1444,6 +1444,72 @@ template void launch_smooth<double>(const BlocksView&, WPrec, const void*, const
 template void launch_smooth<float>(const BlocksView&, WPrec, const void*, const float*, float*,
                                    float*, double, bool, bool, int64_t, hipStream_t, int);
 
+// Multiplicative sweep, transposed colour step: e[I_j] += (W_j^T r[I_j]) for
+// the blocks of one colour; they are disjoint, so the scatter has no races.
+template <typename TV>
+__global__ __launch_bounds__(kThreads) void k_scatter_add(int64_t n, const int32_t* __restrict__ idx,
+                                                          const TV* __restrict__ t,
+                                                          TV* __restrict__ e) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) e[idx[k]] += t[k];
+}
+
+// x = (first ? 0 : x) + a e
+template <typename TV>
+__global__ __launch_bounds__(kThreads) void k_add_scaled(int64_t n, TV a, const TV* __restrict__ e,
+                                                         TV* __restrict__ x, int first) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = (first ? TV(0) : x[i]) + a * e[i];
+}
+
+template <typename TV, typename TW>
+static void smooth_t1_impl(const BlocksView& B, const TW* W, const TV* r, TV* tbuf,
+                           hipStream_t s) {
+  const size_t sm = sizeof(TV) * (size_t)B.max_mpad;
+  hipLaunchKernelGGL((k_smooth_t1<TV, TW>), dim3((unsigned)B.nblk), dim3(kThreads), sm, s, B, W,
+                     r, tbuf);
+}
+
+template <typename TV>
+void launch_smooth_colour(const BlocksView& B, WPrec wp, const void* W, const TV* r, TV* e,
+                          TV* tbuf, int64_t p0, int64_t p1, bool transpose, hipStream_t s,
+                          int threads) {
+  if (!transpose || B.nblk == 0) {
+    launch_smooth<TV>(B, wp, W, r, e, tbuf, 1.0, false, false, 0, s, threads);
+    return;
+  }
+  switch (wp) {
+    case WPrec::F64:
+      smooth_t1_impl<TV, double>(B, (const double*)W, r, tbuf, s);
+      break;
+    case WPrec::F32:
+      smooth_t1_impl<TV, float>(B, (const float*)W, r, tbuf, s);
+      break;
+    case WPrec::BF16:
+      smooth_t1_impl<TV, __hip_bfloat16>(B, (const __hip_bfloat16*)W, r, tbuf, s);
+      break;
+  }
+  const int64_t n = p1 - p0;
+  if (n > 0)
+    hipLaunchKernelGGL((k_scatter_add<TV>), dim3(grid_for(n, kThreads)), dim3(kThreads), 0, s, n,
+                       B.dofs + p0, tbuf + p0, e);
+}
+template void launch_smooth_colour<double>(const BlocksView&, WPrec, const void*, const double*,
+                                           double*, double*, int64_t, int64_t, bool, hipStream_t,
+                                           int);
+template void launch_smooth_colour<float>(const BlocksView&, WPrec, const void*, const float*,
+                                          float*, float*, int64_t, int64_t, bool, hipStream_t,
+                                          int);
+
+template <typename TV>
+void launch_add_scaled(int64_t n, double a, const TV* e, TV* x, bool first, hipStream_t s) {
+  if (n > 0)
+    hipLaunchKernelGGL((k_add_scaled<TV>), dim3(grid_for(n, kThreads)), dim3(kThreads), 0, s, n,
+                       (TV)a, e, x, (int)first);
+}
+template void launch_add_scaled<double>(int64_t, double, const double*, double*, bool, hipStream_t);
+template void launch_add_scaled<float>(int64_t, double, const float*, float*, bool, hipStream_t);
+
 void launch_gather_blocks(const int32_t* jlist, int64_t nb, const BlocksView& B,
                           const int64_t* rowptr, const int32_t* col, const double* val,
                           const int64_t* dense_off, double* dense, hipStream_t s) {

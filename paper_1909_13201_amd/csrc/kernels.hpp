@@ -129,6 +129,19 @@ void launch_smooth(const BlocksView& B, WPrec wp, const void* W, const TV* r, TV
                    double omega, bool first, bool transpose, int64_t N, hipStream_t s,
                    int threads = 0);
 
+// ---- multiplicative sweep, one colour: B views the colour's blocks (all
+// rows owned, mutually uncoupled) and no Jacobi unknowns, or no blocks and
+// the Jacobi unknowns.  e[I_j] += W_j r[I_j] (transpose: W_j^T r[I_j]);
+// Jacobi: e[i] += r[i] / A_ii.  p0..p1: positions of the colour's blocks in
+// B.dofs (transposed step, which goes through tbuf) ----
+template <typename TV>
+void launch_smooth_colour(const BlocksView& B, WPrec wp, const void* W, const TV* r, TV* e,
+                          TV* tbuf, int64_t p0, int64_t p1, bool transpose, hipStream_t s,
+                          int threads = 0);
+// x = (first ? 0 : x) + a e
+template <typename TV>
+void launch_add_scaled(int64_t n, double a, const TV* e, TV* x, bool first, hipStream_t s);
+
 // ---- block setup ----
 // Block setup over a list of block ids (jlist[b], b < nb; launch b of the
 // list works on block jlist[b]).  Dense copies of the blocks' principal

@@ -261,6 +261,9 @@ struct DLevel {
   int64_t W_elems = 0;
   double *b64 = nullptr, *x64 = nullptr, *r64 = nullptr, *tb64 = nullptr;
   float *b32 = nullptr, *x32 = nullptr, *r32 = nullptr, *tb32 = nullptr;
+  // multiplicative sweep: correction e and the residual of the latest iterate
+  double *e64 = nullptr, *rc64 = nullptr;
+  float *e32 = nullptr, *rc32 = nullptr;
 };
 
 }  // namespace
@@ -693,8 +696,26 @@ void upload_blocks(fsgmg_hierarchy& h, int l) {
   const Level& lv = h.levels[l];
   const BlockSet& bs = h.blocks[l];
   DLevel& d = h.dl[l];
+  // release the previous index sets, inverses and sweep buffers of the level
+  {
+    BlocksView& o = d.bv;
+    for (const void* q : {(const void*)o.dof_ptr, (const void*)o.dofs, (const void*)o.own_ptr,
+                          (const void*)o.own_dof, (const void*)o.own_loc, (const void*)o.w_off,
+                          (const void*)o.mpad, (const void*)o.jac, o.jac_inv,
+                          (const void*)o.tpos_ptr, (const void*)o.tpos, (const void*)o.order,
+                          (const void*)d.W, (const void*)d.tb64, (const void*)d.tb32,
+                          (const void*)d.e64, (const void*)d.rc64, (const void*)d.e32,
+                          (const void*)d.rc32})
+      h.dfree(const_cast<void*>(q));
+    o = BlocksView{};
+    d.W = nullptr;
+    d.tb64 = d.e64 = d.rc64 = nullptr;
+    d.tb32 = d.e32 = d.rc32 = nullptr;
+  }
   const int RV = rows_per_vector(h.sopt.prec);
   const int64_t nb = bs.nblk();
+  // multiplicative sweep: a block writes every one of its rows
+  const bool all_rows = h.sopt.schwarz == FSGMG_SCHWARZ_MULTIPLICATIVE;
   std::vector<int32_t> own_ptr(1, 0), own_dof, own_loc, mpad(nb);
   std::vector<int64_t> w_off(nb + 1, 0);
   int max_n = 0, max_mpad = 0;
@@ -702,7 +723,7 @@ void upload_blocks(fsgmg_hierarchy& h, int l) {
     const int64_t b0 = bs.ptr[j], n = bs.ptr[j + 1] - b0;
     int m = 0;
     for (int64_t k = 0; k < n; ++k)
-      if (bs.owner[bs.dofs[b0 + k]] == (int32_t)j) {
+      if (all_rows || bs.owner[bs.dofs[b0 + k]] == (int32_t)j) {
         own_dof.push_back(bs.dofs[b0 + k]);
         own_loc.push_back((int32_t)k);
         ++m;
@@ -751,11 +772,15 @@ void upload_blocks(fsgmg_hierarchy& h, int l) {
   v.tpos_ptr = h.upload(tcnt);
   v.tpos = h.upload(tpos);
   {
+    // largest inverses first, inside each colour of a multiplicative sweep
     std::vector<int32_t> order(nb);
     for (int64_t j = 0; j < nb; ++j) order[j] = (int32_t)j;
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-      return w_off[a + 1] - w_off[a] > w_off[b + 1] - w_off[b];
-    });
+    std::vector<int64_t> seg = all_rows ? bs.colour_ptr : std::vector<int64_t>{0, nb};
+    for (size_t c = 0; c + 1 < seg.size(); ++c)
+      std::stable_sort(order.begin() + seg[c], order.begin() + seg[c + 1],
+                       [&](int32_t a, int32_t b) {
+                         return w_off[a + 1] - w_off[a] > w_off[b + 1] - w_off[b];
+                       });
     v.order = h.upload(order);
   }
   d.W_elems = w_off[nb];
@@ -765,6 +790,15 @@ void upload_blocks(fsgmg_hierarchy& h, int l) {
     d.tb64 = h.zeros<double>(std::max<int64_t>(ntot, 1));
   else
     d.tb32 = h.zeros<float>(std::max<int64_t>(ntot, 1));
+  if (all_rows) {
+    if (h.sopt.prec == FSGMG_FP64) {
+      d.e64 = h.zeros<double>(lv.N);
+      d.rc64 = h.zeros<double>(lv.N);
+    } else {
+      d.e32 = h.zeros<float>(lv.N);
+      d.rc32 = h.zeros<float>(lv.N);
+    }
+  }
 }
 
 void plan_factor(fsgmg_hierarchy& h, int l) {
@@ -922,6 +956,8 @@ struct Vec<double> {
   static double* x(DLevel& d) { return d.x64; }
   static double* r(DLevel& d) { return d.r64; }
   static double* t(DLevel& d) { return d.tb64; }
+  static double* e(DLevel& d) { return d.e64; }
+  static double* rc(DLevel& d) { return d.rc64; }
   static const BOpView<double>& op(DLevel& d, bool tr) { return tr ? d.AT.v64 : d.A.v64; }
   static const TransferView<double>& tv(DLevel& d) { return d.t64; }
 };
@@ -931,12 +967,81 @@ struct Vec<float> {
   static float* x(DLevel& d) { return d.x32; }
   static float* r(DLevel& d) { return d.r32; }
   static float* t(DLevel& d) { return d.tb32; }
+  static float* e(DLevel& d) { return d.e32; }
+  static float* rc(DLevel& d) { return d.rc32; }
   static const BOpView<float>& op(DLevel& d, bool tr) { return tr ? d.AT.v32 : d.A.v32; }
   static const TransferView<float>& tv(DLevel& d) { return d.t32; }
 };
 
+// Multiplicative sweeps on level l (Section 3.2): from r0 = b - A x (b when
+// starting from zero) the correction e is built colour by colour, each colour
+// on the residual r0 - A e of the latest correction, the Jacobi unknowns last;
+// then x += omega e.  Transposed: A^T, the Jacobi unknowns first, colours in
+// reverse order, transposed block solves.
+template <typename TV>
+void smooth_level_mult(fsgmg_hierarchy& h, int l, int nsweeps, bool transpose, bool from_zero) {
+  DLevel& d = h.dl[l];
+  const BlockSet& bs = h.blocks[l];
+  const int D = h.D;
+  const WPrec wp = wprec(h.sopt.prec);
+  TV* b = Vec<TV>::b(d);
+  TV* x = Vec<TV>::x(d);
+  TV* r0 = Vec<TV>::r(d);
+  TV* e = Vec<TV>::e(d);
+  TV* rc = Vec<TV>::rc(d);
+  const bool fin = l == h.L - 1;
+  const int64_t ncol = (int64_t)bs.colour_ptr.size() - 1;
+  const BOpView<TV>& A = Vec<TV>::op(d, transpose);
+  const int lanes = h.tune[l].spmv_lanes;
+  for (int s = 0; s < nsweeps; ++s) {
+    const bool first = s == 0 && from_zero;
+    const TV* rs = b;
+    if (!first) {
+      TimedLaunch t(h, 1, fin);
+      launch_spmv<TV>(A, D, x, b, r0, true, h.stream, lanes);
+      rs = r0;
+    }
+    launch_fill<TV>(e, TV(0), d.N, h.stream);
+    bool fresh = true;   // e == 0: the residual of the latest iterate is rs
+    auto step = [&](const BlocksView& v, int64_t p0, int64_t p1) {
+      if (v.nblk == 0 && v.njac == 0) return;
+      const TV* rr = rs;
+      if (!fresh) {
+        TimedLaunch t(h, 1, fin);
+        launch_spmv<TV>(A, D, e, rs, rc, true, h.stream, lanes);
+        rr = rc;
+      }
+      TimedLaunch t(h, 0, fin);
+      launch_smooth_colour<TV>(v, wp, d.W, rr, e, Vec<TV>::t(d), p0, p1, transpose, h.stream,
+                               h.tune[l].smooth_threads);
+      fresh = false;
+    };
+    BlocksView jv = d.bv;
+    jv.nblk = 0;
+    auto colour = [&](int64_t c) {
+      BlocksView v = d.bv;
+      v.order = d.bv.order + bs.colour_ptr[c];
+      v.nblk = bs.colour_ptr[c + 1] - bs.colour_ptr[c];
+      v.njac = 0;
+      step(v, bs.ptr[bs.colour_ptr[c]], bs.ptr[bs.colour_ptr[c + 1]]);
+    };
+    if (transpose) {
+      step(jv, 0, 0);
+      for (int64_t c = ncol - 1; c >= 0; --c) colour(c);
+    } else {
+      for (int64_t c = 0; c < ncol; ++c) colour(c);
+      step(jv, 0, 0);
+    }
+    launch_add_scaled<TV>(d.N, h.sopt.omega, e, x, first, h.stream);
+  }
+}
+
 template <typename TV>
 void smooth_level(fsgmg_hierarchy& h, int l, int nsweeps, bool transpose, bool from_zero) {
+  if (h.sopt.schwarz == FSGMG_SCHWARZ_MULTIPLICATIVE) {
+    smooth_level_mult<TV>(h, l, nsweeps, transpose, from_zero);
+    return;
+  }
   DLevel& d = h.dl[l];
   const int D = h.D;
   const WPrec wp = wprec(h.sopt.prec);
@@ -1293,9 +1398,16 @@ void autotune_impl(fsgmg_hierarchy& h) {
       }
     }
     best = 1e30f;
+    // multiplicative sweep: time the first colour (disjoint blocks, no Jacobi)
+    BlocksView tv = d.bv;
+    const BlockSet& bs = h.blocks[l];
+    if (h.sopt.schwarz == FSGMG_SCHWARZ_MULTIPLICATIVE && bs.colour_ptr.size() > 1) {
+      tv.nblk = bs.colour_ptr[1];
+      tv.njac = 0;
+    }
     for (int th : threads) {
       const float t = time_launch(h, [&] {
-        launch_smooth<TV>(d.bv, wp, d.W, Vec<TV>::b(d), Vec<TV>::x(d), Vec<TV>::t(d), 1.0, true,
+        launch_smooth<TV>(tv, wp, d.W, Vec<TV>::b(d), Vec<TV>::x(d), Vec<TV>::t(d), 1.0, true,
                           false, d.N, h.stream, th);
       });
       if (t < best) {
@@ -1421,21 +1533,26 @@ fsgmg_status build_fs_as_blocks(fsgmg_h h, const fsgmg_smoother_opts* opts) {
     if (opts->cycle < FSGMG_CYCLE_V || opts->cycle > FSGMG_CYCLE_F)
       throw Fail{FSGMG_EINVAL, "cycle must be FSGMG_CYCLE_V, _W or _F"};
     if (opts->iface_mult < 0) throw Fail{FSGMG_EINVAL, "iface_mult must be >= 0"};
+    if (opts->schwarz != FSGMG_SCHWARZ_ADDITIVE && opts->schwarz != FSGMG_SCHWARZ_MULTIPLICATIVE)
+      throw Fail{FSGMG_EINVAL, "schwarz must be FSGMG_SCHWARZ_ADDITIVE or _MULTIPLICATIVE"};
     const int mult = std::max(1, opts->iface_mult);
     const bool same_sets = h->have_blocks && h->sopt.halo == opts->halo &&
                            h->sopt.core[0] == opts->core[0] && h->sopt.core[1] == opts->core[1] &&
                            h->sopt.core[2] == opts->core[2] &&
                            std::max(1, h->sopt.iface_mult) == mult &&
                            (h->sopt.monolithic != 0) == (opts->monolithic != 0) &&
-                           h->sopt.prec == opts->prec;
+                           h->sopt.schwarz == opts->schwarz && h->sopt.prec == opts->prec;
     h->sopt = *opts;
     h->factors_valid = false;
     h->invalidate_graphs();
     if (!same_sets) {
       try {
-        for (int l = 1; l < h->L; ++l)
+        for (int l = 1; l < h->L; ++l) {
           build_blocks(h->levels[l], opts->core, opts->halo, mult, opts->monolithic != 0,
                        h->blocks[l]);
+          if (opts->schwarz == FSGMG_SCHWARZ_MULTIPLICATIVE)
+            colour_blocks(h->ops[l].A, h->ops[l].piece, 4, h->blocks[l]);
+        }
       } catch (const std::invalid_argument& e) {
         h->have_blocks = false;
         throw Fail{FSGMG_EINVAL, e.what()};
@@ -1664,6 +1781,20 @@ fsgmg_status export_blocks(fsgmg_h h, int level, int64_t sizes[2], int64_t* ptr,
     if (ptr) std::memcpy(ptr, bs.ptr.data(), bs.ptr.size() * sizeof(int64_t));
     if (dofs) std::memcpy(dofs, bs.dofs.data(), bs.dofs.size() * sizeof(int32_t));
     if (owner) std::memcpy(owner, bs.owner.data(), bs.owner.size() * sizeof(int32_t));
+    return FSGMG_OK;
+  });
+}
+
+fsgmg_status block_colours(fsgmg_h h, int level, int64_t* ncolours, int64_t* colour_ptr) {
+  if (!h || !ncolours) return FSGMG_EINVAL;
+  return guarded(h, [&]() -> fsgmg_status {
+    if (!h->have_blocks) throw Fail{FSGMG_ESTATE, "blocks not built"};
+    if (level < 1 || level >= h->L) throw Fail{FSGMG_EINVAL, "blocks exist on levels >= 1"};
+    const BlockSet& bs = h->blocks[level];
+    const bool mult = h->sopt.schwarz == FSGMG_SCHWARZ_MULTIPLICATIVE;
+    *ncolours = mult ? (int64_t)bs.colour_ptr.size() - 1 : 0;
+    if (mult && colour_ptr)
+      std::memcpy(colour_ptr, bs.colour_ptr.data(), bs.colour_ptr.size() * sizeof(int64_t));
     return FSGMG_OK;
   });
 }

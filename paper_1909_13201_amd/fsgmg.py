@@ -21,11 +21,12 @@ FSGMG_OK, FSGMG_NOT_CONVERGED = 0, 1
 STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "EHIP", -3: "ESINGULAR",
           -4: "ENOMEM", -5: "ESTATE"}
 CYCLE = {"V": 0, "W": 1, "F": 2}
+SCHWARZ = {"additive": 0, "multiplicative": 1}
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
 
 EXPORTED = ["setup_hierarchy", "build_fs_as_blocks", "vcycle_apply", "gmres_solve",
             "adjoint_solve", "assemble_load", "load_adjoint", "apply_operator", "param_grad",
-            "update_params", "level_info", "export_csr", "export_vector", "export_blocks",
+            "update_params", "level_info", "export_csr", "export_vector", "export_blocks", "block_colours",
             "kernel_timing", "tuning_info", "last_error", "hierarchy_destroy"]
 
 
@@ -47,7 +48,7 @@ class SmootherOpts(C.Structure):
     _fields_ = [("core", C.c_int * 3), ("halo", C.c_int), ("nu_pre", C.c_int),
                 ("nu_post", C.c_int), ("omega", C.c_double), ("prec", C.c_int),
                 ("use_graph", C.c_int), ("iface_mult", C.c_int), ("monolithic", C.c_int),
-                ("cycle", C.c_int)]
+                ("cycle", C.c_int), ("schwarz", C.c_int)]
 
 
 class KrylovOpts(C.Structure):
@@ -90,6 +91,7 @@ def lib():
             "export_csr": ([H, C.c_int, C.c_int, C.POINTER(C.c_int64), P, P, P], C.c_int),
             "export_vector": ([H, C.c_int, C.c_int, P], C.c_int),
             "export_blocks": ([H, C.c_int, C.POINTER(C.c_int64), P, P, P], C.c_int),
+            "block_colours": ([H, C.c_int, C.POINTER(C.c_int64), P], C.c_int),
             "kernel_timing": ([H, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double)],
                               C.c_int),
             "tuning_info": ([H, C.c_int, C.POINTER(C.c_int32)], C.c_int),
@@ -184,7 +186,8 @@ def setup_hierarchy(cfg, w=None, device=0, stream=None):
 
 
 def build_fs_as_blocks(h, core=(4, 4), halo=1, nu_pre=2, nu_post=2, omega=0.8, prec="fp64",
-                       use_graph=True, iface_mult=1, monolithic=False, cycle="V"):
+                       use_graph=True, iface_mult=1, monolithic=False, cycle="V",
+                       schwarz="additive"):
     o = SmootherOpts()
     for a in range(3):
         o.core[a] = int(core[a]) if a < len(core) else 1
@@ -195,6 +198,7 @@ def build_fs_as_blocks(h, core=(4, 4), halo=1, nu_pre=2, nu_post=2, omega=0.8, p
     o.iface_mult = int(iface_mult)
     o.monolithic = int(bool(monolithic))
     o.cycle = CYCLE[cycle] if isinstance(cycle, str) else int(cycle)
+    o.schwarz = SCHWARZ[schwarz] if isinstance(schwarz, str) else int(schwarz)
     _check(h, lib().build_fs_as_blocks(h, C.byref(o)))
 
 
@@ -287,6 +291,17 @@ def export_blocks(h, level):
     return ptr, dofs[:tot], owner
 
 
+def block_colours(h, level):
+    """First block of each colour of the multiplicative sweep (export_blocks
+    order, last entry = number of blocks); empty for the additive smoother."""
+    n = C.c_int64(0)
+    _check(h, lib().block_colours(h, int(level), C.byref(n), None))
+    ptr = np.zeros(n.value + 1, np.int64)
+    if n.value:
+        _check(h, lib().block_colours(h, int(level), C.byref(n), ptr.ctypes.data_as(C.c_void_p)))
+    return ptr if n.value else np.zeros(0, np.int64)
+
+
 def kernel_timing(h, enable):
     """Start (enable=True) or stop event timing; on stop returns
     {kind: (launches, total_ms)} for kinds smoother / vspmv / outer_spmv / transfer."""
@@ -343,7 +358,8 @@ class Hierarchy:
                     nu_pre=self.cfg.get("nu_pre", 2), nu_post=self.cfg.get("nu_post", 2),
                     omega=self.cfg.get("omega", 0.8), iface_mult=self.cfg.get("iface_mult", 1),
                     monolithic=self.cfg.get("monolithic", False),
-                    cycle=self.cfg.get("cycle", "V"))
+                    cycle=self.cfg.get("cycle", "V"),
+                    schwarz=self.cfg.get("schwarz", "additive"))
         opts.update(kw)
         build_fs_as_blocks(self.h, **opts)
 

@@ -148,6 +148,56 @@ def test_monolithic_comparator_parity(key):
     H.close()
 
 
+@pytest.mark.parametrize("key", ["c1", "c2L3", "c2L3mono", "chan3d"])
+def test_multiplicative_schwarz_parity(key):
+    """Multicolour multiplicative Schwarz smoother: FP64 V-cycle and its
+    transpose against the oracle's sequential sweep in the same colour order,
+    the colour ranges equal to the oracle's, and an FP32 solve to a true
+    1e-10 in no more iterations than the additive smoother needs."""
+    import tests.cfgs as cfgs
+    from oracle.schwarz import block_colouring, build_blocks, colour_major
+    mono = key.endswith("mono")
+    if key == "c1":
+        cfg = inputs.config("c1")
+    elif key == "chan3d":
+        cfg = cfgs.channel3d(levels=2, nc=(2, 2, 2))
+    else:
+        cfg = inputs.with_levels(inputs.config("c2"), 3)
+    cfg = dict(cfg, schwarz="multiplicative", monolithic=mono)
+    w = None if key == "chan3d" else inputs.advecting_field(cfg)
+    O = OracleHierarchy(cfg, w)
+    H = fsgmg.Hierarchy(cfg, w, device=0)
+    H.build_fs_as_blocks(prec="fp64")
+    for l in range(1, H.L):
+        blocks, _ = build_blocks(O.levels[l], cfg["core"], cfg["halo"],
+                                 cfg.get("iface_mult", 1), mono)
+        _, oc = colour_major(blocks, block_colouring(O.coupling_pattern(l), blocks))
+        oc = np.array(oc)
+        assert np.array_equal(fsgmg.block_colours(H.h, l),
+                              np.searchsorted(oc, np.arange(oc.max() + 2)))
+    rng = np.random.default_rng(13)
+    r = rng.standard_normal(H.N)
+    z = torch.zeros(H.N, dtype=torch.float64, device="cuda")
+    for tr in (False, True):
+        H.vcycle_apply(dev(r), z, transpose=tr)
+        ref = O.vcycle(r, transpose=tr)
+        err = np.linalg.norm(host(z) - ref) / np.linalg.norm(ref)
+        say("[multiplicative]", key, "transpose", tr, "rel err %.3e" % err)
+        assert err <= 1e-9
+    b = O.rhs(inputs.body_force(cfg))
+    its = {}
+    for kind in ("multiplicative", "additive"):
+        H.build_fs_as_blocks(prec="fp32", schwarz=kind)
+        x = torch.zeros(H.N, dtype=torch.float64, device="cuda")
+        info = H.gmres_solve(dev(b), x, rtol=1e-10)
+        true = np.linalg.norm(b - O.A[-1] @ host(x)) / np.linalg.norm(b)
+        say("   %s fp32 solve iters %d true %.2e" % (kind, info["iters"], true))
+        assert info["converged"] and true <= 1e-10
+        its[kind] = info["iters"]
+    assert its["multiplicative"] <= its["additive"]
+    H.close()
+
+
 @pytest.mark.parametrize("kind", ["W", "F"])
 def test_w_and_f_cycles_parity(kind):
     """W- and F-cycles (c2 at 3 levels): FP64 cycle and its transpose against

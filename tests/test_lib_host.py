@@ -136,6 +136,35 @@ def test_monolithic_blocks_match_oracle(name, L, mult):
     H.close()
 
 
+@pytest.mark.parametrize("name,L,mult,mono", [("c1", 2, 1, False), ("c2", 3, 1, False),
+                                           ("c3", 2, 3, False), ("c2", 3, 1, True)])
+def test_multiplicative_colours_match_oracle(name, L, mult, mono):
+    """Greedy colouring and colour-major block order of the multiplicative
+    sweep: the library's equal the oracle's (blocks, order, colour ranges)."""
+    from oracle.schwarz import block_colouring, colour_major
+    cfg = inputs.with_levels(inputs.config(name), L)
+    w = inputs.advecting_field(cfg)
+    H = fsgmg.Hierarchy(cfg, w, device=-1)
+    O = OracleHierarchy(cfg, w, build_smoothers=False)
+    fsgmg.build_fs_as_blocks(H.h, core=cfg["core"], halo=cfg["halo"], iface_mult=mult,
+                             monolithic=mono, schwarz="multiplicative")
+    for l in range(1, H.L):
+        ptr, dofs, owner = fsgmg.export_blocks(H.h, l)
+        cptr = fsgmg.block_colours(H.h, l)
+        blocks, _ = build_blocks(O.levels[l], cfg["core"], cfg["halo"], mult, mono)
+        ob, oc = colour_major(blocks, block_colouring(O.coupling_pattern(l), blocks))
+        assert len(ptr) - 1 == len(ob)
+        for j, I in enumerate(ob):
+            assert np.array_equal(dofs[ptr[j]:ptr[j + 1]], I), (l, j)
+        oc = np.array(oc)
+        assert np.array_equal(cptr, np.searchsorted(oc, np.arange(oc.max() + 2))), l
+        assert np.array_equal(owner, owners(O.levels[l].N, ob))
+    fsgmg.build_fs_as_blocks(H.h, core=cfg["core"], halo=cfg["halo"], iface_mult=mult,
+                             monolithic=mono)
+    assert fsgmg.block_colours(H.h, 1).size == 0
+    H.close()
+
+
 def test_enlarged_interface_needs_layered_regions():
     import tests.cfgs as cfgs
     cfg = cfgs.small(nc=(4, 4), solid_rows=(), levels=2)
