@@ -131,7 +131,12 @@ typedef struct {
  * FSGMG_EINVAL); the damping omega scales the whole sweep's correction.  The
  * blocks are then stored colour by colour (export_blocks shows that order),
  * with full inverses (every row of a block is written).  The transposed
- * sweep runs the reverse order with transposed block solves. */
+ * sweep runs the reverse order with transposed block solves.
+ * sweep_form: 0 = chosen per level by the autotuner (see tuning_info),
+ * 1 = a residual SpMV before each forward sweep, 2 = forward sweeps that
+ * form their blocks' residual rows inside the smoother launch (additive:
+ * alternating between two iterate buffers; multiplicative: in place, colour
+ * by colour).  Transposed sweeps always take the residual SpMV. */
 typedef struct {
   int core[3];
   int halo;
@@ -143,6 +148,7 @@ typedef struct {
   int monolithic;
   int cycle;
   int schwarz;
+  int sweep_form;
 } fsgmg_smoother_opts;
 
 /* FGMRES(restart), right preconditioned, x0 = 0, CGS2; converged when the
@@ -255,8 +261,11 @@ fsgmg_status kernel_timing(fsgmg_h h, int enable, int64_t counts[4], double tota
  * width with non-temporal loads of the block inverses; 0 on level 0),
  * out[2] = lanes per row of the outer FP64 product, out[3] / out[4] = lanes
  * per output of the restriction from / prolongation to this level (0 on
+ * level 0), out[5] = 1 when the level's forward sweeps form their residual
+ * inside the smoother launch from per-block copies of the operator rows
+ * (one launch per sweep) instead of a residual SpMV before each sweep (0 on
  * level 0).  ESTATE before the first device block build. */
-fsgmg_status tuning_info(fsgmg_h h, int level, int32_t out[5]);
+fsgmg_status tuning_info(fsgmg_h h, int level, int32_t out[6]);
 
 const char* last_error(fsgmg_h h);
 void hierarchy_destroy(fsgmg_h h);

@@ -388,40 +388,16 @@ struct WTraits<__hip_bfloat16> {
   }
 };
 
-// Forward sweep: x[own] = (first ? 0 : x[own]) + omega * (W_j r[I_j])[own].
-constexpr int kSmoothMaxThreads = 1024;
-
-template <typename TV, typename TW, bool NT>
-__global__ __launch_bounds__(kSmoothMaxThreads) void k_smooth_fwd(BlocksView B, const TW* __restrict__ W,
-                                                         const TV* __restrict__ r,
-                                                         TV* __restrict__ x, TV omega, int first) {
-  using TA = TV;
+// Owned rows of W_j r for one block: W_j is stored column-major over its
+// mp (padded) owned rows; the workgroup's lanes form G = mp / RV groups of RV
+// rows times S column slices; slice s of group g leaves its partial sums in
+// red[s * mp + g * RV + i].  Returns S (the caller sums the slices).
+template <typename TA, typename TW, bool NT>
+__device__ inline int owned_gemv(const TW* __restrict__ Wj, int n, int mp, const TA* rl, TA* red) {
   constexpr int RV = WTraits<TW>::RV;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  TA* smem = reinterpret_cast<TA*>(smem_raw);
   const int tid = threadIdx.x;
-  if (blockIdx.x >= B.nblk) {
-    const int64_t q = (blockIdx.x - B.nblk) * blockDim.x + tid;
-    if (q < B.njac) {
-      const int32_t gi = B.jac[q];
-      const TV jv = reinterpret_cast<const TV*>(B.jac_inv)[q];
-      x[gi] = (first ? TV(0) : x[gi]) + omega * r[gi] * jv;
-    }
-    return;
-  }
-  const int64_t j = B.order[blockIdx.x];
-  const int64_t d0 = B.dof_ptr[j];
-  const int n = (int)(B.dof_ptr[j + 1] - d0);
-  const int o0 = B.own_ptr[j];
-  const int m = B.own_ptr[j + 1] - o0;
-  const int mp = B.mpad[j];
-  TA* rl = smem;
-  TA* red = smem + ((n + 3) & ~3);
-  for (int k = tid; k < n; k += blockDim.x) rl[k] = (TA)r[B.dofs[d0 + k]];
-  __syncthreads();
   const int G = mp / RV;
   const int S = G >= (int)blockDim.x ? 1 : (int)blockDim.x / G;
-  const TW* Wj = W + B.w_off[j];
   for (int gg = tid; gg < G * S; gg += blockDim.x) {
     const int g = gg % G, s = gg / G;
     TA acc[RV];
@@ -455,6 +431,40 @@ __global__ __launch_bounds__(kSmoothMaxThreads) void k_smooth_fwd(BlocksView B, 
 #pragma unroll
     for (int i = 0; i < RV; ++i) red[s * mp + g * RV + i] = acc[i];
   }
+  return S;
+}
+
+// Forward sweep: x[own] = (first ? 0 : x[own]) + omega * (W_j r[I_j])[own].
+constexpr int kSmoothMaxThreads = 1024;
+
+template <typename TV, typename TW, bool NT>
+__global__ __launch_bounds__(kSmoothMaxThreads) void k_smooth_fwd(BlocksView B, const TW* __restrict__ W,
+                                                         const TV* __restrict__ r,
+                                                         TV* __restrict__ x, TV omega, int first) {
+  using TA = TV;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  TA* smem = reinterpret_cast<TA*>(smem_raw);
+  const int tid = threadIdx.x;
+  if (blockIdx.x >= B.nblk) {
+    const int64_t q = (blockIdx.x - B.nblk) * blockDim.x + tid;
+    if (q < B.njac) {
+      const int32_t gi = B.jac[q];
+      const TV jv = reinterpret_cast<const TV*>(B.jac_inv)[q];
+      x[gi] = (first ? TV(0) : x[gi]) + omega * r[gi] * jv;
+    }
+    return;
+  }
+  const int64_t j = B.order[blockIdx.x];
+  const int64_t d0 = B.dof_ptr[j];
+  const int n = (int)(B.dof_ptr[j + 1] - d0);
+  const int o0 = B.own_ptr[j];
+  const int m = B.own_ptr[j + 1] - o0;
+  const int mp = B.mpad[j];
+  TA* rl = smem;
+  TA* red = smem + ((n + 3) & ~3);
+  for (int k = tid; k < n; k += blockDim.x) rl[k] = (TA)r[B.dofs[d0 + k]];
+  __syncthreads();
+  const int S = owned_gemv<TA, TW, NT>(W + B.w_off[j], n, mp, rl, red);
   __syncthreads();
   for (int i = tid; i < m; i += blockDim.x) {
     TA v = TA(0);
@@ -462,6 +472,152 @@ __global__ __launch_bounds__(kSmoothMaxThreads) void k_smooth_fwd(BlocksView B, 
     const int32_t gi = B.own_dof[o0 + i];
     x[gi] = (first ? TV(0) : x[gi]) + omega * (TV)v;
   }
+}
+
+// Fused sweep: the block's residual rows b - A xin are formed here from the
+// block's copy of its operator rows, then xout[own] = (first ? 0 : xin[own])
+// + omega (W_j r)[own]; the workgroups past the blocks do the Jacobi rows.
+// xin and xout may be the same buffer (multiplicative colour step: the blocks
+// of one launch neither read nor write each other's unknowns; each workgroup
+// reads its own rows' unknowns before the barrier and writes after it).
+template <typename TV, typename TW, bool NT>
+__global__ __launch_bounds__(kSmoothMaxThreads) void k_smooth_fused(BlocksView B, const TW* __restrict__ W,
+                                                           const TV* __restrict__ b,
+                                                           const TV* xin, TV* xout, TV omega,
+                                                           int first) {
+  using TA = TV;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  TA* smem = reinterpret_cast<TA*>(smem_raw);
+  const int tid = threadIdx.x;
+  if (blockIdx.x >= B.nblk) {
+    const int64_t q = (blockIdx.x - B.nblk) * blockDim.x + tid;
+    if (q < B.njac) {
+      const int32_t gi = B.jac[q];
+      TA r = (TA)b[gi];
+      if (!first) {
+        const TV* jv = reinterpret_cast<const TV*>(B.jrow_val);
+        for (int k = 0; k < B.jrow_w; ++k)
+          r -= (TA)jv[(int64_t)k * B.njac + q] * (TA)xin[B.jrow_col[(int64_t)k * B.njac + q]];
+      }
+      const TV jinv = reinterpret_cast<const TV*>(B.jac_inv)[q];
+      xout[gi] = (first ? TV(0) : xin[gi]) + omega * (TV)r * jinv;
+    }
+    return;
+  }
+  const int64_t j = B.order[blockIdx.x];
+  const int64_t d0 = B.dof_ptr[j];
+  const int n = (int)(B.dof_ptr[j + 1] - d0);
+  const int o0 = B.own_ptr[j];
+  const int m = B.own_ptr[j + 1] - o0;
+  const int mp = B.mpad[j];
+  TA* rl = smem;
+  TA* red = smem + ((n + 3) & ~3);
+  if (first) {
+    for (int k = tid; k < n; k += blockDim.x) rl[k] = (TA)b[B.dofs[d0 + k]];
+  } else {
+    // P consecutive lanes per row (P a power of two up to 8 while the
+    // workgroup is wider than the block), four entries in flight per lane,
+    // partial sums combined by a fixed butterfly
+    const int w = B.rows_w[j];
+    const TV* __restrict__ rv = reinterpret_cast<const TV*>(B.rows_val) + B.rows_off[j];
+    const int32_t* __restrict__ rc = B.rows_col + B.rows_off[j];
+    int P = 1;
+    while (P < 8 && 2 * P * n <= (int)blockDim.x) P *= 2;
+    const int R = (int)blockDim.x / P;
+    const int p = tid % P;
+    for (int base = 0; base < n; base += R) {
+      const int k = base + tid / P;
+      TA acc = TA(0);
+      if (k < n) {
+        int e = p;
+        for (; e + 3 * P < w; e += 4 * P) {
+          const int64_t q0 = (int64_t)e * n + k, q1 = q0 + (int64_t)P * n,
+                        q2 = q1 + (int64_t)P * n, q3 = q2 + (int64_t)P * n;
+          const int32_t c0 = rc[q0], c1 = rc[q1], c2 = rc[q2], c3 = rc[q3];
+          const TA a0 = (TA)rv[q0], a1 = (TA)rv[q1], a2 = (TA)rv[q2], a3 = (TA)rv[q3];
+          const TA y0 = (TA)xin[c0], y1 = (TA)xin[c1], y2 = (TA)xin[c2], y3 = (TA)xin[c3];
+          acc += a0 * y0;
+          acc += a1 * y1;
+          acc += a2 * y2;
+          acc += a3 * y3;
+        }
+        for (; e < w; e += P) acc += (TA)rv[(int64_t)e * n + k] * (TA)xin[rc[(int64_t)e * n + k]];
+      }
+      for (int o = P / 2; o > 0; o /= 2) acc += __shfl_xor(acc, o);
+      if (k < n && p == 0) rl[k] = (TA)b[B.dofs[d0 + k]] - acc;
+    }
+  }
+  __syncthreads();
+  const int S = owned_gemv<TA, TW, NT>(W + B.w_off[j], n, mp, rl, red);
+  __syncthreads();
+  for (int i = tid; i < m; i += blockDim.x) {
+    TA v = TA(0);
+    for (int s = 0; s < S; ++s) v += red[s * mp + i];
+    const int32_t gi = B.own_dof[o0 + i];
+    xout[gi] = (first ? TV(0) : xin[gi]) + omega * (TV)v;
+  }
+}
+
+// Operator rows of every block (workgroup j < nblk) and of the Jacobi rows
+// (the workgroups after them) gathered from the FP64 CSR in ELL layout.
+template <typename TV>
+__global__ __launch_bounds__(kThreads) void k_block_rows(BlocksView B, const int64_t* __restrict__ rp,
+                                                         const int32_t* __restrict__ col,
+                                                         const double* __restrict__ val,
+                                                         int32_t* __restrict__ ocol,
+                                                         TV* __restrict__ oval,
+                                                         int32_t* __restrict__ jcol,
+                                                         TV* __restrict__ jval) {
+  const int64_t j = blockIdx.x;
+  if (j < B.nblk) {
+    const int64_t d0 = B.dof_ptr[j];
+    const int64_t n = B.dof_ptr[j + 1] - d0;
+    const int64_t tot = n * B.rows_w[j];
+    const int64_t base = B.rows_off[j];
+    for (int64_t t = threadIdx.x; t < tot; t += blockDim.x) {
+      const int64_t k = t / n, i = t - k * n;
+      const int32_t g = B.dofs[d0 + i];
+      const int64_t p = rp[g] + k;
+      const bool in = p < rp[g + 1];
+      ocol[base + t] = in ? col[p] : g;
+      oval[base + t] = in ? (TV)val[p] : TV(0);
+    }
+    return;
+  }
+  const int64_t t = (j - B.nblk) * blockDim.x + threadIdx.x;
+  if (t < B.njac * (int64_t)B.jrow_w) {
+    const int64_t k = t / B.njac, q = t - k * B.njac;
+    const int32_t g = B.jac[q];
+    const int64_t p = rp[g] + k;
+    const bool in = p < rp[g + 1];
+    jcol[t] = in ? col[p] : g;
+    jval[t] = in ? (TV)val[p] : TV(0);
+  }
+}
+
+// Multiplicative sweep end, part 1: Jacobi rows on the latest iterate (they
+// are mutually uncoupled, so the row reads no entry another lane writes).
+template <typename TV>
+__global__ __launch_bounds__(kThreads) void k_mult_jac(BlocksView B, const TV* __restrict__ b,
+                                                       TV* y) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= B.njac) return;
+  const int32_t gi = B.jac[q];
+  const TV* jv = reinterpret_cast<const TV*>(B.jrow_val);
+  TV r = b[gi];
+  for (int k = 0; k < B.jrow_w; ++k)
+    r -= jv[(int64_t)k * B.njac + q] * y[B.jrow_col[(int64_t)k * B.njac + q]];
+  y[gi] += r * reinterpret_cast<const TV*>(B.jac_inv)[q];
+}
+
+// part 2: x = (first ? 0 : x) + omega (y - (first ? 0 : x))
+template <typename TV>
+__global__ __launch_bounds__(kThreads) void k_mult_combine(int64_t n, TV omega, const TV* __restrict__ y,
+                                                           TV* __restrict__ x, int first) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const TV x0 = first ? TV(0) : x[i];
+  x[i] = x0 + omega * (y[i] - x0);
 }
 
 // Transposed sweep, part 1: t_j = W_j^T r[own_j] into the per-block buffer.
@@ -1443,6 +1599,76 @@ template void launch_smooth<double>(const BlocksView&, WPrec, const void*, const
                                     double*, double, bool, bool, int64_t, hipStream_t, int);
 template void launch_smooth<float>(const BlocksView&, WPrec, const void*, const float*, float*,
                                    float*, double, bool, bool, int64_t, hipStream_t, int);
+
+template <typename TV, typename TW>
+static void fused_impl(const BlocksView& B, const TW* W, const TV* b, const TV* xin, TV* xout,
+                       double omega, bool first, hipStream_t s, int threads) {
+  const bool nt = threads < 0;
+  const int tabs = threads < 0 ? -threads : threads;
+  const int T = tabs > 0 ? tabs : (B.nblk < 1024 ? kSmoothMaxThreads : kThreads);
+  const int64_t nj = (B.njac + T - 1) / T;
+  const unsigned g = (unsigned)(B.nblk + nj);
+  if (!g) return;
+  const int RV = WTraits<TW>::RV;
+  const size_t sm = sizeof(TV) * (size_t)(((B.max_n + 3) & ~3) + T * RV + B.max_mpad);
+  if (nt)
+    hipLaunchKernelGGL((k_smooth_fused<TV, TW, true>), dim3(g), dim3(T), sm, s, B, W, b, xin, xout,
+                       (TV)omega, (int)first);
+  else
+    hipLaunchKernelGGL((k_smooth_fused<TV, TW, false>), dim3(g), dim3(T), sm, s, B, W, b, xin,
+                       xout, (TV)omega, (int)first);
+}
+
+template <typename TV>
+void launch_smooth_fused(const BlocksView& B, WPrec wp, const void* W, const TV* b, const TV* xin,
+                         TV* xout, double omega, bool first, hipStream_t s, int threads) {
+  switch (wp) {
+    case WPrec::F64:
+      fused_impl<TV, double>(B, (const double*)W, b, xin, xout, omega, first, s, threads);
+      break;
+    case WPrec::F32:
+      fused_impl<TV, float>(B, (const float*)W, b, xin, xout, omega, first, s, threads);
+      break;
+    case WPrec::BF16:
+      fused_impl<TV, __hip_bfloat16>(B, (const __hip_bfloat16*)W, b, xin, xout, omega, first, s,
+                                     threads);
+      break;
+  }
+}
+template void launch_smooth_fused<double>(const BlocksView&, WPrec, const void*, const double*,
+                                          const double*, double*, double, bool, hipStream_t, int);
+template void launch_smooth_fused<float>(const BlocksView&, WPrec, const void*, const float*,
+                                         const float*, float*, double, bool, hipStream_t, int);
+
+template <typename TV>
+void launch_block_rows(const BlocksView& B, const int64_t* rowptr, const int32_t* col,
+                       const double* val, hipStream_t s) {
+  const int64_t nj = (B.njac * (int64_t)B.jrow_w + kThreads - 1) / kThreads;
+  const unsigned g = (unsigned)(B.nblk + nj);
+  if (g)
+    hipLaunchKernelGGL((k_block_rows<TV>), dim3(g), dim3(kThreads), 0, s, B, rowptr, col, val,
+                       const_cast<int32_t*>(B.rows_col), (TV*)const_cast<void*>(B.rows_val),
+                       const_cast<int32_t*>(B.jrow_col), (TV*)const_cast<void*>(B.jrow_val));
+}
+template void launch_block_rows<double>(const BlocksView&, const int64_t*, const int32_t*,
+                                        const double*, hipStream_t);
+template void launch_block_rows<float>(const BlocksView&, const int64_t*, const int32_t*,
+                                       const double*, hipStream_t);
+
+template <typename TV>
+void launch_mult_finish(const BlocksView& B, const TV* b, TV* y, TV* x, int64_t N, double omega,
+                        bool first, hipStream_t s) {
+  if (B.njac > 0)
+    hipLaunchKernelGGL((k_mult_jac<TV>), dim3(grid_for(B.njac, kThreads)), dim3(kThreads), 0, s, B,
+                       b, y);
+  if (y != x && N > 0)
+    hipLaunchKernelGGL((k_mult_combine<TV>), dim3(grid_for(N, kThreads)), dim3(kThreads), 0, s, N,
+                       (TV)omega, y, x, (int)first);
+}
+template void launch_mult_finish<double>(const BlocksView&, const double*, double*, double*,
+                                         int64_t, double, bool, hipStream_t);
+template void launch_mult_finish<float>(const BlocksView&, const float*, float*, float*, int64_t,
+                                        double, bool, hipStream_t);
 
 // Multiplicative sweep, transposed colour step: e[I_j] += (W_j^T r[I_j]) for
 // the blocks of one colour; they are disjoint, so the scatter has no races.

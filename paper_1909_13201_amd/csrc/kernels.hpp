@@ -100,6 +100,18 @@ struct BlocksView {
   // blocks are sorted by decreasing inverse size so that the largest start
   // first (longest-processing-time-first over the CUs)
   const int32_t* order;
+  // rows of the level operator for the fused residual: block j's rows
+  // A[I_j, :] as ELL of width rows_w[j], column-major (entry k of local row i
+  // at rows_off[j] + k * n_j + i), padding entries point at the row's own
+  // unknown with value 0; the Jacobi unknowns' rows likewise (entry k of
+  // Jacobi row q at k * njac + q); values in the vector precision
+  const int64_t* rows_off;
+  const int32_t* rows_w;
+  const int32_t* rows_col;
+  const void* rows_val;
+  int jrow_w;
+  const int32_t* jrow_col;
+  const void* jrow_val;
 };
 
 enum class WPrec { F64 = 0, F32 = 1, BF16 = 2 };
@@ -128,6 +140,26 @@ template <typename TV>
 void launch_smooth(const BlocksView& B, WPrec wp, const void* W, const TV* r, TV* x, TV* tbuf,
                    double omega, bool first, bool transpose, int64_t N, hipStream_t s,
                    int threads = 0);
+
+// ---- fused sweep: the residual b - A xin of every block's rows (and of the
+// Jacobi rows) is formed inside the launch from B.rows_* (first: xin = 0,
+// residual = b), then xout[own] = (first ? 0 : xin[own]) + omega (W_j r)[own],
+// xout[jac] likewise.  Additive sweep: xout != xin, every entry of xout is
+// written.  Multiplicative colour step (B views one colour, all rows owned,
+// no Jacobi rows): xin == xout, omega 1, first 0 (the blocks of a colour
+// neither read nor write each other's unknowns) ----
+template <typename TV>
+void launch_smooth_fused(const BlocksView& B, WPrec wp, const void* W, const TV* b, const TV* xin,
+                         TV* xout, double omega, bool first, hipStream_t s, int threads = 0);
+// gather B.rows_* / B.jrow_* from the level's FP64 CSR (values cast to TV)
+template <typename TV>
+void launch_block_rows(const BlocksView& B, const int64_t* rowptr, const int32_t* col,
+                       const double* val, hipStream_t s);
+// multiplicative sweep end: y[jac] += (b - A y)[jac] / A_jj, then
+// x = (first ? 0 : x) + omega (y - (first ? 0 : x))
+template <typename TV>
+void launch_mult_finish(const BlocksView& B, const TV* b, TV* y, TV* x, int64_t N, double omega,
+                        bool first, hipStream_t s);
 
 // ---- multiplicative sweep, one colour: B views the colour's blocks (all
 // rows owned, mutually uncoupled) and no Jacobi unknowns, or no blocks and

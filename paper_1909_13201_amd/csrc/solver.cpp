@@ -264,6 +264,9 @@ struct DLevel {
   // multiplicative sweep: correction e and the residual of the latest iterate
   double *e64 = nullptr, *rc64 = nullptr;
   float *e32 = nullptr, *rc32 = nullptr;
+  // fused additive sweeps alternate between x and x2
+  double* x2_64 = nullptr;
+  float* x2_32 = nullptr;
 };
 
 }  // namespace
@@ -319,6 +322,7 @@ struct fsgmg_hierarchy {
     int smooth_threads = 0;
     int restrict_lanes = 8;   // transfers into this level's coarse neighbour
     int prolong_lanes = 2;    // transfers from it
+    int fused = 0;            // smoother sweeps form their residual in-launch
   };
   std::vector<Tune> tune;
   int outer_lanes = 1;
@@ -705,12 +709,14 @@ void upload_blocks(fsgmg_hierarchy& h, int l) {
                           (const void*)o.tpos_ptr, (const void*)o.tpos, (const void*)o.order,
                           (const void*)d.W, (const void*)d.tb64, (const void*)d.tb32,
                           (const void*)d.e64, (const void*)d.rc64, (const void*)d.e32,
-                          (const void*)d.rc32})
+                          (const void*)d.rc32, (const void*)o.rows_off, (const void*)o.rows_w,
+                          (const void*)o.rows_col, o.rows_val, (const void*)o.jrow_col,
+                          o.jrow_val, (const void*)d.x2_64, (const void*)d.x2_32})
       h.dfree(const_cast<void*>(q));
     o = BlocksView{};
     d.W = nullptr;
-    d.tb64 = d.e64 = d.rc64 = nullptr;
-    d.tb32 = d.e32 = d.rc32 = nullptr;
+    d.tb64 = d.e64 = d.rc64 = d.x2_64 = nullptr;
+    d.tb32 = d.e32 = d.rc32 = d.x2_32 = nullptr;
   }
   const int RV = rows_per_vector(h.sopt.prec);
   const int64_t nb = bs.nblk();
@@ -798,6 +804,35 @@ void upload_blocks(fsgmg_hierarchy& h, int l) {
       d.e32 = h.zeros<float>(lv.N);
       d.rc32 = h.zeros<float>(lv.N);
     }
+  }
+  // operator rows of the blocks and of the Jacobi unknowns (fused sweeps);
+  // the values are gathered on the device with every factorization
+  {
+    std::vector<int64_t> roff(nb + 1, 0);
+    std::vector<int32_t> rw(nb, 0);
+    for (int64_t j = 0; j < nb; ++j) {
+      int w = 0;
+      for (int64_t p = bs.ptr[j]; p < bs.ptr[j + 1]; ++p) {
+        const int32_t g = bs.dofs[p];
+        w = std::max(w, (int)(A.rowptr[g + 1] - A.rowptr[g]));
+      }
+      rw[j] = w;
+      roff[j + 1] = roff[j] + (bs.ptr[j + 1] - bs.ptr[j]) * w;
+    }
+    int jw = 0;
+    for (int32_t g : bs.jac) jw = std::max(jw, (int)(A.rowptr[g + 1] - A.rowptr[g]));
+    const size_t vb = h.sopt.prec == FSGMG_FP64 ? 8 : 4;
+    v.rows_off = h.upload(roff);
+    v.rows_w = h.upload(rw);
+    v.rows_col = (const int32_t*)h.dalloc((size_t)roff[nb] * sizeof(int32_t));
+    v.rows_val = h.dalloc((size_t)roff[nb] * vb);
+    v.jrow_w = jw;
+    v.jrow_col = (const int32_t*)h.dalloc((size_t)bs.jac.size() * jw * sizeof(int32_t));
+    v.jrow_val = h.dalloc((size_t)bs.jac.size() * jw * vb);
+    if (h.sopt.prec == FSGMG_FP64)
+      d.x2_64 = h.zeros<double>(lv.N);
+    else
+      d.x2_32 = h.zeros<float>(lv.N);
   }
 }
 
@@ -892,6 +927,10 @@ void factor_blocks(fsgmg_hierarchy& h) {
     if (nb == 0) continue;
     HIPCHECK(hipStreamWaitEvent(fp.stream, h.factor_start, 0));
     HIPCHECK(hipMemsetAsync(fp.status, 0, (size_t)nb * sizeof(int32_t), fp.stream));
+    if (h.sopt.prec == FSGMG_FP64)
+      launch_block_rows<double>(d.bv, d.rp, d.col, d.val, fp.stream);
+    else
+      launch_block_rows<float>(d.bv, d.rp, d.col, d.val, fp.stream);
     for (const FactorPlan::Chunk& c : fp.chunks) {
       const int64_t cnt = c.b1 - c.b0;
       const int32_t* jl = fp.jlist + c.b0;
@@ -958,6 +997,7 @@ struct Vec<double> {
   static double* t(DLevel& d) { return d.tb64; }
   static double* e(DLevel& d) { return d.e64; }
   static double* rc(DLevel& d) { return d.rc64; }
+  static double* x2(DLevel& d) { return d.x2_64; }
   static const BOpView<double>& op(DLevel& d, bool tr) { return tr ? d.AT.v64 : d.A.v64; }
   static const TransferView<double>& tv(DLevel& d) { return d.t64; }
 };
@@ -969,6 +1009,7 @@ struct Vec<float> {
   static float* t(DLevel& d) { return d.tb32; }
   static float* e(DLevel& d) { return d.e32; }
   static float* rc(DLevel& d) { return d.rc32; }
+  static float* x2(DLevel& d) { return d.x2_32; }
   static const BOpView<float>& op(DLevel& d, bool tr) { return tr ? d.AT.v32 : d.A.v32; }
   static const TransferView<float>& tv(DLevel& d) { return d.t32; }
 };
@@ -993,6 +1034,28 @@ void smooth_level_mult(fsgmg_hierarchy& h, int l, int nsweeps, bool transpose, b
   const int64_t ncol = (int64_t)bs.colour_ptr.size() - 1;
   const BOpView<TV>& A = Vec<TV>::op(d, transpose);
   const int lanes = h.tune[l].spmv_lanes;
+  if (!transpose && h.tune[l].fused) {
+    // in-place colour steps on y (a copy of x, or 0), residuals formed in-launch
+    for (int s = 0; s < nsweeps; ++s) {
+      const bool first = s == 0 && from_zero;
+      if (first)
+        launch_fill<TV>(e, TV(0), d.N, h.stream);
+      else
+        launch_add_scaled<TV>(d.N, 1.0, x, e, true, h.stream);
+      for (int64_t c = 0; c < ncol; ++c) {
+        BlocksView v = d.bv;
+        v.order = d.bv.order + bs.colour_ptr[c];
+        v.nblk = bs.colour_ptr[c + 1] - bs.colour_ptr[c];
+        v.njac = 0;
+        TimedLaunch t(h, 0, fin);
+        // the first colour of a sweep from zero: y = 0, the residual is b
+        launch_smooth_fused<TV>(v, wp, d.W, b, e, e, 1.0, first && c == 0, h.stream,
+                                h.tune[l].smooth_threads);
+      }
+      launch_mult_finish<TV>(d.bv, b, e, x, d.N, h.sopt.omega, first, h.stream);
+    }
+    return;
+  }
   for (int s = 0; s < nsweeps; ++s) {
     const bool first = s == 0 && from_zero;
     const TV* rs = b;
@@ -1049,6 +1112,19 @@ void smooth_level(fsgmg_hierarchy& h, int l, int nsweeps, bool transpose, bool f
   TV* x = Vec<TV>::x(d);
   TV* r = Vec<TV>::r(d);
   const bool fin = l == h.L - 1;
+  if (!transpose && h.tune[l].fused) {
+    // every sweep reads one buffer and writes all of the other
+    TV* cur = x;
+    for (int s = 0; s < nsweeps; ++s) {
+      TV* out = cur == x ? Vec<TV>::x2(d) : x;
+      TimedLaunch t(h, 0, fin);
+      launch_smooth_fused<TV>(d.bv, wp, d.W, b, cur, out, h.sopt.omega, s == 0 && from_zero,
+                              h.stream, h.tune[l].smooth_threads);
+      cur = out;
+    }
+    if (cur != x) launch_add_scaled<TV>(d.N, 1.0, cur, x, true, h.stream);
+    return;
+  }
   for (int s = 0; s < nsweeps; ++s) {
     if (s == 0 && from_zero) {
       TimedLaunch t(h, 0, fin);
@@ -1415,6 +1491,34 @@ void autotune_impl(fsgmg_hierarchy& h) {
         h.tune[l].smooth_threads = th;
       }
     }
+    // a sweep after the first: residual SpMV + sweep, or one fused launch
+    // that forms the blocks' residual rows itself (fewer launches, but every
+    // block reads its own copy of its operator rows)
+    {
+      const float t_sep = time_launch(h, [&] {
+        launch_spmv<TV>(Vec<TV>::op(d, false), h.D, Vec<TV>::x(d), Vec<TV>::b(d), Vec<TV>::r(d),
+                        true, h.stream, h.tune[l].spmv_lanes);
+        launch_smooth<TV>(tv, wp, d.W, Vec<TV>::r(d), Vec<TV>::x(d), Vec<TV>::t(d), 1.0, false,
+                          false, d.N, h.stream, h.tune[l].smooth_threads);
+      });
+      float t_fused = 1e30f;
+      int th_fused = h.tune[l].smooth_threads;
+      for (int th : threads) {
+        const float t = time_launch(h, [&] {
+          launch_smooth_fused<TV>(tv, wp, d.W, Vec<TV>::b(d), Vec<TV>::x(d), Vec<TV>::x2(d), 1.0,
+                                  false, h.stream, th);
+        });
+        if (t < t_fused) {
+          t_fused = t;
+          th_fused = th;
+        }
+      }
+      const int form = h.sopt.sweep_form;
+      if (form == 2 || (form == 0 && t_fused < t_sep)) {
+        h.tune[l].fused = 1;
+        h.tune[l].smooth_threads = th_fused;
+      }
+    }
   }
   DLevel& F = h.dl[h.L - 1];
   float best = 1e30f;
@@ -1535,6 +1639,8 @@ fsgmg_status build_fs_as_blocks(fsgmg_h h, const fsgmg_smoother_opts* opts) {
     if (opts->iface_mult < 0) throw Fail{FSGMG_EINVAL, "iface_mult must be >= 0"};
     if (opts->schwarz != FSGMG_SCHWARZ_ADDITIVE && opts->schwarz != FSGMG_SCHWARZ_MULTIPLICATIVE)
       throw Fail{FSGMG_EINVAL, "schwarz must be FSGMG_SCHWARZ_ADDITIVE or _MULTIPLICATIVE"};
+    if (opts->sweep_form < 0 || opts->sweep_form > 2)
+      throw Fail{FSGMG_EINVAL, "sweep_form must be 0 (autotuned), 1 (SpMV) or 2 (fused)"};
     const int mult = std::max(1, opts->iface_mult);
     const bool same_sets = h->have_blocks && h->sopt.halo == opts->halo &&
                            h->sopt.core[0] == opts->core[0] && h->sopt.core[1] == opts->core[1] &&
@@ -1542,6 +1648,7 @@ fsgmg_status build_fs_as_blocks(fsgmg_h h, const fsgmg_smoother_opts* opts) {
                            std::max(1, h->sopt.iface_mult) == mult &&
                            (h->sopt.monolithic != 0) == (opts->monolithic != 0) &&
                            h->sopt.schwarz == opts->schwarz && h->sopt.prec == opts->prec;
+    const int prev_form = h->sopt.sweep_form;
     h->sopt = *opts;
     h->factors_valid = false;
     h->invalidate_graphs();
@@ -1568,7 +1675,7 @@ fsgmg_status build_fs_as_blocks(fsgmg_h h, const fsgmg_smoother_opts* opts) {
     factor_blocks(*h);
     // launch shapes depend on the block structure only: keep them while the
     // index sets and precision are unchanged, so rebuilds stay reproducible
-    if (!same_sets || !h->tuned) autotune(*h);
+    if (!same_sets || !h->tuned || prev_form != opts->sweep_form) autotune(*h);
     h->tuned = true;
     h->factors_valid = true;
     return FSGMG_OK;
@@ -1827,7 +1934,7 @@ fsgmg_status kernel_timing(fsgmg_h h, int enable, int64_t counts[4], double tota
   });
 }
 
-fsgmg_status tuning_info(fsgmg_h h, int level, int32_t out[5]) {
+fsgmg_status tuning_info(fsgmg_h h, int level, int32_t out[6]) {
   // out[1] < 0 means non-temporal loads of the block inverses
   if (!h || !out) return FSGMG_EINVAL;
   if (level < 0 || level >= h->L || (int)h->tune.size() != h->L) return FSGMG_ESTATE;
@@ -1836,6 +1943,7 @@ fsgmg_status tuning_info(fsgmg_h h, int level, int32_t out[5]) {
   out[2] = h->outer_lanes;
   out[3] = level > 0 ? h->tune[level].restrict_lanes : 0;
   out[4] = level > 0 ? h->tune[level].prolong_lanes : 0;
+  out[5] = level > 0 ? h->tune[level].fused : 0;
   return FSGMG_OK;
 }
 

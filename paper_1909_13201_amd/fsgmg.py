@@ -22,6 +22,7 @@ STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "EHIP", -3: "ESINGULAR"
           -4: "ENOMEM", -5: "ESTATE"}
 CYCLE = {"V": 0, "W": 1, "F": 2}
 SCHWARZ = {"additive": 0, "multiplicative": 1}
+SWEEP_FORM = {"auto": 0, "spmv": 1, "fused": 2}
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
 
 EXPORTED = ["setup_hierarchy", "build_fs_as_blocks", "vcycle_apply", "gmres_solve",
@@ -48,7 +49,7 @@ class SmootherOpts(C.Structure):
     _fields_ = [("core", C.c_int * 3), ("halo", C.c_int), ("nu_pre", C.c_int),
                 ("nu_post", C.c_int), ("omega", C.c_double), ("prec", C.c_int),
                 ("use_graph", C.c_int), ("iface_mult", C.c_int), ("monolithic", C.c_int),
-                ("cycle", C.c_int), ("schwarz", C.c_int)]
+                ("cycle", C.c_int), ("schwarz", C.c_int), ("sweep_form", C.c_int)]
 
 
 class KrylovOpts(C.Structure):
@@ -187,7 +188,7 @@ def setup_hierarchy(cfg, w=None, device=0, stream=None):
 
 def build_fs_as_blocks(h, core=(4, 4), halo=1, nu_pre=2, nu_post=2, omega=0.8, prec="fp64",
                        use_graph=True, iface_mult=1, monolithic=False, cycle="V",
-                       schwarz="additive"):
+                       schwarz="additive", sweep_form="auto"):
     o = SmootherOpts()
     for a in range(3):
         o.core[a] = int(core[a]) if a < len(core) else 1
@@ -199,6 +200,7 @@ def build_fs_as_blocks(h, core=(4, 4), halo=1, nu_pre=2, nu_post=2, omega=0.8, p
     o.monolithic = int(bool(monolithic))
     o.cycle = CYCLE[cycle] if isinstance(cycle, str) else int(cycle)
     o.schwarz = SCHWARZ[schwarz] if isinstance(schwarz, str) else int(schwarz)
+    o.sweep_form = SWEEP_FORM[sweep_form] if isinstance(sweep_form, str) else int(sweep_form)
     _check(h, lib().build_fs_as_blocks(h, C.byref(o)))
 
 
@@ -315,10 +317,10 @@ def kernel_timing(h, enable):
 
 
 def tuning_info(h, level):
-    out = (C.c_int32 * 5)()
+    out = (C.c_int32 * 6)()
     _check(h, lib().tuning_info(h, int(level), out))
     return dict(spmv_lanes=int(out[0]), smooth_threads=int(out[1]), outer_lanes=int(out[2]),
-                restrict_lanes=int(out[3]), prolong_lanes=int(out[4]))
+                restrict_lanes=int(out[3]), prolong_lanes=int(out[4]), fused=int(out[5]))
 
 
 def hierarchy_destroy(h):

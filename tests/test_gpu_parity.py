@@ -198,6 +198,52 @@ def test_multiplicative_schwarz_parity(key):
     H.close()
 
 
+@pytest.mark.parametrize("schwarz", ["additive", "multiplicative"])
+@pytest.mark.parametrize("key", ["c1", "c2L3", "chan3d"])
+def test_fused_and_spmv_sweeps_parity(key, schwarz):
+    """Forward sweeps that form their residual inside the smoother launch
+    (sweep_form "fused") and sweeps after a residual SpMV ("spmv"): each FP64
+    cycle and its transpose against the oracle's, the two forms against each
+    other, FP32 solves to a true 1e-10 with the same iteration counts."""
+    import tests.cfgs as cfgs
+    if key == "c1":
+        cfg = inputs.config("c1")
+    elif key == "chan3d":
+        cfg = cfgs.channel3d(levels=2, nc=(2, 2, 2))
+    else:
+        cfg = inputs.with_levels(inputs.config("c2"), 3)
+    cfg = dict(cfg, schwarz=schwarz)
+    w = None if key == "chan3d" else inputs.advecting_field(cfg)
+    O = OracleHierarchy(cfg, w)
+    H = fsgmg.Hierarchy(cfg, w, device=0)
+    rng = np.random.default_rng(17)
+    r = rng.standard_normal(H.N)
+    b = O.rhs(inputs.body_force(cfg))
+    z = torch.zeros(H.N, dtype=torch.float64, device="cuda")
+    zs, its = {}, {}
+    for form in ("fused", "spmv"):
+        H.build_fs_as_blocks(prec="fp64", sweep_form=form)
+        assert all(t["fused"] == (form == "fused") for t in H.tuning_info()[1:])
+        for tr in (False, True):
+            H.vcycle_apply(dev(r), z, transpose=tr)
+            zs[form, tr] = host(z)
+            ref = O.vcycle(r, transpose=tr)
+            err = np.linalg.norm(zs[form, tr] - ref) / np.linalg.norm(ref)
+            say("[sweeps]", key, schwarz, form, "transpose", tr, "rel err %.3e" % err)
+            assert err <= 1e-9
+        H.build_fs_as_blocks(prec="fp32", sweep_form=form)
+        x = torch.zeros(H.N, dtype=torch.float64, device="cuda")
+        info = H.gmres_solve(dev(b), x, rtol=1e-10)
+        true = np.linalg.norm(b - O.A[-1] @ host(x)) / np.linalg.norm(b)
+        say("   %s fp32 solve iters %d true %.2e" % (form, info["iters"], true))
+        assert info["converged"] and true <= 1e-10
+        its[form] = info["iters"]
+    d = np.linalg.norm(zs["fused", False] - zs["spmv", False]) / np.linalg.norm(zs["spmv", False])
+    assert d <= 1e-12
+    assert abs(its["fused"] - its["spmv"]) <= 1
+    H.close()
+
+
 @pytest.mark.parametrize("kind", ["W", "F"])
 def test_w_and_f_cycles_parity(kind):
     """W- and F-cycles (c2 at 3 levels): FP64 cycle and its transpose against
