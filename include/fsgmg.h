@@ -264,8 +264,10 @@ fsgmg_status kernel_timing(fsgmg_h h, int enable, int64_t counts[4], double tota
  * level 0), out[5] = 1 when the level's forward sweeps form their residual
  * inside the smoother launch from per-block copies of the operator rows
  * (one launch per sweep) instead of a residual SpMV before each sweep (0 on
- * level 0).  ESTATE before the first device block build. */
-fsgmg_status tuning_info(fsgmg_h h, int level, int32_t out[6]);
+ * level 0), out[6] = workgroups sharing one block in the SpMV-form forward
+ * sweep (1, 2, 4 or 8; each takes a contiguous share of the block's rows;
+ * 0 on level 0).  ESTATE before the first device block build. */
+fsgmg_status tuning_info(fsgmg_h h, int level, int32_t out[7]);
 
 const char* last_error(fsgmg_h h);
 void hierarchy_destroy(fsgmg_h h);

@@ -389,21 +389,22 @@ struct WTraits<__hip_bfloat16> {
 };
 
 // Owned rows of W_j r for one block: W_j is stored column-major over its
-// mp (padded) owned rows; the workgroup's lanes form G = mp / RV groups of RV
-// rows times S column slices; slice s of group g leaves its partial sums in
-// red[s * mp + g * RV + i].  Returns S (the caller sums the slices).
+// mp (padded) owned rows, i.e. mp / RV groups of RV rows.  The workgroup
+// takes the G groups from g0 on; its lanes form those G groups times S
+// column slices, and slice s of local group g leaves its partial sums in
+// red[s * G * RV + g * RV + i].  Returns S (the caller sums the slices).
 template <typename TA, typename TW, bool NT>
-__device__ inline int owned_gemv(const TW* __restrict__ Wj, int n, int mp, const TA* rl, TA* red) {
+__device__ inline int owned_gemv(const TW* __restrict__ Wj, int n, int mp, int g0, int G,
+                                 const TA* rl, TA* red) {
   constexpr int RV = WTraits<TW>::RV;
   const int tid = threadIdx.x;
-  const int G = mp / RV;
   const int S = G >= (int)blockDim.x ? 1 : (int)blockDim.x / G;
   for (int gg = tid; gg < G * S; gg += blockDim.x) {
     const int g = gg % G, s = gg / G;
     TA acc[RV];
 #pragma unroll
     for (int i = 0; i < RV; ++i) acc[i] = TA(0);
-    const TW* p = Wj + (int64_t)g * RV;
+    const TW* p = Wj + (int64_t)(g0 + g) * RV;
     int k = s;
     // four columns per step: four independent 16-byte loads in flight per lane
     for (; k + 3 * S < n; k += 4 * S) {
@@ -429,24 +430,29 @@ __device__ inline int owned_gemv(const TW* __restrict__ Wj, int n, int mp, const
       for (int i = 0; i < RV; ++i) acc[i] += w[i] * rk;
     }
 #pragma unroll
-    for (int i = 0; i < RV; ++i) red[s * mp + g * RV + i] = acc[i];
+    for (int i = 0; i < RV; ++i) red[s * G * RV + g * RV + i] = acc[i];
   }
   return S;
 }
 
 // Forward sweep: x[own] = (first ? 0 : x[own]) + omega * (W_j r[I_j])[own].
+// `split` workgroups share a block (levels with few blocks): workgroup
+// (b, s) takes the s-th contiguous share of the block's row groups.
 constexpr int kSmoothMaxThreads = 1024;
 
 template <typename TV, typename TW, bool NT>
 __global__ __launch_bounds__(kSmoothMaxThreads) void k_smooth_fwd(BlocksView B, const TW* __restrict__ W,
                                                          const TV* __restrict__ r,
-                                                         TV* __restrict__ x, TV omega, int first) {
+                                                         TV* __restrict__ x, TV omega, int first,
+                                                         int split) {
   using TA = TV;
+  constexpr int RV = WTraits<TW>::RV;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   TA* smem = reinterpret_cast<TA*>(smem_raw);
   const int tid = threadIdx.x;
-  if (blockIdx.x >= B.nblk) {
-    const int64_t q = (blockIdx.x - B.nblk) * blockDim.x + tid;
+  const int64_t nwg = B.nblk * split;
+  if (blockIdx.x >= nwg) {
+    const int64_t q = (blockIdx.x - nwg) * blockDim.x + tid;
     if (q < B.njac) {
       const int32_t gi = B.jac[q];
       const TV jv = reinterpret_cast<const TV*>(B.jac_inv)[q];
@@ -454,21 +460,27 @@ __global__ __launch_bounds__(kSmoothMaxThreads) void k_smooth_fwd(BlocksView B, 
     }
     return;
   }
-  const int64_t j = B.order[blockIdx.x];
+  const int64_t j = B.order[blockIdx.x / split];
+  const int part = blockIdx.x % split;
   const int64_t d0 = B.dof_ptr[j];
   const int n = (int)(B.dof_ptr[j + 1] - d0);
   const int o0 = B.own_ptr[j];
   const int m = B.own_ptr[j + 1] - o0;
   const int mp = B.mpad[j];
+  const int Gt = mp / RV;
+  const int g0 = (int)((int64_t)Gt * part / split);
+  const int G = (int)((int64_t)Gt * (part + 1) / split) - g0;
+  if (G <= 0) return;
   TA* rl = smem;
   TA* red = smem + ((n + 3) & ~3);
   for (int k = tid; k < n; k += blockDim.x) rl[k] = (TA)r[B.dofs[d0 + k]];
   __syncthreads();
-  const int S = owned_gemv<TA, TW, NT>(W + B.w_off[j], n, mp, rl, red);
+  const int S = owned_gemv<TA, TW, NT>(W + B.w_off[j], n, mp, g0, G, rl, red);
   __syncthreads();
-  for (int i = tid; i < m; i += blockDim.x) {
+  const int i0 = g0 * RV, i1 = min((g0 + G) * RV, m);
+  for (int i = i0 + tid; i < i1; i += blockDim.x) {
     TA v = TA(0);
-    for (int s = 0; s < S; ++s) v += red[s * mp + i];
+    for (int s = 0; s < S; ++s) v += red[s * G * RV + (i - i0)];
     const int32_t gi = B.own_dof[o0 + i];
     x[gi] = (first ? TV(0) : x[gi]) + omega * (TV)v;
   }
@@ -548,7 +560,8 @@ __global__ __launch_bounds__(kSmoothMaxThreads) void k_smooth_fused(BlocksView B
     }
   }
   __syncthreads();
-  const int S = owned_gemv<TA, TW, NT>(W + B.w_off[j], n, mp, rl, red);
+  constexpr int RV = WTraits<TW>::RV;
+  const int S = owned_gemv<TA, TW, NT>(W + B.w_off[j], n, mp, 0, mp / RV, rl, red);
   __syncthreads();
   for (int i = tid; i < m; i += blockDim.x) {
     TA v = TA(0);
@@ -1545,24 +1558,26 @@ template void launch_transfer<float>(const TransferView<float>&, int, int, const
 template <typename TV, typename TW>
 static void smooth_impl(const BlocksView& B, const TW* W, const TV* r, TV* x, TV* tbuf,
                         double omega, bool first, bool transpose, int64_t N, hipStream_t s,
-                        int threads) {
+                        int threads, int split) {
   if (!transpose) {
-    // few blocks (coarse levels): wider workgroups shorten each lane's column loop
+    // few blocks (coarse levels): wider workgroups shorten each lane's column
+    // loop, and `split` workgroups per block fill more CUs
     // threads < 0: non-temporal loads of the block inverses with |threads| lanes
     const bool nt = threads < 0;
     const int tabs = threads < 0 ? -threads : threads;
     const int T = tabs > 0 ? tabs : (B.nblk < 1024 ? kSmoothMaxThreads : kThreads);
+    const int sp = split > 1 ? split : 1;
     const int64_t nj = (B.njac + T - 1) / T;
-    const unsigned g = (unsigned)(B.nblk + nj);
+    const unsigned g = (unsigned)(B.nblk * sp + nj);
     if (!g) return;
     const int RV = WTraits<TW>::RV;
     const size_t sm = sizeof(TV) * (size_t)(((B.max_n + 3) & ~3) + T * RV + B.max_mpad);
     if (nt)
       hipLaunchKernelGGL((k_smooth_fwd<TV, TW, true>), dim3(g), dim3(T), sm, s, B, W, r, x,
-                         (TV)omega, (int)first);
+                         (TV)omega, (int)first, sp);
     else
       hipLaunchKernelGGL((k_smooth_fwd<TV, TW, false>), dim3(g), dim3(T), sm, s, B, W, r, x,
-                         (TV)omega, (int)first);
+                         (TV)omega, (int)first, sp);
     return;
   }
   if (B.nblk) {
@@ -1579,26 +1594,26 @@ static void smooth_impl(const BlocksView& B, const TW* W, const TV* r, TV* x, TV
 template <typename TV>
 void launch_smooth(const BlocksView& B, WPrec wp, const void* W, const TV* r, TV* x, TV* tbuf,
                    double omega, bool first, bool transpose, int64_t N, hipStream_t s,
-                   int threads) {
+                   int threads, int split) {
   switch (wp) {
     case WPrec::F64:
       smooth_impl<TV, double>(B, (const double*)W, r, x, tbuf, omega, first, transpose, N, s,
-                              threads);
+                              threads, split);
       break;
     case WPrec::F32:
       smooth_impl<TV, float>(B, (const float*)W, r, x, tbuf, omega, first, transpose, N, s,
-                             threads);
+                             threads, split);
       break;
     case WPrec::BF16:
       smooth_impl<TV, __hip_bfloat16>(B, (const __hip_bfloat16*)W, r, x, tbuf, omega, first,
-                                      transpose, N, s, threads);
+                                      transpose, N, s, threads, split);
       break;
   }
 }
 template void launch_smooth<double>(const BlocksView&, WPrec, const void*, const double*, double*,
-                                    double*, double, bool, bool, int64_t, hipStream_t, int);
+                                    double*, double, bool, bool, int64_t, hipStream_t, int, int);
 template void launch_smooth<float>(const BlocksView&, WPrec, const void*, const float*, float*,
-                                   float*, double, bool, bool, int64_t, hipStream_t, int);
+                                   float*, double, bool, bool, int64_t, hipStream_t, int, int);
 
 template <typename TV, typename TW>
 static void fused_impl(const BlocksView& B, const TW* W, const TV* b, const TV* xin, TV* xout,
@@ -1699,9 +1714,9 @@ static void smooth_t1_impl(const BlocksView& B, const TW* W, const TV* r, TV* tb
 template <typename TV>
 void launch_smooth_colour(const BlocksView& B, WPrec wp, const void* W, const TV* r, TV* e,
                           TV* tbuf, int64_t p0, int64_t p1, bool transpose, hipStream_t s,
-                          int threads) {
+                          int threads, int split) {
   if (!transpose || B.nblk == 0) {
-    launch_smooth<TV>(B, wp, W, r, e, tbuf, 1.0, false, false, 0, s, threads);
+    launch_smooth<TV>(B, wp, W, r, e, tbuf, 1.0, false, false, 0, s, threads, split);
     return;
   }
   switch (wp) {
@@ -1722,10 +1737,10 @@ void launch_smooth_colour(const BlocksView& B, WPrec wp, const void* W, const TV
 }
 template void launch_smooth_colour<double>(const BlocksView&, WPrec, const void*, const double*,
                                            double*, double*, int64_t, int64_t, bool, hipStream_t,
-                                           int);
+                                           int, int);
 template void launch_smooth_colour<float>(const BlocksView&, WPrec, const void*, const float*,
                                           float*, float*, int64_t, int64_t, bool, hipStream_t,
-                                          int);
+                                          int, int);
 
 template <typename TV>
 void launch_add_scaled(int64_t n, double a, const TV* e, TV* x, bool first, hipStream_t s) {

@@ -139,7 +139,7 @@ void launch_transfer(const TransferView<T>& t, int D, int mode, const T* in, T* 
 template <typename TV>
 void launch_smooth(const BlocksView& B, WPrec wp, const void* W, const TV* r, TV* x, TV* tbuf,
                    double omega, bool first, bool transpose, int64_t N, hipStream_t s,
-                   int threads = 0);
+                   int threads = 0, int split = 1);
 
 // ---- fused sweep: the residual b - A xin of every block's rows (and of the
 // Jacobi rows) is formed inside the launch from B.rows_* (first: xin = 0,
@@ -169,7 +169,7 @@ void launch_mult_finish(const BlocksView& B, const TV* b, TV* y, TV* x, int64_t 
 template <typename TV>
 void launch_smooth_colour(const BlocksView& B, WPrec wp, const void* W, const TV* r, TV* e,
                           TV* tbuf, int64_t p0, int64_t p1, bool transpose, hipStream_t s,
-                          int threads = 0);
+                          int threads = 0, int split = 1);
 // x = (first ? 0 : x) + a e
 template <typename TV>
 void launch_add_scaled(int64_t n, double a, const TV* e, TV* x, bool first, hipStream_t s);

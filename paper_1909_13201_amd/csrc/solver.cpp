@@ -323,6 +323,7 @@ struct fsgmg_hierarchy {
     int restrict_lanes = 8;   // transfers into this level's coarse neighbour
     int prolong_lanes = 2;    // transfers from it
     int fused = 0;            // smoother sweeps form their residual in-launch
+    int split = 1;            // workgroups per block in the forward sweep
   };
   std::vector<Tune> tune;
   int outer_lanes = 1;
@@ -1076,7 +1077,7 @@ void smooth_level_mult(fsgmg_hierarchy& h, int l, int nsweeps, bool transpose, b
       }
       TimedLaunch t(h, 0, fin);
       launch_smooth_colour<TV>(v, wp, d.W, rr, e, Vec<TV>::t(d), p0, p1, transpose, h.stream,
-                               h.tune[l].smooth_threads);
+                               h.tune[l].smooth_threads, h.tune[l].split);
       fresh = false;
     };
     BlocksView jv = d.bv;
@@ -1129,7 +1130,7 @@ void smooth_level(fsgmg_hierarchy& h, int l, int nsweeps, bool transpose, bool f
     if (s == 0 && from_zero) {
       TimedLaunch t(h, 0, fin);
       launch_smooth<TV>(d.bv, wp, d.W, b, x, Vec<TV>::t(d), h.sopt.omega, true, transpose, d.N,
-                        h.stream, h.tune[l].smooth_threads);
+                        h.stream, h.tune[l].smooth_threads, h.tune[l].split);
     } else {
       {
         TimedLaunch t(h, 1, fin);
@@ -1137,7 +1138,7 @@ void smooth_level(fsgmg_hierarchy& h, int l, int nsweeps, bool transpose, bool f
       }
       TimedLaunch t(h, 0, fin);
       launch_smooth<TV>(d.bv, wp, d.W, r, x, Vec<TV>::t(d), h.sopt.omega, false, transpose, d.N,
-                        h.stream, h.tune[l].smooth_threads);
+                        h.stream, h.tune[l].smooth_threads, h.tune[l].split);
     }
   }
 }
@@ -1481,16 +1482,21 @@ void autotune_impl(fsgmg_hierarchy& h) {
       tv.nblk = bs.colour_ptr[1];
       tv.njac = 0;
     }
-    for (int th : threads) {
-      const float t = time_launch(h, [&] {
-        launch_smooth<TV>(tv, wp, d.W, Vec<TV>::b(d), Vec<TV>::x(d), Vec<TV>::t(d), 1.0, true,
-                          false, d.N, h.stream, th);
-      });
-      if (t < best) {
-        best = t;
-        h.tune[l].smooth_threads = th;
+    // workgroups per block: more than one only where the blocks leave CUs idle
+    const int splits[4] = {1, 2, 4, 8};
+    const int nsplit = tv.nblk < 1024 ? 4 : 1;
+    for (int th : threads)
+      for (int q = 0; q < nsplit; ++q) {
+        const float t = time_launch(h, [&] {
+          launch_smooth<TV>(tv, wp, d.W, Vec<TV>::b(d), Vec<TV>::x(d), Vec<TV>::t(d), 1.0, true,
+                            false, d.N, h.stream, th, splits[q]);
+        });
+        if (t < best) {
+          best = t;
+          h.tune[l].smooth_threads = th;
+          h.tune[l].split = splits[q];
+        }
       }
-    }
     // a sweep after the first: residual SpMV + sweep, or one fused launch
     // that forms the blocks' residual rows itself (fewer launches, but every
     // block reads its own copy of its operator rows)
@@ -1499,7 +1505,7 @@ void autotune_impl(fsgmg_hierarchy& h) {
         launch_spmv<TV>(Vec<TV>::op(d, false), h.D, Vec<TV>::x(d), Vec<TV>::b(d), Vec<TV>::r(d),
                         true, h.stream, h.tune[l].spmv_lanes);
         launch_smooth<TV>(tv, wp, d.W, Vec<TV>::r(d), Vec<TV>::x(d), Vec<TV>::t(d), 1.0, false,
-                          false, d.N, h.stream, h.tune[l].smooth_threads);
+                          false, d.N, h.stream, h.tune[l].smooth_threads, h.tune[l].split);
       });
       float t_fused = 1e30f;
       int th_fused = h.tune[l].smooth_threads;
@@ -1517,6 +1523,7 @@ void autotune_impl(fsgmg_hierarchy& h) {
       if (form == 2 || (form == 0 && t_fused < t_sep)) {
         h.tune[l].fused = 1;
         h.tune[l].smooth_threads = th_fused;
+        h.tune[l].split = 1;
       }
     }
   }
@@ -1934,7 +1941,7 @@ fsgmg_status kernel_timing(fsgmg_h h, int enable, int64_t counts[4], double tota
   });
 }
 
-fsgmg_status tuning_info(fsgmg_h h, int level, int32_t out[6]) {
+fsgmg_status tuning_info(fsgmg_h h, int level, int32_t out[7]) {
   // out[1] < 0 means non-temporal loads of the block inverses
   if (!h || !out) return FSGMG_EINVAL;
   if (level < 0 || level >= h->L || (int)h->tune.size() != h->L) return FSGMG_ESTATE;
@@ -1944,6 +1951,7 @@ fsgmg_status tuning_info(fsgmg_h h, int level, int32_t out[6]) {
   out[3] = level > 0 ? h->tune[level].restrict_lanes : 0;
   out[4] = level > 0 ? h->tune[level].prolong_lanes : 0;
   out[5] = level > 0 ? h->tune[level].fused : 0;
+  out[6] = level > 0 ? h->tune[level].split : 0;
   return FSGMG_OK;
 }
 

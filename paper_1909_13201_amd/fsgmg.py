@@ -317,10 +317,11 @@ def kernel_timing(h, enable):
 
 
 def tuning_info(h, level):
-    out = (C.c_int32 * 6)()
+    out = (C.c_int32 * 7)()
     _check(h, lib().tuning_info(h, int(level), out))
     return dict(spmv_lanes=int(out[0]), smooth_threads=int(out[1]), outer_lanes=int(out[2]),
-                restrict_lanes=int(out[3]), prolong_lanes=int(out[4]), fused=int(out[5]))
+                restrict_lanes=int(out[3]), prolong_lanes=int(out[4]), fused=int(out[5]),
+                split=int(out[6]))
 
 
 def hierarchy_destroy(h):
