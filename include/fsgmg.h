@@ -187,6 +187,17 @@ fsgmg_status build_fs_as_blocks(fsgmg_h h, const fsgmg_smoother_opts* opts);
 /* z = M^{-1} r (transpose = 0) or z = M^{-T} r (transpose = 1), one V-cycle. */
 fsgmg_status vcycle_apply(fsgmg_h h, const double* r, double* z, int transpose);
 
+/* The cycle of vcycle_apply (forward, additive smoother) on k right-hand
+ * sides at once, 1 <= k <= 64: r and z are device FP64 arrays of N * k
+ * entries, unknown-major (entry (i, c) at i * k + c: a contiguous N x k
+ * row-major matrix), caller-owned, r != z.  Column c of z equals
+ * vcycle_apply of column c of r up to rounding (every launch works on all k
+ * columns; the block apply of the smoother runs on the matrix cores).
+ * Work buffers of N_l * k entries per level are allocated on the first call
+ * with a larger k and kept.  EINVAL for k out of range or the multiplicative
+ * smoother, ESTATE before build_fs_as_blocks. */
+fsgmg_status vcycle_apply_batch(fsgmg_h h, const double* r, double* z, int k);
+
 /* Solve A x = b on the finest level (x is overwritten; x0 = 0). */
 fsgmg_status gmres_solve(fsgmg_h h, const double* b, double* x,
                          const fsgmg_krylov_opts* opts, fsgmg_solve_info* info);

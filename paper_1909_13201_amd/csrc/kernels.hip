@@ -1468,6 +1468,323 @@ __global__ __launch_bounds__(kThreads) void k_scatter(int64_t n, const double* _
   if (o32) o32[d] = (float)v[k];
 }
 
+// ------------------------------------------------------------------------
+// several right-hand sides on one operator: vectors stored unknown-major,
+// entry (i, c) of a K-column block at i * K + c, so every gather of an
+// unknown fetches its K values contiguously
+// ------------------------------------------------------------------------
+// Y = B - A X (residual) or A X: one thread per (output row, column)
+template <typename T, int D>
+__global__ __launch_bounds__(kThreads) void k_spmm(BOpView<T> A, const T* __restrict__ X,
+                                                   const T* __restrict__ Bm, T* __restrict__ Y,
+                                                   int K, int residual) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t rr = t / K;
+  const int c = (int)(t - rr * K);
+  if (rr < A.nsn * 64) {
+    const int64_t sl = rr / 64;
+    const int r = (int)(rr % 64);
+    const int row = A.n_rows[sl * 64 + r];
+    if (row < 0) return;
+    const int wa = A.n_wa[sl], wb = A.n_wb[sl];
+    const int32_t* ca = A.n_ca + A.n_oa[sl] + r;
+    const T* va = A.n_va + (A.n_oa[sl] + r) * (D * D);
+    T acc[D];
+#pragma unroll
+    for (int q = 0; q < D; ++q) acc[q] = T(0);
+    for (int k = 0; k < wa; ++k) {
+      const int64_t col = ca[(int64_t)k * 64];
+      const T* v = va + (int64_t)k * 64 * (D * D);
+      T xv[D];
+#pragma unroll
+      for (int q = 0; q < D; ++q) xv[q] = X[(col + q) * K + c];
+#pragma unroll
+      for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int q = 0; q < D; ++q) acc[i] += v[i * D + q] * xv[q];
+    }
+    const int32_t* cb = A.n_cb + A.n_ob[sl] + r;
+    const T* vb = A.n_vb + (A.n_ob[sl] + r) * D;
+    for (int k = 0; k < wb; ++k) {
+      const T xp = X[(int64_t)cb[(int64_t)k * 64] * K + c];
+      const T* v = vb + (int64_t)k * 64 * D;
+#pragma unroll
+      for (int i = 0; i < D; ++i) acc[i] += v[i] * xp;
+    }
+    const int64_t o = A.nrow_off[row];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      const int64_t e = (o + i) * K + c;
+      Y[e] = residual ? Bm[e] - acc[i] : acc[i];
+    }
+    return;
+  }
+  const int64_t pr = rr - A.nsn * 64;
+  if (pr >= A.nsp * 64) return;
+  const int64_t sl = pr / 64;
+  const int r = (int)(pr % 64);
+  const int row = A.p_rows[sl * 64 + r];
+  if (row < 0) return;
+  const int wa = A.p_wa[sl], wb = A.p_wb[sl];
+  const int32_t* ca = A.p_ca + A.p_oa[sl] + r;
+  const T* va = A.p_va + (A.p_oa[sl] + r) * D;
+  T acc = T(0);
+  for (int k = 0; k < wa; ++k) {
+    const int64_t col = ca[(int64_t)k * 64];
+    const T* v = va + (int64_t)k * 64 * D;
+#pragma unroll
+    for (int q = 0; q < D; ++q) acc += v[q] * X[(col + q) * K + c];
+  }
+  const int32_t* cb = A.p_cb + A.p_ob[sl] + r;
+  const T* vb = A.p_vb + A.p_ob[sl] + r;
+  for (int k = 0; k < wb; ++k) acc += vb[(int64_t)k * 64] * X[(int64_t)cb[(int64_t)k * 64] * K + c];
+  const int64_t e = (int64_t)A.prow_off[row] * K + c;
+  Y[e] = residual ? Bm[e] - acc : acc;
+}
+
+// Restriction (mode 0: out = D_c R in) and prolongation (mode 1:
+// out += D_f P in) of K columns: one thread per (output row, column), the
+// same equation routing and Dirichlet masks as the one-column transfer.
+template <typename T, int D>
+__global__ __launch_bounds__(kThreads) void k_transfer_mc(TransferView<T> t, int mode,
+                                                          const T* __restrict__ in,
+                                                          T* __restrict__ out, int K) {
+  const int64_t tt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t id = tt / K;
+  const int c = (int)(tt - id * K);
+  if (mode == 0) {
+    if (id < t.N2c) {
+      const int64_t I = id;
+      const uint8_t fc = t.flags_c[I];
+      const bool ssI = fc & kSolid;
+      T bd[D], bu[D];
+#pragma unroll
+      for (int q = 0; q < D; ++q) bd[q] = bu[q] = T(0);
+      for (int k = t.rn_ptr[I]; k < t.rn_ptr[I + 1]; ++k) {
+        const int64_t i = t.rn_col[k];
+        const T w = t.rn_val[k];
+        const bool ssi = t.flags_f[i] & kSolid;
+        if (ssI == ssi) {
+#pragma unroll
+          for (int q = 0; q < D; ++q) {
+            bd[q] += w * in[(D * i + q) * K + c];
+            bu[q] += w * in[(t.offu_f + D * i + q) * K + c];
+          }
+        } else if (ssI) {
+#pragma unroll
+          for (int q = 0; q < D; ++q) bd[q] += w * in[(t.offu_f + D * i + q) * K + c];
+        }
+      }
+      const bool zd = fc & kDirD, zu = fc & kDirU;
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        out[(D * I + q) * K + c] = zd ? T(0) : bd[q];
+        out[(t.offu_c + D * I + q) * K + c] = zu ? T(0) : bu[q];
+      }
+      return;
+    }
+    int64_t p = id - t.N2c;
+    const int32_t *rp, *rc;
+    const T* rv;
+    int64_t off_in, off_out;
+    if (p < t.Npsc) {
+      rp = t.rps_ptr; rc = t.rps_col; rv = t.rps_val; off_in = t.offps_f; off_out = t.offps_c;
+    } else {
+      p -= t.Npsc;
+      if (p >= t.Npfc) return;
+      rp = t.rpf_ptr; rc = t.rpf_col; rv = t.rpf_val; off_in = t.offpf_f; off_out = t.offpf_c;
+    }
+    T sum = T(0);
+    for (int k = rp[p]; k < rp[p + 1]; ++k) sum += rv[k] * in[(off_in + rc[k]) * K + c];
+    out[(off_out + p) * K + c] = sum;
+    return;
+  }
+  if (id < t.N2f) {
+    const int64_t i = id;
+    const uint8_t ff = t.flags_f[i];
+    T ad[D], au[D];
+#pragma unroll
+    for (int q = 0; q < D; ++q) ad[q] = au[q] = T(0);
+    for (int k = t.pn_ptr[i]; k < t.pn_ptr[i + 1]; ++k) {
+      const int64_t I = t.pn_col[k];
+      const T w = t.pn_val[k];
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        ad[q] += w * in[(D * I + q) * K + c];
+        au[q] += w * in[(t.offu_c + D * I + q) * K + c];
+      }
+    }
+    const bool md = ff & kDirD, mu = ff & kDirU;
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      if (!md) out[(D * i + q) * K + c] += ad[q];
+      if (!mu) out[(t.offu_f + D * i + q) * K + c] += au[q];
+    }
+    return;
+  }
+  int64_t p = id - t.N2f;
+  const int32_t *rp, *rc;
+  const T* rv;
+  int64_t off_in, off_out;
+  if (p < t.Npsf) {
+    rp = t.pps_ptr; rc = t.pps_col; rv = t.pps_val; off_in = t.offps_c; off_out = t.offps_f;
+  } else {
+    p -= t.Npsf;
+    if (p >= t.Npff) return;
+    rp = t.ppf_ptr; rc = t.ppf_col; rv = t.ppf_val; off_in = t.offpf_c; off_out = t.offpf_f;
+  }
+  T sum = T(0);
+  for (int k = rp[p]; k < rp[p + 1]; ++k) sum += rv[k] * in[(off_in + rc[k]) * K + c];
+  out[(off_out + p) * K + c] += sum;
+}
+
+// X = Ainv B for the dense FP64 coarse inverse (row-major n x n): one thread
+// per (row, column); a row of Ainv is shared by the K threads of that row.
+template <typename TV>
+__global__ __launch_bounds__(kThreads) void k_dense_mc(int64_t n, const double* __restrict__ Ainv,
+                                                       const TV* __restrict__ Bm,
+                                                       TV* __restrict__ X, int K) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = t / K;
+  const int c = (int)(t - i * K);
+  if (i >= n) return;
+  const double* a = Ainv + i * n;
+  double acc = 0.0;
+  for (int64_t j = 0; j < n; ++j) acc += a[j] * (double)Bm[j * K + c];
+  X[i * K + c] = (TV)acc;
+}
+
+// Matrix-core tile of the block apply: 16 owned rows x 16 right-hand sides
+// accumulated over 4 block columns per instruction.  Operand layout of the
+// 16x16x4 instructions: A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k;
+// accumulator entry r of lane l is row rowof(l, r) of column l % 16, with
+// rows 4 (l / 16) + r for FP32 and l / 16 + 4 r for FP64.
+using f32x4 = __attribute__((__vector_size__(4 * sizeof(float)))) float;
+template <typename TA>
+struct MfmaTile;
+template <>
+struct MfmaTile<float> {
+  using acc_t = f32x4;
+  __device__ static acc_t step(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int lg, int r) { return 4 * lg + r; }
+};
+template <>
+struct MfmaTile<double> {
+  using acc_t = f64x4;
+  __device__ static acc_t step(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int lg, int r) { return lg + 4 * r; }
+};
+
+template <typename TW, typename TA>
+__device__ inline TA w_scalar(const TW* p) {
+  if constexpr (sizeof(TW) == 2)
+    return (TA)__uint_as_float((uint32_t)(*reinterpret_cast<const uint16_t*>(p)) << 16);
+  else
+    return (TA)*p;
+}
+
+constexpr int kMcChunk = 64;    // block columns staged per pass
+constexpr int kMcMaxTiles = 4;  // 16-column tiles of right-hand sides (K <= 64)
+constexpr int kMcThreads = 512;
+constexpr int kMcRowTiles = 4;  // row tiles per wave and round
+
+// Block apply for K right-hand sides: X[own] = (first ? 0 : X[own]) +
+// omega (W_j R[I_j, :])[own].  Workgroup b takes block order[b]; its waves
+// deal the block's 16-row tiles round-robin (up to kMcRowTiles per wave in a
+// round, rounds until all owned rows are done) and keep one accumulator per
+// (row tile, column tile).  The residual rows are staged in LDS 64 block
+// columns at a time; each inverse entry is read by exactly one lane of one
+// wave.  Workgroups past the blocks do the Jacobi unknowns.
+template <typename TV, typename TW>
+__global__ __launch_bounds__(kMcThreads) void k_smooth_mc(BlocksView B, const TW* __restrict__ W,
+                                                          const TV* __restrict__ R,
+                                                          TV* __restrict__ X, int K, TV omega,
+                                                          int first) {
+  using TA = TV;
+  using Tile = MfmaTile<TA>;
+  using acc_t = typename Tile::acc_t;
+  const int tid = threadIdx.x;
+  if (blockIdx.x >= B.nblk) {
+    const int64_t t = (int64_t)(blockIdx.x - B.nblk) * blockDim.x + tid;
+    const int64_t q = t / K;
+    const int c = (int)(t - q * K);
+    if (q < B.njac) {
+      const int64_t gi = B.jac[q];
+      const TV jv = reinterpret_cast<const TV*>(B.jac_inv)[q];
+      X[gi * K + c] = (first ? TV(0) : X[gi * K + c]) + omega * R[gi * K + c] * jv;
+    }
+    return;
+  }
+  __shared__ TA rl[kMcChunk * 16 * kMcMaxTiles];
+  const int64_t j = B.order[blockIdx.x];
+  const int64_t d0 = B.dof_ptr[j];
+  const int n = (int)(B.dof_ptr[j + 1] - d0);
+  const int o0 = B.own_ptr[j];
+  const int m = B.own_ptr[j + 1] - o0;
+  const int mp = B.mpad[j];
+  const TW* Wj = W + B.w_off[j];
+  const int KT = (K + 15) / 16;        // column tiles
+  const int KP = KT * 16;
+  const int lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
+  const int lr = lane & 15, lg = lane >> 4;
+  const int RT = (m + 15) / 16;        // row tiles
+  for (int rt0 = 0; rt0 < RT; rt0 += kMcRowTiles * nwave) {
+    acc_t acc[kMcRowTiles][kMcMaxTiles];
+#pragma unroll
+    for (int a = 0; a < kMcRowTiles; ++a)
+#pragma unroll
+      for (int b = 0; b < kMcMaxTiles; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[a][b][r] = TA(0);
+    for (int k0 = 0; k0 < n; k0 += kMcChunk) {
+      const int kc = min(kMcChunk, n - k0);
+      __syncthreads();
+      for (int e = tid; e < kMcChunk * KP; e += blockDim.x) {
+        const int kk = e / KP, c = e - kk * KP;
+        rl[e] = (kk < kc && c < K) ? (TA)R[(int64_t)B.dofs[d0 + k0 + kk] * K + c] : TA(0);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int a = 0; a < kMcRowTiles; ++a) {
+        const int rt = rt0 + wave + a * nwave;
+        if (rt >= RT) break;
+        const int row = rt * 16 + lr;
+        for (int q = 0; q < kc; q += 4) {
+          const int kk = q + lg;
+          const TA av = (kk < kc && row < mp)
+                            ? w_scalar<TW, TA>(Wj + (int64_t)(k0 + kk) * mp + row)
+                            : TA(0);
+#pragma unroll
+          for (int b = 0; b < kMcMaxTiles; ++b)
+            if (b < KT) acc[a][b] = Tile::step(av, rl[kk * KP + b * 16 + lr], acc[a][b]);
+        }
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < kMcRowTiles; ++a) {
+      const int rt = rt0 + wave + a * nwave;
+      if (rt >= RT) break;
+#pragma unroll
+      for (int b = 0; b < kMcMaxTiles; ++b) {
+        if (b >= KT) break;
+        const int c = b * 16 + lr;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = rt * 16 + Tile::row(lg, r);
+          if (i < m && c < K) {
+            const int64_t e = (int64_t)B.own_dof[o0 + i] * K + c;
+            X[e] = (first ? TV(0) : X[e]) + omega * (TV)acc[a][b][r];
+          }
+        }
+      }
+    }
+  }
+}
+
 }  // namespace
 
 // ========================================================================
@@ -1807,6 +2124,80 @@ template void launch_dense_gemv<double>(int64_t, const double*, bool, const doub
                                         hipStream_t);
 template void launch_dense_gemv<float>(int64_t, const double*, bool, const float*, float*,
                                        hipStream_t);
+
+// ---- several right-hand sides ----
+template <typename T>
+void launch_spmm(const BOpView<T>& A, int D, const T* X, const T* Bm, T* Y, int K, bool residual,
+                 hipStream_t s) {
+  const int64_t n = (A.nsn + A.nsp) * 64 * (int64_t)K;
+  if (n == 0) return;
+  if (D == 2)
+    hipLaunchKernelGGL((k_spmm<T, 2>), dim3(grid_for(n, kThreads)), dim3(kThreads), 0, s, A, X, Bm,
+                       Y, K, (int)residual);
+  else
+    hipLaunchKernelGGL((k_spmm<T, 3>), dim3(grid_for(n, kThreads)), dim3(kThreads), 0, s, A, X, Bm,
+                       Y, K, (int)residual);
+}
+template void launch_spmm<double>(const BOpView<double>&, int, const double*, const double*,
+                                  double*, int, bool, hipStream_t);
+template void launch_spmm<float>(const BOpView<float>&, int, const float*, const float*, float*,
+                                 int, bool, hipStream_t);
+
+template <typename T>
+void launch_transfer_mc(const TransferView<T>& t, int D, int mode, const T* in, T* out, int K,
+                        hipStream_t s) {
+  const int64_t rows = mode == 0 ? t.N2c + t.Npsc + t.Npfc : t.N2f + t.Npsf + t.Npff;
+  const int64_t n = rows * K;
+  if (n == 0) return;
+  if (D == 2)
+    hipLaunchKernelGGL((k_transfer_mc<T, 2>), dim3(grid_for(n, kThreads)), dim3(kThreads), 0, s, t,
+                       mode, in, out, K);
+  else
+    hipLaunchKernelGGL((k_transfer_mc<T, 3>), dim3(grid_for(n, kThreads)), dim3(kThreads), 0, s, t,
+                       mode, in, out, K);
+}
+template void launch_transfer_mc<double>(const TransferView<double>&, int, int, const double*,
+                                         double*, int, hipStream_t);
+template void launch_transfer_mc<float>(const TransferView<float>&, int, int, const float*,
+                                        float*, int, hipStream_t);
+
+template <typename TV>
+void launch_dense_mc(int64_t n, const double* Ainv, const TV* Bm, TV* X, int K, hipStream_t s) {
+  if (n > 0)
+    hipLaunchKernelGGL((k_dense_mc<TV>), dim3(grid_for(n * K, kThreads)), dim3(kThreads), 0, s, n,
+                       Ainv, Bm, X, K);
+}
+template void launch_dense_mc<double>(int64_t, const double*, const double*, double*, int,
+                                      hipStream_t);
+template void launch_dense_mc<float>(int64_t, const double*, const float*, float*, int,
+                                     hipStream_t);
+
+template <typename TV, typename TW>
+static void smooth_mc_impl(const BlocksView& B, const TW* W, const TV* R, TV* X, int K,
+                           double omega, bool first, hipStream_t s) {
+  const int64_t nj = (B.njac * (int64_t)K + kMcThreads - 1) / kMcThreads;
+  const unsigned g = (unsigned)(B.nblk + nj);
+  if (g)
+    hipLaunchKernelGGL((k_smooth_mc<TV, TW>), dim3(g), dim3(kMcThreads), 0, s, B, W, R, X, K,
+                       (TV)omega, (int)first);
+}
+
+template <typename TV>
+void launch_smooth_mc(const BlocksView& B, WPrec wp, const void* W, const TV* R, TV* X, int K,
+                      double omega, bool first, hipStream_t s) {
+  if constexpr (sizeof(TV) == 8) {
+    smooth_mc_impl<double, double>(B, (const double*)W, R, X, K, omega, first, s);
+  } else {
+    if (wp == WPrec::BF16)
+      smooth_mc_impl<float, __hip_bfloat16>(B, (const __hip_bfloat16*)W, R, X, K, omega, first, s);
+    else
+      smooth_mc_impl<float, float>(B, (const float*)W, R, X, K, omega, first, s);
+  }
+}
+template void launch_smooth_mc<double>(const BlocksView&, WPrec, const void*, const double*,
+                                       double*, int, double, bool, hipStream_t);
+template void launch_smooth_mc<float>(const BlocksView&, WPrec, const void*, const float*, float*,
+                                      int, double, bool, hipStream_t);
 
 int krylov_partials() { return kPartials * kMaxK; }
 

@@ -161,6 +161,25 @@ template <typename TV>
 void launch_mult_finish(const BlocksView& B, const TV* b, TV* y, TV* x, int64_t N, double omega,
                         bool first, hipStream_t s);
 
+// ---- several right-hand sides on one operator (K <= 64 columns, entry
+// (i, c) at i * K + c): Y = B - A X or A X; restriction (mode 0) /
+// prolongation (mode 1, adds) of K columns; X = Ainv B for the dense coarse
+// inverse; block apply X[own] = (first ? 0 : X[own]) + omega (W_j R[I_j])[own]
+// on the matrix cores (FP64 vectors with FP64 inverses, FP32 vectors with
+// FP32 or BF16 inverses), Jacobi unknowns likewise ----
+constexpr int kMaxRhs = 64;
+template <typename T>
+void launch_spmm(const BOpView<T>& A, int D, const T* X, const T* B, T* Y, int K, bool residual,
+                 hipStream_t s);
+template <typename T>
+void launch_transfer_mc(const TransferView<T>& t, int D, int mode, const T* in, T* out, int K,
+                        hipStream_t s);
+template <typename TV>
+void launch_dense_mc(int64_t n, const double* Ainv, const TV* B, TV* X, int K, hipStream_t s);
+template <typename TV>
+void launch_smooth_mc(const BlocksView& B, WPrec wp, const void* W, const TV* R, TV* X, int K,
+                      double omega, bool first, hipStream_t s);
+
 // ---- multiplicative sweep, one colour: B views the colour's blocks (all
 // rows owned, mutually uncoupled) and no Jacobi unknowns, or no blocks and
 // the Jacobi unknowns.  e[I_j] += W_j r[I_j] (transpose: W_j^T r[I_j]);

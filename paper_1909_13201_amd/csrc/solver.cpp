@@ -267,6 +267,11 @@ struct DLevel {
   // fused additive sweeps alternate between x and x2
   double* x2_64 = nullptr;
   float* x2_32 = nullptr;
+  // several right-hand sides: K-column blocks (entry (i, c) at i * K + c)
+  // of b, x, r in FP64 / FP32, sized for mcap64 / mcap32 columns
+  int mcap64 = 0, mcap32 = 0;
+  double *bm64 = nullptr, *xm64 = nullptr, *rm64 = nullptr;
+  float *bm32 = nullptr, *xm32 = nullptr, *rm32 = nullptr;
 };
 
 }  // namespace
@@ -999,6 +1004,9 @@ struct Vec<double> {
   static double* e(DLevel& d) { return d.e64; }
   static double* rc(DLevel& d) { return d.rc64; }
   static double* x2(DLevel& d) { return d.x2_64; }
+  static double* bm(DLevel& d) { return d.bm64; }
+  static double* xm(DLevel& d) { return d.xm64; }
+  static double* rm(DLevel& d) { return d.rm64; }
   static const BOpView<double>& op(DLevel& d, bool tr) { return tr ? d.AT.v64 : d.A.v64; }
   static const TransferView<double>& tv(DLevel& d) { return d.t64; }
 };
@@ -1011,6 +1019,9 @@ struct Vec<float> {
   static float* e(DLevel& d) { return d.e32; }
   static float* rc(DLevel& d) { return d.rc32; }
   static float* x2(DLevel& d) { return d.x2_32; }
+  static float* bm(DLevel& d) { return d.bm32; }
+  static float* xm(DLevel& d) { return d.xm32; }
+  static float* rm(DLevel& d) { return d.rm32; }
   static const BOpView<float>& op(DLevel& d, bool tr) { return tr ? d.AT.v32 : d.A.v32; }
   static const TransferView<float>& tv(DLevel& d) { return d.t32; }
 };
@@ -1251,6 +1262,105 @@ void vcycle(fsgmg_hierarchy& h, const double* r, double* z, bool transpose) {
     vcycle_impl<double>(h, r, z, transpose);
   else
     vcycle_impl<float>(h, r, z, transpose);
+}
+
+// ---------------------------------------------------------------------------
+// Several right-hand sides on the same operator: the cycle of each column is
+// the one-column cycle (same operators, smoother, transfers, coarse solve),
+// every launch works on all K columns, so each matrix and block inverse is
+// read once per K columns and the block apply runs on the matrix cores.
+// ---------------------------------------------------------------------------
+template <typename TV>
+void ensure_mc_buffers(fsgmg_hierarchy& h, int K) {
+  for (int l = 0; l < h.L; ++l) {
+    DLevel& d = h.dl[l];
+    const int64_t n = d.N * (int64_t)K;
+    if (sizeof(TV) == 8) {
+      if (d.mcap64 >= K) continue;
+      for (void* q : {(void*)d.bm64, (void*)d.xm64, (void*)d.rm64}) h.dfree(q);
+      d.bm64 = d.xm64 = d.rm64 = nullptr;
+      d.mcap64 = 0;
+      d.bm64 = h.zeros<double>(n);
+      d.xm64 = h.zeros<double>(n);
+      d.rm64 = h.zeros<double>(n);
+      d.mcap64 = K;
+    } else {
+      if (d.mcap32 >= K) continue;
+      for (void* q : {(void*)d.bm32, (void*)d.xm32, (void*)d.rm32}) h.dfree(q);
+      d.bm32 = d.xm32 = d.rm32 = nullptr;
+      d.mcap32 = 0;
+      d.bm32 = h.zeros<float>(n);
+      d.xm32 = h.zeros<float>(n);
+      d.rm32 = h.zeros<float>(n);
+      d.mcap32 = K;
+    }
+  }
+}
+
+template <typename TV>
+void smooth_level_mc(fsgmg_hierarchy& h, int l, int nsweeps, bool from_zero, int K) {
+  DLevel& d = h.dl[l];
+  const WPrec wp = wprec(h.sopt.prec);
+  TV* b = Vec<TV>::bm(d);
+  TV* x = Vec<TV>::xm(d);
+  TV* r = Vec<TV>::rm(d);
+  for (int s = 0; s < nsweeps; ++s) {
+    if (s == 0 && from_zero) {
+      launch_smooth_mc<TV>(d.bv, wp, d.W, b, x, K, h.sopt.omega, true, h.stream);
+    } else {
+      launch_spmm<TV>(Vec<TV>::op(d, false), h.D, x, b, r, K, true, h.stream);
+      launch_smooth_mc<TV>(d.bv, wp, d.W, r, x, K, h.sopt.omega, false, h.stream);
+    }
+  }
+}
+
+template <typename TV>
+void cycle_level_mc(fsgmg_hierarchy& h, int l, int kind, bool zero_init, int K) {
+  if (l == 0) {
+    DLevel& C = h.dl[0];
+    launch_dense_mc<TV>(h.n0, h.coarse_inv, Vec<TV>::bm(C), Vec<TV>::xm(C), K, h.stream);
+    return;
+  }
+  DLevel& d = h.dl[l];
+  const int64_t nk = d.N * (int64_t)K;
+  if (h.sopt.nu_pre == 0 && zero_init) launch_fill<TV>(Vec<TV>::xm(d), TV(0), nk, h.stream);
+  smooth_level_mc<TV>(h, l, h.sopt.nu_pre, zero_init, K);
+  launch_spmm<TV>(Vec<TV>::op(d, false), h.D, Vec<TV>::xm(d), Vec<TV>::bm(d), Vec<TV>::rm(d), K,
+                  true, h.stream);
+  launch_transfer_mc<TV>(Vec<TV>::tv(d), h.D, 0, Vec<TV>::rm(d), Vec<TV>::bm(h.dl[l - 1]), K,
+                         h.stream);
+  int seq[2] = {FSGMG_CYCLE_V, FSGMG_CYCLE_V};
+  int nseq = 1;
+  if (kind == FSGMG_CYCLE_W) {
+    seq[0] = seq[1] = FSGMG_CYCLE_W;
+    nseq = 2;
+  } else if (kind == FSGMG_CYCLE_F) {
+    seq[0] = FSGMG_CYCLE_F;
+    nseq = 2;
+  }
+  for (int i = 0; i < nseq; ++i) cycle_level_mc<TV>(h, l - 1, seq[i], i == 0, K);
+  launch_transfer_mc<TV>(Vec<TV>::tv(d), h.D, 1, Vec<TV>::xm(h.dl[l - 1]), Vec<TV>::xm(d), K,
+                         h.stream);
+  smooth_level_mc<TV>(h, l, h.sopt.nu_post, false, K);
+}
+void vcycle_mc(fsgmg_hierarchy& h, const double* r, double* z, int K) {
+  if (h.L == 1) {
+    launch_dense_mc<double>(h.n0, h.coarse_inv, r, z, K, h.stream);
+    return;
+  }
+  auto run = [&](auto tag) {
+    using TV = decltype(tag);
+    ensure_mc_buffers<TV>(h, K);
+    DLevel& F = h.dl[h.L - 1];
+    const int64_t nk = F.N * (int64_t)K;
+    launch_cast<double, TV>(r, Vec<TV>::bm(F), nk, h.stream);
+    cycle_level_mc<TV>(h, h.L - 1, h.sopt.cycle, true, K);
+    launch_cast<TV, double>(Vec<TV>::xm(F), z, nk, h.stream);
+  };
+  if (h.sopt.prec == FSGMG_FP64)
+    run(double{});
+  else
+    run(float{});
 }
 
 // ---------------------------------------------------------------------------
@@ -1696,6 +1806,20 @@ fsgmg_status vcycle_apply(fsgmg_h h, const double* r, double* z, int transpose) 
     if (!h->factors_valid) throw Fail{FSGMG_ESTATE, "build_fs_as_blocks has not been called"};
     if (transpose) ensure_transposed(*h);
     vcycle(*h, r, z, transpose != 0);
+    HIPCHECK(hipGetLastError());
+    return FSGMG_OK;
+  });
+}
+
+fsgmg_status vcycle_apply_batch(fsgmg_h h, const double* r, double* z, int k) {
+  if (!h || !r || !z || r == z) return FSGMG_EINVAL;
+  return guarded(h, [&]() -> fsgmg_status {
+    check_device(*h);
+    if (!h->factors_valid) throw Fail{FSGMG_ESTATE, "build_fs_as_blocks has not been called"};
+    if (k < 1 || k > kMaxRhs) throw Fail{FSGMG_EINVAL, "k must be in 1..64"};
+    if (h->sopt.schwarz != FSGMG_SCHWARZ_ADDITIVE)
+      throw Fail{FSGMG_EINVAL, "several right-hand sides need the additive smoother"};
+    vcycle_mc(*h, r, z, k);
     HIPCHECK(hipGetLastError());
     return FSGMG_OK;
   });

@@ -25,7 +25,8 @@ SCHWARZ = {"additive": 0, "multiplicative": 1}
 SWEEP_FORM = {"auto": 0, "spmv": 1, "fused": 2}
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
 
-EXPORTED = ["setup_hierarchy", "build_fs_as_blocks", "vcycle_apply", "gmres_solve",
+EXPORTED = ["setup_hierarchy", "build_fs_as_blocks", "vcycle_apply", "vcycle_apply_batch",
+            "gmres_solve",
             "adjoint_solve", "assemble_load", "load_adjoint", "apply_operator", "param_grad",
             "update_params", "level_info", "export_csr", "export_vector", "export_blocks", "block_colours",
             "kernel_timing", "tuning_info", "last_error", "hierarchy_destroy"]
@@ -81,6 +82,7 @@ def lib():
                                  C.POINTER(H)], C.c_int),
             "build_fs_as_blocks": ([H, C.POINTER(SmootherOpts)], C.c_int),
             "vcycle_apply": ([H, P, P, C.c_int], C.c_int),
+            "vcycle_apply_batch": ([H, P, P, C.c_int], C.c_int),
             "gmres_solve": ([H, P, P, C.POINTER(KrylovOpts), C.POINTER(SolveInfo)], C.c_int),
             "adjoint_solve": ([H, P, P, C.POINTER(KrylovOpts), C.POINTER(SolveInfo)], C.c_int),
             "assemble_load": ([H, P, P], C.c_int),
@@ -206,6 +208,10 @@ def build_fs_as_blocks(h, core=(4, 4), halo=1, nu_pre=2, nu_post=2, omega=0.8, p
 
 def vcycle_apply(h, r, z, transpose=False):
     _check(h, lib().vcycle_apply(h, _ptr(r), _ptr(z), int(bool(transpose))))
+
+
+def vcycle_apply_batch(h, r, z, k):
+    _check(h, lib().vcycle_apply_batch(h, _ptr(r), _ptr(z), int(k)))
 
 
 def _solve(fn, h, b, x, restart, max_restarts, rtol, history_cap):
@@ -382,6 +388,18 @@ class Hierarchy:
 
     def vcycle_apply(self, r, z, transpose=False):
         vcycle_apply(self.h, self._vec(r), self._vec(z), transpose)
+
+    def vcycle_apply_batch(self, r, z):
+        """Cycle on the columns of r ((N, k) float64 device tensors)."""
+        import torch
+        for t in (r, z):
+            if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
+                raise TypeError("expected float64 device tensors")
+            if t.dim() != 2 or t.shape[0] != self.N or not t.is_contiguous():
+                raise ValueError("expected contiguous (N, k) tensors with N = %d" % self.N)
+        if r.shape != z.shape:
+            raise ValueError("r and z must have the same shape")
+        vcycle_apply_batch(self.h, r, z, r.shape[1])
 
     def gmres_solve(self, b, x, **kw):
         return gmres_solve(self.h, self._vec(b), self._vec(x), **kw)

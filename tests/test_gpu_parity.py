@@ -244,6 +244,56 @@ def test_fused_and_spmv_sweeps_parity(key, schwarz):
     H.close()
 
 
+@pytest.mark.parametrize("key,cycle", [("c1", "V"), ("c2L3", "V"), ("c2L3", "W"),
+                                       ("chan3d", "V")])
+def test_vcycle_batch_parity(key, cycle):
+    """Several right-hand sides at once (vcycle_apply_batch, k columns
+    unknown-major, block apply on the matrix cores): every column against the
+    one-column cycle of the same precision (FP64 to 1e-12, FP32 and BF16
+    factors to the FP32 rounding of the cycle), FP64 columns against the
+    oracle's cycle, ragged k (5, 17) and the largest k (64); error paths."""
+    import tests.cfgs as cfgs
+    if key == "c1":
+        cfg = inputs.config("c1")
+    elif key == "chan3d":
+        cfg = cfgs.channel3d(levels=2, nc=(2, 2, 2))
+    else:
+        cfg = inputs.with_levels(inputs.config("c2"), 3)
+    cfg = dict(cfg, cycle=cycle)
+    w = None if key == "chan3d" else inputs.advecting_field(cfg)
+    O = OracleHierarchy(cfg, w)
+    H = fsgmg.Hierarchy(cfg, w, device=0)
+    rng = np.random.default_rng(23)
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-5), ("bf16", 1e-5)):
+        H.build_fs_as_blocks(prec=prec)
+        for k in ((5, 17, 64) if prec == "fp64" else (32,)):
+            R = rng.standard_normal((H.N, k))
+            Rd = dev(R.ravel()).reshape(H.N, k).contiguous()
+            Z = torch.zeros_like(Rd)
+            H.vcycle_apply_batch(Rd, Z)
+            Zb = host(Z.reshape(-1)).reshape(H.N, k)
+            z = torch.zeros(H.N, dtype=torch.float64, device="cuda")
+            worst = 0.0
+            for c in range(k):
+                H.vcycle_apply(dev(np.ascontiguousarray(R[:, c])), z)
+                zc = host(z)
+                worst = max(worst, np.linalg.norm(Zb[:, c] - zc) / np.linalg.norm(zc))
+            say("[batch]", key, cycle, prec, "k", k, "max col rel diff %.3e" % worst)
+            assert worst <= tol
+            if prec == "fp64":
+                for c in (0, k - 1):
+                    ref = O.vcycle(R[:, c])
+                    assert np.linalg.norm(Zb[:, c] - ref) / np.linalg.norm(ref) <= 1e-9
+    Rd = torch.zeros((H.N, 65), dtype=torch.float64, device="cuda")
+    with pytest.raises(fsgmg.FsgmgError):
+        H.vcycle_apply_batch(Rd, torch.zeros_like(Rd))
+    H.build_fs_as_blocks(prec="fp64", schwarz="multiplicative")
+    Rd = torch.zeros((H.N, 4), dtype=torch.float64, device="cuda")
+    with pytest.raises(fsgmg.FsgmgError):
+        H.vcycle_apply_batch(Rd, torch.zeros_like(Rd))
+    H.close()
+
+
 @pytest.mark.parametrize("kind", ["W", "F"])
 def test_w_and_f_cycles_parity(kind):
     """W- and F-cycles (c2 at 3 levels): FP64 cycle and its transpose against
