@@ -306,6 +306,25 @@ def main():
         H.vcycle_apply(r, z)
     torch.cuda.synchronize()
     tv = time.perf_counter() - t0
+    # several right-hand sides on the same operator (vcycle_apply_batch):
+    # K columns per call, column-cycles/s against the one-column cycles/s
+    mrhs = {}
+    for K in (8, 32, 64):
+        R = torch.randn((H.N, K), dtype=torch.float64, device=dev)
+        Z = torch.zeros_like(R)
+        for _ in range(2):
+            H.vcycle_apply_batch(R, Z)
+        torch.cuda.synchronize()
+        nb_calls = max(5, args.steps)
+        t0 = time.perf_counter()
+        for _ in range(nb_calls):
+            H.vcycle_apply_batch(R, Z)
+        torch.cuda.synchronize()
+        tb_calls = time.perf_counter() - t0
+        mrhs[str(K)] = dict(calls_per_s=round(nb_calls / tb_calls, 2),
+                            column_cycles_per_s=round(K * nb_calls / tb_calls, 1),
+                            over_one_column=round((K * nb_calls / tb_calls) / (nv / tv), 2))
+        del R, Z
     # adjoint solve (mixed)
     c = torch.zeros_like(b)
     c[H.info[-1]["off_u"]:H.info[-1]["off_u"] + 2 * H.info[-1]["N2"]:2] = 1.0
@@ -364,7 +383,8 @@ def main():
                            core=list(cfg["core"]), halo=cfg["halo"], cycle=cfg["cycle"],
                            restart=30, rtol=rtol),
                fp64_solves_per_s=round(sps64, 4), mixed_over_fp64=round(sps32 / sps64, 3),
-               vcycles_per_s=round(nv / tv, 2), iters_mixed=inf32[-1]["iters"],
+               vcycles_per_s=round(nv / tv, 2), multi_rhs_vcycles=mrhs,
+               iters_mixed=inf32[-1]["iters"],
                iters_fp64=inf64[-1]["iters"], rel_res_true_mixed=inf32[-1]["rel_res_true"],
                rel_res_true_fp64=inf64[-1]["rel_res_true"], rel_diff_mixed_vs_fp64=rel_diff,
                setup_hierarchy_s=round(t_setup, 3), build_blocks_fp64_s=round(t_blocks64, 3),

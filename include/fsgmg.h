@@ -194,8 +194,9 @@ fsgmg_status vcycle_apply(fsgmg_h h, const double* r, double* z, int transpose);
  * vcycle_apply of column c of r up to rounding (every launch works on all k
  * columns; the block apply of the smoother runs on the matrix cores).
  * Work buffers of N_l * k entries per level are allocated on the first call
- * with a larger k and kept.  EINVAL for k out of range or the multiplicative
- * smoother, ESTATE before build_fs_as_blocks. */
+ * with a larger k and kept.  EINVAL for k out of range, the multiplicative
+ * smoother or a Schwarz block of more than 1024 unknowns, ESTATE before
+ * build_fs_as_blocks. */
 fsgmg_status vcycle_apply_batch(fsgmg_h h, const double* r, double* z, int k);
 
 /* Solve A x = b on the finest level (x is overwritten; x0 = 0). */

@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "kernels.hpp"
@@ -1492,7 +1493,27 @@ __global__ __launch_bounds__(kThreads) void k_spmm(BOpView<T> A, const T* __rest
     T acc[D];
 #pragma unroll
     for (int q = 0; q < D; ++q) acc[q] = T(0);
-    for (int k = 0; k < wa; ++k) {
+    int k = 0;
+    // four entries per step: their column indices, blocks and gathers in flight together
+    for (; k + 3 < wa; k += 4) {
+      int64_t col[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) col[u] = ca[(int64_t)(k + u) * 64];
+      T v[4][D * D], xv[4][D];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        load_block<T, D>(va + (int64_t)(k + u) * 64 * (D * D), v[u]);
+#pragma unroll
+        for (int q = 0; q < D; ++q) xv[u][q] = X[(col[u] + q) * K + c];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+          for (int q = 0; q < D; ++q) acc[i] += v[u][i * D + q] * xv[u][q];
+    }
+    for (; k < wa; ++k) {
       const int64_t col = ca[(int64_t)k * 64];
       const T* v = va + (int64_t)k * 64 * (D * D);
       T xv[D];
@@ -1687,98 +1708,124 @@ __device__ inline TA w_scalar(const TW* p) {
     return (TA)*p;
 }
 
-constexpr int kMcChunk = 64;    // block columns staged per pass
 constexpr int kMcMaxTiles = 4;  // 16-column tiles of right-hand sides (K <= 64)
 constexpr int kMcThreads = 512;
-constexpr int kMcRowTiles = 4;  // row tiles per wave and round
+constexpr int kMcRTW = 2;       // row tiles per wave and round
+constexpr int kMcRows = kMcThreads / 64 * kMcRTW * 16;   // owned rows per round
+constexpr int kMcWs = kMcRows + 16;   // LDS stride of a staged column (lane groups on disjoint banks)
+constexpr int kMcMaxN = kMaxRhsBlock;   // largest block the staged index list holds
 
 // Block apply for K right-hand sides: X[own] = (first ? 0 : X[own]) +
-// omega (W_j R[I_j, :])[own].  Workgroup b takes block order[b]; its waves
-// deal the block's 16-row tiles round-robin (up to kMcRowTiles per wave in a
-// round, rounds until all owned rows are done) and keep one accumulator per
-// (row tile, column tile).  The residual rows are staged in LDS 64 block
-// columns at a time; each inverse entry is read by exactly one lane of one
-// wave.  Workgroups past the blocks do the Jacobi unknowns.
+// omega (W_j R[I_j, :])[own].  Workgroup (b, s) takes rows s * kMcRows ..
+// of block order[b] (`split` workgroups per block, enough for the largest);
+// each wave keeps kMcRTW 16-row tiles times the column tiles as matrix-core
+// accumulators.  Per chunk of block columns the residual rows (gathered
+// through the block's index list, staged in LDS once) and the inverse
+// columns (16-byte loads) are staged in LDS; every inverse entry is loaded
+// once.  Workgroups past the blocks do the Jacobi unknowns.
 template <typename TV, typename TW>
 __global__ __launch_bounds__(kMcThreads) void k_smooth_mc(BlocksView B, const TW* __restrict__ W,
                                                           const TV* __restrict__ R,
                                                           TV* __restrict__ X, int K, TV omega,
-                                                          int first) {
+                                                          int first, int split) {
   using TA = TV;
   using Tile = MfmaTile<TA>;
   using acc_t = typename Tile::acc_t;
+  constexpr int RV = WTraits<TW>::RV;
+  constexpr int CH = 16;   // block columns per staged chunk (small LDS: several workgroups per CU)
   const int tid = threadIdx.x;
-  if (blockIdx.x >= B.nblk) {
-    const int64_t t = (int64_t)(blockIdx.x - B.nblk) * blockDim.x + tid;
-    const int64_t q = t / K;
-    const int c = (int)(t - q * K);
-    if (q < B.njac) {
+  const int64_t nwg = B.nblk * split;
+  if (blockIdx.x >= nwg) {
+    // Jacobi unknowns: the workgroups past the blocks stride over (q, c)
+    const int64_t nt = (int64_t)(gridDim.x - nwg) * blockDim.x;
+    for (int64_t t = (int64_t)(blockIdx.x - nwg) * blockDim.x + tid; t < B.njac * (int64_t)K;
+         t += nt) {
+      const int64_t q = t / K;
+      const int c = (int)(t - q * K);
       const int64_t gi = B.jac[q];
       const TV jv = reinterpret_cast<const TV*>(B.jac_inv)[q];
       X[gi * K + c] = (first ? TV(0) : X[gi * K + c]) + omega * R[gi * K + c] * jv;
     }
     return;
   }
-  __shared__ TA rl[kMcChunk * 16 * kMcMaxTiles];
-  const int64_t j = B.order[blockIdx.x];
-  const int64_t d0 = B.dof_ptr[j];
-  const int n = (int)(B.dof_ptr[j + 1] - d0);
+  __shared__ TA rl[CH * 16 * kMcMaxTiles];
+  __shared__ TA wl[CH * kMcWs];
+  __shared__ int32_t ldof[kMcMaxN];
+  const int64_t j = B.order[blockIdx.x / split];
   const int o0 = B.own_ptr[j];
   const int m = B.own_ptr[j + 1] - o0;
+  const int r0 = (int)(blockIdx.x % split) * kMcRows;
+  if (r0 >= m) return;
+  const int64_t d0 = B.dof_ptr[j];
+  const int n = (int)(B.dof_ptr[j + 1] - d0);
   const int mp = B.mpad[j];
   const TW* Wj = W + B.w_off[j];
   const int KT = (K + 15) / 16;        // column tiles
   const int KP = KT * 16;
-  const int lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
+  const int lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lg = lane >> 4;
-  const int RT = (m + 15) / 16;        // row tiles
-  for (int rt0 = 0; rt0 < RT; rt0 += kMcRowTiles * nwave) {
-    acc_t acc[kMcRowTiles][kMcMaxTiles];
+  for (int k = tid; k < n; k += blockDim.x) ldof[k] = B.dofs[d0 + k];
+  // owned rows r0 .. r0 + nr of the padded inverse (nr a multiple of RV)
+  const int nr = min(kMcRows, mp - r0);
+  const int nv = nr / RV;
+  acc_t acc[kMcRTW][kMcMaxTiles];
 #pragma unroll
-    for (int a = 0; a < kMcRowTiles; ++a)
+  for (int a = 0; a < kMcRTW; ++a)
 #pragma unroll
-      for (int b = 0; b < kMcMaxTiles; ++b)
+    for (int b = 0; b < kMcMaxTiles; ++b)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) acc[a][b][r] = TA(0);
-    for (int k0 = 0; k0 < n; k0 += kMcChunk) {
-      const int kc = min(kMcChunk, n - k0);
-      __syncthreads();
-      for (int e = tid; e < kMcChunk * KP; e += blockDim.x) {
-        const int kk = e / KP, c = e - kk * KP;
-        rl[e] = (kk < kc && c < K) ? (TA)R[(int64_t)B.dofs[d0 + k0 + kk] * K + c] : TA(0);
-      }
-      __syncthreads();
-#pragma unroll
-      for (int a = 0; a < kMcRowTiles; ++a) {
-        const int rt = rt0 + wave + a * nwave;
-        if (rt >= RT) break;
-        const int row = rt * 16 + lr;
-        for (int q = 0; q < kc; q += 4) {
-          const int kk = q + lg;
-          const TA av = (kk < kc && row < mp)
-                            ? w_scalar<TW, TA>(Wj + (int64_t)(k0 + kk) * mp + row)
-                            : TA(0);
-#pragma unroll
-          for (int b = 0; b < kMcMaxTiles; ++b)
-            if (b < KT) acc[a][b] = Tile::step(av, rl[kk * KP + b * 16 + lr], acc[a][b]);
-        }
-      }
+      for (int r = 0; r < 4; ++r) acc[a][b][r] = TA(0);
+  for (int k0 = 0; k0 < n; k0 += CH) {
+    const int kc = min(CH, n - k0);
+    __syncthreads();
+    // residual rows of the chunk, zero-padded to KP columns and CH rows
+    for (int e = tid; e < CH * KP; e += blockDim.x) {
+      const int kk = e / KP, c = e - kk * KP;
+      rl[e] = (kk < kc && c < K) ? (TA)R[(int64_t)ldof[k0 + kk] * K + c] : TA(0);
     }
+    // the chunk's inverse columns, rows r0 .. r0 + nr, with 16-byte loads
+    for (int e = tid; e < kc * nv; e += blockDim.x) {
+      const int kk = e / nv, v = e - kk * nv;
+      TA w[RV];
+      WTraits<TW>::template load<true>(Wj + (int64_t)(k0 + kk) * mp + r0 + v * RV, w);
 #pragma unroll
-    for (int a = 0; a < kMcRowTiles; ++a) {
-      const int rt = rt0 + wave + a * nwave;
-      if (rt >= RT) break;
+      for (int u = 0; u < RV; ++u) wl[kk * kMcWs + v * RV + u] = w[u];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < CH / 4; ++q) {
+      if (4 * q >= kc) break;
+      const int kk = 4 * q + lg;
+      const bool kin = kk < kc;
+      const TA* rq = rl + kk * KP + lr;
+      TA av[kMcRTW];
+#pragma unroll
+      for (int a = 0; a < kMcRTW; ++a) {
+        const int i = (wave + a * (kMcThreads / 64)) * 16 + lr;
+        av[a] = (kin && i < nr) ? wl[kk * kMcWs + i] : TA(0);
+      }
 #pragma unroll
       for (int b = 0; b < kMcMaxTiles; ++b) {
         if (b >= KT) break;
-        const int c = b * 16 + lr;
+        const TA bv = rq[b * 16];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int i = rt * 16 + Tile::row(lg, r);
-          if (i < m && c < K) {
-            const int64_t e = (int64_t)B.own_dof[o0 + i] * K + c;
-            X[e] = (first ? TV(0) : X[e]) + omega * (TV)acc[a][b][r];
-          }
+        for (int a = 0; a < kMcRTW; ++a) acc[a][b] = Tile::step(av[a], bv, acc[a][b]);
+      }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < kMcRTW; ++a) {
+    const int tile = wave + a * (kMcThreads / 64);
+#pragma unroll
+    for (int b = 0; b < kMcMaxTiles; ++b) {
+      if (b >= KT) break;
+      const int c = b * 16 + lr;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = r0 + tile * 16 + Tile::row(lg, r);
+        if (i < m && c < K) {
+          const int64_t e = (int64_t)B.own_dof[o0 + i] * K + c;
+          X[e] = (first ? TV(0) : X[e]) + omega * (TV)acc[a][b][r];
         }
       }
     }
@@ -2175,11 +2222,12 @@ template void launch_dense_mc<float>(int64_t, const double*, const float*, float
 template <typename TV, typename TW>
 static void smooth_mc_impl(const BlocksView& B, const TW* W, const TV* R, TV* X, int K,
                            double omega, bool first, hipStream_t s) {
-  const int64_t nj = (B.njac * (int64_t)K + kMcThreads - 1) / kMcThreads;
-  const unsigned g = (unsigned)(B.nblk + nj);
+  const int split = (B.max_mpad + kMcRows - 1) / kMcRows;
+  const int64_t nj = std::min<int64_t>((B.njac * (int64_t)K + kMcThreads - 1) / kMcThreads, 512);
+  const unsigned g = (unsigned)(B.nblk * split + nj);
   if (g)
     hipLaunchKernelGGL((k_smooth_mc<TV, TW>), dim3(g), dim3(kMcThreads), 0, s, B, W, R, X, K,
-                       (TV)omega, (int)first);
+                       (TV)omega, (int)first, split);
 }
 
 template <typename TV>

@@ -168,6 +168,7 @@ void launch_mult_finish(const BlocksView& B, const TV* b, TV* y, TV* x, int64_t 
 // on the matrix cores (FP64 vectors with FP64 inverses, FP32 vectors with
 // FP32 or BF16 inverses), Jacobi unknowns likewise ----
 constexpr int kMaxRhs = 64;
+constexpr int kMaxRhsBlock = 1024;   // largest block (unknowns) of the K-column block apply
 template <typename T>
 void launch_spmm(const BOpView<T>& A, int D, const T* X, const T* B, T* Y, int K, bool residual,
                  hipStream_t s);

@@ -1819,6 +1819,10 @@ fsgmg_status vcycle_apply_batch(fsgmg_h h, const double* r, double* z, int k) {
     if (k < 1 || k > kMaxRhs) throw Fail{FSGMG_EINVAL, "k must be in 1..64"};
     if (h->sopt.schwarz != FSGMG_SCHWARZ_ADDITIVE)
       throw Fail{FSGMG_EINVAL, "several right-hand sides need the additive smoother"};
+    for (int l = 1; l < h->L; ++l)
+      if (h->dl[l].bv.max_n > kMaxRhsBlock)
+        throw Fail{FSGMG_EINVAL, "several right-hand sides: a Schwarz block exceeds " +
+                                     std::to_string(kMaxRhsBlock) + " unknowns"};
     vcycle_mc(*h, r, z, k);
     HIPCHECK(hipGetLastError());
     return FSGMG_OK;
