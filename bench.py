@@ -58,6 +58,58 @@ def smoother_bytes(H, level, prec):
     return int((n * m).sum() * sW + 4 * (n.sum() + m.sum()) + 3 * N * sV), int(len(n))
 
 
+MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 157.3}   # dense; BF16 inverses run FP32 MFMA
+
+
+def mc_smoother_model(H, level, prec, K):
+    """One K-column block apply on `level`: algorithmic bytes (owned rows of
+    every inverse once, index lists, K columns of residual read and
+    correction read + write) and matrix-core flops (2 n_j m_j K per block)."""
+    from paper_1909_13201_amd import fsgmg
+    ptr, dofs, owner = fsgmg.export_blocks(H.h, level)
+    n = np.diff(ptr)
+    m = np.bincount(owner[owner >= 0], minlength=len(n))
+    sW = {"fp64": 8, "fp32": 4, "bf16": 2}[prec]
+    sV = 8 if prec == "fp64" else 4
+    N = H.info[level]["N"]
+    nbytes = int((n * m).sum() * sW + 4 * (n.sum() + m.sum()) + 3 * N * K * sV)
+    flops = int(2 * (n * m).sum() * K)
+    return nbytes, flops
+
+
+def mrhs_measure(H, K, calls, prec, dev):
+    """K-column cycles: calls/s, column-cycles/s and the finest-level block
+    apply (HIP events on the handle stream) against HBM and matrix-core peaks."""
+    import torch
+    R = torch.randn((H.N, K), dtype=torch.float64, device=dev)
+    Z = torch.zeros_like(R)
+    for _ in range(2):
+        H.vcycle_apply_batch(R, Z)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        H.vcycle_apply_batch(R, Z)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    H.kernel_timing(True)
+    for _ in range(3):
+        H.vcycle_apply_batch(R, Z)
+    torch.cuda.synchronize()
+    kt = H.kernel_timing(False)
+    n_l, ms_l = kt["smoother"]
+    us = 1e3 * ms_l / max(n_l, 1)
+    nbytes, flops = mc_smoother_model(H, H.L - 1, prec, K)
+    gbs = nbytes / (us * 1e-6) / 1e9
+    tfl = flops / (us * 1e-6) / 1e12
+    return dict(calls_per_s=round(calls / t, 2), column_cycles_per_s=round(K * calls / t, 1),
+                block_apply=dict(kernel="k_smooth_mc (finest level)", launches=n_l,
+                                 avg_us=round(us, 2), bytes_per_launch=nbytes,
+                                 flops_per_launch=flops, achieved_gbs=round(gbs, 1),
+                                 hbm_frac=round(gbs / HBM_PEAK_GBS, 4),
+                                 achieved_tflops=round(tfl, 2),
+                                 mfma_frac=round(tfl / MFMA_PEAK_TFLOPS[prec], 4)))
+
+
 def _units(info):
     """Node-block unit of every unknown: a Q2 node's dim components of d (or
     u) form one unit, each pressure is its own unit."""
@@ -237,6 +289,8 @@ def main():
     ap.add_argument("--cycle", default="V", choices=["V", "W", "F"], help="multigrid cycle")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run three plain 256 MiB device copies first (counter calibration)")
+    ap.add_argument("--mrhs", type=int, default=0,
+                    help="only time K-column cycles (vcycle_apply_batch) with this K, FP32")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the solver has no multi-GPU path "
@@ -274,6 +328,28 @@ def main():
     x64 = torch.zeros_like(b)
     x32 = torch.zeros_like(b)
 
+    if args.mrhs:
+        H.build_fs_as_blocks(prec="fp32")
+        m = mrhs_measure(H, args.mrhs, max(5, args.steps), "fp32", dev)
+        ba = m["block_apply"]
+        line = dict(metric="K-column V-cycles (one operator, K right-hand sides)",
+                    value=m["column_cycles_per_s"], unit="column-cycles/s", n_gpus=1,
+                    steps=max(5, args.steps), warmup=2, ms_per_step=round(1e3 / m["calls_per_s"], 3),
+                    higher_is_better=True, scaling="weak", vs_baseline=None,
+                    dtype="f32 (FP32 matrix cores)", data="synthetic",
+                    config=dict(workload=WORKLOADS.get(cfg["name"], cfg["name"]), name=cfg["name"],
+                                levels=int(cfg["n_levels"]), unknowns=H.N, K=args.mrhs),
+                    calls_per_s=m["calls_per_s"],
+                    roofline=dict(bound="mfma", kernel=ba["kernel"], achieved=ba["achieved_tflops"],
+                                  peak=MFMA_PEAK_TFLOPS["fp32"], unit="TFLOP/s",
+                                  frac=ba["mfma_frac"], traffic=None,
+                                  hbm_gbs=ba["achieved_gbs"], hbm_frac=ba["hbm_frac"],
+                                  avg_launch_us=ba["avg_us"], launches=ba["launches"],
+                                  bytes_per_launch=ba["bytes_per_launch"],
+                                  flops_per_launch=ba["flops_per_launch"]))
+        H.close()
+        print(json.dumps(line), flush=True)
+        return
     res = {}
     # ---- plain FP64 path ----
     t0 = time.perf_counter()
@@ -310,21 +386,8 @@ def main():
     # K columns per call, column-cycles/s against the one-column cycles/s
     mrhs = {}
     for K in (8, 32, 64):
-        R = torch.randn((H.N, K), dtype=torch.float64, device=dev)
-        Z = torch.zeros_like(R)
-        for _ in range(2):
-            H.vcycle_apply_batch(R, Z)
-        torch.cuda.synchronize()
-        nb_calls = max(5, args.steps)
-        t0 = time.perf_counter()
-        for _ in range(nb_calls):
-            H.vcycle_apply_batch(R, Z)
-        torch.cuda.synchronize()
-        tb_calls = time.perf_counter() - t0
-        mrhs[str(K)] = dict(calls_per_s=round(nb_calls / tb_calls, 2),
-                            column_cycles_per_s=round(K * nb_calls / tb_calls, 1),
-                            over_one_column=round((K * nb_calls / tb_calls) / (nv / tv), 2))
-        del R, Z
+        mrhs[str(K)] = mrhs_measure(H, K, max(5, args.steps), "fp32", dev)
+        mrhs[str(K)]["over_one_column"] = round(mrhs[str(K)]["column_cycles_per_s"] / (nv / tv), 2)
     # adjoint solve (mixed)
     c = torch.zeros_like(b)
     c[H.info[-1]["off_u"]:H.info[-1]["off_u"] + 2 * H.info[-1]["N2"]:2] = 1.0
@@ -347,6 +410,12 @@ def main():
     x64h = x64.double()
     rel_diff = float((x32 - x64h).norm() / x64h.norm())
     sm_bytes, nblk = smoother_bytes(H, H.L - 1, "fp32")
+    # launch grid (threads) of the finest sweep, which names it in a kernel trace
+    tfin = H.tuning_info()[-1]
+    _, _, owner_f = fsgmg.export_blocks(H.h, H.L - 1)
+    njac_f = int((owner_f < 0).sum())
+    wg = abs(tfin["smooth_threads"]) or (1024 if nblk < 1024 else 256)
+    grid_f = (nblk * max(1, tfin["split"]) + (njac_f + wg - 1) // wg) * wg
     n_sm, ms_sm = ktime["smoother"]
     avg_ms = ms_sm / max(n_sm, 1)
     achieved = sm_bytes / (avg_ms * 1e-3) / 1e9
@@ -354,7 +423,7 @@ def main():
                 achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4),
                 traffic=measured_traffic() if cfg["name"] == "c2" and not args.levels else None,
-                bytes_per_launch=sm_bytes, blocks_per_launch=nblk,
+                bytes_per_launch=sm_bytes, blocks_per_launch=nblk, grid_threads=grid_f,
                 avg_launch_us=round(avg_ms * 1e3, 2), launches=n_sm)
     # the other HBM-bound kernels of the path, same live HIP-event timing
     fin = H.L - 1

@@ -262,7 +262,9 @@ fsgmg_status block_colours(fsgmg_h h, int level, int64_t* ncolours, int64_t* col
  * synchronizes and returns per kind the number of launches and their summed
  * duration: 0 smoother sweep on the finest level, 1 residual SpMV of the
  * V-cycle on the finest level, 2 outer FP64 SpMV of FGMRES, 3 restriction +
- * prolongation between the two finest levels.  counts / total_ms may be NULL. */
+ * prolongation between the two finest levels (vcycle_apply_batch records its
+ * K-column block applies as kind 0 and its K-column residuals as kind 1).
+ * counts / total_ms may be NULL. */
 fsgmg_status kernel_timing(fsgmg_h h, int enable, int64_t counts[4], double total_ms[4]);
 
 /* Launch shapes chosen by the autotuner that build_fs_as_blocks runs on the

@@ -1659,20 +1659,33 @@ __global__ __launch_bounds__(kThreads) void k_transfer_mc(TransferView<T> t, int
   out[(off_out + p) * K + c] += sum;
 }
 
-// X = Ainv B for the dense FP64 coarse inverse (row-major n x n): one thread
-// per (row, column); a row of Ainv is shared by the K threads of that row.
+// X = Ainv B for the dense FP64 coarse inverse (row-major n x n): one
+// workgroup per row i; lane t takes column t % K and the row entries
+// j = t / K, t / K + S, ... (S = blockDim / K slices), then the slices are
+// summed in a fixed order.
+constexpr int kDenseMcThreads = 1024;
 template <typename TV>
-__global__ __launch_bounds__(kThreads) void k_dense_mc(int64_t n, const double* __restrict__ Ainv,
-                                                       const TV* __restrict__ Bm,
-                                                       TV* __restrict__ X, int K) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t i = t / K;
-  const int c = (int)(t - i * K);
-  if (i >= n) return;
-  const double* a = Ainv + i * n;
+__global__ __launch_bounds__(kDenseMcThreads) void k_dense_mc(int64_t n,
+                                                              const double* __restrict__ Ainv,
+                                                              const TV* __restrict__ Bm,
+                                                              TV* __restrict__ X, int K) {
+  __shared__ double part[kDenseMcThreads];
+  const int64_t i = blockIdx.x;
+  const int t = threadIdx.x;
+  const int S = (int)blockDim.x / K;
+  const int c = t % K, sl = t / K;
   double acc = 0.0;
-  for (int64_t j = 0; j < n; ++j) acc += a[j] * (double)Bm[j * K + c];
-  X[i * K + c] = (TV)acc;
+  if (sl < S) {
+    const double* a = Ainv + i * n;
+    for (int64_t j = sl; j < n; j += S) acc += a[j] * (double)Bm[j * K + c];
+  }
+  part[t] = acc;
+  __syncthreads();
+  if (t < K) {
+    double v = 0.0;
+    for (int s2 = 0; s2 < S; ++s2) v += part[s2 * K + t];
+    X[i * K + t] = (TV)v;
+  }
 }
 
 // Matrix-core tile of the block apply: 16 owned rows x 16 right-hand sides
@@ -2211,8 +2224,8 @@ template void launch_transfer_mc<float>(const TransferView<float>&, int, int, co
 template <typename TV>
 void launch_dense_mc(int64_t n, const double* Ainv, const TV* Bm, TV* X, int K, hipStream_t s) {
   if (n > 0)
-    hipLaunchKernelGGL((k_dense_mc<TV>), dim3(grid_for(n * K, kThreads)), dim3(kThreads), 0, s, n,
-                       Ainv, Bm, X, K);
+    hipLaunchKernelGGL((k_dense_mc<TV>), dim3((unsigned)n), dim3(kDenseMcThreads), 0, s, n, Ainv,
+                       Bm, X, K);
 }
 template void launch_dense_mc<double>(int64_t, const double*, const double*, double*, int,
                                       hipStream_t);

@@ -1304,11 +1304,17 @@ void smooth_level_mc(fsgmg_hierarchy& h, int l, int nsweeps, bool from_zero, int
   TV* b = Vec<TV>::bm(d);
   TV* x = Vec<TV>::xm(d);
   TV* r = Vec<TV>::rm(d);
+  const bool fin = l == h.L - 1;
   for (int s = 0; s < nsweeps; ++s) {
     if (s == 0 && from_zero) {
+      TimedLaunch t(h, 0, fin);
       launch_smooth_mc<TV>(d.bv, wp, d.W, b, x, K, h.sopt.omega, true, h.stream);
     } else {
-      launch_spmm<TV>(Vec<TV>::op(d, false), h.D, x, b, r, K, true, h.stream);
+      {
+        TimedLaunch t(h, 1, fin);
+        launch_spmm<TV>(Vec<TV>::op(d, false), h.D, x, b, r, K, true, h.stream);
+      }
+      TimedLaunch t(h, 0, fin);
       launch_smooth_mc<TV>(d.bv, wp, d.W, r, x, K, h.sopt.omega, false, h.stream);
     }
   }
