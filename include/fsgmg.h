@@ -204,6 +204,18 @@ fsgmg_status gmres_solve(fsgmg_h h, const double* b, double* x,
                          const fsgmg_krylov_opts* opts, fsgmg_solve_info* info);
 
 /* Solve A^T lam = c with the transposed V-cycle as right preconditioner. */
+/* FGMRES of gmres_solve on k right-hand sides at once (1 <= k <= 64, additive
+ * smoother): b and x are device FP64 arrays of N * k entries, unknown-major
+ * (entry (i, c) at i * k + c), caller-owned, b != x, x overwritten (x0 = 0).
+ * Every column has its own Krylov basis, Givens rotations and convergence
+ * test, exactly as gmres_solve; every operator product, cycle
+ * (vcycle_apply_batch) and Gram-Schmidt pass works on all k columns at once.
+ * infos: host array of k entries (history is not recorded) or NULL.
+ * Returns FSGMG_OK when every column converged, FSGMG_NOT_CONVERGED if some
+ * did not; the other errors as vcycle_apply_batch. */
+fsgmg_status gmres_solve_batch(fsgmg_h h, const double* b, double* x, int k,
+                               const fsgmg_krylov_opts* opts, fsgmg_solve_info* infos);
+
 fsgmg_status adjoint_solve(fsgmg_h h, const double* c, double* lam,
                            const fsgmg_krylov_opts* opts, fsgmg_solve_info* info);
 

@@ -1845,6 +1845,102 @@ __global__ __launch_bounds__(kMcThreads) void k_smooth_mc(BlocksView B, const TW
   }
 }
 
+// ------------------------------------------------------------------------
+// Krylov building blocks on K unknown-major columns (FP64): every column its
+// own dot products; partial sums per workgroup in a fixed order, then one
+// fixed-order reduction per (vector, column)
+// ------------------------------------------------------------------------
+constexpr int kMcParts = 512;     // workgroups of the K-column reductions
+constexpr int kMcSlots = 64;      // column slots per wave (K <= 64)
+
+// mode 0: part <- dots of w with V_0..V_{nv-1};  mode 1: w -= V h, then dots
+// of the new w with V_0..V_{nv-1};  mode 2: w -= V h, then |w|^2 (nv terms
+// of h, one partial).  h is nv x K (entry (i, c) at i * K + c).
+__global__ __launch_bounds__(kThreads) void k_mc_dots(int mode, const double* __restrict__ V,
+                                                      int64_t ld, int nv,
+                                                      const double* __restrict__ h,
+                                                      double* __restrict__ w, int64_t N, int K,
+                                                      double* __restrict__ part) {
+  extern __shared__ double red[];   // kThreads / 64 waves x kMaxK x kMcSlots
+  const int c = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  constexpr int NW = kThreads / 64;
+  double acc[kMaxK];
+#pragma unroll
+  for (int i = 0; i < kMaxK; ++i) acc[i] = 0.0;
+  double hc[kMaxK];
+#pragma unroll
+  for (int i = 0; i < kMaxK; ++i) hc[i] = (mode != 0 && i < nv && c < K) ? h[i * K + c] : 0.0;
+  if (c < K) {
+    for (int64_t r = (int64_t)blockIdx.x * NW + wv; r < N; r += (int64_t)gridDim.x * NW) {
+      const int64_t e = r * K + c;
+      double wr = w[e];
+      if (mode != 0 && nv > 0) {
+#pragma unroll
+        for (int i = 0; i < kMaxK; ++i)
+          if (i < nv) wr -= hc[i] * V[i * ld + e];
+        w[e] = wr;
+      }
+      if (mode == 2) {
+        acc[0] += wr * wr;
+      } else {
+#pragma unroll
+        for (int i = 0; i < kMaxK; ++i)
+          if (i < nv) acc[i] += V[i * ld + e] * wr;
+      }
+    }
+  }
+  const int nout = mode == 2 ? 1 : nv;
+  for (int i = 0; i < nout; ++i) red[(wv * kMaxK + i) * kMcSlots + c] = acc[i];
+  __syncthreads();
+  for (int t = threadIdx.x; t < nout * kMcSlots; t += blockDim.x) {
+    const int i = t / kMcSlots, cc = t - i * kMcSlots;
+    double s2 = 0.0;
+    for (int q = 0; q < NW; ++q) s2 += red[(q * kMaxK + i) * kMcSlots + cc];
+    part[((int64_t)blockIdx.x * kMaxK + i) * kMcSlots + cc] = s2;
+  }
+}
+
+// out[i * K + c] = sum over the workgroups' partials (sqrt when `root`)
+__global__ __launch_bounds__(kThreads) void k_mc_reduce(const double* __restrict__ part, int nparts,
+                                                        int K, int root,
+                                                        double* __restrict__ out) {
+  __shared__ double red[kThreads];
+  const int i = blockIdx.x;
+  const int c = threadIdx.x & 63, sl = threadIdx.x >> 6;
+  constexpr int NS = kThreads / 64;
+  double s = 0.0;
+  for (int g = sl; g < nparts; g += NS) s += part[((int64_t)g * kMaxK + i) * kMcSlots + c];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  if (sl == 0 && c < K) {
+    double v = 0.0;
+    for (int q = 0; q < NS; ++q) v += red[q * 64 + c];
+    out[i * K + c] = root ? sqrt(v) : v;
+  }
+}
+
+// y[r * K + c] = scale[c] * w[r * K + c]
+__global__ __launch_bounds__(kThreads) void k_mc_scale(int64_t n, int K,
+                                                       const double* __restrict__ scale,
+                                                       const double* __restrict__ w,
+                                                       double* __restrict__ y) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) y[e] = scale[e % K] * w[e];
+}
+
+// x[r * K + c] += sum_{i < nv} y[i * K + c] Z_i[r * K + c]
+__global__ __launch_bounds__(kThreads) void k_mc_update(const double* __restrict__ Z, int64_t ld,
+                                                        int nv, const double* __restrict__ y,
+                                                        double* __restrict__ x, int64_t n,
+                                                        int K) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int c = (int)(e % K);
+  double s = 0.0;
+  for (int i = 0; i < nv; ++i) s += y[i * K + c] * Z[i * ld + e];
+  x[e] += s;
+}
+
 }  // namespace
 
 // ========================================================================
@@ -2259,6 +2355,45 @@ template void launch_smooth_mc<double>(const BlocksView&, WPrec, const void*, co
                                        double*, int, double, bool, hipStream_t);
 template void launch_smooth_mc<float>(const BlocksView&, WPrec, const void*, const float*, float*,
                                       int, double, bool, hipStream_t);
+
+// ---- K-column Krylov ----
+int krylov_mc_partials() { return kMcParts * kMaxK * kMcSlots; }
+
+static void mc_dots(int mode, const double* V, int64_t ld, int nv, const double* h, double* w,
+                    int64_t N, int K, double* part, double* out, hipStream_t s) {
+  const size_t sm = sizeof(double) * (kThreads / 64) * kMaxK * kMcSlots;
+  hipLaunchKernelGGL(k_mc_dots, dim3(kMcParts), dim3(kThreads), sm, s, mode, V, ld, nv, h, w, N,
+                     K, part);
+  const int nout = mode == 2 ? 1 : nv;
+  hipLaunchKernelGGL(k_mc_reduce, dim3(nout), dim3(kThreads), 0, s, part, kMcParts, K,
+                     (int)(mode == 2), out);
+}
+void launch_mc_mdot(const double* V, int64_t ld, int nv, const double* w, int64_t N, int K,
+                    double* part, double* out, hipStream_t s) {
+  mc_dots(0, V, ld, nv, nullptr, const_cast<double*>(w), N, K, part, out, s);
+}
+void launch_mc_maxpy_mdot(const double* V, int64_t ld, int nv, const double* h, double* w,
+                          int64_t N, int K, double* part, double* out, hipStream_t s) {
+  mc_dots(1, V, ld, nv, h, w, N, K, part, out, s);
+}
+void launch_mc_maxpy_norm(const double* V, int64_t ld, int nv, const double* h, double* w,
+                          int64_t N, int K, double* part, double* out, hipStream_t s) {
+  mc_dots(2, V, ld, nv, h, w, N, K, part, out, s);
+}
+void launch_mc_scale(int64_t N, int K, const double* scale, const double* w, double* y,
+                     hipStream_t s) {
+  const int64_t n = N * K;
+  if (n > 0)
+    hipLaunchKernelGGL(k_mc_scale, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, s, n, K, scale,
+                       w, y);
+}
+void launch_mc_update(const double* Z, int64_t ld, int nv, const double* y, double* x, int64_t N,
+                      int K, hipStream_t s) {
+  const int64_t n = N * K;
+  if (n > 0 && nv > 0)
+    hipLaunchKernelGGL(k_mc_update, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, s, Z, ld, nv, y,
+                       x, n, K);
+}
 
 int krylov_partials() { return kPartials * kMaxK; }
 

@@ -181,6 +181,25 @@ template <typename TV>
 void launch_smooth_mc(const BlocksView& B, WPrec wp, const void* W, const TV* R, TV* X, int K,
                       double omega, bool first, hipStream_t s);
 
+// ---- K-column Krylov (FP64, K <= 64 unknown-major columns; basis vector i
+// of a K-column block at V + i * ld; h, out: nv x K, entry (i, c) at i * K + c;
+// `part` holds krylov_mc_partials() doubles; fixed-order reductions) ----
+int krylov_mc_partials();
+void launch_mc_mdot(const double* V, int64_t ld, int nv, const double* w, int64_t N, int K,
+                    double* part, double* out, hipStream_t s);
+// w -= V h, then out = V^T w (per column)
+void launch_mc_maxpy_mdot(const double* V, int64_t ld, int nv, const double* h, double* w,
+                          int64_t N, int K, double* part, double* out, hipStream_t s);
+// w -= V h, then out[c] = |w[:, c]|
+void launch_mc_maxpy_norm(const double* V, int64_t ld, int nv, const double* h, double* w,
+                          int64_t N, int K, double* part, double* out, hipStream_t s);
+// y[:, c] = scale[c] w[:, c]
+void launch_mc_scale(int64_t N, int K, const double* scale, const double* w, double* y,
+                     hipStream_t s);
+// x[:, c] += sum_{i < nv} y[i, c] Z_i[:, c]
+void launch_mc_update(const double* Z, int64_t ld, int nv, const double* y, double* x, int64_t N,
+                      int K, hipStream_t s);
+
 // ---- multiplicative sweep, one colour: B views the colour's blocks (all
 // rows owned, mutually uncoupled) and no Jacobi unknowns, or no blocks and
 // the Jacobi unknowns.  e[I_j] += W_j r[I_j] (transpose: W_j^T r[I_j]);

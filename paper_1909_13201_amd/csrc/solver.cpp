@@ -352,6 +352,13 @@ struct fsgmg_hierarchy {
   }
   double* tmp = nullptr;
   double* pinned = nullptr;
+  // K-column FGMRES workspace: basis / preconditioned vectors (ld_mc per
+  // K-column block), work block, partial sums, small device arrays and their
+  // pinned host mirror
+  int mc_K = 0, mc_m = 0;
+  int64_t ld_mc = 0;
+  double *mc_V = nullptr, *mc_Z = nullptr, *mc_w = nullptr, *mc_part = nullptr;
+  double *mc_small = nullptr, *mc_pinned = nullptr;
   // kernel timing: HIP events around selected launches on the handle stream
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -425,6 +432,7 @@ struct fsgmg_hierarchy {
       if (cap_stream) (void)hipStreamDestroy(cap_stream);
       for (void* p : allocs) (void)hipFree(p);
       if (pinned) (void)hipHostFree(pinned);
+      if (mc_pinned) (void)hipHostFree(mc_pinned);
     }
   }
 };
@@ -1433,6 +1441,207 @@ void run_arnoldi_step(fsgmg_hierarchy& h, int j, bool transpose) {
   HIPCHECK(hipGraphLaunch(v[j], h.stream));
 }
 
+// ---------------------------------------------------------------------------
+// FGMRES on K right-hand sides in lockstep: every column has its own Krylov
+// basis, Hessenberg matrix, Givens rotations and convergence test (the
+// one-column algorithm of fgmres, column by column); every operator product,
+// K-column cycle and Gram-Schmidt pass works on all K columns at once.  A
+// column that has converged (or met a breakdown) in the current restart
+// cycle gets a zero next basis vector, so it stays zero through the rest of
+// the cycle's launches.
+// ---------------------------------------------------------------------------
+// mc_small layout (doubles): h1 [kMaxMcK * 32], h2 [kMaxMcK * 32], norms
+// [kMaxMcK], scale [kMaxMcK], y [32 * kMaxMcK]
+constexpr int kMaxMcK = kMaxRhs;
+constexpr int kMcH1 = 0, kMcH2 = 32 * kMaxMcK, kMcNrm = 64 * kMaxMcK, kMcScale = 65 * kMaxMcK,
+              kMcY = 66 * kMaxMcK, kMcSmall = 98 * kMaxMcK;
+
+void ensure_mc_workspace(fsgmg_hierarchy& h, int K, int m) {
+  if (h.mc_K >= K && h.mc_m >= m) return;
+  for (void* q : {(void*)h.mc_V, (void*)h.mc_Z, (void*)h.mc_w, (void*)h.mc_part,
+                  (void*)h.mc_small})
+    h.dfree(q);
+  h.mc_V = h.mc_Z = h.mc_w = h.mc_part = h.mc_small = nullptr;
+  h.mc_K = h.mc_m = 0;
+  const int64_t N = h.dl[h.L - 1].N;
+  h.ld_mc = (N * K + 63) / 64 * 64;
+  h.mc_V = h.zeros<double>((int64_t)(m + 1) * h.ld_mc);
+  h.mc_Z = h.zeros<double>((int64_t)m * h.ld_mc);
+  h.mc_w = h.zeros<double>(h.ld_mc);
+  h.mc_part = h.zeros<double>(krylov_mc_partials());
+  h.mc_small = h.zeros<double>(kMcSmall);
+  if (!h.mc_pinned)
+    HIPCHECK(hipHostMalloc((void**)&h.mc_pinned, kMcSmall * sizeof(double), hipHostMallocDefault));
+  h.mc_K = K;
+  h.mc_m = m;
+}
+
+fsgmg_status fgmres_batch(fsgmg_hierarchy& h, const double* b, double* x, int K,
+                          const fsgmg_krylov_opts& o, fsgmg_solve_info* infos) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (o.restart < 1 || o.restart > 31 || o.rtol <= 0 || o.max_restarts < 0)
+    throw Fail{FSGMG_EINVAL, "krylov options out of range (restart 1..31, rtol > 0)"};
+  if (!h.factors_valid) throw Fail{FSGMG_ESTATE, "build_fs_as_blocks has not been called"};
+  const int m = o.restart;
+  ensure_mc_workspace(h, K, m);
+  DLevel& F = h.dl[h.L - 1];
+  const int64_t N = F.N, ld = h.ld_mc;
+  const BOpView<double>& A = F.A.v64;
+  double* dsm = h.mc_small;
+  double* hp = h.mc_pinned;
+  auto norms = [&](const double* v, std::vector<double>& out) {
+    launch_mc_maxpy_norm(nullptr, ld, 0, nullptr, const_cast<double*>(v), N, K, h.mc_part,
+                         dsm + kMcNrm, h.stream);
+    HIPCHECK(hipMemcpyAsync(hp + kMcNrm, dsm + kMcNrm, K * sizeof(double), hipMemcpyDeviceToHost,
+                            h.stream));
+    HIPCHECK(hipStreamSynchronize(h.stream));
+    out.assign(hp + kMcNrm, hp + kMcNrm + K);
+  };
+  auto upload_scale = [&](const std::vector<double>& sc) {
+    for (int c = 0; c < K; ++c) hp[kMcScale + c] = sc[c];
+    HIPCHECK(hipMemcpyAsync(dsm + kMcScale, hp + kMcScale, K * sizeof(double),
+                            hipMemcpyHostToDevice, h.stream));
+  };
+  std::vector<double> bnorm, beta, nrm, scale(K);
+  norms(b, bnorm);
+  for (int c = 0; c < K; ++c)
+    if (!std::isfinite(bnorm[c])) throw Fail{FSGMG_EINVAL, "right-hand side contains NaN or Inf"};
+  launch_fill<double>(x, 0.0, N * K, h.stream);
+  std::vector<int> iters(K, 0), restarts(K, 0), conv(K, 0);
+  std::vector<double> true_rel(K, NAN);
+  for (int c = 0; c < K; ++c)
+    if (bnorm[c] == 0.0) {
+      conv[c] = 1;
+      true_rel[c] = 0.0;
+    }
+  std::vector<double> H((size_t)K * (m + 1) * m), cs((size_t)K * m), sn((size_t)K * m),
+      g((size_t)K * (m + 1)), y((size_t)m * K);
+  std::vector<int> jc(K), done(K);
+  auto all_conv = [&] {
+    for (int c = 0; c < K; ++c)
+      if (!conv[c]) return false;
+    return true;
+  };
+  for (int cycle = 0; !all_conv() && cycle <= o.max_restarts; ++cycle) {
+    launch_spmm<double>(A, h.D, x, b, h.mc_w, K, true, h.stream);
+    norms(h.mc_w, beta);
+    for (int c = 0; c < K; ++c) {
+      if (!conv[c] && beta[c] <= o.rtol * bnorm[c]) {
+        conv[c] = 1;
+        true_rel[c] = beta[c] / bnorm[c];
+      }
+      done[c] = conv[c];
+      jc[c] = 0;
+      scale[c] = done[c] ? 0.0 : 1.0 / beta[c];
+      std::fill(H.begin() + (size_t)c * (m + 1) * m, H.begin() + (size_t)(c + 1) * (m + 1) * m, 0.0);
+      std::fill(g.begin() + (size_t)c * (m + 1), g.begin() + (size_t)(c + 1) * (m + 1), 0.0);
+      g[(size_t)c * (m + 1)] = beta[c];
+    }
+    if (all_conv()) break;
+    upload_scale(scale);
+    launch_mc_scale(N, K, dsm + kMcScale, h.mc_w, h.mc_V, h.stream);
+    for (int j = 0; j < m; ++j) {
+      bool any = false;
+      for (int c = 0; c < K; ++c) any |= !done[c];
+      if (!any) break;
+      double* Vj = h.mc_V + (int64_t)j * ld;
+      double* Zj = h.mc_Z + (int64_t)j * ld;
+      vcycle_mc(h, Vj, Zj, K);
+      launch_spmm<double>(A, h.D, Zj, nullptr, h.mc_w, K, false, h.stream);
+      launch_mc_mdot(h.mc_V, ld, j + 1, h.mc_w, N, K, h.mc_part, dsm + kMcH1, h.stream);
+      launch_mc_maxpy_mdot(h.mc_V, ld, j + 1, dsm + kMcH1, h.mc_w, N, K, h.mc_part, dsm + kMcH2,
+                           h.stream);
+      launch_mc_maxpy_norm(h.mc_V, ld, j + 1, dsm + kMcH2, h.mc_w, N, K, h.mc_part, dsm + kMcNrm,
+                           h.stream);
+      HIPCHECK(hipMemcpyAsync(hp, dsm, (size_t)(kMcNrm + K) * sizeof(double),
+                              hipMemcpyDeviceToHost, h.stream));
+      HIPCHECK(hipStreamSynchronize(h.stream));
+      for (int c = 0; c < K; ++c) {
+        scale[c] = 0.0;
+        if (done[c]) continue;
+        double* Hc = H.data() + (size_t)c * (m + 1) * m;
+        double* csc = cs.data() + (size_t)c * m;
+        double* snc = sn.data() + (size_t)c * m;
+        double* gc = g.data() + (size_t)c * (m + 1);
+        const double hn = hp[kMcNrm + c];
+        for (int i = 0; i <= j; ++i) Hc[i * m + j] = hp[kMcH1 + i * K + c] + hp[kMcH2 + i * K + c];
+        Hc[(j + 1) * m + j] = hn;
+        for (int i = 0; i < j; ++i) {
+          const double t = csc[i] * Hc[i * m + j] + snc[i] * Hc[(i + 1) * m + j];
+          Hc[(i + 1) * m + j] = -snc[i] * Hc[i * m + j] + csc[i] * Hc[(i + 1) * m + j];
+          Hc[i * m + j] = t;
+        }
+        const double den = std::hypot(Hc[j * m + j], Hc[(j + 1) * m + j]);
+        csc[j] = Hc[j * m + j] / den;
+        snc[j] = Hc[(j + 1) * m + j] / den;
+        Hc[j * m + j] = den;
+        Hc[(j + 1) * m + j] = 0.0;
+        gc[j + 1] = -snc[j] * gc[j];
+        gc[j] = csc[j] * gc[j];
+        ++iters[c];
+        jc[c] = j + 1;
+        const double est = std::fabs(gc[j + 1]);
+        if (!std::isfinite(est)) throw Fail{FSGMG_EINVAL, "non-finite residual estimate"};
+        if (est <= o.rtol * bnorm[c] || hn == 0.0)
+          done[c] = 1;
+        else
+          scale[c] = 1.0 / hn;
+      }
+      if (j + 1 < m) {
+        upload_scale(scale);
+        launch_mc_scale(N, K, dsm + kMcScale, h.mc_w, h.mc_V + (int64_t)(j + 1) * ld, h.stream);
+      }
+    }
+    // per-column least squares, then one K-column update of x
+    int kmax = 0;
+    std::fill(y.begin(), y.end(), 0.0);
+    for (int c = 0; c < K; ++c) {
+      if (conv[c]) continue;
+      const int k = jc[c];
+      kmax = std::max(kmax, k);
+      const double* Hc = H.data() + (size_t)c * (m + 1) * m;
+      const double* gc = g.data() + (size_t)c * (m + 1);
+      for (int i = k - 1; i >= 0; --i) {
+        double sum = gc[i];
+        for (int q = i + 1; q < k; ++q) sum -= Hc[i * m + q] * y[(size_t)q * K + c];
+        y[(size_t)i * K + c] = sum / Hc[i * m + i];
+      }
+    }
+    for (int i = 0; i < kmax; ++i)
+      for (int c = 0; c < K; ++c) hp[kMcY + i * K + c] = y[(size_t)i * K + c];
+    HIPCHECK(hipMemcpyAsync(dsm + kMcY, hp + kMcY, (size_t)kmax * K * sizeof(double),
+                            hipMemcpyHostToDevice, h.stream));
+    launch_mc_update(h.mc_Z, ld, kmax, dsm + kMcY, x, N, K, h.stream);
+    launch_spmm<double>(A, h.D, x, b, h.mc_w, K, true, h.stream);
+    std::vector<double> tn;
+    norms(h.mc_w, tn);
+    for (int c = 0; c < K; ++c) {
+      if (conv[c]) continue;
+      true_rel[c] = tn[c] / bnorm[c];
+      if (true_rel[c] <= o.rtol)
+        conv[c] = 1;
+      else
+        ++restarts[c];
+    }
+  }
+  HIPCHECK(hipGetLastError());
+  bool ok = true;
+  const double ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  for (int c = 0; c < K; ++c) {
+    ok &= conv[c] != 0;
+    if (infos) {
+      infos[c].iters = iters[c];
+      infos[c].restarts = restarts[c];
+      infos[c].converged = conv[c];
+      infos[c].rel_res_true = true_rel[c];
+      infos[c].history_len = 0;
+      infos[c].t_solve_ms = ms;
+    }
+  }
+  return ok ? FSGMG_OK : FSGMG_NOT_CONVERGED;
+}
+
 fsgmg_status fgmres(fsgmg_hierarchy& h, const double* b, double* x, const fsgmg_krylov_opts& o,
                     fsgmg_solve_info* info, bool transpose) {
   const auto t0 = std::chrono::steady_clock::now();
@@ -1832,6 +2041,22 @@ fsgmg_status vcycle_apply_batch(fsgmg_h h, const double* r, double* z, int k) {
     vcycle_mc(*h, r, z, k);
     HIPCHECK(hipGetLastError());
     return FSGMG_OK;
+  });
+}
+
+fsgmg_status gmres_solve_batch(fsgmg_h h, const double* b, double* x, int k,
+                               const fsgmg_krylov_opts* opts, fsgmg_solve_info* infos) {
+  if (!h || !b || !x || !opts || b == x) return FSGMG_EINVAL;
+  return guarded(h, [&]() -> fsgmg_status {
+    check_device(*h);
+    if (k < 1 || k > kMaxRhs) throw Fail{FSGMG_EINVAL, "k must be in 1..64"};
+    if (h->sopt.schwarz != FSGMG_SCHWARZ_ADDITIVE)
+      throw Fail{FSGMG_EINVAL, "several right-hand sides need the additive smoother"};
+    for (int l = 1; l < h->L; ++l)
+      if (h->dl[l].bv.max_n > kMaxRhsBlock)
+        throw Fail{FSGMG_EINVAL, "several right-hand sides: a Schwarz block exceeds " +
+                                     std::to_string(kMaxRhsBlock) + " unknowns"};
+    return fgmres_batch(*h, b, x, k, *opts, infos);
   });
 }
 

@@ -26,7 +26,7 @@ SWEEP_FORM = {"auto": 0, "spmv": 1, "fused": 2}
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
 
 EXPORTED = ["setup_hierarchy", "build_fs_as_blocks", "vcycle_apply", "vcycle_apply_batch",
-            "gmres_solve",
+            "gmres_solve", "gmres_solve_batch",
             "adjoint_solve", "assemble_load", "load_adjoint", "apply_operator", "param_grad",
             "update_params", "level_info", "export_csr", "export_vector", "export_blocks", "block_colours",
             "kernel_timing", "tuning_info", "last_error", "hierarchy_destroy"]
@@ -83,6 +83,7 @@ def lib():
             "build_fs_as_blocks": ([H, C.POINTER(SmootherOpts)], C.c_int),
             "vcycle_apply": ([H, P, P, C.c_int], C.c_int),
             "vcycle_apply_batch": ([H, P, P, C.c_int], C.c_int),
+            "gmres_solve_batch": ([H, P, P, C.c_int, C.POINTER(KrylovOpts), P], C.c_int),
             "gmres_solve": ([H, P, P, C.POINTER(KrylovOpts), C.POINTER(SolveInfo)], C.c_int),
             "adjoint_solve": ([H, P, P, C.POINTER(KrylovOpts), C.POINTER(SolveInfo)], C.c_int),
             "assemble_load": ([H, P, P], C.c_int),
@@ -226,6 +227,16 @@ def _solve(fn, h, b, x, restart, max_restarts, rtol, history_cap):
     return dict(converged=bool(info.converged), iters=info.iters, restarts=info.restarts,
                 rel_res_true=info.rel_res_true, history=hist[:n].copy(),
                 t_solve_ms=info.t_solve_ms, status=STATUS[st])
+
+
+def gmres_solve_batch(h, b, x, k, restart=30, max_restarts=20, rtol=1e-10):
+    o = KrylovOpts(int(restart), int(max_restarts), float(rtol))
+    infos = (SolveInfo * int(k))()
+    st = lib().gmres_solve_batch(h, _ptr(b), _ptr(x), int(k), C.byref(o),
+                                 C.cast(infos, C.c_void_p))
+    _check(h, st, allow_not_converged=True)
+    return [dict(converged=bool(i.converged), iters=i.iters, restarts=i.restarts,
+                 rel_res_true=i.rel_res_true, t_solve_ms=i.t_solve_ms) for i in infos]
 
 
 def gmres_solve(h, b, x, restart=30, max_restarts=20, rtol=1e-10, history_cap=1024):
@@ -403,6 +414,18 @@ class Hierarchy:
 
     def gmres_solve(self, b, x, **kw):
         return gmres_solve(self.h, self._vec(b), self._vec(x), **kw)
+
+    def gmres_solve_batch(self, b, x, **kw):
+        """FGMRES on the columns of b ((N, k) float64 device tensors)."""
+        import torch
+        for t in (b, x):
+            if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
+                raise TypeError("expected float64 device tensors")
+            if t.dim() != 2 or t.shape[0] != self.N or not t.is_contiguous():
+                raise ValueError("expected contiguous (N, k) tensors with N = %d" % self.N)
+        if b.shape != x.shape:
+            raise ValueError("b and x must have the same shape")
+        return gmres_solve_batch(self.h, b, x, b.shape[1], **kw)
 
     def adjoint_solve(self, c, lam, **kw):
         return adjoint_solve(self.h, self._vec(c), self._vec(lam), **kw)

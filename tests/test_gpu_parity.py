@@ -294,6 +294,53 @@ def test_vcycle_batch_parity(key, cycle):
     H.close()
 
 
+@pytest.mark.parametrize("key,k", [("c1", 5), ("c2L3", 32), ("chan3d", 17)])
+def test_gmres_solve_batch(key, k):
+    """FGMRES on k loads at once (gmres_solve_batch, FP32 cycle): every column
+    converges to a true 1e-10 (recomputed with the oracle's matrix), in the
+    iteration count of its one-column solve (+-1), and agrees with that
+    solve's solution; a zero column and a repeated column are handled."""
+    import tests.cfgs as cfgs
+    if key == "c1":
+        cfg = inputs.config("c1")
+    elif key == "chan3d":
+        cfg = cfgs.channel3d(levels=2, nc=(2, 2, 2))
+    else:
+        cfg = inputs.with_levels(inputs.config("c2"), 3)
+    w = None if key == "chan3d" else inputs.advecting_field(cfg)
+    O = OracleHierarchy(cfg, w, build_smoothers=False)
+    H = fsgmg.Hierarchy(cfg, w, device=0)
+    H.build_fs_as_blocks(prec="fp32")
+    rng = np.random.default_rng(29)
+    Bh = np.column_stack([O.rhs(inputs.body_force(cfg, seed=s)) for s in range(k)])
+    Bh[:, 1] = 0.0                        # a zero load
+    Bh[:, 2] = Bh[:, 0]                   # a repeated load
+    Bh[:, 3] *= 1e-6                      # a small one
+    Bd = dev(Bh.ravel()).reshape(H.N, k).contiguous()
+    Xd = torch.zeros_like(Bd)
+    infos = H.gmres_solve_batch(Bd, Xd, rtol=1e-10)
+    Xh = host(Xd.reshape(-1)).reshape(H.N, k)
+    A = O.A[-1]
+    x1 = torch.zeros(H.N, dtype=torch.float64, device="cuda")
+    for c in range(k):
+        bn = np.linalg.norm(Bh[:, c])
+        if bn == 0.0:
+            assert infos[c]["converged"] and np.all(Xh[:, c] == 0.0)
+            continue
+        true = np.linalg.norm(Bh[:, c] - A @ Xh[:, c]) / bn
+        one = H.gmres_solve(dev(np.ascontiguousarray(Bh[:, c])), x1, rtol=1e-10)
+        xs = host(x1)
+        d = np.linalg.norm(Xh[:, c] - xs) / np.linalg.norm(xs)
+        if c < 5 or c == k - 1:
+            say("[gmres batch]", key, "col", c, "iters", infos[c]["iters"], "one-column", one["iters"],
+                "true %.2e" % true, "diff %.2e" % d)
+        assert infos[c]["converged"] and true <= 1e-10
+        assert abs(infos[c]["iters"] - one["iters"]) <= 1
+        assert d <= 1e-7
+    assert np.array_equal(Xh[:, 0], Xh[:, 2])
+    H.close()
+
+
 @pytest.mark.parametrize("kind", ["W", "F"])
 def test_w_and_f_cycles_parity(kind):
     """W- and F-cycles (c2 at 3 levels): FP64 cycle and its transpose against
