@@ -77,6 +77,31 @@ def mc_smoother_model(H, level, prec, K):
     return nbytes, flops
 
 
+def mrhs_solves(H, cfg, K, steps, rtol, dev):
+    """FGMRES on K seeded loads at once (gmres_solve_batch): solves/s over all
+    columns, iterations and the worst true relative residual."""
+    import torch
+    from paper_1909_13201_amd import inputs
+    Bm = torch.zeros((H.N, K), dtype=torch.float64, device=dev)
+    bc = torch.zeros(H.N, dtype=torch.float64, device=dev)
+    for c in range(K):
+        f = inputs.body_force(cfg, seed=1000 + c)
+        H.assemble_load(torch.tensor(f.ravel(), dtype=torch.float64, device=dev), bc)
+        Bm[:, c] = bc
+    Xm = torch.zeros_like(Bm)
+    H.gmres_solve_batch(Bm, Xm, rtol=rtol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        infos = H.gmres_solve_batch(Bm, Xm, rtol=rtol)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    return dict(solves_per_s=round(K * steps / t, 2), ms_per_call=round(1e3 * t / steps, 3),
+                iters_max=max(i["iters"] for i in infos), iters_min=min(i["iters"] for i in infos),
+                all_converged=all(i["converged"] for i in infos),
+                worst_rel_res_true=max(i["rel_res_true"] for i in infos))
+
+
 def mrhs_measure(H, K, calls, prec, dev):
     """K-column cycles: calls/s, column-cycles/s and the finest-level block
     apply (HIP events on the handle stream) against HBM and matrix-core peaks."""
@@ -388,6 +413,11 @@ def main():
     for K in (8, 32, 64):
         mrhs[str(K)] = mrhs_measure(H, K, max(5, args.steps), "fp32", dev)
         mrhs[str(K)]["over_one_column"] = round(mrhs[str(K)]["column_cycles_per_s"] / (nv / tv), 2)
+    # FGMRES on K loads at once against one-load solves
+    msol = {}
+    for K in (8, 32):
+        msol[str(K)] = mrhs_solves(H, cfg, K, max(2, args.steps // 3), rtol, dev)
+        msol[str(K)]["over_one_load"] = round(msol[str(K)]["solves_per_s"] / (args.steps / t32), 2)
     # adjoint solve (mixed)
     c = torch.zeros_like(b)
     c[H.info[-1]["off_u"]:H.info[-1]["off_u"] + 2 * H.info[-1]["N2"]:2] = 1.0
@@ -452,7 +482,7 @@ def main():
                            core=list(cfg["core"]), halo=cfg["halo"], cycle=cfg["cycle"],
                            restart=30, rtol=rtol),
                fp64_solves_per_s=round(sps64, 4), mixed_over_fp64=round(sps32 / sps64, 3),
-               vcycles_per_s=round(nv / tv, 2), multi_rhs_vcycles=mrhs,
+               vcycles_per_s=round(nv / tv, 2), multi_rhs_vcycles=mrhs, multi_rhs_solves=msol,
                iters_mixed=inf32[-1]["iters"],
                iters_fp64=inf64[-1]["iters"], rel_res_true_mixed=inf32[-1]["rel_res_true"],
                rel_res_true_fp64=inf64[-1]["rel_res_true"], rel_diff_mixed_vs_fp64=rel_diff,

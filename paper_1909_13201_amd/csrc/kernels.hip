@@ -1850,7 +1850,7 @@ __global__ __launch_bounds__(kMcThreads) void k_smooth_mc(BlocksView B, const TW
 // own dot products; partial sums per workgroup in a fixed order, then one
 // fixed-order reduction per (vector, column)
 // ------------------------------------------------------------------------
-constexpr int kMcParts = 512;     // workgroups of the K-column reductions
+constexpr int kMcParts = 1024;    // workgroups of the K-column reductions
 constexpr int kMcSlots = 64;      // column slots per wave (K <= 64)
 
 // mode 0: part <- dots of w with V_0..V_{nv-1};  mode 1: w -= V h, then dots
@@ -1862,8 +1862,13 @@ __global__ __launch_bounds__(kThreads) void k_mc_dots(int mode, const double* __
                                                       double* __restrict__ w, int64_t N, int K,
                                                       double* __restrict__ part) {
   extern __shared__ double red[];   // kThreads / 64 waves x kMaxK x kMcSlots
-  const int c = threadIdx.x & 63, wv = threadIdx.x >> 6;
   constexpr int NW = kThreads / 64;
+  // lane = (row within the wave) * Kp + column, Kp = K rounded up to a power
+  // of two: every lane of a wave works when K < 64
+  int Kp = 1;
+  while (Kp < K) Kp *= 2;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int c = lane % Kp, rs = lane / Kp, R = 64 / Kp;
   double acc[kMaxK];
 #pragma unroll
   for (int i = 0; i < kMaxK; ++i) acc[i] = 0.0;
@@ -1871,7 +1876,8 @@ __global__ __launch_bounds__(kThreads) void k_mc_dots(int mode, const double* __
 #pragma unroll
   for (int i = 0; i < kMaxK; ++i) hc[i] = (mode != 0 && i < nv && c < K) ? h[i * K + c] : 0.0;
   if (c < K) {
-    for (int64_t r = (int64_t)blockIdx.x * NW + wv; r < N; r += (int64_t)gridDim.x * NW) {
+    const int64_t stride = (int64_t)gridDim.x * NW * R;
+    for (int64_t r = ((int64_t)blockIdx.x * NW + wv) * R + rs; r < N; r += stride) {
       const int64_t e = r * K + c;
       double wr = w[e];
       if (mode != 0 && nv > 0) {
@@ -1890,12 +1896,18 @@ __global__ __launch_bounds__(kThreads) void k_mc_dots(int mode, const double* __
     }
   }
   const int nout = mode == 2 ? 1 : nv;
-  for (int i = 0; i < nout; ++i) red[(wv * kMaxK + i) * kMcSlots + c] = acc[i];
+  // rows of the wave -> one sum per column (fixed butterfly over the row lanes)
+  for (int i = 0; i < nout; ++i) {
+    double v = acc[i];
+    for (int o = Kp; o < 64; o *= 2) v += __shfl_xor(v, o);
+    if (rs == 0) red[(wv * kMaxK + i) * kMcSlots + c] = v;
+  }
   __syncthreads();
   for (int t = threadIdx.x; t < nout * kMcSlots; t += blockDim.x) {
     const int i = t / kMcSlots, cc = t - i * kMcSlots;
     double s2 = 0.0;
-    for (int q = 0; q < NW; ++q) s2 += red[(q * kMaxK + i) * kMcSlots + cc];
+    if (cc < Kp)
+      for (int q = 0; q < NW; ++q) s2 += red[(q * kMaxK + i) * kMcSlots + cc];
     part[((int64_t)blockIdx.x * kMaxK + i) * kMcSlots + cc] = s2;
   }
 }
