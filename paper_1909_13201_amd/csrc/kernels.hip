@@ -1953,6 +1953,13 @@ __global__ __launch_bounds__(kThreads) void k_mc_update(const double* __restrict
   x[e] += s;
 }
 
+// dst[i] = src[i] for i < n, dst being pinned host memory mapped into the
+// device's address space (a kernel node instead of a copy node in a graph)
+__global__ __launch_bounds__(64) void k_store_host(const double* __restrict__ src,
+                                                   double* __restrict__ dst, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+}
+
 }  // namespace
 
 // ========================================================================
@@ -2405,6 +2412,10 @@ void launch_mc_update(const double* Z, int64_t ld, int nv, const double* y, doub
   if (n > 0 && nv > 0)
     hipLaunchKernelGGL(k_mc_update, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, s, Z, ld, nv, y,
                        x, n, K);
+}
+
+void launch_store_host(const double* src, double* dst_mapped, int n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_store_host, dim3(1), dim3(64), 0, s, src, dst_mapped, n);
 }
 
 int krylov_partials() { return kPartials * kMaxK; }

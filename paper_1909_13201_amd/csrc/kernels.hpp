@@ -181,6 +181,11 @@ template <typename TV>
 void launch_smooth_mc(const BlocksView& B, WPrec wp, const void* W, const TV* R, TV* X, int K,
                       double omega, bool first, hipStream_t s);
 
+// dst_mapped[i] = src[i], i < n: dst_mapped is the device address of pinned
+// host memory (hipHostGetDevicePointer); the host reads it after the stream
+// has passed the launch
+void launch_store_host(const double* src, double* dst_mapped, int n, hipStream_t s);
+
 // ---- K-column Krylov (FP64, K <= 64 unknown-major columns; basis vector i
 // of a K-column block at V + i * ld; h, out: nv x K, entry (i, c) at i * K + c;
 // `part` holds krylov_mc_partials() doubles; fixed-order reductions) ----

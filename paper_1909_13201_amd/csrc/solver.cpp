@@ -352,6 +352,8 @@ struct fsgmg_hierarchy {
   }
   double* tmp = nullptr;
   double* pinned = nullptr;
+  double* pinned_dev = nullptr;   // device address of `pinned`
+  hipEvent_t step_done[2] = {nullptr, nullptr};   // read-back of Arnoldi steps of each parity
   // K-column FGMRES workspace: basis / preconditioned vectors (ld_mc per
   // K-column block), work block, partial sums, small device arrays and their
   // pinned host mirror
@@ -427,6 +429,8 @@ struct fsgmg_hierarchy {
         if (d.fp.done) (void)hipEventDestroy(d.fp.done);
       }
       if (factor_start) (void)hipEventDestroy(factor_start);
+      for (hipEvent_t e : step_done)
+        if (e) (void)hipEventDestroy(e);
       for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
       invalidate_graphs();
       if (cap_stream) (void)hipStreamDestroy(cap_stream);
@@ -1383,7 +1387,12 @@ void vcycle_mc(fsgmg_hierarchy& h, const double* r, double* z, int K) {
 void ensure_reduction_buffers(fsgmg_hierarchy& h) {
   if (!h.part) h.part = h.zeros<double>(krylov_partials());
   if (!h.small) h.small = h.zeros<double>(256);
-  if (!h.pinned) HIPCHECK(hipHostMalloc((void**)&h.pinned, 256 * sizeof(double), hipHostMallocDefault));
+  for (hipEvent_t& e : h.step_done)
+    if (!e) HIPCHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  if (!h.pinned) {
+    HIPCHECK(hipHostMalloc((void**)&h.pinned, 256 * sizeof(double), hipHostMallocMapped));
+    HIPCHECK(hipHostGetDevicePointer((void**)&h.pinned_dev, h.pinned, 0));
+  }
 }
 
 void ensure_workspace(fsgmg_hierarchy& h, int m) {
@@ -1409,16 +1418,22 @@ double device_norm(fsgmg_hierarchy& h, const double* v, int64_t N) {
 // Enqueue Arnoldi step j: v_j = w / ||w|| (j > 0), z_j = M^{-1} v_j,
 // w = A z_j, two classical Gram-Schmidt passes and ||w||; the Hessenberg
 // column pieces [h1 | h2 | ||w||] are copied to pinned host memory.
+// Step j leaves h1, h2 and ||w|| in the device / pinned area of its parity
+// (small and pinned at step_area(j)), so step j + 1 can be queued before the
+// host has read step j's values; v_j is normalized with ||w|| of step j - 1.
+constexpr int kStepArea = 160;
+inline int step_area(int j) { return (j & 1) ? kStepArea : 0; }
+
 void arnoldi_step(fsgmg_hierarchy& h, int j, bool transpose) {
   DLevel& F = h.dl[h.L - 1];
   const int64_t N = F.N, ld = h.ld;
   const BOpView<double>& A = transpose ? F.AT.v64 : F.A.v64;
-  double* const h1 = h.small;
-  double* const h2 = h.small + 32;
-  double* const nr = h.small + 64;
+  double* const h1 = h.small + step_area(j);
+  double* const h2 = h1 + 32;
+  double* const nr = h1 + 64;
   double* vj = h.V + (int64_t)j * ld;
   double* zj = h.Z + (int64_t)j * ld;
-  if (j > 0) launch_scale_copy(h.w, nr, vj, N, h.stream);
+  if (j > 0) launch_scale_copy(h.w, h.small + step_area(j - 1) + 64, vj, N, h.stream);
   vcycle(h, vj, zj, transpose);
   {
     TimedLaunch t(h, 2, true);
@@ -1427,7 +1442,7 @@ void arnoldi_step(fsgmg_hierarchy& h, int j, bool transpose) {
   launch_mdot(h.V, ld, j + 1, h.w, N, h.part, h1, h.stream);
   launch_maxpy_mdot(h.V, ld, j + 1, h1, h.w, N, h.part, h2, h.stream);
   launch_maxpy_norm(h.V, ld, j + 1, h2, h.w, N, h.part, nr, h.stream);
-  HIPCHECK(hipMemcpyAsync(h.pinned, h.small, 65 * sizeof(double), hipMemcpyDeviceToHost, h.stream));
+  launch_store_host(h1, h.pinned_dev + step_area(j), 65, h.stream);
 }
 
 void run_arnoldi_step(fsgmg_hierarchy& h, int j, bool transpose) {
@@ -1642,6 +1657,10 @@ fsgmg_status fgmres_batch(fsgmg_hierarchy& h, const double* b, double* x, int K,
   return ok ? FSGMG_OK : FSGMG_NOT_CONVERGED;
 }
 
+// An Arnoldi step is queued ahead of the host's read-back of the previous one
+// while the last residual estimate exceeds kSpeculate times the target.
+constexpr double kSpeculate = 1e3;
+
 fsgmg_status fgmres(fsgmg_hierarchy& h, const double* b, double* x, const fsgmg_krylov_opts& o,
                     fsgmg_solve_info* info, bool transpose) {
   const auto t0 = std::chrono::steady_clock::now();
@@ -1681,11 +1700,24 @@ fsgmg_status fgmres(fsgmg_hierarchy& h, const double* b, double* x, const fsgmg_
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
     int k = 0;
+    int queued = -1;          // last Arnoldi step enqueued
+    double last_est = beta;   // latest residual estimate known on the host
     for (int j = 0; j < m; ++j) {
-      run_arnoldi_step(h, j, transpose);
-      HIPCHECK(hipStreamSynchronize(h.stream));
-      const double hn = h.pinned[64];
-      for (int i = 0; i <= j; ++i) H[i * m + j] = h.pinned[i] + h.pinned[32 + i];
+      if (queued < j) {
+        run_arnoldi_step(h, j, transpose);
+        queued = j;
+      }
+      HIPCHECK(hipEventRecord(h.step_done[j & 1], h.stream));
+      // queue step j + 1 before reading step j back while convergence is
+      // still far off (a step queued past convergence is wasted work only)
+      if (j + 1 < m && last_est > kSpeculate * o.rtol * bnorm) {
+        run_arnoldi_step(h, j + 1, transpose);
+        queued = j + 1;
+      }
+      HIPCHECK(hipEventSynchronize(h.step_done[j & 1]));
+      const double* pv = h.pinned + step_area(j);
+      const double hn = pv[64];
+      for (int i = 0; i <= j; ++i) H[i * m + j] = pv[i] + pv[32 + i];
       H[(j + 1) * m + j] = hn;
       for (int i = 0; i < j; ++i) {
         const double t = cs[i] * H[i * m + j] + sn[i] * H[(i + 1) * m + j];
@@ -1704,6 +1736,7 @@ fsgmg_status fgmres(fsgmg_hierarchy& h, const double* b, double* x, const fsgmg_
       const double est = std::fabs(g[j + 1]);
       hist.push_back(est / bnorm);
       if (!std::isfinite(est)) throw Fail{FSGMG_EINVAL, "non-finite residual estimate"};
+      last_est = est;
       if (est <= o.rtol * bnorm || hn == 0.0) break;
     }
     for (int i = k - 1; i >= 0; --i) {
