@@ -533,6 +533,56 @@ def test_full_size_c2_bench_configuration():
     H.close()
 
 
+def test_full_size_c2_multiplicative_and_k_loads():
+    """c2 at full size (5 levels, 281,095 unknowns): the multicolour
+    multiplicative FP64 cycle against the oracle's sequential sweep (same
+    colour order), an FP32 multiplicative solve, and FGMRES on 32 seeded
+    loads at once (K-column cycle on the matrix cores) whose every column
+    reaches a true 1e-10 with the oracle's matrix in the iteration count of
+    its one-load solve (sampled columns)."""
+    cfg = dict(inputs.config("c2"), schwarz="multiplicative")
+    w = inputs.advecting_field(cfg)
+    say("[full c2 mult] oracle setup")
+    O = OracleHierarchy(cfg, w)
+    H = fsgmg.Hierarchy(cfg, w, device=0)
+    H.build_fs_as_blocks(prec="fp64")
+    rng = np.random.default_rng(31)
+    r = rng.standard_normal(H.N)
+    z = torch.zeros(H.N, dtype=torch.float64, device="cuda")
+    H.vcycle_apply(dev(r), z)
+    ref = O.vcycle(r)
+    err = np.linalg.norm(host(z) - ref) / np.linalg.norm(ref)
+    say("   multiplicative fp64 cycle rel err %.3e" % err)
+    assert err <= 1e-9
+    A = O.A[-1]
+    b = O.rhs(inputs.body_force(cfg))
+    H.build_fs_as_blocks(prec="fp32")
+    x = torch.zeros(H.N, dtype=torch.float64, device="cuda")
+    info = H.gmres_solve(dev(b), x, rtol=1e-10)
+    true = np.linalg.norm(b - A @ host(x)) / np.linalg.norm(b)
+    say("   multiplicative fp32 iters", info["iters"], "true %.2e" % true)
+    assert info["converged"] and true <= 1e-10
+    K = 32
+    H.build_fs_as_blocks(prec="fp32", schwarz="additive")
+    Bh = np.column_stack([O.rhs(inputs.body_force(cfg, seed=100 + c)) for c in range(K)])
+    Bd = dev(Bh.ravel()).reshape(H.N, K).contiguous()
+    Xd = torch.zeros_like(Bd)
+    infos = H.gmres_solve_batch(Bd, Xd, rtol=1e-10)
+    Xh = host(Xd.reshape(-1)).reshape(H.N, K)
+    worst = 0.0
+    for c in range(K):
+        t = np.linalg.norm(Bh[:, c] - A @ Xh[:, c]) / np.linalg.norm(Bh[:, c])
+        worst = max(worst, t)
+        assert infos[c]["converged"] and t <= 1e-10
+    x1 = torch.zeros(H.N, dtype=torch.float64, device="cuda")
+    for c in (0, K - 1):
+        one = H.gmres_solve(dev(np.ascontiguousarray(Bh[:, c])), x1, rtol=1e-10)
+        assert abs(infos[c]["iters"] - one["iters"]) <= 1
+    say("   %d loads: iters %d..%d, worst true %.2e" % (K, min(i["iters"] for i in infos),
+                                                         max(i["iters"] for i in infos), worst))
+    H.close()
+
+
 def test_c3_enlarged_interface_blocks_parity():
     """c3 (bulge geometry, layered walls, 4 x 12 interface cores) at 4
     levels: uneven blocks in one launch; FP64 V-cycle against the oracle's,
