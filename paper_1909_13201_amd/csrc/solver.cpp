@@ -1769,22 +1769,25 @@ fsgmg_status fgmres(fsgmg_hierarchy& h, const double* b, double* x, const fsgmg_
   return converged ? FSGMG_OK : FSGMG_NOT_CONVERGED;
 }
 
-// Launch-shape autotuner: for every level time the V-cycle SpMV with 4, 8
-// and 16 lanes per row and the smoother sweep with 256, 512 and 1024-thread
-// workgroups (HIP events on the handle's stream, best of the averages of
-// three launches after one warm-up), and the outer FP64 product's lanes.
+// Launch-shape autotuner: for every level time the V-cycle SpMV with 1 to 16
+// lanes per row, the transfers' lanes, the smoother sweep with 256, 512 and
+// 1024-thread workgroups (and several workgroups per block where blocks are
+// few), the fused against the SpMV form of a sweep (HIP events on the
+// handle's stream, best of the averages of ten launches after one warm-up),
+// and the outer FP64 product's lanes.
 template <typename F>
 float time_launch(fsgmg_hierarchy& h, F&& f) {
+  constexpr int kReps = 10;   // enough launches that clock ramps and jitter average out
   hipEvent_t a = h.next_event(), b = h.next_event();
   f();
   HIPCHECK(hipEventRecord(a, h.stream));
-  for (int i = 0; i < 3; ++i) f();
+  for (int i = 0; i < kReps; ++i) f();
   HIPCHECK(hipEventRecord(b, h.stream));
   HIPCHECK(hipEventSynchronize(b));
   float ms = 0.f;
   HIPCHECK(hipEventElapsedTime(&ms, a, b));
   h.ev_used -= 2;
-  return ms / 3.f;
+  return ms / kReps;
 }
 
 template <typename TV>
