@@ -1960,6 +1960,29 @@ __global__ __launch_bounds__(64) void k_store_host(const double* __restrict__ sr
   for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
 }
 
+// Column permutation that undoes the coarse factorization's row
+// interchanges (applied in reverse order of the pivot steps): one thread
+// walks the pivot list with the permutation held in LDS.
+__global__ __launch_bounds__(64) void k_coarse_sigma(const int32_t* __restrict__ piv, int64_t np,
+                                                     int32_t* __restrict__ sig) {
+  extern __shared__ int32_t sp[];   // np permutation entries, then np pivots
+  int32_t* pv = sp + np;
+  for (int64_t c = threadIdx.x; c < np; c += blockDim.x) {
+    sp[c] = (int32_t)c;
+    pv[c] = piv[c];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int64_t c = np - 1; c >= 0; --c) {
+      const int32_t p = pv[c];
+      const int32_t t = sp[c];
+      sp[c] = sp[p];
+      sp[p] = t;
+    }
+  __syncthreads();
+  for (int64_t c = threadIdx.x; c < np; c += blockDim.x) sig[c] = sp[c];
+}
+
 }  // namespace
 
 // ========================================================================
@@ -2416,6 +2439,11 @@ void launch_mc_update(const double* Z, int64_t ld, int nv, const double* y, doub
 
 void launch_store_host(const double* src, double* dst_mapped, int n, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_store_host, dim3(1), dim3(64), 0, s, src, dst_mapped, n);
+}
+
+size_t coarse_sigma_lds(int64_t np) { return (size_t)np * 2 * sizeof(int32_t); }
+void launch_coarse_sigma(const int32_t* piv, int64_t np, int32_t* sig, hipStream_t s) {
+  hipLaunchKernelGGL(k_coarse_sigma, dim3(1), dim3(64), coarse_sigma_lds(np), s, piv, np, sig);
 }
 
 int krylov_partials() { return kPartials * kMaxK; }

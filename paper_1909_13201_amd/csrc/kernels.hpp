@@ -250,6 +250,10 @@ void launch_extract_owned(const int32_t* jlist, int64_t nb, const BlocksView& B,
 // a[:, sigma[q]]), launch_coarse_finish writes the n x n inverse and its
 // transpose.
 int coarse_panel_width(int64_t np, int max_lds);
+// sigma from the pivot list on the device (one workgroup, coarse_sigma_lds(np)
+// bytes of LDS)
+size_t coarse_sigma_lds(int64_t np);
+void launch_coarse_sigma(const int32_t* piv, int64_t np, int32_t* sig, hipStream_t s);
 void launch_coarse_factor(int64_t n, int64_t np, const int64_t* rp, const int32_t* col,
                           const double* val, double* a, double* ybuf, int32_t* piv,
                           int32_t* status, int nb, hipStream_t s);

@@ -299,6 +299,9 @@ struct fsgmg_hierarchy {
   std::vector<void*> allocs;
   std::vector<DLevel> dl;
   double* coarse_inv = nullptr;
+  hipStream_t coarse_stream = nullptr;   // asynchronous coarse rebuilds
+  hipEvent_t coarse_in = nullptr, coarse_done = nullptr;
+  bool coarse_pending = false;
   double* coarse_invT = nullptr;
   double* coarse_work = nullptr;
   int32_t* coarse_piv = nullptr;
@@ -428,6 +431,12 @@ struct fsgmg_hierarchy {
         if (d.fp.stream) (void)hipStreamDestroy(d.fp.stream);
         if (d.fp.done) (void)hipEventDestroy(d.fp.done);
       }
+      if (coarse_stream) {
+        (void)hipStreamSynchronize(coarse_stream);
+        (void)hipStreamDestroy(coarse_stream);
+      }
+      if (coarse_in) (void)hipEventDestroy(coarse_in);
+      if (coarse_done) (void)hipEventDestroy(coarse_done);
       if (factor_start) (void)hipEventDestroy(factor_start);
       for (hipEvent_t e : step_done)
         if (e) (void)hipEventDestroy(e);
@@ -597,7 +606,24 @@ void upload_transfer(fsgmg_hierarchy& h, int l) {
 
 // dense FP64 copy of the coarse-level matrix, inverted on the device; the
 // transpose of the inverse is kept for the transposed V-cycle
-void build_coarse_inverse(fsgmg_hierarchy& h) {
+// Wait for a coarse inverse built on the coarse stream and check that the
+// coarse matrix was not singular (every cycle entry point calls this).
+void ensure_coarse(fsgmg_hierarchy& h) {
+  if (!h.coarse_pending) return;
+  HIPCHECK(hipEventSynchronize(h.coarse_done));
+  h.coarse_pending = false;
+  int32_t st = 0;
+  const int64_t np = (h.ops[0].A.nrows + 15) & ~(int64_t)15;
+  HIPCHECK(hipMemcpy(&st, h.coarse_piv + 2 * np, sizeof(int32_t), hipMemcpyDeviceToHost));
+  if (st) throw Fail{FSGMG_ESINGULAR, "coarse-level matrix is singular"};
+}
+
+// Dense FP64 inverse of the level-0 operator from its device CSR.  With
+// `async` the work runs on the coarse stream (after the handle stream's work
+// so far) and the call returns at once: the factorization is one long chain
+// of panel steps that leaves most of the GPU idle, so it overlaps the block
+// factorization that follows a parameter update; ensure_coarse joins it.
+void build_coarse_inverse(fsgmg_hierarchy& h, bool async = false) {
   const int64_t n = h.ops[0].A.nrows;
   if (n > 20000) throw Fail{FSGMG_EINVAL, "coarse level too large for the dense inverse (n > 20000)"};
   const int64_t np = (n + 15) & ~(int64_t)15;
@@ -613,8 +639,26 @@ void build_coarse_inverse(fsgmg_hierarchy& h) {
     h.coarse_piv = (int32_t*)h.dalloc((size_t)(2 * np + 1) * sizeof(int32_t));
   }
   int32_t* status = h.coarse_piv + 2 * np;
-  HIPCHECK(hipMemsetAsync(status, 0, sizeof(int32_t), h.stream));
   const DLevel& C = h.dl[0];   // device CSR of level 0 (current parameter values)
+  int32_t* dsig = h.coarse_piv + np;
+  if (async && coarse_sigma_lds(np) <= (size_t)max_lds) {
+    if (!h.coarse_stream) HIPCHECK(hipStreamCreateWithFlags(&h.coarse_stream, hipStreamNonBlocking));
+    if (!h.coarse_done) HIPCHECK(hipEventCreateWithFlags(&h.coarse_done, hipEventDisableTiming));
+    if (!h.coarse_in) HIPCHECK(hipEventCreateWithFlags(&h.coarse_in, hipEventDisableTiming));
+    HIPCHECK(hipEventRecord(h.coarse_in, h.stream));
+    HIPCHECK(hipStreamWaitEvent(h.coarse_stream, h.coarse_in, 0));
+    HIPCHECK(hipMemsetAsync(status, 0, sizeof(int32_t), h.coarse_stream));
+    launch_coarse_factor(n, np, C.rp, C.col, C.val, h.coarse_work, h.coarse_work + np * np,
+                         h.coarse_piv, status, nb, h.coarse_stream);
+    launch_coarse_sigma(h.coarse_piv, np, dsig, h.coarse_stream);
+    launch_coarse_finish(h.coarse_work, np, n, dsig, h.coarse_inv, h.coarse_invT, h.coarse_stream);
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipEventRecord(h.coarse_done, h.coarse_stream));
+    h.coarse_pending = true;
+    h.n0 = n;
+    return;
+  }
+  HIPCHECK(hipMemsetAsync(status, 0, sizeof(int32_t), h.stream));
   launch_coarse_factor(n, np, C.rp, C.col, C.val, h.coarse_work, h.coarse_work + np * np,
                        h.coarse_piv, status, nb, h.stream);
   HIPCHECK(hipGetLastError());
@@ -628,7 +672,6 @@ void build_coarse_inverse(fsgmg_hierarchy& h) {
   std::vector<int32_t> sig(np);
   for (int64_t c = 0; c < np; ++c) sig[c] = (int32_t)c;
   for (int64_t c = np - 1; c >= 0; --c) std::swap(sig[c], sig[piv[c]]);
-  int32_t* dsig = h.coarse_piv + np;
   HIPCHECK(hipMemcpyAsync(dsig, sig.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, h.stream));
   launch_coarse_finish(h.coarse_work, np, n, dsig, h.coarse_inv, h.coarse_invT, h.stream);
   HIPCHECK(hipGetLastError());
@@ -2056,6 +2099,7 @@ fsgmg_status vcycle_apply(fsgmg_h h, const double* r, double* z, int transpose) 
     check_device(*h);
     if (!h->factors_valid) throw Fail{FSGMG_ESTATE, "build_fs_as_blocks has not been called"};
     if (transpose) ensure_transposed(*h);
+    ensure_coarse(*h);
     vcycle(*h, r, z, transpose != 0);
     HIPCHECK(hipGetLastError());
     return FSGMG_OK;
@@ -2074,6 +2118,7 @@ fsgmg_status vcycle_apply_batch(fsgmg_h h, const double* r, double* z, int k) {
       if (h->dl[l].bv.max_n > kMaxRhsBlock)
         throw Fail{FSGMG_EINVAL, "several right-hand sides: a Schwarz block exceeds " +
                                      std::to_string(kMaxRhsBlock) + " unknowns"};
+    ensure_coarse(*h);
     vcycle_mc(*h, r, z, k);
     HIPCHECK(hipGetLastError());
     return FSGMG_OK;
@@ -2092,6 +2137,7 @@ fsgmg_status gmres_solve_batch(fsgmg_h h, const double* b, double* x, int k,
       if (h->dl[l].bv.max_n > kMaxRhsBlock)
         throw Fail{FSGMG_EINVAL, "several right-hand sides: a Schwarz block exceeds " +
                                      std::to_string(kMaxRhsBlock) + " unknowns"};
+    ensure_coarse(*h);
     return fgmres_batch(*h, b, x, k, *opts, infos);
   });
 }
@@ -2101,6 +2147,7 @@ fsgmg_status gmres_solve(fsgmg_h h, const double* b, double* x, const fsgmg_kryl
   if (!h || !b || !x || !opts || b == x) return FSGMG_EINVAL;
   return guarded(h, [&]() -> fsgmg_status {
     check_device(*h);
+    ensure_coarse(*h);
     return fgmres(*h, b, x, *opts, info, false);
   });
 }
@@ -2110,6 +2157,7 @@ fsgmg_status adjoint_solve(fsgmg_h h, const double* c, double* lam, const fsgmg_
   if (!h || !c || !lam || !opts || c == lam) return FSGMG_EINVAL;
   return guarded(h, [&]() -> fsgmg_status {
     check_device(*h);
+    ensure_coarse(*h);
     return fgmres(*h, c, lam, *opts, info, true);
   });
 }
@@ -2195,6 +2243,8 @@ fsgmg_status update_params(fsgmg_h h, double E, double mu) {
       h->ensure_host_values();
       return FSGMG_OK;
     }
+    // a coarse rebuild still in flight reads the level-0 values
+    if (h->coarse_pending) HIPCHECK(hipStreamWaitEvent(h->stream, h->coarse_done, 0));
     for (int l = 0; l < h->L; ++l) {
       DLevel& d = h->dl[l];
       launch_recombine(d.nnz, d.piece[0], d.piece[1], d.piece[2], d.piece[3], G, invlam, mu, d.val,
@@ -2206,7 +2256,7 @@ fsgmg_status update_params(fsgmg_h h, double E, double mu) {
     launch_recombine(NF, h->lift_piece[0], h->lift_piece[1], h->lift_piece[2], h->lift_piece[3], G,
                      invlam, mu, h->lift, nullptr, h->stream);
     HIPCHECK(hipGetLastError());
-    build_coarse_inverse(*h);
+    build_coarse_inverse(*h, true);
     return FSGMG_OK;
   });
 }
