@@ -1254,7 +1254,7 @@ __global__ __launch_bounds__(kThreads) void k_recombine(int64_t n, const double*
 //  * k_cgj_update (whole grid, one wavefront per 16-column x 64-row piece):
 //    A[:, j] += (T - E_K) ybuf[:, j] on v_mfma_f64_16x16x4f64, T the panel.
 // The interchanges are finally undone as a column permutation.
-constexpr int kCgjThreads = 1024;
+constexpr int kCgjThreads = 512;
 
 __global__ __launch_bounds__(kThreads) void k_dense_from_csr(int64_t n, int64_t np,
                                                              const int64_t* __restrict__ rp,
