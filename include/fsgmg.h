@@ -187,17 +187,19 @@ fsgmg_status build_fs_as_blocks(fsgmg_h h, const fsgmg_smoother_opts* opts);
 /* z = M^{-1} r (transpose = 0) or z = M^{-T} r (transpose = 1), one V-cycle. */
 fsgmg_status vcycle_apply(fsgmg_h h, const double* r, double* z, int transpose);
 
-/* The cycle of vcycle_apply (forward, additive smoother) on k right-hand
- * sides at once, 1 <= k <= 64: r and z are device FP64 arrays of N * k
- * entries, unknown-major (entry (i, c) at i * k + c: a contiguous N x k
- * row-major matrix), caller-owned, r != z.  Column c of z equals
- * vcycle_apply of column c of r up to rounding (every launch works on all k
- * columns; the block apply of the smoother runs on the matrix cores).
+/* The cycle of vcycle_apply (additive smoother; transpose != 0: its exact
+ * transpose) on k right-hand sides at once, 1 <= k <= 64: r and z are device
+ * FP64 arrays of N * k entries, unknown-major (entry (i, c) at i * k + c: a
+ * contiguous N x k row-major matrix), caller-owned, r != z.  Column c of z
+ * equals vcycle_apply of column c of r (same transpose flag) up to rounding
+ * (every launch works on all k columns; the block applies run on the matrix
+ * cores, the transposed one with transposed copies of the block inverses
+ * made on first use after each factorization).
  * Work buffers of N_l * k entries per level are allocated on the first call
  * with a larger k and kept.  EINVAL for k out of range, the multiplicative
  * smoother or a Schwarz block of more than 1024 unknowns, ESTATE before
  * build_fs_as_blocks. */
-fsgmg_status vcycle_apply_batch(fsgmg_h h, const double* r, double* z, int k);
+fsgmg_status vcycle_apply_batch(fsgmg_h h, const double* r, double* z, int k, int transpose);
 
 /* Solve A x = b on the finest level (x is overwritten; x0 = 0). */
 fsgmg_status gmres_solve(fsgmg_h h, const double* b, double* x,
@@ -215,6 +217,11 @@ fsgmg_status gmres_solve(fsgmg_h h, const double* b, double* x,
  * did not; the other errors as vcycle_apply_batch. */
 fsgmg_status gmres_solve_batch(fsgmg_h h, const double* b, double* x, int k,
                                const fsgmg_krylov_opts* opts, fsgmg_solve_info* infos);
+
+/* adjoint_solve on k right-hand sides at once: gmres_solve_batch with A^T
+ * and the transposed cycle (same arguments, layout and errors). */
+fsgmg_status adjoint_solve_batch(fsgmg_h h, const double* c, double* lam, int k,
+                                 const fsgmg_krylov_opts* opts, fsgmg_solve_info* infos);
 
 fsgmg_status adjoint_solve(fsgmg_h h, const double* c, double* lam,
                            const fsgmg_krylov_opts* opts, fsgmg_solve_info* info);

@@ -1563,9 +1563,10 @@ __global__ __launch_bounds__(kThreads) void k_spmm(BOpView<T> A, const T* __rest
   Y[e] = residual ? Bm[e] - acc : acc;
 }
 
-// Restriction (mode 0: out = D_c R in) and prolongation (mode 1:
-// out += D_f P in) of K columns: one thread per (output row, column), the
-// same equation routing and Dirichlet masks as the one-column transfer.
+// The four transfers on K columns (mode 0: out = D_c R in, 1: out += D_f P
+// in, 2: out = (D_f P)^T in, 3: out += (D_c R)^T in): one thread per (output
+// row, column), the same equation routing and Dirichlet masks as the
+// one-column transfer.
 template <typename T, int D>
 __global__ __launch_bounds__(kThreads) void k_transfer_mc(TransferView<T> t, int mode,
                                                           const T* __restrict__ in,
@@ -1573,7 +1574,7 @@ __global__ __launch_bounds__(kThreads) void k_transfer_mc(TransferView<T> t, int
   const int64_t tt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t id = tt / K;
   const int c = (int)(tt - id * K);
-  if (mode == 0) {
+  if (mode == 0 || mode == 2) {
     if (id < t.N2c) {
       const int64_t I = id;
       const uint8_t fc = t.flags_c[I];
@@ -1584,19 +1585,28 @@ __global__ __launch_bounds__(kThreads) void k_transfer_mc(TransferView<T> t, int
       for (int k = t.rn_ptr[I]; k < t.rn_ptr[I + 1]; ++k) {
         const int64_t i = t.rn_col[k];
         const T w = t.rn_val[k];
-        const bool ssi = t.flags_f[i] & kSolid;
-        if (ssI == ssi) {
+        const uint8_t ff = t.flags_f[i];
+        if (mode == 0) {
+          const bool ssi = ff & kSolid;
+          if (ssI == ssi) {
+#pragma unroll
+            for (int q = 0; q < D; ++q) {
+              bd[q] += w * in[(D * i + q) * K + c];
+              bu[q] += w * in[(t.offu_f + D * i + q) * K + c];
+            }
+          } else if (ssI) {
+#pragma unroll
+            for (int q = 0; q < D; ++q) bd[q] += w * in[(t.offu_f + D * i + q) * K + c];
+          }
+        } else {
 #pragma unroll
           for (int q = 0; q < D; ++q) {
-            bd[q] += w * in[(D * i + q) * K + c];
-            bu[q] += w * in[(t.offu_f + D * i + q) * K + c];
+            if (!(ff & kDirD)) bd[q] += w * in[(D * i + q) * K + c];
+            if (!(ff & kDirU)) bu[q] += w * in[(t.offu_f + D * i + q) * K + c];
           }
-        } else if (ssI) {
-#pragma unroll
-          for (int q = 0; q < D; ++q) bd[q] += w * in[(t.offu_f + D * i + q) * K + c];
         }
       }
-      const bool zd = fc & kDirD, zu = fc & kDirU;
+      const bool zd = (mode == 0) && (fc & kDirD), zu = (mode == 0) && (fc & kDirU);
 #pragma unroll
       for (int q = 0; q < D; ++q) {
         out[(D * I + q) * K + c] = zd ? T(0) : bd[q];
@@ -1623,19 +1633,36 @@ __global__ __launch_bounds__(kThreads) void k_transfer_mc(TransferView<T> t, int
   if (id < t.N2f) {
     const int64_t i = id;
     const uint8_t ff = t.flags_f[i];
+    const bool ssi = ff & kSolid;
     T ad[D], au[D];
 #pragma unroll
     for (int q = 0; q < D; ++q) ad[q] = au[q] = T(0);
     for (int k = t.pn_ptr[i]; k < t.pn_ptr[i + 1]; ++k) {
       const int64_t I = t.pn_col[k];
       const T w = t.pn_val[k];
+      if (mode == 1) {
 #pragma unroll
-      for (int q = 0; q < D; ++q) {
-        ad[q] += w * in[(D * I + q) * K + c];
-        au[q] += w * in[(t.offu_c + D * I + q) * K + c];
+        for (int q = 0; q < D; ++q) {
+          ad[q] += w * in[(D * I + q) * K + c];
+          au[q] += w * in[(t.offu_c + D * I + q) * K + c];
+        }
+      } else {
+        const uint8_t fc = t.flags_c[I];
+        const bool ssI = fc & kSolid;
+#pragma unroll
+        for (int q = 0; q < D; ++q) {
+          const T xd = (fc & kDirD) ? T(0) : in[(D * I + q) * K + c];
+          const T xu = (fc & kDirU) ? T(0) : in[(t.offu_c + D * I + q) * K + c];
+          if (ssI == ssi) {
+            ad[q] += w * xd;
+            au[q] += w * xu;
+          } else if (ssI) {
+            au[q] += w * xd;
+          }
+        }
       }
     }
-    const bool md = ff & kDirD, mu = ff & kDirU;
+    const bool md = (mode == 1) && (ff & kDirD), mu = (mode == 1) && (ff & kDirU);
 #pragma unroll
     for (int q = 0; q < D; ++q) {
       if (!md) out[(D * i + q) * K + c] += ad[q];
@@ -1728,16 +1755,22 @@ constexpr int kMcRows = kMcThreads / 64 * kMcRTW * 16;   // owned rows per round
 constexpr int kMcWs = kMcRows + 16;   // LDS stride of a staged column (lane groups on disjoint banks)
 constexpr int kMcMaxN = kMaxRhsBlock;   // largest block the staged index list holds
 
-// Block apply for K right-hand sides: X[own] = (first ? 0 : X[own]) +
-// omega (W_j R[I_j, :])[own].  Workgroup (b, s) takes rows s * kMcRows ..
-// of block order[b] (`split` workgroups per block, enough for the largest);
-// each wave keeps kMcRTW 16-row tiles times the column tiles as matrix-core
-// accumulators.  Per chunk of block columns the residual rows (gathered
-// through the block's index list, staged in LDS once) and the inverse
-// columns (16-byte loads) are staged in LDS; every inverse entry is loaded
-// once.  Workgroups past the blocks do the Jacobi unknowns.
-template <typename TV, typename TW>
+// Block apply for K right-hand sides on the matrix cores.
+//  forward (TR = false): X[own] = (first ? 0 : X[own]) + omega (W_j R[I_j, :])[own]
+//    (W_j: owned rows, column-major over mp_j rows, n_j block columns);
+//  transposed (TR = true): T[I_j, :] = W_j^T R[own_j, :] into the per-block
+//    buffer T (Wt_j = W_j^T column-major over np_j = n_j padded rows, m_j
+//    columns); k_smooth_mc_t2 then sums the blocks' outputs per unknown.
+// Workgroup (b, s) takes output rows s * kMcRows .. of block order[b]
+// (`split` workgroups per block, enough for the largest); each wave keeps
+// kMcRTW 16-row tiles times the column tiles as matrix-core accumulators.
+// Per chunk of the reduction the residual rows (gathered through the block's
+// input index list, staged in LDS once) and the chunk's matrix columns
+// (16-byte loads) are staged in LDS; every matrix entry is loaded once.
+// Forward: the workgroups past the blocks do the Jacobi unknowns.
+template <typename TV, typename TW, bool TR>
 __global__ __launch_bounds__(kMcThreads) void k_smooth_mc(BlocksView B, const TW* __restrict__ W,
+                                                          const int64_t* __restrict__ wt_off,
                                                           const TV* __restrict__ R,
                                                           TV* __restrict__ X, int K, TV omega,
                                                           int first, int split) {
@@ -1745,10 +1778,11 @@ __global__ __launch_bounds__(kMcThreads) void k_smooth_mc(BlocksView B, const TW
   using Tile = MfmaTile<TA>;
   using acc_t = typename Tile::acc_t;
   constexpr int RV = WTraits<TW>::RV;
-  constexpr int CH = 16;   // block columns per staged chunk (small LDS: several workgroups per CU)
+  constexpr int CH = 16;   // reduction columns per staged chunk (small LDS: several workgroups per CU)
   const int tid = threadIdx.x;
   const int64_t nwg = B.nblk * split;
   if (blockIdx.x >= nwg) {
+    if (TR) return;
     // Jacobi unknowns: the workgroups past the blocks stride over (q, c)
     const int64_t nt = (int64_t)(gridDim.x - nwg) * blockDim.x;
     for (int64_t t = (int64_t)(blockIdx.x - nwg) * blockDim.x + tid; t < B.njac * (int64_t)K;
@@ -1765,20 +1799,23 @@ __global__ __launch_bounds__(kMcThreads) void k_smooth_mc(BlocksView B, const TW
   __shared__ TA wl[CH * kMcWs];
   __shared__ int32_t ldof[kMcMaxN];
   const int64_t j = B.order[blockIdx.x / split];
+  const int64_t d0 = B.dof_ptr[j];
+  const int nb = (int)(B.dof_ptr[j + 1] - d0);
   const int o0 = B.own_ptr[j];
-  const int m = B.own_ptr[j + 1] - o0;
+  const int mo = B.own_ptr[j + 1] - o0;
+  // output rows / their padding / reduction length / the matrix of the block
+  const int m = TR ? nb : mo;
+  const int mp = TR ? (nb + RV - 1) / RV * RV : B.mpad[j];
+  const int n = TR ? mo : nb;
+  const TW* Wj = W + (TR ? wt_off[j] : B.w_off[j]);
   const int r0 = (int)(blockIdx.x % split) * kMcRows;
   if (r0 >= m) return;
-  const int64_t d0 = B.dof_ptr[j];
-  const int n = (int)(B.dof_ptr[j + 1] - d0);
-  const int mp = B.mpad[j];
-  const TW* Wj = W + B.w_off[j];
   const int KT = (K + 15) / 16;        // column tiles
   const int KP = KT * 16;
   const int lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lg = lane >> 4;
-  for (int k = tid; k < n; k += blockDim.x) ldof[k] = B.dofs[d0 + k];
-  // owned rows r0 .. r0 + nr of the padded inverse (nr a multiple of RV)
+  for (int k = tid; k < n; k += blockDim.x) ldof[k] = TR ? B.own_dof[o0 + k] : B.dofs[d0 + k];
+  // output rows r0 .. r0 + nr of the padded matrix (nr a multiple of RV)
   const int nr = min(kMcRows, mp - r0);
   const int nv = nr / RV;
   acc_t acc[kMcRTW][kMcMaxTiles];
@@ -1796,7 +1833,7 @@ __global__ __launch_bounds__(kMcThreads) void k_smooth_mc(BlocksView B, const TW
       const int kk = e / KP, c = e - kk * KP;
       rl[e] = (kk < kc && c < K) ? (TA)R[(int64_t)ldof[k0 + kk] * K + c] : TA(0);
     }
-    // the chunk's inverse columns, rows r0 .. r0 + nr, with 16-byte loads
+    // the chunk's matrix columns, rows r0 .. r0 + nr, with 16-byte loads
     for (int e = tid; e < kc * nv; e += blockDim.x) {
       const int kk = e / nv, v = e - kk * nv;
       TA w[RV];
@@ -1837,11 +1874,62 @@ __global__ __launch_bounds__(kMcThreads) void k_smooth_mc(BlocksView B, const TW
       for (int r = 0; r < 4; ++r) {
         const int i = r0 + tile * 16 + Tile::row(lg, r);
         if (i < m && c < K) {
-          const int64_t e = (int64_t)B.own_dof[o0 + i] * K + c;
-          X[e] = (first ? TV(0) : X[e]) + omega * (TV)acc[a][b][r];
+          if (TR) {
+            X[(d0 + i) * K + c] = (TV)acc[a][b][r];
+          } else {
+            const int64_t e = (int64_t)B.own_dof[o0 + i] * K + c;
+            X[e] = (first ? TV(0) : X[e]) + omega * (TV)acc[a][b][r];
+          }
         }
       }
     }
+  }
+}
+
+// Transposed K-column sweep, part 2: X[i] = (first ? 0 : X[i]) + omega *
+// (fixed-order sum of the block outputs of unknown i); Jacobi unknowns
+// X[i] += omega R[i] / A_ii.  One thread per (unknown, column).
+template <typename TV>
+__global__ __launch_bounds__(kThreads) void k_smooth_mc_t2(BlocksView B, const TV* __restrict__ T,
+                                                           const TV* __restrict__ R,
+                                                           TV* __restrict__ X, int64_t N, int K,
+                                                           TV omega, int first) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t id = t / K;
+  const int c = (int)(t - id * K);
+  if (id < N) {
+    const int b = B.tpos_ptr[id], e = B.tpos_ptr[id + 1];
+    if (b == e) return;
+    TV s = TV(0);
+    for (int k = b; k < e; ++k) s += T[(int64_t)B.tpos[k] * K + c];
+    X[id * K + c] = (first ? TV(0) : X[id * K + c]) + omega * s;
+    return;
+  }
+  const int64_t q = id - N;
+  if (q < B.njac) {
+    const int64_t gi = B.jac[q];
+    const TV jv = reinterpret_cast<const TV*>(B.jac_inv)[q];
+    X[gi * K + c] = (first ? TV(0) : X[gi * K + c]) + omega * R[gi * K + c] * jv;
+  }
+}
+
+// Wt_j[i, kk] = W_j[kk, i]: the transposed inverse of every block, column-
+// major over n_j rows padded to the vector width, zero in the padding
+template <typename TW>
+__global__ __launch_bounds__(kThreads) void k_transpose_blocks(BlocksView B, const TW* __restrict__ W,
+                                                               const int64_t* __restrict__ wt_off,
+                                                               TW* __restrict__ Wt) {
+  constexpr int RV = WTraits<TW>::RV;
+  const int64_t j = blockIdx.x;
+  const int n = (int)(B.dof_ptr[j + 1] - B.dof_ptr[j]);
+  const int m = B.own_ptr[j + 1] - B.own_ptr[j];
+  const int mp = B.mpad[j];
+  const int np = (n + RV - 1) / RV * RV;
+  const TW* Wj = W + B.w_off[j];
+  TW* Tj = Wt + wt_off[j];
+  for (int64_t e = threadIdx.x; e < (int64_t)m * np; e += blockDim.x) {
+    const int kk = (int)(e / np), i = (int)(e - (int64_t)kk * np);
+    Tj[e] = i < n ? Wj[(int64_t)i * mp + kk] : TW(0.0f);
   }
 }
 
@@ -2344,7 +2432,7 @@ template void launch_spmm<float>(const BOpView<float>&, int, const float*, const
 template <typename T>
 void launch_transfer_mc(const TransferView<T>& t, int D, int mode, const T* in, T* out, int K,
                         hipStream_t s) {
-  const int64_t rows = mode == 0 ? t.N2c + t.Npsc + t.Npfc : t.N2f + t.Npsf + t.Npff;
+  const int64_t rows = (mode == 0 || mode == 2) ? t.N2c + t.Npsc + t.Npfc : t.N2f + t.Npsf + t.Npff;
   const int64_t n = rows * K;
   if (n == 0) return;
   if (D == 2)
@@ -2371,32 +2459,89 @@ template void launch_dense_mc<float>(int64_t, const double*, const float*, float
                                      hipStream_t);
 
 template <typename TV, typename TW>
-static void smooth_mc_impl(const BlocksView& B, const TW* W, const TV* R, TV* X, int K,
-                           double omega, bool first, hipStream_t s) {
-  const int split = (B.max_mpad + kMcRows - 1) / kMcRows;
-  const int64_t nj = std::min<int64_t>((B.njac * (int64_t)K + kMcThreads - 1) / kMcThreads, 512);
-  const unsigned g = (unsigned)(B.nblk * split + nj);
+static void smooth_mc_impl(const BlocksView& B, const TW* W, const int64_t* wt_off, const TV* R,
+                           TV* X, int K, double omega, bool first, bool transpose, hipStream_t s) {
+  constexpr int RV = WTraits<TW>::RV;
+  if (!transpose) {
+    const int split = (B.max_mpad + kMcRows - 1) / kMcRows;
+    const int64_t nj =
+        std::min<int64_t>((B.njac * (int64_t)K + kMcThreads - 1) / kMcThreads, 512);
+    const unsigned g = (unsigned)(B.nblk * split + nj);
+    if (g)
+      hipLaunchKernelGGL((k_smooth_mc<TV, TW, false>), dim3(g), dim3(kMcThreads), 0, s, B, W,
+                         wt_off, R, X, K, (TV)omega, (int)first, split);
+    return;
+  }
+  const int npm = (B.max_n + RV - 1) / RV * RV;
+  const int split = (npm + kMcRows - 1) / kMcRows;
+  const unsigned g = (unsigned)(B.nblk * split);
   if (g)
-    hipLaunchKernelGGL((k_smooth_mc<TV, TW>), dim3(g), dim3(kMcThreads), 0, s, B, W, R, X, K,
-                       (TV)omega, (int)first, split);
+    hipLaunchKernelGGL((k_smooth_mc<TV, TW, true>), dim3(g), dim3(kMcThreads), 0, s, B, W, wt_off,
+                       R, X, K, (TV)omega, 0, split);
 }
 
 template <typename TV>
 void launch_smooth_mc(const BlocksView& B, WPrec wp, const void* W, const TV* R, TV* X, int K,
                       double omega, bool first, hipStream_t s) {
   if constexpr (sizeof(TV) == 8) {
-    smooth_mc_impl<double, double>(B, (const double*)W, R, X, K, omega, first, s);
+    smooth_mc_impl<double, double>(B, (const double*)W, nullptr, R, X, K, omega, first, false, s);
   } else {
     if (wp == WPrec::BF16)
-      smooth_mc_impl<float, __hip_bfloat16>(B, (const __hip_bfloat16*)W, R, X, K, omega, first, s);
+      smooth_mc_impl<float, __hip_bfloat16>(B, (const __hip_bfloat16*)W, nullptr, R, X, K, omega,
+                                            first, false, s);
     else
-      smooth_mc_impl<float, float>(B, (const float*)W, R, X, K, omega, first, s);
+      smooth_mc_impl<float, float>(B, (const float*)W, nullptr, R, X, K, omega, first, false, s);
   }
 }
 template void launch_smooth_mc<double>(const BlocksView&, WPrec, const void*, const double*,
                                        double*, int, double, bool, hipStream_t);
 template void launch_smooth_mc<float>(const BlocksView&, WPrec, const void*, const float*, float*,
                                       int, double, bool, hipStream_t);
+
+template <typename TV>
+void launch_smooth_mc_t(const BlocksView& B, WPrec wp, const void* Wt, const int64_t* wt_off,
+                        const TV* R, TV* X, TV* T, int64_t N, int K, double omega, bool first,
+                        hipStream_t s) {
+  if constexpr (sizeof(TV) == 8) {
+    smooth_mc_impl<double, double>(B, (const double*)Wt, wt_off, R, T, K, omega, first, true, s);
+  } else {
+    if (wp == WPrec::BF16)
+      smooth_mc_impl<float, __hip_bfloat16>(B, (const __hip_bfloat16*)Wt, wt_off, R, T, K, omega,
+                                            first, true, s);
+    else
+      smooth_mc_impl<float, float>(B, (const float*)Wt, wt_off, R, T, K, omega, first, true, s);
+  }
+  const int64_t n = (N + B.njac) * (int64_t)K;
+  if (n > 0)
+    hipLaunchKernelGGL((k_smooth_mc_t2<TV>), dim3(grid_for(n, kThreads)), dim3(kThreads), 0, s, B,
+                       T, R, X, N, K, (TV)omega, (int)first);
+}
+template void launch_smooth_mc_t<double>(const BlocksView&, WPrec, const void*, const int64_t*,
+                                         const double*, double*, double*, int64_t, int, double,
+                                         bool, hipStream_t);
+template void launch_smooth_mc_t<float>(const BlocksView&, WPrec, const void*, const int64_t*,
+                                        const float*, float*, float*, int64_t, int, double, bool,
+                                        hipStream_t);
+
+void launch_transpose_blocks(const BlocksView& B, WPrec wp, const void* W, const int64_t* wt_off,
+                             void* Wt, hipStream_t s) {
+  if (B.nblk == 0) return;
+  const dim3 g((unsigned)B.nblk), t(kThreads);
+  switch (wp) {
+    case WPrec::F64:
+      hipLaunchKernelGGL((k_transpose_blocks<double>), g, t, 0, s, B, (const double*)W, wt_off,
+                         (double*)Wt);
+      break;
+    case WPrec::F32:
+      hipLaunchKernelGGL((k_transpose_blocks<float>), g, t, 0, s, B, (const float*)W, wt_off,
+                         (float*)Wt);
+      break;
+    case WPrec::BF16:
+      hipLaunchKernelGGL((k_transpose_blocks<__hip_bfloat16>), g, t, 0, s, B,
+                         (const __hip_bfloat16*)W, wt_off, (__hip_bfloat16*)Wt);
+      break;
+  }
+}
 
 // ---- K-column Krylov ----
 int krylov_mc_partials() { return kMcParts * kMaxK * kMcSlots; }

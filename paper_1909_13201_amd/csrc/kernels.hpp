@@ -180,6 +180,17 @@ void launch_dense_mc(int64_t n, const double* Ainv, const TV* B, TV* X, int K, h
 template <typename TV>
 void launch_smooth_mc(const BlocksView& B, WPrec wp, const void* W, const TV* R, TV* X, int K,
                       double omega, bool first, hipStream_t s);
+// transposed K-column sweep: T[I_j] = W_j^T R[own_j] per block (Wt: the
+// transposed inverses, column-major over n_j padded to the vector width, at
+// wt_off[j]; T: one K-column row per block entry), then X[i] = (first ? 0 :
+// X[i]) + omega (fixed-order sum over the blocks containing i), Jacobi
+// unknowns likewise
+template <typename TV>
+void launch_smooth_mc_t(const BlocksView& B, WPrec wp, const void* Wt, const int64_t* wt_off,
+                        const TV* R, TV* X, TV* T, int64_t N, int K, double omega, bool first,
+                        hipStream_t s);
+void launch_transpose_blocks(const BlocksView& B, WPrec wp, const void* W, const int64_t* wt_off,
+                             void* Wt, hipStream_t s);
 
 // dst_mapped[i] = src[i], i < n: dst_mapped is the device address of pinned
 // host memory (hipHostGetDevicePointer); the host reads it after the stream

@@ -270,8 +270,13 @@ struct DLevel {
   // several right-hand sides: K-column blocks (entry (i, c) at i * K + c)
   // of b, x, r in FP64 / FP32, sized for mcap64 / mcap32 columns
   int mcap64 = 0, mcap32 = 0;
-  double *bm64 = nullptr, *xm64 = nullptr, *rm64 = nullptr;
-  float *bm32 = nullptr, *xm32 = nullptr, *rm32 = nullptr;
+  double *bm64 = nullptr, *xm64 = nullptr, *rm64 = nullptr, *tm64 = nullptr;
+  float *bm32 = nullptr, *xm32 = nullptr, *rm32 = nullptr, *tm32 = nullptr;
+  // transposed block inverses for the K-column transposed sweep (built on
+  // first use after each factorization)
+  void* Wt = nullptr;
+  int64_t* wt_off = nullptr;
+  bool wt_valid = false;
 };
 
 }  // namespace
@@ -772,12 +777,24 @@ void upload_blocks(fsgmg_hierarchy& h, int l) {
                           (const void*)d.e64, (const void*)d.rc64, (const void*)d.e32,
                           (const void*)d.rc32, (const void*)o.rows_off, (const void*)o.rows_w,
                           (const void*)o.rows_col, o.rows_val, (const void*)o.jrow_col,
-                          o.jrow_val, (const void*)d.x2_64, (const void*)d.x2_32})
+                          o.jrow_val, (const void*)d.x2_64, (const void*)d.x2_32, (const void*)d.Wt,
+                          (const void*)d.wt_off})
       h.dfree(const_cast<void*>(q));
     o = BlocksView{};
     d.W = nullptr;
     d.tb64 = d.e64 = d.rc64 = d.x2_64 = nullptr;
     d.tb32 = d.e32 = d.rc32 = d.x2_32 = nullptr;
+    d.Wt = nullptr;
+    d.wt_off = nullptr;
+    d.wt_valid = false;
+    // K-column work blocks: the per-block rows depend on the index sets
+    for (const void* q : {(const void*)d.bm64, (const void*)d.xm64, (const void*)d.rm64,
+                          (const void*)d.tm64, (const void*)d.bm32, (const void*)d.xm32,
+                          (const void*)d.rm32, (const void*)d.tm32})
+      h.dfree(const_cast<void*>(q));
+    d.bm64 = d.xm64 = d.rm64 = d.tm64 = nullptr;
+    d.bm32 = d.xm32 = d.rm32 = d.tm32 = nullptr;
+    d.mcap64 = d.mcap32 = 0;
   }
   const int RV = rows_per_vector(h.sopt.prec);
   const int64_t nb = bs.nblk();
@@ -988,6 +1005,7 @@ void factor_blocks(fsgmg_hierarchy& h) {
     if (nb == 0) continue;
     HIPCHECK(hipStreamWaitEvent(fp.stream, h.factor_start, 0));
     HIPCHECK(hipMemsetAsync(fp.status, 0, (size_t)nb * sizeof(int32_t), fp.stream));
+    d.wt_valid = false;
     if (h.sopt.prec == FSGMG_FP64)
       launch_block_rows<double>(d.bv, d.rp, d.col, d.val, fp.stream);
     else
@@ -1062,6 +1080,7 @@ struct Vec<double> {
   static double* bm(DLevel& d) { return d.bm64; }
   static double* xm(DLevel& d) { return d.xm64; }
   static double* rm(DLevel& d) { return d.rm64; }
+  static double* tm(DLevel& d) { return d.tm64; }
   static const BOpView<double>& op(DLevel& d, bool tr) { return tr ? d.AT.v64 : d.A.v64; }
   static const TransferView<double>& tv(DLevel& d) { return d.t64; }
 };
@@ -1077,6 +1096,7 @@ struct Vec<float> {
   static float* bm(DLevel& d) { return d.bm32; }
   static float* xm(DLevel& d) { return d.xm32; }
   static float* rm(DLevel& d) { return d.rm32; }
+  static float* tm(DLevel& d) { return d.tm32; }
   static const BOpView<float>& op(DLevel& d, bool tr) { return tr ? d.AT.v32 : d.A.v32; }
   static const TransferView<float>& tv(DLevel& d) { return d.t32; }
 };
@@ -1330,36 +1350,78 @@ void ensure_mc_buffers(fsgmg_hierarchy& h, int K) {
   for (int l = 0; l < h.L; ++l) {
     DLevel& d = h.dl[l];
     const int64_t n = d.N * (int64_t)K;
+    // per-block rows of the transposed sweep: one K-column row per block entry
+    const int64_t nt = (l > 0 ? (int64_t)h.blocks[l].dofs.size() : 0) * K;
     if (sizeof(TV) == 8) {
       if (d.mcap64 >= K) continue;
-      for (void* q : {(void*)d.bm64, (void*)d.xm64, (void*)d.rm64}) h.dfree(q);
-      d.bm64 = d.xm64 = d.rm64 = nullptr;
+      for (void* q : {(void*)d.bm64, (void*)d.xm64, (void*)d.rm64, (void*)d.tm64}) h.dfree(q);
+      d.bm64 = d.xm64 = d.rm64 = d.tm64 = nullptr;
       d.mcap64 = 0;
       d.bm64 = h.zeros<double>(n);
       d.xm64 = h.zeros<double>(n);
       d.rm64 = h.zeros<double>(n);
+      d.tm64 = h.zeros<double>(std::max<int64_t>(nt, 1));
       d.mcap64 = K;
     } else {
       if (d.mcap32 >= K) continue;
-      for (void* q : {(void*)d.bm32, (void*)d.xm32, (void*)d.rm32}) h.dfree(q);
-      d.bm32 = d.xm32 = d.rm32 = nullptr;
+      for (void* q : {(void*)d.bm32, (void*)d.xm32, (void*)d.rm32, (void*)d.tm32}) h.dfree(q);
+      d.bm32 = d.xm32 = d.rm32 = d.tm32 = nullptr;
       d.mcap32 = 0;
       d.bm32 = h.zeros<float>(n);
       d.xm32 = h.zeros<float>(n);
       d.rm32 = h.zeros<float>(n);
+      d.tm32 = h.zeros<float>(std::max<int64_t>(nt, 1));
       d.mcap32 = K;
     }
   }
 }
 
+// transposed inverses of level l's blocks (after the latest factorization)
+void ensure_wt(fsgmg_hierarchy& h, int l) {
+  DLevel& d = h.dl[l];
+  if (d.wt_valid) return;
+  const BlockSet& bs = h.blocks[l];
+  const int RV = rows_per_vector(h.sopt.prec);
+  if (!d.Wt) {
+    const int64_t nb = bs.nblk();
+    std::vector<int64_t> off(nb + 1, 0);
+    for (int64_t j = 0; j < nb; ++j) {
+      const int64_t n = bs.ptr[j + 1] - bs.ptr[j];
+      int64_t m = 0;
+      for (int64_t p = bs.ptr[j]; p < bs.ptr[j + 1]; ++p) m += bs.owner[bs.dofs[p]] == (int32_t)j;
+      off[j + 1] = off[j] + m * ((n + RV - 1) / RV * RV);
+    }
+    d.wt_off = h.upload(off);
+    d.Wt = h.dalloc((size_t)off[nb] * w_bytes(h.sopt.prec) + 64);
+  }
+  launch_transpose_blocks(d.bv, wprec(h.sopt.prec), d.W, d.wt_off, d.Wt, h.stream);
+  HIPCHECK(hipGetLastError());
+  d.wt_valid = true;
+}
+
 template <typename TV>
-void smooth_level_mc(fsgmg_hierarchy& h, int l, int nsweeps, bool from_zero, int K) {
+void smooth_level_mc(fsgmg_hierarchy& h, int l, int nsweeps, bool from_zero, int K,
+                     bool transpose = false) {
   DLevel& d = h.dl[l];
   const WPrec wp = wprec(h.sopt.prec);
   TV* b = Vec<TV>::bm(d);
   TV* x = Vec<TV>::xm(d);
   TV* r = Vec<TV>::rm(d);
   const bool fin = l == h.L - 1;
+  if (transpose) {
+    ensure_wt(h, l);
+    for (int s = 0; s < nsweeps; ++s) {
+      const bool first = s == 0 && from_zero;
+      if (!first) {
+        TimedLaunch t(h, 1, fin);
+        launch_spmm<TV>(Vec<TV>::op(d, true), h.D, x, b, r, K, true, h.stream);
+      }
+      TimedLaunch t(h, 0, fin);
+      launch_smooth_mc_t<TV>(d.bv, wp, d.Wt, d.wt_off, first ? b : r, x, Vec<TV>::tm(d), d.N, K,
+                             h.sopt.omega, first, h.stream);
+    }
+    return;
+  }
   for (int s = 0; s < nsweeps; ++s) {
     if (s == 0 && from_zero) {
       TimedLaunch t(h, 0, fin);
@@ -1376,37 +1438,42 @@ void smooth_level_mc(fsgmg_hierarchy& h, int l, int nsweeps, bool from_zero, int
 }
 
 template <typename TV>
-void cycle_level_mc(fsgmg_hierarchy& h, int l, int kind, bool zero_init, int K) {
+void cycle_level_mc(fsgmg_hierarchy& h, int l, int kind, bool zero_init, int K,
+                    bool transpose = false) {
   if (l == 0) {
     DLevel& C = h.dl[0];
-    launch_dense_mc<TV>(h.n0, h.coarse_inv, Vec<TV>::bm(C), Vec<TV>::xm(C), K, h.stream);
+    launch_dense_mc<TV>(h.n0, transpose ? h.coarse_invT : h.coarse_inv, Vec<TV>::bm(C),
+                        Vec<TV>::xm(C), K, h.stream);
     return;
   }
   DLevel& d = h.dl[l];
   const int64_t nk = d.N * (int64_t)K;
-  if (h.sopt.nu_pre == 0 && zero_init) launch_fill<TV>(Vec<TV>::xm(d), TV(0), nk, h.stream);
-  smooth_level_mc<TV>(h, l, h.sopt.nu_pre, zero_init, K);
-  launch_spmm<TV>(Vec<TV>::op(d, false), h.D, Vec<TV>::xm(d), Vec<TV>::bm(d), Vec<TV>::rm(d), K,
-                  true, h.stream);
-  launch_transfer_mc<TV>(Vec<TV>::tv(d), h.D, 0, Vec<TV>::rm(d), Vec<TV>::bm(h.dl[l - 1]), K,
-                         h.stream);
+  const int npre = transpose ? h.sopt.nu_post : h.sopt.nu_pre;
+  const int npost = transpose ? h.sopt.nu_pre : h.sopt.nu_post;
+  if (npre == 0 && zero_init) launch_fill<TV>(Vec<TV>::xm(d), TV(0), nk, h.stream);
+  smooth_level_mc<TV>(h, l, npre, zero_init, K, transpose);
+  launch_spmm<TV>(Vec<TV>::op(d, transpose), h.D, Vec<TV>::xm(d), Vec<TV>::bm(d), Vec<TV>::rm(d),
+                  K, true, h.stream);
+  launch_transfer_mc<TV>(Vec<TV>::tv(d), h.D, transpose ? 2 : 0, Vec<TV>::rm(d),
+                         Vec<TV>::bm(h.dl[l - 1]), K, h.stream);
   int seq[2] = {FSGMG_CYCLE_V, FSGMG_CYCLE_V};
   int nseq = 1;
   if (kind == FSGMG_CYCLE_W) {
     seq[0] = seq[1] = FSGMG_CYCLE_W;
     nseq = 2;
   } else if (kind == FSGMG_CYCLE_F) {
-    seq[0] = FSGMG_CYCLE_F;
+    seq[0] = transpose ? FSGMG_CYCLE_V : FSGMG_CYCLE_F;
+    seq[1] = transpose ? FSGMG_CYCLE_F : FSGMG_CYCLE_V;
     nseq = 2;
   }
-  for (int i = 0; i < nseq; ++i) cycle_level_mc<TV>(h, l - 1, seq[i], i == 0, K);
-  launch_transfer_mc<TV>(Vec<TV>::tv(d), h.D, 1, Vec<TV>::xm(h.dl[l - 1]), Vec<TV>::xm(d), K,
-                         h.stream);
-  smooth_level_mc<TV>(h, l, h.sopt.nu_post, false, K);
+  for (int i = 0; i < nseq; ++i) cycle_level_mc<TV>(h, l - 1, seq[i], i == 0, K, transpose);
+  launch_transfer_mc<TV>(Vec<TV>::tv(d), h.D, transpose ? 3 : 1, Vec<TV>::xm(h.dl[l - 1]),
+                         Vec<TV>::xm(d), K, h.stream);
+  smooth_level_mc<TV>(h, l, npost, false, K, transpose);
 }
-void vcycle_mc(fsgmg_hierarchy& h, const double* r, double* z, int K) {
+void vcycle_mc(fsgmg_hierarchy& h, const double* r, double* z, int K, bool transpose = false) {
   if (h.L == 1) {
-    launch_dense_mc<double>(h.n0, h.coarse_inv, r, z, K, h.stream);
+    launch_dense_mc<double>(h.n0, transpose ? h.coarse_invT : h.coarse_inv, r, z, K, h.stream);
     return;
   }
   auto run = [&](auto tag) {
@@ -1415,7 +1482,7 @@ void vcycle_mc(fsgmg_hierarchy& h, const double* r, double* z, int K) {
     DLevel& F = h.dl[h.L - 1];
     const int64_t nk = F.N * (int64_t)K;
     launch_cast<double, TV>(r, Vec<TV>::bm(F), nk, h.stream);
-    cycle_level_mc<TV>(h, h.L - 1, h.sopt.cycle, true, K);
+    cycle_level_mc<TV>(h, h.L - 1, h.sopt.cycle, true, K, transpose);
     launch_cast<TV, double>(Vec<TV>::xm(F), z, nk, h.stream);
   };
   if (h.sopt.prec == FSGMG_FP64)
@@ -1535,16 +1602,18 @@ void ensure_mc_workspace(fsgmg_hierarchy& h, int K, int m) {
 }
 
 fsgmg_status fgmres_batch(fsgmg_hierarchy& h, const double* b, double* x, int K,
-                          const fsgmg_krylov_opts& o, fsgmg_solve_info* infos) {
+                          const fsgmg_krylov_opts& o, fsgmg_solve_info* infos,
+                          bool transpose = false) {
   const auto t0 = std::chrono::steady_clock::now();
   if (o.restart < 1 || o.restart > 31 || o.rtol <= 0 || o.max_restarts < 0)
     throw Fail{FSGMG_EINVAL, "krylov options out of range (restart 1..31, rtol > 0)"};
   if (!h.factors_valid) throw Fail{FSGMG_ESTATE, "build_fs_as_blocks has not been called"};
   const int m = o.restart;
   ensure_mc_workspace(h, K, m);
+  if (transpose) ensure_transposed(h);
   DLevel& F = h.dl[h.L - 1];
   const int64_t N = F.N, ld = h.ld_mc;
-  const BOpView<double>& A = F.A.v64;
+  const BOpView<double>& A = transpose ? F.AT.v64 : F.A.v64;
   double* dsm = h.mc_small;
   double* hp = h.mc_pinned;
   auto norms = [&](const double* v, std::vector<double>& out) {
@@ -1604,7 +1673,7 @@ fsgmg_status fgmres_batch(fsgmg_hierarchy& h, const double* b, double* x, int K,
       if (!any) break;
       double* Vj = h.mc_V + (int64_t)j * ld;
       double* Zj = h.mc_Z + (int64_t)j * ld;
-      vcycle_mc(h, Vj, Zj, K);
+      vcycle_mc(h, Vj, Zj, K, transpose);
       launch_spmm<double>(A, h.D, Zj, nullptr, h.mc_w, K, false, h.stream);
       launch_mc_mdot(h.mc_V, ld, j + 1, h.mc_w, N, K, h.mc_part, dsm + kMcH1, h.stream);
       launch_mc_maxpy_mdot(h.mc_V, ld, j + 1, dsm + kMcH1, h.mc_w, N, K, h.mc_part, dsm + kMcH2,
@@ -1953,6 +2022,17 @@ void autotune(fsgmg_hierarchy& h) {
     autotune_impl<float>(h);
 }
 
+// the checks shared by the several-right-hand-side entry points
+void check_mc(fsgmg_hierarchy& h, int k) {
+  if (k < 1 || k > kMaxRhs) throw Fail{FSGMG_EINVAL, "k must be in 1..64"};
+  if (h.sopt.schwarz != FSGMG_SCHWARZ_ADDITIVE)
+    throw Fail{FSGMG_EINVAL, "several right-hand sides need the additive smoother"};
+  for (int l = 1; l < h.L; ++l)
+    if (h.dl[l].bv.max_n > kMaxRhsBlock)
+      throw Fail{FSGMG_EINVAL, "several right-hand sides: a Schwarz block exceeds " +
+                                   std::to_string(kMaxRhsBlock) + " unknowns"};
+}
+
 void check_device(fsgmg_hierarchy& h) {
   if (h.host_only()) throw Fail{FSGMG_ESTATE, "device call on a host-only handle"};
 }
@@ -2106,20 +2186,15 @@ fsgmg_status vcycle_apply(fsgmg_h h, const double* r, double* z, int transpose) 
   });
 }
 
-fsgmg_status vcycle_apply_batch(fsgmg_h h, const double* r, double* z, int k) {
+fsgmg_status vcycle_apply_batch(fsgmg_h h, const double* r, double* z, int k, int transpose) {
   if (!h || !r || !z || r == z) return FSGMG_EINVAL;
   return guarded(h, [&]() -> fsgmg_status {
     check_device(*h);
     if (!h->factors_valid) throw Fail{FSGMG_ESTATE, "build_fs_as_blocks has not been called"};
-    if (k < 1 || k > kMaxRhs) throw Fail{FSGMG_EINVAL, "k must be in 1..64"};
-    if (h->sopt.schwarz != FSGMG_SCHWARZ_ADDITIVE)
-      throw Fail{FSGMG_EINVAL, "several right-hand sides need the additive smoother"};
-    for (int l = 1; l < h->L; ++l)
-      if (h->dl[l].bv.max_n > kMaxRhsBlock)
-        throw Fail{FSGMG_EINVAL, "several right-hand sides: a Schwarz block exceeds " +
-                                     std::to_string(kMaxRhsBlock) + " unknowns"};
+    check_mc(*h, k);
     ensure_coarse(*h);
-    vcycle_mc(*h, r, z, k);
+    if (transpose) ensure_transposed(*h);
+    vcycle_mc(*h, r, z, k, transpose != 0);
     HIPCHECK(hipGetLastError());
     return FSGMG_OK;
   });
@@ -2130,15 +2205,20 @@ fsgmg_status gmres_solve_batch(fsgmg_h h, const double* b, double* x, int k,
   if (!h || !b || !x || !opts || b == x) return FSGMG_EINVAL;
   return guarded(h, [&]() -> fsgmg_status {
     check_device(*h);
-    if (k < 1 || k > kMaxRhs) throw Fail{FSGMG_EINVAL, "k must be in 1..64"};
-    if (h->sopt.schwarz != FSGMG_SCHWARZ_ADDITIVE)
-      throw Fail{FSGMG_EINVAL, "several right-hand sides need the additive smoother"};
-    for (int l = 1; l < h->L; ++l)
-      if (h->dl[l].bv.max_n > kMaxRhsBlock)
-        throw Fail{FSGMG_EINVAL, "several right-hand sides: a Schwarz block exceeds " +
-                                     std::to_string(kMaxRhsBlock) + " unknowns"};
+    check_mc(*h, k);
     ensure_coarse(*h);
     return fgmres_batch(*h, b, x, k, *opts, infos);
+  });
+}
+
+fsgmg_status adjoint_solve_batch(fsgmg_h h, const double* c, double* lam, int k,
+                                 const fsgmg_krylov_opts* opts, fsgmg_solve_info* infos) {
+  if (!h || !c || !lam || !opts || c == lam) return FSGMG_EINVAL;
+  return guarded(h, [&]() -> fsgmg_status {
+    check_device(*h);
+    check_mc(*h, k);
+    ensure_coarse(*h);
+    return fgmres_batch(*h, c, lam, k, *opts, infos, true);
   });
 }
 

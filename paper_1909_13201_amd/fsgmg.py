@@ -26,7 +26,7 @@ SWEEP_FORM = {"auto": 0, "spmv": 1, "fused": 2}
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
 
 EXPORTED = ["setup_hierarchy", "build_fs_as_blocks", "vcycle_apply", "vcycle_apply_batch",
-            "gmres_solve", "gmres_solve_batch",
+            "gmres_solve", "gmres_solve_batch", "adjoint_solve_batch",
             "adjoint_solve", "assemble_load", "load_adjoint", "apply_operator", "param_grad",
             "update_params", "level_info", "export_csr", "export_vector", "export_blocks", "block_colours",
             "kernel_timing", "tuning_info", "last_error", "hierarchy_destroy"]
@@ -82,8 +82,9 @@ def lib():
                                  C.POINTER(H)], C.c_int),
             "build_fs_as_blocks": ([H, C.POINTER(SmootherOpts)], C.c_int),
             "vcycle_apply": ([H, P, P, C.c_int], C.c_int),
-            "vcycle_apply_batch": ([H, P, P, C.c_int], C.c_int),
+            "vcycle_apply_batch": ([H, P, P, C.c_int, C.c_int], C.c_int),
             "gmres_solve_batch": ([H, P, P, C.c_int, C.POINTER(KrylovOpts), P], C.c_int),
+            "adjoint_solve_batch": ([H, P, P, C.c_int, C.POINTER(KrylovOpts), P], C.c_int),
             "gmres_solve": ([H, P, P, C.POINTER(KrylovOpts), C.POINTER(SolveInfo)], C.c_int),
             "adjoint_solve": ([H, P, P, C.POINTER(KrylovOpts), C.POINTER(SolveInfo)], C.c_int),
             "assemble_load": ([H, P, P], C.c_int),
@@ -211,8 +212,8 @@ def vcycle_apply(h, r, z, transpose=False):
     _check(h, lib().vcycle_apply(h, _ptr(r), _ptr(z), int(bool(transpose))))
 
 
-def vcycle_apply_batch(h, r, z, k):
-    _check(h, lib().vcycle_apply_batch(h, _ptr(r), _ptr(z), int(k)))
+def vcycle_apply_batch(h, r, z, k, transpose=False):
+    _check(h, lib().vcycle_apply_batch(h, _ptr(r), _ptr(z), int(k), int(bool(transpose))))
 
 
 def _solve(fn, h, b, x, restart, max_restarts, rtol, history_cap):
@@ -229,14 +230,21 @@ def _solve(fn, h, b, x, restart, max_restarts, rtol, history_cap):
                 t_solve_ms=info.t_solve_ms, status=STATUS[st])
 
 
-def gmres_solve_batch(h, b, x, k, restart=30, max_restarts=20, rtol=1e-10):
+def _solve_batch(fn, h, b, x, k, restart, max_restarts, rtol):
     o = KrylovOpts(int(restart), int(max_restarts), float(rtol))
     infos = (SolveInfo * int(k))()
-    st = lib().gmres_solve_batch(h, _ptr(b), _ptr(x), int(k), C.byref(o),
-                                 C.cast(infos, C.c_void_p))
+    st = fn(h, _ptr(b), _ptr(x), int(k), C.byref(o), C.cast(infos, C.c_void_p))
     _check(h, st, allow_not_converged=True)
     return [dict(converged=bool(i.converged), iters=i.iters, restarts=i.restarts,
                  rel_res_true=i.rel_res_true, t_solve_ms=i.t_solve_ms) for i in infos]
+
+
+def gmres_solve_batch(h, b, x, k, restart=30, max_restarts=20, rtol=1e-10):
+    return _solve_batch(lib().gmres_solve_batch, h, b, x, k, restart, max_restarts, rtol)
+
+
+def adjoint_solve_batch(h, c, lam, k, restart=30, max_restarts=20, rtol=1e-10):
+    return _solve_batch(lib().adjoint_solve_batch, h, c, lam, k, restart, max_restarts, rtol)
 
 
 def gmres_solve(h, b, x, restart=30, max_restarts=20, rtol=1e-10, history_cap=1024):
@@ -400,32 +408,31 @@ class Hierarchy:
     def vcycle_apply(self, r, z, transpose=False):
         vcycle_apply(self.h, self._vec(r), self._vec(z), transpose)
 
-    def vcycle_apply_batch(self, r, z):
-        """Cycle on the columns of r ((N, k) float64 device tensors)."""
+    def _cols(self, a, b):
         import torch
-        for t in (r, z):
+        for t in (a, b):
             if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
                 raise TypeError("expected float64 device tensors")
             if t.dim() != 2 or t.shape[0] != self.N or not t.is_contiguous():
                 raise ValueError("expected contiguous (N, k) tensors with N = %d" % self.N)
-        if r.shape != z.shape:
-            raise ValueError("r and z must have the same shape")
-        vcycle_apply_batch(self.h, r, z, r.shape[1])
+        if a.shape != b.shape:
+            raise ValueError("the two tensors must have the same shape")
+        return a.shape[1]
+
+    def vcycle_apply_batch(self, r, z, transpose=False):
+        """Cycle (or its transpose) on the columns of r ((N, k) float64 device tensors)."""
+        vcycle_apply_batch(self.h, r, z, self._cols(r, z), transpose)
 
     def gmres_solve(self, b, x, **kw):
         return gmres_solve(self.h, self._vec(b), self._vec(x), **kw)
 
     def gmres_solve_batch(self, b, x, **kw):
         """FGMRES on the columns of b ((N, k) float64 device tensors)."""
-        import torch
-        for t in (b, x):
-            if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
-                raise TypeError("expected float64 device tensors")
-            if t.dim() != 2 or t.shape[0] != self.N or not t.is_contiguous():
-                raise ValueError("expected contiguous (N, k) tensors with N = %d" % self.N)
-        if b.shape != x.shape:
-            raise ValueError("b and x must have the same shape")
-        return gmres_solve_batch(self.h, b, x, b.shape[1], **kw)
+        return gmres_solve_batch(self.h, b, x, self._cols(b, x), **kw)
+
+    def adjoint_solve_batch(self, c, lam, **kw):
+        """Adjoint FGMRES (A^T) on the columns of c ((N, k) float64 device tensors)."""
+        return adjoint_solve_batch(self.h, c, lam, self._cols(c, lam), **kw)
 
     def adjoint_solve(self, c, lam, **kw):
         return adjoint_solve(self.h, self._vec(c), self._vec(lam), **kw)

@@ -248,10 +248,11 @@ def test_fused_and_spmv_sweeps_parity(key, schwarz):
                                        ("chan3d", "V")])
 def test_vcycle_batch_parity(key, cycle):
     """Several right-hand sides at once (vcycle_apply_batch, k columns
-    unknown-major, block apply on the matrix cores): every column against the
-    one-column cycle of the same precision (FP64 to 1e-12, FP32 and BF16
-    factors to the FP32 rounding of the cycle), FP64 columns against the
-    oracle's cycle, ragged k (5, 17) and the largest k (64); error paths."""
+    unknown-major, block apply on the matrix cores), the cycle and its
+    transpose: every column against the one-column cycle of the same
+    precision (FP64 to 1e-12, FP32 and BF16 factors to the FP32 rounding of
+    the cycle), FP64 columns against the oracle's cycle, ragged k (5, 17) and
+    the largest k (64); error paths."""
     import tests.cfgs as cfgs
     if key == "c1":
         cfg = inputs.config("c1")
@@ -270,20 +271,22 @@ def test_vcycle_batch_parity(key, cycle):
             R = rng.standard_normal((H.N, k))
             Rd = dev(R.ravel()).reshape(H.N, k).contiguous()
             Z = torch.zeros_like(Rd)
-            H.vcycle_apply_batch(Rd, Z)
-            Zb = host(Z.reshape(-1)).reshape(H.N, k)
             z = torch.zeros(H.N, dtype=torch.float64, device="cuda")
-            worst = 0.0
-            for c in range(k):
-                H.vcycle_apply(dev(np.ascontiguousarray(R[:, c])), z)
-                zc = host(z)
-                worst = max(worst, np.linalg.norm(Zb[:, c] - zc) / np.linalg.norm(zc))
-            say("[batch]", key, cycle, prec, "k", k, "max col rel diff %.3e" % worst)
-            assert worst <= tol
-            if prec == "fp64":
-                for c in (0, k - 1):
-                    ref = O.vcycle(R[:, c])
-                    assert np.linalg.norm(Zb[:, c] - ref) / np.linalg.norm(ref) <= 1e-9
+            for tr in (False, True):
+                H.vcycle_apply_batch(Rd, Z, transpose=tr)
+                Zb = host(Z.reshape(-1)).reshape(H.N, k)
+                worst = 0.0
+                for c in range(k):
+                    H.vcycle_apply(dev(np.ascontiguousarray(R[:, c])), z, transpose=tr)
+                    zc = host(z)
+                    worst = max(worst, np.linalg.norm(Zb[:, c] - zc) / np.linalg.norm(zc))
+                say("[batch]", key, cycle, prec, "k", k, "transpose", tr,
+                    "max col rel diff %.3e" % worst)
+                assert worst <= tol
+                if prec == "fp64":
+                    for c in (0, k - 1):
+                        ref = O.vcycle(R[:, c], transpose=tr)
+                        assert np.linalg.norm(Zb[:, c] - ref) / np.linalg.norm(ref) <= 1e-9
     Rd = torch.zeros((H.N, 65), dtype=torch.float64, device="cuda")
     with pytest.raises(fsgmg.FsgmgError):
         H.vcycle_apply_batch(Rd, torch.zeros_like(Rd))
@@ -299,7 +302,9 @@ def test_gmres_solve_batch(key, k):
     """FGMRES on k loads at once (gmres_solve_batch, FP32 cycle): every column
     converges to a true 1e-10 (recomputed with the oracle's matrix), in the
     iteration count of its one-column solve (+-1), and agrees with that
-    solve's solution; a zero column and a repeated column are handled."""
+    solve's solution; a zero column and a repeated column are handled.  The
+    adjoint on the same k right-hand sides (adjoint_solve_batch) reaches a
+    true 1e-10 with A^T in the one-column adjoint's iteration count."""
     import tests.cfgs as cfgs
     if key == "c1":
         cfg = inputs.config("c1")
@@ -338,6 +343,19 @@ def test_gmres_solve_batch(key, k):
         assert abs(infos[c]["iters"] - one["iters"]) <= 1
         assert d <= 1e-7
     assert np.array_equal(Xh[:, 0], Xh[:, 2])
+    # adjoint on the same loads (A^T, transposed K-column cycle)
+    Ld = torch.zeros_like(Bd)
+    ainfos = H.adjoint_solve_batch(Bd, Ld, rtol=1e-10)
+    Lh = host(Ld.reshape(-1)).reshape(H.N, k)
+    AT = A.T.tocsr()
+    for c in (0, 3, k - 1):
+        bn = np.linalg.norm(Bh[:, c])
+        true = np.linalg.norm(Bh[:, c] - AT @ Lh[:, c]) / bn
+        one = H.adjoint_solve(dev(np.ascontiguousarray(Bh[:, c])), x1, rtol=1e-10)
+        say("[adjoint batch]", key, "col", c, "iters", ainfos[c]["iters"], "one-column", one["iters"],
+            "true %.2e" % true)
+        assert ainfos[c]["converged"] and true <= 1e-10
+        assert abs(ainfos[c]["iters"] - one["iters"]) <= 1
     H.close()
 
 
