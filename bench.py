@@ -288,6 +288,46 @@ def grad_bench(cfg, args):
         out[prec] = batch / (time.perf_counter() - t0)
     a, b = np.array(res["fp64"]), np.array(res["fp32"])
     rel = np.abs(a - b) / np.maximum(np.abs(a), 1e-300)
+
+    # the same loads on one operator (E, mu of sample 0): one K-column forward
+    # solve, one adjoint solve (J's gradient in x is c for every load, so one
+    # lambda serves all), the shared load adjoint, and each load's parameter
+    # gradients; sample 0 checked against its per-sample result above
+    E0, mu0 = float(params[0][0]), float(params[0][1])
+    Fm = torch.tensor(np.stack([l.ravel() for l in loads]), dtype=torch.float64, device=dev)
+
+    def shared():
+        H.update_params(E0, mu0)
+        H.build_fs_as_blocks(prec="fp32")
+        Bm = torch.empty((H.N, batch), dtype=torch.float64, device=dev)
+        bc = torch.empty(H.N, dtype=torch.float64, device=dev)
+        for i in range(batch):
+            H.assemble_load(Fm[i].contiguous(), bc)
+            Bm[:, i] = bc
+        Xm = torch.zeros_like(Bm)
+        infos = H.gmres_solve_batch(Bm, Xm, rtol=cfg["rtol"])
+        lam = torch.empty(H.N, dtype=torch.float64, device=dev)
+        ainfo = H.adjoint_solve(c, lam, rtol=cfg["rtol"])
+        gf = torch.empty(Fm.shape[1], dtype=torch.float64, device=dev)
+        H.load_adjoint(lam, gf)
+        Js = (c[:, None] * Xm).sum(0)
+        grads = [H.param_grad(lam, Xm[:, i].contiguous()) for i in range(batch)]
+        torch.cuda.synchronize()
+        ok = all(i_["converged"] for i_ in infos) and ainfo["converged"]
+        return Js, grads, gf, ok
+
+    shared()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Js, grads, gf, ok = shared()
+    t_sh = time.perf_counter() - t0
+    got0 = np.array([float(Js[0]), grads[0][0], grads[0][1], float((gf * probe).sum())])
+    ref0 = np.array(res["fp32"][0])
+    shared_line = dict(samples_per_s=round(batch / t_sh, 2),
+                       over_per_sample=round((batch / t_sh) / out["fp32"], 2),
+                       all_converged=bool(ok),
+                       sample0_max_rel_diff=float((np.abs(got0 - ref0) /
+                                                   np.maximum(np.abs(ref0), 1e-300)).max()))
     line = dict(metric="differentiated solves/s (forward + adjoint + gradients, blocks refactored per sample)",
                 value=round(out["fp32"], 3), unit="samples/s", n_gpus=1, steps=batch, warmup=1,
                 ms_per_step=round(1e3 / out["fp32"], 3), higher_is_better=True, scaling="weak",
@@ -297,7 +337,8 @@ def grad_bench(cfg, args):
                 fp64_samples_per_s=round(out["fp64"], 3),
                 max_rel_diff_fp32_vs_fp64=dict(J=float(rel[:, 0].max()), dJ_dE=float(rel[:, 1].max()),
                                                dJ_dmu=float(rel[:, 2].max()),
-                                               dJ_df_probe=float(rel[:, 3].max())))
+                                               dJ_df_probe=float(rel[:, 3].max())),
+                shared_operator=shared_line)
     H.close()
     print(json.dumps(line), flush=True)
 
