@@ -181,6 +181,28 @@ def transfer_bytes(H, level, sv):
     return int((br + bp) / 2)
 
 
+def copy_ceiling(dev, nbytes=1 << 30, reps=5):
+    """Streaming ceiling measured on the device: bytes read plus bytes written
+    per second by torch's device-to-device copy of `nbytes` (median of
+    `reps`, HIP events on torch's stream, which runs the copy)."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / sorted(ts)[reps // 2] / 1e9
+
+
 def measured_traffic():
     """HBM bytes per launch of the finest-level smoother from the committed
     rocprofv3 counter summary, or None when kernels.hip has changed since the
@@ -496,6 +518,9 @@ def main():
                 traffic=measured_traffic() if cfg["name"] == "c2" and not args.levels else None,
                 bytes_per_launch=sm_bytes, blocks_per_launch=nblk, grid_threads=grid_f,
                 avg_launch_us=round(avg_ms * 1e3, 2), launches=n_sm)
+    ceil = copy_ceiling(dev)
+    roof["copy_ceiling_gbs"] = round(ceil, 1)
+    roof["frac_of_copy"] = round(achieved / ceil, 4)
     # the other HBM-bound kernels of the path, same live HIP-event timing
     fin = H.L - 1
     model = dict(vspmv=("k_spmv<float> residual, finest", operator_bytes(H, fin, 4, 3)),

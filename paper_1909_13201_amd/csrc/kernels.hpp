@@ -197,6 +197,10 @@ void launch_transpose_blocks(const BlocksView& B, WPrec wp, const void* W, const
 // has passed the launch
 void launch_store_host(const double* src, double* dst_mapped, int n, hipStream_t s);
 
+// one read pass over `bytes` of zero-filled device memory (cache eviction
+// before a timed launch); sink is a separate 4-byte device word
+void launch_flush(const void* buf, int64_t bytes, uint32_t* sink, hipStream_t s);
+
 // ---- K-column Krylov (FP64, K <= 64 unknown-major columns; basis vector i
 // of a K-column block at V + i * ld; h, out: nv x K, entry (i, c) at i * K + c;
 // `part` holds krylov_mc_partials() doubles; fixed-order reductions) ----

@@ -1884,26 +1884,60 @@ fsgmg_status fgmres(fsgmg_hierarchy& h, const double* b, double* x, const fsgmg_
 // Launch-shape autotuner: for every level time the V-cycle SpMV with 1 to 16
 // lanes per row, the transfers' lanes, the smoother sweep with 256, 512 and
 // 1024-thread workgroups (and several workgroups per block where blocks are
-// few), the fused against the SpMV form of a sweep (HIP events on the
-// handle's stream, best of the averages of ten launches after one warm-up),
-// and the outer FP64 product's lanes.
+// few), the fused against the SpMV form of a sweep, and the outer FP64
+// product's lanes.  Each candidate is timed cold: a read pass over a buffer
+// larger than the last-level cache runs before every timed launch, as the
+// finer levels' sweeps evict a coarse level's data inside a cycle (with the
+// data cached, launch shapes with long chains of dependent loads look
+// cheaper than they are there).  HIP events on the handle's stream around
+// the launch alone; the median of five after one warm-up.
+struct Flush {
+  static constexpr int64_t kBytes = int64_t(512) << 20;   // twice the 256 MB cache
+  void* buf = nullptr;
+  uint32_t* sink = nullptr;
+  Flush() {
+    if (hipMalloc(&buf, kBytes + 256) != hipSuccess) {
+      (void)hipGetLastError();
+      buf = nullptr;   // no room: the candidates are timed warm
+      return;
+    }
+    if (hipMemset(buf, 0, kBytes + 256) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipFree(buf);
+      buf = nullptr;
+      return;
+    }
+    sink = reinterpret_cast<uint32_t*>(static_cast<char*>(buf) + kBytes);
+  }
+  ~Flush() {
+    if (buf) (void)hipFree(buf);
+  }
+  Flush(const Flush&) = delete;
+  Flush& operator=(const Flush&) = delete;
+};
+
 template <typename F>
-float time_launch(fsgmg_hierarchy& h, F&& f) {
-  constexpr int kReps = 10;   // enough launches that clock ramps and jitter average out
+float time_launch(fsgmg_hierarchy& h, const Flush& fl, F&& f) {
+  constexpr int kReps = 5;
   hipEvent_t a = h.next_event(), b = h.next_event();
   f();
-  HIPCHECK(hipEventRecord(a, h.stream));
-  for (int i = 0; i < kReps; ++i) f();
-  HIPCHECK(hipEventRecord(b, h.stream));
-  HIPCHECK(hipEventSynchronize(b));
-  float ms = 0.f;
-  HIPCHECK(hipEventElapsedTime(&ms, a, b));
+  float t[kReps];
+  for (int i = 0; i < kReps; ++i) {
+    if (fl.buf) launch_flush(fl.buf, Flush::kBytes, fl.sink, h.stream);
+    HIPCHECK(hipEventRecord(a, h.stream));
+    f();
+    HIPCHECK(hipEventRecord(b, h.stream));
+    HIPCHECK(hipEventSynchronize(b));
+    HIPCHECK(hipEventElapsedTime(&t[i], a, b));
+  }
   h.ev_used -= 2;
-  return ms / kReps;
+  std::sort(t, t + kReps);
+  return t[kReps / 2];
 }
 
 template <typename TV>
 void autotune_impl(fsgmg_hierarchy& h) {
+  const Flush fl;
   const bool was_timing = h.timing;
   h.timing = false;
   h.tune.assign(h.L, {});
@@ -1913,7 +1947,7 @@ void autotune_impl(fsgmg_hierarchy& h) {
     DLevel& d = h.dl[l];
     float best = 1e30f;
     for (int lg : lanes) {
-      const float t = time_launch(h, [&] {
+      const float t = time_launch(h, fl, [&] {
         launch_spmv<TV>(Vec<TV>::op(d, false), h.D, Vec<TV>::x(d), Vec<TV>::b(d), Vec<TV>::r(d),
                         true, h.stream, lg);
       });
@@ -1927,7 +1961,7 @@ void autotune_impl(fsgmg_hierarchy& h) {
     // each) and prolongation from it (fine outputs, 1-4 weights each)
     best = 1e30f;
     for (int lg : lanes) {
-      const float t = time_launch(h, [&] {
+      const float t = time_launch(h, fl, [&] {
         launch_transfer<TV>(Vec<TV>::tv(d), h.D, 0, Vec<TV>::r(d), Vec<TV>::b(h.dl[l - 1]),
                             h.stream, lg);
       });
@@ -1938,7 +1972,7 @@ void autotune_impl(fsgmg_hierarchy& h) {
     }
     best = 1e30f;
     for (int lg : lanes) {
-      const float t = time_launch(h, [&] {
+      const float t = time_launch(h, fl, [&] {
         launch_transfer<TV>(Vec<TV>::tv(d), h.D, 1, Vec<TV>::x(h.dl[l - 1]), Vec<TV>::r(d),
                             h.stream, lg);
       });
@@ -1960,7 +1994,7 @@ void autotune_impl(fsgmg_hierarchy& h) {
     const int nsplit = tv.nblk < 1024 ? 4 : 1;
     for (int th : threads)
       for (int q = 0; q < nsplit; ++q) {
-        const float t = time_launch(h, [&] {
+        const float t = time_launch(h, fl, [&] {
           launch_smooth<TV>(tv, wp, d.W, Vec<TV>::b(d), Vec<TV>::x(d), Vec<TV>::t(d), 1.0, true,
                             false, d.N, h.stream, th, splits[q]);
         });
@@ -1974,7 +2008,7 @@ void autotune_impl(fsgmg_hierarchy& h) {
     // that forms the blocks' residual rows itself (fewer launches, but every
     // block reads its own copy of its operator rows)
     {
-      const float t_sep = time_launch(h, [&] {
+      const float t_sep = time_launch(h, fl, [&] {
         launch_spmv<TV>(Vec<TV>::op(d, false), h.D, Vec<TV>::x(d), Vec<TV>::b(d), Vec<TV>::r(d),
                         true, h.stream, h.tune[l].spmv_lanes);
         launch_smooth<TV>(tv, wp, d.W, Vec<TV>::r(d), Vec<TV>::x(d), Vec<TV>::t(d), 1.0, false,
@@ -1983,7 +2017,7 @@ void autotune_impl(fsgmg_hierarchy& h) {
       float t_fused = 1e30f;
       int th_fused = h.tune[l].smooth_threads;
       for (int th : threads) {
-        const float t = time_launch(h, [&] {
+        const float t = time_launch(h, fl, [&] {
           launch_smooth_fused<TV>(tv, wp, d.W, Vec<TV>::b(d), Vec<TV>::x(d), Vec<TV>::x2(d), 1.0,
                                   false, h.stream, th);
         });
@@ -2003,7 +2037,7 @@ void autotune_impl(fsgmg_hierarchy& h) {
   DLevel& F = h.dl[h.L - 1];
   float best = 1e30f;
   for (int lg : lanes) {
-    const float t = time_launch(h, [&] {
+    const float t = time_launch(h, fl, [&] {
       launch_spmv<double>(F.A.v64, h.D, F.x64, F.b64, F.r64, true, h.stream, lg);
     });
     if (t < best) {
