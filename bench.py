@@ -238,12 +238,10 @@ def timed_solves(H, b, x, steps, warmup, rtol):
 
 def cpu_baseline(cfg, w, f):
     """The oracle as it stands: one full FGMRES solve of the same workload on
-    the host (hierarchy and LU factors built first, untimed)."""
-    try:
-        from threadpoolctl import threadpool_limits
-        limiter = threadpool_limits(1)
-    except Exception:   # pragma: no cover
-        limiter = None
+    the host (hierarchy and LU factors built first, untimed), once with the
+    BLAS pools held to one thread (the reported value) and once with the
+    host's default pools (SciPy's sparse products stay single-threaded)."""
+    from threadpoolctl import threadpool_info, threadpool_limits
     from oracle.krylov import fgmres
     from oracle.multigrid import Hierarchy as OracleHierarchy
     t0 = time.perf_counter()
@@ -251,16 +249,22 @@ def cpu_baseline(cfg, w, f):
     t_setup = time.perf_counter() - t0
     b = O.rhs(f)
     A = O.A[-1]
-    t0 = time.perf_counter()
-    x, info = fgmres(lambda v: A @ v, O.vcycle, b, restart=30, rtol=cfg["rtol"])
-    t = time.perf_counter() - t0
-    if limiter is not None:
-        limiter.unregister() if hasattr(limiter, "unregister") else None
+
+    def solve():
+        t0 = time.perf_counter()
+        _, info = fgmres(lambda v: A @ v, O.vcycle, b, restart=30, rtol=cfg["rtol"])
+        return time.perf_counter() - t0, info
+
+    with threadpool_limits(limits=1):
+        t, info = solve()
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    t_all, _ = solve()
     return dict(value=1.0 / t, unit="solves/s", cores=1, kind="oracle",
                 sample="one full FGMRES(30) solve of the same %s workload to 1e-10 "
                        "(%d iterations, %.1f s; hierarchy and block LUs built "
                        "beforehand in %.1f s, untimed), NumPy/SciPy FP64, one thread"
-                       % (cfg["name"], info["iters"], t, t_setup))
+                       % (cfg["name"], info["iters"], t, t_setup),
+                default_threads=dict(value=round(1.0 / t_all, 4), blas_threads=threads))
 
 
 def grad_bench(cfg, args):
