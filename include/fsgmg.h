@@ -290,8 +290,12 @@ fsgmg_status block_colours(fsgmg_h h, int level, int64_t* ncolours, int64_t* col
 fsgmg_status kernel_timing(fsgmg_h h, int enable, int64_t counts[4], double total_ms[4]);
 
 /* Launch shapes chosen by the autotuner that build_fs_as_blocks runs on the
- * device (HIP-event timing of the candidates on the level's own data; kept
- * by later builds with the same block structure and precision):
+ * device (HIP-event timing of each candidate launch on the level's own data,
+ * median of five, each after a read pass over a 512 MB scratch buffer that
+ * evicts the caches as the finer levels do inside a cycle; the buffer is
+ * allocated for the autotuning only, and without room for it the candidates
+ * are timed warm; kept by later builds with the same block structure and
+ * precision):
  * out[0] = lanes per row of the level's V-cycle SpMV (1, 2, 4, 8, 16),
  * out[1] = smoother workgroup width (256, 512, 1024; negative = the same
  * width with non-temporal loads of the block inverses; 0 on level 0),
