@@ -108,8 +108,10 @@ typedef struct {
  * stores block inverses in bfloat16 and keeps FP32 level operators).
  * use_graph != 0 captures each FGMRES Arnoldi step (V-cycle, operator
  * product, Gram-Schmidt, Hessenberg read-back) and the V-cycle of
- * vcycle_apply as HIP graphs on first use; the graphs are rebuilt after the
- * next build_fs_as_blocks.  Graphs are bypassed while kernel_timing records.
+ * vcycle_apply as HIP graphs on first use; they are kept by a later
+ * build_fs_as_blocks with the same options (refactoring into the same
+ * buffers, as after update_params) and captured again after any other.
+ * Graphs are bypassed while kernel_timing records.
  * iface_mult (0 or 1 = off): for each region, a tile row of cores touching
  * another region across a face normal to axis 1 absorbs the next
  * iface_mult - 1 tile rows away from that interface, giving enlarged

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -395,16 +396,24 @@ struct fsgmg_hierarchy {
     allocs.push_back(p);
     return p;
   }
+  // Copies and fills go through the handle's stream and are complete on
+  // return: the handle may run on a non-blocking stream, which does not wait
+  // for work on the null stream, and the new buffer may next be used on any
+  // of the handle's streams.
   template <typename T>
   T* upload(const std::vector<T>& v) {
     T* p = (T*)dalloc(v.size() * sizeof(T));
-    if (!v.empty()) HIPCHECK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    if (!v.empty()) {
+      HIPCHECK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, stream));
+      HIPCHECK(hipStreamSynchronize(stream));
+    }
     return p;
   }
   template <typename T>
   T* zeros(int64_t n) {
     T* p = (T*)dalloc((size_t)n * sizeof(T));
-    HIPCHECK(hipMemset(p, 0, (size_t)n * sizeof(T)));
+    HIPCHECK(hipMemsetAsync(p, 0, (size_t)n * sizeof(T), stream));
+    HIPCHECK(hipStreamSynchronize(stream));
     return p;
   }
   hipEvent_t factor_start = nullptr;
@@ -619,7 +628,9 @@ void ensure_coarse(fsgmg_hierarchy& h) {
   h.coarse_pending = false;
   int32_t st = 0;
   const int64_t np = (h.ops[0].A.nrows + 15) & ~(int64_t)15;
-  HIPCHECK(hipMemcpy(&st, h.coarse_piv + 2 * np, sizeof(int32_t), hipMemcpyDeviceToHost));
+  HIPCHECK(hipMemcpyAsync(&st, h.coarse_piv + 2 * np, sizeof(int32_t), hipMemcpyDeviceToHost,
+                          h.coarse_stream));
+  HIPCHECK(hipStreamSynchronize(h.coarse_stream));
   if (st) throw Fail{FSGMG_ESINGULAR, "coarse-level matrix is singular"};
 }
 
@@ -748,7 +759,9 @@ void ensure_transposed(fsgmg_hierarchy& h) {
     BOpHost bt = build_bop(h.levels[l], T);
     std::vector<int64_t> m(A.nnz());
     for (int64_t k = 0; k < A.nnz(); ++k) m[k] = bt.map[pos[k]];
-    HIPCHECK(hipMemcpy(d.AT.map, m.data(), m.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpyAsync(d.AT.map, m.data(), m.size() * sizeof(int64_t), hipMemcpyHostToDevice,
+                            h.stream));
+    HIPCHECK(hipStreamSynchronize(h.stream));
   }
 }
 
@@ -1031,7 +1044,9 @@ void factor_blocks(fsgmg_hierarchy& h) {
     const int64_t nb = h.blocks[l].nblk();
     if (nb == 0) continue;
     std::vector<int32_t> st(nb);
-    HIPCHECK(hipMemcpy(st.data(), h.dl[l].fp.status, nb * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIPCHECK(hipMemcpyAsync(st.data(), h.dl[l].fp.status, nb * sizeof(int32_t),
+                            hipMemcpyDeviceToHost, h.stream));
+    HIPCHECK(hipStreamSynchronize(h.stream));
     for (int64_t j = 0; j < nb; ++j)
       if (st[j])
         throw Fail{FSGMG_ESINGULAR, "singular Schwarz block " + std::to_string(j) + " on level " +
@@ -1287,8 +1302,14 @@ void vcycle_core(fsgmg_hierarchy& h, bool transpose) {
 bool graphs_on(const fsgmg_hierarchy& h) { return h.sopt.use_graph && !h.timing && !h.capturing; }
 
 // Capture whatever `enqueue` puts on the handle stream into an executable graph.
+// Captures are serialized over the process: handles driven from several host
+// threads have seen one thread's capture end with "unjoined work" while
+// another thread captured at the same time.
+std::mutex capture_mutex;
+
 template <typename F>
 hipGraphExec_t capture(fsgmg_hierarchy& h, F&& enqueue) {
+  const std::lock_guard<std::mutex> lock(capture_mutex);
   if (!h.cap_stream) HIPCHECK(hipStreamCreateWithFlags(&h.cap_stream, hipStreamNonBlocking));
   hipStream_t saved = h.stream;
   h.stream = h.cap_stream;
@@ -1895,13 +1916,13 @@ struct Flush {
   static constexpr int64_t kBytes = int64_t(512) << 20;   // twice the 256 MB cache
   void* buf = nullptr;
   uint32_t* sink = nullptr;
-  Flush() {
+  explicit Flush(hipStream_t s) {
     if (hipMalloc(&buf, kBytes + 256) != hipSuccess) {
       (void)hipGetLastError();
       buf = nullptr;   // no room: the candidates are timed warm
       return;
     }
-    if (hipMemset(buf, 0, kBytes + 256) != hipSuccess) {
+    if (hipMemsetAsync(buf, 0, kBytes + 256, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
       (void)hipGetLastError();
       (void)hipFree(buf);
       buf = nullptr;
@@ -1937,7 +1958,7 @@ float time_launch(fsgmg_hierarchy& h, const Flush& fl, F&& f) {
 
 template <typename TV>
 void autotune_impl(fsgmg_hierarchy& h) {
-  const Flush fl;
+  const Flush fl(h.stream);
   const bool was_timing = h.timing;
   h.timing = false;
   h.tune.assign(h.L, {});
@@ -2174,9 +2195,19 @@ fsgmg_status build_fs_as_blocks(fsgmg_h h, const fsgmg_smoother_opts* opts) {
                            (h->sopt.monolithic != 0) == (opts->monolithic != 0) &&
                            h->sopt.schwarz == opts->schwarz && h->sopt.prec == opts->prec;
     const int prev_form = h->sopt.sweep_form;
+    // The captured graphs hold buffer addresses, launch shapes and the
+    // options' scalars only.  A rebuild that keeps the index sets, the
+    // precision, every other option and the tuning refactors into the same
+    // buffers (update_params likewise rewrites values in place), so its
+    // graphs stay valid and are not captured again.
+    const fsgmg_smoother_opts& o = h->sopt;
+    const bool keep_graphs = same_sets && h->tuned && o.nu_pre == opts->nu_pre &&
+                             o.nu_post == opts->nu_post && o.omega == opts->omega &&
+                             o.use_graph == opts->use_graph && o.cycle == opts->cycle &&
+                             o.sweep_form == opts->sweep_form;
     h->sopt = *opts;
     h->factors_valid = false;
-    h->invalidate_graphs();
+    if (!keep_graphs) h->invalidate_graphs();
     if (!same_sets) {
       try {
         for (int l = 1; l < h->L; ++l) {

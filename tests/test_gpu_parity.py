@@ -784,3 +784,54 @@ def test_autograd_batch_gradients(prec, levels, nsamp):
         assert mt.grad.item() == pytest.approx(omu, rel=1e-6)
         assert gdf == pytest.approx(dJ, rel=1e-6)
     H.close()
+
+
+def test_handle_pool_gradients():
+    """Several handles at once (HandlePool: one stream and host thread per
+    handle; c5 at 2 levels, 6 seeded samples over 3 handles): each sample's
+    forward solve, adjoint solve and parameter gradients through the library
+    calls FSISolve makes, against the oracle's direct solves and adjoint
+    gradients, and every handle's launches interleaved with the others'."""
+    from paper_1909_13201_amd.pool import HandlePool
+    cfg = inputs.with_levels(inputs.config("c5"), 2)
+    w = inputs.advecting_field(cfg)
+    nsamp = 6
+    params = inputs.sample_parameters(cfg, nsamp)
+    loads = inputs.sample_loads(cfg, nsamp)
+    O0 = OracleHierarchy(cfg, w, build_smoothers=False)
+    taus = [q["tau"] for q in O0.parts]
+    c = oadj.outlet_flux_vector(O0.finest)
+    ct = dev(c)
+    torch.cuda.synchronize()
+
+    def pipeline(H, i):
+        H.update_params(float(params[i][0]), float(params[i][1]))
+        H.build_fs_as_blocks(prec="fp32")
+        f = torch.tensor(loads[i].ravel(), dtype=torch.float64, device="cuda")
+        b = torch.empty(H.N, dtype=torch.float64, device="cuda")
+        H.assemble_load(f, b)
+        x = torch.empty_like(b)
+        inf = H.gmres_solve(b, x, rtol=1e-11, max_restarts=40)
+        lam = torch.empty_like(x)
+        ainf = H.adjoint_solve(ct, lam, rtol=1e-11, max_restarts=40)
+        gE, gmu = H.param_grad(lam, x)
+        return inf["converged"] and ainf["converged"], float((ct * x).sum()), gE, gmu
+
+    say("[pool] 3 handles,", nsamp, "samples")
+    with HandlePool(cfg, w, n=3, device=0) as pool:
+        got = pool.map(pipeline, range(nsamp))
+        got2 = pool.map(pipeline, reversed(range(nsamp)))[::-1]   # handles see other samples
+    for i in range(nsamp):
+        E, mu = params[i]
+        Oi = OracleHierarchy(dict(cfg, E=float(E), mu=float(mu)), w, taus=taus,
+                             build_smoothers=False)
+        A = Oi.A[-1]
+        xd = spla.splu(A.tocsc()).solve(Oi.rhs(loads[i]))
+        lam = spla.splu(A.T.tocsc()).solve(c)
+        oE, omu = oadj.gradients(Oi, xd, lam)
+        for ok, J, gE, gmu in (got[i], got2[i]):
+            say("   sample", i, "J %.9e vs %.9e" % (J, c @ xd), "dJ/dE %.6e vs %.6e" % (gE, oE))
+            assert ok
+            assert J == pytest.approx(c @ xd, rel=1e-8)
+            assert gE == pytest.approx(oE, rel=1e-6)
+            assert gmu == pytest.approx(omu, rel=1e-6)
