@@ -1302,9 +1302,9 @@ void vcycle_core(fsgmg_hierarchy& h, bool transpose) {
 bool graphs_on(const fsgmg_hierarchy& h) { return h.sopt.use_graph && !h.timing && !h.capturing; }
 
 // Capture whatever `enqueue` puts on the handle stream into an executable graph.
-// Captures are serialized over the process: handles driven from several host
-// threads have seen one thread's capture end with "unjoined work" while
-// another thread captured at the same time.
+// Captures are serialized over the process, so that handles driven from
+// several host threads never capture at the same time (a run with several
+// threads and unserialized captures ended one with "unjoined work").
 std::mutex capture_mutex;
 
 template <typename F>
