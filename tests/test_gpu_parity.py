@@ -238,6 +238,20 @@ def test_fused_and_spmv_sweeps_parity(key, schwarz):
         say("   %s fp32 solve iters %d true %.2e" % (form, info["iters"], true))
         assert info["converged"] and true <= 1e-10
         its[form] = info["iters"]
+        tune = H.tuning_info()
+        for t in tune[1:]:
+            assert t["spmv_lanes"] in (1, 2, 4, 8, 16)
+            assert abs(t["smooth_threads"]) in (256, 512, 1024)
+            assert t["restrict_lanes"] in (1, 2, 4, 8, 16)
+            assert t["prolong_lanes"] in (1, 2, 4, 8, 16)
+            assert t["split"] in (1, 2, 4, 8)
+        # a rebuild with the same options keeps the launch shapes and the
+        # captured graphs, and refactors in place: the same solve, bit for bit
+        H.build_fs_as_blocks(prec="fp32", sweep_form=form)
+        assert H.tuning_info() == tune
+        x2 = torch.zeros_like(x)
+        info2 = H.gmres_solve(dev(b), x2, rtol=1e-10)
+        assert info2["iters"] == info["iters"] and torch.equal(x, x2)
     d = np.linalg.norm(zs["fused", False] - zs["spmv", False]) / np.linalg.norm(zs["spmv", False])
     assert d <= 1e-12
     assert abs(its["fused"] - its["spmv"]) <= 1
