@@ -248,10 +248,10 @@ fsgmg_status param_grad(fsgmg_h h, const double* lam, const double* x, double ou
 
 /* Recombine every level operator and the Dirichlet lift for new (E, mu)
  * from the stored affine pieces (SUPG tau frozen at setup).  Invalidates the
- * blocks: call build_fs_as_blocks again.  The coarse inverse is rebuilt on a
- * stream of its own and overlaps the block factorization; the next cycle or
- * solve waits for it and returns FSGMG_ESINGULAR if the coarse matrix turned
- * out singular. */
+ * blocks: call build_fs_as_blocks again.  The coarse inverse is rebuilt on
+ * the handle's stream without waiting for it (the call returns at once); the
+ * next cycle or solve checks it and returns FSGMG_ESINGULAR if the coarse
+ * matrix turned out singular. */
 fsgmg_status update_params(fsgmg_h h, double E, double mu);
 
 /* out[0..8] = N, N2, Nps, Npf, off_ps, off_u, off_pf, nnz(A_l), dim. */

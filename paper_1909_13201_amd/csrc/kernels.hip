@@ -1439,6 +1439,206 @@ __global__ __launch_bounds__(kThreads) void k_cgj_update(double* __restrict__ a,
   }
 }
 
+// Register-panel variant for np <= RPT * kCgjThreads, with two work
+// matrices: the panel step reads the matrix a, and the update writes the
+// next matrix an, so no row interchange has to be applied in place.
+//  * k_cgj_panel_r (one workgroup): thread t holds rows t, t + kCgjThreads,
+//    ... of the NB panel columns in registers and runs the panel's NB
+//    Gauss-Jordan steps (the same pivot rule and arithmetic as k_cgj_panel;
+//    the pivot row and the current row are passed through LDS), writes the
+//    panel T into an, and src[r] = the row of a that row r of the
+//    interchanged matrix comes from;
+//  * k_cgj_update_r (whole grid): an[r][j] = a[src r][j] + sum_q (T - E_K)[r][q]
+//    a[src(k0 + q)][j] for every column j outside the panel, on
+//    v_mfma_f64_16x16x4f64 (16-column tiles; NB = 16 keeps a tile inside or
+//    outside the panel as a whole).
+constexpr int kCgjMaxRpt = 3;   // larger row counts per thread spill the panel to scratch
+
+template <int NB, int RPT>
+__global__ __launch_bounds__(kCgjThreads) void k_cgj_panel_r(const double* __restrict__ a,
+                                                              double* __restrict__ an, int64_t np,
+                                                              int64_t k0, int32_t* __restrict__ piv,
+                                                              int32_t* __restrict__ src,
+                                                              int32_t* __restrict__ status) {
+  constexpr int NW = kCgjThreads / 64;
+  __shared__ double wval[2][NW];
+  __shared__ int widx[2][NW];
+  __shared__ double prow[2][NB], crow[2][NB];
+  __shared__ int lpiv[NB];
+  __shared__ int swl[2 * NB], swv[2 * NB], swn;
+  if (status[0]) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int n = (int)np;
+  double t[RPT][NB];
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int r = tid + i * kCgjThreads;
+#pragma unroll
+    for (int q = 0; q < NB; q += 2) {
+      double2 v = make_double2(0.0, 0.0);
+      if (r < n) v = *reinterpret_cast<const double2*>(a + (int64_t)r * np + k0 + q);
+      t[i][q] = v.x;
+      t[i][q + 1] = v.y;
+    }
+  }
+#pragma unroll
+  for (int kk = 0; kk < NB; ++kk) {
+    const int c = (int)k0 + kk;
+    const int par = kk & 1;
+    double best = -1.0;
+    int bi = n;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int r = tid + i * kCgjThreads;
+      if (r >= c && r < n) {
+        const double v = fabs(t[i][kk]);
+        if (v > best) {
+          best = v;
+          bi = r;
+        }
+      }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double v2 = __shfl_xor(best, off, 64);
+      const int i2 = __shfl_xor(bi, off, 64);
+      if (v2 > best || (v2 == best && i2 < bi)) {
+        best = v2;
+        bi = i2;
+      }
+    }
+    if (lane == 0) {
+      wval[par][wv] = best;
+      widx[par][wv] = bi;
+    }
+    __syncthreads();
+    best = wval[par][0];
+    bi = widx[par][0];
+    for (int w = 1; w < NW; ++w)
+      if (wval[par][w] > best || (wval[par][w] == best && widx[par][w] < bi)) {
+        best = wval[par][w];
+        bi = widx[par][w];
+      }
+    if (!(best > 0.0)) {   // the same decision in every thread
+      if (tid == 0) status[0] = 1;
+      return;
+    }
+    const int p = bi;
+    if (tid == 0) lpiv[kk] = p;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int r = tid + i * kCgjThreads;
+      if (r == p)
+#pragma unroll
+        for (int q = 0; q < NB; ++q) prow[par][q] = t[i][q];
+      if (r == c)
+#pragma unroll
+        for (int q = 0; q < NB; ++q) crow[par][q] = t[i][q];
+    }
+    __syncthreads();
+    const double d = 1.0 / prow[par][kk];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int r = tid + i * kCgjThreads;
+      if (r >= n) continue;
+      if (r == c) {
+#pragma unroll
+        for (int q = 0; q < NB; ++q) t[i][q] = (q == kk) ? d : prow[par][q] * d;
+      } else {
+        const double tt = (r == p) ? crow[par][kk] : t[i][kk];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+          const double rc = (q == kk) ? d : prow[par][q] * d;
+          const double old = (r == p) ? crow[par][q] : t[i][q];
+          t[i][q] = (q == kk ? 0.0 : old) - tt * rc;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int r = tid + i * kCgjThreads;
+    if (r < n)
+#pragma unroll
+      for (int q = 0; q < NB; q += 2)
+        *reinterpret_cast<double2*>(an + (int64_t)r * np + k0 + q) = make_double2(t[i][q], t[i][q + 1]);
+  }
+  if (tid == 0) {
+    // the composition of the panel's interchanges: new row swl[x] = old row swv[x]
+    int ns = 0;
+    for (int kk = 0; kk < NB; ++kk) {
+      const int c = (int)k0 + kk, p = lpiv[kk];
+      piv[c] = p;
+      if (p == c) continue;
+      int ic = -1, ip = -1;
+      for (int x = 0; x < ns; ++x) {
+        if (swl[x] == c) ic = x;
+        if (swl[x] == p) ip = x;
+      }
+      if (ic < 0) {
+        swl[ns] = c;
+        swv[ns] = c;
+        ic = ns++;
+      }
+      if (ip < 0) {
+        swl[ns] = p;
+        swv[ns] = p;
+        ip = ns++;
+      }
+      const int tmp = swv[ic];
+      swv[ic] = swv[ip];
+      swv[ip] = tmp;
+    }
+    swn = ns;
+  }
+  __syncthreads();
+  const int ns = swn;
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int r = tid + i * kCgjThreads;
+    if (r >= n) continue;
+    int sr = r;
+    for (int x = 0; x < ns; ++x)
+      if (swl[x] == r) sr = swv[x];
+    src[r] = sr;
+  }
+}
+
+template <int NB>
+__global__ __launch_bounds__(kThreads) void k_cgj_update_r(const double* __restrict__ a,
+                                                           double* __restrict__ an, int64_t np,
+                                                           int64_t k0, const int32_t* __restrict__ src,
+                                                           const int32_t* __restrict__ status) {
+  static_assert(NB % 16 == 0, "a 16-column tile lies inside or outside the panel");
+  constexpr int kRowTiles = 4;   // 64 rows per wavefront
+  if (status[0]) return;
+  const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+  const int64_t item = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  const int64_t ntile = np / 16;
+  const int64_t nchunk = (ntile + kRowTiles - 1) / kRowTiles;
+  if (item >= ntile * nchunk) return;
+  const int64_t J = item / nchunk, ch = item % nchunk;
+  if (J * 16 >= k0 && J * 16 < k0 + NB) return;   // the panel's columns are final (whole wave)
+  const int64_t c0 = J * 16 + lr;
+  double bq[NB / 4];
+#pragma unroll
+  for (int q = 0; q < NB / 4; ++q) bq[q] = a[(int64_t)src[k0 + 4 * q + lg] * np + c0];
+  for (int64_t it = ch * kRowTiles; it < min(ntile, (ch + 1) * kRowTiles); ++it) {
+    const int64_t r0 = it * 16 + lg, ra = it * 16 + lr;
+    f64x4 acc;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r] = a[(int64_t)src[r0 + 4 * r] * np + c0];
+#pragma unroll
+    for (int q = 0; q < NB / 4; ++q) {
+      const int64_t kc = k0 + 4 * q + lg;
+      const double tq = an[ra * np + kc] - (ra == kc ? 1.0 : 0.0);
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(tq, bq[q], acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) an[(r0 + 4 * r) * np + c0] = acc[r];
+  }
+}
+
 // inverse[i][q] = a[i][sigma[q]] and its transpose, i, q < n
 __global__ __launch_bounds__(kThreads) void k_cgj_finish(const double* __restrict__ a, int64_t np,
                                                          int64_t n, const int32_t* __restrict__ sigma,
@@ -2800,11 +3000,40 @@ int coarse_panel_width(int64_t np, int max_lds) {
   return (size_t)np * 9 * 8 <= (size_t)max_lds ? 8 : 4;
 }
 
-void launch_coarse_factor(int64_t n, int64_t np, const int64_t* rp, const int32_t* col,
-                          const double* val, double* a, double* ybuf, int32_t* piv,
-                          int32_t* status, int nb, hipStream_t s) {
+namespace {
+template <int RPT>
+void coarse_register_panels(int64_t np, double*& cur, double*& nxt, int32_t* piv, int32_t* src,
+                            int32_t* status, hipStream_t s) {
+  constexpr int NB = 16;
+  const int64_t ntile = np / 16;
+  const int64_t items = ntile * ((ntile + 3) / 4);
+  const unsigned gu = grid_for(items * 64, kThreads);
+  for (int64_t k0 = 0; k0 < np; k0 += NB) {
+    hipLaunchKernelGGL((k_cgj_panel_r<NB, RPT>), dim3(1), dim3(kCgjThreads), 0, s, cur, nxt, np, k0,
+                       piv, src, status);
+    hipLaunchKernelGGL((k_cgj_update_r<NB>), dim3(gu), dim3(kThreads), 0, s, cur, nxt, np, k0, src,
+                       status);
+    std::swap(cur, nxt);
+  }
+}
+}  // namespace
+
+const double* launch_coarse_factor(int64_t n, int64_t np, const int64_t* rp, const int32_t* col,
+                                   const double* val, double* a, double* ybuf, double* a2,
+                                   int32_t* src, int32_t* piv, int32_t* status, int nb,
+                                   hipStream_t s) {
   hipLaunchKernelGGL(k_dense_from_csr, dim3((unsigned)np), dim3(kThreads), 0, s, n, np, rp, col, val,
                      a);
+  if (a2 && src && np <= (int64_t)kCgjMaxRpt * kCgjThreads) {
+    double *cur = a, *nxt = a2;
+    const int rpt = (int)((np + kCgjThreads - 1) / kCgjThreads);
+    switch (rpt) {
+      case 1: coarse_register_panels<1>(np, cur, nxt, piv, src, status, s); break;
+      case 2: coarse_register_panels<2>(np, cur, nxt, piv, src, status, s); break;
+      default: coarse_register_panels<3>(np, cur, nxt, piv, src, status, s); break;
+    }
+    return cur;
+  }
   const int64_t ntile = np / 16;
   const int64_t items = ntile * ((ntile + 3) / 4);
   const unsigned gu = grid_for(items * 64, kThreads);
@@ -2820,7 +3049,10 @@ void launch_coarse_factor(int64_t n, int64_t np, const int64_t* rp, const int32_
       hipLaunchKernelGGL((k_cgj_update<4>), dim3(gu), dim3(kThreads), 0, s, a, np, k0, ybuf, status);
     }
   }
+  return a;
 }
+
+bool coarse_register_path(int64_t np) { return np <= (int64_t)kCgjMaxRpt * kCgjThreads; }
 
 void launch_coarse_finish(const double* a, int64_t np, int64_t n, const int32_t* sigma, double* inv,
                           double* invT, hipStream_t s) {

@@ -258,20 +258,25 @@ void launch_extract_owned(const int32_t* jlist, int64_t nb, const BlocksView& B,
 // Dense inverse of the coarse-level matrix (CSR, n rows) by blocked
 // Gauss-Jordan with partial pivoting spread over the GPU.  launch_coarse_factor
 // gathers the CSR into the work matrix a (np x np, np = n rounded up to 16,
-// identity tail) and factors it in panels of nb (8 or 4, coarse_panel_width)
-// columns; piv (np) receives the pivot row of every column, status[0] = 1 on
-// a zero pivot (must be 0 on entry); ybuf: nb x np scratch.  After the host
-// has turned piv into the column permutation sigma (inverse[:, q] =
-// a[:, sigma[q]]), launch_coarse_finish writes the n x n inverse and its
-// transpose.
+// identity tail) and factors it; piv (np) receives the pivot row of every
+// column, status[0] = 1 on a zero pivot (must be 0 on entry).  Where
+// coarse_register_path(np) holds and a2 (a second np x np matrix) and src
+// (np) are given, 16-column panels held in registers alternate between a
+// and a2; otherwise panels of nb (8 or 4, coarse_panel_width) columns in LDS
+// are applied to a in place, with ybuf (nb x np) as scratch.  Returns the
+// matrix that holds the result.  After piv has been turned into the column
+// permutation sigma (inverse[:, q] = result[:, sigma[q]]),
+// launch_coarse_finish writes the n x n inverse and its transpose.
 int coarse_panel_width(int64_t np, int max_lds);
+bool coarse_register_path(int64_t np);
 // sigma from the pivot list on the device (one workgroup, coarse_sigma_lds(np)
 // bytes of LDS)
 size_t coarse_sigma_lds(int64_t np);
 void launch_coarse_sigma(const int32_t* piv, int64_t np, int32_t* sig, hipStream_t s);
-void launch_coarse_factor(int64_t n, int64_t np, const int64_t* rp, const int32_t* col,
-                          const double* val, double* a, double* ybuf, int32_t* piv,
-                          int32_t* status, int nb, hipStream_t s);
+const double* launch_coarse_factor(int64_t n, int64_t np, const int64_t* rp, const int32_t* col,
+                                   const double* val, double* a, double* ybuf, double* a2,
+                                   int32_t* src, int32_t* piv, int32_t* status, int nb,
+                                   hipStream_t s);
 void launch_coarse_finish(const double* a, int64_t np, int64_t n, const int32_t* sigma, double* inv,
                           double* invT, hipStream_t s);
 

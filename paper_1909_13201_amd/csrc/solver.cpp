@@ -305,8 +305,7 @@ struct fsgmg_hierarchy {
   std::vector<void*> allocs;
   std::vector<DLevel> dl;
   double* coarse_inv = nullptr;
-  hipStream_t coarse_stream = nullptr;   // asynchronous coarse rebuilds
-  hipEvent_t coarse_in = nullptr, coarse_done = nullptr;
+  hipEvent_t coarse_done = nullptr;   // end of a coarse rebuild not yet checked
   bool coarse_pending = false;
   double* coarse_invT = nullptr;
   double* coarse_work = nullptr;
@@ -445,12 +444,10 @@ struct fsgmg_hierarchy {
         if (d.fp.stream) (void)hipStreamDestroy(d.fp.stream);
         if (d.fp.done) (void)hipEventDestroy(d.fp.done);
       }
-      if (coarse_stream) {
-        (void)hipStreamSynchronize(coarse_stream);
-        (void)hipStreamDestroy(coarse_stream);
+      if (coarse_done) {
+        if (coarse_pending) (void)hipEventSynchronize(coarse_done);
+        (void)hipEventDestroy(coarse_done);
       }
-      if (coarse_in) (void)hipEventDestroy(coarse_in);
-      if (coarse_done) (void)hipEventDestroy(coarse_done);
       if (factor_start) (void)hipEventDestroy(factor_start);
       for (hipEvent_t e : step_done)
         if (e) (void)hipEventDestroy(e);
@@ -620,7 +617,7 @@ void upload_transfer(fsgmg_hierarchy& h, int l) {
 
 // dense FP64 copy of the coarse-level matrix, inverted on the device; the
 // transpose of the inverse is kept for the transposed V-cycle
-// Wait for a coarse inverse built on the coarse stream and check that the
+// Wait for a coarse inverse enqueued by update_params and check that the
 // coarse matrix was not singular (every cycle entry point calls this).
 void ensure_coarse(fsgmg_hierarchy& h) {
   if (!h.coarse_pending) return;
@@ -629,16 +626,18 @@ void ensure_coarse(fsgmg_hierarchy& h) {
   int32_t st = 0;
   const int64_t np = (h.ops[0].A.nrows + 15) & ~(int64_t)15;
   HIPCHECK(hipMemcpyAsync(&st, h.coarse_piv + 2 * np, sizeof(int32_t), hipMemcpyDeviceToHost,
-                          h.coarse_stream));
-  HIPCHECK(hipStreamSynchronize(h.coarse_stream));
+                          h.stream));
+  HIPCHECK(hipStreamSynchronize(h.stream));
   if (st) throw Fail{FSGMG_ESINGULAR, "coarse-level matrix is singular"};
 }
 
 // Dense FP64 inverse of the level-0 operator from its device CSR.  With
-// `async` the work runs on the coarse stream (after the handle stream's work
-// so far) and the call returns at once: the factorization is one long chain
-// of panel steps that leaves most of the GPU idle, so it overlaps the block
-// factorization that follows a parameter update; ensure_coarse joins it.
+// `async` the work is enqueued on the handle's stream (the column
+// permutation formed on the device) and the call returns at once;
+// ensure_coarse checks its status before the next cycle.  It runs in order
+// with the block refactorization that follows a parameter update: on a
+// stream of its own it found no room on CUs filled by the refactorization's
+// workgroups, and both together took longer than one after the other.
 void build_coarse_inverse(fsgmg_hierarchy& h, bool async = false) {
   const int64_t n = h.ops[0].A.nrows;
   if (n > 20000) throw Fail{FSGMG_EINVAL, "coarse level too large for the dense inverse (n > 20000)"};
@@ -646,37 +645,40 @@ void build_coarse_inverse(fsgmg_hierarchy& h, bool async = false) {
   int max_lds = 0;
   HIPCHECK(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h.device));
   const int nb = coarse_panel_width(np, max_lds);
-  if ((size_t)np * (nb + 1) * 8 > (size_t)max_lds)
+  const bool reg = coarse_register_path(np);
+  if (!reg && (size_t)np * (nb + 1) * 8 > (size_t)max_lds)
     throw Fail{FSGMG_EINVAL, "coarse level too large for the panel factorization"};
   if (!h.coarse_inv) {
     h.coarse_inv = (double*)h.dalloc((size_t)(n * n) * sizeof(double));
     h.coarse_invT = (double*)h.dalloc((size_t)(n * n) * sizeof(double));
-    h.coarse_work = (double*)h.dalloc((size_t)(np * np + 8 * np) * sizeof(double));
-    h.coarse_piv = (int32_t*)h.dalloc((size_t)(2 * np + 1) * sizeof(int32_t));
+    // work matrix + panel scratch, and the second work matrix of the register path
+    h.coarse_work = (double*)h.dalloc((size_t)((reg ? 2 : 1) * np * np + 8 * np) * sizeof(double));
+    // pivots, sigma, status, source rows
+    h.coarse_piv = (int32_t*)h.dalloc((size_t)(3 * np + 1) * sizeof(int32_t));
   }
   int32_t* status = h.coarse_piv + 2 * np;
+  int32_t* src = h.coarse_piv + 2 * np + 1;
+  double* a2 = reg ? h.coarse_work + np * np + 8 * np : nullptr;
   const DLevel& C = h.dl[0];   // device CSR of level 0 (current parameter values)
   int32_t* dsig = h.coarse_piv + np;
   if (async && coarse_sigma_lds(np) <= (size_t)max_lds) {
-    if (!h.coarse_stream) HIPCHECK(hipStreamCreateWithFlags(&h.coarse_stream, hipStreamNonBlocking));
     if (!h.coarse_done) HIPCHECK(hipEventCreateWithFlags(&h.coarse_done, hipEventDisableTiming));
-    if (!h.coarse_in) HIPCHECK(hipEventCreateWithFlags(&h.coarse_in, hipEventDisableTiming));
-    HIPCHECK(hipEventRecord(h.coarse_in, h.stream));
-    HIPCHECK(hipStreamWaitEvent(h.coarse_stream, h.coarse_in, 0));
-    HIPCHECK(hipMemsetAsync(status, 0, sizeof(int32_t), h.coarse_stream));
-    launch_coarse_factor(n, np, C.rp, C.col, C.val, h.coarse_work, h.coarse_work + np * np,
-                         h.coarse_piv, status, nb, h.coarse_stream);
-    launch_coarse_sigma(h.coarse_piv, np, dsig, h.coarse_stream);
-    launch_coarse_finish(h.coarse_work, np, n, dsig, h.coarse_inv, h.coarse_invT, h.coarse_stream);
+    HIPCHECK(hipMemsetAsync(status, 0, sizeof(int32_t), h.stream));
+    const double* res = launch_coarse_factor(n, np, C.rp, C.col, C.val, h.coarse_work,
+                                             h.coarse_work + np * np, a2, src, h.coarse_piv,
+                                             status, nb, h.stream);
+    launch_coarse_sigma(h.coarse_piv, np, dsig, h.stream);
+    launch_coarse_finish(res, np, n, dsig, h.coarse_inv, h.coarse_invT, h.stream);
     HIPCHECK(hipGetLastError());
-    HIPCHECK(hipEventRecord(h.coarse_done, h.coarse_stream));
+    HIPCHECK(hipEventRecord(h.coarse_done, h.stream));
     h.coarse_pending = true;
     h.n0 = n;
     return;
   }
   HIPCHECK(hipMemsetAsync(status, 0, sizeof(int32_t), h.stream));
-  launch_coarse_factor(n, np, C.rp, C.col, C.val, h.coarse_work, h.coarse_work + np * np,
-                       h.coarse_piv, status, nb, h.stream);
+  const double* res = launch_coarse_factor(n, np, C.rp, C.col, C.val, h.coarse_work,
+                                           h.coarse_work + np * np, a2, src, h.coarse_piv, status,
+                                           nb, h.stream);
   HIPCHECK(hipGetLastError());
   std::vector<int32_t> piv(np + 1);
   HIPCHECK(hipMemcpyAsync(piv.data(), h.coarse_piv, np * sizeof(int32_t), hipMemcpyDeviceToHost,
@@ -689,7 +691,7 @@ void build_coarse_inverse(fsgmg_hierarchy& h, bool async = false) {
   for (int64_t c = 0; c < np; ++c) sig[c] = (int32_t)c;
   for (int64_t c = np - 1; c >= 0; --c) std::swap(sig[c], sig[piv[c]]);
   HIPCHECK(hipMemcpyAsync(dsig, sig.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, h.stream));
-  launch_coarse_finish(h.coarse_work, np, n, dsig, h.coarse_inv, h.coarse_invT, h.stream);
+  launch_coarse_finish(res, np, n, dsig, h.coarse_inv, h.coarse_invT, h.stream);
   HIPCHECK(hipGetLastError());
   HIPCHECK(hipStreamSynchronize(h.stream));
   h.n0 = n;
@@ -2388,8 +2390,6 @@ fsgmg_status update_params(fsgmg_h h, double E, double mu) {
       h->ensure_host_values();
       return FSGMG_OK;
     }
-    // a coarse rebuild still in flight reads the level-0 values
-    if (h->coarse_pending) HIPCHECK(hipStreamWaitEvent(h->stream, h->coarse_done, 0));
     for (int l = 0; l < h->L; ++l) {
       DLevel& d = h->dl[l];
       launch_recombine(d.nnz, d.piece[0], d.piece[1], d.piece[2], d.piece[3], G, invlam, mu, d.val,
