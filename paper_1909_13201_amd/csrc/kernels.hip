@@ -783,6 +783,10 @@ __global__ __launch_bounds__(kInvThreads) void k_invert_blocked(
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int lr = lane & 15, lg = lane >> 4;
   const int ntile = np / 16;
+  // identity permutation first: a block that stops at a zero pivot leaves
+  // column indices the extraction can still use (the host then reports the
+  // singular block); each thread later overwrites the same entries
+  for (int c = tid; c < np; c += kInvThreads) sigma_all[soff[blockIdx.x] + c] = c;
 
   for (int K0 = 0; K0 < np; K0 += NO) {
   const int nko = min(NO, np - K0);   // a multiple of 16
@@ -2370,9 +2374,14 @@ __global__ __launch_bounds__(kThreads) void k_flush(const uint4* __restrict__ p,
 // interchanges (applied in reverse order of the pivot steps): one thread
 // walks the pivot list with the permutation held in LDS.
 __global__ __launch_bounds__(64) void k_coarse_sigma(const int32_t* __restrict__ piv, int64_t np,
+                                                     const int32_t* __restrict__ status,
                                                      int32_t* __restrict__ sig) {
   extern __shared__ int32_t sp[];   // np permutation entries, then np pivots
   int32_t* pv = sp + np;
+  if (status[0]) {   // zero pivot: the pivot list is incomplete; an identity keeps
+    for (int64_t c = threadIdx.x; c < np; c += blockDim.x) sig[c] = (int32_t)c;   // reads in bounds
+    return;
+  }
   for (int64_t c = threadIdx.x; c < np; c += blockDim.x) {
     sp[c] = (int32_t)c;
     pv[c] = piv[c];
@@ -2933,8 +2942,10 @@ void launch_flush(const void* buf, int64_t bytes, uint32_t* sink, hipStream_t s)
 }
 
 size_t coarse_sigma_lds(int64_t np) { return (size_t)np * 2 * sizeof(int32_t); }
-void launch_coarse_sigma(const int32_t* piv, int64_t np, int32_t* sig, hipStream_t s) {
-  hipLaunchKernelGGL(k_coarse_sigma, dim3(1), dim3(64), coarse_sigma_lds(np), s, piv, np, sig);
+void launch_coarse_sigma(const int32_t* piv, int64_t np, const int32_t* status, int32_t* sig,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_coarse_sigma, dim3(1), dim3(64), coarse_sigma_lds(np), s, piv, np, status,
+                     sig);
 }
 
 int krylov_partials() { return kPartials * kMaxK; }

@@ -270,9 +270,10 @@ void launch_extract_owned(const int32_t* jlist, int64_t nb, const BlocksView& B,
 int coarse_panel_width(int64_t np, int max_lds);
 bool coarse_register_path(int64_t np);
 // sigma from the pivot list on the device (one workgroup, coarse_sigma_lds(np)
-// bytes of LDS)
+// bytes of LDS); the identity when status[0] reports a zero pivot
 size_t coarse_sigma_lds(int64_t np);
-void launch_coarse_sigma(const int32_t* piv, int64_t np, int32_t* sig, hipStream_t s);
+void launch_coarse_sigma(const int32_t* piv, int64_t np, const int32_t* status, int32_t* sig,
+                         hipStream_t s);
 const double* launch_coarse_factor(int64_t n, int64_t np, const int64_t* rp, const int32_t* col,
                                    const double* val, double* a, double* ybuf, double* a2,
                                    int32_t* src, int32_t* piv, int32_t* status, int nb,

@@ -9,11 +9,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <mutex>
 #include <chrono>
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -667,7 +667,7 @@ void build_coarse_inverse(fsgmg_hierarchy& h, bool async = false) {
     const double* res = launch_coarse_factor(n, np, C.rp, C.col, C.val, h.coarse_work,
                                              h.coarse_work + np * np, a2, src, h.coarse_piv,
                                              status, nb, h.stream);
-    launch_coarse_sigma(h.coarse_piv, np, dsig, h.stream);
+    launch_coarse_sigma(h.coarse_piv, np, status, dsig, h.stream);
     launch_coarse_finish(res, np, n, dsig, h.coarse_inv, h.coarse_invT, h.stream);
     HIPCHECK(hipGetLastError());
     HIPCHECK(hipEventRecord(h.coarse_done, h.stream));
@@ -2117,7 +2117,9 @@ fsgmg_status setup_hierarchy(const fsgmg_mesh_desc* mesh, const fsgmg_physics* p
       nce *= mesh->nc[a];
     }
     if (!mesh->region) throw Fail{FSGMG_EINVAL, "region tags missing"};
-    if (!(phys->E > 0) || !(phys->nu > 0 && phys->nu <= 0.5) || !(phys->mu > 0) || !(phys->rho > 0))
+    if (!(phys->E > 0) || !(phys->nu > 0 && phys->nu <= 0.5) || !(phys->mu > 0) ||
+        !(phys->rho > 0) || !std::isfinite(phys->E) || !std::isfinite(phys->mu) ||
+        !std::isfinite(phys->rho))
       throw Fail{FSGMG_EINVAL, "physical parameters out of range"};
     h->mesh = *mesh;
     for (int a = 0; a < mesh->dim; ++a) {
@@ -2373,7 +2375,8 @@ fsgmg_status param_grad(fsgmg_h h, const double* lam, const double* x, double ou
 fsgmg_status update_params(fsgmg_h h, double E, double mu) {
   if (!h) return FSGMG_EINVAL;
   return guarded(h, [&]() -> fsgmg_status {
-    if (!(E > 0) || !(mu > 0)) throw Fail{FSGMG_EINVAL, "parameters must be positive"};
+    if (!(E > 0) || !(mu > 0) || !std::isfinite(E) || !std::isfinite(mu))
+      throw Fail{FSGMG_EINVAL, "parameters must be positive and finite"};
     h->phys.E = E;
     h->phys.mu = mu;
     double G, invlam;

@@ -212,7 +212,16 @@ def test_error_paths():
     with pytest.raises(fsgmg.FsgmgError) as e:
         fsgmg.setup_hierarchy(bad, None, device=-1)
     assert e.value.status == -1
+    for E in (float("inf"), float("nan")):
+        with pytest.raises(fsgmg.FsgmgError) as e:
+            fsgmg.setup_hierarchy(dict(cfg, E=E), None, device=-1)
+        assert e.value.status == -1
     H = fsgmg.Hierarchy(cfg, None, device=-1)
+    # parameter updates must be positive and finite
+    for E, mu in ((float("inf"), 1e-2), (1e3, float("nan")), (0.0, 1e-2)):
+        with pytest.raises(fsgmg.FsgmgError) as e:
+            H.update_params(E, mu)
+        assert e.value.status == -1
     # device work on a host-only handle is a state error
     import ctypes as C
     st = fsgmg.lib().vcycle_apply(H.h, C.c_void_p(16), C.c_void_p(32), 0)
