@@ -10,11 +10,12 @@ so the handles' work interleaves on the device.  Every handle computes
 exactly what a lone handle computes (its own launch shapes may differ, which
 changes results only by rounding).
 
-Each handle issues work on up to five streams of its own (cycle, coarse
-inverse, one per level's block factorization); the HIP runtime maps a
+Each handle issues work on its own stream and, during a block
+factorization, on one more stream per level; the HIP runtime maps a
 process's streams onto GPU_MAX_HW_QUEUES hardware queues (4 by default), and
-streams sharing a queue run in order, so more queues let the handles overlap
-(set it in the environment before the runtime starts).
+streams sharing a queue run in order, so more queues can let the handles
+overlap further (set it in the environment before the runtime starts).
+Tensors that several items share must be complete before map is called.
 """
 from __future__ import annotations
 
