@@ -831,10 +831,18 @@ def test_handle_pool_gradients():
         gE, gmu = H.param_grad(lam, x)
         return inf["converged"] and ainf["converged"], float((ct * x).sum()), gE, gmu
 
+    def failing(H, i):
+        if i == 4:
+            raise ValueError("item 4")
+        return pipeline(H, i)
+
     say("[pool] 3 handles,", nsamp, "samples")
     with HandlePool(cfg, w, n=3, device=0) as pool:
         got = pool.map(pipeline, range(nsamp))
         got2 = pool.map(pipeline, reversed(range(nsamp)))[::-1]   # handles see other samples
+        with pytest.raises(ValueError, match="item 4"):               # an item's error reaches the caller
+            pool.map(failing, range(nsamp))
+        assert pool.map(pipeline, [1])[0][1] == pytest.approx(got[1][1], rel=1e-9)   # still usable
     for i in range(nsamp):
         E, mu = params[i]
         Oi = OracleHierarchy(dict(cfg, E=float(E), mu=float(mu)), w, taus=taus,
