@@ -2045,7 +2045,7 @@ constexpr int kMcMaxN = kMaxRhsBlock;   // largest block the staged index list h
 // input index list, staged in LDS once) and the chunk's matrix columns
 // (16-byte loads) are staged in LDS; every matrix entry is loaded once.
 // Forward: the workgroups past the blocks do the Jacobi unknowns.
-template <typename TV, typename TW, bool TR>
+template <typename TV, typename TW, bool TR, int MT>
 __global__ __launch_bounds__(kMcThreads, 4) void k_smooth_mc(BlocksView B, const TW* __restrict__ W,
                                                           const int64_t* __restrict__ wt_off,
                                                           const TV* __restrict__ R,
@@ -2072,7 +2072,7 @@ __global__ __launch_bounds__(kMcThreads, 4) void k_smooth_mc(BlocksView B, const
     }
     return;
   }
-  __shared__ TA rl[CH * 16 * kMcMaxTiles];
+  __shared__ TA rl[CH * 16 * MT];
   __shared__ TA wl[CH * kMcWs];
   __shared__ int32_t ldof[kMcMaxN];
   const int64_t j = B.order[blockIdx.x / split];
@@ -2095,17 +2095,17 @@ __global__ __launch_bounds__(kMcThreads, 4) void k_smooth_mc(BlocksView B, const
   // output rows r0 .. r0 + nr of the padded matrix (nr a multiple of RV)
   const int nr = min(kMcRows, mp - r0);
   const int nv = nr / RV;
-  acc_t acc[kMcRTW][kMcMaxTiles];
+  acc_t acc[kMcRTW][MT];
 #pragma unroll
   for (int a = 0; a < kMcRTW; ++a)
 #pragma unroll
-    for (int b = 0; b < kMcMaxTiles; ++b)
+    for (int b = 0; b < MT; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[a][b][r] = TA(0);
   // The next chunk's residual rows and matrix columns are loaded into
   // registers while the matrix cores work on the current one (PR / PW loads
   // per thread at most), so two chunks of loads are in flight per workgroup.
-  constexpr int PR = CH * 16 * kMcMaxTiles / kMcThreads;
+  constexpr int PR = (CH * 16 * MT + kMcThreads - 1) / kMcThreads;
   constexpr int PW = (CH * (kMcRows / RV) + kMcThreads - 1) / kMcThreads;
   TA pr[PR], pw[PW][RV];
   const int ne_r = CH * KP;
@@ -2162,7 +2162,7 @@ __global__ __launch_bounds__(kMcThreads, 4) void k_smooth_mc(BlocksView B, const
         av[a] = (kin && i < nr) ? wl[kk * kMcWs + i] : TA(0);
       }
 #pragma unroll
-      for (int b = 0; b < kMcMaxTiles; ++b) {
+      for (int b = 0; b < MT; ++b) {
         if (b >= KT) break;
         const TA bv = rq[b * 16];
 #pragma unroll
@@ -2175,7 +2175,7 @@ __global__ __launch_bounds__(kMcThreads, 4) void k_smooth_mc(BlocksView B, const
   for (int a = 0; a < kMcRTW; ++a) {
     const int tile = wave + a * (kMcThreads / 64);
 #pragma unroll
-    for (int b = 0; b < kMcMaxTiles; ++b) {
+    for (int b = 0; b < MT; ++b) {
       if (b >= KT) break;
       const int c = b * 16 + lr;
 #pragma unroll
@@ -2806,6 +2806,34 @@ template void launch_dense_mc<double>(int64_t, const double*, const double*, dou
 template void launch_dense_mc<float>(int64_t, const double*, const float*, float*, int,
                                      hipStream_t);
 
+// one instantiation per count of 16-column tiles: accumulators and the
+// staged residual rows are sized for the K at hand, so small K keeps fewer
+// registers and LDS and more workgroups per CU
+template <typename TV, typename TW, bool TR>
+static void launch_smooth_mc_tiles(unsigned g, const BlocksView& B, const TW* W,
+                                   const int64_t* wt_off, const TV* R, TV* X, int K, double omega,
+                                   bool first, int split, hipStream_t s) {
+  const dim3 gg(g), tb(kMcThreads);
+  switch ((K + 15) / 16) {
+    case 1:
+      hipLaunchKernelGGL((k_smooth_mc<TV, TW, TR, 1>), gg, tb, 0, s, B, W, wt_off, R, X, K,
+                         (TV)omega, (int)first, split);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_smooth_mc<TV, TW, TR, 2>), gg, tb, 0, s, B, W, wt_off, R, X, K,
+                         (TV)omega, (int)first, split);
+      break;
+    case 3:
+      hipLaunchKernelGGL((k_smooth_mc<TV, TW, TR, 3>), gg, tb, 0, s, B, W, wt_off, R, X, K,
+                         (TV)omega, (int)first, split);
+      break;
+    default:
+      hipLaunchKernelGGL((k_smooth_mc<TV, TW, TR, kMcMaxTiles>), gg, tb, 0, s, B, W, wt_off, R, X,
+                         K, (TV)omega, (int)first, split);
+      break;
+  }
+}
+
 template <typename TV, typename TW>
 static void smooth_mc_impl(const BlocksView& B, const TW* W, const int64_t* wt_off, const TV* R,
                            TV* X, int K, double omega, bool first, bool transpose, hipStream_t s) {
@@ -2815,17 +2843,13 @@ static void smooth_mc_impl(const BlocksView& B, const TW* W, const int64_t* wt_o
     const int64_t nj =
         std::min<int64_t>((B.njac * (int64_t)K + kMcThreads - 1) / kMcThreads, 512);
     const unsigned g = (unsigned)(B.nblk * split + nj);
-    if (g)
-      hipLaunchKernelGGL((k_smooth_mc<TV, TW, false>), dim3(g), dim3(kMcThreads), 0, s, B, W,
-                         wt_off, R, X, K, (TV)omega, (int)first, split);
+    if (g) launch_smooth_mc_tiles<TV, TW, false>(g, B, W, wt_off, R, X, K, omega, first, split, s);
     return;
   }
   const int npm = (B.max_n + RV - 1) / RV * RV;
   const int split = (npm + kMcRows - 1) / kMcRows;
   const unsigned g = (unsigned)(B.nblk * split);
-  if (g)
-    hipLaunchKernelGGL((k_smooth_mc<TV, TW, true>), dim3(g), dim3(kMcThreads), 0, s, B, W, wt_off,
-                       R, X, K, (TV)omega, 0, split);
+  if (g) launch_smooth_mc_tiles<TV, TW, true>(g, B, W, wt_off, R, X, K, omega, false, split, s);
 }
 
 template <typename TV>

@@ -265,8 +265,8 @@ def test_vcycle_batch_parity(key, cycle):
     unknown-major, block apply on the matrix cores), the cycle and its
     transpose: every column against the one-column cycle of the same
     precision (FP64 to 1e-12, FP32 and BF16 factors to the FP32 rounding of
-    the cycle), FP64 columns against the oracle's cycle, ragged k (5, 17) and
-    the largest k (64); error paths."""
+    the cycle), FP64 columns against the oracle's cycle, ragged k (5, 17,
+    40: one to three 16-column tiles) and the largest k (64); error paths."""
     import tests.cfgs as cfgs
     if key == "c1":
         cfg = inputs.config("c1")
@@ -281,7 +281,7 @@ def test_vcycle_batch_parity(key, cycle):
     rng = np.random.default_rng(23)
     for prec, tol in (("fp64", 1e-12), ("fp32", 1e-5), ("bf16", 1e-5)):
         H.build_fs_as_blocks(prec=prec)
-        for k in ((5, 17, 64) if prec == "fp64" else (32,)):
+        for k in ((5, 17, 40, 64) if prec == "fp64" else (8, 32)):
             R = rng.standard_normal((H.N, k))
             Rd = dev(R.ravel()).reshape(H.N, k).contiguous()
             Z = torch.zeros_like(Rd)
