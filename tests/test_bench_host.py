@@ -50,3 +50,28 @@ def test_smoother_bytes_from_oracle_blocks(prec, sw, sv):
         assert nblk == len(blocks)
         assert got == total
     H.close()
+
+
+@pytest.mark.parametrize("K", [1, 32])
+def test_k_column_model_from_oracle_blocks(K):
+    import bench
+    cfg = inputs.with_levels(inputs.config("c2"), 3)
+    w = inputs.advecting_field(cfg)
+    H = fsgmg.Hierarchy(cfg, w, device=-1)
+    fsgmg.build_fs_as_blocks(H.h, core=cfg["core"], halo=cfg["halo"])
+    O = OracleHierarchy(cfg, w, build_smoothers=False)
+    l = H.L - 1
+    nbytes, flops = bench.mc_smoother_model(H, l, "fp32", K)
+    blocks, _ = build_blocks(O.levels[l], cfg["core"], cfg["halo"])
+    own = owners(O.levels[l].N, blocks)
+    b = f = 0
+    for j, I in enumerate(blocks):
+        m = int((own[I] == j).sum())
+        b += len(I) * m * 4 + 4 * (len(I) + m)
+        f += 2 * len(I) * m * K        # one multiply-add per kept inverse entry and column
+    b += 3 * O.levels[l].N * K * 4
+    assert (nbytes, flops) == (b, f)
+    # one column: the model reduces to the one-column sweep's bytes
+    if K == 1:
+        assert nbytes == bench.smoother_bytes(H, l, "fp32")[0]
+    H.close()
