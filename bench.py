@@ -96,6 +96,7 @@ def mrhs_solves(H, cfg, K, steps, rtol, dev):
         infos = H.gmres_solve_batch(Bm, Xm, rtol=rtol)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
+    check_converged(infos, rtol, "%d-load batch" % K)
     return dict(solves_per_s=round(K * steps / t, 2), ms_per_call=round(1e3 * t / steps, 3),
                 iters_max=max(i["iters"] for i in infos), iters_min=min(i["iters"] for i in infos),
                 all_converged=all(i["converged"] for i in infos),
@@ -203,6 +204,92 @@ def copy_ceiling(dev, nbytes=1 << 30, reps=5):
     return 2 * nbytes / sorted(ts)[reps // 2] / 1e9
 
 
+def read_ceiling(dev, nbytes=1 << 30, reps=5):
+    """Read-only streaming ceiling measured on the device: bytes read per
+    second by a sum over `nbytes` of FP32 (torch's reduction, which reads
+    the buffer once and writes a scalar; median of `reps`, HIP events on
+    torch's stream).  The smoother sweep reads far more than it writes, so
+    this, not a read-plus-write copy, is the ceiling it is held against."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    out = src.sum()
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        out = src.sum()
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3)
+    del src, out
+    torch.cuda.empty_cache()
+    return nbytes / sorted(ts)[reps // 2] / 1e9
+
+
+def kernel_fracs(H, ktime, prec):
+    """Per-kernel HBM rates of the finest level from a kernel_timing record:
+    the smoother sweep, the V-cycle residual product, the outer FP64 product
+    and the transfers, each against its algorithmic bytes."""
+    sv = 8 if prec == "fp64" else 4
+    fin = H.L - 1
+    sm_bytes, nblk = smoother_bytes(H, fin, prec)
+    model = dict(smoother=("k_smooth_fwd (finest level)", sm_bytes),
+                 vspmv=("k_spmv residual, finest", operator_bytes(H, fin, sv, 3)),
+                 outer_spmv=("k_spmv<double> outer product, finest", operator_bytes(H, fin, 8, 2)),
+                 transfer=("k_transfer restriction / prolongation, finest",
+                           transfer_bytes(H, fin, sv)))
+    out = {}
+    for k, (name, nbytes) in model.items():
+        n, ms = ktime[k]
+        us = ms * 1e3 / max(n, 1)
+        gbs = nbytes / (us * 1e-6) / 1e9 if n else 0.0
+        out[k] = dict(kernel=name, launches=n, avg_us=round(us, 2), bytes_per_launch=nbytes,
+                      achieved_gbs=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4))
+    return out
+
+
+def c3_legs(args, dev):
+    """The aneurysm-like workload (c3, 2.2 M unknowns, working set far beyond
+    the 256 MB Infinity Cache): FP64, FP32 and BF16-factor solves/s and the
+    finest-level kernels' HBM rates, GPU legs only (the oracle is timed on
+    c2).  Returned as the `c3` object of the c2 line."""
+    import torch
+    from paper_1909_13201_amd import fsgmg, inputs
+    cfg = inputs.config("c3")
+    w = inputs.advecting_field(cfg)
+    f = inputs.body_force(cfg)
+    rtol = cfg["rtol"]
+    steps = max(3, args.steps // 2)
+    t0 = time.perf_counter()
+    H = fsgmg.Hierarchy(cfg, w, device=0)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    b = torch.zeros(H.N, dtype=torch.float64, device=dev)
+    H.assemble_load(torch.tensor(f.ravel(), dtype=torch.float64, device=dev), b)
+    out = dict(workload=WORKLOADS["c3"], unknowns=H.N, levels=H.L, steps=steps,
+               setup_hierarchy_s=round(t_setup, 3))
+    sps = {}
+    for prec in ("fp64", "fp32", "bf16"):
+        H.build_fs_as_blocks(prec=prec)
+        x = torch.zeros_like(b)
+        t, infos = timed_solves(H, b, x, steps, 1, rtol, "c3 " + prec)
+        sps[prec] = steps / t
+        leg = dict(solves_per_s=round(sps[prec], 4), iters=infos[-1]["iters"],
+                   rel_res_true=infos[-1]["rel_res_true"])
+        if prec != "fp64":
+            H.kernel_timing(True)
+            H.gmres_solve(b, x, restart=30, rtol=rtol)
+            torch.cuda.synchronize()
+            leg["kernels"] = kernel_fracs(H, H.kernel_timing(False), prec)
+        out[prec] = leg
+    out["mixed_over_fp64"] = round(sps["fp32"] / sps["fp64"], 3)
+    out["bf16_over_fp64"] = round(sps["bf16"] / sps["fp64"], 3)
+    H.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def measured_traffic():
     """HBM bytes per launch of the finest-level smoother from the committed
     rocprofv3 counter summary, or None when kernels.hip has changed since the
@@ -222,7 +309,21 @@ def measured_traffic():
     return int(vals["traffic_bytes_per_launch"])
 
 
-def timed_solves(H, b, x, steps, warmup, rtol):
+class SolveFailed(RuntimeError):
+    """A timed solve did not reach the tolerance: no throughput is reported."""
+
+
+def check_converged(infos, rtol, what):
+    """Every timed solve must have converged with a true relative residual
+    <= rtol, else the line would count solves that are not solves."""
+    bad = [i for i in infos if not i["converged"] or not (i["rel_res_true"] <= rtol)]
+    if bad:
+        raise SolveFailed("%s: %d of %d timed solves missed rtol %.1e (first: %r)"
+                          % (what, len(bad), len(infos), rtol,
+                             {k: bad[0][k] for k in ("converged", "iters", "rel_res_true")}))
+
+
+def timed_solves(H, b, x, steps, warmup, rtol, what="solve"):
     import torch
     infos = []
     for _ in range(warmup):
@@ -233,6 +334,7 @@ def timed_solves(H, b, x, steps, warmup, rtol):
         infos.append(H.gmres_solve(b, x, restart=30, rtol=rtol))
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
+    check_converged(infos, rtol, what)
     return t, infos
 
 
@@ -305,7 +407,6 @@ def grad_bench(cfg, args):
 
     res, out = {}, {}
     for prec in ("fp64", "fp32"):
-        H._blocks_ok = False
         one(0, prec)                                   # warm-up: plan, graphs, tuning
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -416,7 +517,9 @@ def main():
     ap.add_argument("--config", default="c2")
     ap.add_argument("--levels", type=int, default=0, help="override the number of levels")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--bf16", action="store_true", help="also time BF16-stored block inverses")
+    ap.add_argument("--no-bf16", action="store_true", help="skip the BF16-stored block inverses")
+    ap.add_argument("--no-c3", action="store_true",
+                    help="skip the aneurysm-like c3 legs that the default c2 run adds")
     ap.add_argument("--cycle", default="V", choices=["V", "W", "F"], help="multigrid cycle")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run three plain 256 MiB device copies first (counter calibration)")
@@ -550,12 +653,13 @@ def main():
     torch.cuda.synchronize()
     t_adj = time.perf_counter() - t0
     bf = None
-    if args.bf16:
+    if not args.no_bf16:
         H.build_fs_as_blocks(prec="bf16")
         xb = torch.zeros_like(b)
-        tb, infb = timed_solves(H, b, xb, args.steps, 1, rtol)
-        bf = dict(solves_per_s=args.steps / tb, iters=infb[-1]["iters"],
-                  rel_res_true=infb[-1]["rel_res_true"])
+        tb, infb = timed_solves(H, b, xb, args.steps, 1, rtol, "bf16")
+        bf = dict(solves_per_s=round(args.steps / tb, 4), iters=infb[-1]["iters"],
+                  rel_res_true=infb[-1]["rel_res_true"],
+                  over_fp64=round((args.steps / tb) / (args.steps / t64), 3))
         H.build_fs_as_blocks(prec="fp32")
 
     x64h = x64.double()
@@ -579,6 +683,9 @@ def main():
     ceil = copy_ceiling(dev)
     roof["copy_ceiling_gbs"] = round(ceil, 1)
     roof["frac_of_copy"] = round(achieved / ceil, 4)
+    rceil = read_ceiling(dev)
+    roof["read_ceiling_gbs"] = round(rceil, 1)
+    roof["frac_of_read"] = round(achieved / rceil, 4)
     # the other HBM-bound kernels of the path, same live HIP-event timing
     fin = H.L - 1
     model = dict(vspmv=("k_spmv<float> residual, finest", operator_bytes(H, fin, 4, 3)),
@@ -637,7 +744,7 @@ def main():
         comp["max_block"] = int(np.diff(ptr).max())
         comp["fs_over_as_fp32"] = round((args.steps / t32) / comp["fp32"]["solves_per_s"], 3)
         comp["fs_over_as_fp64"] = round((args.steps / t64) / comp["fp64"]["solves_per_s"], 3)
-    except fsgmg.FsgmgError as e:     # e.g. monolithic blocks beyond one workgroup's LDS
+    except (fsgmg.FsgmgError, SolveFailed) as e:   # e.g. monolithic blocks beyond one workgroup's LDS
         comp = dict(not_run=str(e))
 
     out["comparator_as"] = comp
@@ -658,13 +765,22 @@ def main():
                                      for l in range(1, H.L)]
         mult["mult_over_add_fp32"] = round(mult["fp32"]["solves_per_s"] / (args.steps / t32), 3)
         mult["mult_over_add_fp64"] = round(mult["fp64"]["solves_per_s"] / (args.steps / t64), 3)
-    except fsgmg.FsgmgError as e:
+    except (fsgmg.FsgmgError, SolveFailed) as e:
         mult = dict(not_run=str(e))
     out["multiplicative"] = mult
+    if cfg["name"] == "c2" and not args.levels and not args.no_c3:
+        H.close()
+        torch.cuda.empty_cache()
+        out["c3"] = c3_legs(args, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, w, f)
     print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":
-    main()
+    try:
+        main()
+    except SolveFailed as e:
+        print(json.dumps(dict(metric=METRIC, value=None, unit="solves/s", n_gpus=1,
+                              failed=str(e))), flush=True)
+        sys.exit(1)

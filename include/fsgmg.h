@@ -22,7 +22,12 @@
  * elements in vertex order.  Offsets are returned by level_info().
  *
  * Ownership: the handle owns every matrix, transfer, block inverse and
- * Krylov work vector (device memory from hipMalloc on the handle's device).
+ * Krylov work vector.  Their device memory comes from the fsgmg_allocator
+ * given to setup_hierarchy (e.g. a framework's caching allocator), or from
+ * hipMalloc on the handle's device when none is given; the handle returns
+ * all of it through the same allocator in hierarchy_destroy (and earlier
+ * when a rebuild replaces a buffer).  Two small pinned host buffers for
+ * Hessenberg read-backs come from hipHostMalloc.
  * Vector arguments are caller-owned and must not alias each other.
  * Streams: all device work is enqueued on the stream given to
  * setup_hierarchy (NULL = default stream).  vcycle_apply, apply_operator and
@@ -57,6 +62,21 @@ typedef enum {
 
 typedef enum { FSGMG_FP64 = 0, FSGMG_FP32 = 1, FSGMG_BF16 = 2 } fsgmg_prec;
 
+/* Device memory for a handle.  alloc(bytes, stream, user) returns device
+ * memory of at least `bytes` bytes, 256-byte aligned, usable on `stream`
+ * (the stream given to setup_hierarchy), or NULL when it has none (the call
+ * then fails with FSGMG_ENOMEM).  free(ptr, stream, user) takes back a
+ * pointer alloc returned; the library calls it only after every launch of
+ * the handle that may use the memory has finished, so an allocator may hand
+ * the memory out again at once.  Both are called from the thread that
+ * calls into the library, never during a HIP graph capture.  alloc and
+ * free must both be set (or the whole struct be NULL). */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* stream, void* user);
+  void (*free)(void* ptr, void* stream, void* user);
+  void* user;
+} fsgmg_allocator;
+
 /* Multigrid cycle (Section 3.2 admits any): V, W (two coarse cycles per
  * level), F (an F-cycle then a V-cycle on the coarser level). */
 typedef enum { FSGMG_CYCLE_V = 0, FSGMG_CYCLE_W = 1, FSGMG_CYCLE_F = 2 } fsgmg_cycle;
@@ -75,14 +95,17 @@ typedef enum { FSGMG_SCHWARZ_ADDITIVE = 0, FSGMG_SCHWARZ_MULTIPLICATIVE = 1 } fs
  * the face.  A tag applies to every node of the face that belongs to an
  * element of that region.  region: 0 fluid, 1 solid. */
 typedef struct {
-  int dim;                     /* 2 (3 reserved)                          */
+  int dim;                     /* 2 (quadrilaterals) or 3 (hexahedra)     */
   int n_levels;                /* >= 1; level 0 = coarse mesh             */
   int nc[3];                   /* coarse elements per axis                */
   const double* breaks[3];     /* host, nc[a]+1 reference breakpoints     */
   const int8_t* region;        /* host, prod(nc) tags, x fastest          */
   int mapping;                 /* 0 identity, 1 circular bulge, 2 smooth  *
-                                * cos^2 bulge tangent to the wall (2D)    */
-  double map_params[8];        /* bulge: centre x, radius, blend y0, y1   */
+                                * cos^2 bulge tangent to the wall (2D),   *
+                                * 3 square (x, y) section [0,1]^2 onto a  *
+                                * disc (tube along z)                     */
+  double map_params[8];        /* bulge: centre x, radius, blend y0, y1;  *
+                                * disc: centre x, centre y, radius        */
   int8_t bc_d[6][2];
   int8_t bc_u[6][2];
   double inflow_peak;
@@ -104,8 +127,11 @@ typedef struct {
 /* Smoother: cores of core[0] x core[1] elements per region, Vanka halo of
  * `halo` element layers (1 = the paper's selection rule), nu_pre / nu_post
  * Richardson sweeps with damping omega, block inverses and level operators
- * of the V-cycle in `prec` (the coarse solve is always FP64; FSGMG_BF16
- * stores block inverses in bfloat16 and keeps FP32 level operators).
+ * of the V-cycle in `prec` (FSGMG_BF16 stores block inverses in bfloat16
+ * and keeps FP32 level operators).  The coarse solve's inverse and its
+ * accumulation are always FP64; in an FP32 / BF16 cycle its right-hand side
+ * is the FP32 restriction and its result is rounded to FP32 for the
+ * prolongation, like every other vector inside that cycle.
  * use_graph != 0 captures each FGMRES Arnoldi step (V-cycle, operator
  * product, Gram-Schmidt, Hessenberg read-back) and the V-cycle of
  * vcycle_apply as HIP graphs on first use; they are kept by a later
@@ -162,7 +188,7 @@ typedef struct {
 } fsgmg_krylov_opts;
 
 typedef struct {
-  int iters;          /* Arnoldi steps (= preconditioner applications) */
+  int iters;          /* Arnoldi steps                                     */
   int restarts;
   int converged;
   double rel_res_true;
@@ -170,27 +196,45 @@ typedef struct {
   int history_cap;
   int history_len;
   double t_solve_ms;  /* wall time of the call                           */
+  int vcycles;        /* multigrid cycles applied (one per Arnoldi step)  */
+  double t_setup_ms;  /* wall time of the handle's setup_hierarchy        */
+  double t_blocks_ms; /* wall time of its last build_fs_as_blocks         */
 } fsgmg_solve_info;
 
-/* Build the mesh hierarchy, assemble every level operator (re-discretized,
- * Dirichlet rows/columns eliminated symmetrically), the transfers and the
- * coarse FP64 inverse.  device >= 0: upload to that HIP device and use
- * `stream`; device == -1: host-only handle (export_* queries only). */
+/* Build the mesh hierarchy (Section 3.3: nested midpoint refinements with
+ * the same regions on every level), assemble every level operator in the
+ * J2 ordering (Sections 2.2 and 3.1, eq. matrix_J2; re-discretized,
+ * Dirichlet rows/columns eliminated symmetrically), the transfers (Section
+ * 3.3) and the coarse FP64 inverse (the direct solve on level 0 of Section
+ * 3.2).  mesh, phys and the host arrays they point to are read during the
+ * call only.  alloc: device memory for the handle (NULL: hipMalloc).
+ * device >= 0: upload to that HIP device and use `stream`; device == -1:
+ * host-only handle (export_* and dof_map queries only).  *out receives the
+ * handle also on failure (read last_error, then hierarchy_destroy); EINVAL
+ * for an invalid description or parameters, ENOMEM, EHIP. */
 fsgmg_status setup_hierarchy(const fsgmg_mesh_desc* mesh, const fsgmg_physics* phys,
-                             int device, void* stream, fsgmg_h* out);
+                             const fsgmg_allocator* alloc, int device, void* stream,
+                             fsgmg_h* out);
 
-/* Build the FS-AS block index sets (Section 3.2 selection rule, last-writer
- * owner map), gather every block's principal submatrix, invert it in FP64 on
+/* Build the FS-AS block index sets (Section 3.2: the field split P_2 of
+ * eq. FS, its blocks solved by additive Schwarz AS_1 / AS_2 with the Vanka
+ * selection rule and the last-writer owner map), gather every block's principal submatrix, invert it in FP64 on
  * the device (partial pivoting) and keep the owned rows in opts->prec.
  * ESINGULAR (block id in last_error) on a zero pivot.  On a host-only handle
  * only the index sets are built. */
 fsgmg_status build_fs_as_blocks(fsgmg_h h, const fsgmg_smoother_opts* opts);
 
-/* z = M^{-1} r (transpose = 0) or z = M^{-T} r (transpose = 1), one V-cycle. */
+/* z = M^{-1} r (transpose = 0) or z = M^{-T} r (transpose = 1): one cycle of
+ * the geometric multigrid preconditioner of Section 3.2 (damped Richardson
+ * with the FS-AS smoother on levels >= 1, restriction R_2 and prolongation
+ * of Section 3.3, direct solve on level 0); the transpose runs every step
+ * transposed in reverse order.  r, z: device FP64, finest level, r != z.
+ * Asynchronous on the handle's stream.  ESTATE before build_fs_as_blocks,
+ * ESINGULAR when a pending coarse rebuild met a zero pivot. */
 fsgmg_status vcycle_apply(fsgmg_h h, const double* r, double* z, int transpose);
 
-/* The cycle of vcycle_apply (additive smoother; transpose != 0: its exact
- * transpose) on k right-hand sides at once, 1 <= k <= 64: r and z are device
+/* The cycle of vcycle_apply (Section 3.2; additive smoother; transpose != 0:
+ * its exact transpose) on k right-hand sides at once, 1 <= k <= 64: r and z are device
  * FP64 arrays of N * k entries, unknown-major (entry (i, c) at i * k + c: a
  * contiguous N x k row-major matrix), caller-owned, r != z.  Column c of z
  * equals vcycle_apply of column c of r (same transpose flag) up to rounding
@@ -203,11 +247,17 @@ fsgmg_status vcycle_apply(fsgmg_h h, const double* r, double* z, int transpose);
  * build_fs_as_blocks. */
 fsgmg_status vcycle_apply_batch(fsgmg_h h, const double* r, double* z, int k, int transpose);
 
-/* Solve A x = b on the finest level (x is overwritten; x0 = 0). */
+/* Solve A x = b on the finest level: GMRES (Section 3.2's outer solver, here
+ * FGMRES(restart) with CGS2) right-preconditioned by one cycle of
+ * vcycle_apply per iteration.  b, x: device FP64, finest level, b != x; x is
+ * overwritten (x0 = 0).  Returns after the convergence decision; info (host,
+ * optional) receives iterations, restarts, the true relative residual,
+ * times and the residual history.  NOT_CONVERGED leaves the last iterate in
+ * x; EINVAL for NaN/Inf in b or bad options; ESTATE before
+ * build_fs_as_blocks. */
 fsgmg_status gmres_solve(fsgmg_h h, const double* b, double* x,
                          const fsgmg_krylov_opts* opts, fsgmg_solve_info* info);
 
-/* Solve A^T lam = c with the transposed V-cycle as right preconditioner. */
 /* FGMRES of gmres_solve on k right-hand sides at once (1 <= k <= 64, additive
  * smoother): b and x are device FP64 arrays of N * k entries, unknown-major
  * (entry (i, c) at i * k + c), caller-owned, b != x, x overwritten (x0 = 0).
@@ -225,37 +275,71 @@ fsgmg_status gmres_solve_batch(fsgmg_h h, const double* b, double* x, int k,
 fsgmg_status adjoint_solve_batch(fsgmg_h h, const double* c, double* lam, int k,
                                  const fsgmg_krylov_opts* opts, fsgmg_solve_info* infos);
 
+/* Solve A^T lam = c (the adjoint of the linearized system of Sections 2.2
+ * and 3.1) by gmres_solve's FGMRES with A^T and the transposed cycle of
+ * vcycle_apply as right preconditioner.  Same arguments, layout, return and
+ * errors as gmres_solve; A^T and the transposed block inverses are built on
+ * first use. */
 fsgmg_status adjoint_solve(fsgmg_h h, const double* c, double* lam,
                            const fsgmg_krylov_opts* opts, fsgmg_solve_info* info);
 
-/* b = F (L f) + lift: momentum load rho (f_h, phi) (+ SUPG) of a nodal body
- * force f (device, finest N2 x dim), Dirichlet rows set to their values and
- * the Dirichlet lift applied (F zeroes Dirichlet rows). */
+/* b = F (L f) + lift: the momentum load rho (f_h, phi) of the weak form of
+ * Section 2.2 (+ its SUPG counterpart, eq. tausupg) for a nodal body force
+ * f (device, finest N2 x dim), Dirichlet rows set to their values and the
+ * Dirichlet lift applied (F zeroes Dirichlet rows).  Asynchronous. */
 fsgmg_status assemble_load(fsgmg_h h, const double* f_nodal, double* b);
 
-/* gf = (F L)^T lam: the adjoint of assemble_load's linear part, i.e. the
- * gradient of lam^T b with respect to the nodal body force (device, finest
- * N2 x dim output, lam of the finest level size). */
+/* gf = (F L)^T lam: the adjoint of assemble_load's linear part (the load of
+ * Section 2.2), i.e. the gradient of lam^T b with respect to the nodal body
+ * force (device, finest N2 x dim output, lam of the finest level size). */
 fsgmg_status load_adjoint(fsgmg_h h, const double* lam, double* gf);
 
-/* y = A_l x or A_l^T x on level `level` (FP64 operator, device vectors of
- * that level's size). */
+/* y = A_l x or A_l^T x on level `level`: the linearized operator J2 of eq.
+ * matrix_J2 (Sections 2.2, 3.1) re-discretized on that level, FP64, device
+ * vectors of that level's size, x != y.  Asynchronous. */
 fsgmg_status apply_operator(fsgmg_h h, int level, const double* x, double* y, int transpose);
 
 /* out[0] = -(F lam)^T dA/dE x, out[1] = -(F lam)^T dA/dmu x on the finest
- * level (unreduced derivative, tau frozen); lam, x device; out host. */
+ * level: the parameter gradients of a functional through the adjoint of the
+ * system of Section 2.2 (E enters the solid stress through G and lambda_L,
+ * mu the fluid stress and the Dirichlet lift; unreduced derivative, SUPG
+ * tau frozen); lam, x device; out host (synchronizes). */
 fsgmg_status param_grad(fsgmg_h h, const double* lam, const double* x, double out[2]);
 
 /* Recombine every level operator and the Dirichlet lift for new (E, mu)
- * from the stored affine pieces (SUPG tau frozen at setup).  Invalidates the
+ * from the stored affine pieces of the Section 2.2 operator (it is affine in
+ * G, 1/lambda_L and mu; SUPG tau frozen at setup).  Invalidates the
  * blocks: call build_fs_as_blocks again.  The coarse inverse is rebuilt on
  * the handle's stream without waiting for it (the call returns at once); the
  * next cycle or solve checks it and returns FSGMG_ESINGULAR if the coarse
  * matrix turned out singular. */
 fsgmg_status update_params(fsgmg_h h, double E, double mu);
 
+/* Test hook that makes FSGMG_ESINGULAR observable with valid data: the next
+ * build_fs_as_blocks replaces the gathered matrix of Schwarz block `block`
+ * (export_blocks numbering) of level `level` (1 .. L-1) by zeros before
+ * inverting it, so that block's first pivot is zero and the call returns
+ * FSGMG_ESINGULAR naming it in last_error; every kernel still runs to its
+ * normal end (the zero-pivot exit leaves an identity column permutation
+ * for the owned-row extraction).  The hook applies once; block < 0 clears
+ * it.  A block id beyond the level's blocks never matches (no effect).
+ * EINVAL for a level out of range. */
+fsgmg_status debug_zero_block(fsgmg_h h, int level, int64_t block);
+
 /* out[0..8] = N, N2, Nps, Npf, off_ps, off_u, off_pf, nnz(A_l), dim. */
 fsgmg_status level_info(fsgmg_h h, int level, int64_t out[9]);
+
+/* What each unknown of level `level` is (the J2 unknowns of eq. matrix_J2 in
+ * the vector layout above).  *n: in, the length of the output arrays; out,
+ * the level's number of unknowns N (call with every array NULL to get it).
+ * Per unknown i (host arrays, each optional): field[i] 0 = d, 1 = p^s,
+ * 2 = u, 3 = p^f; comp[i] the vector component (0 for pressures); node[i]
+ * the Q2 node (d, u) or Q1 vertex (pressures) index, both x-fastest on the
+ * level's node / vertex lines; xyz[3 i .. 3 i + 2] the physical coordinates
+ * of that node (z = 0 in 2D).  EINVAL for a bad level or arrays shorter
+ * than N.  Valid on host-only handles. */
+fsgmg_status dof_map(fsgmg_h h, int level, int64_t* n, int32_t* field, int32_t* comp,
+                     int32_t* node, double* xyz);
 
 /* Host copies of setup data (inspection and tests).  which: 0 reduced level
  * operator A_l, 1 prolongation P_l (level l from l-1, Dirichlet-masked),

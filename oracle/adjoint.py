@@ -25,9 +25,10 @@ from .mesh import Level
 
 
 def outlet_flux_vector(lv: Level) -> np.ndarray:
-    """c with c^T x = int over the fluid part of the x-max face of u.n ds (2D)."""
-    if lv.D != 2:
-        raise NotImplementedError
+    """c with c^T x = int over the fluid part of the outlet face of u.n ds:
+    the x-max face in 2D, the z-max face in 3D (the tube's axis)."""
+    if lv.D == 3:
+        return _outlet_flux_vector_3d(lv)
     c = np.zeros(lv.N)
     nx, ny = lv.ne
     L, dL, _ = q2_1d(GAUSS_PTS)
@@ -44,6 +45,38 @@ def outlet_flux_vector(lv: Level) -> np.ndarray:
                 wphi = GAUSS_W[q] * L[q, a]
                 c[lv.u(nodes[a], 0)] += wphi * t[1]
                 c[lv.u(nodes[a], 1)] += -wphi * t[0]
+    return c
+
+
+def _outlet_flux_vector_3d(lv: Level) -> np.ndarray:
+    """The z-max face of every fluid element of the last element layer: the
+    face's 3 x 3 Q2 trace nodes (local z index 2), 3 x 3 Gauss points, and
+    n dS = (dX/dxi x dX/deta) dxi deta on the face parametrized by the
+    element's reference (xi, eta), which points along +z (outward)."""
+    c = np.zeros(lv.N)
+    nx, ny, nz = lv.ne
+    L, dL, _ = q2_1d(GAUSS_PTS)
+    for ey in range(ny):
+        for ex in range(nx):
+            e = ex + nx * (ey + ny * (nz - 1))
+            if lv.region[e] != 0:
+                continue
+            # local node (a, b, 2) with a, b in 0..2, x fastest
+            loc = np.array([a + 3 * b + 18 for b in range(3) for a in range(3)])
+            nodes = lv.elem_nodes[e][loc]
+            X = lv.X[nodes].reshape(3, 3, 3)              # (b, a, xyz)
+            for qa in range(3):
+                for qb in range(3):
+                    t1 = np.einsum("a,bac->c", dL[qa], X * L[qb][:, None, None])
+                    t2 = np.einsum("b,bac->c", dL[qb], X * L[qa][None, :, None])
+                    n = np.cross(t1, t2)
+                    wq = GAUSS_W[qa] * GAUSS_W[qb]
+                    for b in range(3):
+                        for a in range(3):
+                            phi = wq * L[qa, a] * L[qb, b]
+                            node = nodes[a + 3 * b]
+                            for comp in range(3):
+                                c[lv.u(node, comp)] += phi * n[comp]
     return c
 
 

@@ -69,6 +69,17 @@ def physical_map(cfg: dict, xref: np.ndarray) -> np.ndarray:
         s = np.clip((xref[:, 1] - ya) / (yb - ya), 0.0, 1.0)
         x[:, 1] = xref[:, 1] + bump * s
         return x
+    if cfg["mapping"] == 3:
+        # the square cross-section [0,1]^2 onto a disc of centre (cx, cy) and
+        # radius R: with a, b the section coordinates scaled to [-1, 1],
+        # x' = a sqrt(1 - b^2/2), y' = b sqrt(1 - a^2/2) sends each edge of
+        # the square onto the circle; the axis coordinate is unchanged
+        cx, cy, R = cfg["map_params"][:3]
+        a = 2.0 * xref[:, 0] - 1.0
+        b = 2.0 * xref[:, 1] - 1.0
+        x[:, 0] = cx + R * a * np.sqrt(1.0 - 0.5 * b * b)
+        x[:, 1] = cy + R * b * np.sqrt(1.0 - 0.5 * a * a)
+        return x
     raise ValueError("unknown mapping %r" % cfg["mapping"])
 
 

@@ -2,36 +2,41 @@
 
     x = FSISolve.apply(f, E, mu, hierarchy, opts)
 
-forward: b = assemble_load(f) (momentum load plus the Dirichlet lift, which
-depends on mu through the fluid rows), blocks refactored when (E, mu)
-changed (update_params + build_fs_as_blocks), x = gmres_solve(b).
+forward: the handle is brought to (E, mu) with blocks built for the smoother
+options in opts (update_params and build_fs_as_blocks only when the handle
+holds other parameters or blocks built with other options), b =
+assemble_load(f) (momentum load plus the Dirichlet lift, which depends on mu
+through the fluid rows), x = gmres_solve(b).
 backward, for an incoming gradient g = dL/dx:
     A^T lam = g                      (adjoint_solve: FGMRES with the
                                       transposed FS-AS V-cycle)
     dL/df  = (F L)^T lam             (load_adjoint)
     dL/dE  = -(F lam)^T dA/dE  x     (param_grad; includes the lift's
     dL/dmu = -(F lam)^T dA/dmu x      dependence, SUPG tau held fixed)
+The operator of the adjoint is the forward's: (E, mu) and the smoother
+options are saved with the forward, and the handle is brought back to them
+before the adjoint solve when other solves ran on it in between (several
+forwards on one handle, then one backward of their summed loss).
 Argument marshalling only: every step runs in the library.
 """
 from __future__ import annotations
 
 import torch
 
-from . import fsgmg
+
+def _split(opts):
+    opts = dict(opts or {})
+    krylov = dict(restart=opts.pop("restart", 30), max_restarts=opts.pop("max_restarts", 20),
+                  rtol=opts.pop("rtol", 1e-10))
+    return opts, krylov
 
 
 class FSISolve(torch.autograd.Function):
     @staticmethod
     def forward(ctx, f, E, mu, H, opts=None):
-        opts = dict(opts or {})
-        krylov = dict(restart=opts.pop("restart", 30), max_restarts=opts.pop("max_restarts", 20),
-                      rtol=opts.pop("rtol", 1e-10))
+        sopts, krylov = _split(opts)
         Ev, muv = float(E), float(mu)
-        if (Ev, muv) != (float(H.cfg["E"]), float(H.cfg["mu"])) or not getattr(H, "_blocks_ok", False):
-            if (Ev, muv) != (float(H.cfg["E"]), float(H.cfg["mu"])):
-                H.update_params(Ev, muv)
-            H.build_fs_as_blocks(**opts)
-            H._blocks_ok = True
+        H.ensure_blocks(Ev, muv, **sopts)
         b = torch.empty(H.N, dtype=torch.float64, device=f.device)
         H.assemble_load(f.detach().contiguous().view(-1), b)
         x = torch.empty_like(b)
@@ -39,6 +44,7 @@ class FSISolve(torch.autograd.Function):
         if not info["converged"]:
             raise RuntimeError("forward solve did not converge: %r" % info)
         ctx.H, ctx.krylov, ctx.fshape = H, krylov, f.shape
+        ctx.params, ctx.sopts = (Ev, muv), sopts
         ctx.save_for_backward(x)
         ctx.info = info
         return x
@@ -47,6 +53,7 @@ class FSISolve(torch.autograd.Function):
     def backward(ctx, gx):
         (x,) = ctx.saved_tensors
         H = ctx.H
+        H.ensure_blocks(*ctx.params, **ctx.sopts)
         lam = torch.empty_like(x)
         info = H.adjoint_solve(gx.contiguous(), lam, **ctx.krylov)
         if not info["converged"]:

@@ -1643,6 +1643,164 @@ __global__ __launch_bounds__(kThreads) void k_cgj_update_r(const double* __restr
   }
 }
 
+// Wide-panel variant for coarse matrices whose LDS panel does not fit
+// (np > 4096): the same Gauss-Jordan steps on a strip of kCgjWide columns
+// held in the work matrix itself, one column at a time over the whole GPU,
+// then the strip's row interchanges and a rank-kCgjWide update of every
+// other column (k_cgj_update), so the matrix is streamed once per
+// kCgjWide columns.  np is a multiple of kCgjWide on this path.
+//  * k_cgjw_pivot (one workgroup): pivot p of column c = k0 + kk (largest
+//    magnitude at or below the diagonal, smallest row on ties), a snapshot
+//    of column c (tcol), the scaled pivot row over the strip (rc[0, W))
+//    and the old row c over the strip (rc[W, 2W));
+//  * k_cgjw_elim (whole grid, one thread per strip entry): row c takes the
+//    scaled pivot row, row p the eliminated old row c, every other row r
+//    a[r][q] - tcol[r] rc[q] (zero in column c);
+//  * k_cgjw_swap (whole grid, one thread per column outside the strip):
+//    the composition of the strip's interchanges (new row swl[x] = old row
+//    swv[x], at most 2W rows) and the strip's pivot rows into ybuf.
+constexpr int kCgjWide = 64;
+constexpr int kCgjwThreads = 1024;
+
+__global__ __launch_bounds__(kCgjwThreads) void k_cgjw_pivot(const double* __restrict__ a,
+                                                             int64_t np, int64_t k0, int kk,
+                                                             int32_t* __restrict__ piv,
+                                                             double* __restrict__ tcol,
+                                                             double* __restrict__ rc,
+                                                             int32_t* __restrict__ status) {
+  constexpr int NW = kCgjwThreads / 64;
+  __shared__ double wval[NW];
+  __shared__ int64_t widx[NW];
+  if (status[0]) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int64_t c = k0 + kk;
+  double best = -1.0;
+  int64_t bi = np;
+  for (int64_t r = c + tid; r < np; r += kCgjwThreads) {
+    const double v = fabs(a[r * np + c]);
+    if (v > best) {
+      best = v;
+      bi = r;
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double v2 = __shfl_xor(best, off, 64);
+    const int64_t i2 = __shfl_xor(bi, off, 64);
+    if (v2 > best || (v2 == best && i2 < bi)) {
+      best = v2;
+      bi = i2;
+    }
+  }
+  if (lane == 0) {
+    wval[wv] = best;
+    widx[wv] = bi;
+  }
+  __syncthreads();
+  best = wval[0];
+  bi = widx[0];
+  for (int w = 1; w < NW; ++w)
+    if (wval[w] > best || (wval[w] == best && widx[w] < bi)) {
+      best = wval[w];
+      bi = widx[w];
+    }
+  if (!(best > 0.0)) {   // the same decision in every thread
+    if (tid == 0) status[0] = 1;
+    return;
+  }
+  const int64_t p = bi;
+  for (int64_t r = tid; r < np; r += kCgjwThreads) tcol[r] = a[r * np + c];
+  const double d = 1.0 / a[p * np + c];
+  for (int q = tid; q < kCgjWide; q += kCgjwThreads) {
+    rc[q] = (q == kk) ? d : a[p * np + k0 + q] * d;
+    rc[kCgjWide + q] = a[c * np + k0 + q];
+  }
+  if (tid == 0) piv[c] = (int32_t)p;
+}
+
+__global__ __launch_bounds__(kThreads) void k_cgjw_elim(double* __restrict__ a, int64_t np,
+                                                        int64_t k0, int kk,
+                                                        const int32_t* __restrict__ piv,
+                                                        const double* __restrict__ tcol,
+                                                        const double* __restrict__ rc,
+                                                        const int32_t* __restrict__ status) {
+  if (status[0]) return;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= np * kCgjWide) return;
+  const int64_t r = e / kCgjWide;
+  const int q = (int)(e - r * kCgjWide);
+  const int64_t c = k0 + kk, p = piv[c];
+  double* ar = a + r * np + k0;
+  if (r == c) {
+    ar[q] = rc[q];
+  } else if (r == p) {
+    ar[q] = (q == kk ? 0.0 : rc[kCgjWide + q]) - tcol[c] * rc[q];
+  } else {
+    ar[q] = (q == kk ? 0.0 : ar[q]) - tcol[r] * rc[q];
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_cgjw_swap(double* __restrict__ a, int64_t np,
+                                                        int64_t k0,
+                                                        const int32_t* __restrict__ piv,
+                                                        double* __restrict__ ybuf,
+                                                        const int32_t* __restrict__ status) {
+  __shared__ int64_t swl[2 * kCgjWide], swv[2 * kCgjWide];
+  __shared__ int swn;
+  if (status[0]) return;
+  if (threadIdx.x == 0) {
+    int ns = 0;
+    for (int kk = 0; kk < kCgjWide; ++kk) {
+      const int64_t c = k0 + kk, p = piv[c];
+      if (p == c) continue;
+      int ic = -1, ip = -1;
+      for (int x = 0; x < ns; ++x) {
+        if (swl[x] == c) ic = x;
+        if (swl[x] == p) ip = x;
+      }
+      if (ic < 0) {
+        swl[ns] = c;
+        swv[ns] = c;
+        ic = ns++;
+      }
+      if (ip < 0) {
+        swl[ns] = p;
+        swv[ns] = p;
+        ip = ns++;
+      }
+      const int64_t t = swv[ic];
+      swv[ic] = swv[ip];
+      swv[ip] = t;
+    }
+    swn = ns;
+  }
+  __syncthreads();
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= np - kCgjWide) return;
+  const int64_t col = j < k0 ? j : j + kCgjWide;   // columns outside the strip
+  const int ns = swn;
+  for (int x0 = 0; x0 < ns; x0 += 16) {
+    double v[16];
+#pragma unroll
+    for (int x = 0; x < 16; ++x)
+      if (x0 + x < ns) v[x] = a[swv[x0 + x] * np + col];
+    // all reads of the composition come before any write: a later group
+    // may read a row this group writes, so stage the whole list first
+    if (ns <= 16) {
+#pragma unroll
+      for (int x = 0; x < 16; ++x)
+        if (x0 + x < ns) a[swl[x0 + x] * np + col] = v[x];
+    } else {
+#pragma unroll
+      for (int x = 0; x < 16; ++x)
+        if (x0 + x < ns) ybuf[(int64_t)(kCgjWide + x0 + x) * np + col] = v[x];
+    }
+  }
+  if (ns > 16)
+    for (int x = 0; x < ns; ++x) a[swl[x] * np + col] = ybuf[(int64_t)(kCgjWide + x) * np + col];
+  for (int q = 0; q < kCgjWide; ++q) ybuf[(int64_t)q * np + col] = a[(k0 + q) * np + col];
+}
+
 // inverse[i][q] = a[i][sigma[q]] and its transpose, i, q < n
 __global__ __launch_bounds__(kThreads) void k_cgj_finish(const double* __restrict__ a, int64_t np,
                                                          int64_t n, const int32_t* __restrict__ sigma,
@@ -3032,8 +3190,12 @@ void launch_masked_dot(const double* a, const uint8_t* mask, const double* b, in
 }
 
 int coarse_panel_width(int64_t np, int max_lds) {
-  return (size_t)np * 9 * 8 <= (size_t)max_lds ? 8 : 4;
+  if ((size_t)np * 9 * 8 <= (size_t)max_lds) return 8;
+  if ((size_t)np * 5 * 8 <= (size_t)max_lds) return 4;
+  return kCgjWide;
 }
+
+int coarse_wide_panel() { return kCgjWide; }
 
 namespace {
 template <int RPT>
@@ -3072,6 +3234,26 @@ const double* launch_coarse_factor(int64_t n, int64_t np, const int64_t* rp, con
   const int64_t ntile = np / 16;
   const int64_t items = ntile * ((ntile + 3) / 4);
   const unsigned gu = grid_for(items * 64, kThreads);
+  if (nb == kCgjWide) {
+    // ybuf: kCgjWide pivot rows + 2 kCgjWide staged rows (np each), tcol (np), rc (2 kCgjWide)
+    double* tcol = ybuf + (int64_t)3 * kCgjWide * np;
+    double* rc = tcol + np;
+    const unsigned ge = grid_for(np * kCgjWide, kThreads);
+    const unsigned gs = grid_for(np - kCgjWide, kThreads);
+    for (int64_t k0 = 0; k0 < np; k0 += kCgjWide) {
+      for (int kk = 0; kk < kCgjWide; ++kk) {
+        hipLaunchKernelGGL(k_cgjw_pivot, dim3(1), dim3(kCgjwThreads), 0, s, a, np, k0, kk, piv,
+                           tcol, rc, status);
+        hipLaunchKernelGGL(k_cgjw_elim, dim3(ge), dim3(kThreads), 0, s, a, np, k0, kk, piv, tcol,
+                           rc, status);
+      }
+      if (gs) hipLaunchKernelGGL(k_cgjw_swap, dim3(gs), dim3(kThreads), 0, s, a, np, k0, piv, ybuf,
+                                 status);
+      hipLaunchKernelGGL((k_cgj_update<kCgjWide>), dim3(gu), dim3(kThreads), 0, s, a, np, k0, ybuf,
+                         status);
+    }
+    return a;
+  }
   const size_t sm = (size_t)np * (nb + 1) * sizeof(double);
   for (int64_t k0 = 0; k0 < np; k0 += nb) {
     if (nb == 8) {

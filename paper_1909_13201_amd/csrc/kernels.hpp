@@ -267,7 +267,11 @@ void launch_extract_owned(const int32_t* jlist, int64_t nb, const BlocksView& B,
 // matrix that holds the result.  After piv has been turned into the column
 // permutation sigma (inverse[:, q] = result[:, sigma[q]]),
 // launch_coarse_finish writes the n x n inverse and its transpose.
+// 8 or 4 (LDS panels), or coarse_wide_panel() when np x 5 doubles exceed the
+// LDS: then np must be a multiple of coarse_wide_panel() and the scratch
+// after the work matrix must hold (3 W + 1) np + 2 W doubles (W the width)
 int coarse_panel_width(int64_t np, int max_lds);
+int coarse_wide_panel();
 bool coarse_register_path(int64_t np);
 // sigma from the pivot list on the device (one workgroup, coarse_sigma_lds(np)
 // bytes of LDS); the identity when status[0] reports a zero pivot

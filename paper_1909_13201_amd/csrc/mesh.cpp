@@ -80,6 +80,16 @@ static void map_point(const fsgmg_mesh_desc& m, const double* xr, double* x) {
     x[1] = xr[1] + bump * s;
     return;
   }
+  if (m.mapping == 3) {
+    // square cross-section [0,1]^2 onto the disc of centre (cx, cy) and
+    // radius R (x' = a sqrt(1 - b^2 / 2), y' = b sqrt(1 - a^2 / 2) with
+    // a, b in [-1, 1]: the square's edges land on the circle); z unchanged
+    const double cx = m.map_params[0], cy = m.map_params[1], R = m.map_params[2];
+    const double a = 2.0 * xr[0] - 1.0, b = 2.0 * xr[1] - 1.0;
+    x[0] = cx + R * a * std::sqrt(1.0 - 0.5 * b * b);
+    x[1] = cy + R * b * std::sqrt(1.0 - 0.5 * a * a);
+    return;
+  }
   throw std::invalid_argument("unknown mapping");
 }
 

@@ -237,6 +237,8 @@ struct FactorPlan {
   };
   bool ready = false;
   std::vector<Chunk> chunks;
+  std::vector<int32_t> order;    // host copy of jlist (blocks by size)
+  std::vector<int64_t> hoffs;    // host copy of offs
   int32_t* jlist = nullptr;
   int64_t* offs = nullptr;
   double* dense = nullptr;
@@ -293,6 +295,14 @@ struct fsgmg_hierarchy {
   int device = -1;
   hipStream_t stream = nullptr;
   std::string err;
+  // device memory comes from the caller's allocator when one was given
+  fsgmg_allocator alloc{nullptr, nullptr, nullptr};
+  bool user_alloc() const { return alloc.alloc != nullptr; }
+  // wall times of setup_hierarchy and of the last build_fs_as_blocks
+  double t_setup_ms = 0, t_blocks_ms = 0;
+  // debug_zero_block: the next factorization zeroes this block's matrix
+  int zero_block_level = -1;
+  int64_t zero_block = -1;
   // host setup data
   std::vector<Level> levels;
   std::vector<LevelOperator> ops;
@@ -311,6 +321,7 @@ struct fsgmg_hierarchy {
   double* coarse_work = nullptr;
   int32_t* coarse_piv = nullptr;
   int64_t n0 = 0;
+  int64_t coarse_np = 0;   // padded order of the coarse work matrix
   // finest-level extras
   int64_t* load_rp = nullptr;
   int32_t* load_col = nullptr;
@@ -385,13 +396,35 @@ struct fsgmg_hierarchy {
     return ev_pool[ev_used++];
   }
 
-  void* dalloc(size_t bytes) {
+  // Device memory: the caller's allocator, else hipMalloc; nullptr when
+  // neither has room (no exception).
+  void* raw_alloc(size_t bytes) {
     void* p = nullptr;
-    if (bytes == 0) bytes = 16;
-    if (hipMalloc(&p, bytes) != hipSuccess || !p) {
+    if (user_alloc()) {
+      p = alloc.alloc(bytes, (void*)stream, alloc.user);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
       (void)hipGetLastError();
-      throw Fail{FSGMG_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+      p = nullptr;
     }
+    return p;
+  }
+  void raw_free(void* p) {
+    if (!p) return;
+    if (user_alloc()) {
+      // a caller's allocator may hand the memory out again at once on its
+      // stream: every launch of this handle that may still use it ends first
+      quiesce();
+      alloc.free(p, (void*)stream, alloc.user);
+    } else {
+      (void)hipFree(p);
+    }
+  }
+  void quiesce();
+  void* dalloc(size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    void* p = raw_alloc(bytes);
+    if (!p)
+      throw Fail{FSGMG_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed"};
     allocs.push_back(p);
     return p;
   }
@@ -432,7 +465,7 @@ struct fsgmg_hierarchy {
     if (!p) return;
     auto it = std::find(allocs.begin(), allocs.end(), p);
     if (it != allocs.end()) {
-      (void)hipFree(p);
+      raw_free(p);
       allocs.erase(it);
     }
   }
@@ -454,12 +487,28 @@ struct fsgmg_hierarchy {
       for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
       invalidate_graphs();
       if (cap_stream) (void)hipStreamDestroy(cap_stream);
-      for (void* p : allocs) (void)hipFree(p);
+      quiesce();
+      for (void* p : allocs) {
+        if (user_alloc())
+          alloc.free(p, (void*)stream, alloc.user);
+        else
+          (void)hipFree(p);
+      }
       if (pinned) (void)hipHostFree(pinned);
       if (mc_pinned) (void)hipHostFree(mc_pinned);
     }
   }
 };
+
+// Wait for every stream this handle launches on (its own, the capture
+// stream and the per-level factorization streams).
+void fsgmg_hierarchy::quiesce() {
+  if (device < 0) return;
+  (void)hipStreamSynchronize(stream);
+  if (cap_stream) (void)hipStreamSynchronize(cap_stream);
+  for (DLevel& d : dl)
+    if (d.fp.stream) (void)hipStreamSynchronize(d.fp.stream);
+}
 
 namespace {
 
@@ -624,7 +673,7 @@ void ensure_coarse(fsgmg_hierarchy& h) {
   HIPCHECK(hipEventSynchronize(h.coarse_done));
   h.coarse_pending = false;
   int32_t st = 0;
-  const int64_t np = (h.ops[0].A.nrows + 15) & ~(int64_t)15;
+  const int64_t np = h.coarse_np;
   HIPCHECK(hipMemcpyAsync(&st, h.coarse_piv + 2 * np, sizeof(int32_t), hipMemcpyDeviceToHost,
                           h.stream));
   HIPCHECK(hipStreamSynchronize(h.stream));
@@ -641,24 +690,29 @@ void ensure_coarse(fsgmg_hierarchy& h) {
 void build_coarse_inverse(fsgmg_hierarchy& h, bool async = false) {
   const int64_t n = h.ops[0].A.nrows;
   if (n > 20000) throw Fail{FSGMG_EINVAL, "coarse level too large for the dense inverse (n > 20000)"};
-  const int64_t np = (n + 15) & ~(int64_t)15;
+  int64_t np = (n + 15) & ~(int64_t)15;
   int max_lds = 0;
   HIPCHECK(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h.device));
   const int nb = coarse_panel_width(np, max_lds);
   const bool reg = coarse_register_path(np);
-  if (!reg && (size_t)np * (nb + 1) * 8 > (size_t)max_lds)
-    throw Fail{FSGMG_EINVAL, "coarse level too large for the panel factorization"};
+  const int64_t W = coarse_wide_panel();
+  const bool wide = !reg && nb == W;
+  if (wide) np = (n + W - 1) / W * W;   // whole strips on the wide-panel path
+  // scratch after the work matrix: panel rows (LDS paths), or pivot rows,
+  // staged interchanges, the pivot column and the scaled pivot row (wide)
+  const int64_t scratch = wide ? (3 * W + 1) * np + 2 * W : 8 * np;
   if (!h.coarse_inv) {
     h.coarse_inv = (double*)h.dalloc((size_t)(n * n) * sizeof(double));
     h.coarse_invT = (double*)h.dalloc((size_t)(n * n) * sizeof(double));
-    // work matrix + panel scratch, and the second work matrix of the register path
-    h.coarse_work = (double*)h.dalloc((size_t)((reg ? 2 : 1) * np * np + 8 * np) * sizeof(double));
+    // work matrix + scratch, and the second work matrix of the register path
+    h.coarse_work = (double*)h.dalloc((size_t)((reg ? 2 : 1) * np * np + scratch) * sizeof(double));
     // pivots, sigma, status, source rows
     h.coarse_piv = (int32_t*)h.dalloc((size_t)(3 * np + 1) * sizeof(int32_t));
   }
+  h.coarse_np = np;
   int32_t* status = h.coarse_piv + 2 * np;
   int32_t* src = h.coarse_piv + 2 * np + 1;
-  double* a2 = reg ? h.coarse_work + np * np + 8 * np : nullptr;
+  double* a2 = reg ? h.coarse_work + np * np + scratch : nullptr;
   const DLevel& C = h.dl[0];   // device CSR of level 0 (current parameter values)
   int32_t* dsig = h.coarse_piv + np;
   if (async && coarse_sigma_lds(np) <= (size_t)max_lds) {
@@ -998,6 +1052,8 @@ void plan_factor(fsgmg_hierarchy& h, int l) {
   }
   fp.jlist = h.upload(order);
   fp.offs = h.upload(hoff);
+  fp.order = order;
+  fp.hoffs = hoff;
   fp.dense = (double*)h.dalloc(maxchunk);
   fp.sigma = (int32_t*)h.dalloc(maxsig);
   fp.status = (int32_t*)h.dalloc((size_t)nb * sizeof(int32_t));
@@ -1031,6 +1087,13 @@ void factor_blocks(fsgmg_hierarchy& h) {
       const int64_t* doff = fp.offs + c.off;
       const int64_t* soff = doff + cnt + 1;
       launch_gather_blocks(jl, cnt, d.bv, d.rp, d.col, d.val, doff, fp.dense, fp.stream);
+      if (h.zero_block_level == l)
+        for (int64_t b = 0; b < cnt; ++b)
+          if (fp.order[c.b0 + b] == h.zero_block) {
+            // test hook: a zero matrix, so the block's first pivot is zero
+            const int64_t o = fp.hoffs[c.off + b], n2 = fp.hoffs[c.off + b + 1] - o;
+            launch_fill<double>(fp.dense + o, 0.0, n2, fp.stream);
+          }
       launch_invert_blocks(jl, cnt, d.bv.dof_ptr, doff, soff, fp.dense, fp.sigma, fp.status,
                            c.max_n, fp.stream);
       launch_extract_owned(jl, cnt, d.bv, doff, soff, fp.dense, fp.sigma, wprec(h.sopt.prec),
@@ -1787,6 +1850,9 @@ fsgmg_status fgmres_batch(fsgmg_hierarchy& h, const double* b, double* x, int K,
       infos[c].rel_res_true = true_rel[c];
       infos[c].history_len = 0;
       infos[c].t_solve_ms = ms;
+      infos[c].vcycles = iters[c];
+      infos[c].t_setup_ms = h.t_setup_ms;
+      infos[c].t_blocks_ms = h.t_blocks_ms;
     }
   }
   return ok ? FSGMG_OK : FSGMG_NOT_CONVERGED;
@@ -1900,6 +1966,9 @@ fsgmg_status fgmres(fsgmg_hierarchy& h, const double* b, double* x, const fsgmg_
       for (int i = 0; i < std::min(info->history_cap, (int)hist.size()); ++i) info->history[i] = hist[i];
     info->t_solve_ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    info->vcycles = iters;
+    info->t_setup_ms = h.t_setup_ms;
+    info->t_blocks_ms = h.t_blocks_ms;
   }
   return converged ? FSGMG_OK : FSGMG_NOT_CONVERGED;
 }
@@ -1916,24 +1985,23 @@ fsgmg_status fgmres(fsgmg_hierarchy& h, const double* b, double* x, const fsgmg_
 // the launch alone; the median of five after one warm-up.
 struct Flush {
   static constexpr int64_t kBytes = int64_t(512) << 20;   // twice the 256 MB cache
+  fsgmg_hierarchy& h;
   void* buf = nullptr;
   uint32_t* sink = nullptr;
-  explicit Flush(hipStream_t s) {
-    if (hipMalloc(&buf, kBytes + 256) != hipSuccess) {
+  explicit Flush(fsgmg_hierarchy& hh) : h(hh) {
+    buf = h.raw_alloc(kBytes + 256);
+    if (!buf) return;   // no room: the candidates are timed warm
+    if (hipMemsetAsync(buf, 0, kBytes + 256, h.stream) != hipSuccess ||
+        hipStreamSynchronize(h.stream) != hipSuccess) {
       (void)hipGetLastError();
-      buf = nullptr;   // no room: the candidates are timed warm
-      return;
-    }
-    if (hipMemsetAsync(buf, 0, kBytes + 256, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
-      (void)hipGetLastError();
-      (void)hipFree(buf);
+      h.raw_free(buf);
       buf = nullptr;
       return;
     }
     sink = reinterpret_cast<uint32_t*>(static_cast<char*>(buf) + kBytes);
   }
   ~Flush() {
-    if (buf) (void)hipFree(buf);
+    if (buf) h.raw_free(buf);
   }
   Flush(const Flush&) = delete;
   Flush& operator=(const Flush&) = delete;
@@ -1960,7 +2028,7 @@ float time_launch(fsgmg_hierarchy& h, const Flush& fl, F&& f) {
 
 template <typename TV>
 void autotune_impl(fsgmg_hierarchy& h) {
-  const Flush fl(h.stream);
+  const Flush fl(h);
   const bool was_timing = h.timing;
   h.timing = false;
   h.tune.assign(h.L, {});
@@ -2099,16 +2167,22 @@ void check_device(fsgmg_hierarchy& h) {
 // ===========================================================================
 // C ABI
 // ===========================================================================
+static fsgmg_status build_fs_as_blocks_impl(fsgmg_h h, const fsgmg_smoother_opts* opts);
+
 extern "C" {
 
-fsgmg_status setup_hierarchy(const fsgmg_mesh_desc* mesh, const fsgmg_physics* phys, int device,
-                             void* stream, fsgmg_h* out) {
+fsgmg_status setup_hierarchy(const fsgmg_mesh_desc* mesh, const fsgmg_physics* phys,
+                             const fsgmg_allocator* alloc, int device, void* stream, fsgmg_h* out) {
   if (!mesh || !phys || !out) return FSGMG_EINVAL;
   *out = nullptr;
+  const auto t0 = std::chrono::steady_clock::now();
   auto h = std::make_unique<fsgmg_hierarchy>();
   h->device = device;
   h->stream = (hipStream_t)stream;
   fsgmg_status st = guarded(h.get(), [&]() -> fsgmg_status {
+    if (alloc && (!alloc->alloc) != (!alloc->free))
+      throw Fail{FSGMG_EINVAL, "an allocator needs both alloc and free"};
+    if (alloc && alloc->alloc) h->alloc = *alloc;
     if (mesh->dim != 2 && mesh->dim != 3) throw Fail{FSGMG_EINVAL, "dim must be 2 or 3"};
     if (mesh->n_levels < 1 || mesh->n_levels > 12) throw Fail{FSGMG_EINVAL, "n_levels out of range"};
     int64_t nce = 1;
@@ -2168,6 +2242,8 @@ fsgmg_status setup_hierarchy(const fsgmg_mesh_desc* mesh, const fsgmg_physics* p
       upload_all(*h);
       HIPCHECK(hipStreamSynchronize(h->stream));
     }
+    h->t_setup_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return FSGMG_OK;
   });
   // on failure the handle is still returned so that last_error() can be read;
@@ -2178,6 +2254,15 @@ fsgmg_status setup_hierarchy(const fsgmg_mesh_desc* mesh, const fsgmg_physics* p
 
 fsgmg_status build_fs_as_blocks(fsgmg_h h, const fsgmg_smoother_opts* opts) {
   if (!h || !opts) return FSGMG_EINVAL;
+  const auto t0 = std::chrono::steady_clock::now();
+  const fsgmg_status st = build_fs_as_blocks_impl(h, opts);
+  if (st == FSGMG_OK)
+    h->t_blocks_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return st;
+}
+
+static fsgmg_status build_fs_as_blocks_impl(fsgmg_h h, const fsgmg_smoother_opts* opts) {
   return guarded(h, [&]() -> fsgmg_status {
     if (opts->halo < 0 || opts->nu_pre < 0 || opts->nu_post < 0 || !(opts->omega > 0))
       throw Fail{FSGMG_EINVAL, "smoother options out of range"};
@@ -2232,6 +2317,10 @@ fsgmg_status build_fs_as_blocks(fsgmg_h h, const fsgmg_smoother_opts* opts) {
         }
     }
     if (h->host_only()) return FSGMG_OK;
+    struct ClearHook {
+      fsgmg_hierarchy* h;
+      ~ClearHook() { h->zero_block_level = -1, h->zero_block = -1; }
+    } clear_hook{h};
     factor_blocks(*h);
     // launch shapes depend on the block structure only: keep them while the
     // index sets and precision are unchanged, so rebuilds stay reproducible
@@ -2409,6 +2498,21 @@ fsgmg_status update_params(fsgmg_h h, double E, double mu) {
   });
 }
 
+fsgmg_status debug_zero_block(fsgmg_h h, int level, int64_t block) {
+  if (!h) return FSGMG_EINVAL;
+  return guarded(h, [&]() -> fsgmg_status {
+    if (block < 0) {
+      h->zero_block_level = -1;
+      h->zero_block = -1;
+      return FSGMG_OK;
+    }
+    if (level < 1 || level >= h->L) throw Fail{FSGMG_EINVAL, "level out of range (1 .. L-1)"};
+    h->zero_block_level = level;
+    h->zero_block = block;
+    return FSGMG_OK;
+  });
+}
+
 fsgmg_status level_info(fsgmg_h h, int level, int64_t out[9]) {
   if (!h || !out) return FSGMG_EINVAL;
   if (level < 0 || level >= h->L) return FSGMG_EINVAL;
@@ -2423,6 +2527,38 @@ fsgmg_status level_info(fsgmg_h h, int level, int64_t out[9]) {
   out[7] = h->ops[level].A.nnz();
   out[8] = lv.D;
   return FSGMG_OK;
+}
+
+fsgmg_status dof_map(fsgmg_h h, int level, int64_t* n, int32_t* field, int32_t* comp,
+                     int32_t* node, double* xyz) {
+  if (!h || !n) return FSGMG_EINVAL;
+  return guarded(h, [&]() -> fsgmg_status {
+    if (level < 0 || level >= h->L) throw Fail{FSGMG_EINVAL, "level out of range"};
+    const Level& lv = h->levels[level];
+    const int64_t cap = *n;
+    *n = lv.N;
+    if (!field && !comp && !node && !xyz) return FSGMG_OK;
+    if (cap < lv.N) throw Fail{FSGMG_EINVAL, "output arrays shorter than the level's unknowns"};
+    const int D = lv.D;
+    auto put = [&](int64_t i, int f, int c, int64_t nd, int64_t q2) {
+      if (field) field[i] = f;
+      if (comp) comp[i] = c;
+      if (node) node[i] = (int32_t)nd;
+      if (xyz)
+        for (int a = 0; a < 3; ++a) xyz[3 * i + a] = a < D ? lv.X[q2 * D + a] : 0.0;
+    };
+    for (int64_t q = 0; q < lv.N2; ++q)
+      for (int c = 0; c < D; ++c) {
+        put(D * q + c, 0, c, q, q);
+        put(lv.off_u + D * q + c, 2, c, q, q);
+      }
+    for (int64_t v = 0; v < lv.NV; ++v) {
+      const int64_t q2 = lv.vertex_node(v);
+      if (lv.ps_of_vert[v] >= 0) put(lv.ps_of_vert[v], 1, 0, v, q2);
+      if (lv.pf_of_vert[v] >= 0) put(lv.pf_of_vert[v], 3, 0, v, q2);
+    }
+    return FSGMG_OK;
+  });
 }
 
 fsgmg_status export_csr(fsgmg_h h, int level, int which, int64_t dims[3], int64_t* rowptr,

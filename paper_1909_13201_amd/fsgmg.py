@@ -28,7 +28,7 @@ PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
 EXPORTED = ["setup_hierarchy", "build_fs_as_blocks", "vcycle_apply", "vcycle_apply_batch",
             "gmres_solve", "gmres_solve_batch", "adjoint_solve_batch",
             "adjoint_solve", "assemble_load", "load_adjoint", "apply_operator", "param_grad",
-            "update_params", "level_info", "export_csr", "export_vector", "export_blocks", "block_colours",
+            "update_params", "level_info", "dof_map", "debug_zero_block", "export_csr", "export_vector", "export_blocks", "block_colours",
             "kernel_timing", "tuning_info", "last_error", "hierarchy_destroy"]
 
 
@@ -61,7 +61,49 @@ class SolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int), ("restarts", C.c_int), ("converged", C.c_int),
                 ("rel_res_true", C.c_double), ("history", C.POINTER(C.c_double)),
                 ("history_cap", C.c_int), ("history_len", C.c_int),
-                ("t_solve_ms", C.c_double)]
+                ("t_solve_ms", C.c_double), ("vcycles", C.c_int),
+                ("t_setup_ms", C.c_double), ("t_blocks_ms", C.c_double)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class Allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", C.c_void_p)]
+
+
+class TorchAllocator:
+    """The handle's device memory from torch's caching allocator on `device`:
+    every buffer the library allocates is a block of torch's pool on the
+    handle's stream.  The ctypes callbacks live as long as this object, which
+    the owning Hierarchy keeps; `allocs` / `frees` count the calls."""
+
+    def __init__(self, device):
+        import torch
+        self.device = int(device)
+        self.allocs = self.frees = 0
+        self.live = {}
+
+        def _alloc(nbytes, stream, user):
+            try:
+                p = torch.cuda.caching_allocator_alloc(int(nbytes), self.device, int(stream or 0))
+            except Exception:   # noqa: BLE001 - out of memory: NULL tells the library
+                return None
+            self.allocs += 1
+            self.live[p] = int(nbytes)
+            return p
+
+        def _free(ptr, stream, user):
+            try:
+                self.live.pop(ptr, None)
+                self.frees += 1
+                torch.cuda.caching_allocator_delete(ptr)
+            except Exception:   # noqa: BLE001 - interpreter shutdown
+                pass
+
+        self._cb = (ALLOC_FN(_alloc), FREE_FN(_free))
+        self.struct = Allocator(self._cb[0], self._cb[1], None)
 
 
 _lib = None
@@ -78,8 +120,8 @@ def lib():
         H = C.c_void_p
         P = C.c_void_p
         sig = {
-            "setup_hierarchy": ([C.POINTER(MeshDesc), C.POINTER(Physics), C.c_int, P,
-                                 C.POINTER(H)], C.c_int),
+            "setup_hierarchy": ([C.POINTER(MeshDesc), C.POINTER(Physics), C.POINTER(Allocator),
+                                 C.c_int, P, C.POINTER(H)], C.c_int),
             "build_fs_as_blocks": ([H, C.POINTER(SmootherOpts)], C.c_int),
             "vcycle_apply": ([H, P, P, C.c_int], C.c_int),
             "vcycle_apply_batch": ([H, P, P, C.c_int, C.c_int], C.c_int),
@@ -93,6 +135,8 @@ def lib():
             "param_grad": ([H, P, P, C.POINTER(C.c_double)], C.c_int),
             "update_params": ([H, C.c_double, C.c_double], C.c_int),
             "level_info": ([H, C.c_int, C.POINTER(C.c_int64)], C.c_int),
+            "dof_map": ([H, C.c_int, C.POINTER(C.c_int64), P, P, P, P], C.c_int),
+            "debug_zero_block": ([H, C.c_int, C.c_int64], C.c_int),
             "export_csr": ([H, C.c_int, C.c_int, C.POINTER(C.c_int64), P, P, P], C.c_int),
             "export_vector": ([H, C.c_int, C.c_int, P], C.c_int),
             "export_blocks": ([H, C.c_int, C.POINTER(C.c_int64), P, P, P], C.c_int),
@@ -175,13 +219,18 @@ def _check(h, st, allow_not_converged=False):
 # C-ABI named wrappers
 # ----------------------------------------------------------------------------
 
-def setup_hierarchy(cfg, w=None, device=0, stream=None):
+def setup_hierarchy(cfg, w=None, device=0, stream=None, allocator=None):
+    """allocator: an Allocator structure (or an object with a `struct`
+    attribute holding one) for the handle's device memory, None = hipMalloc.
+    It must outlive the handle."""
     keep = []
     m = _mesh_desc(cfg, keep)
     p = _physics(cfg, w, keep)
     h = C.c_void_p()
     s = C.c_void_p(stream) if stream is not None else None
-    st = lib().setup_hierarchy(C.byref(m), C.byref(p), int(device), s, C.byref(h))
+    a = getattr(allocator, "struct", allocator)
+    st = lib().setup_hierarchy(C.byref(m), C.byref(p), C.byref(a) if a is not None else None,
+                               int(device), s, C.byref(h))
     if st != FSGMG_OK:
         msg = lib().last_error(h).decode() if h else ""
         if h:
@@ -227,7 +276,8 @@ def _solve(fn, h, b, x, restart, max_restarts, rtol, history_cap):
     n = min(info.history_len, history_cap)
     return dict(converged=bool(info.converged), iters=info.iters, restarts=info.restarts,
                 rel_res_true=info.rel_res_true, history=hist[:n].copy(),
-                t_solve_ms=info.t_solve_ms, status=STATUS[st])
+                t_solve_ms=info.t_solve_ms, vcycles=info.vcycles, t_setup_ms=info.t_setup_ms,
+                t_blocks_ms=info.t_blocks_ms, status=STATUS[st])
 
 
 def _solve_batch(fn, h, b, x, k, restart, max_restarts, rtol):
@@ -236,7 +286,8 @@ def _solve_batch(fn, h, b, x, k, restart, max_restarts, rtol):
     st = fn(h, _ptr(b), _ptr(x), int(k), C.byref(o), C.cast(infos, C.c_void_p))
     _check(h, st, allow_not_converged=True)
     return [dict(converged=bool(i.converged), iters=i.iters, restarts=i.restarts,
-                 rel_res_true=i.rel_res_true, t_solve_ms=i.t_solve_ms) for i in infos]
+                 rel_res_true=i.rel_res_true, t_solve_ms=i.t_solve_ms, vcycles=i.vcycles)
+            for i in infos]
 
 
 def gmres_solve_batch(h, b, x, k, restart=30, max_restarts=20, rtol=1e-10):
@@ -282,6 +333,31 @@ def level_info(h, level):
     _check(h, lib().level_info(h, int(level), out))
     keys = ["N", "N2", "Nps", "Npf", "off_ps", "off_u", "off_pf", "nnz", "dim"]
     return {k: int(v) for k, v in zip(keys, out)}
+
+
+FIELDS = ("d", "ps", "u", "pf")
+
+
+def debug_zero_block(h, level, block):
+    """Test hook: the next build_fs_as_blocks zeroes that block's matrix
+    (it then reports ESINGULAR); block < 0 clears the hook."""
+    _check(h, lib().debug_zero_block(h, int(level), int(block)))
+
+
+def dof_map(h, level):
+    """Per unknown of `level`: field code (0 d, 1 p^s, 2 u, 3 p^f), component,
+    Q2 node or Q1 vertex index, physical coordinates (N x 3)."""
+    n = C.c_int64(0)
+    _check(h, lib().dof_map(h, int(level), C.byref(n), None, None, None, None))
+    N = n.value
+    field = np.zeros(N, np.int32)
+    comp = np.zeros(N, np.int32)
+    node = np.zeros(N, np.int32)
+    xyz = np.zeros((N, 3))
+    _check(h, lib().dof_map(h, int(level), C.byref(n), field.ctypes.data_as(C.c_void_p),
+                            comp.ctypes.data_as(C.c_void_p), node.ctypes.data_as(C.c_void_p),
+                            xyz.ctypes.data_as(C.c_void_p)))
+    return field, comp, node, xyz
 
 
 def export_csr(h, level, which):
@@ -359,13 +435,21 @@ class Hierarchy:
     """Owning wrapper of a handle.  device=-1 builds a host-only handle (setup
     data can be inspected, no device call is valid)."""
 
-    def __init__(self, cfg, w=None, device=0, stream=None):
+    def __init__(self, cfg, w=None, device=0, stream=None, allocator="torch"):
+        """allocator: "torch" (device memory from torch's caching allocator,
+        the default), None (the library's hipMalloc) or an object with a
+        `struct` Allocator attribute."""
         self.cfg = dict(cfg)
         self.device = device
+        self.h = None
         if device >= 0 and stream is None:
             import torch
             stream = torch.cuda.current_stream(device).cuda_stream
-        self.h = setup_hierarchy(cfg, w, device, stream)
+        if allocator == "torch":
+            allocator = TorchAllocator(device) if device >= 0 else None
+        self.allocator = allocator   # outlives the handle (closed first)
+        self.built_key = None      # (E, mu, options) of the current block inverses
+        self.h = setup_hierarchy(cfg, w, device, stream, allocator)
         self.L = int(cfg["n_levels"])
         self.info = [level_info(self.h, l) for l in range(self.L)]
         self.N = self.info[-1]["N"]
@@ -381,15 +465,44 @@ class Hierarchy:
         except Exception:
             pass
 
-    def build_fs_as_blocks(self, **kw):
-        opts = dict(core=self.cfg.get("core", (4, 4)), halo=self.cfg.get("halo", 1),
+    def smoother_options(self, **kw):
+        """The full option set build_fs_as_blocks(**kw) would use: the
+        workload's settings, the library defaults, then kw."""
+        opts = dict(core=tuple(self.cfg.get("core", (4, 4))), halo=self.cfg.get("halo", 1),
                     nu_pre=self.cfg.get("nu_pre", 2), nu_post=self.cfg.get("nu_post", 2),
-                    omega=self.cfg.get("omega", 0.8), iface_mult=self.cfg.get("iface_mult", 1),
+                    omega=self.cfg.get("omega", 0.8), prec="fp64", use_graph=True,
+                    iface_mult=self.cfg.get("iface_mult", 1),
                     monolithic=self.cfg.get("monolithic", False),
                     cycle=self.cfg.get("cycle", "V"),
-                    schwarz=self.cfg.get("schwarz", "additive"))
+                    schwarz=self.cfg.get("schwarz", "additive"), sweep_form="auto")
         opts.update(kw)
+        if "core" in kw:
+            opts["core"] = tuple(kw["core"])
+        return opts
+
+    def blocks_key(self, **kw):
+        """What the block inverses depend on: (E, mu) and the smoother options."""
+        opts = self.smoother_options(**kw)
+        return (float(self.cfg["E"]), float(self.cfg["mu"]), tuple(sorted(opts.items())))
+
+    def build_fs_as_blocks(self, **kw):
+        opts = self.smoother_options(**kw)
+        self.built_key = None
         build_fs_as_blocks(self.h, **opts)
+        self.built_key = self.blocks_key(**kw)
+
+    def ensure_blocks(self, E, mu, **kw):
+        """Bring the handle to parameters (E, mu) with blocks built for the
+        smoother options kw: update_params when (E, mu) differ from the
+        handle's, build_fs_as_blocks when the blocks were built for other
+        parameters or options (or never)."""
+        if (float(E), float(mu)) != (float(self.cfg["E"]), float(self.cfg["mu"])):
+            self.update_params(E, mu)
+        if self.built_key != self.blocks_key(**kw):
+            self.build_fs_as_blocks(**kw)
+
+    def dof_map(self, level=None):
+        return dof_map(self.h, self.L - 1 if level is None else level)
 
     def csr(self, level, which=0):
         import scipy.sparse as sp
@@ -453,6 +566,7 @@ class Hierarchy:
         return param_grad(self.h, self._vec(lam), self._vec(x))
 
     def update_params(self, E, mu):
+        self.built_key = None
         update_params(self.h, E, mu)
         self.cfg.update(E=float(E), mu=float(mu))
 

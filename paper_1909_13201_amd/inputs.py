@@ -20,6 +20,13 @@ not public; Section 4 of the paper):
 * ``c3``  2D aneurysm-like channel with a bulge of height and half-width 0.3
   on the top wall (smooth cos^2 profile tangent to the wall), coarse 16x8,
   6 levels (finest 512x256), 2-element-thick walls, interface cores 4 x 12.
+* ``c4``  3D tube along z with an elastic wall and a leaflet-like plate:
+  reference box [0,1]^2 x [0,2], coarse 4x4x8, the square section mapped to
+  a disc of radius 0.5, the outer coarse ring of the section solid (graded
+  to 0.1 R), one thin coarse z-layer at z = 1 solid over x < 0.5 of the
+  lumen (attached to the wall), 4 levels (finest 32x32x64), E=1e5,
+  nu=0.45, mu=3.5e-3, Oseen about a seeded 3D field with SUPG, one-element
+  cores with the one-element Vanka halo.
 * ``c5``  c2 at 4 levels (finest 64x64), one backward-Euler step dt = 1/32,
   with 32 seeded (load, E, mu) samples.
 
@@ -41,7 +48,7 @@ import copy
 import numpy as np
 
 FACE_XMIN, FACE_XMAX, FACE_YMIN, FACE_YMAX, FACE_ZMIN, FACE_ZMAX = range(6)
-MAP_IDENTITY, MAP_BULGE, MAP_SMOOTH_BULGE = 0, 1, 2
+MAP_IDENTITY, MAP_BULGE, MAP_SMOOTH_BULGE, MAP_DISC = 0, 1, 2, 3
 
 
 def _uniform(n, lo=0.0, hi=1.0):
@@ -126,6 +133,30 @@ def config(name: str) -> dict:
                    # enlarged ones about 2x the unknowns of the interior ones
                    iface_mult=3,
                    restart=30, rtol=1e-10, seed=0)
+    elif name == "c4":
+        # tube along z: solid ring clamped at both ends, fluid inflow on
+        # z-min, natural outflow on z-max, fluid mesh displacement fixed on
+        # the end faces; the outer surface of the ring is traction-free
+        bc_d, bc_u = _bc_tables()
+        for f in (FACE_ZMIN, FACE_ZMAX):
+            bc_d[f][1] = 1
+            bc_d[f][0] = 1
+        bc_u[FACE_ZMIN][0] = 2
+        sec = [0.0, 0.05, 0.5, 0.95, 1.0]          # ring graded to 0.1 R
+        zb = [0.0, 0.25, 0.5, 0.75, 0.975, 1.025, 1.35, 1.675, 2.0]
+        region = np.zeros((8, 4, 4), np.int8)      # (z, y, x), x fastest
+        region[:, 0, :] = region[:, 3, :] = 1
+        region[:, :, 0] = region[:, :, 3] = 1
+        region[4, 1:3, 1] = 1                      # leaflet: z in [0.975, 1.025], x < 0.5
+        cfg = dict(dim=3, n_levels=4, nc=(4, 4, 8), breaks=(sec, list(sec), zb),
+                   region=region.ravel(), mapping=MAP_DISC, map_params=[0.5, 0.5, 0.5],
+                   bc_d=bc_d, bc_u=bc_u, inflow_peak=1.0,
+                   E=1e5, nu=0.45, mu=3.5e-3, rho=1.0, supg=True, w_amp=1.0,
+                   ale_k=0, k_mass=0,
+                   # in 3D only the literal Vanka rule (one-element cores
+                   # with the one-element halo) converges
+                   core=(1, 1, 1), halo=1, nu_pre=2, nu_post=2, omega=0.8,
+                   restart=30, rtol=1e-10, seed=0)
     else:
         raise KeyError(name)
     cfg["name"] = name
@@ -184,13 +215,37 @@ def body_force(cfg: dict, seed: int | None = None) -> np.ndarray:
 
 
 def _fluid_box(cfg: dict):
-    """Reference-coordinate bounding box of the fluid region (2D only)."""
+    """Reference-coordinate bounding box of the fluid region, per axis."""
     nc = cfg["nc"]
-    reg = np.asarray(cfg["region"]).reshape(nc[1], nc[0])
-    rows = np.where((reg == 0).any(axis=1))[0]
-    cols = np.where((reg == 0).any(axis=0))[0]
-    xb, yb = cfg["breaks"][0], cfg["breaks"][1]
-    return (xb[cols.min()], xb[cols.max() + 1]), (yb[rows.min()], yb[rows.max() + 1])
+    D = cfg["dim"]
+    reg = np.asarray(cfg["region"]).reshape(tuple(nc[a] for a in reversed(range(D))))
+    fluid = reg == 0
+    box = []
+    for a in range(D):
+        ax = D - 1 - a                              # numpy axis of reference axis a
+        other = tuple(i for i in range(D) if i != ax)
+        idx = np.where(fluid.any(axis=other))[0]
+        b = cfg["breaks"][a]
+        box.append((b[idx.min()], b[idx.max() + 1]))
+    return tuple(box)
+
+
+def _nodes_touching_solid(cfg: dict) -> np.ndarray:
+    """Finest Q2 nodes that belong to at least one solid element, (N2,) bool."""
+    D = cfg["dim"]
+    s = 2 ** (cfg["n_levels"] - 1)
+    nc = cfg["nc"]
+    reg = np.asarray(cfg["region"]).reshape(tuple(nc[a] for a in reversed(range(D))))
+    fine = reg
+    for ax in range(D):
+        fine = np.repeat(fine, s, axis=ax)            # finest elements, (z,) y, x
+    solid = fine == 1
+    ne = solid.shape
+    out = np.zeros(tuple(2 * n + 1 for n in ne), bool)
+    for off in np.ndindex(*(3,) * D):
+        sl = tuple(slice(o, o + 2 * n, 2) for o, n in zip(off, ne))
+        out[sl] |= solid
+    return out.ravel()
 
 
 def advecting_field(cfg: dict, seed: int | None = None) -> np.ndarray | None:
@@ -204,8 +259,8 @@ def advecting_field(cfg: dict, seed: int | None = None) -> np.ndarray | None:
     """
     if not cfg.get("w_amp", 0.0):
         return None
-    if cfg["dim"] != 2:
-        raise NotImplementedError("advecting field is defined for 2D configurations")
+    if cfg["dim"] == 3:
+        return _advecting_field_3d(cfg, seed)
     rng = np.random.default_rng(1000 + (cfg["seed"] if seed is None else seed))
     a = rng.standard_normal((3, 3))
     (x0, x1), (y0, y1) = _fluid_box(cfg)
@@ -231,6 +286,48 @@ def advecting_field(cfg: dict, seed: int | None = None) -> np.ndarray | None:
     wx = np.where(inside, wx, 0.0)
     wy = np.where(inside, wy, 0.0)
     w = np.stack([wx.ravel(), wy.ravel()], axis=1)
+    mx = np.sqrt((w ** 2).sum(axis=1)).max()
+    return w * (cfg["w_amp"] / mx)
+
+
+def _advecting_field_3d(cfg: dict, seed: int | None = None) -> np.ndarray:
+    """Seeded smooth 3D advecting velocity at every finest Q2 node, (N2, 3).
+
+    With (s, t, q) the reference coordinates normalised to the fluid box,
+    w = (d psi/dt, -d psi/ds, phi): a swirl from the stream function
+    psi = (s(1-s))^2 (t(1-t))^2 (1 + sin(pi q)/2) sum_{k,l<=3} a_kl
+    sin(k pi s) sin(l pi t), a_kl ~ N(0,1), plus the axial profile
+    phi = 16 s(1-s) t(1-t); both are divergence-free in (s, t, q).  w is
+    zero outside the open fluid box and at every node of a solid element
+    (the wall and the leaflet), and scaled to max |w|_2 = w_amp."""
+    rng = np.random.default_rng(1000 + (cfg["seed"] if seed is None else seed))
+    a = rng.standard_normal((3, 3))
+    (x0, x1), (y0, y1), (z0, z1) = _fluid_box(cfg)
+    xr, yr, zr = finest_node_reference_coords(cfg)
+    Z, Y, X = np.meshgrid(zr, yr, xr, indexing="ij")     # x fastest after ravel
+    s = (X - x0) / (x1 - x0)
+    t = (Y - y0) / (y1 - y0)
+    q = (Z - z0) / (z1 - z0)
+    inside = (s > 0) & (s < 1) & (t > 0) & (t < 1) & (q >= 0) & (q <= 1)
+    Bs, dBs = (s * (1 - s)) ** 2, 2 * s * (1 - s) * (1 - 2 * s)
+    Bt, dBt = (t * (1 - t)) ** 2, 2 * t * (1 - t) * (1 - 2 * t)
+    g = 1.0 + 0.5 * np.sin(np.pi * q)
+    S = np.zeros_like(s)
+    dS_ds = np.zeros_like(s)
+    dS_dt = np.zeros_like(s)
+    for k in range(1, 4):
+        for l in range(1, 4):
+            sk, ck = np.sin(k * np.pi * s), np.cos(k * np.pi * s)
+            sl, cl = np.sin(l * np.pi * t), np.cos(l * np.pi * t)
+            S += a[k - 1, l - 1] * sk * sl
+            dS_ds += a[k - 1, l - 1] * k * np.pi * ck * sl
+            dS_dt += a[k - 1, l - 1] * l * np.pi * sk * cl
+    w_s = g * Bs * (dBt * S + Bt * dS_dt)
+    w_t = -g * Bt * (dBs * S + Bs * dS_ds)
+    w_q = 16.0 * s * (1 - s) * t * (1 - t)
+    w = np.stack([w_s.ravel(), w_t.ravel(), w_q.ravel()], axis=1)
+    w[~inside.ravel()] = 0.0
+    w[_nodes_touching_solid(cfg)] = 0.0
     mx = np.sqrt((w ** 2).sum(axis=1)).max()
     return w * (cfg["w_amp"] / mx)
 

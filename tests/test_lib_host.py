@@ -39,7 +39,7 @@ def test_library_exports_every_declared_symbol():
     assert set(fsgmg.EXPORTED) == set(decl)
 
 
-CASES = [("c1", 2), ("c2", 3), ("c3", 2), ("c5", 2)]
+CASES = [("c1", 2), ("c2", 3), ("c3", 2), ("c4", 2), ("c5", 2)]
 
 
 @pytest.fixture(scope="module", params=CASES, ids=lambda c: "%s-L%d" % c)
@@ -56,6 +56,58 @@ def pair(request):
 def _rel(a, b):
     d = abs(a - b)
     return (d.max() if d.nnz else 0.0) / max(abs(b).max(), 1e-300)
+
+
+def _oracle_dof_map(lv):
+    """Field, component, node / vertex and coordinates of every unknown of an
+    oracle level, from its documented layout."""
+    D, N = lv.D, lv.N
+    field = np.full(N, -1)
+    comp = np.zeros(N, np.int64)
+    node = np.zeros(N, np.int64)
+    xyz = np.zeros((N, 3))
+    q = np.arange(lv.N2)
+    for c in range(D):
+        for f, dofs in ((0, lv.d(q, c)), (2, lv.u(q, c))):
+            field[dofs], comp[dofs], node[dofs] = f, c, q
+            xyz[dofs, :D] = lv.X[q]
+    for f, of_vert in ((1, lv.ps_of_vert), (3, lv.pf_of_vert)):
+        v = np.where(of_vert >= 0)[0]
+        field[of_vert[v]], node[of_vert[v]] = f, v
+        xyz[of_vert[v], :D] = lv.X[lv.node_of_vertex(v)]
+    return field, comp, node, xyz
+
+
+def test_dof_map_matches_oracle_layout(pair):
+    cfg, w, H, O = pair
+    for l, lv in enumerate(O.levels):
+        field, comp, node, xyz = H.dof_map(l)
+        of, oc, on, ox = _oracle_dof_map(lv)
+        assert (of >= 0).all()
+        assert np.array_equal(field, of) and np.array_equal(comp, oc)
+        assert np.array_equal(node, on)
+        assert np.allclose(xyz, ox, rtol=0, atol=1e-14)
+    # every node of the d and u fields appears once per component
+    assert np.bincount(node[field == 0], minlength=lv.N2).tolist() == [lv.D] * lv.N2
+
+
+def test_dof_map_3d_and_errors():
+    from tests.cfgs import channel3d
+    cfg = channel3d(levels=2)
+    H = fsgmg.Hierarchy(cfg, None, device=-1)
+    O = OracleHierarchy(cfg, None, build_smoothers=False)
+    for l, lv in enumerate(O.levels):
+        got = H.dof_map(l)
+        ref = _oracle_dof_map(lv)
+        for g, r in zip(got, ref):
+            assert np.allclose(g, r, rtol=0, atol=1e-14)
+    import ctypes as C
+    n = C.c_int64(5)
+    arr = np.zeros(5, np.int32)
+    assert fsgmg.lib().dof_map(H.h, 0, C.byref(n), arr.ctypes.data_as(C.c_void_p),
+                               None, None, None) == -1          # arrays too short
+    assert fsgmg.lib().dof_map(H.h, 7, C.byref(n), None, None, None, None) == -1
+    H.close()
 
 
 def test_level_layout(pair):

@@ -558,3 +558,94 @@ def test_mapped_area_closed_form(mapping):
     # tangent, so its rate is lower); a wrong height or blend would stall
     assert errs[-1] < (2e-3 if mapping == 1 else 1e-5)
     assert errs[-1] < errs[-2] / (1.5 if mapping == 1 else 4.0)
+
+
+# --------------------------------------------------------------------------
+# the disc cross-section map of the 3D tube (mapping 3) and the 3D outlet
+# flux functional
+# --------------------------------------------------------------------------
+def _tube_cfg(levels=1, nc=(4, 4, 2), **kw):
+    cfg = _region_cfg3(nc, (), levels=levels, **kw)
+    cfg["breaks"] = ([0, 0.05, 0.5, 0.95, 1.0][:nc[0] + 1] if nc[0] == 4 else
+                     list(np.linspace(0, 1, nc[0] + 1)),
+                     [0, 0.05, 0.5, 0.95, 1.0][:nc[1] + 1] if nc[1] == 4 else
+                     list(np.linspace(0, 1, nc[1] + 1)),
+                     list(np.linspace(0, 0.6, nc[2] + 1)))
+    cfg["mapping"] = 3
+    cfg["map_params"] = [0.5, 0.5, 0.5]
+    return cfg
+
+
+def test_disc_map_section_area_closed_form():
+    """The map sends the square section onto the disc of radius R: the
+    isoparametric element volumes of one element layer converge to
+    pi R^2 times the layer height (a wrong scale, centre or square-root
+    factor would stall away from it)."""
+    errs = []
+    for L in (1, 2, 3):
+        cfg = _tube_cfg(levels=L, nc=(4, 4, 1))
+        cfg["breaks"] = (cfg["breaks"][0], cfg["breaks"][1], [0.0, 0.6])
+        lv = Level(cfg, L - 1)
+        dV = fem.geometry(fem.RefElement(3), lv.X[lv.elem_nodes])[0].sum(axis=1)
+        errs.append(abs(dV.sum() - np.pi * 0.25 * 0.6))
+    assert errs[-1] < 2e-4
+    assert errs[-1] < errs[-2] / 8.0
+    # the mapped elements are curved (the map is not affine)
+    lv = Level(_tube_cfg(levels=1, nc=(4, 4, 1)), 0)
+    Xe = lv.X[lv.elem_nodes]
+    corners = Xe[:, [0, 2, 6, 8, 18, 20, 24, 26]].mean(axis=1)
+    assert abs(Xe[:, 13] - corners).max() > 1e-4
+
+
+def test_patch_disc_mapped_solid_3d():
+    """Isoparametric Q2 on the disc-mapped tube reproduces fields linear in
+    the physical coordinates: a constant-stress solid state leaves zero
+    residual on interior test functions."""
+    x, y, z = SYM
+    cfg = _tube_cfg(levels=1, nc=(4, 4, 2), E=7.0, nu=0.3)
+    cfg["region"] = np.ones_like(cfg["region"])
+    lv = Level(cfg, 0)
+    G, inv_lam = fem.lame_constants(cfg["E"], cfg["nu"])
+    d = [0.3 * x - 0.7 * y + 0.1 * z, 0.2 * x + 0.5 * y, -0.4 * z + 0.1 * x]
+    p = -(0.3 + 0.5 - 0.4) / inv_lam
+    xv = _state(lv, d=d, ps=sy.Float(p))
+    asm = fem.assemble_level(lv, cfg)
+    r = asm["A"] @ xv
+    inner = _interior_nodes(lv)
+    assert inner.sum() > 0
+    scale = abs(asm["A"]).max() * abs(xv).max()
+    assert abs(_rows(lv, r, "d")[inner]).max() < 1e-11 * scale
+    assert abs(_rows(lv, r, "ps")).max() < 1e-11 * scale
+    d2 = [x * x, 0 * y, 0 * z]
+    r2 = asm["A"] @ _state(lv, d=d2, ps=sy.Float(0.0))
+    assert abs(_rows(lv, r2, "d")[inner]).max() > 1e-6 * scale
+
+
+def test_outlet_flux_3d_closed_forms():
+    """c^T x = int over the fluid part of the z-max face of u.n: with u
+    constant along z it is the fluid section's area, with u_z = x the first
+    moment, with tangential u zero; solid elements of the last layer do not
+    count (a solid ring around the fluid)."""
+    from oracle import adjoint
+    x, y, z = SYM
+    cfg = _region_cfg3((3, 4, 2), (0,), levels=1)
+    cfg["breaks"] = ([0, 0.2, 0.7, 1.1], [0, 0.1, 0.4, 0.8, 1.0], [0, 0.3, 0.9])
+    lv = Level(cfg, 0)
+    c = adjoint.outlet_flux_vector(lv)
+    y0, y1 = 0.1, 1.0                              # fluid rows (solid y-layer 0)
+    area = 1.1 * (y1 - y0)
+    assert c @ _state(lv, u=[0 * x, 0 * y, 1 + 0 * z]) == pytest.approx(area, rel=1e-13)
+    assert c @ _state(lv, u=[0 * x, 0 * y, x]) == pytest.approx(0.5 * 1.1 ** 2 * (y1 - y0),
+                                                                 rel=1e-13)
+    assert c @ _state(lv, u=[1 + 0 * x, y, 0 * z]) == pytest.approx(0.0, abs=1e-14)
+    # Q2 traces are exact for quadratic profiles: u_z = y^2 on the fluid rows
+    assert c @ _state(lv, u=[0 * x, 0 * y, y * y]) == pytest.approx(
+        1.1 * (y1 ** 3 - y0 ** 3) / 3, rel=1e-13)
+    # on the disc-mapped tube the flux of u = e_z converges to the section area
+    errs = []
+    for L in (1, 2):
+        cfg = _tube_cfg(levels=L, nc=(4, 4, 1))
+        lv = Level(cfg, L - 1)
+        c = adjoint.outlet_flux_vector(lv)
+        errs.append(abs(c @ _state(lv, u=[0 * x, 0 * y, 1 + 0 * z]) - np.pi * 0.25))
+    assert errs[-1] < 1e-3 and errs[-1] < errs[0]
