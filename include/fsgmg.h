@@ -306,6 +306,20 @@ fsgmg_status apply_operator(fsgmg_h h, int level, const double* x, double* y, in
  * tau frozen); lam, x device; out host (synchronizes). */
 fsgmg_status param_grad(fsgmg_h h, const double* lam, const double* x, double out[2]);
 
+/* param_grad for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same kernels in the same order, so the same out[] bit for bit, with
+ * the product dA/dtheta x, the reduction partials and the three sums in a
+ * file-scope device array of 32 MiB instead of the handle's lazily
+ * allocated buffers; it calls no allocating routine.  Limit: the finest
+ * level's unknowns N must satisfy 8 N + 256 KiB <= 32 MiB (N up to about
+ * 4.1 M), else EINVAL.  Each GPU holds one such array until the process
+ * ends, shared by every call on that GPU: calls that overlap on one GPU
+ * (several host threads or streams) race and must be serialized by the
+ * caller.  Synchronizes the handle's stream; EHIP when the array's device
+ * address cannot be obtained; other errors as param_grad. */
+fsgmg_status param_grad_noalloc(fsgmg_h h, const double* lam, const double* x, double out[2]);
+
 /* Recombine every level operator and the Dirichlet lift for new (E, mu)
  * from the stored affine pieces of the Section 2.2 operator (it is affine in
  * G, 1/lambda_L and mu; SUPG tau frozen at setup).  Invalidates the

@@ -14,6 +14,8 @@
 //  * FGMRES building blocks: multi-vector dot products with fixed-order
 //    partial sums (deterministic), fused MAXPY + dot, norms
 #include <hip/hip_runtime.h>
+
+#include <mutex>
 #include <hip/hip_bf16.h>
 
 #include <algorithm>
@@ -3181,6 +3183,38 @@ void launch_load_rhs(int64_t n, const int64_t* rowptr, const int32_t* col, const
                      const double* f, const double* lift, double* b, hipStream_t s) {
   hipLaunchKernelGGL(k_load_rhs, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, s, n, rowptr, col,
                      val, f, lift, b);
+}
+
+// The allocation-free entry points' scratch: its name is a host-side
+// stand-in, so host code only ever passes the address that
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+void* noalloc_scratch(int device, const char** err) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  if (device < 0 || device >= kMaxDevices) {
+    *err = "device index out of range for the allocation-free scratch";
+    return nullptr;
+  }
+  const std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess || cur != device) {
+      *err = "the allocation-free scratch is looked up with its device current";
+      return nullptr;
+    }
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      *err = "hipGetSymbolAddress of the allocation-free scratch failed";
+      return nullptr;
+    }
+    addr[device] = p;
+  }
+  return addr[device];
 }
 
 void launch_masked_dot(const double* a, const uint8_t* mask, const double* b, int64_t n,

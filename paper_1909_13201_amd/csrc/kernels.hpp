@@ -324,4 +324,13 @@ void launch_recombine(int64_t n, const double* p0, const double* p1, const doubl
                       const double* p3, double c1, double c2, double c3, double* out64,
                       float* out32, hipStream_t s);
 
+// ---- allocation-free scratch ----
+// A file-scope device array of kNoAllocScratchBytes bytes (one copy per GPU,
+// held until the process ends) for entry points that must not allocate.
+// noalloc_scratch(device) returns its device address on `device` (looked up
+// once per device with that device current, then cached), or nullptr and a
+// message when the lookup fails.
+constexpr size_t kNoAllocScratchBytes = size_t(32) << 20;
+void* noalloc_scratch(int device, const char** err);
+
 }  // namespace fsgmg

@@ -2461,6 +2461,46 @@ fsgmg_status param_grad(fsgmg_h h, const double* lam, const double* x, double ou
   });
 }
 
+fsgmg_status param_grad_noalloc(fsgmg_h h, const double* lam, const double* x, double out[2]) {
+  if (!h || !lam || !x || !out) return FSGMG_EINVAL;
+  return guarded(h, [&]() -> fsgmg_status {
+    check_device(*h);
+    const Level& F = h->levels[h->L - 1];
+    // scratch layout: dA/dtheta x (N doubles) | reduction partials | 3 sums
+    auto up256 = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t off_part = up256((size_t)F.N * sizeof(double));
+    const size_t off_sum = off_part + up256((size_t)krylov_partials() * sizeof(double));
+    const size_t need = off_sum + 3 * sizeof(double);
+    if (need > kNoAllocScratchBytes)
+      throw Fail{FSGMG_EINVAL, "param_grad_noalloc: " + std::to_string(F.N) +
+                                   " unknowns need " + std::to_string(need) +
+                                   " bytes of scratch, more than its " +
+                                   std::to_string(kNoAllocScratchBytes)};
+    const char* err = "";
+    char* base = static_cast<char*>(noalloc_scratch(h->device, &err));
+    if (!base) throw Fail{FSGMG_EHIP, err};
+    double* tmp = reinterpret_cast<double*>(base);
+    double* part = reinterpret_cast<double*>(base + off_part);
+    double* sum = reinterpret_cast<double*>(base + off_sum);
+    // every scratch word read below is written first in the same call (the
+    // product with beta = 0, each workgroup's partial, each sum)
+    const int pieces[3] = {1, 2, 3};
+    for (int q = 0; q < 3; ++q) {
+      launch_csr_spmv(F.N, h->full_rp, h->full_col, h->full_piece[pieces[q]], x, tmp, 0.0, h->stream);
+      launch_masked_dot(lam, h->dir_mask, tmp, F.N, part, sum + q, h->stream);
+    }
+    double s[3];
+    HIPCHECK(hipMemcpyAsync(s, sum, sizeof(s), hipMemcpyDeviceToHost, h->stream));
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    const double nu = h->phys.nu, E = h->phys.E;
+    const double dG = 1.0 / (2.0 * (1.0 + nu));
+    const double dI = nu >= 0.5 ? 0.0 : -(1.0 + nu) * (1.0 - 2.0 * nu) / (nu * E * E);
+    out[0] = -(dG * s[0] + dI * s[1]);
+    out[1] = -s[2];
+    return FSGMG_OK;
+  });
+}
+
 fsgmg_status update_params(fsgmg_h h, double E, double mu) {
   if (!h) return FSGMG_EINVAL;
   return guarded(h, [&]() -> fsgmg_status {

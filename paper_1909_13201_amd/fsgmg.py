@@ -28,6 +28,7 @@ PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
 EXPORTED = ["setup_hierarchy", "build_fs_as_blocks", "vcycle_apply", "vcycle_apply_batch",
             "gmres_solve", "gmres_solve_batch", "adjoint_solve_batch",
             "adjoint_solve", "assemble_load", "load_adjoint", "apply_operator", "param_grad",
+            "param_grad_noalloc",
             "update_params", "level_info", "dof_map", "debug_zero_block", "export_csr", "export_vector", "export_blocks", "block_colours",
             "kernel_timing", "tuning_info", "last_error", "hierarchy_destroy"]
 
@@ -133,6 +134,7 @@ def lib():
             "load_adjoint": ([H, P, P], C.c_int),
             "apply_operator": ([H, C.c_int, P, P, C.c_int], C.c_int),
             "param_grad": ([H, P, P, C.POINTER(C.c_double)], C.c_int),
+            "param_grad_noalloc": ([H, P, P, C.POINTER(C.c_double)], C.c_int),
             "update_params": ([H, C.c_double, C.c_double], C.c_int),
             "level_info": ([H, C.c_int, C.POINTER(C.c_int64)], C.c_int),
             "dof_map": ([H, C.c_int, C.POINTER(C.c_int64), P, P, P, P], C.c_int),
