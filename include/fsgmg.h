@@ -218,8 +218,10 @@ fsgmg_status setup_hierarchy(const fsgmg_mesh_desc* mesh, const fsgmg_physics* p
 
 /* Build the FS-AS block index sets (Section 3.2: the field split P_2 of
  * eq. FS, its blocks solved by additive Schwarz AS_1 / AS_2 with the Vanka
- * selection rule and the last-writer owner map), gather every block's principal submatrix, invert it in FP64 on
- * the device (partial pivoting) and keep the owned rows in opts->prec.
+ * selection rule and the last-writer owner map), gather every block's principal submatrix, invert it on the
+ * device by Gauss-Jordan with partial pivoting (in FP64 for FP64 inverses,
+ * in FP32 for FP32 and BF16 inverses) and keep the owned rows in
+ * opts->prec.
  * ESINGULAR (block id in last_error) on a zero pivot.  On a host-only handle
  * only the index sets are built. */
 fsgmg_status build_fs_as_blocks(fsgmg_h h, const fsgmg_smoother_opts* opts);
@@ -388,6 +390,14 @@ fsgmg_status block_colours(fsgmg_h h, int level, int64_t* ncolours, int64_t* col
  * K-column block applies as kind 0 and its K-column residuals as kind 1).
  * counts / total_ms may be NULL. */
 fsgmg_status kernel_timing(fsgmg_h h, int enable, int64_t counts[4], double total_ms[4]);
+
+/* Measurement: the read-only streaming rate of the device, as the ceiling a
+ * read-dominated kernel is held against.  A buffer of `bytes` (>= 1 MiB,
+ * from the handle's allocator, freed on return) is read once per launch
+ * with 16-byte loads by a grid of 2,048 workgroups, `reps` times after one
+ * warm-up; *gbs = bytes / median launch time (HIP events on the handle's
+ * stream), in GB/s.  Synchronizes; ENOMEM without room for the buffer. */
+fsgmg_status stream_read_ceiling(fsgmg_h h, int64_t bytes, int reps, double* gbs);
 
 /* Launch shapes chosen by the autotuner that build_fs_as_blocks runs on the
  * device (HIP-event timing of each candidate launch on the level's own data,

@@ -700,21 +700,22 @@ __global__ __launch_bounds__(kThreads) void k_smooth_t2(BlocksView B, const TV* 
 // in the leading n x n corner.
 __device__ inline int pad16(int n) { return (n + 15) & ~15; }
 
+template <typename TF>
 __global__ __launch_bounds__(kThreads) void k_gather_blocks(const int32_t* __restrict__ jlist,
                                                             BlocksView B,
                                                             const int64_t* __restrict__ rp,
                                                             const int32_t* __restrict__ col,
                                                             const double* __restrict__ val,
                                                             const int64_t* __restrict__ doff,
-                                                            double* __restrict__ dense) {
+                                                            TF* __restrict__ dense) {
   const int64_t j = jlist[blockIdx.x];
   const int64_t d0 = B.dof_ptr[j];
   const int n = (int)(B.dof_ptr[j + 1] - d0);
   const int np = pad16(n);
-  double* a = dense + doff[blockIdx.x];
+  TF* a = dense + doff[blockIdx.x];
   for (int64_t e = threadIdx.x; e < (int64_t)np * np; e += blockDim.x) {
     const int r = (int)(e / np);
-    a[e] = (r >= n && e == (int64_t)r * np + r) ? 1.0 : 0.0;
+    a[e] = (r >= n && e == (int64_t)r * np + r) ? TF(1) : TF(0);
   }
   __syncthreads();
   const int32_t* I = B.dofs + d0;
@@ -727,7 +728,7 @@ __global__ __launch_bounds__(kThreads) void k_gather_blocks(const int32_t* __res
         const int mid = (lo + hi) >> 1;
         const int32_t v = I[mid];
         if (v == c) {
-          a[(int64_t)k * np + mid] = val[e];
+          a[(int64_t)k * np + mid] = (TF)val[e];
           break;
         }
         if (v < c)
@@ -756,15 +757,42 @@ __global__ __launch_bounds__(kThreads) void k_gather_blocks(const int32_t* __res
 // result[:, sigma[q]]) that the owned-row extraction applies, instead of
 // column swaps over the whole matrix.
 using f64x4 = __attribute__((__vector_size__(4 * sizeof(double)))) double;
+// Matrix-core tile: 16 x 16 output, 4 inner products per instruction.
+// Operand layout of the 16x16x4 instructions: A[i][k] in lane i + 16 k,
+// B[k][j] in lane j + 16 k; accumulator entry r of lane l is row
+// row(l / 16, r) of column l % 16: rows 4 (l / 16) + r for FP32 and
+// l / 16 + 4 r for FP64.
+using f32x4 = __attribute__((__vector_size__(4 * sizeof(float)))) float;
+template <typename TA>
+struct MfmaTile;
+template <>
+struct MfmaTile<float> {
+  using acc_t = f32x4;
+  __device__ static acc_t step(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int lg, int r) { return 4 * lg + r; }
+};
+template <>
+struct MfmaTile<double> {
+  using acc_t = f64x4;
+  __device__ static acc_t step(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int lg, int r) { return lg + 4 * r; }
+};
+
 constexpr int kPanel = 16;      // LDS strip width
 constexpr int kInvThreads = 256;   // workgroup of the block inversion (measured best of 256 / 512 / 1024)
 constexpr int kOuterPanel = 64; // columns per pass over the block
 
-template <int NB, int NO>
+template <typename TF, int NB, int NO>
 __global__ __launch_bounds__(kInvThreads) void k_invert_blocked(
     const int32_t* __restrict__ jlist, const int64_t* __restrict__ dof_ptr,
-    const int64_t* __restrict__ doff, const int64_t* __restrict__ soff, double* __restrict__ dense,
+    const int64_t* __restrict__ doff, const int64_t* __restrict__ soff, TF* __restrict__ dense,
     int32_t* __restrict__ sigma_all, int32_t* __restrict__ status) {
+  using MT = MfmaTile<TF>;
+  using acc_t = typename MT::acc_t;
   static_assert(NB == 16 && NO % NB == 0, "strip of one tile, outer panel of whole strips");
   constexpr int LDT = NB + 1;   // LDS row stride (doubles) of the strip
   constexpr int NW = kInvThreads / 64;
@@ -772,10 +800,10 @@ __global__ __launch_bounds__(kInvThreads) void k_invert_blocked(
   const int64_t j = jlist[blockIdx.x];
   const int n = (int)(dof_ptr[j + 1] - dof_ptr[j]);
   const int np = pad16(n);
-  double* a = dense + doff[blockIdx.x];
-  double* T = reinterpret_cast<double*>(smem_raw);   // np x LDT
-  double* rowc = T + (size_t)np * LDT;                // NB
-  double* wval = rowc + NB;                           // NW
+  TF* a = dense + doff[blockIdx.x];
+  TF* T = reinterpret_cast<TF*>(smem_raw);            // np x LDT
+  TF* rowc = T + (size_t)np * LDT;                    // NB
+  TF* wval = rowc + NB;                               // NW
   int* widx = reinterpret_cast<int*>(wval + NW);      // NW
   int* piv = widx + NW;                               // np
   int* sig = piv + np;                                // np
@@ -802,10 +830,10 @@ __global__ __launch_bounds__(kInvThreads) void k_invert_blocked(
     __syncthreads();
     for (int kk = 0; kk < nbk; ++kk) {
       const int c = k0 + kk;
-      double best = -1.0;
+      TF best = TF(-1);
       int bi = np;
       for (int r = c + tid; r < np; r += kInvThreads) {
-        const double v = fabs(T[r * LDT + kk]);
+        const TF v = fabs(T[r * LDT + kk]);
         if (v > best) {
           best = v;
           bi = r;
@@ -813,7 +841,7 @@ __global__ __launch_bounds__(kInvThreads) void k_invert_blocked(
       }
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) {
-        const double v2 = __shfl_xor(best, off, 64);
+        const TF v2 = __shfl_xor(best, off, 64);
         const int i2 = __shfl_xor(bi, off, 64);
         if (v2 > best || (v2 == best && i2 < bi)) {
           best = v2;
@@ -833,7 +861,7 @@ __global__ __launch_bounds__(kInvThreads) void k_invert_blocked(
           best = wval[w];
           bi = widx[w];
         }
-      if (!(best > 0.0)) {   // the same decision in every thread
+      if (!(best > TF(0))) {   // the same decision in every thread
         if (tid == 0) status[j] = 1;
         return;
       }
@@ -843,30 +871,30 @@ __global__ __launch_bounds__(kInvThreads) void k_invert_blocked(
       // interchange and the elimination are one pass: position c receives
       // the scaled pivot row, position p the eliminated old row c, every
       // other row is eliminated in place (rows are owned by single threads)
-      double prow[NB], crow[NB];
+      TF prow[NB], crow[NB];
 #pragma unroll
       for (int q = 0; q < NB; ++q) {
         prow[q] = T[p * LDT + q];
         crow[q] = T[c * LDT + q];
       }
       __syncthreads();
-      const double d = 1.0 / prow[kk];
-      double rc[NB];
+      const TF d = TF(1) / prow[kk];
+      TF rc[NB];
 #pragma unroll
       for (int q = 0; q < NB; ++q) rc[q] = (q == kk) ? d : prow[q] * d;
       for (int r = tid; r < np; r += kInvThreads) {
-        double* Tr = T + r * LDT;
+        TF* Tr = T + r * LDT;
         if (r == c) {
 #pragma unroll
           for (int q = 0; q < NB; ++q) Tr[q] = rc[q];
         } else if (r == p) {
-          const double t = crow[kk];
+          const TF t = crow[kk];
 #pragma unroll
-          for (int q = 0; q < NB; ++q) Tr[q] = (q == kk ? 0.0 : crow[q]) - t * rc[q];
+          for (int q = 0; q < NB; ++q) Tr[q] = (q == kk ? TF(0) : crow[q]) - t * rc[q];
         } else {
-          const double t = Tr[kk];
+          const TF t = Tr[kk];
 #pragma unroll
-          for (int q = 0; q < NB; ++q) Tr[q] = (q == kk ? 0.0 : Tr[q]) - t * rc[q];
+          for (int q = 0; q < NB; ++q) Tr[q] = (q == kk ? TF(0) : Tr[q]) - t * rc[q];
         }
       }
       __syncthreads();
@@ -904,7 +932,7 @@ __global__ __launch_bounds__(kInvThreads) void k_invert_blocked(
       const int ns = swn[0];
       for (int col = tid; col < np - nbk; col += kInvThreads) {
         const int cc = col < k0 ? col : col + nbk;
-        double v[2 * NB];
+        TF v[2 * NB];
 #pragma unroll
         for (int x = 0; x < 2 * NB; ++x)
           if (x < ns) v[x] = a[(int64_t)swv[x] * np + cc];
@@ -917,9 +945,9 @@ __global__ __launch_bounds__(kInvThreads) void k_invert_blocked(
     // the strip's final values, then T - E_K in LDS for the update
     for (int e = tid; e < np * nbk; e += kInvThreads) {
       const int r = e / nbk, q = e - r * nbk;
-      const double v = T[r * LDT + q];
+      const TF v = T[r * LDT + q];
       a[(int64_t)r * np + k0 + q] = v;
-      if (r == k0 + q) T[r * LDT + q] = v - 1.0;
+      if (r == k0 + q) T[r * LDT + q] = v - TF(1);
     }
     __syncthreads();
     // rank-16 update of the outer panel's other column tiles (one wavefront
@@ -928,22 +956,19 @@ __global__ __launch_bounds__(kInvThreads) void k_invert_blocked(
     for (int J = u0 + wv; J < u1; J += NW) {
       if (J == ts) continue;
       const int c0 = J * 16 + lr;
-      double bq[NB / 4];
+      TF bq[NB / 4];
 #pragma unroll
       for (int q = 0; q < NB / 4; ++q) bq[q] = a[(int64_t)(k0 + 4 * q + lg) * np + c0];
-      // accumulator layout of v_mfma_f64_16x16x4f64: lane (lr, lg) holds
-      // rows lg, lg + 4, lg + 8, lg + 12 of column lr
+      // accumulator entry r of lane (lr, lg): row MT::row(lg, r) of column lr
       for (int it = 0; it < ntile; ++it) {
-        const int r0 = it * 16 + lg;
-        f64x4 acc;
+        acc_t acc;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) acc[r] = a[(int64_t)(r0 + 4 * r) * np + c0];
-        const double* Tt = T + (it * 16 + lr) * LDT + lg;
+        for (int r = 0; r < 4; ++r) acc[r] = a[(int64_t)(it * 16 + MT::row(lg, r)) * np + c0];
+        const TF* Tt = T + (it * 16 + lr) * LDT + lg;
 #pragma unroll
-        for (int q = 0; q < NB / 4; ++q)
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Tt[4 * q], bq[q], acc, 0, 0, 0);
+        for (int q = 0; q < NB / 4; ++q) acc = MT::step(Tt[4 * q], bq[q], acc);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) a[(int64_t)(r0 + 4 * r) * np + c0] = acc[r];
+        for (int r = 0; r < 4; ++r) a[(int64_t)(it * 16 + MT::row(lg, r)) * np + c0] = acc[r];
       }
     }
     __syncthreads();
@@ -957,26 +982,25 @@ __global__ __launch_bounds__(kInvThreads) void k_invert_blocked(
   for (int J = wv; J < ntile; J += NW) {
     if (J >= u0 && J < u1) continue;
     const int c0 = J * 16 + lr;
-    double bq[NO / 4];
+    TF bq[NO / 4];
 #pragma unroll
     for (int q = 0; q < NO / 4; ++q)
-      bq[q] = (4 * q < nko) ? a[(int64_t)(K0 + 4 * q + lg) * np + c0] : 0.0;
+      bq[q] = (4 * q < nko) ? a[(int64_t)(K0 + 4 * q + lg) * np + c0] : TF(0);
     for (int it = 0; it < ntile; ++it) {
-      const int r0 = it * 16 + lg;
       const int ra = it * 16 + lr;   // A-operand row of this lane
-      f64x4 acc;
+      acc_t acc;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) acc[r] = a[(int64_t)(r0 + 4 * r) * np + c0];
-      const double* Ta = a + (int64_t)ra * np + K0 + lg;
+      for (int r = 0; r < 4; ++r) acc[r] = a[(int64_t)(it * 16 + MT::row(lg, r)) * np + c0];
+      const TF* Ta = a + (int64_t)ra * np + K0 + lg;
 #pragma unroll
       for (int q = 0; q < NO / 4; ++q) {
         if (4 * q < nko) {
-          const double t = Ta[4 * q] - (ra == K0 + 4 * q + lg ? 1.0 : 0.0);
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(t, bq[q], acc, 0, 0, 0);
+          const TF t = Ta[4 * q] - (ra == K0 + 4 * q + lg ? TF(1) : TF(0));
+          acc = MT::step(t, bq[q], acc);
         }
       }
 #pragma unroll
-      for (int r = 0; r < 4; ++r) a[(int64_t)(r0 + 4 * r) * np + c0] = acc[r];
+      for (int r = 0; r < 4; ++r) a[(int64_t)(it * 16 + MT::row(lg, r)) * np + c0] = acc[r];
     }
   }
   __syncthreads();
@@ -1007,12 +1031,12 @@ __device__ inline float to_w<float>(double v) { return (float)v; }
 template <>
 __device__ inline __hip_bfloat16 to_w<__hip_bfloat16>(double v) { return __float2bfloat16((float)v); }
 
-template <typename TW>
+template <typename TW, typename TF>
 __global__ __launch_bounds__(kThreads) void k_extract(const int32_t* __restrict__ jlist,
                                                       BlocksView B,
                                                       const int64_t* __restrict__ doff,
                                                       const int64_t* __restrict__ soff,
-                                                      const double* __restrict__ dense,
+                                                      const TF* __restrict__ dense,
                                                       const int32_t* __restrict__ sigma_all,
                                                       TW* __restrict__ W) {
   const int64_t j = jlist[blockIdx.x];
@@ -1021,13 +1045,13 @@ __global__ __launch_bounds__(kThreads) void k_extract(const int32_t* __restrict_
   const int o0 = B.own_ptr[j];
   const int m = B.own_ptr[j + 1] - o0;
   const int mp = B.mpad[j];
-  const double* a = dense + doff[blockIdx.x];
+  const TF* a = dense + doff[blockIdx.x];
   const int32_t* sg = sigma_all + soff[blockIdx.x];
   TW* Wj = W + B.w_off[j];
   // W (column-major, mp rows): W[k][i] = inverse[own_loc[i]][k]
   for (int64_t e = threadIdx.x; e < (int64_t)n * mp; e += blockDim.x) {
     const int k = (int)(e / mp), i = (int)(e - (int64_t)k * mp);
-    const double v = i < m ? a[(int64_t)B.own_loc[o0 + i] * np + sg[k]] : 0.0;
+    const double v = i < m ? (double)a[(int64_t)B.own_loc[o0 + i] * np + sg[k]] : 0.0;
     Wj[e] = to_w<TW>(v);
   }
 }
@@ -2157,26 +2181,6 @@ __global__ __launch_bounds__(kDenseMcThreads) void k_dense_mc(int64_t n,
 // 16x16x4 instructions: A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k;
 // accumulator entry r of lane l is row rowof(l, r) of column l % 16, with
 // rows 4 (l / 16) + r for FP32 and l / 16 + 4 r for FP64.
-using f32x4 = __attribute__((__vector_size__(4 * sizeof(float)))) float;
-template <typename TA>
-struct MfmaTile;
-template <>
-struct MfmaTile<float> {
-  using acc_t = f32x4;
-  __device__ static acc_t step(float a, float b, acc_t c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  __device__ static int row(int lg, int r) { return 4 * lg + r; }
-};
-template <>
-struct MfmaTile<double> {
-  using acc_t = f64x4;
-  __device__ static acc_t step(double a, double b, acc_t c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  __device__ static int row(int lg, int r) { return lg + 4 * r; }
-};
-
 template <typename TW, typename TA>
 __device__ inline TA w_scalar(const TW* p) {
   if constexpr (sizeof(TW) == 2)
@@ -2843,44 +2847,67 @@ template void launch_add_scaled<float>(int64_t, double, const float*, float*, bo
 
 void launch_gather_blocks(const int32_t* jlist, int64_t nb, const BlocksView& B,
                           const int64_t* rowptr, const int32_t* col, const double* val,
-                          const int64_t* dense_off, double* dense, hipStream_t s) {
-  if (nb > 0)
-    hipLaunchKernelGGL(k_gather_blocks, dim3((unsigned)nb), dim3(kThreads), 0, s, jlist, B, rowptr,
-                       col, val, dense_off, dense);
+                          const int64_t* dense_off, void* dense, bool f32, hipStream_t s) {
+  if (nb <= 0) return;
+  if (f32)
+    hipLaunchKernelGGL((k_gather_blocks<float>), dim3((unsigned)nb), dim3(kThreads), 0, s, jlist, B,
+                       rowptr, col, val, dense_off, (float*)dense);
+  else
+    hipLaunchKernelGGL((k_gather_blocks<double>), dim3((unsigned)nb), dim3(kThreads), 0, s, jlist,
+                       B, rowptr, col, val, dense_off, (double*)dense);
 }
 
-size_t invert_blocks_lds(int np_max) {
-  return (size_t)np_max * (kPanel + 1) * 8 + (size_t)kPanel * 8 + (kInvThreads / 64) * 12 +
+size_t invert_blocks_lds(int np_max, bool f32) {
+  const size_t tf = f32 ? 4 : 8;
+  // strip (np x (NB + 1)), the pivot row's copy (NB), the wave maxima and
+  // their rows, pivots and sigma (np each), the interchange lists
+  return (size_t)np_max * (kPanel + 1) * tf + (size_t)kPanel * tf + (kInvThreads / 64) * (tf + 4) +
          (size_t)np_max * 8 + (size_t)(4 * kPanel + 1) * 4;
 }
 
 void launch_invert_blocks(const int32_t* jlist, int64_t nb, const int64_t* dof_ptr,
-                          const int64_t* dense_off, const int64_t* sigma_off, double* dense,
-                          int32_t* sigma, int32_t* status, int max_n, hipStream_t s) {
+                          const int64_t* dense_off, const int64_t* sigma_off, void* dense,
+                          bool f32, int32_t* sigma, int32_t* status, int max_n, hipStream_t s) {
   if (nb <= 0) return;
-  const size_t sm = invert_blocks_lds((max_n + 15) & ~15);
-  hipLaunchKernelGGL((k_invert_blocked<kPanel, kOuterPanel>), dim3((unsigned)nb), dim3(kInvThreads), sm, s, jlist,
-                     dof_ptr, dense_off, sigma_off, dense, sigma, status);
+  const size_t sm = invert_blocks_lds((max_n + 15) & ~15, f32);
+  if (f32)
+    hipLaunchKernelGGL((k_invert_blocked<float, kPanel, kOuterPanel>), dim3((unsigned)nb),
+                       dim3(kInvThreads), sm, s, jlist, dof_ptr, dense_off, sigma_off,
+                       (float*)dense, sigma, status);
+  else
+    hipLaunchKernelGGL((k_invert_blocked<double, kPanel, kOuterPanel>), dim3((unsigned)nb),
+                       dim3(kInvThreads), sm, s, jlist, dof_ptr, dense_off, sigma_off,
+                       (double*)dense, sigma, status);
 }
 
-void launch_extract_owned(const int32_t* jlist, int64_t nb, const BlocksView& B,
-                          const int64_t* dense_off, const int64_t* sigma_off, const double* dense,
-                          const int32_t* sigma, WPrec wp, void* W, hipStream_t s) {
-  if (nb <= 0) return;
+template <typename TF>
+static void extract_as(const int32_t* jlist, int64_t nb, const BlocksView& B,
+                       const int64_t* dense_off, const int64_t* sigma_off, const TF* dense,
+                       const int32_t* sigma, WPrec wp, void* W, hipStream_t s) {
   switch (wp) {
     case WPrec::F64:
-      hipLaunchKernelGGL((k_extract<double>), dim3((unsigned)nb), dim3(kThreads), 0, s, jlist, B,
-                         dense_off, sigma_off, dense, sigma, (double*)W);
+      hipLaunchKernelGGL((k_extract<double, TF>), dim3((unsigned)nb), dim3(kThreads), 0, s, jlist,
+                         B, dense_off, sigma_off, dense, sigma, (double*)W);
       break;
     case WPrec::F32:
-      hipLaunchKernelGGL((k_extract<float>), dim3((unsigned)nb), dim3(kThreads), 0, s, jlist, B,
-                         dense_off, sigma_off, dense, sigma, (float*)W);
+      hipLaunchKernelGGL((k_extract<float, TF>), dim3((unsigned)nb), dim3(kThreads), 0, s, jlist,
+                         B, dense_off, sigma_off, dense, sigma, (float*)W);
       break;
     case WPrec::BF16:
-      hipLaunchKernelGGL((k_extract<__hip_bfloat16>), dim3((unsigned)nb), dim3(kThreads), 0, s,
+      hipLaunchKernelGGL((k_extract<__hip_bfloat16, TF>), dim3((unsigned)nb), dim3(kThreads), 0, s,
                          jlist, B, dense_off, sigma_off, dense, sigma, (__hip_bfloat16*)W);
       break;
   }
+}
+
+void launch_extract_owned(const int32_t* jlist, int64_t nb, const BlocksView& B,
+                          const int64_t* dense_off, const int64_t* sigma_off, const void* dense,
+                          bool f32, const int32_t* sigma, WPrec wp, void* W, hipStream_t s) {
+  if (nb <= 0) return;
+  if (f32)
+    extract_as<float>(jlist, nb, B, dense_off, sigma_off, (const float*)dense, sigma, wp, W, s);
+  else
+    extract_as<double>(jlist, nb, B, dense_off, sigma_off, (const double*)dense, sigma, wp, W, s);
 }
 
 template <typename TV>

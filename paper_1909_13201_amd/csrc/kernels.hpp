@@ -238,22 +238,25 @@ void launch_add_scaled(int64_t n, double a, const TV* e, TV* x, bool first, hipS
 // list works on block jlist[b]).  Dense copies of the blocks' principal
 // submatrices, row stride np = n rounded up to 16, identity in the padding;
 // dense_off[b] = element offset of list entry b.
+// The dense copies, the factorization and the extraction run in the factor
+// type: FP64 (f32 = false) for FP64 inverses, FP32 (f32 = true) for FP32 and
+// BF16 inverses; `dense` holds elements of that type.
 void launch_gather_blocks(const int32_t* jlist, int64_t nb, const BlocksView& B,
                           const int64_t* rowptr, const int32_t* col, const double* val,
-                          const int64_t* dense_off, double* dense, hipStream_t s);
+                          const int64_t* dense_off, void* dense, bool f32, hipStream_t s);
 // Blocked in-place Gauss-Jordan inversion with partial pivoting of the padded
-// dense blocks (16-column panels, FP64 MFMA trailing updates);
+// dense blocks (16-column panels, MFMA trailing updates in the factor type);
 // sigma[sigma_off[b] + q] receives the column permutation that completes the
 // inverse; status[j] = 1 on a zero pivot.  max_n bounds the listed blocks'
 // sizes (it sizes the LDS); invert_blocks_lds: the LDS bytes one workgroup
 // needs for blocks of padded size np_max.
-size_t invert_blocks_lds(int np_max);
+size_t invert_blocks_lds(int np_max, bool f32);
 void launch_invert_blocks(const int32_t* jlist, int64_t nb, const int64_t* dof_ptr,
-                          const int64_t* dense_off, const int64_t* sigma_off, double* dense,
-                          int32_t* sigma, int32_t* status, int max_n, hipStream_t s);
+                          const int64_t* dense_off, const int64_t* sigma_off, void* dense,
+                          bool f32, int32_t* sigma, int32_t* status, int max_n, hipStream_t s);
 void launch_extract_owned(const int32_t* jlist, int64_t nb, const BlocksView& B,
-                          const int64_t* dense_off, const int64_t* sigma_off, const double* dense,
-                          const int32_t* sigma, WPrec wp, void* W, hipStream_t s);
+                          const int64_t* dense_off, const int64_t* sigma_off, const void* dense,
+                          bool f32, const int32_t* sigma, WPrec wp, void* W, hipStream_t s);
 
 // Dense inverse of the coarse-level matrix (CSR, n rows) by blocked
 // Gauss-Jordan with partial pivoting spread over the GPU.  launch_coarse_factor

@@ -983,6 +983,10 @@ void upload_blocks(fsgmg_hierarchy& h, int l) {
   }
 }
 
+// FP32 and BF16 inverses are factored in FP32 (FP32 matrix cores, half the
+// bytes and LDS of the FP64 factorization), FP64 inverses in FP64.
+bool factor_f32(const fsgmg_hierarchy& h) { return h.sopt.prec != FSGMG_FP64; }
+
 void plan_factor(fsgmg_hierarchy& h, int l) {
   const BlockSet& bs = h.blocks[l];
   DLevel& d = h.dl[l];
@@ -1005,7 +1009,7 @@ void plan_factor(fsgmg_hierarchy& h, int l) {
   auto padded = [](int64_t n) { return (n + 15) & ~(int64_t)15; };
   int max_lds = 0;
   HIPCHECK(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h.device));
-  if (invert_blocks_lds((int)padded(d.bv.max_n)) > (size_t)max_lds)
+  if (invert_blocks_lds((int)padded(d.bv.max_n), factor_f32(h)) > (size_t)max_lds)
     throw Fail{FSGMG_EINVAL, "Schwarz block of " + std::to_string(d.bv.max_n) +
                                  " unknowns exceeds the LDS of one workgroup"};
   // np <= 384: 55 KB of LDS, three workgroups per CU
@@ -1086,17 +1090,21 @@ void factor_blocks(fsgmg_hierarchy& h) {
       const int32_t* jl = fp.jlist + c.b0;
       const int64_t* doff = fp.offs + c.off;
       const int64_t* soff = doff + cnt + 1;
-      launch_gather_blocks(jl, cnt, d.bv, d.rp, d.col, d.val, doff, fp.dense, fp.stream);
+      const bool f32 = factor_f32(h);
+      launch_gather_blocks(jl, cnt, d.bv, d.rp, d.col, d.val, doff, fp.dense, f32, fp.stream);
       if (h.zero_block_level == l)
         for (int64_t b = 0; b < cnt; ++b)
           if (fp.order[c.b0 + b] == h.zero_block) {
             // test hook: a zero matrix, so the block's first pivot is zero
             const int64_t o = fp.hoffs[c.off + b], n2 = fp.hoffs[c.off + b + 1] - o;
-            launch_fill<double>(fp.dense + o, 0.0, n2, fp.stream);
+            if (f32)
+              launch_fill<float>(reinterpret_cast<float*>(fp.dense) + o, 0.0f, n2, fp.stream);
+            else
+              launch_fill<double>(fp.dense + o, 0.0, n2, fp.stream);
           }
-      launch_invert_blocks(jl, cnt, d.bv.dof_ptr, doff, soff, fp.dense, fp.sigma, fp.status,
+      launch_invert_blocks(jl, cnt, d.bv.dof_ptr, doff, soff, fp.dense, f32, fp.sigma, fp.status,
                            c.max_n, fp.stream);
-      launch_extract_owned(jl, cnt, d.bv, doff, soff, fp.dense, fp.sigma, wprec(h.sopt.prec),
+      launch_extract_owned(jl, cnt, d.bv, doff, soff, fp.dense, f32, fp.sigma, wprec(h.sopt.prec),
                            d.W, fp.stream);
       HIPCHECK(hipGetLastError());
     }
@@ -2678,6 +2686,39 @@ fsgmg_status block_colours(fsgmg_h h, int level, int64_t* ncolours, int64_t* col
     *ncolours = mult ? (int64_t)bs.colour_ptr.size() - 1 : 0;
     if (mult && colour_ptr)
       std::memcpy(colour_ptr, bs.colour_ptr.data(), bs.colour_ptr.size() * sizeof(int64_t));
+    return FSGMG_OK;
+  });
+}
+
+fsgmg_status stream_read_ceiling(fsgmg_h h, int64_t bytes, int reps, double* gbs) {
+  if (!h || !gbs || bytes < (int64_t)(1 << 20) || reps < 1) return FSGMG_EINVAL;
+  return guarded(h, [&]() -> fsgmg_status {
+    check_device(*h);
+    bytes &= ~(int64_t)255;
+    void* buf = h->raw_alloc((size_t)bytes + 256);
+    if (!buf) throw Fail{FSGMG_ENOMEM, "no room for the streaming buffer"};
+    struct Release {
+      fsgmg_hierarchy* h;
+      void* p;
+      ~Release() { h->raw_free(p); }
+    } rel{h, buf};
+    uint32_t* sink = reinterpret_cast<uint32_t*>(static_cast<char*>(buf) + bytes);
+    HIPCHECK(hipMemsetAsync(buf, 0, (size_t)bytes + 256, h->stream));
+    launch_flush(buf, bytes, sink, h->stream);   // warm-up
+    std::vector<float> ms;
+    hipEvent_t a = h->next_event(), b = h->next_event();
+    for (int r = 0; r < reps; ++r) {
+      HIPCHECK(hipEventRecord(a, h->stream));
+      launch_flush(buf, bytes, sink, h->stream);
+      HIPCHECK(hipEventRecord(b, h->stream));
+      HIPCHECK(hipEventSynchronize(b));
+      float t = 0;
+      HIPCHECK(hipEventElapsedTime(&t, a, b));
+      ms.push_back(t);
+    }
+    h->ev_used -= 2;
+    std::sort(ms.begin(), ms.end());
+    *gbs = (double)bytes / (ms[ms.size() / 2] * 1e-3) / 1e9;
     return FSGMG_OK;
   });
 }

@@ -30,7 +30,8 @@ EXPORTED = ["setup_hierarchy", "build_fs_as_blocks", "vcycle_apply", "vcycle_app
             "adjoint_solve", "assemble_load", "load_adjoint", "apply_operator", "param_grad",
             "param_grad_noalloc",
             "update_params", "level_info", "dof_map", "debug_zero_block", "export_csr", "export_vector", "export_blocks", "block_colours",
-            "kernel_timing", "tuning_info", "last_error", "hierarchy_destroy"]
+            "kernel_timing", "stream_read_ceiling", "tuning_info", "last_error",
+            "hierarchy_destroy"]
 
 
 class MeshDesc(C.Structure):
@@ -146,6 +147,7 @@ def lib():
             "kernel_timing": ([H, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double)],
                               C.c_int),
             "tuning_info": ([H, C.c_int, C.POINTER(C.c_int32)], C.c_int),
+            "stream_read_ceiling": ([H, C.c_int64, C.c_int, C.POINTER(C.c_double)], C.c_int),
             "last_error": ([H], C.c_char_p),
             "hierarchy_destroy": ([H], None),
         }
@@ -577,3 +579,9 @@ class Hierarchy:
 
     def tuning_info(self):
         return [tuning_info(self.h, l) for l in range(self.L)]
+
+    def stream_read_ceiling(self, nbytes=1 << 30, reps=7):
+        """Read-only streaming rate of the device in GB/s (measurement)."""
+        out = C.c_double(0.0)
+        _check(self.h, lib().stream_read_ceiling(self.h, int(nbytes), int(reps), C.byref(out)))
+        return out.value
