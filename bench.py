@@ -776,6 +776,25 @@ def main():
     except (fsgmg.FsgmgError, SolveFailed) as e:
         mult = dict(not_run=str(e))
     out["multiplicative"] = mult
+    # the interchanged cascade (the paper's future work: GMRES preconditioned
+    # by the field split, each diagonal block by one GMG cycle on it)
+    inter = {}
+    try:
+        for prec in ("fp64", "fp32"):
+            t0 = time.perf_counter()
+            H.build_fs_as_blocks(prec=prec, interchange=True)
+            torch.cuda.synchronize()
+            tb = time.perf_counter() - t0
+            xi = torch.zeros_like(b)
+            ti, infi = timed_solves(H, b, xi, args.steps, args.warmup, rtol)
+            inter[prec] = dict(solves_per_s=round(args.steps / ti, 4), iters=infi[-1]["iters"],
+                               rel_res_true=infi[-1]["rel_res_true"], build_blocks_s=round(tb, 3))
+        inter["over_standard_fp32"] = round(inter["fp32"]["solves_per_s"] / (args.steps / t32), 3)
+        inter["iters_standard"] = inf32[-1]["iters"]
+        H.build_fs_as_blocks(prec="fp32")
+    except (fsgmg.FsgmgError, SolveFailed) as e:
+        inter = dict(not_run=str(e))
+    out["interchange"] = inter
     if cfg["name"] == "c2" and not args.levels and not args.no_c3:
         H.close()
         torch.cuda.empty_cache()

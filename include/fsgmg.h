@@ -164,7 +164,20 @@ typedef struct {
  * 1 = a residual SpMV before each forward sweep, 2 = forward sweeps that
  * form their blocks' residual rows inside the smoother launch (additive:
  * alternating between two iterate buffers; multiplicative: in place, colour
- * by colour).  Transposed sweeps always take the residual SpMV. */
+ * by colour).  Transposed sweeps always take the residual SpMV.
+ * interchange != 0 builds the cascade the paper names as future work
+ * (Section 5: its GMG and FS boxes swapped): GMRES preconditioned by the
+ * field split P_2 of eq. FS, block diagonal over the groups [d, p^s] and
+ * [u, p^f], each diagonal block approximated by one multigrid cycle on that
+ * block.  Both blocks' cycles share the levels, so they run as one cycle on
+ * the field split's diagonal blocks of every level operator (entries that
+ * couple the two groups removed), with the restriction kept inside each
+ * group (without R_2's routing of fine fluid-momentum rows into coarse
+ * solid-momentum rows), the same prolongation and FS-AS smoother, and the
+ * direct solve of level 0's diagonal blocks; FGMRES keeps the whole
+ * operator.  Sweeps use the SpMV form (sweep_form 2: EINVAL); the
+ * transposed cycle, adjoint_solve and the k-column calls are not built for
+ * it (EINVAL). */
 typedef struct {
   int core[3];
   int halo;
@@ -177,6 +190,7 @@ typedef struct {
   int cycle;
   int schwarz;
   int sweep_form;
+  int interchange;
 } fsgmg_smoother_opts;
 
 /* FGMRES(restart), right preconditioned, x0 = 0, CGS2; converged when the

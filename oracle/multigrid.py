@@ -9,6 +9,19 @@ pivoting.
 The transposed cycle applies M^T exactly: it is the V-cycle of A^T with the
 smoother B^T, restriction by (D_f P)^T, prolongation by (D_c R)^T and the
 numbers of pre- and post-sweeps exchanged.
+
+The interchange the paper names as future work (Section 5: the GMG and FS
+boxes of its solver cascade swapped) is built as cfg["interchange"]: GMRES
+preconditioned by the field split P_2 (eq. FS), which is block diagonal over
+the field groups [d, p^s] and [u, p^f], each diagonal block approximated by
+one GMG cycle on that block.  Both diagonal-block cycles share the levels,
+so they are one cycle on blockdiag(D_1, D_2) of every level operator: the
+residuals use the level operators with every entry coupling the two groups
+removed, the restriction keeps only the routing inside a group (R_2 sends
+fine fluid-momentum rows, which belong to D_2, into coarse solid-momentum
+rows of D_1; those entries are dropped), the prolongation never mixes the
+groups, the FS-AS blocks lie inside one group, and level 0 solves its own
+diagonal blocks directly.
 """
 from __future__ import annotations
 
@@ -20,6 +33,21 @@ from . import fem, transfer
 from .mesh import Level, hierarchy_levels
 from .schwarz import (FieldSplitSchwarz, MultiplicativeSchwarz, block_colouring,
                       build_blocks, colour_major, coupling_pattern)
+
+
+def field_groups(lv: Level) -> np.ndarray:
+    """Group of every unknown: 0 for d and p^s (the first row / column block
+    of J_2), 1 for u and p^f."""
+    g = np.zeros(lv.N, np.int8)
+    g[lv.off_u:] = 1
+    return g
+
+
+def diagonal_blocks(M: sp.spmatrix, grow: np.ndarray, gcol: np.ndarray) -> sp.csr_matrix:
+    """M with every entry that couples the two field groups removed."""
+    C = sp.coo_matrix(M)
+    keep = grow[C.row] == gcol[C.col]
+    return sp.csr_matrix((C.data[keep], (C.row[keep], C.col[keep])), shape=M.shape)
 
 
 class Hierarchy:
@@ -41,7 +69,17 @@ class Hierarchy:
                            for l in range(1, self.L)]
         self.R = [None] + [transfer.restriction(self.levels[l], self.levels[l - 1])
                            for l in range(1, self.L)]
-        self.coarse_lu = la.lu_factor(self.A[0].toarray())
+        # operators and restriction of the cycle: the level operators and R_2,
+        # or their field-group diagonal blocks for the interchanged cascade
+        self.interchange = bool(cfg.get("interchange", False))
+        if self.interchange:
+            g = [field_groups(lv) for lv in self.levels]
+            self.Ac = [diagonal_blocks(self.A[l], g[l], g[l]) for l in range(self.L)]
+            self.Rc = [None] + [diagonal_blocks(self.R[l], g[l - 1], g[l])
+                                for l in range(1, self.L)]
+        else:
+            self.Ac, self.Rc = self.A, self.R
+        self.coarse_lu = la.lu_factor(self.Ac[0].toarray())
         self.smoothers = [None] * self.L
         if build_smoothers:
             self.build_smoothers()
@@ -67,11 +105,11 @@ class Hierarchy:
         for l in range(1, self.L):
             blocks, _ = build_blocks(self.levels[l], core, halo, mult, mono)
             if kind == "additive":
-                self.smoothers[l] = FieldSplitSchwarz(self.A[l], blocks)
+                self.smoothers[l] = FieldSplitSchwarz(self.Ac[l], blocks)
             else:
                 blocks, self.colours[l] = colour_major(
                     blocks, block_colouring(self.coupling_pattern(l), blocks))
-                self.smoothers[l] = MultiplicativeSchwarz(self.A[l], blocks)
+                self.smoothers[l] = MultiplicativeSchwarz(self.Ac[l], blocks)
 
     def coupling_pattern(self, l: int) -> sp.csr_matrix:
         """Parameter-independent coupling pattern of the level-l operator (the
@@ -90,7 +128,7 @@ class Hierarchy:
 
     # ------------------------------------------------------------------
     def _sweeps(self, l, b, x, n, transpose):
-        A = self.A[l]
+        A = self.Ac[l]
         S = self.smoothers[l]
         om = self.cfg["omega"]
         for s in range(n):
@@ -127,21 +165,21 @@ class Hierarchy:
         if transpose:
             n1, n2 = n2, n1
         x = self._sweeps(l, b, x0, n1, transpose)
-        A = self.A[l]
+        A = self.Ac[l]
         if x is None:
             x = np.zeros_like(b)
         r = b - (A.T @ x if transpose else A @ x)
         if transpose:
             bc = self.P[l].T @ r
         else:
-            bc = self.R[l] @ r
+            bc = self.Rc[l] @ r
         coarse = {"V": ["V"], "W": ["W", "W"], "F": ["F", "V"]}[kind]
         if transpose:
             coarse = coarse[::-1]
         xc = None
         for k in coarse:
             xc = self.vcycle(bc, l - 1, transpose, xc, k)
-        x = x + (self.R[l].T @ xc if transpose else self.P[l] @ xc)
+        x = x + (self.Rc[l].T @ xc if transpose else self.P[l] @ xc)
         x = self._sweeps(l, b, x, n2, transpose)
         return x
 

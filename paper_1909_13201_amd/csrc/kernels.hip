@@ -197,8 +197,11 @@ __global__ __launch_bounds__(kThreads) void k_transfer(TransferView<T> t, int mo
                                                        T* __restrict__ out) {
   const int lane = threadIdx.x & (LG - 1);
   const int64_t id = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LG;
-  if (mode == 0 || mode == 2) {
-    // coarse outputs
+  if (mode == 0 || mode == 2 || mode == 4) {
+    // coarse outputs (mode 4: the restriction of mode 0 without the routing
+    // of fine fluid-momentum rows into coarse solid-momentum rows, i.e. kept
+    // inside each field group, for the cycle on the field split's diagonal
+    // blocks)
     if (id < t.N2c) {
       const int64_t I = id;
       const uint8_t fc = t.flags_c[I];
@@ -210,7 +213,7 @@ __global__ __launch_bounds__(kThreads) void k_transfer(TransferView<T> t, int mo
         const int64_t i = t.rn_col[k];
         const T w = t.rn_val[k];
         const uint8_t ff = t.flags_f[i];
-        if (mode == 0) {
+        if (mode == 0 || mode == 4) {
           const bool ssi = ff & kSolid;
           if (ssI == ssi) {
 #pragma unroll
@@ -218,7 +221,7 @@ __global__ __launch_bounds__(kThreads) void k_transfer(TransferView<T> t, int mo
               bd[c] += w * in[D * i + c];
               bu[c] += w * in[t.offu_f + D * i + c];
             }
-          } else if (ssI) {
+          } else if (ssI && mode == 0) {
 #pragma unroll
             for (int c = 0; c < D; ++c) bd[c] += w * in[t.offu_f + D * i + c];
           }
@@ -238,7 +241,8 @@ __global__ __launch_bounds__(kThreads) void k_transfer(TransferView<T> t, int mo
           bu[c] += __shfl_xor(bu[c], off, LG);
         }
       if (lane == 0) {
-        const bool zd = (mode == 0) && (fc & kDirD), zu = (mode == 0) && (fc & kDirU);
+        const bool rs = mode == 0 || mode == 4;
+        const bool zd = rs && (fc & kDirD), zu = rs && (fc & kDirU);
 #pragma unroll
         for (int c = 0; c < D; ++c) {
           out[D * I + c] = zd ? T(0) : bd[c];
@@ -2615,7 +2619,8 @@ template <typename T, int D>
 static void transfer_lanes(const TransferView<T>& t, int mode, const T* in, T* out, int lanes,
                            hipStream_t s) {
   const int LG = (lanes == 1 || lanes == 2 || lanes == 4 || lanes == 16) ? lanes : 8;
-  const int64_t n = (mode == 0 || mode == 2) ? t.N2c + t.Npsc + t.Npfc : t.N2f + t.Npsf + t.Npff;
+  const int64_t n =
+      (mode == 0 || mode == 2 || mode == 4) ? t.N2c + t.Npsc + t.Npfc : t.N2f + t.Npsf + t.Npff;
   const unsigned g = grid_for(n * LG, kThreads);
   if (!g) return;
   switch (LG) {

@@ -251,6 +251,14 @@ struct FactorPlan {
 struct DLevel {
   int64_t N = 0, nnz = 0;
   DevBOp A, AT;
+  // the field split's diagonal blocks of A (entries coupling [d, p^s] with
+  // [u, p^f] removed), used by the cycle of the interchanged cascade; level 0
+  // also keeps their CSR for its direct solve
+  DevBOp Abd;
+  bool use_bd = false;
+  int64_t* bd_rp = nullptr;
+  int32_t* bd_col = nullptr;
+  double* bd_val = nullptr;
   FactorPlan fp;
   int64_t* rp = nullptr;
   int32_t* col = nullptr;
@@ -322,6 +330,15 @@ struct fsgmg_hierarchy {
   int32_t* coarse_piv = nullptr;
   int64_t n0 = 0;
   int64_t coarse_np = 0;   // padded order of the coarse work matrix
+  bool coarse_bd = false;  // the coarse inverse is that of level 0's diagonal blocks
+  // host side of the diagonal-block operators: A's entries kept (in order)
+  // and their value slots in the device layout, per level
+  struct BdHost {
+    std::vector<int64_t> keep, bmap;
+    int64_t nvals = 0;
+  };
+  std::vector<BdHost> bd;
+  bool bd_dirty = false;
   // finest-level extras
   int64_t* load_rp = nullptr;
   int32_t* load_col = nullptr;
@@ -713,12 +730,19 @@ void build_coarse_inverse(fsgmg_hierarchy& h, bool async = false) {
   int32_t* status = h.coarse_piv + 2 * np;
   int32_t* src = h.coarse_piv + 2 * np + 1;
   double* a2 = reg ? h.coarse_work + np * np + scratch : nullptr;
-  const DLevel& C = h.dl[0];   // device CSR of level 0 (current parameter values)
+  const DLevel& C = h.dl[0];
+  // device CSR of level 0 (current parameter values), or its field-split
+  // diagonal blocks for the interchanged cascade
+  const bool bd = C.use_bd;
+  const int64_t* crp = bd ? C.bd_rp : C.rp;
+  const int32_t* ccol = bd ? C.bd_col : C.col;
+  const double* cval = bd ? C.bd_val : C.val;
+  h.coarse_bd = bd;
   int32_t* dsig = h.coarse_piv + np;
   if (async && coarse_sigma_lds(np) <= (size_t)max_lds) {
     if (!h.coarse_done) HIPCHECK(hipEventCreateWithFlags(&h.coarse_done, hipEventDisableTiming));
     HIPCHECK(hipMemsetAsync(status, 0, sizeof(int32_t), h.stream));
-    const double* res = launch_coarse_factor(n, np, C.rp, C.col, C.val, h.coarse_work,
+    const double* res = launch_coarse_factor(n, np, crp, ccol, cval, h.coarse_work,
                                              h.coarse_work + np * np, a2, src, h.coarse_piv,
                                              status, nb, h.stream);
     launch_coarse_sigma(h.coarse_piv, np, status, dsig, h.stream);
@@ -730,7 +754,7 @@ void build_coarse_inverse(fsgmg_hierarchy& h, bool async = false) {
     return;
   }
   HIPCHECK(hipMemsetAsync(status, 0, sizeof(int32_t), h.stream));
-  const double* res = launch_coarse_factor(n, np, C.rp, C.col, C.val, h.coarse_work,
+  const double* res = launch_coarse_factor(n, np, crp, ccol, cval, h.coarse_work,
                                            h.coarse_work + np * np, a2, src, h.coarse_piv, status,
                                            nb, h.stream);
   HIPCHECK(hipGetLastError());
@@ -749,6 +773,63 @@ void build_coarse_inverse(fsgmg_hierarchy& h, bool async = false) {
   HIPCHECK(hipGetLastError());
   HIPCHECK(hipStreamSynchronize(h.stream));
   h.n0 = n;
+}
+
+// The field split's diagonal blocks of every level operator (entries that
+// couple the groups [d, p^s] and [u, p^f] removed) on the device, for the
+// interchanged cascade: built from the host values on first use; after
+// update_params only their values are refreshed (the pattern is fixed).
+// Level 0 also keeps their CSR for its direct solve.
+void ensure_bd(fsgmg_hierarchy& h) {
+  const bool first = h.bd.size() != (size_t)h.L;
+  if (!first && !h.bd_dirty) return;
+  h.ensure_host_values();
+  if (first) h.bd.resize(h.L);
+  for (int l = 0; l < h.L; ++l) {
+    DLevel& d = h.dl[l];
+    const Level& lv = h.levels[l];
+    const CsrHost& A = h.ops[l].A;
+    fsgmg_hierarchy::BdHost& bh = h.bd[l];
+    if (first) {
+      CsrHost B;
+      B.nrows = A.nrows;
+      B.ncols = A.ncols;
+      B.rowptr.assign(A.nrows + 1, 0);
+      for (int64_t r = 0; r < A.nrows; ++r) {
+        const bool gr = r >= lv.off_u;
+        for (int64_t k = A.rowptr[r]; k < A.rowptr[r + 1]; ++k)
+          if ((A.col[k] >= lv.off_u) == gr) {
+            B.col.push_back(A.col[k]);
+            B.val.push_back(A.val[k]);
+            bh.keep.push_back(k);
+          }
+        B.rowptr[r + 1] = (int64_t)B.col.size();
+      }
+      const BOpHost bo = build_bop(lv, B);
+      bh.bmap = bo.map;
+      bh.nvals = bo.nvals();
+      upload_bop(h, lv, B, d.Abd);
+      if (l == 0) {
+        d.bd_rp = h.upload(B.rowptr);
+        d.bd_col = h.upload(B.col);
+        d.bd_val = h.upload(B.val);
+      }
+      continue;
+    }
+    std::vector<double> v(bh.nvals, 0.0), kv(bh.keep.size());
+    for (size_t i = 0; i < bh.keep.size(); ++i) kv[i] = A.val[bh.keep[i]];
+    for (size_t i = 0; i < bh.keep.size(); ++i) v[bh.bmap[i]] = kv[i];
+    const std::vector<float> v32(v.begin(), v.end());
+    HIPCHECK(hipMemcpyAsync(d.Abd.vals64, v.data(), v.size() * sizeof(double),
+                            hipMemcpyHostToDevice, h.stream));
+    HIPCHECK(hipMemcpyAsync(d.Abd.vals32, v32.data(), v32.size() * sizeof(float),
+                            hipMemcpyHostToDevice, h.stream));
+    if (l == 0)
+      HIPCHECK(hipMemcpyAsync(d.bd_val, kv.data(), kv.size() * sizeof(double),
+                              hipMemcpyHostToDevice, h.stream));
+    HIPCHECK(hipStreamSynchronize(h.stream));
+  }
+  h.bd_dirty = false;
 }
 
 void upload_all(fsgmg_hierarchy& h) {
@@ -1169,7 +1250,9 @@ struct Vec<double> {
   static double* xm(DLevel& d) { return d.xm64; }
   static double* rm(DLevel& d) { return d.rm64; }
   static double* tm(DLevel& d) { return d.tm64; }
-  static const BOpView<double>& op(DLevel& d, bool tr) { return tr ? d.AT.v64 : d.A.v64; }
+  static const BOpView<double>& op(DLevel& d, bool tr) {
+    return tr ? d.AT.v64 : (d.use_bd ? d.Abd.v64 : d.A.v64);
+  }
   static const TransferView<double>& tv(DLevel& d) { return d.t64; }
 };
 template <>
@@ -1185,7 +1268,9 @@ struct Vec<float> {
   static float* xm(DLevel& d) { return d.xm32; }
   static float* rm(DLevel& d) { return d.rm32; }
   static float* tm(DLevel& d) { return d.tm32; }
-  static const BOpView<float>& op(DLevel& d, bool tr) { return tr ? d.AT.v32 : d.A.v32; }
+  static const BOpView<float>& op(DLevel& d, bool tr) {
+    return tr ? d.AT.v32 : (d.use_bd ? d.Abd.v32 : d.A.v32);
+  }
   static const TransferView<float>& tv(DLevel& d) { return d.t32; }
 };
 
@@ -1345,7 +1430,8 @@ void cycle_level(fsgmg_hierarchy& h, int l, int kind, bool transpose, bool zero_
   }
   {
     TimedLaunch t(h, 3, l == L - 1);
-    launch_transfer<TV>(Vec<TV>::tv(d), D, transpose ? 2 : 0, Vec<TV>::r(d), Vec<TV>::b(h.dl[l - 1]),
+    launch_transfer<TV>(Vec<TV>::tv(d), D, transpose ? 2 : (d.use_bd ? 4 : 0), Vec<TV>::r(d),
+                        Vec<TV>::b(h.dl[l - 1]),
                         h.stream, h.tune[l].restrict_lanes);
   }
   int seq[2] = {FSGMG_CYCLE_V, FSGMG_CYCLE_V};
@@ -2125,8 +2211,11 @@ void autotune_impl(fsgmg_hierarchy& h) {
           th_fused = th;
         }
       }
+      // the fused form reads the blocks' copies of A's rows, so the
+      // interchanged cascade (its cycle uses the diagonal blocks of A) keeps
+      // the SpMV form
       const int form = h.sopt.sweep_form;
-      if (form == 2 || (form == 0 && t_fused < t_sep)) {
+      if (!h.sopt.interchange && (form == 2 || (form == 0 && t_fused < t_sep))) {
         h.tune[l].fused = 1;
         h.tune[l].smooth_threads = th_fused;
         h.tune[l].split = 1;
@@ -2160,6 +2249,8 @@ void check_mc(fsgmg_hierarchy& h, int k) {
   if (k < 1 || k > kMaxRhs) throw Fail{FSGMG_EINVAL, "k must be in 1..64"};
   if (h.sopt.schwarz != FSGMG_SCHWARZ_ADDITIVE)
     throw Fail{FSGMG_EINVAL, "several right-hand sides need the additive smoother"};
+  if (h.sopt.interchange)
+    throw Fail{FSGMG_EINVAL, "several right-hand sides: not built for the interchanged cascade"};
   for (int l = 1; l < h.L; ++l)
     if (h.dl[l].bv.max_n > kMaxRhsBlock)
       throw Fail{FSGMG_EINVAL, "several right-hand sides: a Schwarz block exceeds " +
@@ -2284,6 +2375,8 @@ static fsgmg_status build_fs_as_blocks_impl(fsgmg_h h, const fsgmg_smoother_opts
       throw Fail{FSGMG_EINVAL, "schwarz must be FSGMG_SCHWARZ_ADDITIVE or _MULTIPLICATIVE"};
     if (opts->sweep_form < 0 || opts->sweep_form > 2)
       throw Fail{FSGMG_EINVAL, "sweep_form must be 0 (autotuned), 1 (SpMV) or 2 (fused)"};
+    if (opts->interchange && opts->sweep_form == 2)
+      throw Fail{FSGMG_EINVAL, "the interchanged cascade runs its sweeps in the SpMV form"};
     const int mult = std::max(1, opts->iface_mult);
     const bool same_sets = h->have_blocks && h->sopt.halo == opts->halo &&
                            h->sopt.core[0] == opts->core[0] && h->sopt.core[1] == opts->core[1] &&
@@ -2301,7 +2394,8 @@ static fsgmg_status build_fs_as_blocks_impl(fsgmg_h h, const fsgmg_smoother_opts
     const bool keep_graphs = same_sets && h->tuned && o.nu_pre == opts->nu_pre &&
                              o.nu_post == opts->nu_post && o.omega == opts->omega &&
                              o.use_graph == opts->use_graph && o.cycle == opts->cycle &&
-                             o.sweep_form == opts->sweep_form;
+                             o.sweep_form == opts->sweep_form &&
+                             (o.interchange != 0) == (opts->interchange != 0);
     h->sopt = *opts;
     h->factors_valid = false;
     if (!keep_graphs) h->invalidate_graphs();
@@ -2325,6 +2419,15 @@ static fsgmg_status build_fs_as_blocks_impl(fsgmg_h h, const fsgmg_smoother_opts
         }
     }
     if (h->host_only()) return FSGMG_OK;
+    // the cycle's operators: A, or the field split's diagonal blocks of A
+    // for the interchanged cascade (whose level-0 direct solve is then that
+    // of level 0's diagonal blocks)
+    if (opts->interchange) ensure_bd(*h);
+    for (DLevel& d : h->dl) d.use_bd = opts->interchange != 0;
+    if (h->coarse_bd != (opts->interchange != 0)) {
+      ensure_coarse(*h);
+      build_coarse_inverse(*h);
+    }
     struct ClearHook {
       fsgmg_hierarchy* h;
       ~ClearHook() { h->zero_block_level = -1, h->zero_block = -1; }
@@ -2344,6 +2447,8 @@ fsgmg_status vcycle_apply(fsgmg_h h, const double* r, double* z, int transpose) 
   return guarded(h, [&]() -> fsgmg_status {
     check_device(*h);
     if (!h->factors_valid) throw Fail{FSGMG_ESTATE, "build_fs_as_blocks has not been called"};
+    if (transpose && h->sopt.interchange)
+      throw Fail{FSGMG_EINVAL, "the interchanged cascade has no transposed cycle"};
     if (transpose) ensure_transposed(*h);
     ensure_coarse(*h);
     vcycle(*h, r, z, transpose != 0);
@@ -2403,6 +2508,8 @@ fsgmg_status adjoint_solve(fsgmg_h h, const double* c, double* lam, const fsgmg_
   if (!h || !c || !lam || !opts || c == lam) return FSGMG_EINVAL;
   return guarded(h, [&]() -> fsgmg_status {
     check_device(*h);
+    if (h->sopt.interchange)
+      throw Fail{FSGMG_EINVAL, "the interchanged cascade has no transposed cycle for the adjoint"};
     ensure_coarse(*h);
     return fgmres(*h, c, lam, *opts, info, true);
   });
@@ -2541,6 +2648,8 @@ fsgmg_status update_params(fsgmg_h h, double E, double mu) {
     launch_recombine(NF, h->lift_piece[0], h->lift_piece[1], h->lift_piece[2], h->lift_piece[3], G,
                      invlam, mu, h->lift, nullptr, h->stream);
     HIPCHECK(hipGetLastError());
+    if (!h->bd.empty()) h->bd_dirty = true;      // the diagonal blocks follow the values
+    if (h->dl[0].use_bd) ensure_bd(*h);
     build_coarse_inverse(*h, true);
     return FSGMG_OK;
   });

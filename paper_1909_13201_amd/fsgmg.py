@@ -52,7 +52,8 @@ class SmootherOpts(C.Structure):
     _fields_ = [("core", C.c_int * 3), ("halo", C.c_int), ("nu_pre", C.c_int),
                 ("nu_post", C.c_int), ("omega", C.c_double), ("prec", C.c_int),
                 ("use_graph", C.c_int), ("iface_mult", C.c_int), ("monolithic", C.c_int),
-                ("cycle", C.c_int), ("schwarz", C.c_int), ("sweep_form", C.c_int)]
+                ("cycle", C.c_int), ("schwarz", C.c_int), ("sweep_form", C.c_int),
+                ("interchange", C.c_int)]
 
 
 class KrylovOpts(C.Structure):
@@ -245,7 +246,7 @@ def setup_hierarchy(cfg, w=None, device=0, stream=None, allocator=None):
 
 def build_fs_as_blocks(h, core=(4, 4), halo=1, nu_pre=2, nu_post=2, omega=0.8, prec="fp64",
                        use_graph=True, iface_mult=1, monolithic=False, cycle="V",
-                       schwarz="additive", sweep_form="auto"):
+                       schwarz="additive", sweep_form="auto", interchange=False):
     o = SmootherOpts()
     for a in range(3):
         o.core[a] = int(core[a]) if a < len(core) else 1
@@ -258,6 +259,7 @@ def build_fs_as_blocks(h, core=(4, 4), halo=1, nu_pre=2, nu_post=2, omega=0.8, p
     o.cycle = CYCLE[cycle] if isinstance(cycle, str) else int(cycle)
     o.schwarz = SCHWARZ[schwarz] if isinstance(schwarz, str) else int(schwarz)
     o.sweep_form = SWEEP_FORM[sweep_form] if isinstance(sweep_form, str) else int(sweep_form)
+    o.interchange = int(bool(interchange))
     _check(h, lib().build_fs_as_blocks(h, C.byref(o)))
 
 
@@ -478,7 +480,8 @@ class Hierarchy:
                     iface_mult=self.cfg.get("iface_mult", 1),
                     monolithic=self.cfg.get("monolithic", False),
                     cycle=self.cfg.get("cycle", "V"),
-                    schwarz=self.cfg.get("schwarz", "additive"), sweep_form="auto")
+                    schwarz=self.cfg.get("schwarz", "additive"), sweep_form="auto",
+                    interchange=bool(self.cfg.get("interchange", False)))
         opts.update(kw)
         if "core" in kw:
             opts["core"] = tuple(kw["core"])
