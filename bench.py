@@ -284,6 +284,45 @@ def c3_legs(args, dev):
     return out
 
 
+def time_loop_leg(args, dev):
+    """The time-periodic outer loop (Sections 2.2 and 4): backward-Euler
+    steps of the pulsatile problem (inflow factor 1 + 0.75 sin 2 pi t, dt =
+    1/32: 32 steps a period) from rest on the differentiation workload's
+    channel, each time step by Picard steps (re-assembly about the latest
+    velocity, block refactorization, FGMRES with FP32 inverses) until the
+    iterate changes by less than 1e-6.  Section 4's N, rho and s^max and the
+    split of the wall time.  Returned as the `time_loop` object."""
+    import torch
+    from paper_1909_13201_amd import fsgmg, inputs
+    cfg = inputs.config("c5")
+    n2, dim = inputs.n_finest_nodes(cfg), cfg["dim"]
+    f = inputs.body_force(cfg)
+    H = fsgmg.Hierarchy(cfg, np.zeros((n2, dim)), device=0)
+    try:
+        H.build_fs_as_blocks(prec="fp32")
+        x = torch.zeros(H.N, dtype=torch.float64, device=dev)
+        fd = torch.tensor(f.ravel(), dtype=torch.float64, device=dev)
+        res = H.period_solve(fd, x, steps=args.period_steps, picard_max=4, picard_tol=1e-6,
+                             rtol=1e-10)
+        out = dict(workload="2D channel of c2 at 4 levels (64x64 finest Q2/Q1), E=1e4, nu=0.45, "
+                            "mu=3.5e-3, backward-Euler dt=1/32 from rest, pulsatile inflow, Picard "
+                            "re-linearization of convection and SUPG",
+                   unknowns=H.N, levels=H.L, dt=cfg["dt"], steps=res["steps"], picard_max=4,
+                   picard_tol=1e-6, inflow_amp=0.75, converged=res["converged"],
+                   N=round(res["N"], 3), rho=round(res["rho"], 4), s_max=round(res["s_max"], 3),
+                   solves=res["solves"], max_iters=res["max_iters"],
+                   steps_per_s=round(res["steps"] / (1e-3 * res["t_total_ms"]), 3),
+                   t_total_s=round(1e-3 * res["t_total_ms"], 3),
+                   t_assemble_s=round(1e-3 * res["t_assemble_ms"], 3),
+                   t_factor_s=round(1e-3 * res["t_factor_ms"], 3),
+                   t_solve_s=round(1e-3 * res["t_solve_ms"], 3),
+                   iters_per_step=[[int(v) for v in row if v >= 0] for row in res["iters"]])
+    finally:
+        H.close()
+        torch.cuda.empty_cache()
+    return out
+
+
 def measured_traffic():
     """HBM bytes per launch of the finest-level smoother from the committed
     rocprofv3 counter summary, or None when kernels.hip has changed since the
@@ -514,6 +553,9 @@ def main():
     ap.add_argument("--no-bf16", action="store_true", help="skip the BF16-stored block inverses")
     ap.add_argument("--no-c3", action="store_true",
                     help="skip the aneurysm-like c3 legs that the default c2 run adds")
+    ap.add_argument("--period-steps", type=int, default=32,
+                    help="time steps of the time-loop leg (32 = one period)")
+    ap.add_argument("--no-time-loop", action="store_true", help="skip the time-loop leg")
     ap.add_argument("--cycle", default="V", choices=["V", "W", "F"], help="multigrid cycle")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run three plain 256 MiB device copies first (counter calibration)")
@@ -799,6 +841,8 @@ def main():
         H.close()
         torch.cuda.empty_cache()
         out["c3"] = c3_legs(args, dev)
+    if cfg["name"] == "c2" and not args.levels and not args.no_time_loop:
+        out["time_loop"] = time_loop_leg(args, dev)
     if not args.no_cpu_baseline and (cfg["name"] != "c4" or cfg["n_levels"] <= 2):
         out["cpu_baseline"] = cpu_baseline(cfg, w, f)
     print(json.dumps(out), flush=True)

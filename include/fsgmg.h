@@ -345,6 +345,75 @@ fsgmg_status param_grad_noalloc(fsgmg_h h, const double* lam, const double* x, d
  * matrix turned out singular. */
 fsgmg_status update_params(fsgmg_h h, double E, double mu);
 
+/* Picard step of the nonlinear loop (Section 2.2: the paper linearizes each
+ * time step by Newton's method; here the convection and SUPG terms are
+ * re-linearized about the latest velocity): re-assemble every level
+ * operator, the Dirichlet lift, the load operator and the time operator
+ * about the advecting velocity w = the velocity part of x (device, finest
+ * level vector; w at the finest Q2 nodes, injected at the coarse levels'
+ * nodes), with the current (E, mu).  Host assembly (one thread per level)
+ * and upload; the operators' patterns do not change.  Invalidates the
+ * blocks (call build_fs_as_blocks again) and rebuilds the coarse inverse as
+ * update_params does.  EINVAL for a hierarchy set up without an advecting
+ * velocity (physics.w = NULL) or a velocity with NaN / Inf. */
+fsgmg_status update_advection(fsgmg_h h, const double* x);
+
+/* b = F (L f) + g lift + F T x_prev: the right-hand side of one backward-
+ * Euler step (the time discretization of Section 2.2) of the linearized
+ * system, for the nodal body force f (device, finest N2 x dim), the
+ * Dirichlet data scaled by g (every nonzero prescribed value is inflow, so
+ * g is the pulsatile inflow factor) and the previous state x_prev (device,
+ * finest level).  T holds the operator's terms that carry 1/dt (inertia,
+ * the kinematic coupling of the solid, the SUPG time term) on the free
+ * rows; F zeroes Dirichlet rows, which receive g times their data.  b must
+ * not alias x_prev or f.  EINVAL for a steady hierarchy (dt <= 0 or inf).
+ * Asynchronous. */
+fsgmg_status time_rhs(fsgmg_h h, const double* f_nodal, double g, const double* x_prev,
+                      double* b);
+
+/* One run of the time-periodic outer loop of Sections 2.2 and 4: `steps`
+ * backward-Euler steps t_i = t0 + i dt (dt of the hierarchy) with the
+ * pulsatile inflow factor g(t) = 1 + inflow_amp sin(2 pi t) (the 2D
+ * aneurysm inflow of Section 4.1 has amplitude 0.75), each time step solved
+ * by up to picard_max Picard steps: update_advection about the latest
+ * iterate (the previous state for the first), build_fs_as_blocks with the
+ * handle's current smoother options, time_rhs and gmres_solve (x0 = 0);
+ * a time step ends early once ||x_s - x_{s-1}|| <= picard_tol ||x_s||
+ * (picard_tol = 0: always picard_max steps). */
+typedef struct {
+  int steps;            /* time steps (>= 1)                             */
+  double t0;            /* time of the initial state                     */
+  int picard_max;       /* nonlinear steps per time step (>= 1)          */
+  double picard_tol;    /* relative change that ends a time step (>= 0)  */
+  double inflow_amp;    /* amplitude of the pulsatile inflow factor      */
+} fsgmg_period_opts;
+
+/* Section 4's statistics of the run: s_max the mean number of nonlinear
+ * steps per time step, N the mean GMRES iterations per linear solve, rho
+ * the mean per-iteration residual reduction (r_N / r_0)^(1 / N_i,s) of the
+ * solves (true residuals, r_0 = ||b||); wall times of the host assembly,
+ * the block factorizations, the solves (right-hand side, FGMRES, change
+ * norms) and the whole call. */
+typedef struct {
+  int steps;            /* time steps completed                          */
+  int solves;           /* linear solves                                 */
+  int max_iters;
+  double N, rho, s_max;
+  double t_assemble_ms, t_factor_ms, t_solve_ms, t_total_ms;
+} fsgmg_period_info;
+
+/* x (device, finest level): the state at t0 on entry, at t0 + steps dt on
+ * return.  iters / changes (host, optional, steps x picard_max, row-major;
+ * -1 / NaN where a time step ended early): each linear solve's iterations
+ * and relative change.  Requires a hierarchy set up with a finite dt and an
+ * advecting velocity (EINVAL) whose blocks were built once (ESTATE).
+ * Returns NOT_CONVERGED when a solve misses rtol (x then holds that
+ * solve's iterate, info covers the steps so far); any other error leaves x
+ * as on entry.  Synchronizes. */
+fsgmg_status period_solve(fsgmg_h h, const fsgmg_period_opts* opts,
+                          const fsgmg_krylov_opts* krylov, const double* f_nodal, double* x,
+                          int32_t* iters, double* changes, fsgmg_period_info* info);
+
 /* Test hook that makes FSGMG_ESINGULAR observable with valid data: the next
  * build_fs_as_blocks replaces the gathered matrix of Schwarz block `block`
  * (export_blocks numbering) of level `level` (1 .. L-1) by zeros before
@@ -374,7 +443,8 @@ fsgmg_status dof_map(fsgmg_h h, int level, int64_t* n, int32_t* field, int32_t* 
 /* Host copies of setup data (inspection and tests).  which: 0 reduced level
  * operator A_l, 1 prolongation P_l (level l from l-1, Dirichlet-masked),
  * 2 restriction R_l (level l-1 from l, equation-routed, Dirichlet-masked),
- * 3 load operator L of the finest level (N x dim*N2).  Call with NULL
+ * 3 load operator L of the finest level (N x dim*N2), 4 time operator T of
+ * the finest level (N x N, Dirichlet rows empty; finite dt only).  Call with NULL
  * arrays to get sizes in dims[0..2] = rows, cols, nnz. */
 fsgmg_status export_csr(fsgmg_h h, int level, int which, int64_t dims[3],
                         int64_t* rowptr, int32_t* col, double* val);

@@ -202,13 +202,21 @@ def assemble_level(lv: Level, cfg: dict, w: np.ndarray | None = None,
 
     ``w``: advecting velocity at this level's Q2 nodes (N2, D) or None.
     ``tau``: optional frozen SUPG parameter per (fluid element, Gauss point).
-    Returns dict(A, base, AG, AC, Amu, tau, G, inv_lam)."""
+    Returns dict(A, base, AG, AC, Amu, T, tau, G, inv_lam).  T is the time
+    operator: the sum of the terms that carry 1/dt (a part of ``base``;
+    zero when steady), so that one backward-Euler step solves
+    A x_n = load + T x_{n-1}."""
     D, ref = lv.D, RefElement(lv.D)
     nb, npv = ref.nb, ref.np_
     rho, mu = cfg["rho"], cfg["mu"]
     Gmod, inv_lam = lame_constants(cfg["E"], cfg["nu"])
     inv_dt = 1.0 / cfg.get("dt", np.inf)
     base, AG, AC, Amu = _COO(lv.N), _COO(lv.N), _COO(lv.N), _COO(lv.N)
+    Tt = _COO(lv.N)
+
+    def add_time(rows, cols, vals):
+        base.add(rows, cols, vals)
+        Tt.add(rows, cols, vals)
     comp = np.arange(D)
 
     Xe = lv.X[lv.elem_nodes]
@@ -240,14 +248,14 @@ def assemble_level(lv: Level, cfg: dict, w: np.ndarray | None = None,
             diag[:, idx, idx] = vals
             base.add(dof_u[s], dof_u[s], diag)                           # K_us lumped
             if inv_dt:
-                base.add(dof_u[s], dof_d[s], -inv_dt * diag)             # K_ds
+                add_time(dof_u[s], dof_d[s], -inv_dt * diag)             # K_ds
         else:
             Mc = np.einsum("eab,cf->eacbf", Mq2[s], eyeD).reshape(-1, nb * D, nb * D)
             base.add(dof_u[s], dof_u[s], Mc)
             if inv_dt:
-                base.add(dof_u[s], dof_d[s], -inv_dt * Mc)
+                add_time(dof_u[s], dof_d[s], -inv_dt * Mc)
         if inv_dt:
-            base.add(dof_d[s], dof_u[s], rho * inv_dt *
+            add_time(dof_d[s], dof_u[s], rho * inv_dt *
                      np.einsum("eab,cf->eacbf", Mq2[s], eyeD).reshape(-1, nb * D, nb * D))
 
     # ---------------- fluid elements ----------------
@@ -270,7 +278,7 @@ def assemble_level(lv: Level, cfg: dict, w: np.ndarray | None = None,
         rowA = np.where(np.repeat(ss, D, axis=1), -1, dof_d[f])
         base.add(rowA, dof_d[f], kel[:, None, None] * Kf)                # A_ds, A_df
         if inv_dt:
-            base.add(row_m, dof_u[f], rho * inv_dt *
+            add_time(row_m, dof_u[f], rho * inv_dt *
                      np.einsum("eab,cf->eacbf", Mq2[f], eyeD).reshape(nF, nb * D, nb * D))
         if w is not None and np.any(w != 0):
             we = w[nodes[f]]                                             # (nF, nb, D)
@@ -290,6 +298,10 @@ def assemble_level(lv: Level, cfg: dict, w: np.ndarray | None = None,
                     S1 = S1 + rho * inv_dt * np.einsum("eq,eqa,qb->eab", tw, wg, ref.phi)
                 base.add(row_m, dof_u[f],
                          np.einsum("eab,cf->eacbf", S1, eyeD).reshape(nF, nb * D, nb * D))
+                if inv_dt:                    # the SUPG time term of S1, on its own
+                    St = rho * inv_dt * np.einsum("eq,eqa,qb->eab", tw, wg, ref.phi)
+                    Tt.add(row_m, dof_u[f],
+                           np.einsum("eab,cf->eacbf", St, eyeD).reshape(nF, nb * D, nb * D))
                 lap = np.einsum("eqbii->eqb", H[f])
                 S2 = (np.einsum("eq,eqa,eqb,cf->eacbf", tw, wg, lap, eyeD)
                       + np.einsum("eq,eqa,eqbcf->eacbf", tw, wg, H[f]))
@@ -297,7 +309,7 @@ def assemble_level(lv: Level, cfg: dict, w: np.ndarray | None = None,
                 Sp = np.einsum("eq,eqa,eqmc->eacm", tw, wg, Gp[f]).reshape(nF, nb * D, npv)
                 base.add(row_m, dpf, Sp)
 
-    out = dict(base=base.csr(), AG=AG.csr(), AC=AC.csr(), Amu=Amu.csr(),
+    out = dict(base=base.csr(), AG=AG.csr(), AC=AC.csr(), Amu=Amu.csr(), T=Tt.csr(),
                tau=tau_out, G=Gmod, inv_lam=inv_lam)
     out["A"] = (out["base"] + Gmod * out["AG"] + inv_lam * out["AC"]
                 + mu * out["Amu"]).tocsr()

@@ -214,7 +214,13 @@ struct Triplets {
   std::vector<uint8_t> piece;
   std::vector<double> val;
   void add(int64_t r, int64_t c, int p, double v) {
-    if (v == 0.0 || r < 0) return;
+    if (v == 0.0) return;
+    add_always(r, c, p, v);
+  }
+  // terms that depend on the advecting velocity keep their entries when
+  // they vanish, so the operator's pattern does not depend on w
+  void add_always(int64_t r, int64_t c, int p, double v) {
+    if (r < 0) return;
     row.push_back(r);
     col.push_back((int32_t)c);
     piece.push_back((uint8_t)p);
@@ -293,7 +299,13 @@ void assemble_level(const Level& lv, const Physics& ph, const std::vector<double
   op.mu = ph.mu;
   const bool have_w = w_level != nullptr;
 
-  Triplets T, TL;
+  Triplets T, TL, TT;   // operator pieces, load operator, time operator (finest)
+  // a term that carries 1/dt: into the operator and, on the finest level,
+  // into the time operator as well
+  auto tadd = [&](int64_t r, int64_t c, double v) {
+    T.add(r, c, P_BASE, v);
+    if (finest) TT.add(r, c, 0, v);
+  };
   ElemGeo g;
   static thread_local double Tg[kMaxB][kMaxB][3][3];
   std::vector<double> Ksym(nbD * nbD), Bdiv(np * nbD), M2(nb * nb), M1(np * np);
@@ -374,11 +386,11 @@ void assemble_level(const Level& lv, const Physics& ph, const std::vector<double
             double lump = 0;
             for (int b = 0; b < nb; ++b) lump += M2[a * nb + b];
             T.add(r, r, P_BASE, lump);
-            if (inv_dt != 0.0) T.add(r, dofd[a * D + c], P_BASE, -inv_dt * lump);
+            if (inv_dt != 0.0) tadd(r, dofd[a * D + c], -inv_dt * lump);
           } else {
             for (int b = 0; b < nb; ++b) {
               T.add(r, dofu[b * D + c], P_BASE, M2[a * nb + b]);
-              if (inv_dt != 0.0) T.add(r, dofd[b * D + c], P_BASE, -inv_dt * M2[a * nb + b]);
+              if (inv_dt != 0.0) tadd(r, dofd[b * D + c], -inv_dt * M2[a * nb + b]);
             }
           }
         }
@@ -386,7 +398,7 @@ void assemble_level(const Level& lv, const Physics& ph, const std::vector<double
         for (int a = 0; a < nb; ++a)
           for (int b = 0; b < nb; ++b)
             for (int c = 0; c < D; ++c)
-              T.add(dofd[a * D + c], dofu[b * D + c], P_BASE, rho * inv_dt * M2[a * nb + b]);
+              tadd(dofd[a * D + c], dofu[b * D + c], rho * inv_dt * M2[a * nb + b]);
       continue;
     }
 
@@ -410,18 +422,15 @@ void assemble_level(const Level& lv, const Physics& ph, const std::vector<double
       for (int a = 0; a < nb; ++a)
         for (int b = 0; b < nb; ++b)
           for (int c = 0; c < D; ++c)
-            T.add(rowm[a * D + c], dofu[b * D + c], P_BASE, rho * inv_dt * M2[a * nb + b]);
+            tadd(rowm[a * D + c], dofu[b * D + c], rho * inv_dt * M2[a * nb + b]);
     if (!have_w) continue;
     double wq[kMaxQ][3], wg[kMaxQ][kMaxB];
-    bool nonzero = false;
     for (int q = 0; q < nq; ++q)
       for (int i = 0; i < D; ++i) {
         double s = 0;
         for (int b = 0; b < nb; ++b) s += (*w_level)[nodes[b] * D + i] * R.phi[q][b];
         wq[q][i] = s;
       }
-    for (int b = 0; b < nb && !nonzero; ++b)
-      for (int i = 0; i < D; ++i) nonzero |= (*w_level)[nodes[b] * D + i] != 0.0;
     for (int q = 0; q < nq; ++q)
       for (int a = 0; a < nb; ++a) {
         double s = 0;
@@ -433,9 +442,9 @@ void assemble_level(const Level& lv, const Physics& ph, const std::vector<double
       for (int b = 0; b < nb; ++b) {
         double s = 0;
         for (int q = 0; q < nq; ++q) s += g.dV[q] * R.phi[q][a] * wg[q][b];
-        for (int c = 0; c < D; ++c) T.add(rowm[a * D + c], dofu[b * D + c], P_BASE, rho * s);
+        for (int c = 0; c < D; ++c) T.add_always(rowm[a * D + c], dofu[b * D + c], P_BASE, rho * s);
       }
-    if (!ph.supg || !nonzero) continue;
+    if (!ph.supg) continue;
     // lambda_k from the element bubble
     const int bb = R.bubble;
     double Mb[3][3] = {}, Nb = 0;
@@ -467,7 +476,12 @@ void assemble_level(const Level& lv, const Physics& ph, const std::vector<double
       for (int b = 0; b < nb; ++b) {
         double s1 = 0;
         for (int q = 0; q < nq; ++q) s1 += tw[q] * wg[q][a] * (rho * wg[q][b] + rho * inv_dt * R.phi[q][b]);
-        for (int c = 0; c < D; ++c) T.add(rowm[a * D + c], dofu[b * D + c], P_BASE, s1);
+        for (int c = 0; c < D; ++c) T.add_always(rowm[a * D + c], dofu[b * D + c], P_BASE, s1);
+        if (finest && inv_dt != 0.0) {   // the SUPG time term of s1, on its own
+          double st = 0;
+          for (int q = 0; q < nq; ++q) st += tw[q] * wg[q][a] * rho * inv_dt * R.phi[q][b];
+          for (int c = 0; c < D; ++c) TT.add(rowm[a * D + c], dofu[b * D + c], 0, st);
+        }
         double sl = 0;
         for (int q = 0; q < nq; ++q) sl += rho * rho * tw[q] * wg[q][a] * R.phi[q][b];
         if (finest)
@@ -484,14 +498,14 @@ void assemble_level(const Level& lv, const Physics& ph, const std::vector<double
                 for (int i = 0; i < D; ++i) lap += g.H[q][b][i][i];
               s += tw[q] * wg[q][a] * (lap + g.H[q][b][c][f]);
             }
-            T.add(rowm[a * D + c], dofu[b * D + f], P_MU, -s);
+            T.add_always(rowm[a * D + c], dofu[b * D + f], P_MU, -s);
           }
     for (int a = 0; a < nb; ++a)
       for (int c = 0; c < D; ++c)
         for (int m = 0; m < np; ++m) {
           double s = 0;
           for (int q = 0; q < nq; ++q) s += tw[q] * wg[q][a] * g.Gp[q][m][c];
-          T.add(rowm[a * D + c], dpf[m], P_BASE, s);
+          T.add_always(rowm[a * D + c], dpf[m], P_BASE, s);
         }
   }
 
@@ -556,6 +570,23 @@ void assemble_level(const Level& lv, const Physics& ph, const std::vector<double
           op.load.val.push_back(lp[0][k]);
         }
       op.load.rowptr[i + 1] = (int64_t)op.load.col.size();
+    }
+    // time operator with Dirichlet rows removed (every column kept: the
+    // previous state carries the previous Dirichlet data)
+    CsrHost Tc;
+    std::vector<double> tp[4];
+    to_csr(TT, lv.N, lv.N, 1, Tc, tp);
+    op.time.nrows = op.time.ncols = lv.N;
+    op.time.rowptr.assign(lv.N + 1, 0);
+    op.time.col.clear();
+    op.time.val.clear();
+    for (int64_t i = 0; i < lv.N; ++i) {
+      if (!lv.dir[i])
+        for (int64_t k = Tc.rowptr[i]; k < Tc.rowptr[i + 1]; ++k) {
+          op.time.col.push_back(Tc.col[k]);
+          op.time.val.push_back(tp[0][k]);
+        }
+      op.time.rowptr[i + 1] = (int64_t)op.time.col.size();
     }
     op.full = std::move(full);
     for (int p = 0; p < 4; ++p) op.full_piece[p] = std::move(fp[p]);

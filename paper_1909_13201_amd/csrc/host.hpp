@@ -63,6 +63,7 @@ struct LevelOperator {
   std::vector<double> full_piece[4];
   std::vector<double> lift_piece[4];  // finest: lift = sum coef * lift_piece
   CsrHost load;                     // finest: N x D*N2 load operator
+  CsrHost time;                     // finest: the terms carrying 1/dt, Dirichlet rows removed
   double G = 0, invlam = 0, mu = 0;
 };
 

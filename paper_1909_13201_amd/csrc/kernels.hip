@@ -19,6 +19,7 @@
 #include <hip/hip_bf16.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <cstdint>
 
 #include "kernels.hpp"
@@ -744,22 +745,33 @@ __global__ __launch_bounds__(kThreads) void k_gather_blocks(const int32_t* __res
   }
 }
 
-// Blocked in-place Gauss-Jordan inversion with partial pivoting, one
-// workgroup (four wavefronts) per padded np x np FP64 block.
+// Blocked in-place Gauss-Jordan inversion with partial pivoting of the
+// padded np x np blocks of one size bucket, in outer panels of NO = 64
+// columns; each outer panel takes three launches:
 //
-// Columns are processed in panels of NB.  For a panel the workgroup loads
-// the np x NB column strip into LDS and runs the scalar Gauss-Jordan steps
-// on it (pivot = largest magnitude in the column at or below the diagonal,
-// smallest row on ties; the row interchange is applied to the whole row in
-// global memory).  Afterwards the strip holds T = [-A_iK A_KK^-1 ; A_KK^-1]
-// (K = the panel's pivot rows), and every other column j of the matrix is
-// updated in one rank-NB step
-//     A[:, j] += (T - E_K) A[K, j]
-// which is a dense contraction: 16 x 16 FP64 output tiles, one wavefront per
-// column tile, v_mfma_f64_16x16x4f64 over the NB panel columns.  The
-// interchanges are undone by a column permutation sigma (inverse[:, q] =
+//  * k_invert_panel, one workgroup per block: the panel's columns are
+//    factored in strips of NB = 16 held in LDS (pivot = largest magnitude in
+//    the column at or below the diagonal, smallest row on ties; the row
+//    interchange is applied to the whole row in global memory).  After a
+//    strip its columns hold T = [-A_iK A_KK^-1 ; A_KK^-1] (K = the strip's
+//    pivot rows) and the panel's other column tiles take the rank-16 step
+//        A[:, j] += (T - E_K) A[K, j]
+//    on the matrix cores (one wavefront per 16-column tile).
+//  * k_invert_trailing, many workgroups per block: every column outside the
+//    panel takes the panel's rank-64 step A[:, j] += (T - E_K) A[K, j], T now
+//    the panel's final columns (the panel's row interchanges never involve
+//    an earlier pivot row, so they commute with the earlier eliminations).
+//    A workgroup computes one 64 x 64 output tile of one block from its T
+//    rows and the block's pivot rows staged in LDS.  The pivot rows K are
+//    the B operand of every tile in their column, so the row group holding
+//    them is rewritten by a second launch (A[K, j] <- T_KK A[K, j]) after
+//    all others have read them.
+//
+// The interchanges are undone by a column permutation sigma (inverse[:, q] =
 // result[:, sigma[q]]) that the owned-row extraction applies, instead of
-// column swaps over the whole matrix.
+// column swaps over the whole matrix; during the factorization sigma holds
+// the pivot row of each column, and the panel launch that finishes a block
+// turns the pivots into the permutation.
 using f64x4 = __attribute__((__vector_size__(4 * sizeof(double)))) double;
 // Matrix-core tile: 16 x 16 output, 4 inner products per instruction.
 // Operand layout of the 16x16x4 instructions: A[i][k] in lane i + 16 k,
@@ -786,63 +798,96 @@ struct MfmaTile<double> {
   __device__ static int row(int lg, int r) { return lg + 4 * r; }
 };
 
-constexpr int kPanel = 16;      // LDS strip width
-constexpr int kInvThreads = 256;   // workgroup of the block inversion (measured best of 256 / 512 / 1024)
-constexpr int kOuterPanel = 64; // columns per pass over the block
+// the values of one 16-byte load, stored one by one (unaligned LDS rows)
+__device__ inline void put_vec(float* d, const float4& v) {
+  d[0] = v.x;
+  d[1] = v.y;
+  d[2] = v.z;
+  d[3] = v.w;
+}
+__device__ inline void put_vec(double* d, const double2& v) {
+  d[0] = v.x;
+  d[1] = v.y;
+}
+
+constexpr int kPanel = 16;        // LDS strip width
+constexpr int kInvThreads = 256;  // workgroup of the panel factorization
+constexpr int kOuterPanel = 64;   // columns per outer panel
+constexpr int kTrailThreads = 256;   // workgroup of the trailing update (four row tiles)
 
 template <typename TF, int NB, int NO>
-__global__ __launch_bounds__(kInvThreads) void k_invert_blocked(
+__global__ __launch_bounds__(kInvThreads, sizeof(TF) == 4 ? 4 : 2) void k_invert_panel(
     const int32_t* __restrict__ jlist, const int64_t* __restrict__ dof_ptr,
     const int64_t* __restrict__ doff, const int64_t* __restrict__ soff, TF* __restrict__ dense,
-    int32_t* __restrict__ sigma_all, int32_t* __restrict__ status) {
+    int32_t* __restrict__ sigma_all, int32_t* __restrict__ status, int K0) {
   using MT = MfmaTile<TF>;
   using acc_t = typename MT::acc_t;
   static_assert(NB == 16 && NO % NB == 0, "strip of one tile, outer panel of whole strips");
-  constexpr int LDT = NB + 1;   // LDS row stride (doubles) of the strip
+  constexpr int LDT = NB + 1;   // LDS row stride of the strip
   constexpr int NW = kInvThreads / 64;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int64_t j = jlist[blockIdx.x];
   const int n = (int)(dof_ptr[j + 1] - dof_ptr[j]);
   const int np = pad16(n);
+  if (K0 >= np) return;
+  if (status[j]) return;   // stopped at a zero pivot in an earlier panel
   TF* a = dense + doff[blockIdx.x];
+  int32_t* sg = sigma_all + soff[blockIdx.x];
   TF* T = reinterpret_cast<TF*>(smem_raw);            // np x LDT
-  TF* rowc = T + (size_t)np * LDT;                    // NB
-  TF* wval = rowc + NB;                               // NW
+  TF* Bk = T + (size_t)np * LDT;                      // (NO / NB - 1) x 16 x 16
+  TF* wval = Bk + (NO / NB - 1) * 256;                // NW
   int* widx = reinterpret_cast<int*>(wval + NW);      // NW
-  int* piv = widx + NW;                               // np
-  int* sig = piv + np;                                // np
-  int* swl = sig + np;                                // 2 NB: rows receiving
+  int* piv = widx + NW;                               // NB: the strip's pivots
+  int* swl = piv + NB;                                // 2 NB: rows receiving
   int* swv = swl + 2 * NB;                            // 2 NB: their source rows
   int* swn = swv + 2 * NB;                            // 1
+  int* sig = swn + 1;                                 // np (last panel only)
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int lr = lane & 15, lg = lane >> 4;
   const int ntile = np / 16;
-  // identity permutation first: a block that stops at a zero pivot leaves
-  // column indices the extraction can still use (the host then reports the
-  // singular block); each thread later overwrites the same entries
-  for (int c = tid; c < np; c += kInvThreads) sigma_all[soff[blockIdx.x] + c] = c;
-
-  for (int K0 = 0; K0 < np; K0 += NO) {
+  // first panel: identity permutation, so that a block that stops at a zero
+  // pivot leaves in-range column indices for the extraction (the host then
+  // reports the singular block)
+  if (K0 == 0) {
+    for (int c = tid; c < np; c += kInvThreads) sg[c] = c;
+    __syncthreads();
+  }
   const int nko = min(NO, np - K0);   // a multiple of 16
   const int u0 = K0 / 16, u1 = u0 + nko / 16;   // tiles of the outer panel
+  using vec_t = typename std::conditional<sizeof(TF) == 8, double2, float4>::type;
+  constexpr int VW = 16 / sizeof(TF);   // values per 16-byte load
+  constexpr int VPR = NB / VW;          // 16-byte loads per strip row
+  constexpr int UL = 2;                 // loads in flight per thread
   for (int k0 = K0; k0 < K0 + nko; k0 += NB) {
-    const int nbk = NB;
-    for (int e = tid; e < np * nbk; e += kInvThreads) {
-      const int r = e / nbk, q = e - r * nbk;
-      T[r * LDT + q] = a[(int64_t)r * np + k0 + q];
+    for (int e0 = tid; e0 < np * VPR; e0 += kInvThreads * UL) {
+      vec_t v[UL];
+#pragma unroll
+      for (int u = 0; u < UL; ++u) {
+        const int e = e0 + u * kInvThreads;
+        if (e < np * VPR)
+          v[u] = *reinterpret_cast<const vec_t*>(a + (int64_t)(e / VPR) * np + k0 +
+                                                 (e % VPR) * VW);
+      }
+#pragma unroll
+      for (int u = 0; u < UL; ++u) {
+        const int e = e0 + u * kInvThreads;
+        if (e < np * VPR) put_vec(T + (e / VPR) * LDT + (e % VPR) * VW, v[u]);
+      }
     }
     __syncthreads();
-    for (int kk = 0; kk < nbk; ++kk) {
-      const int c = k0 + kk;
-      TF best = TF(-1);
-      int bi = np;
-      for (int r = c + tid; r < np; r += kInvThreads) {
-        const TF v = fabs(T[r * LDT + kk]);
-        if (v > best) {
-          best = v;
-          bi = r;
-        }
+    // pivot candidates of the strip's first column; every later column's
+    // candidates are taken by the elimination of the step before it
+    TF best = TF(-1);
+    int bi = np;
+    for (int r = k0 + tid; r < np; r += kInvThreads) {
+      const TF v = fabs(T[r * LDT]);
+      if (v > best) {
+        best = v;
+        bi = r;
       }
+    }
+    for (int kk = 0; kk < NB; ++kk) {
+      const int c = k0 + kk;
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) {
         const TF v2 = __shfl_xor(best, off, 64);
@@ -870,7 +915,10 @@ __global__ __launch_bounds__(kInvThreads) void k_invert_blocked(
         return;
       }
       const int p = bi;
-      if (tid == 0) piv[c] = p;
+      if (tid == 0) {
+        piv[kk] = p;
+        sg[c] = p;
+      }
       // every thread takes the pivot row and row c into registers, then the
       // interchange and the elimination are one pass: position c receives
       // the scaled pivot row, position p the eliminated old row c, every
@@ -882,33 +930,62 @@ __global__ __launch_bounds__(kInvThreads) void k_invert_blocked(
         crow[q] = T[c * LDT + q];
       }
       __syncthreads();
-      const TF d = TF(1) / prow[kk];
+      // entries kk of the two rows, selected without indexing the register
+      // arrays at a run-time position (which would place them in scratch)
+      TF pk = TF(0), ck = TF(0);
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        if (q == kk) {
+          pk = prow[q];
+          ck = crow[q];
+        }
+      }
+      const TF d = TF(1) / pk;
       TF rc[NB];
 #pragma unroll
       for (int q = 0; q < NB; ++q) rc[q] = (q == kk) ? d : prow[q] * d;
+      // eliminate, and take this thread's pivot candidate for column kk + 1
+      // among the rows below c (the wave reduction at the top of the next
+      // step is the barrier after these writes)
+      best = TF(-1);
+      bi = np;
+      const int kn = kk + 1 < NB ? kk + 1 : kk;
       for (int r = tid; r < np; r += kInvThreads) {
         TF* Tr = T + r * LDT;
+        TF vn;
         if (r == c) {
 #pragma unroll
           for (int q = 0; q < NB; ++q) Tr[q] = rc[q];
-        } else if (r == p) {
-          const TF t = crow[kk];
+          vn = TF(0);
 #pragma unroll
-          for (int q = 0; q < NB; ++q) Tr[q] = (q == kk ? TF(0) : crow[q]) - t * rc[q];
+          for (int q = 0; q < NB; ++q)
+            if (q == kn) vn = rc[q];
         } else {
-          const TF t = Tr[kk];
+          // row p receives the eliminated old row c; any other row is
+          // eliminated in place
+          const bool isp = r == p;
+          const TF t = isp ? ck : Tr[kk];
+          vn = TF(0);
 #pragma unroll
-          for (int q = 0; q < NB; ++q) Tr[q] = (q == kk ? TF(0) : Tr[q]) - t * rc[q];
+          for (int q = 0; q < NB; ++q) {
+            const TF v = (q == kk ? TF(0) : (isp ? crow[q] : Tr[q])) - t * rc[q];
+            Tr[q] = v;
+            if (q == kn) vn = v;
+          }
+        }
+        if (r > c && fabs(vn) > best) {
+          best = fabs(vn);
+          bi = r;
         }
       }
-      __syncthreads();
     }
+    __syncthreads();
     // The strip's interchanges, applied to the rest of the block at once:
     // their composition moves at most 2 NB rows; new row L[x] = old row V[x].
     if (tid == 0) {
       int ns = 0;
-      for (int kk = 0; kk < nbk; ++kk) {
-        const int c = k0 + kk, p = piv[c];
+      for (int kk = 0; kk < NB; ++kk) {
+        const int c = k0 + kk, p = piv[kk];
         if (p == c) continue;
         int ic = -1, ip = -1;
         for (int x = 0; x < ns; ++x) {
@@ -934,8 +1011,8 @@ __global__ __launch_bounds__(kInvThreads) void k_invert_blocked(
     __syncthreads();
     {
       const int ns = swn[0];
-      for (int col = tid; col < np - nbk; col += kInvThreads) {
-        const int cc = col < k0 ? col : col + nbk;
+      for (int col = tid; col < np - NB; col += kInvThreads) {
+        const int cc = col < k0 ? col : col + NB;
         TF v[2 * NB];
 #pragma unroll
         for (int x = 0; x < 2 * NB; ++x)
@@ -947,83 +1024,134 @@ __global__ __launch_bounds__(kInvThreads) void k_invert_blocked(
     }
     __syncthreads();
     // the strip's final values, then T - E_K in LDS for the update
-    for (int e = tid; e < np * nbk; e += kInvThreads) {
-      const int r = e / nbk, q = e - r * nbk;
+    for (int e = tid; e < np * NB; e += kInvThreads) {
+      const int r = e / NB, q = e - r * NB;
       const TF v = T[r * LDT + q];
       a[(int64_t)r * np + k0 + q] = v;
       if (r == k0 + q) T[r * LDT + q] = v - TF(1);
     }
     __syncthreads();
-    // rank-16 update of the outer panel's other column tiles (one wavefront
-    // per tile); the columns beyond the outer panel wait for its end
+    // rank-16 update of the outer panel's other column tiles; the columns
+    // beyond the outer panel wait for the trailing launches.  The tasks
+    // (tile J, row tile it) are dealt to the wavefronts in turn.  The pivot
+    // rows' part of every such tile is staged in LDS first: the task holding
+    // rows K rewrites it while other tasks still read it.
     const int ts = k0 / 16;
-    for (int J = u0 + wv; J < u1; J += NW) {
-      if (J == ts) continue;
-      const int c0 = J * 16 + lr;
-      TF bq[NB / 4];
-#pragma unroll
-      for (int q = 0; q < NB / 4; ++q) bq[q] = a[(int64_t)(k0 + 4 * q + lg) * np + c0];
+    const int nJ = u1 - u0 - 1;
+    for (int e = tid; e < nJ * 256; e += kInvThreads) {
+      const int jt = e >> 8, rr = (e >> 4) & 15, cc = e & 15;
+      const int J = u0 + jt + (u0 + jt >= ts ? 1 : 0);
+      Bk[e] = a[(int64_t)(k0 + rr) * np + J * 16 + cc];
+    }
+    __syncthreads();
+    const int ntask = nJ * ntile;
+    for (int t = wv; t < ntask; t += NW) {
+      const int jt = t / ntile, rb = (t - jt * ntile) * 16;
+      const int cl = (u0 + jt + (u0 + jt >= ts ? 1 : 0)) * 16 + lr;
       // accumulator entry r of lane (lr, lg): row MT::row(lg, r) of column lr
-      for (int it = 0; it < ntile; ++it) {
-        acc_t acc;
+      acc_t acc;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) acc[r] = a[(int64_t)(it * 16 + MT::row(lg, r)) * np + c0];
-        const TF* Tt = T + (it * 16 + lr) * LDT + lg;
+      for (int r = 0; r < 4; ++r) acc[r] = a[(int64_t)(rb + MT::row(lg, r)) * np + cl];
+      const TF* Tt = T + (rb + lr) * LDT + lg;
+      const TF* Bt = Bk + jt * 256 + lg * 16 + lr;
 #pragma unroll
-        for (int q = 0; q < NB / 4; ++q) acc = MT::step(Tt[4 * q], bq[q], acc);
+      for (int q = 0; q < NB / 4; ++q) acc = MT::step(Tt[4 * q], Bt[64 * q], acc);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) a[(int64_t)(it * 16 + MT::row(lg, r)) * np + c0] = acc[r];
-      }
+      for (int r = 0; r < 4; ++r) a[(int64_t)(rb + MT::row(lg, r)) * np + cl] = acc[r];
     }
     __syncthreads();
   }
-  // The outer panel now holds T = [-A_iK A_KK^-1 ; A_KK^-1] for its nko pivot
-  // rows K (all its row interchanges were applied to whole rows as they
-  // happened; an interchange never involves an earlier pivot row, so they
-  // commute with the earlier eliminations).  Every column tile outside it
-  // takes A[:, j] += (T - E_K) A[K, j] in one rank-nko pass: the block is
-  // streamed once per NO columns instead of once per strip.
-  for (int J = wv; J < ntile; J += NW) {
-    if (J >= u0 && J < u1) continue;
-    const int c0 = J * 16 + lr;
-    TF bq[NO / 4];
-#pragma unroll
-    for (int q = 0; q < NO / 4; ++q)
-      bq[q] = (4 * q < nko) ? a[(int64_t)(K0 + 4 * q + lg) * np + c0] : TF(0);
-    for (int it = 0; it < ntile; ++it) {
-      const int ra = it * 16 + lr;   // A-operand row of this lane
-      acc_t acc;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) acc[r] = a[(int64_t)(it * 16 + MT::row(lg, r)) * np + c0];
-      const TF* Ta = a + (int64_t)ra * np + K0 + lg;
-#pragma unroll
-      for (int q = 0; q < NO / 4; ++q) {
-        if (4 * q < nko) {
-          const TF t = Ta[4 * q] - (ra == K0 + 4 * q + lg ? TF(1) : TF(0));
-          acc = MT::step(t, bq[q], acc);
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) a[(int64_t)(it * 16 + MT::row(lg, r)) * np + c0] = acc[r];
-    }
-  }
-  __syncthreads();
-  }
-  // column permutation that undoes the row interchanges (applied in
-  // reverse order of the pivot steps)
+  if (K0 + nko < np) return;
+  // last panel: the permutation that undoes the row interchanges (applied in
+  // reverse order of the pivot steps); thread 0 wrote this panel's pivots,
+  // earlier launches the others
   if (tid == 0) {
     for (int c = 0; c < np; ++c) sig[c] = c;
     for (int c = np - 1; c >= 0; --c) {
-      const int p = piv[c];
+      const int p = sg[c];
       const int t = sig[c];
       sig[c] = sig[p];
       sig[p] = t;
     }
   }
   __syncthreads();
-  int32_t* sg = sigma_all + soff[blockIdx.x];
   for (int c = tid; c < np; c += kInvThreads) sg[c] = sig[c];
-  if (tid == 0) status[j] = 0;
+}
+
+// Trailing update of the outer panel [K0, K0 + nko) of every block of the
+// bucket: A[:, j] += (T - E_K) A[K, j] for the columns j outside the panel,
+// T = the panel's columns, K = its pivot rows.  A workgroup owns one 64 x 64
+// output tile (row group rg, column group cg) of one block; each wavefront
+// one 16-row tile of it, T's 16 x 64 slice in registers, the pivot rows'
+// 64 x 64 slice shared in LDS.  kgroup = 0 updates every row group but the
+// panel's own (accumulating onto A); kgroup = 1 the panel's row group, whose
+// new value A[K, j] + (T_KK - I) A[K, j] = T_KK A[K, j] starts from zero.
+// Workgroup id -> (block, tile): the tiles of a block are consecutive ids
+// with a stride of 8, so one XCD (ids are dealt to the 8 XCDs round-robin)
+// takes all tiles of a block and serves their shared T and pivot rows from
+// its own L2.
+template <typename TF>
+__global__ __launch_bounds__(kTrailThreads) void k_invert_trailing(
+    const int32_t* __restrict__ jlist, int64_t nblk, const int64_t* __restrict__ dof_ptr,
+    const int64_t* __restrict__ doff, TF* __restrict__ dense, const int32_t* __restrict__ status,
+    int K0, int ngroups, int kgroup) {
+  using MT = MfmaTile<TF>;
+  using acc_t = typename MT::acc_t;
+  using vec_t = typename std::conditional<sizeof(TF) == 8, double2, float4>::type;
+  constexpr int VW = 16 / sizeof(TF);           // values per 16-byte load
+  constexpr int LDS_STRIDE = 64 + VW;          // row stride of the staged tiles
+  __shared__ __align__(16) TF Ts[64 * LDS_STRIDE];
+  __shared__ __align__(16) TF Bs[64 * LDS_STRIDE];
+  const int ntiles = kgroup ? ngroups : ngroups * ngroups;
+  const int64_t L = blockIdx.x, xcd = L & 7, rest = L >> 3;
+  const int64_t b = (rest / ntiles) * 8 + xcd;
+  const int tile = (int)(rest % ntiles);
+  if (b >= nblk) return;
+  const int64_t j = jlist[b];
+  if (status[j]) return;
+  const int np = pad16((int)(dof_ptr[j + 1] - dof_ptr[j]));
+  if (K0 >= np) return;
+  const int kg = K0 / 64, nko = min(64, np - K0);
+  const int rg = kgroup ? kg : tile / ngroups;
+  const int cg = kgroup ? tile : tile % ngroups;
+  if (cg == kg || (!kgroup && rg == kg)) return;
+  const int r0 = rg * 64, c0 = cg * 64;
+  if (r0 >= np || c0 >= np) return;
+  const int nr = min(64, np - r0), nc = min(64, np - c0);
+  TF* a = dense + doff[b];
+  const int tid = threadIdx.x;
+  // stage T[r0 .. r0 + nr, K0 .. K0 + nko) and A[K0 .. K0 + nko, c0 .. c0 + nc)
+  // (zeros beyond), 16-byte loads along the rows
+  for (int e = tid; e < 64 * (64 / VW); e += kTrailThreads) {
+    const int r = e / (64 / VW), q = (e - r * (64 / VW)) * VW;
+    vec_t t{}, v{};
+    if (r < nr && q < nko) t = *reinterpret_cast<const vec_t*>(a + (int64_t)(r0 + r) * np + K0 + q);
+    if (r < nko && q < nc) v = *reinterpret_cast<const vec_t*>(a + (int64_t)(K0 + r) * np + c0 + q);
+    *reinterpret_cast<vec_t*>(Ts + r * LDS_STRIDE + q) = t;
+    *reinterpret_cast<vec_t*>(Bs + r * LDS_STRIDE + q) = v;
+  }
+  __syncthreads();
+  const int lane = tid & 63, wv = tid >> 6;
+  const int lr = lane & 15, lg = lane >> 4;
+  if (16 * wv >= nr) return;
+  const int nq = nko / 4;
+  TF tq[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) tq[q] = Ts[(16 * wv + lr) * LDS_STRIDE + 4 * q + lg];
+  const int64_t rowb = r0 + 16 * wv;
+  for (int ct = 0; ct < nc / 16; ++ct) {
+    const int col = c0 + 16 * ct + lr;
+    acc_t acc;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      acc[r] = kgroup ? TF(0) : a[(rowb + MT::row(lg, r)) * np + col];
+    const TF* Bc = Bs + lg * LDS_STRIDE + 16 * ct + lr;
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+      if (q < nq) acc = MT::step(tq[q], Bc[4 * q * LDS_STRIDE], acc);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) a[(rowb + MT::row(lg, r)) * np + col] = acc[r];
+  }
 }
 
 template <typename TW>
@@ -1249,6 +1377,22 @@ __global__ __launch_bounds__(kThreads) void k_load_rhs(int64_t n, const int64_t*
   if (r >= n) return;
   double s = lift[r];
   for (int64_t k = rp[r]; k < rp[r + 1]; ++k) s += val[k] * f[col[k]];
+  b[r] = s;
+}
+
+// Right-hand side of one backward-Euler step: the load operator's row and
+// the time operator's row (both with Dirichlet rows removed) plus g times the
+// lift, one row per thread.
+__global__ __launch_bounds__(kThreads) void k_time_rhs(
+    int64_t n, const int64_t* __restrict__ lrp, const int32_t* __restrict__ lcol,
+    const double* __restrict__ lval, const double* __restrict__ f, const double* __restrict__ lift,
+    double g, const int64_t* __restrict__ trp, const int32_t* __restrict__ tcol,
+    const double* __restrict__ tval, const double* __restrict__ xp, double* __restrict__ b) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  double s = g * lift[r];
+  for (int64_t k = lrp[r]; k < lrp[r + 1]; ++k) s += lval[k] * f[lcol[k]];
+  for (int64_t k = trp[r]; k < trp[r + 1]; ++k) s += tval[k] * xp[tcol[k]];
   b[r] = s;
 }
 
@@ -2864,25 +3008,47 @@ void launch_gather_blocks(const int32_t* jlist, int64_t nb, const BlocksView& B,
 
 size_t invert_blocks_lds(int np_max, bool f32) {
   const size_t tf = f32 ? 4 : 8;
-  // strip (np x (NB + 1)), the pivot row's copy (NB), the wave maxima and
-  // their rows, pivots and sigma (np each), the interchange lists
-  return (size_t)np_max * (kPanel + 1) * tf + (size_t)kPanel * tf + (kInvThreads / 64) * (tf + 4) +
-         (size_t)np_max * 8 + (size_t)(4 * kPanel + 1) * 4;
+  // strip (np x (NB + 1)), the pivot rows of the panel's other tiles, the
+  // wave maxima and their rows, the strip's pivots and interchange lists,
+  // sigma (np)
+  return (size_t)np_max * (kPanel + 1) * tf + (size_t)(kOuterPanel / kPanel - 1) * 256 * tf +
+         (kInvThreads / 64) * (tf + 4) +
+         (size_t)(5 * kPanel + 1) * 4 + (size_t)np_max * 4;
+}
+
+template <typename TF>
+static void invert_panels(const int32_t* jlist, int64_t nb, const int64_t* dof_ptr,
+                          const int64_t* dense_off, const int64_t* sigma_off, TF* dense,
+                          int32_t* sigma, int32_t* status, int max_n, hipStream_t s) {
+  const int npmax = (max_n + 15) & ~15;
+  const size_t sm = invert_blocks_lds(npmax, sizeof(TF) == 4);
+  const int ngroups = (npmax + 63) / 64;
+  const int64_t nb8 = (nb + 7) / 8 * 8;
+  for (int K0 = 0; K0 < npmax; K0 += kOuterPanel) {
+    hipLaunchKernelGGL((k_invert_panel<TF, kPanel, kOuterPanel>), dim3((unsigned)nb),
+                       dim3(kInvThreads), sm, s, jlist, dof_ptr, dense_off, sigma_off, dense,
+                       sigma, status, K0);
+    if (ngroups > 1) {
+      hipLaunchKernelGGL((k_invert_trailing<TF>), dim3((unsigned)(nb8 * ngroups * ngroups)),
+                         dim3(kTrailThreads), 0, s, jlist, nb, dof_ptr, dense_off, dense, status,
+                         K0, ngroups, 0);
+      hipLaunchKernelGGL((k_invert_trailing<TF>), dim3((unsigned)(nb8 * ngroups)),
+                         dim3(kTrailThreads), 0, s, jlist, nb, dof_ptr, dense_off, dense, status,
+                         K0, ngroups, 1);
+    }
+  }
 }
 
 void launch_invert_blocks(const int32_t* jlist, int64_t nb, const int64_t* dof_ptr,
                           const int64_t* dense_off, const int64_t* sigma_off, void* dense,
                           bool f32, int32_t* sigma, int32_t* status, int max_n, hipStream_t s) {
   if (nb <= 0) return;
-  const size_t sm = invert_blocks_lds((max_n + 15) & ~15, f32);
   if (f32)
-    hipLaunchKernelGGL((k_invert_blocked<float, kPanel, kOuterPanel>), dim3((unsigned)nb),
-                       dim3(kInvThreads), sm, s, jlist, dof_ptr, dense_off, sigma_off,
-                       (float*)dense, sigma, status);
+    invert_panels<float>(jlist, nb, dof_ptr, dense_off, sigma_off, (float*)dense, sigma, status,
+                         max_n, s);
   else
-    hipLaunchKernelGGL((k_invert_blocked<double, kPanel, kOuterPanel>), dim3((unsigned)nb),
-                       dim3(kInvThreads), sm, s, jlist, dof_ptr, dense_off, sigma_off,
-                       (double*)dense, sigma, status);
+    invert_panels<double>(jlist, nb, dof_ptr, dense_off, sigma_off, (double*)dense, sigma, status,
+                          max_n, s);
 }
 
 template <typename TF>
@@ -3215,6 +3381,13 @@ void launch_load_rhs(int64_t n, const int64_t* rowptr, const int32_t* col, const
                      const double* f, const double* lift, double* b, hipStream_t s) {
   hipLaunchKernelGGL(k_load_rhs, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, s, n, rowptr, col,
                      val, f, lift, b);
+}
+void launch_time_rhs(int64_t n, const int64_t* lrp, const int32_t* lcol, const double* lval,
+                     const double* f, const double* lift, double g, const int64_t* trp,
+                     const int32_t* tcol, const double* tval, const double* x_prev, double* b,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_time_rhs, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, s, n, lrp, lcol,
+                     lval, f, lift, g, trp, tcol, tval, x_prev, b);
 }
 
 // The allocation-free entry points' scratch: its name is a host-side

@@ -315,6 +315,11 @@ void launch_cast(const TA* a, TB* b, int64_t n, hipStream_t s);
 void launch_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t s);
 void launch_load_rhs(int64_t n, const int64_t* rowptr, const int32_t* col, const double* val,
                      const double* f, const double* lift, double* b, hipStream_t s);
+// b = L f + g lift + T x_prev (load operator L and time operator T in CSR)
+void launch_time_rhs(int64_t n, const int64_t* lrp, const int32_t* lcol, const double* lval,
+                     const double* f, const double* lift, double g, const int64_t* trp,
+                     const int32_t* tcol, const double* tval, const double* x_prev, double* b,
+                     hipStream_t s);
 // out[0] = sum over unmasked i of a_i b_i
 void launch_masked_dot(const double* a, const uint8_t* mask, const double* b, int64_t n,
                        double* part, double* out, hipStream_t s);

@@ -16,6 +16,7 @@
 #include <mutex>
 #include <stdexcept>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "fsgmg.h"
@@ -347,6 +348,13 @@ struct fsgmg_hierarchy {
   int32_t* loadT_col = nullptr;
   double* loadT_val = nullptr;
   double* lift = nullptr;
+  // finest-level time operator: the terms of the operator that carry 1/dt,
+  // Dirichlet rows removed (set up with a finite dt only)
+  int64_t* time_rp = nullptr;
+  int32_t* time_col = nullptr;
+  double* time_val = nullptr;
+  // period_solve: previous state, current and new iterate, right-hand side
+  double* per_buf = nullptr;
   double* lift_piece[4] = {nullptr, nullptr, nullptr, nullptr};
   int64_t* full_rp = nullptr;
   int32_t* full_col = nullptr;
@@ -832,6 +840,32 @@ void ensure_bd(fsgmg_hierarchy& h) {
   h.bd_dirty = false;
 }
 
+// The finest level's load operator (and its transpose) and time operator,
+// whose patterns follow the advecting velocity (SUPG terms vanish where it
+// does): replaced as a whole on every upload.
+void upload_load_and_time(fsgmg_hierarchy& h) {
+  const LevelOperator& op = h.ops[h.L - 1];
+  for (void* p : {(void*)h.load_rp, (void*)h.load_col, (void*)h.load_val, (void*)h.loadT_rp,
+                  (void*)h.loadT_col, (void*)h.loadT_val, (void*)h.time_rp, (void*)h.time_col,
+                  (void*)h.time_val})
+    h.dfree(p);
+  h.load_rp = h.upload(op.load.rowptr);
+  h.load_col = h.upload(op.load.col);
+  h.load_val = h.upload(op.load.val);
+  CsrHost LT = csr_transpose(op.load);
+  h.loadT_rp = h.upload(LT.rowptr);
+  h.loadT_col = h.upload(LT.col);
+  h.loadT_val = h.upload(LT.val);
+  h.time_rp = nullptr;
+  h.time_col = nullptr;
+  h.time_val = nullptr;
+  if (h.phys.inv_dt != 0.0) {
+    h.time_rp = h.upload(op.time.rowptr);
+    h.time_col = h.upload(op.time.col);
+    h.time_val = h.upload(op.time.val);
+  }
+}
+
 void upload_all(fsgmg_hierarchy& h) {
   h.dl.resize(h.L);
   h.tune.assign(h.L, {});
@@ -857,15 +891,7 @@ void upload_all(fsgmg_hierarchy& h) {
   for (int l = 1; l < h.L; ++l) upload_transfer(h, l);
   const Level& F = h.levels[h.L - 1];
   const LevelOperator& op = h.ops[h.L - 1];
-  h.load_rp = h.upload(op.load.rowptr);
-  h.load_col = h.upload(op.load.col);
-  h.load_val = h.upload(op.load.val);
-  {
-    CsrHost LT = csr_transpose(op.load);
-    h.loadT_rp = h.upload(LT.rowptr);
-    h.loadT_col = h.upload(LT.col);
-    h.loadT_val = h.upload(LT.val);
-  }
+  upload_load_and_time(h);
   for (int p = 0; p < 4; ++p) h.lift_piece[p] = h.upload(op.lift_piece[p]);
   std::vector<double> lift(F.N);
   for (int64_t i = 0; i < F.N; ++i)
@@ -2270,6 +2296,44 @@ static fsgmg_status build_fs_as_blocks_impl(fsgmg_h h, const fsgmg_smoother_opts
 
 extern "C" {
 
+// Assemble every level operator about the handle's physics and finest-level
+// advecting velocity (injected at each level's nodes: the meshes are nested
+// and Q2 nodes of a coarse level are nodes of every finer one); the levels
+// are independent and are assembled on one host thread each.
+static void assemble_all(fsgmg_hierarchy& h, std::vector<LevelOperator>& ops) {
+  const Level& Fl = h.levels[h.L - 1];
+  const std::vector<double> cvol = element_volumes(h.levels[0]);
+  ops.clear();
+  ops.resize(h.L);
+  std::vector<std::thread> pool;
+  std::vector<std::exception_ptr> errs(h.L);
+  for (int l = 0; l < h.L; ++l)
+    pool.emplace_back([&, l]() {
+      try {
+        const Level& lv = h.levels[l];
+        std::vector<double> wl;
+        if (!h.w_finest.empty()) {
+          const int step = 1 << (h.L - 1 - l);
+          wl.resize(lv.N2 * h.D);
+          for (int64_t n = 0; n < lv.N2; ++n) {
+            int ix[kMaxDim] = {0, 0, 0};
+            lv.node_ijk(n, ix);
+            int fx[kMaxDim] = {0, 0, 0};
+            for (int a = 0; a < h.D; ++a) fx[a] = ix[a] * step;
+            const int64_t fn = Fl.node_index(fx);
+            for (int c = 0; c < h.D; ++c) wl[n * h.D + c] = h.w_finest[fn * h.D + c];
+          }
+        }
+        assemble_level(lv, h.phys, cvol, wl.empty() ? nullptr : &wl, l == h.L - 1, ops[l]);
+      } catch (...) {
+        errs[l] = std::current_exception();
+      }
+    });
+  for (std::thread& t : pool) t.join();
+  for (const std::exception_ptr& e : errs)
+    if (e) std::rethrow_exception(e);
+}
+
 fsgmg_status setup_hierarchy(const fsgmg_mesh_desc* mesh, const fsgmg_physics* phys,
                              const fsgmg_allocator* alloc, int device, void* stream, fsgmg_h* out) {
   if (!mesh || !phys || !out) return FSGMG_EINVAL;
@@ -2311,25 +2375,7 @@ fsgmg_status setup_hierarchy(const fsgmg_mesh_desc* mesh, const fsgmg_physics* p
                       (phys->dt > 0 && std::isfinite(phys->dt)) ? 1.0 / phys->dt : 0.0,
                       phys->supg, phys->ale_k, phys->k_mass,
                       h->w_finest.empty() ? nullptr : h->w_finest.data(), h->L};
-    std::vector<double> cvol = element_volumes(h->levels[0]);
-    h->ops.resize(h->L);
-    for (int l = 0; l < h->L; ++l) {
-      const Level& lv = h->levels[l];
-      std::vector<double> wl;
-      if (!h->w_finest.empty()) {
-        const int step = 1 << (h->L - 1 - l);
-        wl.resize(lv.N2 * h->D);
-        for (int64_t n = 0; n < lv.N2; ++n) {
-          int ix[kMaxDim] = {0, 0, 0};
-          lv.node_ijk(n, ix);
-          int fx[kMaxDim] = {0, 0, 0};
-          for (int a = 0; a < h->D; ++a) fx[a] = ix[a] * step;
-          const int64_t fn = Fl.node_index(fx);
-          for (int c = 0; c < h->D; ++c) wl[n * h->D + c] = h->w_finest[fn * h->D + c];
-        }
-      }
-      assemble_level(lv, h->phys, cvol, wl.empty() ? nullptr : &wl, l == h->L - 1, h->ops[l]);
-    }
+    assemble_all(*h, h->ops);
     h->tr.resize(h->L);
     for (int l = 1; l < h->L; ++l) build_transfer(h->levels[l], h->levels[l - 1], h->tr[l]);
     h->blocks.resize(h->L);
@@ -2655,6 +2701,187 @@ fsgmg_status update_params(fsgmg_h h, double E, double mu) {
   });
 }
 
+// Values of every level operator, the Dirichlet lift's pieces and the
+// finest level's unreduced pieces from freshly assembled host operators with
+// the patterns already on the device, recombined for the current (E, mu) as
+// update_params does.
+static void upload_operator_values(fsgmg_hierarchy& h) {
+  for (int l = 0; l < h.L; ++l) {
+    DLevel& d = h.dl[l];
+    const LevelOperator& op = h.ops[l];
+    for (int p = 0; p < 4; ++p)
+      HIPCHECK(hipMemcpyAsync(d.piece[p], op.piece[p].data(), op.piece[p].size() * sizeof(double),
+                              hipMemcpyHostToDevice, h.stream));
+    launch_recombine(d.nnz, d.piece[0], d.piece[1], d.piece[2], d.piece[3], op.G, op.invlam, op.mu,
+                     d.val, nullptr, h.stream);
+    launch_scatter(d.nnz, d.val, d.A.map, d.A.vals64, d.A.vals32, h.stream);
+    if (d.AT.ready) launch_scatter(d.nnz, d.val, d.AT.map, d.AT.vals64, d.AT.vals32, h.stream);
+  }
+  const LevelOperator& F = h.ops[h.L - 1];
+  const int64_t NF = h.dl[h.L - 1].N;
+  for (int p = 0; p < 4; ++p) {
+    HIPCHECK(hipMemcpyAsync(h.lift_piece[p], F.lift_piece[p].data(), NF * sizeof(double),
+                            hipMemcpyHostToDevice, h.stream));
+    HIPCHECK(hipMemcpyAsync(h.full_piece[p], F.full_piece[p].data(),
+                            F.full_piece[p].size() * sizeof(double), hipMemcpyHostToDevice,
+                            h.stream));
+  }
+  launch_recombine(NF, h.lift_piece[0], h.lift_piece[1], h.lift_piece[2], h.lift_piece[3], F.G,
+                   F.invlam, F.mu, h.lift, nullptr, h.stream);
+  HIPCHECK(hipGetLastError());
+  HIPCHECK(hipStreamSynchronize(h.stream));
+}
+
+// Re-assemble every level about the advecting velocity w = the velocity
+// part of the finest-level device vector x (the Picard step of the
+// nonlinear loop): operators, lift, load and time operators.  The blocks
+// and the coarse inverse follow as after update_params.
+static void reassemble_about(fsgmg_hierarchy& h, const double* x) {
+  const Level& F = h.levels[h.L - 1];
+  const size_t nw = (size_t)F.N2 * h.D;
+  HIPCHECK(hipMemcpyAsync(h.w_finest.data(), x + F.off_u, nw * sizeof(double),
+                          hipMemcpyDeviceToHost, h.stream));
+  HIPCHECK(hipStreamSynchronize(h.stream));
+  for (double v : h.w_finest)
+    if (!std::isfinite(v)) throw Fail{FSGMG_EINVAL, "the velocity contains NaN or Inf"};
+  std::vector<LevelOperator> ops;
+  assemble_all(h, ops);
+  for (int l = 0; l < h.L; ++l)
+    if (ops[l].A.rowptr != h.ops[l].A.rowptr || ops[l].A.col != h.ops[l].A.col)
+      throw Fail{FSGMG_ESTATE, "operator pattern changed with the advecting velocity"};
+  if (ops[h.L - 1].full.col != h.ops[h.L - 1].full.col)
+    throw Fail{FSGMG_ESTATE, "operator pattern changed with the advecting velocity"};
+  h.ops = std::move(ops);
+  h.host_vals_stale = false;
+  upload_operator_values(h);
+  upload_load_and_time(h);
+  h.factors_valid = false;
+  // the multiplicative colouring reads the operator's values: recolour
+  if (h.sopt.schwarz == FSGMG_SCHWARZ_MULTIPLICATIVE) h.have_blocks = false;
+  if (!h.bd.empty()) h.bd_dirty = true;
+  if (h.dl[0].use_bd) ensure_bd(h);
+  build_coarse_inverse(h, true);
+}
+
+fsgmg_status update_advection(fsgmg_h h, const double* x) {
+  if (!h || !x) return FSGMG_EINVAL;
+  return guarded(h, [&]() -> fsgmg_status {
+    check_device(*h);
+    if (h->w_finest.empty())
+      throw Fail{FSGMG_EINVAL, "the hierarchy was set up without an advecting velocity"};
+    reassemble_about(*h, x);
+    return FSGMG_OK;
+  });
+}
+
+fsgmg_status time_rhs(fsgmg_h h, const double* f, double g, const double* x_prev, double* b) {
+  if (!h || !f || !x_prev || !b || (const void*)b == (const void*)x_prev ||
+      (const void*)b == (const void*)f || !std::isfinite(g))
+    return FSGMG_EINVAL;
+  return guarded(h, [&]() -> fsgmg_status {
+    check_device(*h);
+    if (!h->time_val) throw Fail{FSGMG_EINVAL, "time_rhs needs a hierarchy set up with a finite dt"};
+    launch_time_rhs(h->dl[h->L - 1].N, h->load_rp, h->load_col, h->load_val, f, h->lift, g,
+                    h->time_rp, h->time_col, h->time_val, x_prev, b, h->stream);
+    HIPCHECK(hipGetLastError());
+    return FSGMG_OK;
+  });
+}
+
+fsgmg_status period_solve(fsgmg_h h, const fsgmg_period_opts* po, const fsgmg_krylov_opts* ko,
+                          const double* f, double* x, int32_t* iters, double* changes,
+                          fsgmg_period_info* info) {
+  if (!h || !po || !ko || !f || !x || (const void*)f == (const void*)x) return FSGMG_EINVAL;
+  return guarded(h, [&]() -> fsgmg_status {
+    check_device(*h);
+    if (po->steps < 1 || po->picard_max < 1 || !(po->picard_tol >= 0) ||
+        !std::isfinite(po->picard_tol) || !std::isfinite(po->t0) || !std::isfinite(po->inflow_amp))
+      throw Fail{FSGMG_EINVAL, "period options out of range"};
+    if (!h->time_val) throw Fail{FSGMG_EINVAL, "period_solve needs a hierarchy set up with a finite dt"};
+    if (h->w_finest.empty())
+      throw Fail{FSGMG_EINVAL, "the hierarchy was set up without an advecting velocity"};
+    if (!h->tuned) throw Fail{FSGMG_ESTATE, "build_fs_as_blocks has not been called"};
+    const auto t_start = std::chrono::steady_clock::now();
+    auto ms_since = [](std::chrono::steady_clock::time_point t) {
+      return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t).count();
+    };
+    const int64_t N = h->dl[h->L - 1].N;
+    if (!h->per_buf) h->per_buf = (double*)h->dalloc((size_t)4 * N * sizeof(double));
+    double* xprev = h->per_buf;
+    double* xcur = h->per_buf + N;
+    double* xnew = h->per_buf + 2 * N;
+    double* b = h->per_buf + 3 * N;
+    HIPCHECK(hipMemcpyAsync(xprev, x, N * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+    if (iters)
+      for (int k = 0; k < po->steps * po->picard_max; ++k) iters[k] = -1;
+    if (changes)
+      for (int k = 0; k < po->steps * po->picard_max; ++k) changes[k] = NAN;
+    const fsgmg_smoother_opts so = h->sopt;
+    const double dt = 1.0 / h->phys.inv_dt;
+    const double two_pi = 6.283185307179586;
+    fsgmg_period_info acc{};
+    double sum_iters = 0, sum_rate = 0, t_asm = 0, t_fac = 0, t_sol = 0;
+    fsgmg_status st = FSGMG_OK;
+    for (int i = 1; i <= po->steps && st == FSGMG_OK; ++i) {
+      const double g = 1.0 + po->inflow_amp * std::sin(two_pi * (po->t0 + i * dt));
+      HIPCHECK(hipMemcpyAsync(xcur, xprev, N * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+      int taken = 0;
+      for (int s = 0; s < po->picard_max; ++s) {
+        auto t0 = std::chrono::steady_clock::now();
+        reassemble_about(*h, xcur);
+        t_asm += ms_since(t0);
+        t0 = std::chrono::steady_clock::now();
+        const fsgmg_status bs = build_fs_as_blocks_impl(h, &so);
+        if (bs != FSGMG_OK) return bs;
+        HIPCHECK(hipStreamSynchronize(h->stream));
+        t_fac += ms_since(t0);
+        t0 = std::chrono::steady_clock::now();
+        launch_time_rhs(N, h->load_rp, h->load_col, h->load_val, f, h->lift, g, h->time_rp,
+                        h->time_col, h->time_val, xprev, b, h->stream);
+        HIPCHECK(hipGetLastError());
+        fsgmg_solve_info si{};
+        const fsgmg_status fs = fgmres(*h, b, xnew, *ko, &si, false);
+        // relative change of the iterate: ||x_new - x_cur|| / ||x_new||
+        launch_add_scaled<double>(N, -1.0, xnew, xcur, false, h->stream);
+        const double dn = device_norm(*h, xcur, N);
+        const double nn = device_norm(*h, xnew, N);
+        t_sol += ms_since(t0);
+        std::swap(xcur, xnew);
+        const double change = nn > 0 ? dn / nn : dn;
+        const int k = (i - 1) * po->picard_max + s;
+        if (iters) iters[k] = si.iters;
+        if (changes) changes[k] = change;
+        ++taken;
+        ++acc.solves;
+        sum_iters += si.iters;
+        acc.max_iters = std::max(acc.max_iters, si.iters);
+        sum_rate += si.iters > 0 ? std::pow(si.rel_res_true, 1.0 / si.iters) : 0.0;
+        if (fs != FSGMG_OK) {
+          st = fs;
+          break;
+        }
+        if (po->picard_tol > 0 && change <= po->picard_tol) break;
+      }
+      HIPCHECK(hipMemcpyAsync(xprev, xcur, N * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+      acc.steps = i;
+      acc.s_max += taken;
+    }
+    HIPCHECK(hipMemcpyAsync(x, xprev, N * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    if (info) {
+      *info = acc;
+      info->s_max = acc.steps ? acc.s_max / acc.steps : 0.0;
+      info->N = acc.solves ? sum_iters / acc.solves : 0.0;
+      info->rho = acc.solves ? sum_rate / acc.solves : 0.0;
+      info->t_assemble_ms = t_asm;
+      info->t_factor_ms = t_fac;
+      info->t_solve_ms = t_sol;
+      info->t_total_ms = ms_since(t_start);
+    }
+    return st;
+  });
+}
+
 fsgmg_status debug_zero_block(fsgmg_h h, int level, int64_t block) {
   if (!h) return FSGMG_EINVAL;
   return guarded(h, [&]() -> fsgmg_status {
@@ -2736,6 +2963,10 @@ fsgmg_status export_csr(fsgmg_h h, int level, int which, int64_t dims[3], int64_
     } else if (which == 3) {
       if (level != h->L - 1) throw Fail{FSGMG_EINVAL, "load operator exists on the finest level"};
       M = &h->ops[level].load;
+    } else if (which == 4) {
+      if (level != h->L - 1) throw Fail{FSGMG_EINVAL, "time operator exists on the finest level"};
+      if (h->phys.inv_dt == 0.0) throw Fail{FSGMG_EINVAL, "steady hierarchy: no time operator"};
+      M = &h->ops[level].time;
     } else {
       throw Fail{FSGMG_EINVAL, "unknown matrix"};
     }

@@ -29,7 +29,7 @@ EXPORTED = ["setup_hierarchy", "build_fs_as_blocks", "vcycle_apply", "vcycle_app
             "gmres_solve", "gmres_solve_batch", "adjoint_solve_batch",
             "adjoint_solve", "assemble_load", "load_adjoint", "apply_operator", "param_grad",
             "param_grad_noalloc",
-            "update_params", "level_info", "dof_map", "debug_zero_block", "export_csr", "export_vector", "export_blocks", "block_colours",
+            "update_params", "update_advection", "time_rhs", "period_solve", "level_info", "dof_map", "debug_zero_block", "export_csr", "export_vector", "export_blocks", "block_colours",
             "kernel_timing", "stream_read_ceiling", "tuning_info", "last_error",
             "hierarchy_destroy"]
 
@@ -58,6 +58,18 @@ class SmootherOpts(C.Structure):
 
 class KrylovOpts(C.Structure):
     _fields_ = [("restart", C.c_int), ("max_restarts", C.c_int), ("rtol", C.c_double)]
+
+
+class PeriodOpts(C.Structure):
+    _fields_ = [("steps", C.c_int), ("t0", C.c_double), ("picard_max", C.c_int),
+                ("picard_tol", C.c_double), ("inflow_amp", C.c_double)]
+
+
+class PeriodInfo(C.Structure):
+    _fields_ = [("steps", C.c_int), ("solves", C.c_int), ("max_iters", C.c_int),
+                ("N", C.c_double), ("rho", C.c_double), ("s_max", C.c_double),
+                ("t_assemble_ms", C.c_double), ("t_factor_ms", C.c_double),
+                ("t_solve_ms", C.c_double), ("t_total_ms", C.c_double)]
 
 
 class SolveInfo(C.Structure):
@@ -138,6 +150,10 @@ def lib():
             "param_grad": ([H, P, P, C.POINTER(C.c_double)], C.c_int),
             "param_grad_noalloc": ([H, P, P, C.POINTER(C.c_double)], C.c_int),
             "update_params": ([H, C.c_double, C.c_double], C.c_int),
+            "update_advection": ([H, P], C.c_int),
+            "time_rhs": ([H, P, C.c_double, P, P], C.c_int),
+            "period_solve": ([H, C.POINTER(PeriodOpts), C.POINTER(KrylovOpts), P, P, P, P,
+                              C.POINTER(PeriodInfo)], C.c_int),
             "level_info": ([H, C.c_int, C.POINTER(C.c_int64)], C.c_int),
             "dof_map": ([H, C.c_int, C.POINTER(C.c_int64), P, P, P, P], C.c_int),
             "debug_zero_block": ([H, C.c_int, C.c_int64], C.c_int),
@@ -576,6 +592,41 @@ class Hierarchy:
         self.built_key = None
         update_params(self.h, E, mu)
         self.cfg.update(E=float(E), mu=float(mu))
+
+    def update_advection(self, x):
+        """Picard step: re-assemble every level about the velocity part of x."""
+        self.built_key = None
+        _check(self.h, lib().update_advection(self.h, _ptr(self._vec(x))))
+
+    def time_rhs(self, f, g, x_prev, b):
+        """b = F L f + g lift + F T x_prev (one backward-Euler step)."""
+        n2d = self.info[-1]["N2"] * self.info[-1]["dim"]
+        _check(self.h, lib().time_rhs(self.h, _ptr(self._vec(f, n2d)), float(g),
+                                      _ptr(self._vec(x_prev)), _ptr(self._vec(b))))
+
+    def period_solve(self, f, x, steps, picard_max=1, picard_tol=0.0, inflow_amp=0.75, t0=0.0,
+                     rtol=None, restart=None, max_restarts=20):
+        """Run `steps` backward-Euler steps with Picard updates (library
+        loop); returns a dict with the statistics and per-solve records."""
+        n2d = self.info[-1]["N2"] * self.info[-1]["dim"]
+        o = PeriodOpts(int(steps), float(t0), int(picard_max), float(picard_tol), float(inflow_amp))
+        k = KrylovOpts(int(self.cfg.get("restart", 30) if restart is None else restart),
+                       int(max_restarts),
+                       float(self.cfg.get("rtol", 1e-10) if rtol is None else rtol))
+        it = np.zeros(steps * picard_max, np.int32)
+        ch = np.zeros(steps * picard_max, np.float64)
+        info = PeriodInfo()
+        st = lib().period_solve(self.h, C.byref(o), C.byref(k), _ptr(self._vec(f, n2d)),
+                                _ptr(self._vec(x)),
+                                it.ctypes.data_as(C.c_void_p), ch.ctypes.data_as(C.c_void_p),
+                                C.byref(info))
+        self.built_key = None
+        if st not in (FSGMG_OK, FSGMG_NOT_CONVERGED):
+            _check(self.h, st)
+        out = {name: getattr(info, name) for name, _ in PeriodInfo._fields_}
+        out.update(converged=(st == FSGMG_OK), iters=it.reshape(steps, picard_max),
+                   changes=ch.reshape(steps, picard_max))
+        return out
 
     def kernel_timing(self, enable):
         return kernel_timing(self.h, enable)

@@ -13,6 +13,7 @@ import re
 
 import numpy as np
 import pytest
+import scipy.sparse as sp
 
 from oracle import fem, transfer
 from oracle.multigrid import Hierarchy as OracleHierarchy
@@ -124,6 +125,33 @@ def test_level_operators_match_oracle(pair):
     cfg, w, H, O = pair
     for l in range(H.L):
         assert _rel(H.csr(l, 0), O.A[l]) < 1e-13
+
+
+def test_time_operator_matches_oracle():
+    """The library's finest time operator (the terms carrying 1/dt, Dirichlet
+    rows removed) equals the oracle's, which is pinned against A(dt) - A(inf);
+    the steady hierarchy has none."""
+    cfg = inputs.with_levels(inputs.config("c5"), 2)
+    w = inputs.advecting_field(cfg)
+    H = fsgmg.Hierarchy(cfg, w, device=-1)
+    O = OracleHierarchy(cfg, w, build_smoothers=False)
+    try:
+        lv = O.finest
+        T = O.parts[-1]["T"].tocsr()
+        keep = sp.diags((~lv.dir_mask).astype(np.float64))
+        Tr = (keep @ T).tocsr()
+        assert Tr.nnz > 0
+        assert _rel(H.csr(H.L - 1, 4), Tr) < 1e-14
+        with pytest.raises(fsgmg.FsgmgError):
+            H.csr(0, 4)
+    finally:
+        H.close()
+    Hs = fsgmg.Hierarchy(inputs.with_levels(inputs.config("c2"), 2), w=None, device=-1)
+    try:
+        with pytest.raises(fsgmg.FsgmgError):
+            Hs.csr(Hs.L - 1, 4)
+    finally:
+        Hs.close()
 
 
 def test_transfers_match_oracle(pair):
