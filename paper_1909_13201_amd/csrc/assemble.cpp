@@ -19,7 +19,9 @@
 #include <algorithm>
 #include <cmath>
 #include <numeric>
+#include <exception>
 #include <stdexcept>
+#include <thread>
 
 #include "host.hpp"
 
@@ -217,6 +219,22 @@ struct Triplets {
     if (v == 0.0) return;
     add_always(r, c, p, v);
   }
+  // append lists in order, releasing them
+  void join(std::vector<Triplets>& parts) {
+    size_t n = row.size();
+    for (const Triplets& p : parts) n += p.row.size();
+    row.reserve(n);
+    col.reserve(n);
+    piece.reserve(n);
+    val.reserve(n);
+    for (Triplets& p : parts) {
+      row.insert(row.end(), p.row.begin(), p.row.end());
+      col.insert(col.end(), p.col.begin(), p.col.end());
+      piece.insert(piece.end(), p.piece.begin(), p.piece.end());
+      val.insert(val.end(), p.val.begin(), p.val.end());
+      p = Triplets();
+    }
+  }
   // terms that depend on the advecting velocity keep their entries when
   // they vanish, so the operator's pattern does not depend on w
   void add_always(int64_t r, int64_t c, int p, double v) {
@@ -228,7 +246,35 @@ struct Triplets {
   }
 };
 
-// Combine triplets into a CSR pattern with one value array per piece.
+// Run f(i0, i1) over contiguous ranges of [0, n) on up to 16 host threads
+// (one when n is small).
+template <typename F>
+static void parallel_ranges(int64_t n, int64_t min_per_thread, F&& f) {
+  const int nthr = (int)std::min<int64_t>(
+      std::max(1u, std::min(16u, std::thread::hardware_concurrency())), n / min_per_thread + 1);
+  if (nthr <= 1) {
+    f((int64_t)0, n);
+    return;
+  }
+  std::vector<std::exception_ptr> errs(nthr);
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nthr; ++t)
+    pool.emplace_back([&, t]() {
+      try {
+        f(n * t / nthr, n * (t + 1) / nthr);
+      } catch (...) {
+        errs[t] = std::current_exception();
+      }
+    });
+  for (std::thread& th : pool) th.join();
+  for (const std::exception_ptr& e : errs)
+    if (e) std::rethrow_exception(e);
+}
+
+// Combine triplets into a CSR pattern with one value array per piece: the
+// triplets of a row are ordered by column (the same sort of the same
+// sequence whatever the threading, so the sums are reproducible) and equal
+// columns summed per piece.
 void to_csr(const Triplets& t, int64_t nrows, int64_t ncols, int npieces, CsrHost& pat,
             std::vector<double>* pieces) {
   const int64_t nt = (int64_t)t.row.size();
@@ -240,28 +286,41 @@ void to_csr(const Triplets& t, int64_t nrows, int64_t ncols, int npieces, CsrHos
     std::vector<int64_t> cur(cnt.begin(), cnt.end() - 1);
     for (int64_t k = 0; k < nt; ++k) order[cur[t.row[k]]++] = k;
   }
+  // each row's triplets sorted by column, and its number of distinct columns
+  std::vector<int64_t> nu(nrows + 1, 0);
+  parallel_ranges(nrows, 4096, [&](int64_t i0, int64_t i1) {
+    for (int64_t i = i0; i < i1; ++i) {
+      auto b = order.begin() + cnt[i], e = order.begin() + cnt[i + 1];
+      std::sort(b, e, [&](int64_t x, int64_t y) { return t.col[x] < t.col[y]; });
+      int64_t u = 0;
+      for (auto k = b; k != e; ++k)
+        if (k == b || t.col[*k] != t.col[*(k - 1)]) ++u;
+      nu[i + 1] = u;
+    }
+  });
   pat.nrows = nrows;
   pat.ncols = ncols;
   pat.rowptr.assign(nrows + 1, 0);
-  pat.col.clear();
-  for (int p = 0; p < npieces; ++p) pieces[p].clear();
-  std::vector<int64_t> idx;
-  for (int64_t i = 0; i < nrows; ++i) {
-    idx.assign(order.begin() + cnt[i], order.begin() + cnt[i + 1]);
-    std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return t.col[a] < t.col[b]; });
-    size_t k = 0;
-    while (k < idx.size()) {
-      const int32_t c = t.col[idx[k]];
-      double acc[4] = {0, 0, 0, 0};
-      while (k < idx.size() && t.col[idx[k]] == c) {
-        acc[t.piece[idx[k]]] += t.val[idx[k]];
-        ++k;
+  for (int64_t i = 0; i < nrows; ++i) pat.rowptr[i + 1] = pat.rowptr[i] + nu[i + 1];
+  const int64_t nnz = pat.rowptr[nrows];
+  pat.col.assign(nnz, 0);
+  for (int p = 0; p < npieces; ++p) pieces[p].assign(nnz, 0.0);
+  parallel_ranges(nrows, 4096, [&](int64_t i0, int64_t i1) {
+    for (int64_t i = i0; i < i1; ++i) {
+      int64_t k = cnt[i], out = pat.rowptr[i];
+      while (k < cnt[i + 1]) {
+        const int32_t c = t.col[order[k]];
+        double acc[4] = {0, 0, 0, 0};
+        while (k < cnt[i + 1] && t.col[order[k]] == c) {
+          acc[t.piece[order[k]]] += t.val[order[k]];
+          ++k;
+        }
+        pat.col[out] = c;
+        for (int p = 0; p < npieces; ++p) pieces[p][out] = acc[p];
+        ++out;
       }
-      pat.col.push_back(c);
-      for (int p = 0; p < npieces; ++p) pieces[p].push_back(acc[p]);
     }
-    pat.rowptr[i + 1] = (int64_t)pat.col.size();
-  }
+  });
 }
 
 enum { P_BASE = 0, P_G = 1, P_C = 2, P_MU = 3 };
@@ -299,214 +358,235 @@ void assemble_level(const Level& lv, const Physics& ph, const std::vector<double
   op.mu = ph.mu;
   const bool have_w = w_level != nullptr;
 
-  Triplets T, TL, TT;   // operator pieces, load operator, time operator (finest)
-  // a term that carries 1/dt: into the operator and, on the finest level,
-  // into the time operator as well
-  auto tadd = [&](int64_t r, int64_t c, double v) {
-    T.add(r, c, P_BASE, v);
-    if (finest) TT.add(r, c, 0, v);
-  };
-  ElemGeo g;
-  static thread_local double Tg[kMaxB][kMaxB][3][3];
-  std::vector<double> Ksym(nbD * nbD), Bdiv(np * nbD), M2(nb * nb), M1(np * np);
-  std::vector<int64_t> dofd(nbD), dofu(nbD), rowm(nbD), dps(np), dpf(np);
-  for (int64_t e = 0; e < lv.nE; ++e) {
-    element_geometry(R, lv, e, g);
-    const int64_t* nodes = &lv.elem_nodes[e * nb];
-    const int64_t* verts = &lv.elem_verts[e * np];
-    // T[a][b][i][j] = sum_q dV G_ai G_bj
-    for (int a = 0; a < nb; ++a)
-      for (int b = 0; b < nb; ++b)
-        for (int i = 0; i < D; ++i)
-          for (int j = 0; j < D; ++j) {
-            double s = 0;
-            for (int q = 0; q < nq; ++q) s += g.dV[q] * g.G[q][a][i] * g.G[q][b][j];
-            Tg[a][b][i][j] = s;
-          }
-    for (int a = 0; a < nb; ++a)
-      for (int c = 0; c < D; ++c)
+  // The element loop over [e_begin, e_end) into the given triplet lists
+  // (operator pieces, load operator, time operator).
+  auto run_elements = [&](int64_t e_begin, int64_t e_end, Triplets& T, Triplets& TL,
+                          Triplets& TT) {
+    // a term that carries 1/dt: into the operator and, on the finest level,
+    // into the time operator as well
+    auto tadd = [&](int64_t r, int64_t c, double v) {
+      T.add(r, c, P_BASE, v);
+      if (finest) TT.add(r, c, 0, v);
+    };
+    ElemGeo g;
+    static thread_local double Tg[kMaxB][kMaxB][3][3];
+    std::vector<double> Ksym(nbD * nbD), Bdiv(np * nbD), M2(nb * nb), M1(np * np);
+    std::vector<int64_t> dofd(nbD), dofu(nbD), rowm(nbD), dps(np), dpf(np);
+    for (int64_t e = e_begin; e < e_end; ++e) {
+      element_geometry(R, lv, e, g);
+      const int64_t* nodes = &lv.elem_nodes[e * nb];
+      const int64_t* verts = &lv.elem_verts[e * np];
+      // T[a][b][i][j] = sum_q dV G_ai G_bj
+      for (int a = 0; a < nb; ++a)
+        for (int b = 0; b < nb; ++b)
+          for (int i = 0; i < D; ++i)
+            for (int j = 0; j < D; ++j) {
+              double s = 0;
+              for (int q = 0; q < nq; ++q) s += g.dV[q] * g.G[q][a][i] * g.G[q][b][j];
+              Tg[a][b][i][j] = s;
+            }
+      for (int a = 0; a < nb; ++a)
+        for (int c = 0; c < D; ++c)
+          for (int b = 0; b < nb; ++b)
+            for (int f = 0; f < D; ++f) {
+              double v = Tg[a][b][f][c];
+              if (c == f)
+                for (int i = 0; i < D; ++i) v += Tg[a][b][i][i];
+              Ksym[(a * D + c) * nbD + b * D + f] = v;
+            }
+      for (int m = 0; m < np; ++m)
         for (int b = 0; b < nb; ++b)
           for (int f = 0; f < D; ++f) {
-            double v = Tg[a][b][f][c];
-            if (c == f)
-              for (int i = 0; i < D; ++i) v += Tg[a][b][i][i];
-            Ksym[(a * D + c) * nbD + b * D + f] = v;
+            double s = 0;
+            for (int q = 0; q < nq; ++q) s += g.dV[q] * R.psi[q][m] * g.G[q][b][f];
+            Bdiv[m * nbD + b * D + f] = s;
           }
-    for (int m = 0; m < np; ++m)
-      for (int b = 0; b < nb; ++b)
-        for (int f = 0; f < D; ++f) {
+      for (int a = 0; a < nb; ++a)
+        for (int b = 0; b < nb; ++b) {
           double s = 0;
-          for (int q = 0; q < nq; ++q) s += g.dV[q] * R.psi[q][m] * g.G[q][b][f];
-          Bdiv[m * nbD + b * D + f] = s;
-        }
-    for (int a = 0; a < nb; ++a)
-      for (int b = 0; b < nb; ++b) {
-        double s = 0;
-        for (int q = 0; q < nq; ++q) s += g.dV[q] * R.phi[q][a] * R.phi[q][b];
-        M2[a * nb + b] = s;
-      }
-    for (int m = 0; m < np; ++m)
-      for (int n = 0; n < np; ++n) {
-        double s = 0;
-        for (int q = 0; q < nq; ++q) s += g.dV[q] * R.psi[q][m] * R.psi[q][n];
-        M1[m * np + n] = s;
-      }
-    for (int a = 0; a < nb; ++a)
-      for (int c = 0; c < D; ++c) {
-        dofd[a * D + c] = (int64_t)D * nodes[a] + c;
-        dofu[a * D + c] = lv.off_u + (int64_t)D * nodes[a] + c;
-      }
-    const bool solid = lv.region[e] == 1;
-    // momentum rows: S for solid-side nodes, F for fluid nodes
-    for (int a = 0; a < nb; ++a)
-      for (int c = 0; c < D; ++c)
-        rowm[a * D + c] = lv.solid_side[nodes[a]] ? dofd[a * D + c] : dofu[a * D + c];
-
-    // load operator: rho (f_h, phi) on momentum rows, columns = nodal force
-    for (int a = 0; a < nb; ++a)
-      for (int b = 0; b < nb; ++b)
-        for (int c = 0; c < D; ++c)
-          if (finest) TL.add(rowm[a * D + c], (int64_t)D * nodes[b] + c, 0, rho * M2[a * nb + b]);
-
-    if (solid) {
-      for (int m = 0; m < np; ++m) dps[m] = lv.ps_of_vert[verts[m]];
-      for (int r = 0; r < nbD; ++r)
-        for (int s = 0; s < nbD; ++s) T.add(dofd[r], dofd[s], P_G, Ksym[r * nbD + s]);
-      for (int m = 0; m < np; ++m)
-        for (int r = 0; r < nbD; ++r) {
-          T.add(dofd[r], dps[m], P_BASE, -Bdiv[m * nbD + r]);
-          T.add(dps[m], dofd[r], P_BASE, -Bdiv[m * nbD + r]);
+          for (int q = 0; q < nq; ++q) s += g.dV[q] * R.phi[q][a] * R.phi[q][b];
+          M2[a * nb + b] = s;
         }
       for (int m = 0; m < np; ++m)
-        for (int n = 0; n < np; ++n) T.add(dps[m], dps[n], P_C, -M1[m * np + n]);
+        for (int n = 0; n < np; ++n) {
+          double s = 0;
+          for (int q = 0; q < nq; ++q) s += g.dV[q] * R.psi[q][m] * R.psi[q][n];
+          M1[m * np + n] = s;
+        }
       for (int a = 0; a < nb; ++a)
         for (int c = 0; c < D; ++c) {
-          const int64_t r = dofu[a * D + c];
-          if (ph.k_mass == 0) {
-            double lump = 0;
-            for (int b = 0; b < nb; ++b) lump += M2[a * nb + b];
-            T.add(r, r, P_BASE, lump);
-            if (inv_dt != 0.0) tadd(r, dofd[a * D + c], -inv_dt * lump);
-          } else {
-            for (int b = 0; b < nb; ++b) {
-              T.add(r, dofu[b * D + c], P_BASE, M2[a * nb + b]);
-              if (inv_dt != 0.0) tadd(r, dofd[b * D + c], -inv_dt * M2[a * nb + b]);
+          dofd[a * D + c] = (int64_t)D * nodes[a] + c;
+          dofu[a * D + c] = lv.off_u + (int64_t)D * nodes[a] + c;
+        }
+      const bool solid = lv.region[e] == 1;
+      // momentum rows: S for solid-side nodes, F for fluid nodes
+      for (int a = 0; a < nb; ++a)
+        for (int c = 0; c < D; ++c)
+          rowm[a * D + c] = lv.solid_side[nodes[a]] ? dofd[a * D + c] : dofu[a * D + c];
+
+      // load operator: rho (f_h, phi) on momentum rows, columns = nodal force
+      for (int a = 0; a < nb; ++a)
+        for (int b = 0; b < nb; ++b)
+          for (int c = 0; c < D; ++c)
+            if (finest) TL.add(rowm[a * D + c], (int64_t)D * nodes[b] + c, 0, rho * M2[a * nb + b]);
+
+      if (solid) {
+        for (int m = 0; m < np; ++m) dps[m] = lv.ps_of_vert[verts[m]];
+        for (int r = 0; r < nbD; ++r)
+          for (int s = 0; s < nbD; ++s) T.add(dofd[r], dofd[s], P_G, Ksym[r * nbD + s]);
+        for (int m = 0; m < np; ++m)
+          for (int r = 0; r < nbD; ++r) {
+            T.add(dofd[r], dps[m], P_BASE, -Bdiv[m * nbD + r]);
+            T.add(dps[m], dofd[r], P_BASE, -Bdiv[m * nbD + r]);
+          }
+        for (int m = 0; m < np; ++m)
+          for (int n = 0; n < np; ++n) T.add(dps[m], dps[n], P_C, -M1[m * np + n]);
+        for (int a = 0; a < nb; ++a)
+          for (int c = 0; c < D; ++c) {
+            const int64_t r = dofu[a * D + c];
+            if (ph.k_mass == 0) {
+              double lump = 0;
+              for (int b = 0; b < nb; ++b) lump += M2[a * nb + b];
+              T.add(r, r, P_BASE, lump);
+              if (inv_dt != 0.0) tadd(r, dofd[a * D + c], -inv_dt * lump);
+            } else {
+              for (int b = 0; b < nb; ++b) {
+                T.add(r, dofu[b * D + c], P_BASE, M2[a * nb + b]);
+                if (inv_dt != 0.0) tadd(r, dofd[b * D + c], -inv_dt * M2[a * nb + b]);
+              }
             }
           }
+        if (inv_dt != 0.0)
+          for (int a = 0; a < nb; ++a)
+            for (int b = 0; b < nb; ++b)
+              for (int c = 0; c < D; ++c)
+                tadd(dofd[a * D + c], dofu[b * D + c], rho * inv_dt * M2[a * nb + b]);
+        continue;
+      }
+
+      // ---------------- fluid element ----------------
+      for (int m = 0; m < np; ++m) dpf[m] = lv.pf_of_vert[verts[m]];
+      for (int r = 0; r < nbD; ++r)
+        for (int s = 0; s < nbD; ++s) T.add(rowm[r], dofu[s], P_MU, Ksym[r * nbD + s]);
+      for (int m = 0; m < np; ++m)
+        for (int r = 0; r < nbD; ++r) {
+          T.add(rowm[r], dpf[m], P_BASE, -Bdiv[m * nbD + r]);
+          T.add(dpf[m], dofu[r], P_BASE, -Bdiv[m * nbD + r]);
         }
+      const double kel = ph.ale_k == 0 ? 1.0 / coarse_vol[lv.parent0[e]] : 1.0;
+      for (int a = 0; a < nb; ++a) {
+        if (lv.solid_side[nodes[a]]) continue;   // ALE test functions vanish on the interface
+        for (int c = 0; c < D; ++c)
+          for (int s = 0; s < nbD; ++s)
+            T.add(dofd[a * D + c], dofd[s], P_BASE, kel * Ksym[(a * D + c) * nbD + s]);
+      }
       if (inv_dt != 0.0)
         for (int a = 0; a < nb; ++a)
           for (int b = 0; b < nb; ++b)
             for (int c = 0; c < D; ++c)
-              tadd(dofd[a * D + c], dofu[b * D + c], rho * inv_dt * M2[a * nb + b]);
-      continue;
-    }
-
-    // ---------------- fluid element ----------------
-    for (int m = 0; m < np; ++m) dpf[m] = lv.pf_of_vert[verts[m]];
-    for (int r = 0; r < nbD; ++r)
-      for (int s = 0; s < nbD; ++s) T.add(rowm[r], dofu[s], P_MU, Ksym[r * nbD + s]);
-    for (int m = 0; m < np; ++m)
-      for (int r = 0; r < nbD; ++r) {
-        T.add(rowm[r], dpf[m], P_BASE, -Bdiv[m * nbD + r]);
-        T.add(dpf[m], dofu[r], P_BASE, -Bdiv[m * nbD + r]);
-      }
-    const double kel = ph.ale_k == 0 ? 1.0 / coarse_vol[lv.parent0[e]] : 1.0;
-    for (int a = 0; a < nb; ++a) {
-      if (lv.solid_side[nodes[a]]) continue;   // ALE test functions vanish on the interface
-      for (int c = 0; c < D; ++c)
-        for (int s = 0; s < nbD; ++s)
-          T.add(dofd[a * D + c], dofd[s], P_BASE, kel * Ksym[(a * D + c) * nbD + s]);
-    }
-    if (inv_dt != 0.0)
+              tadd(rowm[a * D + c], dofu[b * D + c], rho * inv_dt * M2[a * nb + b]);
+      if (!have_w) continue;
+      double wq[kMaxQ][3], wg[kMaxQ][kMaxB];
+      for (int q = 0; q < nq; ++q)
+        for (int i = 0; i < D; ++i) {
+          double s = 0;
+          for (int b = 0; b < nb; ++b) s += (*w_level)[nodes[b] * D + i] * R.phi[q][b];
+          wq[q][i] = s;
+        }
+      for (int q = 0; q < nq; ++q)
+        for (int a = 0; a < nb; ++a) {
+          double s = 0;
+          for (int i = 0; i < D; ++i) s += wq[q][i] * g.G[q][a][i];
+          wg[q][a] = s;
+        }
+      // convection rho (w.grad u, phi)
       for (int a = 0; a < nb; ++a)
-        for (int b = 0; b < nb; ++b)
-          for (int c = 0; c < D; ++c)
-            tadd(rowm[a * D + c], dofu[b * D + c], rho * inv_dt * M2[a * nb + b]);
-    if (!have_w) continue;
-    double wq[kMaxQ][3], wg[kMaxQ][kMaxB];
-    for (int q = 0; q < nq; ++q)
-      for (int i = 0; i < D; ++i) {
-        double s = 0;
-        for (int b = 0; b < nb; ++b) s += (*w_level)[nodes[b] * D + i] * R.phi[q][b];
-        wq[q][i] = s;
-      }
-    for (int q = 0; q < nq; ++q)
-      for (int a = 0; a < nb; ++a) {
-        double s = 0;
-        for (int i = 0; i < D; ++i) s += wq[q][i] * g.G[q][a][i];
-        wg[q][a] = s;
-      }
-    // convection rho (w.grad u, phi)
-    for (int a = 0; a < nb; ++a)
-      for (int b = 0; b < nb; ++b) {
-        double s = 0;
-        for (int q = 0; q < nq; ++q) s += g.dV[q] * R.phi[q][a] * wg[q][b];
-        for (int c = 0; c < D; ++c) T.add_always(rowm[a * D + c], dofu[b * D + c], P_BASE, rho * s);
-      }
-    if (!ph.supg) continue;
-    // lambda_k from the element bubble
-    const int bb = R.bubble;
-    double Mb[3][3] = {}, Nb = 0;
-    for (int q = 0; q < nq; ++q) {
-      double lap = 0;
-      for (int i = 0; i < D; ++i) lap += g.H[q][bb][i][i];
-      double v[3][3];
-      for (int a = 0; a < D; ++a)
-        for (int i = 0; i < D; ++i) v[a][i] = (i == a ? lap : 0.0) + g.H[q][bb][i][a];
-      for (int a = 0; a < D; ++a)
-        for (int b = 0; b < D; ++b) {
+        for (int b = 0; b < nb; ++b) {
           double s = 0;
-          for (int i = 0; i < D; ++i) s += v[a][i] * v[b][i];
-          Mb[a][b] += g.dV[q] * s;
+          for (int q = 0; q < nq; ++q) s += g.dV[q] * R.phi[q][a] * wg[q][b];
+          for (int c = 0; c < D; ++c) T.add_always(rowm[a * D + c], dofu[b * D + c], P_BASE, rho * s);
         }
-      for (int i = 0; i < D; ++i) Nb += g.dV[q] * g.G[q][bb][i] * g.G[q][bb][i];
-    }
-    const double lam = max_sym_eig(D, Mb) / Nb;
-    const double nu_k = ph.mu / rho;
-    double tw[kMaxQ];
-    for (int q = 0; q < nq; ++q) {
-      double wn = 0;
-      for (int i = 0; i < D; ++i) wn += wq[q][i] * wq[q][i];
-      wn = std::sqrt(wn);
-      const double tau = 1.0 / std::max(4.0 * lam * nu_k, std::sqrt(lam) * wn);
-      tw[q] = g.dV[q] * tau * rho;
-    }
-    for (int a = 0; a < nb; ++a)
-      for (int b = 0; b < nb; ++b) {
-        double s1 = 0;
-        for (int q = 0; q < nq; ++q) s1 += tw[q] * wg[q][a] * (rho * wg[q][b] + rho * inv_dt * R.phi[q][b]);
-        for (int c = 0; c < D; ++c) T.add_always(rowm[a * D + c], dofu[b * D + c], P_BASE, s1);
-        if (finest && inv_dt != 0.0) {   // the SUPG time term of s1, on its own
-          double st = 0;
-          for (int q = 0; q < nq; ++q) st += tw[q] * wg[q][a] * rho * inv_dt * R.phi[q][b];
-          for (int c = 0; c < D; ++c) TT.add(rowm[a * D + c], dofu[b * D + c], 0, st);
-        }
-        double sl = 0;
-        for (int q = 0; q < nq; ++q) sl += rho * rho * tw[q] * wg[q][a] * R.phi[q][b];
-        if (finest)
-          for (int c = 0; c < D; ++c) TL.add(rowm[a * D + c], (int64_t)D * nodes[b] + c, 0, sl);
-      }
-    for (int a = 0; a < nb; ++a)
-      for (int c = 0; c < D; ++c)
-        for (int b = 0; b < nb; ++b)
-          for (int f = 0; f < D; ++f) {
+      if (!ph.supg) continue;
+      // lambda_k from the element bubble
+      const int bb = R.bubble;
+      double Mb[3][3] = {}, Nb = 0;
+      for (int q = 0; q < nq; ++q) {
+        double lap = 0;
+        for (int i = 0; i < D; ++i) lap += g.H[q][bb][i][i];
+        double v[3][3];
+        for (int a = 0; a < D; ++a)
+          for (int i = 0; i < D; ++i) v[a][i] = (i == a ? lap : 0.0) + g.H[q][bb][i][a];
+        for (int a = 0; a < D; ++a)
+          for (int b = 0; b < D; ++b) {
             double s = 0;
-            for (int q = 0; q < nq; ++q) {
-              double lap = 0;
-              if (c == f)
-                for (int i = 0; i < D; ++i) lap += g.H[q][b][i][i];
-              s += tw[q] * wg[q][a] * (lap + g.H[q][b][c][f]);
-            }
-            T.add_always(rowm[a * D + c], dofu[b * D + f], P_MU, -s);
+            for (int i = 0; i < D; ++i) s += v[a][i] * v[b][i];
+            Mb[a][b] += g.dV[q] * s;
           }
-    for (int a = 0; a < nb; ++a)
-      for (int c = 0; c < D; ++c)
-        for (int m = 0; m < np; ++m) {
-          double s = 0;
-          for (int q = 0; q < nq; ++q) s += tw[q] * wg[q][a] * g.Gp[q][m][c];
-          T.add_always(rowm[a * D + c], dpf[m], P_BASE, s);
+        for (int i = 0; i < D; ++i) Nb += g.dV[q] * g.G[q][bb][i] * g.G[q][bb][i];
+      }
+      const double lam = max_sym_eig(D, Mb) / Nb;
+      const double nu_k = ph.mu / rho;
+      double tw[kMaxQ];
+      for (int q = 0; q < nq; ++q) {
+        double wn = 0;
+        for (int i = 0; i < D; ++i) wn += wq[q][i] * wq[q][i];
+        wn = std::sqrt(wn);
+        const double tau = 1.0 / std::max(4.0 * lam * nu_k, std::sqrt(lam) * wn);
+        tw[q] = g.dV[q] * tau * rho;
+      }
+      for (int a = 0; a < nb; ++a)
+        for (int b = 0; b < nb; ++b) {
+          double s1 = 0;
+          for (int q = 0; q < nq; ++q) s1 += tw[q] * wg[q][a] * (rho * wg[q][b] + rho * inv_dt * R.phi[q][b]);
+          for (int c = 0; c < D; ++c) T.add_always(rowm[a * D + c], dofu[b * D + c], P_BASE, s1);
+          if (finest && inv_dt != 0.0) {   // the SUPG time term of s1, on its own
+            double st = 0;
+            for (int q = 0; q < nq; ++q) st += tw[q] * wg[q][a] * rho * inv_dt * R.phi[q][b];
+            for (int c = 0; c < D; ++c) TT.add(rowm[a * D + c], dofu[b * D + c], 0, st);
+          }
+          double sl = 0;
+          for (int q = 0; q < nq; ++q) sl += rho * rho * tw[q] * wg[q][a] * R.phi[q][b];
+          if (finest)
+            for (int c = 0; c < D; ++c) TL.add(rowm[a * D + c], (int64_t)D * nodes[b] + c, 0, sl);
         }
+      for (int a = 0; a < nb; ++a)
+        for (int c = 0; c < D; ++c)
+          for (int b = 0; b < nb; ++b)
+            for (int f = 0; f < D; ++f) {
+              double s = 0;
+              for (int q = 0; q < nq; ++q) {
+                double lap = 0;
+                if (c == f)
+                  for (int i = 0; i < D; ++i) lap += g.H[q][b][i][i];
+                s += tw[q] * wg[q][a] * (lap + g.H[q][b][c][f]);
+              }
+              T.add_always(rowm[a * D + c], dofu[b * D + f], P_MU, -s);
+            }
+      for (int a = 0; a < nb; ++a)
+        for (int c = 0; c < D; ++c)
+          for (int m = 0; m < np; ++m) {
+            double s = 0;
+            for (int q = 0; q < nq; ++q) s += tw[q] * wg[q][a] * g.Gp[q][m][c];
+            T.add_always(rowm[a * D + c], dpf[m], P_BASE, s);
+          }
+    }
+  };
+  // Contiguous element ranges on host threads; their triplets are joined in
+  // element order, so the summation order (and every value) is that of one
+  // pass over the elements.
+  Triplets T, TL, TT;
+  const int64_t nE = lv.nE;
+  {
+    const int nthr = (int)std::min<int64_t>(
+        std::max(1u, std::min(16u, std::thread::hardware_concurrency())), nE / 256 + 1);
+    std::vector<Triplets> cT(nthr), cL(nthr), cTT(nthr);
+    parallel_ranges(nthr, 1, [&](int64_t t0, int64_t t1) {
+      for (int64_t t = t0; t < t1; ++t)
+        run_elements(nE * t / nthr, nE * (t + 1) / nthr, cT[t], cL[t], cTT[t]);
+    });
+    T.join(cT);
+    TL.join(cL);
+    TT.join(cTT);
   }
 
   // unreduced pattern with pieces
@@ -516,29 +596,44 @@ void assemble_level(const Level& lv, const Physics& ph, const std::vector<double
   T = Triplets();
 
   // reduced operator: Dirichlet rows and columns removed, unit diagonal
+  // (rows counted, then filled, on host threads)
   CsrHost& A = op.A;
   A.nrows = A.ncols = lv.N;
   A.rowptr.assign(lv.N + 1, 0);
-  A.col.clear();
-  for (int p = 0; p < 4; ++p) op.piece[p].clear();
-  for (int64_t i = 0; i < lv.N; ++i) {
-    if (lv.dir[i]) {
-      A.col.push_back((int32_t)i);
-      op.piece[P_BASE].push_back(1.0);
-      for (int p = 1; p < 4; ++p) op.piece[p].push_back(0.0);
-    } else {
-      for (int64_t k = full.rowptr[i]; k < full.rowptr[i + 1]; ++k) {
-        if (lv.dir[full.col[k]]) continue;
-        A.col.push_back(full.col[k]);
-        for (int p = 0; p < 4; ++p) op.piece[p].push_back(fp[p][k]);
+  parallel_ranges(lv.N, 4096, [&](int64_t i0, int64_t i1) {
+    for (int64_t i = i0; i < i1; ++i) {
+      int64_t c = 1;
+      if (!lv.dir[i]) {
+        c = 0;
+        for (int64_t k = full.rowptr[i]; k < full.rowptr[i + 1]; ++k) c += !lv.dir[full.col[k]];
       }
+      A.rowptr[i + 1] = c;
     }
-    A.rowptr[i + 1] = (int64_t)A.col.size();
-  }
-  A.val.resize(A.col.size());
-  for (size_t k = 0; k < A.col.size(); ++k)
-    A.val[k] = op.piece[P_BASE][k] + Gmod * op.piece[P_G][k] + invlam * op.piece[P_C][k] +
-               ph.mu * op.piece[P_MU][k];
+  });
+  for (int64_t i = 0; i < lv.N; ++i) A.rowptr[i + 1] += A.rowptr[i];
+  const int64_t annz = A.rowptr[lv.N];
+  A.col.assign(annz, 0);
+  for (int p = 0; p < 4; ++p) op.piece[p].assign(annz, 0.0);
+  A.val.assign(annz, 0.0);
+  parallel_ranges(lv.N, 4096, [&](int64_t i0, int64_t i1) {
+    for (int64_t i = i0; i < i1; ++i) {
+      int64_t o = A.rowptr[i];
+      if (lv.dir[i]) {
+        A.col[o] = (int32_t)i;
+        op.piece[P_BASE][o] = 1.0;
+      } else {
+        for (int64_t k = full.rowptr[i]; k < full.rowptr[i + 1]; ++k) {
+          if (lv.dir[full.col[k]]) continue;
+          A.col[o] = full.col[k];
+          for (int p = 0; p < 4; ++p) op.piece[p][o] = fp[p][k];
+          ++o;
+        }
+      }
+      for (int64_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k)
+        A.val[k] = op.piece[P_BASE][k] + Gmod * op.piece[P_G][k] + invlam * op.piece[P_C][k] +
+                   ph.mu * op.piece[P_MU][k];
+    }
+  });
 
   if (finest) {
     // lift pieces: lift = g on Dirichlet rows, -(A_full g) on free rows

@@ -705,6 +705,9 @@ __global__ __launch_bounds__(kThreads) void k_smooth_t2(BlocksView B, const TV* 
 // in the leading n x n corner.
 __device__ inline int pad16(int n) { return (n + 15) & ~15; }
 
+// The block's sorted index list is staged in LDS (n entries of dynamic
+// shared memory) for the column searches; the zero fill runs by rows
+// (wavefronts) and 16-byte columns (lanes).
 template <typename TF>
 __global__ __launch_bounds__(kThreads) void k_gather_blocks(const int32_t* __restrict__ jlist,
                                                             BlocksView B,
@@ -713,25 +716,30 @@ __global__ __launch_bounds__(kThreads) void k_gather_blocks(const int32_t* __res
                                                             const double* __restrict__ val,
                                                             const int64_t* __restrict__ doff,
                                                             TF* __restrict__ dense) {
+  using vec_t = typename std::conditional<sizeof(TF) == 8, double2, float4>::type;
+  constexpr int VW = 16 / sizeof(TF);
+  extern __shared__ int32_t Is[];
   const int64_t j = jlist[blockIdx.x];
   const int64_t d0 = B.dof_ptr[j];
   const int n = (int)(B.dof_ptr[j + 1] - d0);
   const int np = pad16(n);
   TF* a = dense + doff[blockIdx.x];
-  for (int64_t e = threadIdx.x; e < (int64_t)np * np; e += blockDim.x) {
-    const int r = (int)(e / np);
-    a[e] = (r >= n && e == (int64_t)r * np + r) ? TF(1) : TF(0);
-  }
-  __syncthreads();
   const int32_t* I = B.dofs + d0;
+  for (int k = threadIdx.x; k < n; k += blockDim.x) Is[k] = I[k];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int r = wv; r < np; r += nw)
+    for (int q = lane; q < np / VW; q += 64)
+      *reinterpret_cast<vec_t*>(a + (int64_t)r * np + q * VW) = vec_t{};
+  __syncthreads();
+  for (int r = n + threadIdx.x; r < np; r += blockDim.x) a[(int64_t)r * np + r] = TF(1);
   for (int k = threadIdx.x; k < n; k += blockDim.x) {
-    const int32_t g = I[k];
+    const int32_t g = Is[k];
     for (int64_t e = rp[g]; e < rp[g + 1]; ++e) {
       const int32_t c = col[e];
       int lo = 0, hi = n - 1;
       while (lo <= hi) {
         const int mid = (lo + hi) >> 1;
-        const int32_t v = I[mid];
+        const int32_t v = Is[mid];
         if (v == c) {
           a[(int64_t)k * np + mid] = (TF)val[e];
           break;
@@ -797,6 +805,12 @@ struct MfmaTile<double> {
   }
   __device__ static int row(int lg, int r) { return lg + 4 * r; }
 };
+
+// component i of a 16-byte vector (i a compile-time constant after unrolling)
+__device__ inline float vcomp(const float4& v, int i) {
+  return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
+}
+__device__ inline double vcomp(const double2& v, int i) { return i == 0 ? v.x : v.y; }
 
 // the values of one 16-byte load, stored one by one (unaligned LDS rows)
 __device__ inline void put_vec(float* d, const float4& v) {
@@ -1100,7 +1114,6 @@ __global__ __launch_bounds__(kTrailThreads) void k_invert_trailing(
   using vec_t = typename std::conditional<sizeof(TF) == 8, double2, float4>::type;
   constexpr int VW = 16 / sizeof(TF);           // values per 16-byte load
   constexpr int LDS_STRIDE = 64 + VW;          // row stride of the staged tiles
-  __shared__ __align__(16) TF Ts[64 * LDS_STRIDE];
   __shared__ __align__(16) TF Bs[64 * LDS_STRIDE];
   const int ntiles = kgroup ? ngroups : ngroups * ngroups;
   const int64_t L = blockIdx.x, xcd = L & 7, rest = L >> 3;
@@ -1120,24 +1133,31 @@ __global__ __launch_bounds__(kTrailThreads) void k_invert_trailing(
   const int nr = min(64, np - r0), nc = min(64, np - c0);
   TF* a = dense + doff[b];
   const int tid = threadIdx.x;
-  // stage T[r0 .. r0 + nr, K0 .. K0 + nko) and A[K0 .. K0 + nko, c0 .. c0 + nc)
-  // (zeros beyond), 16-byte loads along the rows
+  const int lane = tid & 63, wv = tid >> 6;
+  const int lr = lane & 15, lg = lane >> 4;
+  // The inner index of product step q in slot lg is k = 16 lg + q (one
+  // permutation of the summation index for both operands), so a lane's 16
+  // values of T (its row 16 wv + lr, columns K0 + 16 lg ...) are contiguous
+  // and come straight from global memory in 16-byte loads; k >= nko reads
+  // zeros.  These loads are issued before the B tile's staging.
+  vec_t tv[16 / VW];
+  const bool rows_here = 16 * wv < nr;
+#pragma unroll
+  for (int i = 0; i < 16 / VW; ++i) tv[i] = vec_t{};
+  if (rows_here && 16 * lg < nko) {
+    const TF* Tr = a + (int64_t)(r0 + 16 * wv + lr) * np + K0 + 16 * lg;
+#pragma unroll
+    for (int i = 0; i < 16 / VW; ++i) tv[i] = *reinterpret_cast<const vec_t*>(Tr + i * VW);
+  }
+  // stage A[K0 .. K0 + nko, c0 .. c0 + nc) (zeros beyond), 16-byte loads
   for (int e = tid; e < 64 * (64 / VW); e += kTrailThreads) {
     const int r = e / (64 / VW), q = (e - r * (64 / VW)) * VW;
-    vec_t t{}, v{};
-    if (r < nr && q < nko) t = *reinterpret_cast<const vec_t*>(a + (int64_t)(r0 + r) * np + K0 + q);
+    vec_t v{};
     if (r < nko && q < nc) v = *reinterpret_cast<const vec_t*>(a + (int64_t)(K0 + r) * np + c0 + q);
-    *reinterpret_cast<vec_t*>(Ts + r * LDS_STRIDE + q) = t;
     *reinterpret_cast<vec_t*>(Bs + r * LDS_STRIDE + q) = v;
   }
   __syncthreads();
-  const int lane = tid & 63, wv = tid >> 6;
-  const int lr = lane & 15, lg = lane >> 4;
-  if (16 * wv >= nr) return;
-  const int nq = nko / 4;
-  TF tq[16];
-#pragma unroll
-  for (int q = 0; q < 16; ++q) tq[q] = Ts[(16 * wv + lr) * LDS_STRIDE + 4 * q + lg];
+  if (!rows_here) return;
   const int64_t rowb = r0 + 16 * wv;
   for (int ct = 0; ct < nc / 16; ++ct) {
     const int col = c0 + 16 * ct + lr;
@@ -1145,10 +1165,9 @@ __global__ __launch_bounds__(kTrailThreads) void k_invert_trailing(
 #pragma unroll
     for (int r = 0; r < 4; ++r)
       acc[r] = kgroup ? TF(0) : a[(rowb + MT::row(lg, r)) * np + col];
-    const TF* Bc = Bs + lg * LDS_STRIDE + 16 * ct + lr;
+    const TF* Bc = Bs + 16 * lg * LDS_STRIDE + 16 * ct + lr;
 #pragma unroll
-    for (int q = 0; q < 16; ++q)
-      if (q < nq) acc = MT::step(tq[q], Bc[4 * q * LDS_STRIDE], acc);
+    for (int q = 0; q < 16; ++q) acc = MT::step(vcomp(tv[q / VW], q % VW), Bc[q * LDS_STRIDE], acc);
 #pragma unroll
     for (int r = 0; r < 4; ++r) a[(rowb + MT::row(lg, r)) * np + col] = acc[r];
   }
@@ -2996,14 +3015,16 @@ template void launch_add_scaled<float>(int64_t, double, const float*, float*, bo
 
 void launch_gather_blocks(const int32_t* jlist, int64_t nb, const BlocksView& B,
                           const int64_t* rowptr, const int32_t* col, const double* val,
-                          const int64_t* dense_off, void* dense, bool f32, hipStream_t s) {
+                          const int64_t* dense_off, void* dense, bool f32, int max_n,
+                          hipStream_t s) {
   if (nb <= 0) return;
+  const size_t sm = (size_t)std::max(max_n, 1) * sizeof(int32_t);
   if (f32)
-    hipLaunchKernelGGL((k_gather_blocks<float>), dim3((unsigned)nb), dim3(kThreads), 0, s, jlist, B,
-                       rowptr, col, val, dense_off, (float*)dense);
+    hipLaunchKernelGGL((k_gather_blocks<float>), dim3((unsigned)nb), dim3(kThreads), sm, s, jlist,
+                       B, rowptr, col, val, dense_off, (float*)dense);
   else
-    hipLaunchKernelGGL((k_gather_blocks<double>), dim3((unsigned)nb), dim3(kThreads), 0, s, jlist,
-                       B, rowptr, col, val, dense_off, (double*)dense);
+    hipLaunchKernelGGL((k_gather_blocks<double>), dim3((unsigned)nb), dim3(kThreads), sm, s,
+                       jlist, B, rowptr, col, val, dense_off, (double*)dense);
 }
 
 size_t invert_blocks_lds(int np_max, bool f32) {

@@ -243,7 +243,8 @@ void launch_add_scaled(int64_t n, double a, const TV* e, TV* x, bool first, hipS
 // BF16 inverses; `dense` holds elements of that type.
 void launch_gather_blocks(const int32_t* jlist, int64_t nb, const BlocksView& B,
                           const int64_t* rowptr, const int32_t* col, const double* val,
-                          const int64_t* dense_off, void* dense, bool f32, hipStream_t s);
+                          const int64_t* dense_off, void* dense, bool f32, int max_n,
+                          hipStream_t s);
 // Blocked in-place Gauss-Jordan inversion with partial pivoting of the padded
 // dense blocks (16-column panels, MFMA trailing updates in the factor type);
 // sigma[sigma_off[b] + q] receives the column permutation that completes the

@@ -1176,7 +1176,7 @@ void plan_factor(fsgmg_hierarchy& h, int l) {
 // Gather, invert and extract the blocks of every level l >= 1: each level on
 // its own stream (the small coarse levels, one block per CU, overlap the fine
 // one), joined back into the handle's stream.
-void factor_blocks(fsgmg_hierarchy& h) {
+void factor_blocks(fsgmg_hierarchy& h, bool retune) {
   if (!h.factor_start) HIPCHECK(hipEventCreateWithFlags(&h.factor_start, hipEventDisableTiming));
   HIPCHECK(hipEventRecord(h.factor_start, h.stream));
   for (int l = 1; l < h.L; ++l) {
@@ -1188,17 +1188,22 @@ void factor_blocks(fsgmg_hierarchy& h) {
     HIPCHECK(hipStreamWaitEvent(fp.stream, h.factor_start, 0));
     HIPCHECK(hipMemsetAsync(fp.status, 0, (size_t)nb * sizeof(int32_t), fp.stream));
     d.wt_valid = false;
-    if (h.sopt.prec == FSGMG_FP64)
-      launch_block_rows<double>(d.bv, d.rp, d.col, d.val, fp.stream);
-    else
-      launch_block_rows<float>(d.bv, d.rp, d.col, d.val, fp.stream);
+    // the blocks' copies of A's rows serve the fused sweep form only (and
+    // the autotuner's trial of it)
+    if (retune || h.tune[l].fused) {
+      if (h.sopt.prec == FSGMG_FP64)
+        launch_block_rows<double>(d.bv, d.rp, d.col, d.val, fp.stream);
+      else
+        launch_block_rows<float>(d.bv, d.rp, d.col, d.val, fp.stream);
+    }
     for (const FactorPlan::Chunk& c : fp.chunks) {
       const int64_t cnt = c.b1 - c.b0;
       const int32_t* jl = fp.jlist + c.b0;
       const int64_t* doff = fp.offs + c.off;
       const int64_t* soff = doff + cnt + 1;
       const bool f32 = factor_f32(h);
-      launch_gather_blocks(jl, cnt, d.bv, d.rp, d.col, d.val, doff, fp.dense, f32, fp.stream);
+      launch_gather_blocks(jl, cnt, d.bv, d.rp, d.col, d.val, doff, fp.dense, f32, c.max_n,
+                           fp.stream);
       if (h.zero_block_level == l)
         for (int64_t b = 0; b < cnt; ++b)
           if (fp.order[c.b0 + b] == h.zero_block) {
@@ -2478,10 +2483,11 @@ static fsgmg_status build_fs_as_blocks_impl(fsgmg_h h, const fsgmg_smoother_opts
       fsgmg_hierarchy* h;
       ~ClearHook() { h->zero_block_level = -1, h->zero_block = -1; }
     } clear_hook{h};
-    factor_blocks(*h);
     // launch shapes depend on the block structure only: keep them while the
     // index sets and precision are unchanged, so rebuilds stay reproducible
-    if (!same_sets || !h->tuned || prev_form != opts->sweep_form) autotune(*h);
+    const bool retune = !same_sets || !h->tuned || prev_form != opts->sweep_form;
+    factor_blocks(*h, retune);
+    if (retune) autotune(*h);
     h->tuned = true;
     h->factors_valid = true;
     return FSGMG_OK;

@@ -142,7 +142,7 @@ def config(name: str) -> dict:
             bc_d[f][1] = 1
             bc_d[f][0] = 1
         bc_u[FACE_ZMIN][0] = 2
-        sec = [0.0, 0.05, 0.5, 0.95, 1.0]          # ring graded to 0.1 R
+        sec = [0.0, 0.125, 0.5, 0.875, 1.0]        # wall ring a quarter of the radius
         zb = [0.0, 0.25, 0.5, 0.75, 0.975, 1.025, 1.35, 1.675, 2.0]
         region = np.zeros((8, 4, 4), np.int8)      # (z, y, x), x fastest
         region[:, 0, :] = region[:, 3, :] = 1

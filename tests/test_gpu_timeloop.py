@@ -203,3 +203,30 @@ def test_time_loop_error_paths():
             H.period_solve(f, v, steps=0)
     finally:
         H.close()
+
+
+def test_period_parity_3d():
+    """Two steps of the 3D channel (hexahedral Q2/Q1, SUPG, dt = 1/32) with
+    two Picard steps each, FP32 inverses, against the oracle."""
+    from tests.cfgs import channel3d
+    say("[timeloop] period 3D channel")
+    cfg = channel3d(levels=2, dt=1.0 / 32.0, supg=True)
+    lvf = hierarchy_levels(cfg)[-1]
+    f = np.random.default_rng(2).uniform(-1.0, 1.0, (lvf.N2, 3))
+    steps, pm = 2, 2
+    H = fsgmg.Hierarchy(cfg, np.zeros((lvf.N2, 3)), device=0)
+    try:
+        H.build_fs_as_blocks(prec="fp32")
+        x = torch.zeros(H.N, dtype=torch.float64, device="cuda")
+        res = H.period_solve(dev(f), x, steps=steps, picard_max=pm, rtol=1e-10)
+        say("   library iters", res["iters"].tolist())
+        assert res["converged"]
+        xo, _, _ = period(cfg, f, steps=steps, picard_max=pm)
+        tol = {k: steps * pm * v for k, v in SOLVE_TOL.items()}
+        check_fields(host(x), xo, H.info[-1], tol, "3D period")
+        _, recs, _ = period(cfg, f, steps=steps, picard_max=pm, solver="fgmres", rtol=1e-10)
+        it_o = np.array([r["iters"] for r in recs]).reshape(steps, pm)
+        say("   oracle iterations", it_o.tolist())
+        assert np.all(np.abs(res["iters"] - it_o) <= 1)
+    finally:
+        H.close()
