@@ -348,6 +348,39 @@ def time_loop_leg(args, dev):
             Hs.close()
             torch.cuda.empty_cache()
     out["dt_study"] = study
+    # the paper's comparator inside the loop: the monolithic AS blocks
+    # (Section 3.2), the first quarter period, against FS on the same steps
+    cmp = {}
+    for name, mono in (("fs", False), ("as", True)):
+        Ha = fsgmg.Hierarchy(cfg, np.zeros((n2, dim)), device=0)
+        try:
+            Ha.build_fs_as_blocks(prec="fp32", monolithic=mono)
+            xa = torch.zeros(Ha.N, dtype=torch.float64, device=dev)
+            r = Ha.period_solve(fd, xa, steps=8, picard_max=PICARD_MAX, picard_tol=PICARD_TOL,
+                                rtol=1e-10)
+            cmp[name] = dict(N=round(r["N"], 3), rho=round(r["rho"], 4), s_max=round(r["s_max"], 3),
+                             converged=r["converged"],
+                             factor_s=round(1e-3 * r["t_factor_ms"], 3),
+                             solve_s=round(1e-3 * r["t_solve_ms"], 3))
+        finally:
+            Ha.close()
+            torch.cuda.empty_cache()
+    out["fs_vs_as_quarter_period"] = cmp
+    # Crank-Nicolson for the momentum balance (theta = 1/2), the paper's
+    # scheme: the first quarter period
+    c = dict(cfg, theta=0.5)
+    Hc = fsgmg.Hierarchy(c, np.zeros((n2, dim)), device=0)
+    try:
+        Hc.build_fs_as_blocks(prec="fp32")
+        xc = torch.zeros(Hc.N, dtype=torch.float64, device=dev)
+        r = Hc.period_solve(fd, xc, steps=8, picard_max=PICARD_MAX, picard_tol=PICARD_TOL,
+                            rtol=1e-10)
+        out["crank_nicolson"] = dict(steps=r["steps"], N=round(r["N"], 3), rho=round(r["rho"], 4),
+                                     s_max=round(r["s_max"], 3), max_iters=r["max_iters"],
+                                     converged=r["converged"])
+    finally:
+        Hc.close()
+        torch.cuda.empty_cache()
     return out
 
 

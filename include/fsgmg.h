@@ -117,11 +117,19 @@ typedef struct {
  * step (K_ds = -K_us/dt and rho M/dt inertia), dt <= 0 or inf is steady.
  * supg != 0 enables SUPG (eqs. tausupg, lambda_k).  ale_k: 0 k = 1/V of the
  * coarse element containing the point, 1 k = 1.  k_mass: 0 lumped, 1
- * consistent kinematic mass.  w: host array (finest N2 x dim) or NULL. */
+ * consistent kinematic mass.  w: host array (finest N2 x dim) or NULL.
+ * theta (with a finite dt): weight of the steady terms of the momentum rows
+ * (the solid-side d rows and the fluid u rows), the rest of a step's
+ * operator unchanged: 1 (or 0, the zero-initialized default) is backward
+ * Euler, 1/2 Crank-Nicolson for the momentum balance with backward
+ * differences for the other time derivatives (Section 2.2); the explicit
+ * part -(1 - theta) of those terms joins the time operator of time_rhs.
+ * Range [0, 1], else EINVAL. */
 typedef struct {
   double E, nu, mu, rho, dt;
   int supg, ale_k, k_mass;
   const double* w;
+  double theta;
 } fsgmg_physics;
 
 /* Smoother: cores of core[0] x core[1] elements per region, Vanka halo of
@@ -365,7 +373,8 @@ fsgmg_status update_advection(fsgmg_h h, const double* x);
  * g is the pulsatile inflow factor) and the previous state x_prev (device,
  * finest level).  T holds the operator's terms that carry 1/dt (inertia,
  * the kinematic coupling of the solid, the SUPG time term) on the free
- * rows; F zeroes Dirichlet rows, which receive g times their data.  b must
+ * rows (and, for theta < 1, -(1 - theta) times the steady terms of the
+ * momentum rows); F zeroes Dirichlet rows, which receive g times their data.  b must
  * not alias x_prev or f.  EINVAL for a steady hierarchy (dt <= 0 or inf).
  * Asynchronous. */
 fsgmg_status time_rhs(fsgmg_h h, const double* f_nodal, double g, const double* x_prev,

@@ -202,21 +202,36 @@ def assemble_level(lv: Level, cfg: dict, w: np.ndarray | None = None,
 
     ``w``: advecting velocity at this level's Q2 nodes (N2, D) or None.
     ``tau``: optional frozen SUPG parameter per (fluid element, Gauss point).
-    Returns dict(A, base, AG, AC, Amu, T, tau, G, inv_lam).  T is the time
-    operator: the sum of the terms that carry 1/dt (a part of ``base``;
-    zero when steady), so that one backward-Euler step solves
-    A x_n = load + T x_{n-1}."""
+    Returns dict(A, base, AG, AC, Amu, T, Tx, tau, G, inv_lam).  T is the
+    time operator: the sum of the terms that carry 1/dt (a part of ``base``;
+    zero when steady).  cfg["theta"] (default 1) weights the steady terms of
+    the momentum rows (the rows of the momentum balance: solid-side d rows
+    and fluid u rows), theta = 1/2 being Crank-Nicolson for the momentum
+    balance while the other time derivatives stay backward differences;
+    Tx = T - (1 - theta) M with M those steady momentum-row terms, so that
+    one time step solves A x_n = load + Tx x_{n-1} (Tx = T for theta = 1)."""
     D, ref = lv.D, RefElement(lv.D)
     nb, npv = ref.nb, ref.np_
     rho, mu = cfg["rho"], cfg["mu"]
     Gmod, inv_lam = lame_constants(cfg["E"], cfg["nu"])
     inv_dt = 1.0 / cfg.get("dt", np.inf)
+    theta = float(cfg.get("theta", 1.0))
+    if not 0.0 < theta <= 1.0:
+        raise ValueError("theta must lie in (0, 1]")
     base, AG, AC, Amu = _COO(lv.N), _COO(lv.N), _COO(lv.N), _COO(lv.N)
     Tt = _COO(lv.N)
+    # the steady momentum-row terms, per affine piece (for Tx)
+    Mb, MG, Mmu = _COO(lv.N), _COO(lv.N), _COO(lv.N)
 
     def add_time(rows, cols, vals):
         base.add(rows, cols, vals)
         Tt.add(rows, cols, vals)
+
+    def add_mom(piece, mpiece, rows, cols, vals):
+        """A steady term of a momentum row: weight theta in the operator."""
+        piece.add(rows, cols, vals if theta == 1.0 else theta * vals)
+        if inv_dt and theta != 1.0:
+            mpiece.add(rows, cols, vals)
     comp = np.arange(D)
 
     Xe = lv.X[lv.elem_nodes]
@@ -235,8 +250,8 @@ def assemble_level(lv: Level, cfg: dict, w: np.ndarray | None = None,
     s = lv.region == 1
     if s.any():
         dps = lv.ps_of_vert[lv.elem_verts[s]]
-        AG.add(dof_d[s], dof_d[s], Ksym[s])                              # S_ds
-        base.add(dof_d[s], dps, -np.transpose(Bdiv[s], (0, 2, 1)))       # S_ps
+        add_mom(AG, MG, dof_d[s], dof_d[s], Ksym[s])                     # S_ds
+        add_mom(base, Mb, dof_d[s], dps, -np.transpose(Bdiv[s], (0, 2, 1)))   # S_ps
         base.add(dps, dof_d[s], -Bdiv[s])                                # V_ds
         AC.add(dps, dps, -Mq1[s])                                        # V_ps (compressible)
         if cfg.get("k_mass", 0) == 0:
@@ -267,8 +282,8 @@ def assemble_level(lv: Level, cfg: dict, w: np.ndarray | None = None,
         row_m = np.where(np.repeat(ss, D, axis=1), dof_d[f], dof_u[f])   # S or F rows
         dpf = lv.pf_of_vert[lv.elem_verts[f]]
         Kf = Ksym[f]
-        Amu.add(row_m, dof_u[f], Kf)                                     # viscous
-        base.add(row_m, dpf, -np.transpose(Bdiv[f], (0, 2, 1)))          # S_pf / F_pf
+        add_mom(Amu, Mmu, row_m, dof_u[f], Kf)                           # viscous
+        add_mom(base, Mb, row_m, dpf, -np.transpose(Bdiv[f], (0, 2, 1)))  # S_pf / F_pf
         base.add(dpf, dof_u[f], -Bdiv[f])                                # W_u
         # ALE rows, fluid-node test functions only
         if cfg.get("ale_k", 0) == 0:
@@ -285,8 +300,8 @@ def assemble_level(lv: Level, cfg: dict, w: np.ndarray | None = None,
             wq = np.einsum("eai,qa->eqi", we, ref.phi)
             wg = np.einsum("eqi,eqai->eqa", wq, G[f])                    # w . grad phi_a
             Cm = np.einsum("eq,qa,eqb->eab", dV[f], ref.phi, wg)
-            base.add(row_m, dof_u[f],
-                     rho * np.einsum("eab,cf->eacbf", Cm, eyeD).reshape(nF, nb * D, nb * D))
+            add_mom(base, Mb, row_m, dof_u[f],                           # convection
+                    rho * np.einsum("eab,cf->eacbf", Cm, eyeD).reshape(nF, nb * D, nb * D))
             if cfg.get("supg", False):
                 if tau is None:
                     lam = supg_lambda(ref, dV[f], G[f], H[f])
@@ -294,6 +309,10 @@ def assemble_level(lv: Level, cfg: dict, w: np.ndarray | None = None,
                 tau_out = tau
                 tw = dV[f] * tau * rho                                   # (nF, nq)
                 S1 = rho * np.einsum("eq,eqa,eqb->eab", tw, wg, wg)
+                if theta != 1.0 and inv_dt:     # only the steady part carries theta
+                    Mb.add(row_m, dof_u[f],
+                           np.einsum("eab,cf->eacbf", S1, eyeD).reshape(nF, nb * D, nb * D))
+                    S1 = theta * S1
                 if inv_dt:
                     S1 = S1 + rho * inv_dt * np.einsum("eq,eqa,qb->eab", tw, wg, ref.phi)
                 base.add(row_m, dof_u[f],
@@ -305,12 +324,14 @@ def assemble_level(lv: Level, cfg: dict, w: np.ndarray | None = None,
                 lap = np.einsum("eqbii->eqb", H[f])
                 S2 = (np.einsum("eq,eqa,eqb,cf->eacbf", tw, wg, lap, eyeD)
                       + np.einsum("eq,eqa,eqbcf->eacbf", tw, wg, H[f]))
-                Amu.add(row_m, dof_u[f], -S2.reshape(nF, nb * D, nb * D))
+                add_mom(Amu, Mmu, row_m, dof_u[f], -S2.reshape(nF, nb * D, nb * D))
                 Sp = np.einsum("eq,eqa,eqmc->eacm", tw, wg, Gp[f]).reshape(nF, nb * D, npv)
-                base.add(row_m, dpf, Sp)
+                add_mom(base, Mb, row_m, dpf, Sp)
 
     out = dict(base=base.csr(), AG=AG.csr(), AC=AC.csr(), Amu=Amu.csr(), T=Tt.csr(),
-               tau=tau_out, G=Gmod, inv_lam=inv_lam)
+               tau=tau_out, G=Gmod, inv_lam=inv_lam, theta=theta)
+    M = (Mb.csr() + Gmod * MG.csr() + mu * Mmu.csr()).tocsr()
+    out["Tx"] = (out["T"] - (1.0 - theta) * M).tocsr() if theta != 1.0 else out["T"]
     out["A"] = (out["base"] + Gmod * out["AG"] + inv_lam * out["AC"]
                 + mu * out["Amu"]).tocsr()
     return out

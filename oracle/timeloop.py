@@ -12,11 +12,15 @@ solve (N) and the mean convergence rate (rho).
 
 Readings (the linearization of this build is Oseen about a frozen advecting
 velocity, solid linearized at the stress-free state):
-* every time derivative by backward Euler with step dt = cfg["dt"] (the
-  assembled operator A_dt already carries these terms; the part of it that
-  multiplies 1/dt is the time operator T, so one step solves
-      A_dt x_n = F L f + T x_{n-1}
-  on the free rows, x_n = g(t_n) u_D on the Dirichlet rows);
+* the time derivatives by backward differences with step dt = cfg["dt"];
+  the steady terms of the momentum rows carry the weight theta =
+  cfg["theta"] (1, the default, is backward Euler throughout; 1/2 is
+  Crank-Nicolson for the momentum balance, as the paper uses it), the
+  assembled operator A carries the implicit part and Tx = T - (1 - theta) M
+  the explicit one (T the terms that multiply 1/dt, M the steady momentum-
+  row terms), so one step solves
+      A x_n = F L f + Tx x_{n-1}
+  on the free rows, x_n = g(t_n) u_D on the Dirichlet rows;
 * the nonlinear steps are Picard (fixed-point) steps on the advecting
   velocity: step s of time step n assembles every level about w = the
   velocity of the latest iterate (w = u(x_{n-1}) for s = 1) and solves the
@@ -58,7 +62,7 @@ def step_rhs(H: Hierarchy, fnodal: np.ndarray, g: float, x_prev: np.ndarray) -> 
     asm = H.parts[-1]
     b_raw = fem.load_vector(lv, H.cfg, fnodal, H.w_finest, asm["tau"])
     gD = np.where(lv.dir_mask, g * lv.dir_val, 0.0)
-    b = b_raw - H.A_full[-1] @ gD + asm["T"] @ x_prev
+    b = b_raw - H.A_full[-1] @ gD + asm["Tx"] @ x_prev
     return np.where(lv.dir_mask, gD, b)
 
 

@@ -351,6 +351,10 @@ void assemble_level(const Level& lv, const Physics& ph, const std::vector<double
   RefElem R(D);
   const int nb = R.nb, np = R.np, nq = R.nq, nbD = nb * D;
   const double rho = ph.rho, inv_dt = ph.inv_dt;
+  // weight of the steady terms of the momentum rows (1 = backward Euler,
+  // 1/2 = Crank-Nicolson for the momentum balance)
+  const double theta = ph.theta;
+  const bool weighted = inv_dt != 0.0 && theta != 1.0;
   double Gmod, invlam;
   lame(ph.E, ph.nu, Gmod, invlam);
   op.G = Gmod;
@@ -367,6 +371,17 @@ void assemble_level(const Level& lv, const Physics& ph, const std::vector<double
     auto tadd = [&](int64_t r, int64_t c, double v) {
       T.add(r, c, P_BASE, v);
       if (finest) TT.add(r, c, 0, v);
+    };
+    // a steady term of a momentum row: theta times v into the operator and,
+    // on the finest level, -(1 - theta) v into the time operator (the
+    // explicit part of the step)
+    auto madd = [&](int64_t r, int64_t c, int p, double v, bool always) {
+      const double tv = weighted ? theta * v : v;
+      if (always)
+        T.add_always(r, c, p, tv);
+      else
+        T.add(r, c, p, tv);
+      if (finest && weighted) TT.add(r, c, p, -(1.0 - theta) * v);
     };
     ElemGeo g;
     static thread_local double Tg[kMaxB][kMaxB][3][3];
@@ -433,10 +448,10 @@ void assemble_level(const Level& lv, const Physics& ph, const std::vector<double
       if (solid) {
         for (int m = 0; m < np; ++m) dps[m] = lv.ps_of_vert[verts[m]];
         for (int r = 0; r < nbD; ++r)
-          for (int s = 0; s < nbD; ++s) T.add(dofd[r], dofd[s], P_G, Ksym[r * nbD + s]);
+          for (int s = 0; s < nbD; ++s) madd(dofd[r], dofd[s], P_G, Ksym[r * nbD + s], false);
         for (int m = 0; m < np; ++m)
           for (int r = 0; r < nbD; ++r) {
-            T.add(dofd[r], dps[m], P_BASE, -Bdiv[m * nbD + r]);
+            madd(dofd[r], dps[m], P_BASE, -Bdiv[m * nbD + r], false);
             T.add(dps[m], dofd[r], P_BASE, -Bdiv[m * nbD + r]);
           }
         for (int m = 0; m < np; ++m)
@@ -467,10 +482,10 @@ void assemble_level(const Level& lv, const Physics& ph, const std::vector<double
       // ---------------- fluid element ----------------
       for (int m = 0; m < np; ++m) dpf[m] = lv.pf_of_vert[verts[m]];
       for (int r = 0; r < nbD; ++r)
-        for (int s = 0; s < nbD; ++s) T.add(rowm[r], dofu[s], P_MU, Ksym[r * nbD + s]);
+        for (int s = 0; s < nbD; ++s) madd(rowm[r], dofu[s], P_MU, Ksym[r * nbD + s], false);
       for (int m = 0; m < np; ++m)
         for (int r = 0; r < nbD; ++r) {
-          T.add(rowm[r], dpf[m], P_BASE, -Bdiv[m * nbD + r]);
+          madd(rowm[r], dpf[m], P_BASE, -Bdiv[m * nbD + r], false);
           T.add(dpf[m], dofu[r], P_BASE, -Bdiv[m * nbD + r]);
         }
       const double kel = ph.ale_k == 0 ? 1.0 / coarse_vol[lv.parent0[e]] : 1.0;
@@ -504,7 +519,7 @@ void assemble_level(const Level& lv, const Physics& ph, const std::vector<double
         for (int b = 0; b < nb; ++b) {
           double s = 0;
           for (int q = 0; q < nq; ++q) s += g.dV[q] * R.phi[q][a] * wg[q][b];
-          for (int c = 0; c < D; ++c) T.add_always(rowm[a * D + c], dofu[b * D + c], P_BASE, rho * s);
+          for (int c = 0; c < D; ++c) madd(rowm[a * D + c], dofu[b * D + c], P_BASE, rho * s, true);
         }
       if (!ph.supg) continue;
       // lambda_k from the element bubble
@@ -537,7 +552,19 @@ void assemble_level(const Level& lv, const Physics& ph, const std::vector<double
       for (int a = 0; a < nb; ++a)
         for (int b = 0; b < nb; ++b) {
           double s1 = 0;
-          for (int q = 0; q < nq; ++q) s1 += tw[q] * wg[q][a] * (rho * wg[q][b] + rho * inv_dt * R.phi[q][b]);
+          if (!weighted) {
+            for (int q = 0; q < nq; ++q) s1 += tw[q] * wg[q][a] * (rho * wg[q][b] + rho * inv_dt * R.phi[q][b]);
+          } else {
+            // only the steady part carries theta
+            double s1s = 0, s1t = 0;
+            for (int q = 0; q < nq; ++q) {
+              s1s += tw[q] * wg[q][a] * rho * wg[q][b];
+              s1t += tw[q] * wg[q][a] * rho * inv_dt * R.phi[q][b];
+            }
+            s1 = theta * s1s + s1t;
+            if (finest)
+              for (int c = 0; c < D; ++c) TT.add(rowm[a * D + c], dofu[b * D + c], 0, -(1.0 - theta) * s1s);
+          }
           for (int c = 0; c < D; ++c) T.add_always(rowm[a * D + c], dofu[b * D + c], P_BASE, s1);
           if (finest && inv_dt != 0.0) {   // the SUPG time term of s1, on its own
             double st = 0;
@@ -560,14 +587,14 @@ void assemble_level(const Level& lv, const Physics& ph, const std::vector<double
                   for (int i = 0; i < D; ++i) lap += g.H[q][b][i][i];
                 s += tw[q] * wg[q][a] * (lap + g.H[q][b][c][f]);
               }
-              T.add_always(rowm[a * D + c], dofu[b * D + f], P_MU, -s);
+              madd(rowm[a * D + c], dofu[b * D + f], P_MU, -s, true);
             }
       for (int a = 0; a < nb; ++a)
         for (int c = 0; c < D; ++c)
           for (int m = 0; m < np; ++m) {
             double s = 0;
             for (int q = 0; q < nq; ++q) s += tw[q] * wg[q][a] * g.Gp[q][m][c];
-            T.add_always(rowm[a * D + c], dpf[m], P_BASE, s);
+            madd(rowm[a * D + c], dpf[m], P_BASE, s, true);
           }
     }
   };
@@ -668,18 +695,23 @@ void assemble_level(const Level& lv, const Physics& ph, const std::vector<double
     }
     // time operator with Dirichlet rows removed (every column kept: the
     // previous state carries the previous Dirichlet data)
+    // (affine pieces like the operator's when theta < 1: the explicit part
+    // carries G and mu)
     CsrHost Tc;
     std::vector<double> tp[4];
-    to_csr(TT, lv.N, lv.N, 1, Tc, tp);
+    to_csr(TT, lv.N, lv.N, 4, Tc, tp);
     op.time.nrows = op.time.ncols = lv.N;
     op.time.rowptr.assign(lv.N + 1, 0);
     op.time.col.clear();
     op.time.val.clear();
+    for (int p = 0; p < 4; ++p) op.time_piece[p].clear();
     for (int64_t i = 0; i < lv.N; ++i) {
       if (!lv.dir[i])
         for (int64_t k = Tc.rowptr[i]; k < Tc.rowptr[i + 1]; ++k) {
           op.time.col.push_back(Tc.col[k]);
-          op.time.val.push_back(tp[0][k]);
+          for (int p = 0; p < 4; ++p) op.time_piece[p].push_back(tp[p][k]);
+          op.time.val.push_back(tp[P_BASE][k] + Gmod * tp[P_G][k] + invlam * tp[P_C][k] +
+                                ph.mu * tp[P_MU][k]);
         }
       op.time.rowptr[i + 1] = (int64_t)op.time.col.size();
     }

@@ -63,12 +63,17 @@ struct LevelOperator {
   std::vector<double> full_piece[4];
   std::vector<double> lift_piece[4];  // finest: lift = sum coef * lift_piece
   CsrHost load;                     // finest: N x D*N2 load operator
-  CsrHost time;                     // finest: the terms carrying 1/dt, Dirichlet rows removed
+  CsrHost time;                     // finest: the previous state's operator of a time
+                                    // step (the terms carrying 1/dt, and -(1 - theta)
+                                    // times the steady momentum-row terms), Dirichlet
+                                    // rows removed
+  std::vector<double> time_piece[4];  // its affine pieces
   double G = 0, invlam = 0, mu = 0;
 };
 
 struct Physics {
   double E, nu, mu, rho, inv_dt;
+  double theta;      // weight of the steady momentum-row terms (1 = backward Euler)
   int supg, ale_k, k_mass;
   const double* w;   // finest-level nodal advecting velocity or nullptr
   int n_levels;

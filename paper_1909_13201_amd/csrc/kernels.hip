@@ -705,9 +705,11 @@ __global__ __launch_bounds__(kThreads) void k_smooth_t2(BlocksView B, const TV* 
 // in the leading n x n corner.
 __device__ inline int pad16(int n) { return (n + 15) & ~15; }
 
-// The block's sorted index list is staged in LDS (n entries of dynamic
-// shared memory) for the column searches; the zero fill runs by rows
-// (wavefronts) and 16-byte columns (lanes).
+// The block's sorted index list is staged in LDS for the column searches.
+// Each wavefront then assembles one row at a time in an LDS row of its own
+// (zeros, the row's entries placed by a search of the index list, 1 on the
+// padding's diagonal) and stores the whole row with 16-byte stores, so the
+// dense block reaches global memory as full-line writes only.
 template <typename TF>
 __global__ __launch_bounds__(kThreads) void k_gather_blocks(const int32_t* __restrict__ jlist,
                                                             BlocksView B,
@@ -718,38 +720,49 @@ __global__ __launch_bounds__(kThreads) void k_gather_blocks(const int32_t* __res
                                                             TF* __restrict__ dense) {
   using vec_t = typename std::conditional<sizeof(TF) == 8, double2, float4>::type;
   constexpr int VW = 16 / sizeof(TF);
-  extern __shared__ int32_t Is[];
+  extern __shared__ __align__(16) unsigned char gsm[];
   const int64_t j = jlist[blockIdx.x];
   const int64_t d0 = B.dof_ptr[j];
   const int n = (int)(B.dof_ptr[j + 1] - d0);
   const int np = pad16(n);
+  int32_t* Is = reinterpret_cast<int32_t*>(gsm);                  // n
+  TF* rows = reinterpret_cast<TF*>(gsm + ((size_t)n * 4 + 15) / 16 * 16);   // waves x np
   TF* a = dense + doff[blockIdx.x];
   const int32_t* I = B.dofs + d0;
   for (int k = threadIdx.x; k < n; k += blockDim.x) Is[k] = I[k];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (int r = wv; r < np; r += nw)
-    for (int q = lane; q < np / VW; q += 64)
-      *reinterpret_cast<vec_t*>(a + (int64_t)r * np + q * VW) = vec_t{};
   __syncthreads();
-  for (int r = n + threadIdx.x; r < np; r += blockDim.x) a[(int64_t)r * np + r] = TF(1);
-  for (int k = threadIdx.x; k < n; k += blockDim.x) {
-    const int32_t g = Is[k];
-    for (int64_t e = rp[g]; e < rp[g + 1]; ++e) {
-      const int32_t c = col[e];
-      int lo = 0, hi = n - 1;
-      while (lo <= hi) {
-        const int mid = (lo + hi) >> 1;
-        const int32_t v = Is[mid];
-        if (v == c) {
-          a[(int64_t)k * np + mid] = (TF)val[e];
-          break;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  TF* rb = rows + (size_t)wv * np;
+  for (int r = wv; r < np; r += nw) {
+    for (int q = lane; q < np; q += 64) rb[q] = (r >= n && q == r) ? TF(1) : TF(0);
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (r < n) {
+      const int32_t g = Is[r];
+      for (int64_t e = rp[g] + lane; e < rp[g + 1]; e += 64) {
+        const int32_t c = col[e];
+        int lo = 0, hi = n - 1;
+        while (lo <= hi) {
+          const int mid = (lo + hi) >> 1;
+          const int32_t v = Is[mid];
+          if (v == c) {
+            rb[mid] = (TF)val[e];
+            break;
+          }
+          if (v < c)
+            lo = mid + 1;
+          else
+            hi = mid - 1;
         }
-        if (v < c)
-          lo = mid + 1;
-        else
-          hi = mid - 1;
       }
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    for (int q = lane; q < np / VW; q += 64)
+      *reinterpret_cast<vec_t*>(a + (int64_t)r * np + q * VW) =
+          *reinterpret_cast<const vec_t*>(rb + q * VW);
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -3018,7 +3031,10 @@ void launch_gather_blocks(const int32_t* jlist, int64_t nb, const BlocksView& B,
                           const int64_t* dense_off, void* dense, bool f32, int max_n,
                           hipStream_t s) {
   if (nb <= 0) return;
-  const size_t sm = (size_t)std::max(max_n, 1) * sizeof(int32_t);
+  // the index list, then one LDS row per wavefront
+  const int npmax = (std::max(max_n, 1) + 15) & ~15;
+  const size_t sm = ((size_t)std::max(max_n, 1) * 4 + 15) / 16 * 16 +
+                    (size_t)(kThreads / 64) * npmax * (f32 ? 4 : 8);
   if (f32)
     hipLaunchKernelGGL((k_gather_blocks<float>), dim3((unsigned)nb), dim3(kThreads), sm, s, jlist,
                        B, rowptr, col, val, dense_off, (float*)dense);

@@ -247,6 +247,13 @@ struct FactorPlan {
   int32_t* status = nullptr;
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
+  // levels of several chunks: a second scratch and stream, so that the
+  // latency-bound panel launches of one chunk overlap the trailing updates
+  // of the other
+  double* dense2 = nullptr;
+  int32_t* sigma2 = nullptr;
+  hipStream_t stream2 = nullptr;
+  hipEvent_t fork = nullptr, done2 = nullptr;
 };
 
 struct DLevel {
@@ -353,6 +360,7 @@ struct fsgmg_hierarchy {
   int64_t* time_rp = nullptr;
   int32_t* time_col = nullptr;
   double* time_val = nullptr;
+  double* time_piece[4] = {nullptr, nullptr, nullptr, nullptr};
   // period_solve: previous state, current and new iterate, right-hand side
   double* per_buf = nullptr;
   double* lift_piece[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -501,6 +509,9 @@ struct fsgmg_hierarchy {
       for (DLevel& d : dl) {
         if (d.fp.stream) (void)hipStreamDestroy(d.fp.stream);
         if (d.fp.done) (void)hipEventDestroy(d.fp.done);
+        if (d.fp.stream2) (void)hipStreamDestroy(d.fp.stream2);
+        if (d.fp.fork) (void)hipEventDestroy(d.fp.fork);
+        if (d.fp.done2) (void)hipEventDestroy(d.fp.done2);
       }
       if (coarse_done) {
         if (coarse_pending) (void)hipEventSynchronize(coarse_done);
@@ -531,8 +542,10 @@ void fsgmg_hierarchy::quiesce() {
   if (device < 0) return;
   (void)hipStreamSynchronize(stream);
   if (cap_stream) (void)hipStreamSynchronize(cap_stream);
-  for (DLevel& d : dl)
+  for (DLevel& d : dl) {
     if (d.fp.stream) (void)hipStreamSynchronize(d.fp.stream);
+    if (d.fp.stream2) (void)hipStreamSynchronize(d.fp.stream2);
+  }
 }
 
 namespace {
@@ -856,13 +869,16 @@ void upload_load_and_time(fsgmg_hierarchy& h) {
   h.loadT_rp = h.upload(LT.rowptr);
   h.loadT_col = h.upload(LT.col);
   h.loadT_val = h.upload(LT.val);
+  for (int p = 0; p < 4; ++p) h.dfree(h.time_piece[p]);
   h.time_rp = nullptr;
   h.time_col = nullptr;
   h.time_val = nullptr;
+  for (int p = 0; p < 4; ++p) h.time_piece[p] = nullptr;
   if (h.phys.inv_dt != 0.0) {
     h.time_rp = h.upload(op.time.rowptr);
     h.time_col = h.upload(op.time.col);
     h.time_val = h.upload(op.time.val);
+    for (int p = 0; p < 4; ++p) h.time_piece[p] = h.upload(op.time_piece[p]);
   }
 }
 
@@ -1099,9 +1115,11 @@ void plan_factor(fsgmg_hierarchy& h, int l) {
   DLevel& d = h.dl[l];
   FactorPlan& fp = d.fp;
   for (void* q : {(void*)fp.jlist, (void*)fp.offs, (void*)fp.dense, (void*)fp.sigma,
-                  (void*)fp.status})
+                  (void*)fp.status, (void*)fp.dense2, (void*)fp.sigma2})
     h.dfree(q);
   fp.ready = false;
+  fp.dense2 = nullptr;
+  fp.sigma2 = nullptr;
   fp.chunks.clear();
   fp.jlist = nullptr;
   fp.offs = nullptr;
@@ -1170,6 +1188,15 @@ void plan_factor(fsgmg_hierarchy& h, int l) {
   fp.status = (int32_t*)h.dalloc((size_t)nb * sizeof(int32_t));
   if (!fp.stream) HIPCHECK(hipStreamCreateWithFlags(&fp.stream, hipStreamNonBlocking));
   if (!fp.done) HIPCHECK(hipEventCreateWithFlags(&fp.done, hipEventDisableTiming));
+  fp.dense2 = nullptr;
+  fp.sigma2 = nullptr;
+  if (fp.chunks.size() > 1) {
+    fp.dense2 = (double*)h.dalloc(maxchunk);
+    fp.sigma2 = (int32_t*)h.dalloc(maxsig);
+    if (!fp.stream2) HIPCHECK(hipStreamCreateWithFlags(&fp.stream2, hipStreamNonBlocking));
+    if (!fp.fork) HIPCHECK(hipEventCreateWithFlags(&fp.fork, hipEventDisableTiming));
+    if (!fp.done2) HIPCHECK(hipEventCreateWithFlags(&fp.done2, hipEventDisableTiming));
+  }
   fp.ready = true;
 }
 
@@ -1196,29 +1223,44 @@ void factor_blocks(fsgmg_hierarchy& h, bool retune) {
       else
         launch_block_rows<float>(d.bv, d.rp, d.col, d.val, fp.stream);
     }
-    for (const FactorPlan::Chunk& c : fp.chunks) {
+    // chunks alternate between the two scratch slots and streams (one slot
+    // when the level has a single chunk)
+    const bool two = fp.dense2 != nullptr;
+    if (two) {
+      HIPCHECK(hipEventRecord(fp.fork, fp.stream));
+      HIPCHECK(hipStreamWaitEvent(fp.stream2, fp.fork, 0));
+    }
+    for (size_t ci = 0; ci < fp.chunks.size(); ++ci) {
+      const FactorPlan::Chunk& c = fp.chunks[ci];
+      const bool second = two && (ci & 1);
+      hipStream_t cs = second ? fp.stream2 : fp.stream;
+      double* dense = second ? fp.dense2 : fp.dense;
+      int32_t* sigma = second ? fp.sigma2 : fp.sigma;
       const int64_t cnt = c.b1 - c.b0;
       const int32_t* jl = fp.jlist + c.b0;
       const int64_t* doff = fp.offs + c.off;
       const int64_t* soff = doff + cnt + 1;
       const bool f32 = factor_f32(h);
-      launch_gather_blocks(jl, cnt, d.bv, d.rp, d.col, d.val, doff, fp.dense, f32, c.max_n,
-                           fp.stream);
+      launch_gather_blocks(jl, cnt, d.bv, d.rp, d.col, d.val, doff, dense, f32, c.max_n, cs);
       if (h.zero_block_level == l)
         for (int64_t b = 0; b < cnt; ++b)
           if (fp.order[c.b0 + b] == h.zero_block) {
             // test hook: a zero matrix, so the block's first pivot is zero
             const int64_t o = fp.hoffs[c.off + b], n2 = fp.hoffs[c.off + b + 1] - o;
             if (f32)
-              launch_fill<float>(reinterpret_cast<float*>(fp.dense) + o, 0.0f, n2, fp.stream);
+              launch_fill<float>(reinterpret_cast<float*>(dense) + o, 0.0f, n2, cs);
             else
-              launch_fill<double>(fp.dense + o, 0.0, n2, fp.stream);
+              launch_fill<double>(dense + o, 0.0, n2, cs);
           }
-      launch_invert_blocks(jl, cnt, d.bv.dof_ptr, doff, soff, fp.dense, f32, fp.sigma, fp.status,
-                           c.max_n, fp.stream);
-      launch_extract_owned(jl, cnt, d.bv, doff, soff, fp.dense, f32, fp.sigma, wprec(h.sopt.prec),
-                           d.W, fp.stream);
+      launch_invert_blocks(jl, cnt, d.bv.dof_ptr, doff, soff, dense, f32, sigma, fp.status,
+                           c.max_n, cs);
+      launch_extract_owned(jl, cnt, d.bv, doff, soff, dense, f32, sigma, wprec(h.sopt.prec),
+                           d.W, cs);
       HIPCHECK(hipGetLastError());
+    }
+    if (two) {
+      HIPCHECK(hipEventRecord(fp.done2, fp.stream2));
+      HIPCHECK(hipStreamWaitEvent(fp.stream, fp.done2, 0));
     }
     HIPCHECK(hipEventRecord(fp.done, fp.stream));
   }
@@ -2363,6 +2405,8 @@ fsgmg_status setup_hierarchy(const fsgmg_mesh_desc* mesh, const fsgmg_physics* p
         !(phys->rho > 0) || !std::isfinite(phys->E) || !std::isfinite(phys->mu) ||
         !std::isfinite(phys->rho))
       throw Fail{FSGMG_EINVAL, "physical parameters out of range"};
+    if (!(phys->theta >= 0 && phys->theta <= 1))
+      throw Fail{FSGMG_EINVAL, "theta must lie in (0, 1] (0 selects 1)"};
     h->mesh = *mesh;
     for (int a = 0; a < mesh->dim; ++a) {
       h->breaks[a].assign(mesh->breaks[a], mesh->breaks[a] + mesh->nc[a] + 1);
@@ -2378,7 +2422,7 @@ fsgmg_status setup_hierarchy(const fsgmg_mesh_desc* mesh, const fsgmg_physics* p
     if (phys->w) h->w_finest.assign(phys->w, phys->w + Fl.N2 * h->D);
     h->phys = Physics{phys->E, phys->nu, phys->mu, phys->rho,
                       (phys->dt > 0 && std::isfinite(phys->dt)) ? 1.0 / phys->dt : 0.0,
-                      phys->supg, phys->ale_k, phys->k_mass,
+                      phys->theta > 0 ? phys->theta : 1.0, phys->supg, phys->ale_k, phys->k_mass,
                       h->w_finest.empty() ? nullptr : h->w_finest.data(), h->L};
     assemble_all(*h, h->ops);
     h->tr.resize(h->L);
@@ -2699,6 +2743,12 @@ fsgmg_status update_params(fsgmg_h h, double E, double mu) {
     const int64_t NF = h->dl[h->L - 1].N;
     launch_recombine(NF, h->lift_piece[0], h->lift_piece[1], h->lift_piece[2], h->lift_piece[3], G,
                      invlam, mu, h->lift, nullptr, h->stream);
+    if (h->time_val) {   // the explicit part of a theta step carries G and mu
+      const LevelOperator& F = h->ops[h->L - 1];
+      launch_recombine((int64_t)F.time.col.size(), h->time_piece[0], h->time_piece[1],
+                       h->time_piece[2], h->time_piece[3], G, invlam, mu, h->time_val, nullptr,
+                       h->stream);
+    }
     HIPCHECK(hipGetLastError());
     if (!h->bd.empty()) h->bd_dirty = true;      // the diagonal blocks follow the values
     if (h->dl[0].use_bd) ensure_bd(*h);
@@ -2972,7 +3022,12 @@ fsgmg_status export_csr(fsgmg_h h, int level, int which, int64_t dims[3], int64_
     } else if (which == 4) {
       if (level != h->L - 1) throw Fail{FSGMG_EINVAL, "time operator exists on the finest level"};
       if (h->phys.inv_dt == 0.0) throw Fail{FSGMG_EINVAL, "steady hierarchy: no time operator"};
-      M = &h->ops[level].time;
+      const LevelOperator& op = h->ops[level];
+      tmp = op.time;
+      for (size_t k = 0; k < tmp.val.size(); ++k)
+        tmp.val[k] = op.time_piece[0][k] + op.G * op.time_piece[1][k] +
+                     op.invlam * op.time_piece[2][k] + op.mu * op.time_piece[3][k];
+      M = &tmp;
     } else {
       throw Fail{FSGMG_EINVAL, "unknown matrix"};
     }

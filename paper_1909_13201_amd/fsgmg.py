@@ -45,7 +45,8 @@ class MeshDesc(C.Structure):
 class Physics(C.Structure):
     _fields_ = [("E", C.c_double), ("nu", C.c_double), ("mu", C.c_double),
                 ("rho", C.c_double), ("dt", C.c_double), ("supg", C.c_int),
-                ("ale_k", C.c_int), ("k_mass", C.c_int), ("w", C.POINTER(C.c_double))]
+                ("ale_k", C.c_int), ("k_mass", C.c_int), ("w", C.POINTER(C.c_double)),
+                ("theta", C.c_double)]
 
 
 class SmootherOpts(C.Structure):
@@ -222,6 +223,7 @@ def _physics(cfg, w, keep):
     p.supg = int(bool(cfg.get("supg", False)))
     p.ale_k = int(cfg.get("ale_k", 0))
     p.k_mass = int(cfg.get("k_mass", 0))
+    p.theta = float(cfg.get("theta", 1.0))
     if w is not None:
         arr = np.ascontiguousarray(np.asarray(w, dtype=np.float64))
         keep.append(arr)

@@ -230,3 +230,58 @@ def test_period_parity_3d():
         assert np.all(np.abs(res["iters"] - it_o) <= 1)
     finally:
         H.close()
+
+
+def test_period_parity_crank_nicolson():
+    """theta = 1/2 (Crank-Nicolson for the momentum balance): four steps with
+    two Picard steps each, FP32 inverses, against the oracle's states and
+    iteration counts."""
+    say("[timeloop] period c5L2, theta = 1/2")
+    cfg = dict(_cfg(), theta=0.5)
+    f = inputs.body_force(cfg)
+    steps, pm = 4, 2
+    lvf = hierarchy_levels(cfg)[-1]
+    H = fsgmg.Hierarchy(cfg, np.zeros((lvf.N2, lvf.D)), device=0)
+    try:
+        H.build_fs_as_blocks(prec="fp32")
+        x = torch.zeros(H.N, dtype=torch.float64, device="cuda")
+        res = H.period_solve(dev(f), x, steps=steps, picard_max=pm, rtol=1e-10)
+        say("   library iters", res["iters"].tolist())
+        assert res["converged"]
+        xo, _, _ = period(cfg, f, steps=steps, picard_max=pm)
+        tol = {k: steps * pm * v for k, v in SOLVE_TOL.items()}
+        check_fields(host(x), xo, H.info[-1], tol, "Crank-Nicolson period")
+        _, recs, _ = period(cfg, f, steps=steps, picard_max=pm, solver="fgmres", rtol=1e-10)
+        it_o = np.array([r["iters"] for r in recs]).reshape(steps, pm)
+        say("   oracle iterations", it_o.tolist())
+        assert np.all(np.abs(res["iters"] - it_o) <= 1)
+    finally:
+        H.close()
+
+
+def test_period_parity_monolithic_comparator():
+    """The paper's comparator inside the time loop: the monolithic AS blocks
+    (Section 3.2) for two steps with two Picard steps each, FP32 inverses,
+    against the oracle's states and its FGMRES with the same blocks."""
+    say("[timeloop] period c5L2 with the monolithic AS blocks")
+    cfg = _cfg()
+    f = inputs.body_force(cfg)
+    steps, pm = 2, 2
+    lvf = hierarchy_levels(cfg)[-1]
+    H = fsgmg.Hierarchy(cfg, np.zeros((lvf.N2, lvf.D)), device=0)
+    try:
+        H.build_fs_as_blocks(prec="fp32", monolithic=True)
+        x = torch.zeros(H.N, dtype=torch.float64, device="cuda")
+        res = H.period_solve(dev(f), x, steps=steps, picard_max=pm, rtol=1e-10)
+        say("   library iters", res["iters"].tolist())
+        assert res["converged"]
+        xo, _, _ = period(cfg, f, steps=steps, picard_max=pm)
+        tol = {k: steps * pm * v for k, v in SOLVE_TOL.items()}
+        check_fields(host(x), xo, H.info[-1], tol, "AS period")
+        _, recs, _ = period(dict(cfg, monolithic=True), f, steps=steps, picard_max=pm,
+                            solver="fgmres", rtol=1e-10)
+        it_o = np.array([r["iters"] for r in recs]).reshape(steps, pm)
+        say("   oracle iterations", it_o.tolist())
+        assert np.all(np.abs(res["iters"] - it_o) <= 1)
+    finally:
+        H.close()

@@ -154,6 +154,29 @@ def test_time_operator_matches_oracle():
         Hs.close()
 
 
+def test_theta_scheme_operators_match_oracle():
+    """With theta = 1/2 (Crank-Nicolson for the momentum balance) every
+    level operator and the finest time operator (now with the explicit
+    -(1 - theta) part of the steady momentum-row terms) equal the oracle's;
+    after update_params the time operator follows (E, mu)."""
+    cfg = dict(inputs.with_levels(inputs.config("c5"), 2), theta=0.5)
+    w = inputs.advecting_field(cfg)
+    H = fsgmg.Hierarchy(cfg, w, device=-1)
+    O = OracleHierarchy(cfg, w, build_smoothers=False)
+    try:
+        for l in range(H.L):
+            assert _rel(H.csr(l, 0), O.A[l]) < 1e-13
+        keep = sp.diags((~O.finest.dir_mask).astype(np.float64))
+        assert _rel(H.csr(H.L - 1, 4), (keep @ O.parts[-1]["Tx"]).tocsr()) < 1e-13
+        E2, mu2 = 3.0e4, 7.0e-3
+        H.update_params(E2, mu2)
+        O2 = OracleHierarchy(dict(cfg, E=E2, mu=mu2), w, taus=[p["tau"] for p in O.parts],
+                             build_smoothers=False)
+        assert _rel(H.csr(H.L - 1, 4), (keep @ O2.parts[-1]["Tx"]).tocsr()) < 1e-13
+    finally:
+        H.close()
+
+
 def test_transfers_match_oracle(pair):
     cfg, w, H, O = pair
     for l in range(1, H.L):

@@ -133,3 +133,75 @@ def test_period_statistics_by_hand():
     assert st["rho"] == pytest.approx(0.2)
     assert st["s_max"] == pytest.approx(1.5)
     assert st["solves"] == 3
+
+
+def _momentum_rows(lv):
+    """Rows of the momentum balance: d rows of solid-side nodes (the solid
+    momentum equation sits on d) and u rows of the other nodes."""
+    m = np.zeros(lv.N, bool)
+    ss = np.asarray(lv.solid_side, bool)
+    for c in range(lv.D):
+        m[lv.D * np.arange(lv.N2) + c] = ss
+        m[lv.off_u + lv.D * np.arange(lv.N2) + c] = ~ss
+    return m
+
+
+@pytest.mark.parametrize("theta", [0.5, 0.7])
+def test_theta_scheme_operators(theta):
+    """A_theta = T + theta A_inf on the momentum rows (A_inf elsewhere) and
+    Tx = T - (1 - theta) A_inf on the momentum rows, A_inf assembled
+    separately without dt."""
+    import scipy.sparse as sp
+    cfg = dict(_cfg(), theta=theta)
+    lv = hierarchy_levels(cfg)[-1]
+    w = inputs.advecting_field(inputs.with_levels(inputs.config("c5"), 2))
+    a = fem.assemble_level(lv, cfg, w)
+    b = fem.assemble_level(lv, dict(cfg, dt=np.inf, theta=1.0), w, a["tau"])
+    m = _momentum_rows(lv)
+    S = sp.diags(np.where(m, theta, 1.0))
+    Mm = sp.diags(m.astype(float))
+    scale = abs(a["A"]).max()
+    assert abs(a["A"] - a["T"] - S @ b["A"]).max() <= 1e-13 * scale
+    assert abs(a["Tx"] - (a["T"] - (1 - theta) * (Mm @ b["A"]))).max() <= 1e-13 * scale
+    # theta = 1 is backward Euler: the same operator and Tx = T
+    one = fem.assemble_level(lv, dict(cfg, theta=1.0), w, a["tau"])
+    ref = fem.assemble_level(lv, {k: v for k, v in cfg.items() if k != "theta"}, w, a["tau"])
+    assert abs(one["A"] - ref["A"]).max() == 0 and abs(one["Tx"] - one["T"]).max() == 0
+
+
+def test_theta_steady_state_is_a_fixed_point():
+    cfg = dict(_cfg(), theta=0.5)
+    w = inputs.advecting_field(cfg)
+    f = inputs.body_force(cfg)
+    Hs = Hierarchy(dict(cfg, dt=np.inf, theta=1.0), w_finest=w, build_smoothers=False)
+    xs = direct_solve(Hs.A[-1], Hs.rhs(f))
+    Ht = Hierarchy(cfg, w_finest=w, taus=[p["tau"] for p in Hs.parts], build_smoothers=False)
+    x1 = direct_solve(Ht.A[-1], step_rhs(Ht, f, 1.0, xs))
+    assert np.linalg.norm(x1 - xs) <= 1e-9 * np.linalg.norm(xs)
+
+
+@pytest.mark.parametrize("theta,order", [(1.0, 1), (0.5, 2)])
+def test_theta_scheme_convergence_order(theta, order):
+    """A channel without solid (Stokes, parabolic inflow scaled by the
+    pulsatile factor, from the steady state at t = 0): successive
+    differences of the velocity at t = 1/4 for dt = 1/16 ... 1/128 shrink
+    by 2 (backward Euler) or 4 (Crank-Nicolson)."""
+    import scipy.sparse.linalg as spla
+    from tests.cfgs import small
+    cfg0 = small(nc=(4, 4), solid_rows=(), levels=1,
+                 bc_u=[[2, 0], [0, 0], [1, 0], [1, 0], [0, 0], [0, 0]], bc_d=[[1, 0]] * 6)
+    Hs = Hierarchy(dict(cfg0, dt=np.inf), None, build_smoothers=False)
+    lv = Hs.finest
+    f = np.zeros((lv.N2, lv.D))
+    x0 = direct_solve(Hs.A[-1], Hs.rhs(f))
+    us = []
+    for dt in (1 / 16, 1 / 32, 1 / 64, 1 / 128):
+        H = Hierarchy(dict(cfg0, dt=dt, theta=theta), None, build_smoothers=False)
+        lu = spla.splu(H.A[-1].tocsc())
+        x = x0
+        for i in range(1, int(round(0.25 / dt)) + 1):
+            x = lu.solve(step_rhs(H, f, inflow_scale(i * dt), x))
+        us.append(x[lv.off_u:lv.off_pf])
+    e = [np.linalg.norm(us[k] - us[k + 1]) for k in range(3)]
+    ratios = [e[k] / e[k + 1] for k in range(2)]
+    assert all(abs(r - 2 ** order) < 0.35 * 2 ** order for r in ratios), ratios
