@@ -231,6 +231,10 @@ struct DevBOp {
 // (small and large blocks never share a chunk: the LDS of a launch is set by
 // its largest block), with the per-chunk offsets uploaded once; the scratch
 // stays allocated and each level is factored on its own stream.
+// device memory allowed for one level's copies of its blocks' operator rows
+// (read by the fused sweep form only)
+constexpr size_t kRowCopyBudget = (size_t)4 << 30;
+
 struct FactorPlan {
   struct Chunk {
     int64_t b0, b1, off;   // list range, position of its offsets in `offs`
@@ -1092,13 +1096,19 @@ void upload_blocks(fsgmg_hierarchy& h, int l) {
     int jw = 0;
     for (int32_t g : bs.jac) jw = std::max(jw, (int)(A.rowptr[g + 1] - A.rowptr[g]));
     const size_t vb = h.sopt.prec == FSGMG_FP64 ? 8 : 4;
-    v.rows_off = h.upload(roff);
-    v.rows_w = h.upload(rw);
-    v.rows_col = (const int32_t*)h.dalloc((size_t)roff[nb] * sizeof(int32_t));
-    v.rows_val = h.dalloc((size_t)roff[nb] * vb);
-    v.jrow_w = jw;
-    v.jrow_col = (const int32_t*)h.dalloc((size_t)bs.jac.size() * jw * sizeof(int32_t));
-    v.jrow_val = h.dalloc((size_t)bs.jac.size() * jw * vb);
+    // the copies cost sum_j n_j * (longest row of block j) entries: in 3D
+    // (rows of up to 125 node blocks) tens of GB, beyond what the fused form
+    // can gain; such a level keeps the SpMV form only
+    const size_t rows_bytes = ((size_t)roff[nb] + bs.jac.size() * (size_t)jw) * (4 + vb);
+    if (rows_bytes <= kRowCopyBudget) {
+      v.rows_off = h.upload(roff);
+      v.rows_w = h.upload(rw);
+      v.rows_col = (const int32_t*)h.dalloc((size_t)roff[nb] * sizeof(int32_t));
+      v.rows_val = h.dalloc((size_t)roff[nb] * vb);
+      v.jrow_w = jw;
+      v.jrow_col = (const int32_t*)h.dalloc((size_t)bs.jac.size() * jw * sizeof(int32_t));
+      v.jrow_val = h.dalloc((size_t)bs.jac.size() * jw * vb);
+    }
     if (h.sopt.prec == FSGMG_FP64)
       d.x2_64 = h.zeros<double>(lv.N);
     else
@@ -1217,7 +1227,7 @@ void factor_blocks(fsgmg_hierarchy& h, bool retune) {
     d.wt_valid = false;
     // the blocks' copies of A's rows serve the fused sweep form only (and
     // the autotuner's trial of it)
-    if (retune || h.tune[l].fused) {
+    if ((retune || h.tune[l].fused) && d.bv.rows_col) {
       if (h.sopt.prec == FSGMG_FP64)
         launch_block_rows<double>(d.bv, d.rp, d.col, d.val, fp.stream);
       else
@@ -2274,7 +2284,12 @@ void autotune_impl(fsgmg_hierarchy& h) {
       });
       float t_fused = 1e30f;
       int th_fused = h.tune[l].smooth_threads;
+      if (h.sopt.sweep_form == 2 && !tv.rows_col)
+        throw Fail{FSGMG_EINVAL, "the fused sweep form is not available on level " +
+                                     std::to_string(l) +
+                                     " (its blocks' operator-row copies exceed the budget)"};
       for (int th : threads) {
+        if (!tv.rows_col) break;   // no operator-row copies: no fused form
         const float t = time_launch(h, fl, [&] {
           launch_smooth_fused<TV>(tv, wp, d.W, Vec<TV>::b(d), Vec<TV>::x(d), Vec<TV>::x2(d), 1.0,
                                   false, h.stream, th);
