@@ -357,11 +357,16 @@ fsgmg_status update_params(fsgmg_h h, double E, double mu);
  * time step by Newton's method; here the convection and SUPG terms are
  * re-linearized about the latest velocity): re-assemble every level
  * operator, the Dirichlet lift, the load operator and the time operator
- * about the advecting velocity w = the velocity part of x (device, finest
- * level vector; w at the finest Q2 nodes, injected at the coarse levels'
- * nodes), with the current (E, mu).  Host assembly (one thread per level)
- * and upload; the operators' patterns do not change.  Invalidates the
- * blocks (call build_fs_as_blocks again) and rebuilds the coarse inverse as
+ * about the advecting velocity w = the velocity part of x (finest level
+ * vector in device memory, in host memory for a host-only handle; w at the
+ * finest Q2 nodes, injected at the coarse levels' nodes), with the current
+ * (E, mu).  Host assembly (one thread per level) and upload of values; the
+ * operators' patterns do not change.  The first call keeps, per level, the
+ * sums of the terms that do not depend on w (host memory of four values
+ * per operator entry and a 32-bit slot per advective term); every call then adds only the convection and
+ * SUPG terms, element colour by element colour, so the values equal a
+ * fresh setup's about the same w bit for bit.  Invalidates the blocks (call
+ * build_fs_as_blocks again) and rebuilds the coarse inverse as
  * update_params does.  EINVAL for a hierarchy set up without an advecting
  * velocity (physics.w = NULL) or a velocity with NaN / Inf. */
 fsgmg_status update_advection(fsgmg_h h, const double* x);

@@ -18,6 +18,7 @@
 // Operator = base + G*pG + (1/lambda_L)*pC + mu*pMu with tau frozen.
 #include <algorithm>
 #include <cmath>
+#include <memory>
 #include <numeric>
 #include <exception>
 #include <stdexcept>
@@ -345,8 +346,358 @@ std::vector<double> element_volumes(const Level& lv) {
   return vol;
 }
 
+namespace {
+
+// Unknowns of one element: displacement and velocity components of its
+// nodes, the momentum row of each (S on solid-side nodes, F elsewhere) and
+// its solid and fluid pressure unknowns (-1 where a vertex has none).
+struct ElemDofs {
+  int64_t d[kMaxB * 3], u[kMaxB * 3], rowm[kMaxB * 3], ps[kMaxP], pf[kMaxP];
+};
+
+void element_dofs(const Level& lv, int64_t e, int nb, int np, ElemDofs& o) {
+  const int D = lv.D;
+  const int64_t* nodes = &lv.elem_nodes[e * nb];
+  const int64_t* verts = &lv.elem_verts[e * np];
+  for (int a = 0; a < nb; ++a)
+    for (int c = 0; c < D; ++c) {
+      o.d[a * D + c] = (int64_t)D * nodes[a] + c;
+      o.u[a * D + c] = lv.off_u + (int64_t)D * nodes[a] + c;
+      o.rowm[a * D + c] = lv.solid_side[nodes[a]] ? o.d[a * D + c] : o.u[a * D + c];
+    }
+  for (int m = 0; m < np; ++m) {
+    o.ps[m] = lv.ps_of_vert[verts[m]];
+    o.pf[m] = lv.pf_of_vert[verts[m]];
+  }
+}
+
+enum { T_OP = 0, T_TIME = 1, T_LOAD = 2 };
+
+// The terms of fluid element e that depend on the advecting velocity w
+// (Section 2.2: the convection rho (w.grad u, phi) and every SUPG term of
+// the stabilized momentum balance with tau of eq. tausupg, lambda_k from the
+// element bubble), handed in a fixed order to emit(target, row, col, piece,
+// value): T_OP the operator, T_TIME the time operator, T_LOAD the load
+// operator (the last two on the finest level only).
+template <typename Emit>
+void advective_terms(const RefElem& R, const Level& lv, const Physics& ph, const ElemGeo& g,
+                     int64_t e, const ElemDofs& dof, const std::vector<double>& w, bool finest,
+                     Emit&& emit) {
+  const int D = R.D, nb = R.nb, np = R.np, nq = R.nq;
+  const double rho = ph.rho, inv_dt = ph.inv_dt, theta = ph.theta;
+  const bool weighted = inv_dt != 0.0 && theta != 1.0;
+  const int64_t* nodes = &lv.elem_nodes[e * nb];
+  // a steady term of a momentum row: theta v into the operator and, on the
+  // finest level, -(1 - theta) v into the time operator
+  auto madd = [&](int64_t r, int64_t c, int p, double v) {
+    emit(T_OP, r, c, p, weighted ? theta * v : v);
+    if (finest && weighted) emit(T_TIME, r, c, p, -(1.0 - theta) * v);
+  };
+  double wq[kMaxQ][3], wg[kMaxQ][kMaxB];
+  for (int q = 0; q < nq; ++q)
+    for (int i = 0; i < D; ++i) {
+      double s = 0;
+      for (int b = 0; b < nb; ++b) s += w[nodes[b] * D + i] * R.phi[q][b];
+      wq[q][i] = s;
+    }
+  for (int q = 0; q < nq; ++q)
+    for (int a = 0; a < nb; ++a) {
+      double s = 0;
+      for (int i = 0; i < D; ++i) s += wq[q][i] * g.G[q][a][i];
+      wg[q][a] = s;
+    }
+  // convection rho (w.grad u, phi)
+  for (int a = 0; a < nb; ++a)
+    for (int b = 0; b < nb; ++b) {
+      double s = 0;
+      for (int q = 0; q < nq; ++q) s += g.dV[q] * R.phi[q][a] * wg[q][b];
+      for (int c = 0; c < D; ++c) madd(dof.rowm[a * D + c], dof.u[b * D + c], P_BASE, rho * s);
+    }
+  if (!ph.supg) return;
+  // lambda_k from the element bubble
+  const int bb = R.bubble;
+  double Mb[3][3] = {}, Nb = 0;
+  for (int q = 0; q < nq; ++q) {
+    double lap = 0;
+    for (int i = 0; i < D; ++i) lap += g.H[q][bb][i][i];
+    double v[3][3];
+    for (int a = 0; a < D; ++a)
+      for (int i = 0; i < D; ++i) v[a][i] = (i == a ? lap : 0.0) + g.H[q][bb][i][a];
+    for (int a = 0; a < D; ++a)
+      for (int b = 0; b < D; ++b) {
+        double s = 0;
+        for (int i = 0; i < D; ++i) s += v[a][i] * v[b][i];
+        Mb[a][b] += g.dV[q] * s;
+      }
+    for (int i = 0; i < D; ++i) Nb += g.dV[q] * g.G[q][bb][i] * g.G[q][bb][i];
+  }
+  const double lam = max_sym_eig(D, Mb) / Nb;
+  const double nu_k = ph.mu / rho;
+  double tw[kMaxQ];
+  for (int q = 0; q < nq; ++q) {
+    double wn = 0;
+    for (int i = 0; i < D; ++i) wn += wq[q][i] * wq[q][i];
+    wn = std::sqrt(wn);
+    const double tau = 1.0 / std::max(4.0 * lam * nu_k, std::sqrt(lam) * wn);
+    tw[q] = g.dV[q] * tau * rho;
+  }
+  for (int a = 0; a < nb; ++a)
+    for (int b = 0; b < nb; ++b) {
+      // the SUPG inertia: its steady part carries theta, its time part
+      // rho/dt phi_b does not
+      double s1s = 0, s1t = 0;
+      for (int q = 0; q < nq; ++q) {
+        s1s += tw[q] * wg[q][a] * rho * wg[q][b];
+        s1t += tw[q] * wg[q][a] * rho * inv_dt * R.phi[q][b];
+      }
+      const double s1 = weighted ? theta * s1s + s1t : s1s + s1t;
+      for (int c = 0; c < D; ++c) {
+        const int64_t r = dof.rowm[a * D + c], col = dof.u[b * D + c];
+        emit(T_OP, r, col, P_BASE, s1);
+        if (finest && weighted) emit(T_TIME, r, col, P_BASE, -(1.0 - theta) * s1s);
+        if (finest && inv_dt != 0.0) emit(T_TIME, r, col, P_BASE, s1t);
+      }
+      if (finest) {   // the SUPG load term rho^2 tau (w.grad phi_a, f)
+        double sl = 0;
+        for (int q = 0; q < nq; ++q) sl += rho * rho * tw[q] * wg[q][a] * R.phi[q][b];
+        for (int c = 0; c < D; ++c)
+          emit(T_LOAD, dof.rowm[a * D + c], (int64_t)D * nodes[b] + c, P_BASE, sl);
+      }
+    }
+  for (int a = 0; a < nb; ++a)
+    for (int c = 0; c < D; ++c)
+      for (int b = 0; b < nb; ++b)
+        for (int f = 0; f < D; ++f) {
+          double s = 0;
+          for (int q = 0; q < nq; ++q) {
+            double lap = 0;
+            if (c == f)
+              for (int i = 0; i < D; ++i) lap += g.H[q][b][i][i];
+            s += tw[q] * wg[q][a] * (lap + g.H[q][b][c][f]);
+          }
+          madd(dof.rowm[a * D + c], dof.u[b * D + f], P_MU, -s);
+        }
+  for (int a = 0; a < nb; ++a)
+    for (int c = 0; c < D; ++c)
+      for (int m = 0; m < np; ++m) {
+        double s = 0;
+        for (int q = 0; q < nq; ++q) s += tw[q] * wg[q][a] * g.Gp[q][m][c];
+        madd(dof.rowm[a * D + c], dof.pf[m], P_BASE, s);
+      }
+}
+
+// Position of entry (r, c) in a CSR pattern (columns sorted per row).
+int64_t slot_of(const CsrHost& P, int64_t r, int64_t c) {
+  const int32_t* b = P.col.data() + P.rowptr[r];
+  const int32_t* en = P.col.data() + P.rowptr[r + 1];
+  const int32_t* it = std::lower_bound(b, en, (int32_t)c);
+  if (it == en || *it != (int32_t)c)
+    throw std::logic_error("an advective term falls outside the operator's pattern");
+  return it - P.col.data();
+}
+
+// Where the advective terms of a level are added.  op: the unreduced
+// pattern and pieces on the finest level (nothing skipped), the reduced
+// ones elsewhere (entries in a Dirichlet row or column skipped: the reduced
+// operator has none); time / load: the finest level's operators with their
+// Dirichlet rows removed.
+struct AdvTargets {
+  const CsrHost* op;
+  std::vector<double>* op_piece;
+  bool op_reduced;
+  const CsrHost* time;
+  std::vector<double>* time_piece;
+  const CsrHost* load;
+  std::vector<double>* load_val;
+};
+
+// Add the advective terms of every fluid element of the level.  Elements
+// are taken colour by colour (the parity of the element's position along
+// each axis: elements of one colour share no node, hence no row) and the
+// elements of a colour on host threads, so every entry receives its
+// contributions in one order whatever the threading.  Every element emits
+// the same number of terms (the branches depend on the physics only), so
+// the value slot of each emission can be recorded once (record) and
+// replayed (replay) instead of searched for.
+void add_advective(const Level& lv, const Physics& ph, const std::vector<double>& w, bool finest,
+                   const AdvTargets& t, std::vector<int32_t>* record,
+                   const std::vector<int32_t>* replay) {
+  const int D = lv.D;
+  const RefElem R(D);
+  const int ncol = 1 << D;
+  std::vector<std::vector<int64_t>> by_colour(ncol);
+  for (int64_t e = 0; e < lv.nE; ++e) {
+    if (lv.region[e] == 1) continue;
+    int ix[kMaxDim] = {0, 0, 0};
+    lv.node_ijk(lv.elem_nodes[e * R.nb], ix);   // the element's first corner, 2 x its position
+    int colour = 0;
+    for (int a = 0; a < D; ++a) colour |= ((ix[a] >> 1) & 1) << a;
+    by_colour[colour].push_back(e);
+  }
+  int64_t nfluid = 0, per = 0;
+  for (const std::vector<int64_t>& list : by_colour) nfluid += (int64_t)list.size();
+  if (nfluid == 0) return;
+  if (record || replay) {   // emissions per element, counted on one element
+    const int64_t e = [&] {
+      for (const std::vector<int64_t>& list : by_colour)
+        if (!list.empty()) return list[0];
+      return (int64_t)0;
+    }();
+    std::unique_ptr<ElemGeo> g(new ElemGeo);
+    ElemDofs dof;
+    element_geometry(R, lv, e, *g);
+    element_dofs(lv, e, R.nb, R.np, dof);
+    advective_terms(R, lv, ph, *g, e, dof, w, finest,
+                    [&](int, int64_t, int64_t, int, double) { ++per; });
+  }
+  if (record) record->assign(nfluid * per, -1);
+  if (replay && (int64_t)replay->size() != nfluid * per)
+    throw std::logic_error("re-assembly slots do not match the level");
+  int64_t base = 0;
+  for (const std::vector<int64_t>& list : by_colour) {
+    parallel_ranges((int64_t)list.size(), 32, [&](int64_t i0, int64_t i1) {
+      std::unique_ptr<ElemGeo> g(new ElemGeo);
+      ElemDofs dof;
+      for (int64_t i = i0; i < i1; ++i) {
+        const int64_t e = list[i];
+        element_geometry(R, lv, e, *g);
+        element_dofs(lv, e, R.nb, R.np, dof);
+        int64_t k = (base + i) * per;
+        if (replay) {
+          const int32_t* sl = replay->data() + k;
+          advective_terms(R, lv, ph, *g, e, dof, w, finest,
+                          [&](int target, int64_t, int64_t, int p, double v) {
+                            const int32_t s = *sl++;
+                            if (s < 0) return;
+                            if (target == T_OP)
+                              t.op_piece[p][s] += v;
+                            else if (target == T_TIME)
+                              t.time_piece[p][s] += v;
+                            else
+                              (*t.load_val)[s] += v;
+                          });
+          continue;
+        }
+        advective_terms(R, lv, ph, *g, e, dof, w, finest,
+                        [&](int target, int64_t r, int64_t c, int p, double v) {
+                          int64_t s = -1;
+                          if (target == T_OP) {
+                            if (!(t.op_reduced && (lv.dir[r] || lv.dir[c]))) {
+                              s = slot_of(*t.op, r, c);
+                              t.op_piece[p][s] += v;
+                            }
+                          } else if (target == T_TIME) {
+                            if (!lv.dir[r]) {
+                              s = slot_of(*t.time, r, c);
+                              t.time_piece[p][s] += v;
+                            }
+                          } else if (!lv.dir[r]) {
+                            s = slot_of(*t.load, r, c);
+                            (*t.load_val)[s] += v;
+                          }
+                          if (record) (*record)[k++] = (int32_t)s;
+                        });
+      }
+    });
+    base += (int64_t)list.size();
+  }
+}
+
+// Copy of a value array on host threads.
+void copy_values(const std::vector<double>& from, std::vector<double>& to) {
+  to.resize(from.size());
+  parallel_ranges((int64_t)from.size(), 1 << 17, [&](int64_t i0, int64_t i1) {
+    std::copy(from.begin() + i0, from.begin() + i1, to.begin() + i0);
+  });
+}
+
+// Reduced operator values (Dirichlet rows and columns removed, unit
+// diagonal) from the unreduced pieces on the pattern already in op.A.
+void reduce_values(const Level& lv, const CsrHost& full, const std::vector<double>* fp,
+                   LevelOperator& op) {
+  const CsrHost& A = op.A;
+  parallel_ranges(lv.N, 4096, [&](int64_t i0, int64_t i1) {
+    for (int64_t i = i0; i < i1; ++i) {
+      int64_t o = A.rowptr[i];
+      if (lv.dir[i]) {
+        op.piece[P_BASE][o] = 1.0;
+        for (int p = 1; p < 4; ++p) op.piece[p][o] = 0.0;
+        continue;
+      }
+      for (int64_t k = full.rowptr[i]; k < full.rowptr[i + 1]; ++k) {
+        if (lv.dir[full.col[k]]) continue;
+        for (int p = 0; p < 4; ++p) op.piece[p][o] = fp[p][k];
+        ++o;
+      }
+    }
+  });
+}
+
+void combine_values(const std::vector<double>* piece, double G, double invlam, double mu,
+                    std::vector<double>& val) {
+  const int64_t n = (int64_t)piece[0].size();
+  val.resize(n);
+  parallel_ranges(n, 1 << 16, [&](int64_t i0, int64_t i1) {
+    for (int64_t k = i0; k < i1; ++k)
+      val[k] = piece[P_BASE][k] + G * piece[P_G][k] + invlam * piece[P_C][k] + mu * piece[P_MU][k];
+  });
+}
+
+// Lift pieces: lift = g on Dirichlet rows, -(A_full g) on free rows.
+void lift_values(const Level& lv, const CsrHost& full, const std::vector<double>* fp,
+                 LevelOperator& op) {
+  for (int p = 0; p < 4; ++p) op.lift_piece[p].assign(lv.N, 0.0);
+  parallel_ranges(lv.N, 4096, [&](int64_t i0, int64_t i1) {
+    for (int64_t i = i0; i < i1; ++i) {
+      if (lv.dir[i]) {
+        op.lift_piece[P_BASE][i] = lv.dir_val[i];
+        continue;
+      }
+      for (int64_t k = full.rowptr[i]; k < full.rowptr[i + 1]; ++k) {
+        const int32_t j = full.col[k];
+        if (!lv.dir[j] || lv.dir_val[j] == 0.0) continue;
+        for (int p = 0; p < 4; ++p) op.lift_piece[p][i] -= fp[p][k] * lv.dir_val[j];
+      }
+    }
+  });
+}
+
+// Rows of an unreduced CSR with the Dirichlet rows removed (every column
+// kept), pattern and npieces value arrays.
+void drop_dirichlet_rows(const Level& lv, const CsrHost& M, const std::vector<double>* mp,
+                         int npieces, CsrHost& out, std::vector<double>* outp) {
+  out.nrows = lv.N;
+  out.ncols = M.ncols;
+  out.rowptr.assign(lv.N + 1, 0);
+  for (int64_t i = 0; i < lv.N; ++i)
+    out.rowptr[i + 1] = out.rowptr[i] + (lv.dir[i] ? 0 : M.rowptr[i + 1] - M.rowptr[i]);
+  const int64_t nnz = out.rowptr[lv.N];
+  out.col.resize(nnz);
+  for (int p = 0; p < npieces; ++p) outp[p].resize(nnz);
+  parallel_ranges(lv.N, 4096, [&](int64_t i0, int64_t i1) {
+    for (int64_t i = i0; i < i1; ++i) {
+      if (lv.dir[i]) continue;
+      int64_t o = out.rowptr[i];
+      for (int64_t k = M.rowptr[i]; k < M.rowptr[i + 1]; ++k, ++o) {
+        out.col[o] = M.col[k];
+        for (int p = 0; p < npieces; ++p) outp[p][o] = mp[p][k];
+      }
+    }
+  });
+}
+
+// Recorded slots are 32-bit: the patterns they index must be shorter than
+// 2^31 entries.
+bool slots_fit(const CsrHost& op, const CsrHost* time, const CsrHost* load) {
+  const int64_t lim = (int64_t)1 << 31;
+  return op.nnz() < lim && (!time || time->nnz() < lim) && (!load || load->nnz() < lim);
+}
+
+}  // namespace
+
 void assemble_level(const Level& lv, const Physics& ph, const std::vector<double>& coarse_vol,
-                    const std::vector<double>* w_level, bool finest, LevelOperator& op) {
+                    const std::vector<double>* w_level, bool finest, LevelOperator& op,
+                    AdvectionPlan* plan) {
   const int D = lv.D;
   RefElem R(D);
   const int nb = R.nb, np = R.np, nq = R.nq, nbD = nb * D;
@@ -363,7 +714,9 @@ void assemble_level(const Level& lv, const Physics& ph, const std::vector<double
   const bool have_w = w_level != nullptr;
 
   // The element loop over [e_begin, e_end) into the given triplet lists
-  // (operator pieces, load operator, time operator).
+  // (operator pieces, load operator, time operator): every term that does
+  // not depend on the advecting velocity, and zero-valued entries where the
+  // advective terms land (they are added later, on the fixed pattern).
   auto run_elements = [&](int64_t e_begin, int64_t e_end, Triplets& T, Triplets& TL,
                           Triplets& TT) {
     // a term that carries 1/dt: into the operator and, on the finest level,
@@ -375,22 +728,21 @@ void assemble_level(const Level& lv, const Physics& ph, const std::vector<double
     // a steady term of a momentum row: theta times v into the operator and,
     // on the finest level, -(1 - theta) v into the time operator (the
     // explicit part of the step)
-    auto madd = [&](int64_t r, int64_t c, int p, double v, bool always) {
-      const double tv = weighted ? theta * v : v;
-      if (always)
-        T.add_always(r, c, p, tv);
-      else
-        T.add(r, c, p, tv);
+    auto madd = [&](int64_t r, int64_t c, int p, double v) {
+      T.add(r, c, p, weighted ? theta * v : v);
       if (finest && weighted) TT.add(r, c, p, -(1.0 - theta) * v);
     };
     ElemGeo g;
+    ElemDofs dof;
     static thread_local double Tg[kMaxB][kMaxB][3][3];
     std::vector<double> Ksym(nbD * nbD), Bdiv(np * nbD), M2(nb * nb), M1(np * np);
-    std::vector<int64_t> dofd(nbD), dofu(nbD), rowm(nbD), dps(np), dpf(np);
     for (int64_t e = e_begin; e < e_end; ++e) {
       element_geometry(R, lv, e, g);
+      element_dofs(lv, e, nb, np, dof);
       const int64_t* nodes = &lv.elem_nodes[e * nb];
-      const int64_t* verts = &lv.elem_verts[e * np];
+      const int64_t* dofd = dof.d;
+      const int64_t* dofu = dof.u;
+      const int64_t* rowm = dof.rowm;
       // T[a][b][i][j] = sum_q dV G_ai G_bj
       for (int a = 0; a < nb; ++a)
         for (int b = 0; b < nb; ++b)
@@ -428,16 +780,7 @@ void assemble_level(const Level& lv, const Physics& ph, const std::vector<double
           for (int q = 0; q < nq; ++q) s += g.dV[q] * R.psi[q][m] * R.psi[q][n];
           M1[m * np + n] = s;
         }
-      for (int a = 0; a < nb; ++a)
-        for (int c = 0; c < D; ++c) {
-          dofd[a * D + c] = (int64_t)D * nodes[a] + c;
-          dofu[a * D + c] = lv.off_u + (int64_t)D * nodes[a] + c;
-        }
       const bool solid = lv.region[e] == 1;
-      // momentum rows: S for solid-side nodes, F for fluid nodes
-      for (int a = 0; a < nb; ++a)
-        for (int c = 0; c < D; ++c)
-          rowm[a * D + c] = lv.solid_side[nodes[a]] ? dofd[a * D + c] : dofu[a * D + c];
 
       // load operator: rho (f_h, phi) on momentum rows, columns = nodal force
       for (int a = 0; a < nb; ++a)
@@ -446,12 +789,12 @@ void assemble_level(const Level& lv, const Physics& ph, const std::vector<double
             if (finest) TL.add(rowm[a * D + c], (int64_t)D * nodes[b] + c, 0, rho * M2[a * nb + b]);
 
       if (solid) {
-        for (int m = 0; m < np; ++m) dps[m] = lv.ps_of_vert[verts[m]];
+        const int64_t* dps = dof.ps;
         for (int r = 0; r < nbD; ++r)
-          for (int s = 0; s < nbD; ++s) madd(dofd[r], dofd[s], P_G, Ksym[r * nbD + s], false);
+          for (int s = 0; s < nbD; ++s) madd(dofd[r], dofd[s], P_G, Ksym[r * nbD + s]);
         for (int m = 0; m < np; ++m)
           for (int r = 0; r < nbD; ++r) {
-            madd(dofd[r], dps[m], P_BASE, -Bdiv[m * nbD + r], false);
+            madd(dofd[r], dps[m], P_BASE, -Bdiv[m * nbD + r]);
             T.add(dps[m], dofd[r], P_BASE, -Bdiv[m * nbD + r]);
           }
         for (int m = 0; m < np; ++m)
@@ -480,12 +823,12 @@ void assemble_level(const Level& lv, const Physics& ph, const std::vector<double
       }
 
       // ---------------- fluid element ----------------
-      for (int m = 0; m < np; ++m) dpf[m] = lv.pf_of_vert[verts[m]];
+      const int64_t* dpf = dof.pf;
       for (int r = 0; r < nbD; ++r)
-        for (int s = 0; s < nbD; ++s) madd(rowm[r], dofu[s], P_MU, Ksym[r * nbD + s], false);
+        for (int s = 0; s < nbD; ++s) madd(rowm[r], dofu[s], P_MU, Ksym[r * nbD + s]);
       for (int m = 0; m < np; ++m)
         for (int r = 0; r < nbD; ++r) {
-          madd(rowm[r], dpf[m], P_BASE, -Bdiv[m * nbD + r], false);
+          madd(rowm[r], dpf[m], P_BASE, -Bdiv[m * nbD + r]);
           T.add(dpf[m], dofu[r], P_BASE, -Bdiv[m * nbD + r]);
         }
       const double kel = ph.ale_k == 0 ? 1.0 / coarse_vol[lv.parent0[e]] : 1.0;
@@ -501,101 +844,12 @@ void assemble_level(const Level& lv, const Physics& ph, const std::vector<double
             for (int c = 0; c < D; ++c)
               tadd(rowm[a * D + c], dofu[b * D + c], rho * inv_dt * M2[a * nb + b]);
       if (!have_w) continue;
-      double wq[kMaxQ][3], wg[kMaxQ][kMaxB];
-      for (int q = 0; q < nq; ++q)
-        for (int i = 0; i < D; ++i) {
-          double s = 0;
-          for (int b = 0; b < nb; ++b) s += (*w_level)[nodes[b] * D + i] * R.phi[q][b];
-          wq[q][i] = s;
-        }
-      for (int q = 0; q < nq; ++q)
-        for (int a = 0; a < nb; ++a) {
-          double s = 0;
-          for (int i = 0; i < D; ++i) s += wq[q][i] * g.G[q][a][i];
-          wg[q][a] = s;
-        }
-      // convection rho (w.grad u, phi)
-      for (int a = 0; a < nb; ++a)
-        for (int b = 0; b < nb; ++b) {
-          double s = 0;
-          for (int q = 0; q < nq; ++q) s += g.dV[q] * R.phi[q][a] * wg[q][b];
-          for (int c = 0; c < D; ++c) madd(rowm[a * D + c], dofu[b * D + c], P_BASE, rho * s, true);
-        }
-      if (!ph.supg) continue;
-      // lambda_k from the element bubble
-      const int bb = R.bubble;
-      double Mb[3][3] = {}, Nb = 0;
-      for (int q = 0; q < nq; ++q) {
-        double lap = 0;
-        for (int i = 0; i < D; ++i) lap += g.H[q][bb][i][i];
-        double v[3][3];
-        for (int a = 0; a < D; ++a)
-          for (int i = 0; i < D; ++i) v[a][i] = (i == a ? lap : 0.0) + g.H[q][bb][i][a];
-        for (int a = 0; a < D; ++a)
-          for (int b = 0; b < D; ++b) {
-            double s = 0;
-            for (int i = 0; i < D; ++i) s += v[a][i] * v[b][i];
-            Mb[a][b] += g.dV[q] * s;
-          }
-        for (int i = 0; i < D; ++i) Nb += g.dV[q] * g.G[q][bb][i] * g.G[q][bb][i];
-      }
-      const double lam = max_sym_eig(D, Mb) / Nb;
-      const double nu_k = ph.mu / rho;
-      double tw[kMaxQ];
-      for (int q = 0; q < nq; ++q) {
-        double wn = 0;
-        for (int i = 0; i < D; ++i) wn += wq[q][i] * wq[q][i];
-        wn = std::sqrt(wn);
-        const double tau = 1.0 / std::max(4.0 * lam * nu_k, std::sqrt(lam) * wn);
-        tw[q] = g.dV[q] * tau * rho;
-      }
-      for (int a = 0; a < nb; ++a)
-        for (int b = 0; b < nb; ++b) {
-          double s1 = 0;
-          if (!weighted) {
-            for (int q = 0; q < nq; ++q) s1 += tw[q] * wg[q][a] * (rho * wg[q][b] + rho * inv_dt * R.phi[q][b]);
-          } else {
-            // only the steady part carries theta
-            double s1s = 0, s1t = 0;
-            for (int q = 0; q < nq; ++q) {
-              s1s += tw[q] * wg[q][a] * rho * wg[q][b];
-              s1t += tw[q] * wg[q][a] * rho * inv_dt * R.phi[q][b];
-            }
-            s1 = theta * s1s + s1t;
-            if (finest)
-              for (int c = 0; c < D; ++c) TT.add(rowm[a * D + c], dofu[b * D + c], 0, -(1.0 - theta) * s1s);
-          }
-          for (int c = 0; c < D; ++c) T.add_always(rowm[a * D + c], dofu[b * D + c], P_BASE, s1);
-          if (finest && inv_dt != 0.0) {   // the SUPG time term of s1, on its own
-            double st = 0;
-            for (int q = 0; q < nq; ++q) st += tw[q] * wg[q][a] * rho * inv_dt * R.phi[q][b];
-            for (int c = 0; c < D; ++c) TT.add(rowm[a * D + c], dofu[b * D + c], 0, st);
-          }
-          double sl = 0;
-          for (int q = 0; q < nq; ++q) sl += rho * rho * tw[q] * wg[q][a] * R.phi[q][b];
-          if (finest)
-            for (int c = 0; c < D; ++c) TL.add(rowm[a * D + c], (int64_t)D * nodes[b] + c, 0, sl);
-        }
-      for (int a = 0; a < nb; ++a)
-        for (int c = 0; c < D; ++c)
-          for (int b = 0; b < nb; ++b)
-            for (int f = 0; f < D; ++f) {
-              double s = 0;
-              for (int q = 0; q < nq; ++q) {
-                double lap = 0;
-                if (c == f)
-                  for (int i = 0; i < D; ++i) lap += g.H[q][b][i][i];
-                s += tw[q] * wg[q][a] * (lap + g.H[q][b][c][f]);
-              }
-              madd(rowm[a * D + c], dofu[b * D + f], P_MU, -s, true);
-            }
-      for (int a = 0; a < nb; ++a)
-        for (int c = 0; c < D; ++c)
-          for (int m = 0; m < np; ++m) {
-            double s = 0;
-            for (int q = 0; q < nq; ++q) s += tw[q] * wg[q][a] * g.Gp[q][m][c];
-            madd(rowm[a * D + c], dpf[m], P_BASE, s, true);
-          }
+      // the pattern of the advective terms, whatever their values (an
+      // entry stays when w vanishes there)
+      advective_terms(R, lv, ph, g, e, dof, *w_level, finest,
+                      [&](int target, int64_t r, int64_t c, int p, double) {
+                        (target == T_OP ? T : (target == T_TIME ? TT : TL)).add_always(r, c, p, 0.0);
+                      });
     }
   };
   // Contiguous element ranges on host threads; their triplets are joined in
@@ -622,7 +876,7 @@ void assemble_level(const Level& lv, const Physics& ph, const std::vector<double
   to_csr(T, lv.N, lv.N, 4, full, fp);
   T = Triplets();
 
-  // reduced operator: Dirichlet rows and columns removed, unit diagonal
+  // reduced pattern: Dirichlet rows and columns removed, unit diagonal
   // (rows counted, then filled, on host threads)
   CsrHost& A = op.A;
   A.nrows = A.ncols = lv.N;
@@ -640,84 +894,93 @@ void assemble_level(const Level& lv, const Physics& ph, const std::vector<double
   for (int64_t i = 0; i < lv.N; ++i) A.rowptr[i + 1] += A.rowptr[i];
   const int64_t annz = A.rowptr[lv.N];
   A.col.assign(annz, 0);
-  for (int p = 0; p < 4; ++p) op.piece[p].assign(annz, 0.0);
-  A.val.assign(annz, 0.0);
   parallel_ranges(lv.N, 4096, [&](int64_t i0, int64_t i1) {
     for (int64_t i = i0; i < i1; ++i) {
       int64_t o = A.rowptr[i];
       if (lv.dir[i]) {
         A.col[o] = (int32_t)i;
-        op.piece[P_BASE][o] = 1.0;
-      } else {
-        for (int64_t k = full.rowptr[i]; k < full.rowptr[i + 1]; ++k) {
-          if (lv.dir[full.col[k]]) continue;
-          A.col[o] = full.col[k];
-          for (int p = 0; p < 4; ++p) op.piece[p][o] = fp[p][k];
-          ++o;
-        }
-      }
-      for (int64_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k)
-        A.val[k] = op.piece[P_BASE][k] + Gmod * op.piece[P_G][k] + invlam * op.piece[P_C][k] +
-                   ph.mu * op.piece[P_MU][k];
-    }
-  });
-
-  if (finest) {
-    // lift pieces: lift = g on Dirichlet rows, -(A_full g) on free rows
-    for (int p = 0; p < 4; ++p) op.lift_piece[p].assign(lv.N, 0.0);
-    for (int64_t i = 0; i < lv.N; ++i) {
-      if (lv.dir[i]) {
-        op.lift_piece[P_BASE][i] = lv.dir_val[i];
         continue;
       }
-      for (int64_t k = full.rowptr[i]; k < full.rowptr[i + 1]; ++k) {
-        const int32_t j = full.col[k];
-        if (!lv.dir[j] || lv.dir_val[j] == 0.0) continue;
-        for (int p = 0; p < 4; ++p) op.lift_piece[p][i] -= fp[p][k] * lv.dir_val[j];
+      for (int64_t k = full.rowptr[i]; k < full.rowptr[i + 1]; ++k)
+        if (!lv.dir[full.col[k]]) A.col[o++] = full.col[k];
+    }
+  });
+  for (int p = 0; p < 4; ++p) op.piece[p].resize(annz);
+
+  if (finest) {
+    // load and time operators with their Dirichlet rows removed (the time
+    // operator keeps every column: the previous state carries the previous
+    // Dirichlet data; its affine pieces are the operator's when theta < 1:
+    // the explicit part carries G and mu)
+    {
+      CsrHost L;
+      std::vector<double> lp[4];
+      to_csr(TL, lv.N, (int64_t)D * lv.N2, 1, L, lp);
+      TL = Triplets();
+      drop_dirichlet_rows(lv, L, lp, 1, op.load, &op.load.val);
+    }
+    {
+      CsrHost Tc;
+      std::vector<double> tp[4];
+      to_csr(TT, lv.N, lv.N, 4, Tc, tp);
+      TT = Triplets();
+      drop_dirichlet_rows(lv, Tc, tp, 4, op.time, op.time_piece);
+    }
+    if (have_w) {
+      if (plan) {
+        for (int p = 0; p < 4; ++p) {
+          plan->stat[p] = fp[p];
+          plan->tstat[p] = op.time_piece[p];
+        }
+        plan->lstat = op.load.val;
       }
+      add_advective(lv, ph, *w_level, true,
+                    AdvTargets{&full, fp, false, &op.time, op.time_piece, &op.load, &op.load.val},
+                    plan && slots_fit(full, &op.time, &op.load) ? &plan->slots : nullptr, nullptr);
     }
-    // load operator with Dirichlet rows removed
-    CsrHost L;
-    std::vector<double> lp[4];
-    to_csr(TL, lv.N, (int64_t)D * lv.N2, 1, L, lp);
-    op.load.nrows = lv.N;
-    op.load.ncols = (int64_t)D * lv.N2;
-    op.load.rowptr.assign(lv.N + 1, 0);
-    op.load.col.clear();
-    op.load.val.clear();
-    for (int64_t i = 0; i < lv.N; ++i) {
-      if (!lv.dir[i])
-        for (int64_t k = L.rowptr[i]; k < L.rowptr[i + 1]; ++k) {
-          op.load.col.push_back(L.col[k]);
-          op.load.val.push_back(lp[0][k]);
-        }
-      op.load.rowptr[i + 1] = (int64_t)op.load.col.size();
-    }
-    // time operator with Dirichlet rows removed (every column kept: the
-    // previous state carries the previous Dirichlet data)
-    // (affine pieces like the operator's when theta < 1: the explicit part
-    // carries G and mu)
-    CsrHost Tc;
-    std::vector<double> tp[4];
-    to_csr(TT, lv.N, lv.N, 4, Tc, tp);
-    op.time.nrows = op.time.ncols = lv.N;
-    op.time.rowptr.assign(lv.N + 1, 0);
-    op.time.col.clear();
-    op.time.val.clear();
-    for (int p = 0; p < 4; ++p) op.time_piece[p].clear();
-    for (int64_t i = 0; i < lv.N; ++i) {
-      if (!lv.dir[i])
-        for (int64_t k = Tc.rowptr[i]; k < Tc.rowptr[i + 1]; ++k) {
-          op.time.col.push_back(Tc.col[k]);
-          for (int p = 0; p < 4; ++p) op.time_piece[p].push_back(tp[p][k]);
-          op.time.val.push_back(tp[P_BASE][k] + Gmod * tp[P_G][k] + invlam * tp[P_C][k] +
-                                ph.mu * tp[P_MU][k]);
-        }
-      op.time.rowptr[i + 1] = (int64_t)op.time.col.size();
-    }
+    reduce_values(lv, full, fp, op);
+    lift_values(lv, full, fp, op);
+    combine_values(op.time_piece, Gmod, invlam, ph.mu, op.time.val);
     op.full = std::move(full);
     for (int p = 0; p < 4; ++p) op.full_piece[p] = std::move(fp[p]);
+  } else {
+    reduce_values(lv, full, fp, op);
+    if (have_w) {
+      if (plan)
+        for (int p = 0; p < 4; ++p) plan->stat[p] = op.piece[p];
+      add_advective(lv, ph, *w_level, false,
+                    AdvTargets{&op.A, op.piece, true, nullptr, nullptr, nullptr, nullptr},
+                    plan && slots_fit(op.A, nullptr, nullptr) ? &plan->slots : nullptr, nullptr);
+    }
   }
+  combine_values(op.piece, Gmod, invlam, ph.mu, A.val);
+  if (plan) plan->ready = have_w;
+}
+
+void reassemble_level(const Level& lv, const Physics& ph, const AdvectionPlan& plan,
+                      const std::vector<double>& w_level, bool finest, LevelOperator& op) {
+  if (!plan.ready) throw std::logic_error("no re-assembly plan for this level");
+  const std::vector<int32_t>* replay = plan.slots.empty() ? nullptr : &plan.slots;
+  if (finest) {
+    for (int p = 0; p < 4; ++p) {
+      copy_values(plan.stat[p], op.full_piece[p]);
+      copy_values(plan.tstat[p], op.time_piece[p]);
+    }
+    copy_values(plan.lstat, op.load.val);
+    add_advective(lv, ph, w_level, true,
+                  AdvTargets{&op.full, op.full_piece, false, &op.time, op.time_piece, &op.load,
+                             &op.load.val},
+                  nullptr, replay);
+    reduce_values(lv, op.full, op.full_piece, op);
+    lift_values(lv, op.full, op.full_piece, op);
+    combine_values(op.time_piece, op.G, op.invlam, op.mu, op.time.val);
+  } else {
+    for (int p = 0; p < 4; ++p) copy_values(plan.stat[p], op.piece[p]);
+    add_advective(lv, ph, w_level, false,
+                  AdvTargets{&op.A, op.piece, true, nullptr, nullptr, nullptr, nullptr}, nullptr,
+                  replay);
+  }
+  combine_values(op.piece, op.G, op.invlam, op.mu, op.A.val);
 }
 
 }  // namespace fsgmg

@@ -81,10 +81,36 @@ struct Physics {
 
 void lame(double E, double nu, double& G, double& invlam);
 
+// What re-assembling a level about a new advecting velocity needs: the sums
+// of every term that does not depend on it, on the patterns the advective
+// terms (convection and SUPG) are added to.  Those patterns hold every
+// entry an advective term can reach, whatever the velocity, so they are
+// fixed.  stat: the unreduced pieces on the finest level, the reduced ones
+// elsewhere; tstat / lstat: the finest level's time and load operators
+// (Dirichlet rows removed); slots: the value slot (-1: none) of every
+// advective term in the order the elements emit them.
+struct AdvectionPlan {
+  std::vector<double> stat[4];
+  std::vector<double> tstat[4];
+  std::vector<double> lstat;
+  std::vector<int32_t> slots;
+  bool ready = false;
+};
+
 // Assemble level `lv` (finest = true also keeps unreduced pieces, lift and
-// load operator).  coarse_vol: level-0 element volumes (ALE k = 1/V).
+// load operator).  coarse_vol: level-0 element volumes (ALE k = 1/V).  The
+// advective terms are added after the others, element colour by element
+// colour, into the fixed pattern; plan != nullptr keeps what
+// reassemble_level needs.
 void assemble_level(const Level& lv, const Physics& ph, const std::vector<double>& coarse_vol,
-                    const std::vector<double>* w_level, bool finest, LevelOperator& op);
+                    const std::vector<double>* w_level, bool finest, LevelOperator& op,
+                    AdvectionPlan* plan = nullptr);
+
+// The values of `op` (assembled by assemble_level with this plan, patterns
+// kept) about a new advecting velocity w_level: equal, bit for bit, to what
+// assemble_level gives about it.
+void reassemble_level(const Level& lv, const Physics& ph, const AdvectionPlan& plan,
+                      const std::vector<double>& w_level, bool finest, LevelOperator& op);
 
 std::vector<double> element_volumes(const Level& lv);
 

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <functional>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -326,6 +327,10 @@ struct fsgmg_hierarchy {
   // host setup data
   std::vector<Level> levels;
   std::vector<LevelOperator> ops;
+  // re-assembly about a new advecting velocity (built at the first one)
+  std::vector<AdvectionPlan> plans;
+  std::vector<int64_t> loadT_perm;   // entry of the load operator at each transpose entry
+  std::vector<double> loadT_host;
   std::vector<Transfer> tr;      // tr[l] for l >= 1
   std::vector<BlockSet> blocks;  // blocks[l] for l >= 1
   bool have_blocks = false;      // index sets built
@@ -857,11 +862,23 @@ void ensure_bd(fsgmg_hierarchy& h) {
   h.bd_dirty = false;
 }
 
+// Entry of A at each position of its transpose as csr_transpose orders it
+// (rows ascending within each column).
+std::vector<int64_t> transpose_order(const CsrHost& A) {
+  std::vector<int64_t> cur(A.ncols + 1, 0);
+  for (int64_t k = 0; k < A.nnz(); ++k) cur[A.col[k] + 1]++;
+  for (int64_t j = 0; j < A.ncols; ++j) cur[j + 1] += cur[j];
+  std::vector<int64_t> perm(A.nnz());
+  for (int64_t i = 0; i < A.nrows; ++i)
+    for (int64_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k) perm[cur[A.col[k]]++] = k;
+  return perm;
+}
+
 // The finest level's load operator (and its transpose) and time operator,
-// whose patterns follow the advecting velocity (SUPG terms vanish where it
-// does): replaced as a whole on every upload.
+// patterns and values.
 void upload_load_and_time(fsgmg_hierarchy& h) {
   const LevelOperator& op = h.ops[h.L - 1];
+  h.loadT_perm = transpose_order(op.load);
   for (void* p : {(void*)h.load_rp, (void*)h.load_col, (void*)h.load_val, (void*)h.loadT_rp,
                   (void*)h.loadT_col, (void*)h.loadT_val, (void*)h.time_rp, (void*)h.time_col,
                   (void*)h.time_val})
@@ -883,6 +900,27 @@ void upload_load_and_time(fsgmg_hierarchy& h) {
     h.time_col = h.upload(op.time.col);
     h.time_val = h.upload(op.time.val);
     for (int p = 0; p < 4; ++p) h.time_piece[p] = h.upload(op.time_piece[p]);
+  }
+}
+
+// Their values only, on the patterns already on the device (re-assembly
+// about a new advecting velocity keeps every pattern).  Asynchronous; the
+// host staging stays valid until the next call.
+void refresh_load_and_time(fsgmg_hierarchy& h) {
+  const LevelOperator& op = h.ops[h.L - 1];
+  HIPCHECK(hipMemcpyAsync(h.load_val, op.load.val.data(), op.load.val.size() * sizeof(double),
+                          hipMemcpyHostToDevice, h.stream));
+  h.loadT_host.resize(h.loadT_perm.size());
+  for (size_t j = 0; j < h.loadT_perm.size(); ++j) h.loadT_host[j] = op.load.val[h.loadT_perm[j]];
+  HIPCHECK(hipMemcpyAsync(h.loadT_val, h.loadT_host.data(), h.loadT_host.size() * sizeof(double),
+                          hipMemcpyHostToDevice, h.stream));
+  if (h.time_val) {
+    const size_t n = op.time.val.size();
+    HIPCHECK(hipMemcpyAsync(h.time_val, op.time.val.data(), n * sizeof(double),
+                            hipMemcpyHostToDevice, h.stream));
+    for (int p = 0; p < 4; ++p)
+      HIPCHECK(hipMemcpyAsync(h.time_piece[p], op.time_piece[p].data(), n * sizeof(double),
+                              hipMemcpyHostToDevice, h.stream));
   }
 }
 
@@ -2358,35 +2396,33 @@ static fsgmg_status build_fs_as_blocks_impl(fsgmg_h h, const fsgmg_smoother_opts
 
 extern "C" {
 
-// Assemble every level operator about the handle's physics and finest-level
-// advecting velocity (injected at each level's nodes: the meshes are nested
-// and Q2 nodes of a coarse level are nodes of every finer one); the levels
-// are independent and are assembled on one host thread each.
-static void assemble_all(fsgmg_hierarchy& h, std::vector<LevelOperator>& ops) {
+// The finest-level advecting velocity injected at the nodes of level l.
+static std::vector<double> level_velocity(const fsgmg_hierarchy& h, int l) {
   const Level& Fl = h.levels[h.L - 1];
-  const std::vector<double> cvol = element_volumes(h.levels[0]);
-  ops.clear();
-  ops.resize(h.L);
+  const Level& lv = h.levels[l];
+  std::vector<double> wl;
+  if (h.w_finest.empty()) return wl;
+  const int step = 1 << (h.L - 1 - l);
+  wl.resize(lv.N2 * h.D);
+  for (int64_t n = 0; n < lv.N2; ++n) {
+    int ix[kMaxDim] = {0, 0, 0};
+    lv.node_ijk(n, ix);
+    int fx[kMaxDim] = {0, 0, 0};
+    for (int a = 0; a < h.D; ++a) fx[a] = ix[a] * step;
+    const int64_t fn = Fl.node_index(fx);
+    for (int c = 0; c < h.D; ++c) wl[n * h.D + c] = h.w_finest[fn * h.D + c];
+  }
+  return wl;
+}
+
+// Run f(l) for every level, one host thread each.
+static void for_levels(int L, const std::function<void(int)>& f) {
   std::vector<std::thread> pool;
-  std::vector<std::exception_ptr> errs(h.L);
-  for (int l = 0; l < h.L; ++l)
+  std::vector<std::exception_ptr> errs(L);
+  for (int l = 0; l < L; ++l)
     pool.emplace_back([&, l]() {
       try {
-        const Level& lv = h.levels[l];
-        std::vector<double> wl;
-        if (!h.w_finest.empty()) {
-          const int step = 1 << (h.L - 1 - l);
-          wl.resize(lv.N2 * h.D);
-          for (int64_t n = 0; n < lv.N2; ++n) {
-            int ix[kMaxDim] = {0, 0, 0};
-            lv.node_ijk(n, ix);
-            int fx[kMaxDim] = {0, 0, 0};
-            for (int a = 0; a < h.D; ++a) fx[a] = ix[a] * step;
-            const int64_t fn = Fl.node_index(fx);
-            for (int c = 0; c < h.D; ++c) wl[n * h.D + c] = h.w_finest[fn * h.D + c];
-          }
-        }
-        assemble_level(lv, h.phys, cvol, wl.empty() ? nullptr : &wl, l == h.L - 1, ops[l]);
+        f(l);
       } catch (...) {
         errs[l] = std::current_exception();
       }
@@ -2394,6 +2430,36 @@ static void assemble_all(fsgmg_hierarchy& h, std::vector<LevelOperator>& ops) {
   for (std::thread& t : pool) t.join();
   for (const std::exception_ptr& e : errs)
     if (e) std::rethrow_exception(e);
+}
+
+// Assemble every level operator about the handle's physics and finest-level
+// advecting velocity (injected at each level's nodes: the meshes are nested
+// and Q2 nodes of a coarse level are nodes of every finer one); the levels
+// are independent and are assembled on one host thread each.  plans !=
+// nullptr also keeps each level's re-assembly plan.
+static void assemble_all(fsgmg_hierarchy& h, std::vector<LevelOperator>& ops,
+                         std::vector<AdvectionPlan>* plans = nullptr) {
+  const std::vector<double> cvol = element_volumes(h.levels[0]);
+  ops.clear();
+  ops.resize(h.L);
+  if (plans) {
+    plans->clear();
+    plans->resize(h.L);
+  }
+  for_levels(h.L, [&](int l) {
+    const std::vector<double> wl = level_velocity(h, l);
+    assemble_level(h.levels[l], h.phys, cvol, wl.empty() ? nullptr : &wl, l == h.L - 1, ops[l],
+                   plans ? &(*plans)[l] : nullptr);
+  });
+}
+
+// Re-assemble the values of every level operator in place about the
+// handle's current advecting velocity, from the plans.
+static void reassemble_all(fsgmg_hierarchy& h) {
+  for_levels(h.L, [&](int l) {
+    reassemble_level(h.levels[l], h.phys, h.plans[l], level_velocity(h, l), l == h.L - 1,
+                     h.ops[l]);
+  });
 }
 
 fsgmg_status setup_hierarchy(const fsgmg_mesh_desc* mesh, const fsgmg_physics* phys,
@@ -2803,32 +2869,52 @@ static void upload_operator_values(fsgmg_hierarchy& h) {
   HIPCHECK(hipStreamSynchronize(h.stream));
 }
 
+static bool same_pattern(const CsrHost& a, const CsrHost& b) {
+  return a.rowptr == b.rowptr && a.col == b.col;
+}
+
 // Re-assemble every level about the advecting velocity w = the velocity
-// part of the finest-level device vector x (the Picard step of the
-// nonlinear loop): operators, lift, load and time operators.  The blocks
-// and the coarse inverse follow as after update_params.
+// part of the finest-level vector x (the Picard step of the nonlinear
+// loop): operators, lift, load and time operators.  The first call keeps a
+// plan per level (the sums of the terms that do not depend on w); later
+// calls add only the advective terms to them, on the fixed patterns, and
+// upload values only.  The blocks and the coarse inverse follow as after
+// update_params.
 static void reassemble_about(fsgmg_hierarchy& h, const double* x) {
   const Level& F = h.levels[h.L - 1];
   const size_t nw = (size_t)F.N2 * h.D;
-  HIPCHECK(hipMemcpyAsync(h.w_finest.data(), x + F.off_u, nw * sizeof(double),
-                          hipMemcpyDeviceToHost, h.stream));
-  HIPCHECK(hipStreamSynchronize(h.stream));
+  if (h.host_only()) {
+    std::memcpy(h.w_finest.data(), x + F.off_u, nw * sizeof(double));
+  } else {
+    HIPCHECK(hipMemcpyAsync(h.w_finest.data(), x + F.off_u, nw * sizeof(double),
+                            hipMemcpyDeviceToHost, h.stream));
+    HIPCHECK(hipStreamSynchronize(h.stream));
+  }
   for (double v : h.w_finest)
     if (!std::isfinite(v)) throw Fail{FSGMG_EINVAL, "the velocity contains NaN or Inf"};
-  std::vector<LevelOperator> ops;
-  assemble_all(h, ops);
-  for (int l = 0; l < h.L; ++l)
-    if (ops[l].A.rowptr != h.ops[l].A.rowptr || ops[l].A.col != h.ops[l].A.col)
+  if (h.plans.size() != (size_t)h.L) {
+    std::vector<LevelOperator> ops;
+    std::vector<AdvectionPlan> plans;
+    assemble_all(h, ops, &plans);
+    const LevelOperator &Fo = h.ops[h.L - 1], &Fn = ops[h.L - 1];
+    for (int l = 0; l < h.L; ++l)
+      if (!same_pattern(ops[l].A, h.ops[l].A))
+        throw Fail{FSGMG_ESTATE, "operator pattern changed with the advecting velocity"};
+    if (!same_pattern(Fn.full, Fo.full) || !same_pattern(Fn.load, Fo.load) ||
+        !same_pattern(Fn.time, Fo.time))
       throw Fail{FSGMG_ESTATE, "operator pattern changed with the advecting velocity"};
-  if (ops[h.L - 1].full.col != h.ops[h.L - 1].full.col)
-    throw Fail{FSGMG_ESTATE, "operator pattern changed with the advecting velocity"};
-  h.ops = std::move(ops);
+    h.ops = std::move(ops);
+    h.plans = std::move(plans);
+  } else {
+    reassemble_all(h);
+  }
   h.host_vals_stale = false;
-  upload_operator_values(h);
-  upload_load_and_time(h);
   h.factors_valid = false;
   // the multiplicative colouring reads the operator's values: recolour
   if (h.sopt.schwarz == FSGMG_SCHWARZ_MULTIPLICATIVE) h.have_blocks = false;
+  if (h.host_only()) return;
+  refresh_load_and_time(h);
+  upload_operator_values(h);
   if (!h.bd.empty()) h.bd_dirty = true;
   if (h.dl[0].use_bd) ensure_bd(h);
   build_coarse_inverse(h, true);
@@ -2837,7 +2923,6 @@ static void reassemble_about(fsgmg_hierarchy& h, const double* x) {
 fsgmg_status update_advection(fsgmg_h h, const double* x) {
   if (!h || !x) return FSGMG_EINVAL;
   return guarded(h, [&]() -> fsgmg_status {
-    check_device(*h);
     if (h->w_finest.empty())
       throw Fail{FSGMG_EINVAL, "the hierarchy was set up without an advecting velocity"};
     reassemble_about(*h, x);

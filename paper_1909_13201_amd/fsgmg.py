@@ -596,8 +596,17 @@ class Hierarchy:
         self.cfg.update(E=float(E), mu=float(mu))
 
     def update_advection(self, x):
-        """Picard step: re-assemble every level about the velocity part of x."""
+        """Picard step: re-assemble every level about the velocity part of x
+        (a float64 device tensor; a float64 numpy array of N entries on a
+        host-only handle)."""
         self.built_key = None
+        if self.device < 0:
+            import numpy as np
+            if not (isinstance(x, np.ndarray) and x.dtype == np.float64 and x.shape == (self.N,)
+                    and x.flags.c_contiguous):
+                raise TypeError("expected a contiguous float64 array of %d entries" % self.N)
+            _check(self.h, lib().update_advection(self.h, x.ctypes.data_as(C.c_void_p)))
+            return
         _check(self.h, lib().update_advection(self.h, _ptr(self._vec(x))))
 
     def time_rhs(self, f, g, x_prev, b):

@@ -177,6 +177,62 @@ def test_theta_scheme_operators_match_oracle():
         H.close()
 
 
+def _same_csr(a, b):
+    return (np.array_equal(a.indptr, b.indptr) and np.array_equal(a.indices, b.indices)
+            and np.array_equal(a.data, b.data))
+
+
+@pytest.mark.parametrize("name,L,theta", [("c5", 2, 1.0), ("c5", 3, 0.5), ("c4", 2, 1.0)])
+def test_update_advection_reassembly(name, L, theta):
+    """Picard re-assembly on a host-only handle (Section 2.2's nonlinear
+    loop).  update_advection about a new velocity keeps the sums of the
+    velocity-independent terms and adds only the convection and SUPG terms,
+    so every exported operator (each level's A, the finest load and time
+    operators, the Dirichlet lift) equals a fresh setup about that velocity
+    bit for bit, call after call; and the oracle's operators about it."""
+    from oracle.mesh import hierarchy_levels
+    from oracle.timeloop import velocity_field
+    cfg = dict(inputs.with_levels(inputs.config(name), L), theta=theta)
+    H = fsgmg.Hierarchy(cfg, inputs.advecting_field(cfg), device=-1)
+    lvf = hierarchy_levels(cfg)[-1]
+    rng = np.random.default_rng(7)
+    try:
+        for call in range(3):
+            x = rng.standard_normal(H.N) * (0.5 + call)
+            H.update_advection(x)
+            w = velocity_field(lvf, x).copy()
+            G = fsgmg.Hierarchy(cfg, w, device=-1)
+            try:
+                for l in range(H.L):
+                    assert _same_csr(H.csr(l, 0), G.csr(l, 0)), (call, l)
+                finest = [3] + ([4] if "dt" in cfg else [])
+                for which in finest:
+                    assert _same_csr(H.csr(H.L - 1, which), G.csr(H.L - 1, which)), (call, which)
+                assert np.array_equal(fsgmg.export_vector(H.h, H.L - 1, 0),
+                                      fsgmg.export_vector(G.h, G.L - 1, 0))
+            finally:
+                G.close()
+        O = OracleHierarchy(cfg, w, build_smoothers=False)
+        for l in range(H.L):
+            assert _rel(H.csr(l, 0), O.A[l]) < 1e-13
+        keep = sp.diags((~O.finest.dir_mask).astype(np.float64))
+        if "dt" in cfg:
+            assert _rel(H.csr(H.L - 1, 4), (keep @ O.parts[-1]["Tx"]).tocsr()) < 1e-13
+        # E and mu after a re-assembly: the pieces stay affine (tau frozen)
+        H.update_params(2.0e4, 5.0e-3)
+        O2 = OracleHierarchy(dict(cfg, E=2.0e4, mu=5.0e-3), w, taus=[p["tau"] for p in O.parts],
+                             build_smoothers=False)
+        assert _rel(H.csr(H.L - 1, 0), O2.A[-1]) < 1e-13
+    finally:
+        H.close()
+    with pytest.raises(TypeError):
+        Hs = fsgmg.Hierarchy(cfg, inputs.advecting_field(cfg), device=-1)
+        try:
+            Hs.update_advection(np.zeros(3))
+        finally:
+            Hs.close()
+
+
 def test_transfers_match_oracle(pair):
     cfg, w, H, O = pair
     for l in range(1, H.L):
