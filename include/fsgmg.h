@@ -363,11 +363,11 @@ fsgmg_status update_params(fsgmg_h h, double E, double mu);
  * (E, mu).  Host assembly (one thread per level) and upload of values; the
  * operators' patterns do not change.  The first call keeps, per level, the
  * sums of the terms that do not depend on w (host memory of four values
- * per operator entry and a 32-bit slot per advective term); every call then adds only the convection and
- * SUPG terms, element colour by element colour, so the values equal a
- * fresh setup's about the same w bit for bit.  Invalidates the blocks (call
- * build_fs_as_blocks again) and rebuilds the coarse inverse as
- * update_params does.  EINVAL for a hierarchy set up without an advecting
+ * per operator entry and a 32-bit slot per advective term); every call
+ * then adds only the convection and SUPG terms, element colour by element
+ * colour, so the values equal a fresh setup's about the same w bit for
+ * bit.  Invalidates the blocks (call build_fs_as_blocks again) and
+ * rebuilds the coarse inverse as update_params does.  EINVAL for a hierarchy set up without an advecting
  * velocity (physics.w = NULL) or a velocity with NaN / Inf. */
 fsgmg_status update_advection(fsgmg_h h, const double* x);
 
