@@ -704,6 +704,7 @@ __global__ __launch_bounds__(kThreads) void k_smooth_t2(BlocksView B, const TV* 
 // matrix is blockdiag(A[I_j, I_j], I) and its inverse carries A[I_j, I_j]^-1
 // in the leading n x n corner.
 __device__ inline int pad16(int n) { return (n + 15) & ~15; }
+__host__ __device__ constexpr size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
 // The block's sorted index list is staged in LDS for the column searches.
 // Each wavefront then assembles one row at a time in an LDS row of its own
@@ -842,8 +843,177 @@ constexpr int kInvThreads = 256;  // workgroup of the panel factorization
 constexpr int kOuterPanel = 64;   // columns per outer panel
 constexpr int kTrailThreads = 256;   // workgroup of the trailing update (four row tiles)
 
-template <typename TF, int NB, int NO>
-__global__ __launch_bounds__(kInvThreads, sizeof(TF) == 4 ? 4 : 2) void k_invert_panel(
+// The NB pivot steps of one strip with its rows in registers: thread t
+// holds rows t + kInvThreads i (i < R), loaded from the LDS strip T and
+// stored back into it at the end.  A step's pivot search reduces within each
+// wavefront; the winning lane of each wavefront publishes its row and the
+// owner of row c publishes row c, so after the step's single barrier every
+// thread picks the pivot among the NW wavefront winners (largest magnitude,
+// smallest row on ties) and reads the pivot row and row c from LDS (two
+// alternating sets: a set is rewritten two steps later, after a barrier
+// every reader has passed).  Same arithmetic, and the same pivots, as the
+// LDS form.  Returns false at a zero pivot (the same decision in every
+// thread).
+template <typename TF, int NB, int R>
+__device__ bool pivot_steps_registers(TF* T, int LDT, TF* Rs, TF* wv2, int* wi2, int* piv,
+                                      int32_t* sg, int np, int k0) {
+  constexpr int NW = kInvThreads / 64;
+  using vec_t = typename std::conditional<sizeof(TF) == 8, double2, float4>::type;
+  constexpr int VW = 16 / sizeof(TF);
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  TF rw[R][NB];
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int r = tid + kInvThreads * i;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) rw[i][q] = r < np ? T[r * LDT + q] : TF(0);
+  }
+  // pivot candidates of the strip's first column; every later column's
+  // candidates are taken by the elimination of the step before it
+  TF best = TF(-1);
+  int bi = np;
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int r = tid + kInvThreads * i;
+    if (r >= k0 && r < np && fabs(rw[i][0]) > best) {
+      best = fabs(rw[i][0]);
+      bi = r;
+    }
+  }
+#pragma unroll
+  for (int kk = 0; kk < NB; ++kk) {
+    const int c = k0 + kk;
+    const int par = kk & 1;
+    TF* rows = Rs + par * (NW + 1) * NB;   // NW wavefront winners, then row c
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const TF v2 = __shfl_xor(best, off, 64);
+      const int i2 = __shfl_xor(bi, off, 64);
+      if (v2 > best || (v2 == best && i2 < bi)) {
+        best = v2;
+        bi = i2;
+      }
+    }
+    if (bi < np && bi % kInvThreads == tid) {
+#pragma unroll
+      for (int i = 0; i < R; ++i)
+        if (i == bi / kInvThreads)
+#pragma unroll
+          for (int q = 0; q < NB; q += VW) {
+            vec_t v;
+            if constexpr (VW == 4) {
+              v.x = rw[i][q], v.y = rw[i][q + 1], v.z = rw[i][q + 2], v.w = rw[i][q + 3];
+            } else {
+              v.x = rw[i][q], v.y = rw[i][q + 1];
+            }
+            *reinterpret_cast<vec_t*>(rows + wv * NB + q) = v;
+          }
+    }
+    if (c % kInvThreads == tid) {
+#pragma unroll
+      for (int i = 0; i < R; ++i)
+        if (i == c / kInvThreads)
+#pragma unroll
+          for (int q = 0; q < NB; q += VW) {
+            vec_t v;
+            if constexpr (VW == 4) {
+              v.x = rw[i][q], v.y = rw[i][q + 1], v.z = rw[i][q + 2], v.w = rw[i][q + 3];
+            } else {
+              v.x = rw[i][q], v.y = rw[i][q + 1];
+            }
+            *reinterpret_cast<vec_t*>(rows + NW * NB + q) = v;
+          }
+    }
+    if (lane == 0) {
+      wv2[par * NW + wv] = best;
+      wi2[par * NW + wv] = bi;
+    }
+    __syncthreads();
+    best = wv2[par * NW];
+    bi = wi2[par * NW];
+    int ws = 0;
+#pragma unroll
+    for (int w = 1; w < NW; ++w) {
+      const TF bw = wv2[par * NW + w];
+      const int iw = wi2[par * NW + w];
+      if (bw > best || (bw == best && iw < bi)) {
+        best = bw;
+        bi = iw;
+        ws = w;
+      }
+    }
+    if (!(best > TF(0))) return false;
+    const int p = bi;
+    if (tid == 0) {
+      piv[kk] = p;
+      sg[c] = p;
+    }
+    // the interchange and the elimination in one pass: position c receives
+    // the scaled pivot row, position p the eliminated old row c, every other
+    // row is eliminated in place
+    const TF* prow = rows + ws * NB;
+    const TF d = TF(1) / prow[kk];
+    TF rc[NB];
+#pragma unroll
+    for (int q = 0; q < NB; q += VW) put_vec(rc + q, *reinterpret_cast<const vec_t*>(prow + q));
+#pragma unroll
+    for (int q = 0; q < NB; ++q) rc[q] = (q == kk) ? d : rc[q] * d;
+    // every row eliminated alike (rows c and p are then replaced by their
+    // owners); the pivot candidates for column kk + 1 among the rows below
+    // c, ties to the smaller row
+    best = TF(-1);
+    bi = np;
+    const int kn = kk + 1 < NB ? kk + 1 : kk;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int r = tid + kInvThreads * i;
+      const TF t = rw[i][kk];
+#pragma unroll
+      for (int q = 0; q < NB; ++q) rw[i][q] = (q == kk ? TF(0) : rw[i][q]) - t * rc[q];
+      const TF vn = fabs(rw[i][kn]);
+      if (r > c && r != p && r < np && vn > best) {
+        best = vn;
+        bi = r;
+      }
+    }
+    if (c % kInvThreads == tid) {   // row c: the scaled pivot row
+#pragma unroll
+      for (int i = 0; i < R; ++i)
+        if (i == c / kInvThreads)
+#pragma unroll
+          for (int q = 0; q < NB; ++q) rw[i][q] = rc[q];
+    }
+    if (p != c && p % kInvThreads == tid) {   // row p: the eliminated old row c
+      const TF* crow = rows + NW * NB;
+      const TF ck = crow[kk];
+#pragma unroll
+      for (int i = 0; i < R; ++i)
+        if (i == p / kInvThreads) {
+#pragma unroll
+          for (int q = 0; q < NB; ++q) rw[i][q] = (q == kk ? TF(0) : crow[q]) - ck * rc[q];
+          const TF vn = fabs(rw[i][kn]);
+          if (p > c && (vn > best || (vn == best && p < bi))) {
+            best = vn;
+            bi = p;
+          }
+        }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int r = tid + kInvThreads * i;
+    if (r < np)
+#pragma unroll
+      for (int q = 0; q < NB; ++q) T[r * LDT + q] = rw[i][q];
+  }
+  return true;
+}
+
+// R > 0: the strip's rows live in registers during the pivot steps (thread
+// t owns rows t + kInvThreads i, i < R; np <= R kInvThreads), R = 0: in LDS.
+template <typename TF, int NB, int NO, int R>
+__global__ __launch_bounds__(kInvThreads, (sizeof(TF) == 4 ? 4 : 2) / (R > 2 ? 2 : 1)) void
+k_invert_panel(
     const int32_t* __restrict__ jlist, const int64_t* __restrict__ dof_ptr,
     const int64_t* __restrict__ doff, const int64_t* __restrict__ soff, TF* __restrict__ dense,
     int32_t* __restrict__ sigma_all, int32_t* __restrict__ status, int K0) {
@@ -869,6 +1039,12 @@ __global__ __launch_bounds__(kInvThreads, sizeof(TF) == 4 ? 4 : 2) void k_invert
   int* swv = swl + 2 * NB;                            // 2 NB: their source rows
   int* swn = swv + 2 * NB;                            // 1
   int* sig = swn + 1;                                 // np (last panel only)
+  // register path: two alternating sets of the wave winners' rows and row c,
+  // the wave maxima and their rows
+  TF* Rs = reinterpret_cast<TF*>(
+      smem_raw + align16((size_t)(reinterpret_cast<unsigned char*>(sig + np) - smem_raw)));
+  TF* wv2 = Rs + 2 * (NW + 1) * NB;                    // 2 NW
+  int* wi2 = reinterpret_cast<int*>(wv2 + 2 * NW);    // 2 NW
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int lr = lane & 15, lg = lane >> 4;
   const int ntile = np / 16;
@@ -902,107 +1078,114 @@ __global__ __launch_bounds__(kInvThreads, sizeof(TF) == 4 ? 4 : 2) void k_invert
       }
     }
     __syncthreads();
-    // pivot candidates of the strip's first column; every later column's
-    // candidates are taken by the elimination of the step before it
-    TF best = TF(-1);
-    int bi = np;
-    for (int r = k0 + tid; r < np; r += kInvThreads) {
-      const TF v = fabs(T[r * LDT]);
-      if (v > best) {
-        best = v;
-        bi = r;
-      }
-    }
-    for (int kk = 0; kk < NB; ++kk) {
-      const int c = k0 + kk;
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const TF v2 = __shfl_xor(best, off, 64);
-        const int i2 = __shfl_xor(bi, off, 64);
-        if (v2 > best || (v2 == best && i2 < bi)) {
-          best = v2;
-          bi = i2;
-        }
-      }
-      if (lane == 0) {
-        wval[wv] = best;
-        widx[wv] = bi;
-      }
-      __syncthreads();
-      best = wval[0];
-      bi = widx[0];
-#pragma unroll
-      for (int w = 1; w < NW; ++w)
-        if (wval[w] > best || (wval[w] == best && widx[w] < bi)) {
-          best = wval[w];
-          bi = widx[w];
-        }
-      if (!(best > TF(0))) {   // the same decision in every thread
-        if (tid == 0) status[j] = 1;
+    if constexpr (R > 0) {
+      if (!pivot_steps_registers<TF, NB, R>(T, LDT, Rs, wv2, wi2, piv, sg, np, k0)) {
+        if (tid == 0) status[j] = 1;   // the same decision in every thread
         return;
       }
-      const int p = bi;
-      if (tid == 0) {
-        piv[kk] = p;
-        sg[c] = p;
-      }
-      // every thread takes the pivot row and row c into registers, then the
-      // interchange and the elimination are one pass: position c receives
-      // the scaled pivot row, position p the eliminated old row c, every
-      // other row is eliminated in place (rows are owned by single threads)
-      TF prow[NB], crow[NB];
-#pragma unroll
-      for (int q = 0; q < NB; ++q) {
-        prow[q] = T[p * LDT + q];
-        crow[q] = T[c * LDT + q];
-      }
-      __syncthreads();
-      // entries kk of the two rows, selected without indexing the register
-      // arrays at a run-time position (which would place them in scratch)
-      TF pk = TF(0), ck = TF(0);
-#pragma unroll
-      for (int q = 0; q < NB; ++q) {
-        if (q == kk) {
-          pk = prow[q];
-          ck = crow[q];
+    } else {
+      // pivot candidates of the strip's first column; every later column's
+      // candidates are taken by the elimination of the step before it
+      TF best = TF(-1);
+      int bi = np;
+      for (int r = k0 + tid; r < np; r += kInvThreads) {
+        const TF v = fabs(T[r * LDT]);
+        if (v > best) {
+          best = v;
+          bi = r;
         }
       }
-      const TF d = TF(1) / pk;
-      TF rc[NB];
+      for (int kk = 0; kk < NB; ++kk) {
+        const int c = k0 + kk;
 #pragma unroll
-      for (int q = 0; q < NB; ++q) rc[q] = (q == kk) ? d : prow[q] * d;
-      // eliminate, and take this thread's pivot candidate for column kk + 1
-      // among the rows below c (the wave reduction at the top of the next
-      // step is the barrier after these writes)
-      best = TF(-1);
-      bi = np;
-      const int kn = kk + 1 < NB ? kk + 1 : kk;
-      for (int r = tid; r < np; r += kInvThreads) {
-        TF* Tr = T + r * LDT;
-        TF vn;
-        if (r == c) {
-#pragma unroll
-          for (int q = 0; q < NB; ++q) Tr[q] = rc[q];
-          vn = TF(0);
-#pragma unroll
-          for (int q = 0; q < NB; ++q)
-            if (q == kn) vn = rc[q];
-        } else {
-          // row p receives the eliminated old row c; any other row is
-          // eliminated in place
-          const bool isp = r == p;
-          const TF t = isp ? ck : Tr[kk];
-          vn = TF(0);
-#pragma unroll
-          for (int q = 0; q < NB; ++q) {
-            const TF v = (q == kk ? TF(0) : (isp ? crow[q] : Tr[q])) - t * rc[q];
-            Tr[q] = v;
-            if (q == kn) vn = v;
+        for (int off = 32; off > 0; off >>= 1) {
+          const TF v2 = __shfl_xor(best, off, 64);
+          const int i2 = __shfl_xor(bi, off, 64);
+          if (v2 > best || (v2 == best && i2 < bi)) {
+            best = v2;
+            bi = i2;
           }
         }
-        if (r > c && fabs(vn) > best) {
-          best = fabs(vn);
-          bi = r;
+        if (lane == 0) {
+          wval[wv] = best;
+          widx[wv] = bi;
+        }
+        __syncthreads();
+        best = wval[0];
+        bi = widx[0];
+#pragma unroll
+        for (int w = 1; w < NW; ++w)
+          if (wval[w] > best || (wval[w] == best && widx[w] < bi)) {
+            best = wval[w];
+            bi = widx[w];
+          }
+        if (!(best > TF(0))) {   // the same decision in every thread
+          if (tid == 0) status[j] = 1;
+          return;
+        }
+        const int p = bi;
+        if (tid == 0) {
+          piv[kk] = p;
+          sg[c] = p;
+        }
+        // every thread takes the pivot row and row c into registers, then the
+        // interchange and the elimination are one pass: position c receives
+        // the scaled pivot row, position p the eliminated old row c, every
+        // other row is eliminated in place (rows are owned by single threads)
+        TF prow[NB], crow[NB];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+          prow[q] = T[p * LDT + q];
+          crow[q] = T[c * LDT + q];
+        }
+        __syncthreads();
+        // entries kk of the two rows, selected without indexing the register
+        // arrays at a run-time position (which would place them in scratch)
+        TF pk = TF(0), ck = TF(0);
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+          if (q == kk) {
+            pk = prow[q];
+            ck = crow[q];
+          }
+        }
+        const TF d = TF(1) / pk;
+        TF rc[NB];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) rc[q] = (q == kk) ? d : prow[q] * d;
+        // eliminate, and take this thread's pivot candidate for column kk + 1
+        // among the rows below c (the wave reduction at the top of the next
+        // step is the barrier after these writes)
+        best = TF(-1);
+        bi = np;
+        const int kn = kk + 1 < NB ? kk + 1 : kk;
+        for (int r = tid; r < np; r += kInvThreads) {
+          TF* Tr = T + r * LDT;
+          TF vn;
+          if (r == c) {
+#pragma unroll
+            for (int q = 0; q < NB; ++q) Tr[q] = rc[q];
+            vn = TF(0);
+#pragma unroll
+            for (int q = 0; q < NB; ++q)
+              if (q == kn) vn = rc[q];
+          } else {
+            // row p receives the eliminated old row c; any other row is
+            // eliminated in place
+            const bool isp = r == p;
+            const TF t = isp ? ck : Tr[kk];
+            vn = TF(0);
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+              const TF v = (q == kk ? TF(0) : (isp ? crow[q] : Tr[q])) - t * rc[q];
+              Tr[q] = v;
+              if (q == kn) vn = v;
+            }
+          }
+          if (r > c && fabs(vn) > best) {
+            best = fabs(vn);
+            bi = r;
+          }
         }
       }
     }
@@ -1037,16 +1220,27 @@ __global__ __launch_bounds__(kInvThreads, sizeof(TF) == 4 ? 4 : 2) void k_invert
     }
     __syncthreads();
     {
+      // the moved rows dealt to the wavefronts (2 NB / NW each), the columns
+      // outside the strip to the lanes in chunks of 64; a chunk's loads all
+      // complete before its stores (a barrier between them)
+      constexpr int XPW = 2 * NB / NW;
       const int ns = swn[0];
-      for (int col = tid; col < np - NB; col += kInvThreads) {
+      const int ncols = np - NB;
+      for (int col0 = 0; col0 < ncols; col0 += 64) {
+        const int col = col0 + lane;
         const int cc = col < k0 ? col : col + NB;
-        TF v[2 * NB];
+        TF v[XPW];
 #pragma unroll
-        for (int x = 0; x < 2 * NB; ++x)
-          if (x < ns) v[x] = a[(int64_t)swv[x] * np + cc];
+        for (int u = 0; u < XPW; ++u) {
+          const int x = wv * XPW + u;
+          if (x < ns && col < ncols) v[u] = a[(int64_t)swv[x] * np + cc];
+        }
+        __syncthreads();
 #pragma unroll
-        for (int x = 0; x < 2 * NB; ++x)
-          if (x < ns) a[(int64_t)swl[x] * np + cc] = v[x];
+        for (int u = 0; u < XPW; ++u) {
+          const int x = wv * XPW + u;
+          if (x < ns && col < ncols) a[(int64_t)swl[x] * np + cc] = v[u];
+        }
       }
     }
     __syncthreads();
@@ -1059,10 +1253,12 @@ __global__ __launch_bounds__(kInvThreads, sizeof(TF) == 4 ? 4 : 2) void k_invert
     }
     __syncthreads();
     // rank-16 update of the outer panel's other column tiles; the columns
-    // beyond the outer panel wait for the trailing launches.  The tasks
-    // (tile J, row tile it) are dealt to the wavefronts in turn.  The pivot
-    // rows' part of every such tile is staged in LDS first: the task holding
-    // rows K rewrites it while other tasks still read it.
+    // beyond the outer panel wait for the trailing launches.  The row tiles
+    // are dealt to the wavefronts RT at a time; a wavefront loads all of its
+    // RT x nJ output tiles before the matrix-core steps, so their loads are
+    // in flight together.  The pivot rows' part of every such tile is staged
+    // in LDS first: the wavefront holding rows K rewrites it while others
+    // still read it.
     const int ts = k0 / 16;
     const int nJ = u1 - u0 - 1;
     for (int e = tid; e < nJ * 256; e += kInvThreads) {
@@ -1071,20 +1267,41 @@ __global__ __launch_bounds__(kInvThreads, sizeof(TF) == 4 ? 4 : 2) void k_invert
       Bk[e] = a[(int64_t)(k0 + rr) * np + J * 16 + cc];
     }
     __syncthreads();
-    const int ntask = nJ * ntile;
-    for (int t = wv; t < ntask; t += NW) {
-      const int jt = t / ntile, rb = (t - jt * ntile) * 16;
-      const int cl = (u0 + jt + (u0 + jt >= ts ? 1 : 0)) * 16 + lr;
+    constexpr int MJ = NO / NB - 1;   // the outer panel's other column tiles
+    constexpr int RT = 1;             // row tiles per wavefront iteration
+    for (int it0 = wv * RT; it0 < ntile; it0 += NW * RT) {
       // accumulator entry r of lane (lr, lg): row MT::row(lg, r) of column lr
-      acc_t acc;
+      acc_t acc[RT][MJ];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) acc[r] = a[(int64_t)(rb + MT::row(lg, r)) * np + cl];
-      const TF* Tt = T + (rb + lr) * LDT + lg;
-      const TF* Bt = Bk + jt * 256 + lg * 16 + lr;
+      for (int u = 0; u < RT; ++u)
 #pragma unroll
-      for (int q = 0; q < NB / 4; ++q) acc = MT::step(Tt[4 * q], Bt[64 * q], acc);
+        for (int jt = 0; jt < MJ; ++jt)
+          if (it0 + u < ntile && jt < nJ) {
+            const int rb = (it0 + u) * 16;
+            const int cl = (u0 + jt + (u0 + jt >= ts ? 1 : 0)) * 16 + lr;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) a[(int64_t)(rb + MT::row(lg, r)) * np + cl] = acc[r];
+            for (int r = 0; r < 4; ++r)
+              acc[u][jt][r] = a[(int64_t)(rb + MT::row(lg, r)) * np + cl];
+          }
+#pragma unroll
+      for (int u = 0; u < RT; ++u) {
+        if (it0 + u >= ntile) break;
+        const int rb = (it0 + u) * 16;
+        const TF* Tt = T + (rb + lr) * LDT + lg;
+        TF tv[NB / 4];
+#pragma unroll
+        for (int q = 0; q < NB / 4; ++q) tv[q] = Tt[4 * q];
+#pragma unroll
+        for (int jt = 0; jt < MJ; ++jt)
+          if (jt < nJ) {
+            const TF* Bt = Bk + jt * 256 + lg * 16 + lr;
+            const int cl = (u0 + jt + (u0 + jt >= ts ? 1 : 0)) * 16 + lr;
+#pragma unroll
+            for (int q = 0; q < NB / 4; ++q) acc[u][jt] = MT::step(tv[q], Bt[64 * q], acc[u][jt]);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) a[(int64_t)(rb + MT::row(lg, r)) * np + cl] = acc[u][jt][r];
+          }
+      }
     }
     __syncthreads();
   }
@@ -3047,10 +3264,13 @@ size_t invert_blocks_lds(int np_max, bool f32) {
   const size_t tf = f32 ? 4 : 8;
   // strip (np x (NB + 1)), the pivot rows of the panel's other tiles, the
   // wave maxima and their rows, the strip's pivots and interchange lists,
-  // sigma (np)
-  return (size_t)np_max * (kPanel + 1) * tf + (size_t)(kOuterPanel / kPanel - 1) * 256 * tf +
-         (kInvThreads / 64) * (tf + 4) +
-         (size_t)(5 * kPanel + 1) * 4 + (size_t)np_max * 4;
+  // sigma (np); then (16-byte aligned) the register form's two sets of
+  // published rows and wave maxima
+  constexpr int NW = kInvThreads / 64;
+  const size_t base = (size_t)np_max * (kPanel + 1) * tf +
+                      (size_t)(kOuterPanel / kPanel - 1) * 256 * tf + NW * (tf + 4) +
+                      (size_t)(5 * kPanel + 1) * 4 + (size_t)np_max * 4;
+  return align16(base) + 2 * (size_t)(NW + 1) * kPanel * tf + 2 * (size_t)NW * (tf + 4);
 }
 
 template <typename TF>
@@ -3061,10 +3281,21 @@ static void invert_panels(const int32_t* jlist, int64_t nb, const int64_t* dof_p
   const size_t sm = invert_blocks_lds(npmax, sizeof(TF) == 4);
   const int ngroups = (npmax + 63) / 64;
   const int64_t nb8 = (nb + 7) / 8 * 8;
+  // rows per thread of the register form of the pivot steps (0: LDS form)
+  const int rpt = npmax <= kInvThreads ? 1 : npmax <= 2 * kInvThreads ? 2
+                  : npmax <= 4 * kInvThreads ? 4 : 0;
   for (int K0 = 0; K0 < npmax; K0 += kOuterPanel) {
-    hipLaunchKernelGGL((k_invert_panel<TF, kPanel, kOuterPanel>), dim3((unsigned)nb),
-                       dim3(kInvThreads), sm, s, jlist, dof_ptr, dense_off, sigma_off, dense,
-                       sigma, status, K0);
+#define FSGMG_PANEL(RR)                                                                         \
+  hipLaunchKernelGGL((k_invert_panel<TF, kPanel, kOuterPanel, RR>), dim3((unsigned)nb),        \
+                     dim3(kInvThreads), sm, s, jlist, dof_ptr, dense_off, sigma_off, dense,   \
+                     sigma, status, K0)
+    switch (rpt) {
+      case 1: FSGMG_PANEL(1); break;
+      case 2: FSGMG_PANEL(2); break;
+      case 4: FSGMG_PANEL(4); break;
+      default: FSGMG_PANEL(0); break;
+    }
+#undef FSGMG_PANEL
     if (ngroups > 1) {
       hipLaunchKernelGGL((k_invert_trailing<TF>), dim3((unsigned)(nb8 * ngroups * ngroups)),
                          dim3(kTrailThreads), 0, s, jlist, nb, dof_ptr, dense_off, dense, status,
