@@ -16,7 +16,9 @@ backward, for an incoming gradient g = dL/dx:
 The operator of the adjoint is the forward's: (E, mu) and the smoother
 options are saved with the forward, and the handle is brought back to them
 before the adjoint solve when other solves ran on it in between (several
-forwards on one handle, then one backward of their summed loss).
+forwards on one handle, then one backward of their summed loss).  A
+re-assembly about another advecting velocity in between cannot be undone
+that way: backward then raises.
 Argument marshalling only: every step runs in the library.
 """
 from __future__ import annotations
@@ -45,6 +47,7 @@ class FSISolve(torch.autograd.Function):
             raise RuntimeError("forward solve did not converge: %r" % info)
         ctx.H, ctx.krylov, ctx.fshape = H, krylov, f.shape
         ctx.params, ctx.sopts = (Ev, muv), sopts
+        ctx.advection = H.advection
         ctx.save_for_backward(x)
         ctx.info = info
         return x
@@ -53,6 +56,11 @@ class FSISolve(torch.autograd.Function):
     def backward(ctx, gx):
         (x,) = ctx.saved_tensors
         H = ctx.H
+        if H.advection != ctx.advection:
+            # the operator was re-assembled about another advecting velocity
+            # since the forward; the library keeps no copy of the old one
+            raise RuntimeError("the hierarchy's advecting velocity changed between forward and "
+                               "backward (update_advection / period_solve)")
         H.ensure_blocks(*ctx.params, **ctx.sopts)
         lam = torch.empty_like(x)
         info = H.adjoint_solve(gx.contiguous(), lam, **ctx.krylov)

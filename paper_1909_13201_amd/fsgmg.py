@@ -473,6 +473,7 @@ class Hierarchy:
             allocator = TorchAllocator(device) if device >= 0 else None
         self.allocator = allocator   # outlives the handle (closed first)
         self.built_key = None      # (E, mu, options) of the current block inverses
+        self.advection = 0         # re-assemblies about a new advecting velocity so far
         self.h = setup_hierarchy(cfg, w, device, stream, allocator)
         self.L = int(cfg["n_levels"])
         self.info = [level_info(self.h, l) for l in range(self.L)]
@@ -600,6 +601,7 @@ class Hierarchy:
         (a float64 device tensor; a float64 numpy array of N entries on a
         host-only handle)."""
         self.built_key = None
+        self.advection += 1
         if self.device < 0:
             import numpy as np
             if not (isinstance(x, np.ndarray) and x.dtype == np.float64 and x.shape == (self.N,)
@@ -632,6 +634,7 @@ class Hierarchy:
                                 it.ctypes.data_as(C.c_void_p), ch.ctypes.data_as(C.c_void_p),
                                 C.byref(info))
         self.built_key = None
+        self.advection += 1
         if st not in (FSGMG_OK, FSGMG_NOT_CONVERGED):
             _check(self.h, st)
         out = {name: getattr(info, name) for name, _ in PeriodInfo._fields_}

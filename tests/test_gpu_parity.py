@@ -1097,6 +1097,28 @@ def test_autograd_two_forwards_one_backward():
     H.close()
 
 
+def test_autograd_refuses_backward_after_advection_update():
+    """A re-assembly about another advecting velocity between a forward and
+    its backward leaves no copy of the forward's operator: the backward
+    raises instead of differentiating the new operator."""
+    from paper_1909_13201_amd.autograd import FSISolve
+    cfg = inputs.with_levels(inputs.config("c5"), 2)
+    H = fsgmg.Hierarchy(cfg, inputs.advecting_field(cfg), device=0)
+    say("[autograd] backward after update_advection")
+    try:
+        E, mu = inputs.sample_parameters(cfg, 1)[0]
+        f = torch.tensor(inputs.sample_loads(cfg, 1)[0].ravel(), dtype=torch.float64,
+                         device="cuda")
+        Et = torch.tensor(E, dtype=torch.float64, requires_grad=True)
+        mt = torch.tensor(mu, dtype=torch.float64, requires_grad=True)
+        x = FSISolve.apply(f, Et, mt, H, dict(prec="fp32"))
+        H.update_advection(x.detach().contiguous())
+        with pytest.raises(RuntimeError, match="advecting velocity changed"):
+            x.sum().backward()
+    finally:
+        H.close()
+
+
 def test_caller_allocator():
     """Device storage through the caller's allocator (torch's caching
     allocator, the binding's default): the library's buffers are blocks of
