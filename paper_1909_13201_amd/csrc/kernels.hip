@@ -1872,7 +1872,8 @@ __global__ __launch_bounds__(kThreads) void k_cgj_update(double* __restrict__ a,
 //  * k_cgj_panel_r (one workgroup): thread t holds rows t, t + kCgjThreads,
 //    ... of the NB panel columns in registers and runs the panel's NB
 //    Gauss-Jordan steps (the same pivot rule and arithmetic as k_cgj_panel;
-//    the pivot row and the current row are passed through LDS), writes the
+//    the pivot row and the current row are passed through LDS, one barrier
+//    per step), writes the
 //    panel T into an, and src[r] = the row of a that row r of the
 //    interchanged matrix comes from;
 //  * k_cgj_update_r (whole grid): an[r][j] = a[src r][j] + sum_q (T - E_K)[r][q]
@@ -1890,7 +1891,8 @@ __global__ __launch_bounds__(kCgjThreads) void k_cgj_panel_r(const double* __res
   constexpr int NW = kCgjThreads / 64;
   __shared__ double wval[2][NW];
   __shared__ int widx[2][NW];
-  __shared__ double prow[2][NB], crow[2][NB];
+  // two alternating sets of the wavefront winners' rows and row c
+  __shared__ __align__(16) double rows[2][NW + 1][NB];
   __shared__ int lpiv[NB];
   __shared__ int swl[2 * NB], swv[2 * NB], swn;
   if (status[0]) return;
@@ -1908,6 +1910,12 @@ __global__ __launch_bounds__(kCgjThreads) void k_cgj_panel_r(const double* __res
       t[i][q + 1] = v.y;
     }
   }
+  // A step: the pivot candidates of column kk reduced within each wavefront;
+  // each wavefront's winning lane publishes its row and the owner of row c
+  // publishes row c, so one barrier separates the publication from the
+  // choice among the NW winners (a set is rewritten two steps later, after a
+  // barrier every reader has passed); every row is then eliminated alike
+  // and the owners of rows c and p overwrite theirs.
 #pragma unroll
   for (int kk = 0; kk < NB; ++kk) {
     const int c = (int)k0 + kk;
@@ -1934,6 +1942,22 @@ __global__ __launch_bounds__(kCgjThreads) void k_cgj_panel_r(const double* __res
         bi = i2;
       }
     }
+    if (bi < n && bi % kCgjThreads == tid) {
+#pragma unroll
+      for (int i = 0; i < RPT; ++i)
+        if (i == bi / kCgjThreads)
+#pragma unroll
+          for (int q = 0; q < NB; q += 2)
+            *reinterpret_cast<double2*>(&rows[par][wv][q]) = make_double2(t[i][q], t[i][q + 1]);
+    }
+    if (c % kCgjThreads == tid) {
+#pragma unroll
+      for (int i = 0; i < RPT; ++i)
+        if (i == c / kCgjThreads)
+#pragma unroll
+          for (int q = 0; q < NB; q += 2)
+            *reinterpret_cast<double2*>(&rows[par][NW][q]) = make_double2(t[i][q], t[i][q + 1]);
+    }
     if (lane == 0) {
       wval[par][wv] = best;
       widx[par][wv] = bi;
@@ -1941,10 +1965,13 @@ __global__ __launch_bounds__(kCgjThreads) void k_cgj_panel_r(const double* __res
     __syncthreads();
     best = wval[par][0];
     bi = widx[par][0];
+    int ws = 0;
+#pragma unroll
     for (int w = 1; w < NW; ++w)
       if (wval[par][w] > best || (wval[par][w] == best && widx[par][w] < bi)) {
         best = wval[par][w];
         bi = widx[par][w];
+        ws = w;
       }
     if (!(best > 0.0)) {   // the same decision in every thread
       if (tid == 0) status[0] = 1;
@@ -1952,34 +1979,38 @@ __global__ __launch_bounds__(kCgjThreads) void k_cgj_panel_r(const double* __res
     }
     const int p = bi;
     if (tid == 0) lpiv[kk] = p;
+    const double* prow = rows[par][ws];
+    const double d = 1.0 / prow[kk];
+    double rc[NB];
 #pragma unroll
-    for (int i = 0; i < RPT; ++i) {
-      const int r = tid + i * kCgjThreads;
-      if (r == p)
-#pragma unroll
-        for (int q = 0; q < NB; ++q) prow[par][q] = t[i][q];
-      if (r == c)
-#pragma unroll
-        for (int q = 0; q < NB; ++q) crow[par][q] = t[i][q];
+    for (int q = 0; q < NB; q += 2) {
+      const double2 v = *reinterpret_cast<const double2*>(prow + q);
+      rc[q] = v.x;
+      rc[q + 1] = v.y;
     }
-    __syncthreads();
-    const double d = 1.0 / prow[par][kk];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) rc[q] = (q == kk) ? d : rc[q] * d;
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
-      const int r = tid + i * kCgjThreads;
-      if (r >= n) continue;
-      if (r == c) {
+      const double tt = t[i][kk];
 #pragma unroll
-        for (int q = 0; q < NB; ++q) t[i][q] = (q == kk) ? d : prow[par][q] * d;
-      } else {
-        const double tt = (r == p) ? crow[par][kk] : t[i][kk];
+      for (int q = 0; q < NB; ++q) t[i][q] = (q == kk ? 0.0 : t[i][q]) - tt * rc[q];
+    }
+    if (c % kCgjThreads == tid) {   // row c: the scaled pivot row
 #pragma unroll
-        for (int q = 0; q < NB; ++q) {
-          const double rc = (q == kk) ? d : prow[par][q] * d;
-          const double old = (r == p) ? crow[par][q] : t[i][q];
-          t[i][q] = (q == kk ? 0.0 : old) - tt * rc;
-        }
-      }
+      for (int i = 0; i < RPT; ++i)
+        if (i == c / kCgjThreads)
+#pragma unroll
+          for (int q = 0; q < NB; ++q) t[i][q] = rc[q];
+    }
+    if (p != c && p % kCgjThreads == tid) {   // row p: the eliminated old row c
+      const double* crow = rows[par][NW];
+      const double ck = crow[kk];
+#pragma unroll
+      for (int i = 0; i < RPT; ++i)
+        if (i == p / kCgjThreads)
+#pragma unroll
+          for (int q = 0; q < NB; ++q) t[i][q] = (q == kk ? 0.0 : crow[q]) - ck * rc[q];
     }
   }
 #pragma unroll
