@@ -328,6 +328,31 @@ enum { P_BASE = 0, P_G = 1, P_C = 2, P_MU = 3 };
 
 }  // namespace
 
+std::vector<double> reference_tables(int D) {
+  const RefElem R(D);
+  constexpr int Q = kMaxQ, B = kMaxB, P = kMaxP;
+  // Gauss weights, phi, dphi, d2phi, psi, dpsi at the maximal sizes (zeros
+  // beyond the element's own counts)
+  std::vector<double> t(Q + Q * B + Q * B * 3 + Q * B * 9 + Q * P + Q * P * 3, 0.0);
+  const size_t o_phi = Q, o_dphi = o_phi + Q * B, o_d2 = o_dphi + Q * B * 3,
+               o_psi = o_d2 + Q * B * 9, o_dpsi = o_psi + Q * P;
+  for (int q = 0; q < R.nq; ++q) {
+    t[q] = R.wq[q];
+    for (int a = 0; a < R.nb; ++a) {
+      t[o_phi + q * B + a] = R.phi[q][a];
+      for (int k = 0; k < D; ++k) {
+        t[o_dphi + (q * B + a) * 3 + k] = R.dphi[q][a][k];
+        for (int m = 0; m < D; ++m) t[o_d2 + ((q * B + a) * 3 + k) * 3 + m] = R.d2phi[q][a][k][m];
+      }
+    }
+    for (int m = 0; m < R.np; ++m) {
+      t[o_psi + q * P + m] = R.psi[q][m];
+      for (int k = 0; k < D; ++k) t[o_dpsi + (q * P + m) * 3 + k] = R.dpsi[q][m][k];
+    }
+  }
+  return t;
+}
+
 void lame(double E, double nu, double& G, double& invlam) {
   G = E / (2.0 * (1.0 + nu));
   invlam = nu >= 0.5 ? 0.0 : (1.0 + nu) * (1.0 - 2.0 * nu) / (E * nu);
@@ -520,8 +545,8 @@ struct AdvTargets {
 // the value slot of each emission can be recorded once (record) and
 // replayed (replay) instead of searched for.
 void add_advective(const Level& lv, const Physics& ph, const std::vector<double>& w, bool finest,
-                   const AdvTargets& t, std::vector<int32_t>* record,
-                   const std::vector<int32_t>* replay) {
+                   const AdvTargets& t, AdvectionPlan* rec, const std::vector<int32_t>* replay) {
+  std::vector<int32_t>* record = rec ? &rec->slots : nullptr;
   const int D = lv.D;
   const RefElem R(D);
   const int ncol = 1 << D;
@@ -550,7 +575,14 @@ void add_advective(const Level& lv, const Physics& ph, const std::vector<double>
     advective_terms(R, lv, ph, *g, e, dof, w, finest,
                     [&](int, int64_t, int64_t, int, double) { ++per; });
   }
-  if (record) record->assign(nfluid * per, -1);
+  if (rec) {
+    rec->slots.assign(nfluid * per, -1);
+    rec->dest.assign(nfluid * per, 0);
+    rec->per = (int)per;
+    rec->elems.clear();
+    for (const std::vector<int64_t>& list : by_colour)
+      for (int64_t e : list) rec->elems.push_back((int32_t)e);
+  }
   if (replay && (int64_t)replay->size() != nfluid * per)
     throw std::logic_error("re-assembly slots do not match the level");
   int64_t base = 0;
@@ -595,7 +627,10 @@ void add_advective(const Level& lv, const Physics& ph, const std::vector<double>
                             s = slot_of(*t.load, r, c);
                             (*t.load_val)[s] += v;
                           }
-                          if (record) (*record)[k++] = (int32_t)s;
+                          if (record) {
+                            rec->dest[k] = (uint8_t)(4 * target + p);
+                            (*record)[k++] = (int32_t)s;
+                          }
                         });
       }
     });
@@ -936,7 +971,7 @@ void assemble_level(const Level& lv, const Physics& ph, const std::vector<double
       }
       add_advective(lv, ph, *w_level, true,
                     AdvTargets{&full, fp, false, &op.time, op.time_piece, &op.load, &op.load.val},
-                    plan && slots_fit(full, &op.time, &op.load) ? &plan->slots : nullptr, nullptr);
+                    plan && slots_fit(full, &op.time, &op.load) ? plan : nullptr, nullptr);
     }
     reduce_values(lv, full, fp, op);
     lift_values(lv, full, fp, op);
@@ -950,7 +985,7 @@ void assemble_level(const Level& lv, const Physics& ph, const std::vector<double
         for (int p = 0; p < 4; ++p) plan->stat[p] = op.piece[p];
       add_advective(lv, ph, *w_level, false,
                     AdvTargets{&op.A, op.piece, true, nullptr, nullptr, nullptr, nullptr},
-                    plan && slots_fit(op.A, nullptr, nullptr) ? &plan->slots : nullptr, nullptr);
+                    plan && slots_fit(op.A, nullptr, nullptr) ? plan : nullptr, nullptr);
     }
   }
   combine_values(op.piece, Gmod, invlam, ph.mu, A.val);

@@ -81,19 +81,30 @@ struct Physics {
 
 void lame(double E, double nu, double& G, double& invlam);
 
+// The reference element's tables (Gauss weights, Q2 values, first and second
+// derivatives, Q1 values and derivatives) at the 27 / 27 / 8 maxima of 3D,
+// flattened in that order (the device re-assembly's layout).
+std::vector<double> reference_tables(int D);
+
 // What re-assembling a level about a new advecting velocity needs: the sums
 // of every term that does not depend on it, on the patterns the advective
 // terms (convection and SUPG) are added to.  Those patterns hold every
 // entry an advective term can reach, whatever the velocity, so they are
 // fixed.  stat: the unreduced pieces on the finest level, the reduced ones
 // elsewhere; tstat / lstat: the finest level's time and load operators
-// (Dirichlet rows removed); slots: the value slot (-1: none) of every
-// advective term in the order the elements emit them.
+// (Dirichlet rows removed); elems: the fluid elements in the order their
+// terms are added (colour by colour), each emitting per terms; slots: the
+// value slot (-1: none) of every advective term in that order, dest its
+// array (4 target + piece; target 0 the operator, 1 the time operator, 2
+// the load operator).
 struct AdvectionPlan {
   std::vector<double> stat[4];
   std::vector<double> tstat[4];
   std::vector<double> lstat;
+  std::vector<int32_t> elems;
   std::vector<int32_t> slots;
+  std::vector<uint8_t> dest;
+  int per = 0;
   bool ready = false;
 };
 

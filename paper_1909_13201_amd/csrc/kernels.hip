@@ -3829,6 +3829,256 @@ void launch_scatter(int64_t n, const double* v, const int64_t* map, double* out6
                        out64, out32);
 }
 
+// ------------------------------------------------------------------------
+// re-assembly of the advective terms (2D): the terms of each fluid element
+// that depend on the advecting velocity (convection and the SUPG terms of
+// the stabilized momentum balance, Section 2.2), in the order and with the
+// arithmetic of the host assembly, written to a per-element list; a gather
+// then forms every touched operator entry as its velocity-independent sum
+// plus its contributions in the host's order.
+// ------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_adv_elements(AdvElemView v) {
+  constexpr int D = 2, NB = 9, NQ = 9, NP = 4, BB = 4;   // BB: the element bubble
+  const int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (i >= v.nfluid) return;
+  const int64_t e = v.elems[i];
+  const int64_t* nodes = v.elem_nodes + e * NB;
+  const double* R = v.ref;
+  auto phi = [&](int q, int a) { return R[kRefPhi + q * kAdvB + a]; };
+  auto dphi = [&](int q, int a, int k) { return R[kRefDphi + (q * kAdvB + a) * 3 + k]; };
+  auto d2phi = [&](int q, int a, int k, int m) {
+    return R[kRefD2phi + ((q * kAdvB + a) * 3 + k) * 3 + m];
+  };
+  auto dpsi = [&](int q, int m, int k) { return R[kRefDpsi + (q * kAdvP + m) * 3 + k]; };
+  double Xe[NB][D], wn[NB][D];
+  for (int b = 0; b < NB; ++b) {
+    const int64_t fn = v.node_fine[nodes[b]];
+    for (int c = 0; c < D; ++c) {
+      Xe[b][c] = v.X[nodes[b] * D + c];
+      wn[b][c] = v.x[v.off_u + (int64_t)D * fn + c];
+    }
+  }
+  // geometry at the Gauss points
+  double dV[NQ], G[NQ][NB][D], H[NQ][NB][D][D], Gp[NQ][NP][D];
+  for (int q = 0; q < NQ; ++q) {
+    double J[D][D];
+    for (int a = 0; a < D; ++a)
+      for (int k = 0; k < D; ++k) {
+        double s = 0;
+        for (int b = 0; b < NB; ++b) s += Xe[b][a] * dphi(q, b, k);
+        J[a][k] = s;
+      }
+    const double det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    double Ji[D][D];
+    Ji[0][0] = J[1][1] / det;
+    Ji[0][1] = -J[0][1] / det;
+    Ji[1][0] = -J[1][0] / det;
+    Ji[1][1] = J[0][0] / det;
+    dV[q] = det * R[kRefWq + q];
+    for (int a = 0; a < NB; ++a) {
+      for (int c = 0; c < D; ++c) {
+        double s = 0;
+        for (int k = 0; k < D; ++k) s += dphi(q, a, k) * Ji[k][c];
+        G[q][a][c] = s;
+      }
+      for (int c = 0; c < D; ++c)
+        for (int f = 0; f < D; ++f) {
+          double s = 0;
+          for (int k = 0; k < D; ++k)
+            for (int m = 0; m < D; ++m) s += Ji[k][c] * d2phi(q, a, k, m) * Ji[m][f];
+          H[q][a][c][f] = s;
+        }
+    }
+    for (int m = 0; m < NP; ++m)
+      for (int c = 0; c < D; ++c) {
+        double s = 0;
+        for (int k = 0; k < D; ++k) s += dpsi(q, m, k) * Ji[k][c];
+        Gp[q][m][c] = s;
+      }
+  }
+  const double rho = v.rho, inv_dt = v.inv_dt, theta = v.theta;
+  const bool weighted = inv_dt != 0.0 && theta != 1.0;
+  const bool finest = v.finest != 0;
+  double* out = v.emit + i * (int64_t)v.per;
+  int k = 0;
+  // the element's k-th term (never beyond its own per slots)
+  auto put = [&](double val) {
+    if (k < v.per) out[k] = val;
+    ++k;
+  };
+  auto madd = [&](double val) {
+    put(weighted ? theta * val : val);
+    if (finest && weighted) put(-(1.0 - theta) * val);
+  };
+  double wq[NQ][D], wg[NQ][NB];
+  for (int q = 0; q < NQ; ++q)
+    for (int c = 0; c < D; ++c) {
+      double s = 0;
+      for (int b = 0; b < NB; ++b) s += wn[b][c] * phi(q, b);
+      wq[q][c] = s;
+    }
+  for (int q = 0; q < NQ; ++q)
+    for (int a = 0; a < NB; ++a) {
+      double s = 0;
+      for (int c = 0; c < D; ++c) s += wq[q][c] * G[q][a][c];
+      wg[q][a] = s;
+    }
+  // convection rho (w.grad u, phi)
+  for (int a = 0; a < NB; ++a)
+    for (int b = 0; b < NB; ++b) {
+      double s = 0;
+      for (int q = 0; q < NQ; ++q) s += dV[q] * phi(q, a) * wg[q][b];
+      for (int c = 0; c < D; ++c) madd(rho * s);
+    }
+  if (v.supg) {
+    // lambda_k from the element bubble
+    double Mb[D][D] = {}, Nb = 0;
+    for (int q = 0; q < NQ; ++q) {
+      double lap = 0;
+      for (int c = 0; c < D; ++c) lap += H[q][BB][c][c];
+      double w2[D][D];
+      for (int a = 0; a < D; ++a)
+        for (int c = 0; c < D; ++c) w2[a][c] = (c == a ? lap : 0.0) + H[q][BB][c][a];
+      for (int a = 0; a < D; ++a)
+        for (int b = 0; b < D; ++b) {
+          double s = 0;
+          for (int c = 0; c < D; ++c) s += w2[a][c] * w2[b][c];
+          Mb[a][b] += dV[q] * s;
+        }
+      for (int c = 0; c < D; ++c) Nb += dV[q] * G[q][BB][c] * G[q][BB][c];
+    }
+    const double ma = Mb[0][0], mb = Mb[0][1], md = Mb[1][1];
+    const double lam = (0.5 * (ma + md) + sqrt(0.25 * (ma - md) * (ma - md) + mb * mb)) / Nb;
+    const double nu_k = v.mu / rho;
+    double tw[NQ];
+    for (int q = 0; q < NQ; ++q) {
+      double w2 = 0;
+      for (int c = 0; c < D; ++c) w2 += wq[q][c] * wq[q][c];
+      const double wnq = sqrt(w2);
+      const double tau = 1.0 / fmax(4.0 * lam * nu_k, sqrt(lam) * wnq);
+      tw[q] = dV[q] * tau * rho;
+    }
+    for (int a = 0; a < NB; ++a)
+      for (int b = 0; b < NB; ++b) {
+        double s1s = 0, s1t = 0;
+        for (int q = 0; q < NQ; ++q) {
+          s1s += tw[q] * wg[q][a] * rho * wg[q][b];
+          s1t += tw[q] * wg[q][a] * rho * inv_dt * phi(q, b);
+        }
+        const double s1 = weighted ? theta * s1s + s1t : s1s + s1t;
+        for (int c = 0; c < D; ++c) {
+          put(s1);
+          if (finest && weighted) put(-(1.0 - theta) * s1s);
+          if (finest && inv_dt != 0.0) put(s1t);
+        }
+        if (finest) {
+          double sl = 0;
+          for (int q = 0; q < NQ; ++q) sl += rho * rho * tw[q] * wg[q][a] * phi(q, b);
+          for (int c = 0; c < D; ++c) put(sl);
+        }
+      }
+    for (int a = 0; a < NB; ++a)
+      for (int c = 0; c < D; ++c)
+        for (int b = 0; b < NB; ++b)
+          for (int f = 0; f < D; ++f) {
+            double s = 0;
+            for (int q = 0; q < NQ; ++q) {
+              double lap = 0;
+              if (c == f)
+                for (int m = 0; m < D; ++m) lap += H[q][b][m][m];
+              s += tw[q] * wg[q][a] * (lap + H[q][b][c][f]);
+            }
+            madd(-s);
+          }
+    for (int a = 0; a < NB; ++a)
+      for (int c = 0; c < D; ++c)
+        for (int m = 0; m < NP; ++m) {
+          double s = 0;
+          for (int q = 0; q < NQ; ++q) s += tw[q] * wg[q][a] * Gp[q][m][c];
+          madd(s);
+        }
+  }
+  if (k != v.per) atomicOr(v.flag, 2);
+}
+
+__global__ __launch_bounds__(kThreads) void k_adv_gather(AdvGatherView g) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= g.n) return;
+  double val = g.stat[i];
+  for (int64_t k = g.ptr[i]; k < g.ptr[i + 1]; ++k) val += g.emit[g.em[k]];
+  const int a = g.arr[i];
+  g.dst[a][g.slot[i]] = val;
+  if (g.red && g.red[i] >= 0) g.dst_red[a][g.red[i]] = val;
+}
+
+__global__ __launch_bounds__(kThreads) void k_adv_lift(int64_t n, const int64_t* row,
+                                                       const int64_t* ptr, const int64_t* kk,
+                                                       const double* g, const double* f0,
+                                                       const double* f1, const double* f2,
+                                                       const double* f3, double* l0, double* l1,
+                                                       double* l2, double* l3) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k) {
+    const int64_t q = kk[k];
+    const double gv = g[k];
+    s0 -= f0[q] * gv;
+    s1 -= f1[q] * gv;
+    s2 -= f2[q] * gv;
+    s3 -= f3[q] * gv;
+  }
+  const int64_t r = row[i];
+  l0[r] = s0;
+  l1[r] = s1;
+  l2[r] = s2;
+  l3[r] = s3;
+}
+
+__global__ __launch_bounds__(kThreads) void k_permute_values(int64_t n, const int64_t* perm,
+                                                             const double* in, double* out) {
+  const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (j < n) out[j] = in[perm[j]];
+}
+
+__global__ __launch_bounds__(kThreads) void k_nonfinite_flag(int64_t n, const double* x,
+                                                             int32_t* flag) {
+  const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (j < n && !isfinite(x[j])) atomicOr(flag, 1);
+}
+
+void launch_adv_elements(const AdvElemView& v, hipStream_t s) {
+  if (v.nfluid > 0)
+    hipLaunchKernelGGL(k_adv_elements, dim3(grid_for(v.nfluid, 64)), dim3(64), 0, s, v);
+}
+
+void launch_adv_gather(const AdvGatherView& g, hipStream_t s) {
+  if (g.n > 0)
+    hipLaunchKernelGGL(k_adv_gather, dim3(grid_for(g.n, kThreads)), dim3(kThreads), 0, s, g);
+}
+
+void launch_adv_lift(int64_t n, const int64_t* row, const int64_t* ptr, const int64_t* kk,
+                     const double* g, const double* f0, const double* f1, const double* f2,
+                     const double* f3, double* l0, double* l1, double* l2, double* l3,
+                     hipStream_t s) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_adv_lift, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, s, n, row, ptr,
+                       kk, g, f0, f1, f2, f3, l0, l1, l2, l3);
+}
+
+void launch_permute_values(int64_t n, const int64_t* perm, const double* in, double* out,
+                           hipStream_t s) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_permute_values, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, s, n,
+                       perm, in, out);
+}
+
+void launch_nonfinite_flag(int64_t n, const double* x, int32_t* flag, hipStream_t s) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_nonfinite_flag, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, s, n, x,
+                       flag);
+}
+
 void launch_recombine(int64_t n, const double* p0, const double* p1, const double* p2,
                       const double* p3, double c1, double c2, double c3, double* out64,
                       float* out32, hipStream_t s) {

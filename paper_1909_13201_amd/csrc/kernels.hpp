@@ -333,6 +333,59 @@ void launch_recombine(int64_t n, const double* p0, const double* p1, const doubl
                       const double* p3, double c1, double c2, double c3, double* out64,
                       float* out32, hipStream_t s);
 
+// ---- re-assembly of the advective terms on the device (2D) ----
+// Reference element tables, RefElem's layout (Gauss weights, phi, dphi,
+// d2phi, psi, dpsi at the 27-point / 27-function / 8-function maxima).
+constexpr int kAdvQ = 27, kAdvB = 27, kAdvP = 8;
+constexpr int kRefWq = 0, kRefPhi = kRefWq + kAdvQ, kRefDphi = kRefPhi + kAdvQ * kAdvB,
+              kRefD2phi = kRefDphi + kAdvQ * kAdvB * 3, kRefPsi = kRefD2phi + kAdvQ * kAdvB * 9,
+              kRefDpsi = kRefPsi + kAdvQ * kAdvP, kRefSize = kRefDpsi + kAdvQ * kAdvP * 3;
+struct AdvElemView {
+  int64_t nfluid = 0;             // fluid elements, in the order their terms are added
+  int per = 0;                    // terms each element emits
+  const int32_t* elems = nullptr;
+  const int64_t* elem_nodes = nullptr;   // nE x 9
+  const double* X = nullptr;             // N2 x 2 node coordinates
+  const int32_t* node_fine = nullptr;    // the finest-level node of each level node
+  const double* x = nullptr;             // finest-level vector; velocity at off_u
+  int64_t off_u = 0;
+  const double* ref = nullptr;           // reference tables (kRefSize doubles)
+  double rho = 1, mu = 1, inv_dt = 0, theta = 1;
+  int supg = 1, finest = 0;
+  double* emit = nullptr;                // nfluid x per values
+  int32_t* flag = nullptr;               // bit 1: an element emitted another number of terms
+};
+// Every fluid element's advective terms (the host assembly's order and
+// arithmetic) into v.emit; one thread per element.
+void launch_adv_elements(const AdvElemView& v, hipStream_t s);
+// dst[arr[i]][slot[i]] = stat[i] + sum of emit[em[k]], k in [ptr[i], ptr[i+1]);
+// where red[i] >= 0 (the finest level's operator arrays) also
+// dst_red[arr[i]][red[i]] = the same value.
+struct AdvGatherView {
+  int64_t n = 0;
+  const uint8_t* arr = nullptr;
+  const int64_t* slot = nullptr;
+  const double* stat = nullptr;
+  const int64_t* ptr = nullptr;
+  const int64_t* em = nullptr;
+  const int64_t* red = nullptr;
+  const double* emit = nullptr;
+  double* dst[12] = {};
+  double* dst_red[4] = {};
+};
+void launch_adv_gather(const AdvGatherView& g, hipStream_t s);
+// lift pieces of the listed rows: lift[p][row[i]] = - sum over k of
+// full[p][kk[k]] g[k], k in [ptr[i], ptr[i+1]), in that order
+void launch_adv_lift(int64_t n, const int64_t* row, const int64_t* ptr, const int64_t* kk,
+                     const double* g, const double* f0, const double* f1, const double* f2,
+                     const double* f3, double* l0, double* l1, double* l2, double* l3,
+                     hipStream_t s);
+// out[j] = in[perm[j]]
+void launch_permute_values(int64_t n, const int64_t* perm, const double* in, double* out,
+                           hipStream_t s);
+// flag[0] |= 1 when any of x[0 .. n) is NaN or infinite
+void launch_nonfinite_flag(int64_t n, const double* x, int32_t* flag, hipStream_t s);
+
 // ---- allocation-free scratch ----
 // A file-scope device array of kNoAllocScratchBytes bytes (one copy per GPU,
 // held until the process ends) for entry points that must not allocate.

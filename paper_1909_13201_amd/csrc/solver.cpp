@@ -329,6 +329,38 @@ struct fsgmg_hierarchy {
   std::vector<LevelOperator> ops;
   // re-assembly about a new advecting velocity (built at the first one)
   std::vector<AdvectionPlan> plans;
+  // the same on the device (2D, additive smoother, not interchanged), per
+  // level: the fluid elements and what their terms need, the per-element
+  // term values, and the touched entries of the value arrays with their
+  // velocity-independent sums and their terms (in the host's order)
+  struct DevAdv {
+    int64_t nfluid = 0;
+    int per = 0;
+    int32_t* elems = nullptr;
+    int64_t* elem_nodes = nullptr;
+    double* X = nullptr;
+    int32_t* node_fine = nullptr;
+    double* emit = nullptr;
+    int64_t nt = 0;
+    uint8_t* t_arr = nullptr;
+    int64_t* t_slot = nullptr;
+    double* t_stat = nullptr;
+    int64_t* t_ptr = nullptr;
+    int64_t* t_em = nullptr;
+    int64_t* t_red = nullptr;
+    int64_t nl = 0;   // finest: rows whose lift reads Dirichlet data
+    int64_t* l_row = nullptr;
+    int64_t* l_ptr = nullptr;
+    int64_t* l_k = nullptr;
+    double* l_g = nullptr;
+  };
+  std::vector<DevAdv> dadv;   // empty: not built
+  double* adv_ref = nullptr;
+  int32_t* adv_flag = nullptr;
+  int64_t* loadT_perm_dev = nullptr;
+  // the device's operator values are newer than the host copies (a device
+  // re-assembly); the host copies are pulled when a host consumer needs them
+  bool device_ahead = false;
   std::vector<int64_t> loadT_perm;   // entry of the load operator at each transpose entry
   std::vector<double> loadT_host;
   std::vector<Transfer> tr;      // tr[l] for l >= 1
@@ -494,7 +526,9 @@ struct fsgmg_hierarchy {
   // host copies of the level operators' values lag behind update_params on
   // a device handle until a host consumer needs them
   bool host_vals_stale = false;
+  void pull_device_values();
   void ensure_host_values() {
+    if (device_ahead) pull_device_values();
     if (!host_vals_stale) return;
     for (LevelOperator& op : ops)
       for (size_t k = 0; k < op.A.val.size(); ++k)
@@ -2576,6 +2610,7 @@ static fsgmg_status build_fs_as_blocks_impl(fsgmg_h h, const fsgmg_smoother_opts
     h->factors_valid = false;
     if (!keep_graphs) h->invalidate_graphs();
     if (!same_sets) {
+      h->ensure_host_values();   // the colouring reads the operator's values
       try {
         for (int l = 1; l < h->L; ++l) {
           build_blocks(h->levels[l], opts->core, opts->halo, mult, opts->monolithic != 0,
@@ -2869,6 +2904,240 @@ static void upload_operator_values(fsgmg_hierarchy& h) {
   HIPCHECK(hipStreamSynchronize(h.stream));
 }
 
+// Host copies of every value array a device re-assembly wrote: the level
+// operators' pieces (the values follow on the host when needed), and on the
+// finest level the unreduced pieces, the lift pieces, the load operator
+// and the time operator's pieces.
+void fsgmg_hierarchy::pull_device_values() {
+  auto pull = [&](std::vector<double>& to, const double* from) {
+    if (!to.empty() && from)
+      HIPCHECK(hipMemcpyAsync(to.data(), from, to.size() * sizeof(double), hipMemcpyDeviceToHost,
+                              stream));
+  };
+  for (int l = 0; l < L; ++l)
+    for (int p = 0; p < 4; ++p) pull(ops[l].piece[p], dl[l].piece[p]);
+  LevelOperator& F = ops[L - 1];
+  for (int p = 0; p < 4; ++p) {
+    pull(F.full_piece[p], full_piece[p]);
+    pull(F.lift_piece[p], lift_piece[p]);
+    if (time_val) pull(F.time_piece[p], time_piece[p]);
+  }
+  pull(F.load.val, load_val);
+  HIPCHECK(hipStreamSynchronize(stream));
+  if (time_val)
+    for (size_t k = 0; k < F.time.val.size(); ++k)
+      F.time.val[k] = F.time_piece[0][k] + F.G * F.time_piece[1][k] +
+                      F.invlam * F.time_piece[2][k] + F.mu * F.time_piece[3][k];
+  device_ahead = false;
+  host_vals_stale = true;
+}
+
+static bool dev_adv_eligible(const fsgmg_hierarchy& h) {
+  if (h.host_only() || h.D != 2 || h.plans.size() != (size_t)h.L) return false;
+  if (h.sopt.schwarz == FSGMG_SCHWARZ_MULTIPLICATIVE || h.sopt.interchange) return false;
+  for (const AdvectionPlan& P : h.plans)
+    if (!P.ready || (!P.elems.empty() && P.slots.empty())) return false;
+  return true;
+}
+
+static void run_dev_adv(fsgmg_hierarchy& h, const double* x);
+
+// Upload what the device re-assembly needs, from the plans (the term slots
+// recorded by the host assembly, in its order), then check once that every
+// element emits the number of terms the host recorded.
+static void build_dev_adv(fsgmg_hierarchy& h, const double* x) {
+  const std::vector<double> ref = reference_tables(h.D);
+  if (ref.size() != (size_t)kRefSize) throw Fail{FSGMG_ESTATE, "reference table layout"};
+  h.adv_ref = h.upload(ref);
+  h.adv_flag = h.zeros<int32_t>(1);
+  h.loadT_perm_dev = h.upload(h.loadT_perm);
+  std::vector<fsgmg_hierarchy::DevAdv> dadv(h.L);
+  const Level& Fl = h.levels[h.L - 1];
+  for (int l = 0; l < h.L; ++l) {
+    const Level& lv = h.levels[l];
+    const AdvectionPlan& P = h.plans[l];
+    const LevelOperator& op = h.ops[l];
+    const bool finest = l == h.L - 1;
+    fsgmg_hierarchy::DevAdv& a = dadv[l];
+    a.nfluid = (int64_t)P.elems.size();
+    a.per = P.per;
+    if (a.nfluid == 0) continue;
+    if ((int64_t)P.slots.size() != a.nfluid * a.per || P.dest.size() != P.slots.size())
+      throw Fail{FSGMG_ESTATE, "re-assembly plan sizes"};
+    a.elems = h.upload(P.elems);
+    a.elem_nodes = h.upload(lv.elem_nodes);
+    a.X = h.upload(lv.X);
+    std::vector<int32_t> nf(lv.N2);
+    const int step = 1 << (h.L - 1 - l);
+    for (int64_t n = 0; n < lv.N2; ++n) {
+      int ix[kMaxDim] = {0, 0, 0}, fx[kMaxDim] = {0, 0, 0};
+      lv.node_ijk(n, ix);
+      for (int c = 0; c < h.D; ++c) fx[c] = ix[c] * step;
+      nf[n] = (int32_t)Fl.node_index(fx);
+    }
+    a.node_fine = h.upload(nf);
+    a.emit = (double*)h.dalloc((size_t)(a.nfluid * a.per) * sizeof(double));
+    // the reduced entry of every unreduced one (finest level), -1 for the
+    // entries of Dirichlet rows and columns
+    std::vector<int64_t> red_of_full;
+    if (finest) {
+      red_of_full.assign(op.full.nnz(), -1);
+      for (int64_t i = 0; i < lv.N; ++i) {
+        if (lv.dir[i]) continue;
+        int64_t o = op.A.rowptr[i];
+        for (int64_t k = op.full.rowptr[i]; k < op.full.rowptr[i + 1]; ++k)
+          if (!lv.dir[op.full.col[k]]) red_of_full[k] = o++;
+      }
+    }
+    // touched entries: the terms grouped by (array, entry), in term order
+    std::vector<std::pair<uint64_t, int64_t>> keyed;
+    keyed.reserve(P.slots.size());
+    for (int64_t k = 0; k < (int64_t)P.slots.size(); ++k)
+      if (P.slots[k] >= 0) keyed.emplace_back(((uint64_t)P.dest[k] << 40) | (uint64_t)P.slots[k], k);
+    std::sort(keyed.begin(), keyed.end());
+    std::vector<uint8_t> arr;
+    std::vector<int64_t> slot, ptr{0}, em, red;
+    std::vector<double> stat;
+    for (size_t q = 0; q < keyed.size(); ++q) {
+      if (q == 0 || keyed[q].first != keyed[q - 1].first) {
+        const int d = (int)(keyed[q].first >> 40);
+        const int64_t sl = (int64_t)(keyed[q].first & ((uint64_t(1) << 40) - 1));
+        const int tgt = d / 4, p = d % 4;
+        if (tgt > 2 || (tgt == 2 && p != 0) || (tgt > 0 && !finest) ||
+            (tgt == 1 && !h.time_piece[p]))
+          throw Fail{FSGMG_ESTATE, "re-assembly plan destinations"};
+        const std::vector<double>& sv = tgt == 0 ? P.stat[p] : (tgt == 1 ? P.tstat[p] : P.lstat);
+        if (sl >= (int64_t)sv.size()) throw Fail{FSGMG_ESTATE, "re-assembly plan slots"};
+        if (q > 0) ptr.push_back((int64_t)em.size());
+        arr.push_back((uint8_t)d);
+        slot.push_back(sl);
+        stat.push_back(sv[sl]);
+        red.push_back(finest && tgt == 0 ? red_of_full[sl] : -1);
+      }
+      em.push_back(keyed[q].second);
+    }
+    ptr.push_back((int64_t)em.size());
+    a.nt = (int64_t)arr.size();
+    a.t_arr = h.upload(arr);
+    a.t_slot = h.upload(slot);
+    a.t_stat = h.upload(stat);
+    a.t_ptr = h.upload(ptr);
+    a.t_em = h.upload(em);
+    a.t_red = finest ? h.upload(red) : nullptr;
+    if (finest) {   // rows whose lift reads nonzero Dirichlet data, and those entries
+      std::vector<int64_t> lrow, lptr{0}, lk;
+      std::vector<double> lg;
+      for (int64_t i = 0; i < lv.N; ++i) {
+        if (lv.dir[i]) continue;
+        const size_t before = lk.size();
+        for (int64_t k = op.full.rowptr[i]; k < op.full.rowptr[i + 1]; ++k) {
+          const int32_t j = op.full.col[k];
+          if (!lv.dir[j] || lv.dir_val[j] == 0.0) continue;
+          lk.push_back(k);
+          lg.push_back(lv.dir_val[j]);
+        }
+        if (lk.size() > before) {
+          lrow.push_back(i);
+          lptr.push_back((int64_t)lk.size());
+        }
+      }
+      a.nl = (int64_t)lrow.size();
+      a.l_row = h.upload(lrow);
+      a.l_ptr = h.upload(lptr);
+      a.l_k = h.upload(lk);
+      a.l_g = h.upload(lg);
+    }
+  }
+  h.dadv = std::move(dadv);
+  // one run: every element must emit the number of terms the host recorded
+  run_dev_adv(h, x);
+  int32_t flag = 0;
+  HIPCHECK(hipMemcpyAsync(&flag, h.adv_flag, sizeof(int32_t), hipMemcpyDeviceToHost, h.stream));
+  HIPCHECK(hipStreamSynchronize(h.stream));
+  if (flag & 2) {
+    h.dadv.clear();
+    throw Fail{FSGMG_ESTATE, "device re-assembly emits another number of terms than the host"};
+  }
+}
+
+// The advective terms of every level about the velocity part of the device
+// vector x, added on the device to the velocity-independent sums; then the
+// lift, the load operator's transpose, the time operator's values and every
+// level operator's values and device layouts follow.  Asynchronous.
+static void run_dev_adv(fsgmg_hierarchy& h, const double* x) {
+  const Level& F = h.levels[h.L - 1];
+  HIPCHECK(hipMemsetAsync(h.adv_flag, 0, sizeof(int32_t), h.stream));
+  for (int l = 0; l < h.L; ++l) {
+    const fsgmg_hierarchy::DevAdv& a = h.dadv[l];
+    if (a.nfluid == 0) continue;
+    const bool finest = l == h.L - 1;
+    AdvElemView v;
+    v.nfluid = a.nfluid;
+    v.per = a.per;
+    v.elems = a.elems;
+    v.elem_nodes = a.elem_nodes;
+    v.X = a.X;
+    v.node_fine = a.node_fine;
+    v.x = x;
+    v.off_u = F.off_u;
+    v.ref = h.adv_ref;
+    v.rho = h.phys.rho;
+    v.mu = h.phys.mu;
+    v.inv_dt = h.phys.inv_dt;
+    v.theta = h.phys.theta;
+    v.supg = h.phys.supg;
+    v.finest = finest ? 1 : 0;
+    v.emit = a.emit;
+    v.flag = h.adv_flag;
+    launch_adv_elements(v, h.stream);
+    AdvGatherView g;
+    g.n = a.nt;
+    g.arr = a.t_arr;
+    g.slot = a.t_slot;
+    g.stat = a.t_stat;
+    g.ptr = a.t_ptr;
+    g.em = a.t_em;
+    g.red = a.t_red;
+    g.emit = a.emit;
+    DLevel& d = h.dl[l];
+    for (int p = 0; p < 4; ++p) {
+      if (finest) {
+        g.dst[p] = h.full_piece[p];
+        g.dst_red[p] = d.piece[p];
+        g.dst[4 + p] = h.time_piece[p];
+      } else {
+        g.dst[p] = d.piece[p];
+      }
+    }
+    if (finest) g.dst[8] = h.load_val;
+    launch_adv_gather(g, h.stream);
+    if (finest) {
+      launch_adv_lift(a.nl, a.l_row, a.l_ptr, a.l_k, a.l_g, h.full_piece[0], h.full_piece[1],
+                      h.full_piece[2], h.full_piece[3], h.lift_piece[0], h.lift_piece[1],
+                      h.lift_piece[2], h.lift_piece[3], h.stream);
+    }
+  }
+  const LevelOperator& Fo = h.ops[h.L - 1];
+  launch_permute_values((int64_t)h.loadT_perm.size(), h.loadT_perm_dev, h.load_val, h.loadT_val,
+                        h.stream);
+  launch_recombine(F.N, h.lift_piece[0], h.lift_piece[1], h.lift_piece[2], h.lift_piece[3], Fo.G,
+                   Fo.invlam, Fo.mu, h.lift, nullptr, h.stream);
+  if (h.time_val)
+    launch_recombine((int64_t)Fo.time.col.size(), h.time_piece[0], h.time_piece[1],
+                     h.time_piece[2], h.time_piece[3], Fo.G, Fo.invlam, Fo.mu, h.time_val,
+                     nullptr, h.stream);
+  for (int l = 0; l < h.L; ++l) {
+    DLevel& d = h.dl[l];
+    const LevelOperator& op = h.ops[l];
+    launch_recombine(d.nnz, d.piece[0], d.piece[1], d.piece[2], d.piece[3], op.G, op.invlam, op.mu,
+                     d.val, nullptr, h.stream);
+    launch_scatter(d.nnz, d.val, d.A.map, d.A.vals64, d.A.vals32, h.stream);
+    if (d.AT.ready) launch_scatter(d.nnz, d.val, d.AT.map, d.AT.vals64, d.AT.vals32, h.stream);
+  }
+  HIPCHECK(hipGetLastError());
+  h.device_ahead = true;
+}
+
 static bool same_pattern(const CsrHost& a, const CsrHost& b) {
   return a.rowptr == b.rowptr && a.col == b.col;
 }
@@ -2883,6 +3152,20 @@ static bool same_pattern(const CsrHost& a, const CsrHost& b) {
 static void reassemble_about(fsgmg_hierarchy& h, const double* x) {
   const Level& F = h.levels[h.L - 1];
   const size_t nw = (size_t)F.N2 * h.D;
+  if (!h.dadv.empty() && dev_adv_eligible(h)) {
+    // device re-assembly: the velocity is checked first, as on the host
+    HIPCHECK(hipMemsetAsync(h.adv_flag, 0, sizeof(int32_t), h.stream));
+    launch_nonfinite_flag((int64_t)nw, x + F.off_u, h.adv_flag, h.stream);
+    int32_t flag = 0;
+    HIPCHECK(hipMemcpyAsync(&flag, h.adv_flag, sizeof(int32_t), hipMemcpyDeviceToHost, h.stream));
+    HIPCHECK(hipStreamSynchronize(h.stream));
+    if (flag & 1) throw Fail{FSGMG_EINVAL, "the velocity contains NaN or Inf"};
+    run_dev_adv(h, x);
+    h.factors_valid = false;
+    if (!h.bd.empty()) h.bd_dirty = true;
+    build_coarse_inverse(h, true);
+    return;
+  }
   if (h.host_only()) {
     std::memcpy(h.w_finest.data(), x + F.off_u, nw * sizeof(double));
   } else {
@@ -2909,12 +3192,15 @@ static void reassemble_about(fsgmg_hierarchy& h, const double* x) {
     reassemble_all(h);
   }
   h.host_vals_stale = false;
+  h.device_ahead = false;
   h.factors_valid = false;
   // the multiplicative colouring reads the operator's values: recolour
   if (h.sopt.schwarz == FSGMG_SCHWARZ_MULTIPLICATIVE) h.have_blocks = false;
   if (h.host_only()) return;
   refresh_load_and_time(h);
   upload_operator_values(h);
+  // the next re-assemblies run on the device where they can
+  if (h.dadv.empty() && dev_adv_eligible(h)) build_dev_adv(h, x);
   if (!h.bd.empty()) h.bd_dirty = true;
   if (h.dl[0].use_bd) ensure_bd(h);
   build_coarse_inverse(h, true);
@@ -3106,6 +3392,7 @@ fsgmg_status export_csr(fsgmg_h h, int level, int which, int64_t dims[3], int64_
   if (!h || !dims) return FSGMG_EINVAL;
   return guarded(h, [&]() -> fsgmg_status {
     if (level < 0 || level >= h->L) throw Fail{FSGMG_EINVAL, "level out of range"};
+    h->ensure_host_values();
     CsrHost tmp;
     const CsrHost* M = nullptr;
     if (which == 0) {
@@ -3148,6 +3435,7 @@ fsgmg_status export_vector(fsgmg_h h, int level, int which, double* out) {
     const Level& lv = h->levels[level];
     if (which == 0) {
       if (level != h->L - 1) throw Fail{FSGMG_EINVAL, "lift exists on the finest level"};
+      h->ensure_host_values();
       const LevelOperator& op = h->ops[level];
       for (int64_t i = 0; i < lv.N; ++i)
         out[i] = op.lift_piece[0][i] + op.G * op.lift_piece[1][i] + op.invlam * op.lift_piece[2][i] +

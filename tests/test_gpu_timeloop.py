@@ -104,6 +104,70 @@ def test_update_advection_matches_reassembly():
         H.close()
 
 
+def _close(a, b, tol):
+    """Same pattern, and entrywise |a - b| <= tol * (largest |b| of the row)."""
+    assert np.array_equal(a.indptr, b.indptr) and np.array_equal(a.indices, b.indices)
+    n = len(b.indptr) - 1
+    row = np.repeat(np.arange(n), np.diff(b.indptr))
+    rowmax = np.zeros(n)
+    np.maximum.at(rowmax, row, np.abs(b.data))
+    assert np.all(np.abs(a.data - b.data) <= tol * rowmax[row] + 1e-300)
+
+
+@pytest.mark.parametrize("theta", [1.0, 0.5])
+def test_device_reassembly_matches_host(theta):
+    """After the first update_advection (host assembly, which also records
+    each term's value slot) the re-assembly runs on the device: per-element
+    convection and SUPG terms, gathered onto the velocity-independent sums
+    in the host's order.  Three calls in a row against a host-only handle
+    given the same velocities: every level operator, the load and time
+    operators and the lift agree entrywise to rounding (the device's
+    element arithmetic rounds differently), the device operator product
+    matches the host operator, and a NaN velocity is refused without
+    touching the operator."""
+    say("[timeloop] device re-assembly c5L3 theta", theta)
+    cfg = dict(inputs.with_levels(inputs.config("c5"), 3), theta=theta)
+    w = inputs.advecting_field(cfg)
+    Hd = fsgmg.Hierarchy(cfg, w, device=0)
+    Hh = fsgmg.Hierarchy(cfg, w, device=-1)
+    rng = np.random.default_rng(11)
+    try:
+        Hd.build_fs_as_blocks(prec="fp32")
+        for call in range(3):
+            x = rng.standard_normal(Hd.N) * (0.5 + call)
+            Hd.update_advection(dev(x))
+            Hh.update_advection(x)
+            for l in range(Hd.L):
+                _close(Hd.csr(l, 0), Hh.csr(l, 0), 1e-13)
+            _close(Hd.csr(Hd.L - 1, 3), Hh.csr(Hh.L - 1, 3), 1e-13)
+            _close(Hd.csr(Hd.L - 1, 4), Hh.csr(Hh.L - 1, 4), 1e-13)
+            ld = fsgmg.export_vector(Hd.h, Hd.L - 1, 0)
+            lh = fsgmg.export_vector(Hh.h, Hh.L - 1, 0)
+            assert np.abs(ld - lh).max() <= 1e-13 * np.abs(lh).max()
+            y = torch.zeros(Hd.N, dtype=torch.float64, device="cuda")
+            Hd.apply_operator(Hd.L - 1, dev(x), y)
+            A = Hh.csr(Hh.L - 1, 0)
+            ref = A @ x
+            assert np.all(np.abs(host(y) - ref) <= 1e-12 * (abs(A) @ np.abs(x)) + 1e-300)
+        before = Hd.csr(Hd.L - 1, 0)
+        bad = x.copy()
+        bad[Hd.info[-1]["off_u"] + 5] = np.nan
+        with pytest.raises(fsgmg.FsgmgError, match="EINVAL"):
+            Hd.update_advection(dev(bad))
+        after = Hd.csr(Hd.L - 1, 0)
+        assert np.array_equal(before.data, after.data)
+        # a solve on the device-assembled operator
+        Hd.build_fs_as_blocks(prec="fp32")
+        b = torch.zeros(Hd.N, dtype=torch.float64, device="cuda")
+        Hd.time_rhs(dev(inputs.body_force(cfg)), 1.0, dev(0 * x), b)
+        xs = torch.zeros_like(b)
+        info = Hd.gmres_solve(b, xs)
+        assert info["converged"]
+    finally:
+        Hd.close()
+        Hh.close()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_period_parity(prec):
     """Four backward-Euler steps of the pulsatile problem from rest, two
