@@ -360,13 +360,19 @@ fsgmg_status update_params(fsgmg_h h, double E, double mu);
  * about the advecting velocity w = the velocity part of x (finest level
  * vector in device memory, in host memory for a host-only handle; w at the
  * finest Q2 nodes, injected at the coarse levels' nodes), with the current
- * (E, mu).  Host assembly (one thread per level) and upload of values; the
- * operators' patterns do not change.  The first call keeps, per level, the
+ * (E, mu); the operators' patterns do not change.  The first call
+ * assembles on the host (one thread per level) and keeps, per level, the
  * sums of the terms that do not depend on w (host memory of four values
- * per operator entry and a 32-bit slot per advective term); every call
- * then adds only the convection and SUPG terms, element colour by element
- * colour, so the values equal a fresh setup's about the same w bit for
- * bit.  Invalidates the blocks (call build_fs_as_blocks again) and
+ * per operator entry and a 32-bit slot per advective term), adding the
+ * convection and SUPG terms element colour by element colour, so the
+ * values equal a fresh setup's about the same w bit for bit.  Later calls
+ * on a 2D device hierarchy with the additive smoother (not interchanged)
+ * run on the device: the elements' terms in the host's order and
+ * arithmetic, gathered onto the kept sums in the host's order, so the
+ * values agree with the host's to rounding (the host copies are fetched
+ * when a host consumer such as export_csr needs them); otherwise on the
+ * host as the first.  Asynchronous on the device except for the check of
+ * the velocity.  Invalidates the blocks (call build_fs_as_blocks again) and
  * rebuilds the coarse inverse as update_params does.  EINVAL for a hierarchy set up without an advecting
  * velocity (physics.w = NULL) or a velocity with NaN / Inf. */
 fsgmg_status update_advection(fsgmg_h h, const double* x);
