@@ -374,6 +374,10 @@ struct fsgmg_hierarchy {
   double* coarse_inv = nullptr;
   hipEvent_t coarse_done = nullptr;   // end of a coarse rebuild not yet checked
   bool coarse_pending = false;
+  // rebuilds after a parameter update or a re-assembly run on a stream of
+  // their own, after the level-0 values are written (coarse_ready)
+  hipStream_t coarse_stream = nullptr;
+  hipEvent_t coarse_ready = nullptr;
   double* coarse_invT = nullptr;
   double* coarse_work = nullptr;
   int32_t* coarse_piv = nullptr;
@@ -560,6 +564,11 @@ struct fsgmg_hierarchy {
         if (coarse_pending) (void)hipEventSynchronize(coarse_done);
         (void)hipEventDestroy(coarse_done);
       }
+      if (coarse_stream) {
+        (void)hipStreamSynchronize(coarse_stream);
+        (void)hipStreamDestroy(coarse_stream);
+      }
+      if (coarse_ready) (void)hipEventDestroy(coarse_ready);
       if (factor_start) (void)hipEventDestroy(factor_start);
       for (hipEvent_t e : step_done)
         if (e) (void)hipEventDestroy(e);
@@ -585,6 +594,7 @@ void fsgmg_hierarchy::quiesce() {
   if (device < 0) return;
   (void)hipStreamSynchronize(stream);
   if (cap_stream) (void)hipStreamSynchronize(cap_stream);
+  if (coarse_stream) (void)hipStreamSynchronize(coarse_stream);
   for (DLevel& d : dl) {
     if (d.fp.stream) (void)hipStreamSynchronize(d.fp.stream);
     if (d.fp.stream2) (void)hipStreamSynchronize(d.fp.stream2);
@@ -762,15 +772,21 @@ void ensure_coarse(fsgmg_hierarchy& h) {
 }
 
 // Dense FP64 inverse of the level-0 operator from its device CSR.  With
-// `async` the work is enqueued on the handle's stream (the column
-// permutation formed on the device) and the call returns at once;
-// ensure_coarse checks its status before the next cycle.  It runs in order
-// with the block refactorization that follows a parameter update: on a
-// stream of its own it found no room on CUs filled by the refactorization's
-// workgroups, and both together took longer than one after the other.
+// `async` the work is enqueued on a stream of its own after the level-0
+// values (the column permutation formed on the device) and the call returns
+// at once, so the block refactorization that follows a parameter update or
+// a re-assembly runs beside it; ensure_coarse checks its status before the
+// next cycle, and writers of level-0 values wait for it on the device.
+// The handle's stream waits for a coarse rebuild still running on its own
+// stream before level-0 values or the coarse buffers are written again.
+void wait_coarse(fsgmg_hierarchy& h) {
+  if (h.coarse_pending && h.coarse_done) HIPCHECK(hipStreamWaitEvent(h.stream, h.coarse_done, 0));
+}
+
 void build_coarse_inverse(fsgmg_hierarchy& h, bool async = false) {
   const int64_t n = h.ops[0].A.nrows;
   if (n > 20000) throw Fail{FSGMG_EINVAL, "coarse level too large for the dense inverse (n > 20000)"};
+  wait_coarse(h);
   int64_t np = (n + 15) & ~(int64_t)15;
   int max_lds = 0;
   HIPCHECK(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h.device));
@@ -805,14 +821,21 @@ void build_coarse_inverse(fsgmg_hierarchy& h, bool async = false) {
   int32_t* dsig = h.coarse_piv + np;
   if (async && coarse_sigma_lds(np) <= (size_t)max_lds) {
     if (!h.coarse_done) HIPCHECK(hipEventCreateWithFlags(&h.coarse_done, hipEventDisableTiming));
-    HIPCHECK(hipMemsetAsync(status, 0, sizeof(int32_t), h.stream));
+    if (!h.coarse_ready) HIPCHECK(hipEventCreateWithFlags(&h.coarse_ready, hipEventDisableTiming));
+    if (!h.coarse_stream) HIPCHECK(hipStreamCreateWithFlags(&h.coarse_stream, hipStreamNonBlocking));
+    // after the level-0 values written on the handle's stream; the block
+    // refactorization that follows a parameter update runs beside it
+    HIPCHECK(hipEventRecord(h.coarse_ready, h.stream));
+    HIPCHECK(hipStreamWaitEvent(h.coarse_stream, h.coarse_ready, 0));
+    hipStream_t cs = h.coarse_stream;
+    HIPCHECK(hipMemsetAsync(status, 0, sizeof(int32_t), cs));
     const double* res = launch_coarse_factor(n, np, crp, ccol, cval, h.coarse_work,
                                              h.coarse_work + np * np, a2, src, h.coarse_piv,
-                                             status, nb, h.stream);
-    launch_coarse_sigma(h.coarse_piv, np, status, dsig, h.stream);
-    launch_coarse_finish(res, np, n, dsig, h.coarse_inv, h.coarse_invT, h.stream);
+                                             status, nb, cs);
+    launch_coarse_sigma(h.coarse_piv, np, status, dsig, cs);
+    launch_coarse_finish(res, np, n, dsig, h.coarse_inv, h.coarse_invT, cs);
     HIPCHECK(hipGetLastError());
-    HIPCHECK(hipEventRecord(h.coarse_done, h.stream));
+    HIPCHECK(hipEventRecord(h.coarse_done, cs));
     h.coarse_pending = true;
     h.n0 = n;
     return;
@@ -847,6 +870,7 @@ void build_coarse_inverse(fsgmg_hierarchy& h, bool async = false) {
 void ensure_bd(fsgmg_hierarchy& h) {
   const bool first = h.bd.size() != (size_t)h.L;
   if (!first && !h.bd_dirty) return;
+  wait_coarse(h);
   h.ensure_host_values();
   if (first) h.bd.resize(h.L);
   for (int l = 0; l < h.L; ++l) {
@@ -2849,6 +2873,7 @@ fsgmg_status update_params(fsgmg_h h, double E, double mu) {
       h->ensure_host_values();
       return FSGMG_OK;
     }
+    wait_coarse(*h);
     for (int l = 0; l < h->L; ++l) {
       DLevel& d = h->dl[l];
       launch_recombine(d.nnz, d.piece[0], d.piece[1], d.piece[2], d.piece[3], G, invlam, mu, d.val,
@@ -2878,6 +2903,7 @@ fsgmg_status update_params(fsgmg_h h, double E, double mu) {
 // the patterns already on the device, recombined for the current (E, mu) as
 // update_params does.
 static void upload_operator_values(fsgmg_hierarchy& h) {
+  wait_coarse(h);
   for (int l = 0; l < h.L; ++l) {
     DLevel& d = h.dl[l];
     const LevelOperator& op = h.ops[l];
@@ -3066,6 +3092,7 @@ static void build_dev_adv(fsgmg_hierarchy& h, const double* x) {
 // level operator's values and device layouts follow.  Asynchronous.
 static void run_dev_adv(fsgmg_hierarchy& h, const double* x) {
   const Level& F = h.levels[h.L - 1];
+  wait_coarse(h);
   HIPCHECK(hipMemsetAsync(h.adv_flag, 0, sizeof(int32_t), h.stream));
   for (int l = 0; l < h.L; ++l) {
     const fsgmg_hierarchy::DevAdv& a = h.dadv[l];
