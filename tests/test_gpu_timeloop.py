@@ -168,6 +168,51 @@ def test_device_reassembly_matches_host(theta):
         Hh.close()
 
 
+def test_back_to_back_updates_order_on_device():
+    """The coarse inverse after a parameter update or a re-assembly runs on
+    a stream of its own; an update issued while it runs must wait for it on
+    the device.  Two updates back to back, then a refactorization and a
+    solve, give bitwise the solve of the second update alone on the same
+    handle (same launch shapes); likewise two device re-assemblies."""
+    say("[timeloop] back-to-back updates c5L3")
+    cfg = inputs.with_levels(inputs.config("c5"), 3)
+    w = inputs.advecting_field(cfg)
+    H = fsgmg.Hierarchy(cfg, w, device=0)
+    rng = np.random.default_rng(5)
+    try:
+        H.build_fs_as_blocks(prec="fp32")
+        f = dev(inputs.body_force(cfg))
+        x0 = rng.standard_normal(H.N)
+        x1 = rng.standard_normal(H.N)
+
+        def solve():
+            H.build_fs_as_blocks(prec="fp32")
+            b = torch.zeros(H.N, dtype=torch.float64, device="cuda")
+            H.time_rhs(f, 1.0, dev(0 * x0), b)
+            x = torch.zeros_like(b)
+            assert H.gmres_solve(b, x)["converged"]
+            return host(x)
+
+        E, mu = cfg["E"], cfg["mu"]
+        H.update_params(2.0 * E, 1.5 * mu)
+        H.update_params(3.0 * E, 0.5 * mu)       # while the first coarse rebuild runs
+        xa = solve()
+        H.update_params(3.0 * E, 0.5 * mu)
+        torch.cuda.synchronize()
+        xb = solve()
+        assert np.array_equal(xa, xb)
+        H.update_advection(dev(x0))              # host assembly, then the device plan
+        H.update_advection(dev(x1))              # device re-assembly
+        H.update_advection(dev(x0))              # ... while the previous coarse rebuild runs
+        xc = solve()
+        H.update_advection(dev(x0))
+        torch.cuda.synchronize()
+        xd = solve()
+        assert np.array_equal(xc, xd)
+    finally:
+        H.close()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_period_parity(prec):
     """Four backward-Euler steps of the pulsatile problem from rest, two
