@@ -1389,17 +1389,28 @@ __global__ __launch_bounds__(kTrailThreads) void k_invert_trailing(
   __syncthreads();
   if (!rows_here) return;
   const int64_t rowb = r0 + 16 * wv;
-  for (int ct = 0; ct < nc / 16; ++ct) {
-    const int col = c0 + 16 * ct + lr;
-    acc_t acc;
+  // two column tiles per iteration: their accumulator loads in flight together
+  const int nct = nc / 16;
+  for (int ct0 = 0; ct0 < nct; ct0 += 2) {
+    acc_t acc[2];
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-      acc[r] = kgroup ? TF(0) : a[(rowb + MT::row(lg, r)) * np + col];
-    const TF* Bc = Bs + 16 * lg * LDS_STRIDE + 16 * ct + lr;
+    for (int u = 0; u < 2; ++u) {
+      const int col = c0 + 16 * (ct0 + u) + lr;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) acc = MT::step(vcomp(tv[q / VW], q % VW), Bc[q * LDS_STRIDE], acc);
+      for (int r = 0; r < 4; ++r)
+        acc[u][r] = (kgroup || ct0 + u >= nct) ? TF(0) : a[(rowb + MT::row(lg, r)) * np + col];
+    }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) a[(rowb + MT::row(lg, r)) * np + col] = acc[r];
+    for (int u = 0; u < 2; ++u) {
+      if (ct0 + u >= nct) break;
+      const int col = c0 + 16 * (ct0 + u) + lr;
+      const TF* Bc = Bs + 16 * lg * LDS_STRIDE + 16 * (ct0 + u) + lr;
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        acc[u] = MT::step(vcomp(tv[q / VW], q % VW), Bc[q * LDS_STRIDE], acc[u]);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) a[(rowb + MT::row(lg, r)) * np + col] = acc[u][r];
+    }
   }
 }
 
