@@ -10,7 +10,7 @@ reports, per period of 1 s with t_step time steps, the mean number of
 nonlinear steps per time step (s^max), the mean GMRES iterations per linear
 solve (N) and the mean convergence rate (rho).
 
-Readings (the linearization of this build is Oseen about a frozen advecting
+Readings (the linearization here is Oseen about a frozen advecting
 velocity, solid linearized at the stress-free state):
 * the time derivatives by backward differences with step dt = cfg["dt"];
   the steady terms of the momentum rows carry the weight theta =
