@@ -114,8 +114,8 @@ def _close(a, b, tol):
     assert np.all(np.abs(a.data - b.data) <= tol * rowmax[row] + 1e-300)
 
 
-@pytest.mark.parametrize("theta", [1.0, 0.5])
-def test_device_reassembly_matches_host(theta):
+@pytest.mark.parametrize("name,theta", [("c5", 1.0), ("c5", 0.5), ("c2", 1.0)])
+def test_device_reassembly_matches_host(name, theta):
     """After the first update_advection (host assembly, which also records
     each term's value slot) the re-assembly runs on the device: per-element
     convection and SUPG terms, gathered onto the velocity-independent sums
@@ -125,8 +125,8 @@ def test_device_reassembly_matches_host(theta):
     element arithmetic rounds differently), the device operator product
     matches the host operator, and a NaN velocity is refused without
     touching the operator."""
-    say("[timeloop] device re-assembly c5L3 theta", theta)
-    cfg = dict(inputs.with_levels(inputs.config("c5"), 3), theta=theta)
+    say("[timeloop] device re-assembly %sL3 theta" % name, theta)
+    cfg = dict(inputs.with_levels(inputs.config(name), 3), theta=theta)   # c2: steady
     w = inputs.advecting_field(cfg)
     Hd = fsgmg.Hierarchy(cfg, w, device=0)
     Hh = fsgmg.Hierarchy(cfg, w, device=-1)
@@ -140,7 +140,8 @@ def test_device_reassembly_matches_host(theta):
             for l in range(Hd.L):
                 _close(Hd.csr(l, 0), Hh.csr(l, 0), 1e-13)
             _close(Hd.csr(Hd.L - 1, 3), Hh.csr(Hh.L - 1, 3), 1e-13)
-            _close(Hd.csr(Hd.L - 1, 4), Hh.csr(Hh.L - 1, 4), 1e-13)
+            if "dt" in cfg:
+                _close(Hd.csr(Hd.L - 1, 4), Hh.csr(Hh.L - 1, 4), 1e-13)
             ld = fsgmg.export_vector(Hd.h, Hd.L - 1, 0)
             lh = fsgmg.export_vector(Hh.h, Hh.L - 1, 0)
             assert np.abs(ld - lh).max() <= 1e-13 * np.abs(lh).max()
@@ -156,10 +157,19 @@ def test_device_reassembly_matches_host(theta):
             Hd.update_advection(dev(bad))
         after = Hd.csr(Hd.L - 1, 0)
         assert np.array_equal(before.data, after.data)
-        # a solve on the device-assembled operator
+        # a solve on the device-assembled operator, re-assembled about the
+        # configuration's own advecting field (the steady Oseen problem about
+        # the random fields above is not one the smoother is built for)
+        xw = np.zeros(Hd.N)
+        ou = Hd.info[-1]["off_u"]
+        xw[ou:ou + w.size] = np.asarray(w).ravel()
+        Hd.update_advection(dev(xw))
         Hd.build_fs_as_blocks(prec="fp32")
         b = torch.zeros(Hd.N, dtype=torch.float64, device="cuda")
-        Hd.time_rhs(dev(inputs.body_force(cfg)), 1.0, dev(0 * x), b)
+        if "dt" in cfg:
+            Hd.time_rhs(dev(inputs.body_force(cfg)), 1.0, dev(0 * x), b)
+        else:
+            Hd.assemble_load(dev(inputs.body_force(cfg).ravel()), b)
         xs = torch.zeros_like(b)
         info = Hd.gmres_solve(b, xs)
         assert info["converged"]
