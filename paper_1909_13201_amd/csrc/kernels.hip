@@ -3848,9 +3848,15 @@ void launch_scatter(int64_t n, const double* v, const int64_t* map, double* out6
 // then forms every touched operator entry as its velocity-independent sum
 // plus its contributions in the host's order.
 // ------------------------------------------------------------------------
+// One thread per (element, test function a): every section of the element's
+// term list runs over a outermost, so thread a writes its own contiguous
+// slice of each section; the element's geometry and SUPG tau are computed
+// by each of its threads.
 __global__ __launch_bounds__(64) void k_adv_elements(AdvElemView v) {
   constexpr int D = 2, NB = 9, NQ = 9, NP = 4, BB = 4;   // BB: the element bubble
-  const int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  const int64_t t = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  const int64_t i = t / NB;
+  const int a = (int)(t - i * NB);
   if (i >= v.nfluid) return;
   const int64_t e = v.elems[i];
   const int64_t* nodes = v.elem_nodes + e * NB;
@@ -3911,7 +3917,14 @@ __global__ __launch_bounds__(64) void k_adv_elements(AdvElemView v) {
   const bool weighted = inv_dt != 0.0 && theta != 1.0;
   const bool finest = v.finest != 0;
   double* out = v.emit + i * (int64_t)v.per;
-  int k = 0;
+  // sizes of the sections' slices per test function
+  const int m1 = (finest && weighted) ? 2 : 1;   // terms per steady momentum-row term
+  const int conv_a = NB * D * m1;
+  const int s1_a = NB * (D * (1 + (finest && weighted ? 1 : 0) + (finest && inv_dt != 0.0 ? 1 : 0)) +
+                         (finest ? D : 0));
+  const int hess_a = D * NB * D * m1;
+  const int gp_a = D * NP * m1;
+  int k = a * conv_a;
   // the element's k-th term (never beyond its own per slots)
   auto put = [&](double val) {
     if (k < v.per) out[k] = val;
@@ -3935,12 +3948,12 @@ __global__ __launch_bounds__(64) void k_adv_elements(AdvElemView v) {
       wg[q][a] = s;
     }
   // convection rho (w.grad u, phi)
-  for (int a = 0; a < NB; ++a)
-    for (int b = 0; b < NB; ++b) {
-      double s = 0;
-      for (int q = 0; q < NQ; ++q) s += dV[q] * phi(q, a) * wg[q][b];
-      for (int c = 0; c < D; ++c) madd(rho * s);
-    }
+  for (int b = 0; b < NB; ++b) {
+    double s = 0;
+    for (int q = 0; q < NQ; ++q) s += dV[q] * phi(q, a) * wg[q][b];
+    for (int c = 0; c < D; ++c) madd(rho * s);
+  }
+  int end = (a + 1) * conv_a;
   if (v.supg) {
     // lambda_k from the element bubble
     double Mb[D][D] = {}, Nb = 0;
@@ -3948,13 +3961,13 @@ __global__ __launch_bounds__(64) void k_adv_elements(AdvElemView v) {
       double lap = 0;
       for (int c = 0; c < D; ++c) lap += H[q][BB][c][c];
       double w2[D][D];
-      for (int a = 0; a < D; ++a)
-        for (int c = 0; c < D; ++c) w2[a][c] = (c == a ? lap : 0.0) + H[q][BB][c][a];
-      for (int a = 0; a < D; ++a)
-        for (int b = 0; b < D; ++b) {
+      for (int e1 = 0; e1 < D; ++e1)
+        for (int c = 0; c < D; ++c) w2[e1][c] = (c == e1 ? lap : 0.0) + H[q][BB][c][e1];
+      for (int e1 = 0; e1 < D; ++e1)
+        for (int e2 = 0; e2 < D; ++e2) {
           double s = 0;
-          for (int c = 0; c < D; ++c) s += w2[a][c] * w2[b][c];
-          Mb[a][b] += dV[q] * s;
+          for (int c = 0; c < D; ++c) s += w2[e1][c] * w2[e2][c];
+          Mb[e1][e2] += dV[q] * s;
         }
       for (int c = 0; c < D; ++c) Nb += dV[q] * G[q][BB][c] * G[q][BB][c];
     }
@@ -3969,47 +3982,53 @@ __global__ __launch_bounds__(64) void k_adv_elements(AdvElemView v) {
       const double tau = 1.0 / fmax(4.0 * lam * nu_k, sqrt(lam) * wnq);
       tw[q] = dV[q] * tau * rho;
     }
-    for (int a = 0; a < NB; ++a)
-      for (int b = 0; b < NB; ++b) {
-        double s1s = 0, s1t = 0;
-        for (int q = 0; q < NQ; ++q) {
-          s1s += tw[q] * wg[q][a] * rho * wg[q][b];
-          s1t += tw[q] * wg[q][a] * rho * inv_dt * phi(q, b);
-        }
-        const double s1 = weighted ? theta * s1s + s1t : s1s + s1t;
-        for (int c = 0; c < D; ++c) {
-          put(s1);
-          if (finest && weighted) put(-(1.0 - theta) * s1s);
-          if (finest && inv_dt != 0.0) put(s1t);
-        }
-        if (finest) {
-          double sl = 0;
-          for (int q = 0; q < NQ; ++q) sl += rho * rho * tw[q] * wg[q][a] * phi(q, b);
-          for (int c = 0; c < D; ++c) put(sl);
-        }
+    const int conv_all = NB * conv_a;
+    k = conv_all + a * s1_a;
+    for (int b = 0; b < NB; ++b) {
+      double s1s = 0, s1t = 0;
+      for (int q = 0; q < NQ; ++q) {
+        s1s += tw[q] * wg[q][a] * rho * wg[q][b];
+        s1t += tw[q] * wg[q][a] * rho * inv_dt * phi(q, b);
       }
-    for (int a = 0; a < NB; ++a)
-      for (int c = 0; c < D; ++c)
-        for (int b = 0; b < NB; ++b)
-          for (int f = 0; f < D; ++f) {
-            double s = 0;
-            for (int q = 0; q < NQ; ++q) {
-              double lap = 0;
-              if (c == f)
-                for (int m = 0; m < D; ++m) lap += H[q][b][m][m];
-              s += tw[q] * wg[q][a] * (lap + H[q][b][c][f]);
-            }
-            madd(-s);
-          }
-    for (int a = 0; a < NB; ++a)
-      for (int c = 0; c < D; ++c)
-        for (int m = 0; m < NP; ++m) {
+      const double s1 = weighted ? theta * s1s + s1t : s1s + s1t;
+      for (int c = 0; c < D; ++c) {
+        put(s1);
+        if (finest && weighted) put(-(1.0 - theta) * s1s);
+        if (finest && inv_dt != 0.0) put(s1t);
+      }
+      if (finest) {
+        double sl = 0;
+        for (int q = 0; q < NQ; ++q) sl += rho * rho * tw[q] * wg[q][a] * phi(q, b);
+        for (int c = 0; c < D; ++c) put(sl);
+      }
+    }
+    if (k != conv_all + (a + 1) * s1_a) atomicOr(v.flag, 2);
+    k = conv_all + NB * s1_a + a * hess_a;
+    for (int c = 0; c < D; ++c)
+      for (int b = 0; b < NB; ++b)
+        for (int f = 0; f < D; ++f) {
           double s = 0;
-          for (int q = 0; q < NQ; ++q) s += tw[q] * wg[q][a] * Gp[q][m][c];
-          madd(s);
+          for (int q = 0; q < NQ; ++q) {
+            double lap = 0;
+            if (c == f)
+              for (int m = 0; m < D; ++m) lap += H[q][b][m][m];
+            s += tw[q] * wg[q][a] * (lap + H[q][b][c][f]);
+          }
+          madd(-s);
         }
+    if (k != conv_all + NB * s1_a + (a + 1) * hess_a) atomicOr(v.flag, 2);
+    k = conv_all + NB * (s1_a + hess_a) + a * gp_a;
+    for (int c = 0; c < D; ++c)
+      for (int m = 0; m < NP; ++m) {
+        double s = 0;
+        for (int q = 0; q < NQ; ++q) s += tw[q] * wg[q][a] * Gp[q][m][c];
+        madd(s);
+      }
+    end = conv_all + NB * (s1_a + hess_a) + (a + 1) * gp_a;
   }
-  if (k != v.per) atomicOr(v.flag, 2);
+  // this thread's last slice ends where it should, and the element's last
+  // slice ends at per
+  if (k != end || (a == NB - 1 && end != v.per)) atomicOr(v.flag, 2);
 }
 
 __global__ __launch_bounds__(kThreads) void k_adv_gather(AdvGatherView g) {
@@ -4060,7 +4079,7 @@ __global__ __launch_bounds__(kThreads) void k_nonfinite_flag(int64_t n, const do
 
 void launch_adv_elements(const AdvElemView& v, hipStream_t s) {
   if (v.nfluid > 0)
-    hipLaunchKernelGGL(k_adv_elements, dim3(grid_for(v.nfluid, 64)), dim3(64), 0, s, v);
+    hipLaunchKernelGGL(k_adv_elements, dim3(grid_for(v.nfluid * 9, 64)), dim3(64), 0, s, v);
 }
 
 void launch_adv_gather(const AdvGatherView& g, hipStream_t s) {
