@@ -348,9 +348,11 @@ fsgmg_status param_grad_noalloc(fsgmg_h h, const double* lam, const double* x, d
  * from the stored affine pieces of the Section 2.2 operator (it is affine in
  * G, 1/lambda_L and mu; SUPG tau frozen at setup).  Invalidates the
  * blocks: call build_fs_as_blocks again.  The coarse inverse is rebuilt on
- * the handle's stream without waiting for it (the call returns at once); the
- * next cycle or solve checks it and returns FSGMG_ESINGULAR if the coarse
- * matrix turned out singular. */
+ * a stream of the library's own, after the new level-0 values on the
+ * handle's stream, without waiting for it (the call returns at once, and a
+ * following block refactorization runs beside it); the next cycle or solve
+ * waits for it and returns FSGMG_ESINGULAR if the coarse matrix turned out
+ * singular. */
 fsgmg_status update_params(fsgmg_h h, double E, double mu);
 
 /* Picard step of the nonlinear loop (Section 2.2: the paper linearizes each
