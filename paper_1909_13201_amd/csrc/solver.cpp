@@ -553,6 +553,10 @@ struct fsgmg_hierarchy {
   ~fsgmg_hierarchy() {
     if (device >= 0) {
       (void)hipSetDevice(device);
+      // every stream drained while it still exists, then events and
+      // streams destroyed, then memory freed
+      if (coarse_pending && coarse_done) (void)hipEventSynchronize(coarse_done);
+      quiesce();
       for (DLevel& d : dl) {
         if (d.fp.stream) (void)hipStreamDestroy(d.fp.stream);
         if (d.fp.done) (void)hipEventDestroy(d.fp.done);
@@ -560,14 +564,8 @@ struct fsgmg_hierarchy {
         if (d.fp.fork) (void)hipEventDestroy(d.fp.fork);
         if (d.fp.done2) (void)hipEventDestroy(d.fp.done2);
       }
-      if (coarse_done) {
-        if (coarse_pending) (void)hipEventSynchronize(coarse_done);
-        (void)hipEventDestroy(coarse_done);
-      }
-      if (coarse_stream) {
-        (void)hipStreamSynchronize(coarse_stream);
-        (void)hipStreamDestroy(coarse_stream);
-      }
+      if (coarse_done) (void)hipEventDestroy(coarse_done);
+      if (coarse_stream) (void)hipStreamDestroy(coarse_stream);
       if (coarse_ready) (void)hipEventDestroy(coarse_ready);
       if (factor_start) (void)hipEventDestroy(factor_start);
       for (hipEvent_t e : step_done)
@@ -575,7 +573,6 @@ struct fsgmg_hierarchy {
       for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
       invalidate_graphs();
       if (cap_stream) (void)hipStreamDestroy(cap_stream);
-      quiesce();
       for (void* p : allocs) {
         if (user_alloc())
           alloc.free(p, (void*)stream, alloc.user);
